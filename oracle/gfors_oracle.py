@@ -1,0 +1,490 @@
+"""GFORS CPU oracle (test infrastructure; FP64 PDHG, exact-integer evaluation).
+
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may import
+this module.  It follows the paper's text step by step:
+
+  * saddle form and data       -- eq. (saddle), Sec. 2
+  * PDHG update                -- Algorithm 2 (Sec. 2.1), gradients eq. (dy)
+  * residuals s^x, s^y         -- Theorem 2 (Sec. 2.1)
+  * Bernoulli sampling         -- Algorithm 3 (Sec. 2.2)
+  * EvalBest / incumbent       -- Algorithm 1 and Sec. 3
+  * Preprocess, UpdatePenalty  -- Sec. 3
+  * Philox4x32-10              -- Salmon, Moraes, Dror, Shaw, "Parallel Random
+                                  Numbers: As Easy as 1, 2, 3", SC'11
+
+Readings where the paper is silent (x0, the tau split, rho constants, the
+uniform resolution, tie-breaking) are listed with each function.
+
+Every function here is pinned by a `-m "not gpu"` test against something
+other than itself (closed forms, library routines, brute force, hand traces,
+the rocRAND Philox engine, or the theorems' inequalities).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "Params", "Scaled", "State", "Incumbent", "preprocess", "csr_to_scipy",
+    "power_norm", "rho_sequence", "rho_value", "init_state", "pdhg_step",
+    "residuals", "philox4x32_10", "uniforms24", "sample_bits", "pack_bits",
+    "unpack_bits", "evaluate", "incumbent_update", "round_candidate", "run_gfors",
+    "M0", "M1", "W0", "W1",
+]
+
+
+# ----------------------------------------------------------------------------
+# Parameters
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Params:
+    """Tunables of Algorithm 1 / Sec. 3.  ``None`` means "derive from data".
+
+    sigma       step-size product bound tau1*tau2 <= sigma (Preprocess, Sec. 3)
+    tau1, tau2  explicit step sizes (override the derived split)
+    rho_*       UpdatePenalty constants (rho_min, rho_max, T, p, delta)
+    k_int       sampling interval of Algorithm 1
+    power_iters power-iteration count for the spectral norms of Preprocess
+    x0          constant starting point x_0 = x0 * 1
+    seed        Philox key
+    """
+    sigma: float = 0.99
+    tau1: Optional[float] = None
+    tau2: Optional[float] = None
+    rho_min: Optional[float] = None
+    rho_max: Optional[float] = None
+    rho_T: float = 10.0
+    rho_p: float = 2.0
+    rho_delta: Optional[float] = None
+    k_int: int = 100
+    power_iters: int = 200
+    x0: float = 0.0
+    seed: int = 0
+
+
+# ----------------------------------------------------------------------------
+# Preprocess (Sec. 3) and the saddle data of eq. (saddle)
+# ----------------------------------------------------------------------------
+
+def csr_to_scipy(M, dtype=np.float64) -> sp.csr_matrix:
+    """Integer CSR (row_ptr, col, val|None) -> scipy CSR of the given dtype."""
+    vals = np.ones(M.nnz, dtype=dtype) if M.val is None else M.val.astype(dtype)
+    return sp.csr_matrix((vals, M.col.astype(np.int64), M.row_ptr.astype(np.int64)),
+                         shape=(M.nrows, M.ncols))
+
+
+def power_norm(M: sp.spmatrix, iters: int) -> float:
+    """Spectral norm ||M||_2 by power iteration on M^T M (reading of Sec. 3,
+    which names the spectral norm but not the method).
+
+    v_0 = 1/sqrt(ncols) * 1;  v <- M^T M v / ||M^T M v||;  ||M||_2 ~ ||M v||."""
+    ncols = M.shape[1]
+    if ncols == 0 or M.nnz == 0:
+        return 0.0
+    v = np.full(ncols, 1.0 / math.sqrt(ncols))
+    Mt = M.T.tocsr()
+    for _ in range(iters):
+        u = Mt @ (M @ v)
+        nu = float(np.sqrt(np.dot(u, u)))
+        if nu == 0.0:
+            return 0.0
+        v = u / nu
+    w = M @ v
+    return float(np.sqrt(np.dot(w, w)))
+
+
+@dataclass
+class Scaled:
+    """Normalised saddle data and step sizes.
+
+    K      = scaled  -[A; B]   (FP64 scipy CSR, m x n)      eq. (saddle)
+    r      = scaled   (b; d)
+    Q, c   = Q / s_o, c / s_o
+    ineq   = boolean mask of rows of K that come from A (dual cone R_+)
+    """
+    n: int
+    m1: int
+    m2: int
+    K: sp.csr_matrix
+    r: np.ndarray
+    Q: Optional[sp.csr_matrix]
+    c: np.ndarray
+    row_norm: np.ndarray
+    s_o: float
+    s_K: float
+    Q_norm: float
+    tau1: float
+    tau2: float
+    rho_min: float
+    rho_max: float
+    rho_T: float
+    rho_p: float
+    rho_delta: float
+    params: Params
+
+    @property
+    def m(self) -> int:
+        return self.m1 + self.m2
+
+
+def preprocess(P, params: Params = Params()) -> Scaled:
+    """Preprocess (Sec. 3) of the saddle data K = -[A;B], r = (b;d) (Sec. 2):
+
+      1. each row of K (and its entry of r) is divided by the row's 2-norm;
+         an all-zero row is left as it is;
+      2. Q and c are divided by s_o = ||Q||_2 + ||c||_2 (skipped if s_o = 0);
+      3. K and r are divided by s_K = ||K||_2 of the row-normalised K
+         (skipped if K has no nonzero).
+
+    Step sizes (reading; the paper only asks tau1*tau2 <= sigma):
+      Q = 0 :  tau1 = tau2 = sqrt(sigma)
+      Q != 0:  tau1 = min(sqrt(sigma), 1/(2 L_max)), L_max = 2(||Q~|| + rho_max),
+               tau2 = sigma / tau1         (keeps tau1 <= 1/(2L) of Prop. 2)
+
+    rho constants (reading; the paper does not print values): with
+    g = ||c~||_inf + ||Q~||_2:  rho_min = 1e-3 g, rho_max = g, delta = 1e-4 g.
+    """
+    n = P.n
+    blocks, rhs = [], []
+    if P.A is not None:
+        blocks.append(-csr_to_scipy(P.A))
+        rhs.append(P.b.astype(np.float64))
+    if P.B is not None:
+        blocks.append(-csr_to_scipy(P.B))
+        rhs.append(P.d.astype(np.float64))
+    m1 = 0 if P.A is None else P.A.nrows
+    m2 = 0 if P.B is None else P.B.nrows
+    if blocks:
+        K = sp.vstack(blocks).tocsr()
+        r = np.concatenate(rhs)
+    else:
+        K = sp.csr_matrix((0, n))
+        r = np.zeros(0)
+    # step 1: row 2-norms
+    sq = np.asarray(K.multiply(K).sum(axis=1)).reshape(-1)
+    row_norm = np.sqrt(sq)
+    inv = np.where(row_norm > 0, 1.0 / np.where(row_norm > 0, row_norm, 1.0), 1.0)
+    K = sp.diags(inv) @ K
+    r = r * inv
+    # step 2: objective scale
+    Qs = csr_to_scipy(P.Q) if P.Q is not None else None
+    cf = P.c.astype(np.float64)
+    q_norm_raw = power_norm(Qs, params.power_iters) if Qs is not None else 0.0
+    s_o = q_norm_raw + float(np.sqrt(np.dot(cf, cf)))
+    if s_o > 0:
+        cs = cf / s_o
+        Qt = (Qs / s_o).tocsr() if Qs is not None else None
+        Q_norm = q_norm_raw / s_o
+    else:
+        cs, Qt, Q_norm = cf.copy(), Qs, 0.0
+    # step 3: constraint scale
+    s_K = power_norm(K, params.power_iters) if K.nnz else 0.0
+    if s_K > 0:
+        K = (K / s_K).tocsr()
+        r = r / s_K
+    K.sort_indices()
+    # step sizes and rho constants
+    g = (float(np.max(np.abs(cs))) if n else 0.0) + Q_norm
+    rho_min = params.rho_min if params.rho_min is not None else 1e-3 * g
+    rho_max = params.rho_max if params.rho_max is not None else g
+    rho_delta = params.rho_delta if params.rho_delta is not None else 1e-4 * g
+    sq_sigma = math.sqrt(params.sigma)
+    if Qt is None or Qt.nnz == 0:
+        tau1 = tau2 = sq_sigma
+    else:
+        L_max = 2.0 * (Q_norm + rho_max)
+        tau1 = min(sq_sigma, 1.0 / (2.0 * L_max))
+        tau2 = params.sigma / tau1
+    if params.tau1 is not None:
+        tau1 = params.tau1
+    if params.tau2 is not None:
+        tau2 = params.tau2
+    return Scaled(n=n, m1=m1, m2=m2, K=K, r=r, Q=Qt, c=cs, row_norm=row_norm,
+                  s_o=s_o, s_K=s_K, Q_norm=Q_norm, tau1=tau1, tau2=tau2,
+                  rho_min=rho_min, rho_max=rho_max, rho_T=params.rho_T,
+                  rho_p=params.rho_p, rho_delta=rho_delta, params=params)
+
+
+# ----------------------------------------------------------------------------
+# UpdatePenalty (Sec. 3)
+# ----------------------------------------------------------------------------
+
+def rho_sequence(S_or_consts, count: int) -> list:
+    """rho_0 .. rho_{count-1} of UpdatePenalty (Sec. 3):
+
+      rho~_n = rho_min (1 + n/T)^p
+      rho_n  = clip(rho~_n, rho_{n-1} + delta, rho_max),  rho_0 = rho_min
+
+    clip(v, lo, hi) = min(max(v, lo), hi): the upper bound wins when the
+    increment floor passes rho_max (reading).  n counts sampling triggers."""
+    if isinstance(S_or_consts, Scaled):
+        rmin, rmax, T, p, delta = (S_or_consts.rho_min, S_or_consts.rho_max,
+                                   S_or_consts.rho_T, S_or_consts.rho_p, S_or_consts.rho_delta)
+    else:
+        rmin, rmax, T, p, delta = S_or_consts
+    out = []
+    prev = None
+    for nn in range(count):
+        if prev is None:
+            rho = rmin
+        else:
+            rt = rmin * (1.0 + nn / T) ** p
+            rho = min(max(rt, prev + delta), rmax)
+        out.append(rho)
+        prev = rho
+    return out
+
+
+def rho_value(S, n_trig: int) -> float:
+    return rho_sequence(S, n_trig + 1)[-1]
+
+
+# ----------------------------------------------------------------------------
+# PDHG (Algorithm 2) and residuals (Theorem 2)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class State:
+    """Iterate state after iteration k: x = x_k, x_prev = x_{k-1},
+    xbar = 2 x_k - x_{k-1}, y = y_k; k counts iterations; n_trig counts
+    sampling triggers (drives rho); rnd counts Philox sampling rounds."""
+    x: np.ndarray
+    x_prev: np.ndarray
+    xbar: np.ndarray
+    y: np.ndarray
+    k: int = 0
+    n_trig: int = 0
+    rnd: int = 0
+
+
+def init_state(S: Scaled) -> State:
+    """x_0 = x_{-1} = xbar_0 = x0 * 1 (auxiliaries of Sec. 2.1), y_0 = 0."""
+    x0 = np.full(S.n, float(S.params.x0))
+    return State(x=x0.copy(), x_prev=x0.copy(), xbar=x0.copy(), y=np.zeros(S.m))
+
+
+def pdhg_step(S: Scaled, st: State, rho: float) -> State:
+    """One FirstOrderStep of Algorithm 2:
+
+      y_k   = Pi_{R+^{m1} x R^{m2}}( y_{k-1} + tau2 (K xbar_{k-1} + r) )
+      delta = c + rho + K^T y_k + 2 Q x_{k-1} - 2 rho x_{k-1}
+      x_k   = Pi_{[0,1]^n}( x_{k-1} - tau1 delta )
+      xbar_k = 2 x_k - x_{k-1}
+    """
+    t = S.K @ st.xbar + S.r
+    y = st.y + S.tau2 * t
+    y[: S.m1] = np.maximum(y[: S.m1], 0.0)
+    delta = S.c + rho + S.K.T @ y - 2.0 * rho * st.x
+    if S.Q is not None:
+        delta = delta + 2.0 * (S.Q @ st.x)
+    x = np.clip(st.x - S.tau1 * delta, 0.0, 1.0)
+    xbar = 2.0 * x - st.x
+    return State(x=x, x_prev=st.x, xbar=xbar, y=y, k=st.k + 1,
+                 n_trig=st.n_trig, rnd=st.rnd)
+
+
+def residuals(S: Scaled, before: State, after: State, rho: float) -> dict:
+    """Quantities CheckHalt (Sec. 3) watches, after the step before -> after:
+
+      s^x = (x_{k-1} - x_k)/tau1 + (2Q - 2 rho I)(x_k - x_{k-1})      (Theorem 2)
+      s^y = (y_{k-1} - y_k)/tau2 + K (xbar_{k-1} - x_k)               (Theorem 2)
+      primal gap = || ( [K x_k + r]_+ on inequality rows, K x_k + r on equality rows ) ||_2
+      binary gap = sum_i x_i (1 - x_i)
+    """
+    dx = after.x - before.x
+    sx = -dx / S.tau1 - 2.0 * rho * dx
+    if S.Q is not None:
+        sx = sx + 2.0 * (S.Q @ dx)
+    sy = (before.y - after.y) / S.tau2 + S.K @ (before.xbar - after.x)
+    t = S.K @ after.x + S.r
+    t[: S.m1] = np.maximum(t[: S.m1], 0.0)
+    return {
+        "sx": float(np.linalg.norm(sx)),
+        "sy": float(np.linalg.norm(sy)),
+        "primal": float(np.linalg.norm(t)),
+        "binary": float(np.sum(after.x * (1.0 - after.x))),
+        "sx_vec": sx,
+        "sy_vec": sy,
+    }
+
+
+# ----------------------------------------------------------------------------
+# Philox4x32-10 (SC'11) and the Bernoulli sampler (Algorithm 3)
+# ----------------------------------------------------------------------------
+
+M0 = 0xD2511F53
+M1 = 0xCD9E8D57
+W0 = 0x9E3779B9
+W1 = 0xBB67AE85
+_MASK = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
+    """Philox4x32 with 10 rounds.  Each round multiplies counter words 0 and 2
+    by the two constants (full 64-bit products split into hi/lo), permutes and
+    mixes in the key:  (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); the key is
+    bumped by the Weyl constants between rounds.  Vectorised over arrays."""
+    c0 = np.asarray(c0, dtype=np.uint64) & _MASK
+    c1 = np.asarray(c1, dtype=np.uint64) & _MASK
+    c2 = np.asarray(c2, dtype=np.uint64) & _MASK
+    c3 = np.asarray(c3, dtype=np.uint64) & _MASK
+    kk0 = np.uint64(k0 & 0xFFFFFFFF)
+    kk1 = np.uint64(k1 & 0xFFFFFFFF)
+    m0 = np.uint64(M0)
+    m1 = np.uint64(M1)
+    for rnd in range(10):
+        p0 = m0 * c0
+        p1 = m1 * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK
+        c0, c1, c2, c3 = (hi1 ^ c1 ^ kk0), lo1, (hi0 ^ c3 ^ kk1), lo0
+        kk0 = (kk0 + np.uint64(W0)) & _MASK
+        kk1 = (kk1 + np.uint64(W1)) & _MASK
+    return (c0.astype(np.uint32), c1.astype(np.uint32),
+            c2.astype(np.uint32), c3.astype(np.uint32))
+
+
+def uniforms24(seed: int, rnd: int, instance: int, i: np.ndarray, l: np.ndarray) -> np.ndarray:
+    """24-bit uniforms U(inst, round, i, l) in [0, 1) as exact FP64 values.
+
+    Counter map (reading): key = (seed lo32, seed hi32),
+    counter = (l, i >> 2, round, instance), output word = i & 3;  u = (U >> 8) 2^-24."""
+    i = np.asarray(i, dtype=np.int64)
+    l = np.asarray(l, dtype=np.int64)
+    i, l = np.broadcast_arrays(i, l)
+    w = philox4x32_10(l, i >> 2, np.full(i.shape, rnd), np.full(i.shape, instance),
+                      seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    sel = (i & 3)
+    U = np.choose(sel, w)
+    return (U >> np.uint32(8)).astype(np.float64) * (2.0 ** -24)
+
+
+def sample_bits(p: np.ndarray, K: int, seed: int, rnd: int, instance: int = 0) -> np.ndarray:
+    """RandSampleStep (Algorithm 3): X[l, i] = 1  iff  u(inst, round, i, l) < p_i,
+    i.e. X[l, i] ~ Bernoulli(p_i) independently.  Strict '<' makes p = 0 never
+    and p = 1 always sample a one.  Returns bool [K, n]."""
+    n = p.shape[0]
+    pf = np.asarray(p, dtype=np.float64)
+    ii = np.arange(n, dtype=np.int64)[None, :]
+    ll = np.arange(K, dtype=np.int64)[:, None]
+    u = uniforms24(seed, rnd, instance, ii, ll)
+    return u < pf[None, :]
+
+
+def pack_bits(X: np.ndarray) -> np.ndarray:
+    """bool [K, n] -> uint64 [n, K/64]: word w of variable i holds candidates
+    64w .. 64w+63, candidate 64w+b in bit b."""
+    K, n = X.shape
+    assert K % 64 == 0
+    Xt = X.T.reshape(n, K // 64, 64).astype(np.uint64)
+    shifts = np.arange(64, dtype=np.uint64)
+    return np.bitwise_or.reduce(Xt << shifts, axis=2)
+
+
+def unpack_bits(words: np.ndarray, K: int) -> np.ndarray:
+    """Inverse of pack_bits."""
+    n = words.shape[0]
+    shifts = np.arange(64, dtype=np.uint64)
+    bits = (words[:, :, None] >> shifts) & np.uint64(1)
+    return bits.reshape(n, K).T.astype(bool)
+
+
+def round_candidate(x: np.ndarray) -> np.ndarray:
+    """round(x_k) of Algorithm 1: x_i > 1/2 -> 1 (ties at exactly 1/2 go to 0)."""
+    return (np.asarray(x, dtype=np.float64) > 0.5)[None, :]
+
+
+# ----------------------------------------------------------------------------
+# EvalBest (Sec. 3) on the original integer data
+# ----------------------------------------------------------------------------
+
+def _int_csr(M) -> sp.csr_matrix:
+    vals = np.ones(M.nnz, dtype=np.int64) if M.val is None else M.val.astype(np.int64)
+    return sp.csr_matrix((vals, M.col.astype(np.int64), M.row_ptr.astype(np.int64)),
+                         shape=(M.nrows, M.ncols))
+
+
+def evaluate(P, X: np.ndarray):
+    """Exact evaluation of candidates X (bool [K, n]) on the ORIGINAL integer data:
+
+      viol_l = #{j : (A x_l)_j < b_j} + #{j : (B x_l)_j != d_j}
+      z_l    = <x_l, Q x_l> + <c, x_l>
+    int64 throughout (products of a 0/1 matrix with integer data)."""
+    Xi = np.asarray(X, dtype=np.int64)
+    K = Xi.shape[0]
+    viol = np.zeros(K, dtype=np.int64)
+    if P.A is not None and P.A.nrows:
+        a = (_int_csr(P.A) @ Xi.T)
+        viol += np.sum(a < P.b.astype(np.int64)[:, None], axis=0)
+    if P.B is not None and P.B.nrows:
+        e = (_int_csr(P.B) @ Xi.T)
+        viol += np.sum(e != P.d.astype(np.int64)[:, None], axis=0)
+    z = Xi @ P.c.astype(np.int64)
+    if P.Q is not None:
+        QX = _int_csr(P.Q) @ Xi.T           # [n, K]
+        z = z + np.sum(Xi.T * QX, axis=0)
+    return viol, z
+
+
+@dataclass
+class Incumbent:
+    """(z_best, x_best) of Algorithm 1; z = None stands for +infinity."""
+    z: Optional[int] = None
+    x: Optional[np.ndarray] = None
+    rnd: int = -2
+    l: int = -1
+    k: int = -1
+
+
+def incumbent_update(inc: Incumbent, X: np.ndarray, viol, z, rnd: int, k: int) -> bool:
+    """EvalBest: among feasible candidates (viol = 0) take the smallest z, the
+    lowest candidate index on ties (reading); replace the incumbent only on a
+    strict improvement.  Returns True if the incumbent changed."""
+    feas = np.nonzero(np.asarray(viol) == 0)[0]
+    if feas.size == 0:
+        return False
+    zf = np.asarray(z)[feas]
+    best = int(feas[int(np.argmin(zf))])   # argmin returns the first minimum
+    zb = int(z[best])
+    if inc.z is None or zb < inc.z:
+        inc.z, inc.x, inc.rnd, inc.l, inc.k = zb, np.asarray(X[best], dtype=bool).copy(), rnd, best, k
+        return True
+    return False
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 driver (fixed iteration budget; CheckHalt not used)
+# ----------------------------------------------------------------------------
+
+def run_gfors(P, params: Params, iters: int, K: int, instance: int = 0,
+              final_round: bool = True, record: bool = False):
+    """Algorithm 1 with k_r = 1 and batch size K: at every iteration k the
+    penalty is rho_{n} (n = triggers so far), one PDHG step is taken, and when
+    k is a multiple of k_int one Philox round of K candidates is sampled from
+    x_k, evaluated and merged into the incumbent; finally round(x_k) is
+    evaluated.  Returns (incumbent, state, scaled, history)."""
+    S = preprocess(P, params)
+    st = init_state(S)
+    inc = Incumbent()
+    hist = []
+    for _ in range(iters):
+        rho = rho_value(S, st.n_trig)
+        st = pdhg_step(S, st, rho)
+        if st.k % params.k_int == 0:
+            X = sample_bits(st.x, K, params.seed, st.rnd, instance)
+            viol, z = evaluate(P, X)
+            incumbent_update(inc, X, viol, z, st.rnd, st.k)
+            if record:
+                hist.append((st.k, st.rnd, inc.z, int(np.sum(viol == 0))))
+            st.rnd += 1
+            st.n_trig += 1
+    if final_round:
+        X = round_candidate(st.x)
+        viol, z = evaluate(P, X)
+        incumbent_update(inc, X, viol, z, -1, st.k)
+    return inc, st, S, hist
