@@ -1,0 +1,187 @@
+/*
+ * gfors.h -- C ABI of the GFORS hot path on MI355X (gfx950).
+ *
+ * The library solves (heuristically) binary integer programs of the form
+ *
+ *     min <x, Q x> + <c, x>   s.t.  A x >= b,  B x = d,  x in {0,1}^n     (eq. bip, Sec. 1)
+ *
+ * with the loop of Algorithm 1: PDHG steps (Algorithm 2) on the penalised
+ * saddle problem (eq. saddle, Sec. 2) interleaved with rounds of Bernoulli
+ * sampling (Algorithm 3) whose candidates are evaluated exactly (EvalBest,
+ * Sec. 3) into an incumbent.  Preprocess and UpdatePenalty follow Sec. 3.
+ *
+ * Conventions
+ *   - Every call returns GFORS_OK (0) or a negative status; no exception crosses
+ *     the ABI.  gfors_last_error() gives a message (thread-local).
+ *   - Host arrays passed in are only read during the call.
+ *   - Device memory: the caller supplies ONE device workspace of at least
+ *     gfors_workspace_bytes() bytes and a HIP stream; the library carves all of
+ *     its device buffers out of that workspace, never frees it, and enqueues all
+ *     device work on that stream.  The workspace must stay alive until
+ *     gfors_destroy_problem().  Device pointers taken by a call (p_override,
+ *     viol_dev, obj_dev) are read/written on the same stream.
+ *   - Calls marked "async" only enqueue work; device faults surface as
+ *     GFORS_E_HIP at the next synchronising call.  A handle is not thread-safe.
+ *   - Coefficients are integers (int32), right-hand sides and costs int64;
+ *     objective values are exact int64, violation counts int32.
+ */
+#ifndef GFORS_H
+#define GFORS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GFORS_OK = 0,
+    GFORS_E_ARG = -1,         /* malformed argument (shape, index, range, NULL) */
+    GFORS_E_NONINT = -2,      /* reserved (non-integer data) */
+    GFORS_E_OOM = -3,         /* workspace too small / size beyond limits */
+    GFORS_E_HIP = -4,         /* a HIP runtime call failed */
+    GFORS_E_STATE = -5,       /* call not valid in the handle's current state */
+    GFORS_E_INFEAS_ROW = -6   /* all-zero row that no x can satisfy */
+};
+
+typedef struct gfors_problem gfors_problem;   /* opaque, owned by the library */
+
+/* Integer CSR matrix on the host.
+ *   row_ptr  int64[nrows+1], row_ptr[0] = 0, non-decreasing, row_ptr[nrows] = nnz < 2^31
+ *   col_idx  int32[nnz], each in [0, ncols)
+ *   val      int32[nnz] coefficients, or NULL meaning every coefficient is 1 */
+typedef struct {
+    int64_t nrows, ncols;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    const int32_t *val;
+} gfors_csr;
+
+/* Tunables of Algorithm 1 and Sec. 3.  gfors_default_params() fills defaults.
+ *   sigma        tau1 * tau2 <= sigma (Preprocess, Sec. 3)
+ *   tau1, tau2   explicit step sizes if > 0; else derived: Q = 0 gives
+ *                tau1 = tau2 = sqrt(sigma); Q != 0 gives tau1 = min(sqrt(sigma),
+ *                1/(2 L_max)), L_max = 2(||Q~|| + rho_max), tau2 = sigma / tau1
+ *   rho_min, rho_max, rho_delta  UpdatePenalty bounds / increment; a negative
+ *                value means "derive": with g = ||c~||_inf + ||Q~||_2 the defaults
+ *                are 1e-3 g, g and 1e-4 g
+ *   rho_T, rho_p growth constants of UpdatePenalty
+ *   k_int        sampling interval used by gfors_run_rounds()
+ *   K_max        largest K accepted by gfors_sample_eval (multiple of 64, <= 4096)
+ *   power_iters  power-iteration count for the spectral norms of Preprocess
+ *   hist_cap     rounds of incumbent history kept on the device
+ *   x0           starting point x_0 = x0 * 1 (in [0,1])
+ *   seed         Philox4x32-10 key (low 32 bits = key word 0, high = key word 1) */
+typedef struct {
+    double sigma, tau1, tau2;
+    double rho_min, rho_max, rho_T, rho_p, rho_delta;
+    int32_t k_int, K_max, power_iters, hist_cap;
+    double x0;
+    uint64_t seed;
+} gfors_params;
+
+void gfors_default_params(gfors_params *p);
+
+/* Device workspace size for a problem with these dimensions.  n variables,
+ * m1 inequality rows, m2 equality rows, nnz of A, B and Q (Q in full symmetric
+ * storage), num_instances >= 1 (block-diagonal batch). */
+int gfors_workspace_bytes(int64_t n, int64_t m1, int64_t m2, int64_t nnzA, int64_t nnzB,
+                          int64_t nnzQ, int32_t num_instances, const gfors_params *p,
+                          size_t *bytes);
+
+/* Build a problem (eq. bip) and run Preprocess (Sec. 3) on the device.
+ *   A, b     inequality rows A x >= b (A may be NULL: m1 = 0; b int64[m1])
+ *   B, d     equality rows B x = d (B may be NULL: m2 = 0; d int64[m2])
+ *   Q        symmetric quadratic term in full storage (NULL: Q = 0)
+ *   c        int64[n] linear costs
+ *   num_instances / inst_offsets  a batch of independent instances stored
+ *            block-diagonally: inst_offsets is int64[(num_instances+1)*3]
+ *            holding, per instance, the start of its (variable, inequality row,
+ *            equality row) ranges; NULL when num_instances == 1.  Every row and
+ *            every Q entry must stay inside its instance's variable range.
+ *   ws, ws_bytes, stream  device workspace and HIP stream (see Conventions)
+ * Errors: E_ARG (malformed CSR, index out of range, row crossing instances),
+ *         E_INFEAS_ROW (zero row with b_j > 0 or d_j != 0), E_OOM (workspace
+ *         too small), E_HIP.  Synchronises the stream before returning. */
+int gfors_create_problem(const gfors_csr *A, const int64_t *b,
+                         const gfors_csr *B, const int64_t *d,
+                         const gfors_csr *Q, const int64_t *c, int64_t n,
+                         int32_t num_instances, const int64_t *inst_offsets,
+                         const gfors_params *p, void *ws, size_t ws_bytes,
+                         void *stream, gfors_problem **out);
+
+void gfors_destroy_problem(gfors_problem *P);
+const char *gfors_last_error(void);
+
+/* Run nsteps PDHG iterations (Algorithm 2) at the current penalty rho of each
+ * instance.  If want_residuals != 0 the last step also computes, in FP64, the
+ * residuals of Theorem 2 and the CheckHalt gaps (read with gfors_get_residuals).
+ * Async. */
+int gfors_pdhg_steps(gfors_problem *P, int32_t nsteps, int32_t want_residuals);
+
+/* One sampling round (Algorithm 3 + EvalBest): K candidates per instance
+ * (K % 64 == 0, 64 <= K <= K_max) drawn from p = x_k, or from the caller's
+ * device array p_override (float[n], values in [0,1]; NULL = use x_k).  The
+ * uniform of candidate l, local variable i of instance t in round r is word
+ * (i & 3) of Philox4x32-10(key = seed, counter = (l, i >> 2, r, t)), taken as
+ * (U >> 8) 2^-24; candidate bit = [u < p_i].  Every candidate is evaluated
+ * exactly on the original integer data; the feasible candidate with the least
+ * objective (lowest index on ties) replaces the incumbent on strict
+ * improvement.  Then the trigger counter advances and rho follows
+ * UpdatePenalty (Sec. 3).  viol_dev (int32[T*K]) and obj_dev (int64[T*K]),
+ * if not NULL, receive the per-candidate violation counts and objectives.
+ * Async. */
+int gfors_sample_eval(gfors_problem *P, int32_t K, const float *p_override,
+                      int32_t *viol_dev, int64_t *obj_dev);
+
+/* Evaluate round(x_k) = [x_k > 1/2] (last step of Algorithm 1) and merge it
+ * into the incumbent (round id -1).  Does not advance rho.  Async. */
+int gfors_final_round(gfors_problem *P);
+
+/* nrounds x (k_int PDHG steps + one sampling round of K candidates), optionally
+ * replayed from a captured HIP graph.  Async. */
+int gfors_run_rounds(gfors_problem *P, int32_t nrounds, int32_t K, int32_t use_graph);
+
+/* Incumbent of instance `inst` (synchronises).  z_best = INT64_MAX and found = 0
+ * while no feasible candidate has been seen (z_best = +inf of Algorithm 1).
+ * x_best_host: uint8[n_inst] or NULL.  info (or NULL): int64[4] =
+ * {iteration k, round (-1 = final rounding), candidate index, triggers so far}. */
+int gfors_best(gfors_problem *P, int32_t inst, int64_t *z_best, uint8_t *x_best_host,
+               int32_t *found, int64_t *info);
+
+/* FP64 residuals of the last instrumented step, per instance:
+ * out[4*t + {0,1,2,3}] = {||s^x||_2, ||s^y||_2, primal gap, binary gap}. Syncs. */
+int gfors_get_residuals(gfors_problem *P, double *out);
+
+/* Per-round incumbent history of instance inst: z_best after each round
+ * (INT64_MAX before the first feasible one).  *count gets the rounds done. Syncs. */
+int gfors_get_history(gfors_problem *P, int32_t inst, int64_t *z_hist, int32_t cap, int32_t *count);
+
+/* Test / resume support (all synchronise).  State after iteration k:
+ * x = x_k, x_prev = x_{k-1} (float[n]), y = y_k (float[m1+m2], inequality rows
+ * first), rho (double[T]), k, rounds done, triggers done. */
+int gfors_get_state(gfors_problem *P, float *x, float *x_prev, float *y, double *rho,
+                    int64_t *k, int64_t *round, int64_t *ntrig);
+int gfors_set_state(gfors_problem *P, const float *x, const float *x_prev, const float *y,
+                    const double *rho, int64_t k, int64_t round, int64_t ntrig);
+
+/* Candidates of the last sampling round: uint64[n * K/64], word w of variable
+ * i at [i*(K/64) + w] holding candidates 64w..64w+63 (bit b = candidate 64w+b). */
+int gfors_get_candidates(gfors_problem *P, uint64_t *bits_host, int32_t *K_out);
+
+/* Preprocess results (synchronise).  row_scale double[m] = 1/||row_j||_2 (1 for a
+ * zero row); per instance (double[T] each): obj_scale s_o = ||Q||_2 + ||c||_2,
+ * K_norm s_K, Q_norm ||Q||_2 (unscaled), tau1, tau2, rho_min, rho_max, rho_delta.
+ * Any pointer may be NULL. */
+int gfors_get_scales(gfors_problem *P, double *row_scale, double *obj_scale, double *K_norm,
+                     double *Q_norm, double *tau1, double *tau2, double *rho_min,
+                     double *rho_max, double *rho_delta);
+
+/* Dimensions: n, m1, m2, number of instances. */
+int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32_t *T);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFORS_H */

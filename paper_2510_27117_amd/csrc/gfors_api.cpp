@@ -1,0 +1,986 @@
+// Host side of libgfors: ingest and validation of the integer model (eq. bip),
+// transposition, row classification and tiling, Preprocess (Sec. 3) with FP64
+// power iterations on the device, the Algorithm 1 loop pieces and HIP-graph
+// replay of whole rounds, and the C ABI declared in include/gfors.h.
+#include "gfors_internal.h"
+#include "../../include/gfors.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <limits>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace gfors;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(GFORS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kSampleTQ = 256;        // quads per sample tile (1024 variables)
+constexpr int kEvalNnz = 4096;        // nnz budget of an evaluation tile
+constexpr int kCoverRows = 128;       // rows per covering tile (max)
+constexpr int kGeneralRows = 4096;    // rows per general tile (max)
+constexpr int kQuadNnz = 4096;        // nnz budget of a Q tile
+constexpr int kQuadRows = 256;
+constexpr int kVarTile = 4096;        // variables per FP64 reduction tile
+constexpr int kRowNnz = 16384;        // nnz budget of a residual row tile
+constexpr int kRowRows = 2048;
+
+enum RowClass { kCover = 0, kGeneral = 1 };
+
+struct HostTiles {
+    std::vector<int32_t> inst, b0, b1, first;
+};
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Upper bounds on tile counts used both by the workspace size and the carve.
+struct Bounds {
+    int64_t st, et, qt, vt, rt;
+};
+Bounds tile_bounds(int64_t n, int64_t m, int64_t nnzK, int64_t nnzQ, int64_t T) {
+    Bounds b;
+    b.st = ceil_div(n / 4 + T, kSampleTQ) + T + 1;
+    // a tile closes when its weight (nnz + rows) reaches the budget or its row
+    // count reaches the cap, so tiles <= weight/budget + rows/cap + 1 per run
+    b.et = m / kCoverRows + (nnzK + m) / kEvalNnz + 4 * T + 4;
+    b.qt = n / kQuadRows + (nnzQ + n) / kQuadNnz + 2 * T + 2;
+    b.vt = n / kVarTile + T + 1;
+    b.rt = m / kRowRows + (nnzK + m) / kRowNnz + 4 * T + 4;
+    return b;
+}
+
+// Bump allocator over the caller's workspace (measure mode when base == null).
+struct Carver {
+    char *base;
+    size_t off = 0;
+    size_t cap;
+    template <class T>
+    T *take(int64_t count) {
+        off = (off + 255) & ~static_cast<size_t>(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += static_cast<size_t>(std::max<int64_t>(count, 1)) * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+struct gfors_problem {
+    hipStream_t stream = nullptr;
+    gfors_params prm{};
+    int64_t n = 0, m1 = 0, m2 = 0, m = 0, nnzK = 0, nnzQ = 0;
+    int T = 1;
+    bool unitK = true, hasQ = false, obj64 = false, acc64 = false;
+    LaunchCfg cfg;
+
+    // host copies
+    std::vector<int64_t> inst_var0, inst_nvar;
+    std::vector<double> rowinv, s_o, s_K, qnorm, tau1, tau2, rmin, rmax, rdelta;
+
+    // device buffers
+    int *rp = nullptr, *ci = nullptr, *val = nullptr;
+    int *rpT = nullptr, *ciT = nullptr, *valT = nullptr;
+    int *rpQ = nullptr, *ciQ = nullptr, *valQ = nullptr;
+    float *omega = nullptr, *rt = nullptr, *ct = nullptr;
+    double *omega64 = nullptr, *rowinv2_d = nullptr, *rowinv_d = nullptr;
+    int64_t *rhs = nullptr, *cost = nullptr;
+    int *var_inst = nullptr, *row_inst = nullptr;
+    int64_t *d_inst_var0 = nullptr, *d_inst_nvar = nullptr;
+    float *xbuf[2] = {nullptr, nullptr}, *xbar = nullptr, *xsave = nullptr;
+    float *ybuf[2] = {nullptr, nullptr}, *wy = nullptr;
+    int cur = 0;
+    uint64_t *X = nullptr;
+    int lastK = 0;
+    int64_t *zpart = nullptr, *zqpart = nullptr;
+    int *vpart = nullptr;
+    int32_t *viol = nullptr;
+    int64_t *z = nullptr;
+    uint8_t *xbest = nullptr;
+    DevCounters *ctr = nullptr;
+    DevInst di{};
+    Tiles st, et, qt, vt, rtile;
+    int *cover_ids = nullptr, *general_ids = nullptr;
+    int n_cover = 0, n_general = 0;
+    int *rows = nullptr;
+    double *pv = nullptr, *pu = nullptr, *pw = nullptr, *part = nullptr, *res = nullptr;
+    double *dnorm = nullptr;
+
+    // graphs: key = (K, parity)
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+int validate_csr(const gfors_csr *M, int64_t ncols_expect, const char *name) {
+    if (!M) return GFORS_OK;
+    if (M->nrows < 0 || M->ncols != ncols_expect)
+        return fail(GFORS_E_ARG, std::string(name) + ": ncols must equal n");
+    if (!M->row_ptr || (M->nrows > 0 && M->row_ptr[0] != 0))
+        return fail(GFORS_E_ARG, std::string(name) + ": row_ptr[0] must be 0");
+    const int64_t nnz = M->row_ptr[M->nrows];
+    if (nnz < 0 || nnz >= (int64_t{1} << 31))
+        return fail(GFORS_E_OOM, std::string(name) + ": nnz must be < 2^31");
+    if (nnz > 0 && !M->col_idx) return fail(GFORS_E_ARG, std::string(name) + ": col_idx is NULL");
+    for (int64_t r = 0; r < M->nrows; ++r)
+        if (M->row_ptr[r + 1] < M->row_ptr[r])
+            return fail(GFORS_E_ARG, std::string(name) + ": row_ptr decreases at row " + std::to_string(r));
+    for (int64_t e = 0; e < nnz; ++e)
+        if (M->col_idx[e] < 0 || M->col_idx[e] >= ncols_expect)
+            return fail(GFORS_E_ARG, std::string(name) + ": column index out of range at entry " + std::to_string(e));
+    return GFORS_OK;
+}
+
+void build_tiles_items(HostTiles &ht, int inst, int64_t count,
+                       const std::function<int64_t(int64_t)> *weight, int64_t budget,
+                       int64_t max_items, int64_t base) {
+    int64_t i = 0;
+    while (i < count) {
+        int64_t j = i, w = 0;
+        while (j < count && (j - i) < max_items && (w < budget || j == i)) {
+            w += weight ? (*weight)(j) + 1 : 1;
+            ++j;
+        }
+        ht.inst.push_back(inst);
+        ht.b0.push_back(static_cast<int32_t>(base + i));
+        ht.b1.push_back(static_cast<int32_t>(base + j));
+        i = j;
+    }
+}
+
+template <class T>
+int upload(hipStream_t s, T *dst, const T *src, int64_t count) {
+    if (count <= 0) return GFORS_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src, static_cast<size_t>(count) * sizeof(T), hipMemcpyHostToDevice, s));
+    return GFORS_OK;
+}
+
+void carve_tiles(Carver &cv, Tiles &t, int64_t count, int64_t bound, int T) {
+    t.count = static_cast<int32_t>(count);
+    t.inst = cv.take<int32_t>(bound);
+    t.b0 = cv.take<int32_t>(bound);
+    t.b1 = cv.take<int32_t>(bound);
+    t.first = cv.take<int32_t>(T + 1);
+}
+
+int upload_tiles(hipStream_t s, Tiles &t, const HostTiles &h, int T) {
+    int rc;
+    if ((rc = upload(s, t.inst, h.inst.data(), t.count))) return rc;
+    if ((rc = upload(s, t.b0, h.b0.data(), t.count))) return rc;
+    if ((rc = upload(s, t.b1, h.b1.data(), t.count))) return rc;
+    if ((rc = upload(s, t.first, h.first.data(), T + 1))) return rc;
+    return GFORS_OK;
+}
+
+void finish_first(HostTiles &h, int T) {
+    h.first.assign(T + 1, 0);
+    // tiles are appended instance by instance
+    std::vector<int32_t> cnt(T, 0);
+    for (int32_t t : h.inst) cnt[t]++;
+    for (int t = 0; t < T; ++t) h.first[t + 1] = h.first[t] + cnt[t];
+}
+
+int sync(gfors_problem *P) {
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    return GFORS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gfors_default_params(gfors_params *p) {
+    if (!p) return;
+    p->sigma = 0.99;
+    p->tau1 = -1.0;
+    p->tau2 = -1.0;
+    p->rho_min = -1.0;
+    p->rho_max = -1.0;
+    p->rho_T = 10.0;
+    p->rho_p = 2.0;
+    p->rho_delta = -1.0;
+    p->k_int = 100;
+    p->K_max = 1024;
+    p->power_iters = 200;
+    p->hist_cap = 4096;
+    p->x0 = 0.0;
+    p->seed = 0;
+}
+
+const char *gfors_last_error(void) { return g_err.c_str(); }
+
+static int check_K(int64_t K) {
+    if (K < 64 || K > 4096 || K % 64 != 0 || (K > 1024 && K % 1024 != 0)) return 0;
+    return 1;
+}
+
+// Carve every device buffer; with base == null only measures the size.
+static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t m2,
+                    int64_t nnzK, int64_t nnzQ, int T, const gfors_params *prm) {
+    const int64_t m = m1 + m2;
+    const int Wmax = prm->K_max / 64;
+    const Bounds b = tile_bounds(n, m, nnzK, nnzQ, T);
+    P->rp = cv.take<int>(m + 1);
+    P->ci = cv.take<int>(nnzK);
+    P->val = cv.take<int>(nnzK);
+    P->rpT = cv.take<int>(n + 1);
+    P->ciT = cv.take<int>(nnzK);
+    P->valT = cv.take<int>(nnzK);
+    P->rpQ = cv.take<int>(n + 1);
+    P->ciQ = cv.take<int>(nnzQ);
+    P->valQ = cv.take<int>(nnzQ);
+    P->omega = cv.take<float>(m);
+    P->rt = cv.take<float>(m);
+    P->omega64 = cv.take<double>(m);
+    P->rowinv_d = cv.take<double>(m);
+    P->rowinv2_d = cv.take<double>(m);
+    P->rhs = cv.take<int64_t>(m);
+    P->row_inst = cv.take<int>(m);
+    P->ct = cv.take<float>(n);
+    P->cost = cv.take<int64_t>(n);
+    P->var_inst = cv.take<int>(n);
+    P->d_inst_var0 = cv.take<int64_t>(T);
+    P->d_inst_nvar = cv.take<int64_t>(T);
+    P->xbuf[0] = cv.take<float>(n);
+    P->xbuf[1] = cv.take<float>(n);
+    P->xbar = cv.take<float>(n);
+    P->xsave = cv.take<float>(n);
+    P->ybuf[0] = cv.take<float>(m);
+    P->ybuf[1] = cv.take<float>(m);
+    P->wy = cv.take<float>(m);
+    P->X = cv.take<uint64_t>(n * Wmax);
+    P->xbest = cv.take<uint8_t>(n);
+    P->zpart = cv.take<int64_t>(b.st * prm->K_max);
+    P->vpart = cv.take<int>(b.et * prm->K_max);
+    P->zqpart = cv.take<int64_t>((nnzQ ? b.qt : 1) * prm->K_max);
+    P->viol = cv.take<int32_t>(static_cast<int64_t>(T) * prm->K_max);
+    P->z = cv.take<int64_t>(static_cast<int64_t>(T) * prm->K_max);
+    P->rows = cv.take<int>(m);
+    P->cover_ids = cv.take<int>(b.et);
+    P->general_ids = cv.take<int>(b.et);
+    P->pv = cv.take<double>(n);
+    P->pu = cv.take<double>(n);
+    P->pw = cv.take<double>(std::max(n, m));
+    P->part = cv.take<double>(2 * std::max(b.vt, b.rt) + 2);
+    P->res = cv.take<double>(4 * static_cast<int64_t>(T));
+    P->dnorm = cv.take<double>(2 * static_cast<int64_t>(T));
+    P->ctr = cv.take<DevCounters>(1);
+    DevInst &d = P->di;
+    d.rho = cv.take<double>(T);
+    d.ntrig = cv.take<int64_t>(T);
+    d.zbest = cv.take<int64_t>(T);
+    d.inc_k = cv.take<int64_t>(T);
+    d.inc_round = cv.take<int64_t>(T);
+    d.inc_l = cv.take<int64_t>(T);
+    d.improved = cv.take<int32_t>(T);
+    d.inc_W = cv.take<int32_t>(T);
+    d.rho_min = cv.take<double>(T);
+    d.rho_max = cv.take<double>(T);
+    d.rho_T = cv.take<double>(T);
+    d.rho_p = cv.take<double>(T);
+    d.rho_delta = cv.take<double>(T);
+    d.tau1 = cv.take<float>(T);
+    d.tau2 = cv.take<float>(T);
+    d.two_so = cv.take<float>(T);
+    d.tau1d = cv.take<double>(T);
+    d.tau2d = cv.take<double>(T);
+    d.two_sod = cv.take<double>(T);
+    d.hist_cap = std::max(1, prm->hist_cap);
+    d.hist = cv.take<int64_t>(static_cast<int64_t>(T) * d.hist_cap);
+    // tile tables are carved by upload_tiles in the same order (see create)
+    return cv.off;
+}
+
+static size_t carve_tiles_measure(Carver &cv, int64_t n, int64_t m, int64_t nnzK, int64_t nnzQ, int T) {
+    const Bounds b = tile_bounds(n, m, nnzK, nnzQ, T);
+    for (int64_t bound : {b.st, b.et, b.qt, b.vt, b.rt}) {
+        cv.take<int32_t>(bound);
+        cv.take<int32_t>(bound);
+        cv.take<int32_t>(bound);
+        cv.take<int32_t>(T + 1);
+    }
+    return cv.off;
+}
+
+int gfors_workspace_bytes(int64_t n, int64_t m1, int64_t m2, int64_t nnzA, int64_t nnzB,
+                          int64_t nnzQ, int32_t num_instances, const gfors_params *p,
+                          size_t *bytes) {
+    if (!p || !bytes || n <= 0 || m1 < 0 || m2 < 0 || nnzA < 0 || nnzB < 0 || nnzQ < 0 ||
+        num_instances < 1)
+        return fail(GFORS_E_ARG, "gfors_workspace_bytes: bad argument");
+    if (!check_K(p->K_max)) return fail(GFORS_E_ARG, "K_max must be a multiple of 64, <= 4096 (multiple of 1024 above 1024)");
+    gfors_problem tmp;
+    Carver cv{nullptr, 0, 0};
+    carve(&tmp, cv, n, m1, m2, nnzA + nnzB, nnzQ, num_instances, p);
+    carve_tiles_measure(cv, n, m1 + m2, nnzA + nnzB, nnzQ, num_instances);
+    *bytes = cv.off + 256;
+    return GFORS_OK;
+}
+
+void gfors_destroy_problem(gfors_problem *P) {
+    if (!P) return;
+    for (auto &kv : P->graphs) hipGraphExecDestroy(kv.second);
+    delete P;
+}
+
+static int device_norms(gfors_problem *P);
+
+int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *B,
+                         const int64_t *d, const gfors_csr *Q, const int64_t *c, int64_t n,
+                         int32_t num_instances, const int64_t *inst_offsets,
+                         const gfors_params *prm, void *ws, size_t ws_bytes, void *stream,
+                         gfors_problem **out) {
+    if (!out || !prm || !c || n <= 0 || num_instances < 1)
+        return fail(GFORS_E_ARG, "gfors_create_problem: NULL argument or n <= 0");
+    *out = nullptr;
+    if (!check_K(prm->K_max)) return fail(GFORS_E_ARG, "K_max must be a multiple of 64, <= 4096 (multiple of 1024 above 1024)");
+    if (!(prm->sigma > 0.0) || prm->k_int < 1 || prm->power_iters < 1 || !(prm->x0 >= 0.0 && prm->x0 <= 1.0))
+        return fail(GFORS_E_ARG, "bad params (sigma > 0, k_int >= 1, power_iters >= 1, x0 in [0,1])");
+    if (n >= (int64_t{1} << 31) / 64) return fail(GFORS_E_OOM, "n too large");
+    int rc;
+    if ((rc = validate_csr(A, n, "A"))) return rc;
+    if ((rc = validate_csr(B, n, "B"))) return rc;
+    if ((rc = validate_csr(Q, n, "Q"))) return rc;
+    if (Q && Q->nrows != n) return fail(GFORS_E_ARG, "Q must be n x n");
+    if (A && A->nrows > 0 && !b) return fail(GFORS_E_ARG, "b is NULL");
+    if (B && B->nrows > 0 && !d) return fail(GFORS_E_ARG, "d is NULL");
+    if (!ws) return fail(GFORS_E_ARG, "workspace is NULL");
+
+    auto *P = new gfors_problem();
+    std::unique_ptr<gfors_problem, void (*)(gfors_problem *)> guard(P, gfors_destroy_problem);
+    P->stream = static_cast<hipStream_t>(stream);
+    P->prm = *prm;
+    P->n = n;
+    P->m1 = A ? A->nrows : 0;
+    P->m2 = B ? B->nrows : 0;
+    P->m = P->m1 + P->m2;
+    const int64_t nnzA = A ? A->row_ptr[A->nrows] : 0;
+    const int64_t nnzB = B ? B->row_ptr[B->nrows] : 0;
+    P->nnzK = nnzA + nnzB;
+    P->nnzQ = Q ? Q->row_ptr[Q->nrows] : 0;
+    P->hasQ = P->nnzQ > 0;
+    P->T = num_instances;
+    const int T = P->T;
+    if (P->nnzK >= (int64_t{1} << 31)) return fail(GFORS_E_OOM, "nnz(A)+nnz(B) must be < 2^31");
+    if (P->m >= (int64_t{1} << 31)) return fail(GFORS_E_OOM, "too many rows");
+
+    // ---- instance ranges
+    std::vector<int64_t> off(static_cast<size_t>(3) * (T + 1), 0);
+    if (T == 1) {
+        off[3] = n;
+        off[4] = P->m1;
+        off[5] = P->m2;
+    } else {
+        if (!inst_offsets) return fail(GFORS_E_ARG, "inst_offsets is NULL with num_instances > 1");
+        std::memcpy(off.data(), inst_offsets, off.size() * sizeof(int64_t));
+        if (off[0] || off[1] || off[2] || off[3 * T] != n || off[3 * T + 1] != P->m1 || off[3 * T + 2] != P->m2)
+            return fail(GFORS_E_ARG, "inst_offsets must start at 0 and end at (n, m1, m2)");
+        for (int t = 0; t < T; ++t)
+            for (int k = 0; k < 3; ++k)
+                if (off[3 * (t + 1) + k] < off[3 * t + k]) return fail(GFORS_E_ARG, "inst_offsets must be non-decreasing");
+        for (int t = 0; t < T; ++t)
+            if (off[3 * (t + 1)] <= off[3 * t]) return fail(GFORS_E_ARG, "every instance needs >= 1 variable");
+    }
+    P->inst_var0.resize(T);
+    P->inst_nvar.resize(T);
+    std::vector<int> var_inst(n), row_inst(P->m);
+    for (int t = 0; t < T; ++t) {
+        P->inst_var0[t] = off[3 * t];
+        P->inst_nvar[t] = off[3 * (t + 1)] - off[3 * t];
+        for (int64_t i = off[3 * t]; i < off[3 * (t + 1)]; ++i) var_inst[i] = t;
+        for (int64_t j = off[3 * t + 1]; j < off[3 * (t + 1) + 1]; ++j) row_inst[j] = t;
+        for (int64_t j = off[3 * t + 2]; j < off[3 * (t + 1) + 2]; ++j) row_inst[P->m1 + j] = t;
+    }
+
+    // ---- stacked constraint CSR [A; B] with original coefficients
+    const int64_t m = P->m;
+    std::vector<int> rp(m + 1, 0), ci(P->nnzK), val(P->nnzK);
+    std::vector<int64_t> rhs(m);
+    P->unitK = (!A || !A->val) && (!B || !B->val);
+    {
+        int64_t e = 0;
+        auto add_rows = [&](const gfors_csr *M, const int64_t *r, int64_t row0) -> int {
+            if (!M) return GFORS_OK;
+            for (int64_t j = 0; j < M->nrows; ++j) {
+                const int t = row_inst[row0 + j];
+                const int64_t lo = P->inst_var0[t], hi = lo + P->inst_nvar[t];
+                for (int64_t q = M->row_ptr[j]; q < M->row_ptr[j + 1]; ++q) {
+                    const int col = M->col_idx[q];
+                    if (col < lo || col >= hi)
+                        return fail(GFORS_E_ARG, "row " + std::to_string(row0 + j) + " references a variable outside its instance");
+                    ci[e] = col;
+                    val[e] = M->val ? M->val[q] : 1;
+                    ++e;
+                }
+                rp[row0 + j + 1] = static_cast<int>(e);
+                rhs[row0 + j] = r[j];
+            }
+            return GFORS_OK;
+        };
+        if ((rc = add_rows(A, b, 0))) return rc;
+        if ((rc = add_rows(B, d, P->m1))) return rc;
+    }
+    // row norms, infeasible zero rows, classes
+    P->rowinv.assign(m, 1.0);
+    std::vector<uint8_t> cls(m);
+    for (int64_t j = 0; j < m; ++j) {
+        double sq = 0.0;
+        int64_t absum = 0;
+        bool allone = true;
+        for (int e = rp[j]; e < rp[j + 1]; ++e) {
+            sq += static_cast<double>(val[e]) * static_cast<double>(val[e]);
+            absum += std::llabs(static_cast<int64_t>(val[e]));
+            allone = allone && val[e] == 1;
+        }
+        if (rp[j + 1] == rp[j]) {
+            const bool bad = (j < P->m1) ? (rhs[j] > 0) : (rhs[j] != 0);
+            if (bad) return fail(GFORS_E_INFEAS_ROW, "row " + std::to_string(j) + " has no coefficient but cannot be satisfied");
+        }
+        const double nrm = std::sqrt(sq);
+        P->rowinv[j] = nrm > 0.0 ? 1.0 / nrm : 1.0;
+        cls[j] = (j < P->m1 && allone && rhs[j] == 1 && rp[j + 1] > rp[j]) ? kCover : kGeneral;
+        if (cls[j] == kGeneral && absum > 2147483647LL) P->acc64 = true;
+    }
+    // transpose (counting sort by column; rows ascending within a column)
+    std::vector<int> rpT(n + 1, 0), ciT(P->nnzK), valT(P->nnzK);
+    for (int64_t e = 0; e < P->nnzK; ++e) rpT[ci[e] + 1]++;
+    for (int64_t i = 0; i < n; ++i) rpT[i + 1] += rpT[i];
+    {
+        std::vector<int> pos(rpT.begin(), rpT.end() - 1);
+        for (int64_t j = 0; j < m; ++j)
+            for (int e = rp[j]; e < rp[j + 1]; ++e) {
+                const int p = pos[ci[e]]++;
+                ciT[p] = static_cast<int>(j);
+                valT[p] = val[e];
+            }
+    }
+    // Q
+    std::vector<int> rpQ, ciQ, valQ;
+    if (P->hasQ) {
+        rpQ.resize(n + 1);
+        ciQ.resize(P->nnzQ);
+        valQ.resize(P->nnzQ);
+        for (int64_t i = 0; i <= n; ++i) rpQ[i] = static_cast<int>(Q->row_ptr[i]);
+        for (int64_t e = 0; e < P->nnzQ; ++e) {
+            const int t = var_inst[std::upper_bound(rpQ.begin(), rpQ.end(), static_cast<int>(e)) - rpQ.begin() - 1];
+            ciQ[e] = Q->col_idx[e];
+            valQ[e] = Q->val ? Q->val[e] : 1;
+            if (ciQ[e] < P->inst_var0[t] || ciQ[e] >= P->inst_var0[t] + P->inst_nvar[t])
+                return fail(GFORS_E_ARG, "Q entry crosses instances");
+        }
+    }
+    // objective accumulation width in the sampler
+    int64_t cmax = 0;
+    for (int64_t i = 0; i < n; ++i) cmax = std::max<int64_t>(cmax, std::llabs(c[i]));
+    P->obj64 = cmax > 0 && (static_cast<double>(cmax) * 4.0 * kSampleTQ >= 2147483647.0);
+
+    // ---- tiles
+    HostTiles hs, he, hq, hv, hr;
+    std::vector<int> rows_list;
+    rows_list.reserve(m);
+    std::vector<int> cover_ids, general_ids;
+    for (int t = 0; t < T; ++t) {
+        const int64_t nq = ceil_div(P->inst_nvar[t], 4);
+        build_tiles_items(hs, t, nq, nullptr, kSampleTQ, kSampleTQ, 0);
+        // evaluation rows of instance t: covering rows, then general rows
+        std::vector<int> rc_list[2];
+        for (int64_t j = off[3 * t + 1]; j < off[3 * (t + 1) + 1]; ++j) rc_list[cls[j]].push_back(static_cast<int>(j));
+        for (int64_t j = off[3 * t + 2]; j < off[3 * (t + 1) + 2]; ++j) rc_list[cls[P->m1 + j]].push_back(static_cast<int>(P->m1 + j));
+        for (int k = 0; k < 2; ++k) {
+            const int64_t base = static_cast<int64_t>(rows_list.size());
+            const std::vector<int> &L = rc_list[k];
+            rows_list.insert(rows_list.end(), L.begin(), L.end());
+            std::function<int64_t(int64_t)> wfun = [&](int64_t q) -> int64_t { return rp[L[q] + 1] - rp[L[q]]; };
+            const size_t before = he.inst.size();
+            build_tiles_items(he, t, static_cast<int64_t>(L.size()), &wfun, kEvalNnz,
+                              k == kCover ? kCoverRows : kGeneralRows, base);
+            for (size_t q = before; q < he.inst.size(); ++q)
+                (k == kCover ? cover_ids : general_ids).push_back(static_cast<int>(q));
+        }
+        if (P->hasQ) {
+            const int64_t v0 = P->inst_var0[t];
+            std::function<int64_t(int64_t)> wq = [&](int64_t q) -> int64_t { return rpQ[v0 + q + 1] - rpQ[v0 + q]; };
+            build_tiles_items(hq, t, P->inst_nvar[t], &wq, kQuadNnz, kQuadRows, v0);
+        }
+        build_tiles_items(hv, t, P->inst_nvar[t], nullptr, kVarTile, kVarTile, P->inst_var0[t]);
+        for (int part = 0; part < 2; ++part) {
+            const int64_t r0 = part == 0 ? off[3 * t + 1] : P->m1 + off[3 * t + 2];
+            const int64_t r1 = part == 0 ? off[3 * (t + 1) + 1] : P->m1 + off[3 * (t + 1) + 2];
+            std::function<int64_t(int64_t)> wr = [&](int64_t q) -> int64_t { return rp[r0 + q + 1] - rp[r0 + q]; };
+            build_tiles_items(hr, t, r1 - r0, &wr, kRowNnz, kRowRows, r0);
+        }
+    }
+    for (HostTiles *h : {&hs, &he, &hq, &hv, &hr}) finish_first(*h, T);
+    P->n_cover = static_cast<int>(cover_ids.size());
+    P->n_general = static_cast<int>(general_ids.size());
+
+    // ---- carve the workspace
+    Carver cv{static_cast<char *>(ws), 0, ws_bytes};
+    // align the base
+    {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(ws);
+        cv.off = (256 - (a & 255)) & 255;
+    }
+    carve(P, cv, n, P->m1, P->m2, P->nnzK, P->nnzQ, T, prm);
+    const Bounds bnd = tile_bounds(n, m, P->nnzK, P->nnzQ, T);
+    hipStream_t s = P->stream;
+    {
+        const std::pair<Tiles *, std::pair<const HostTiles *, int64_t>> tl[5] = {
+            {&P->st, {&hs, bnd.st}}, {&P->et, {&he, bnd.et}}, {&P->qt, {&hq, bnd.qt}},
+            {&P->vt, {&hv, bnd.vt}}, {&P->rtile, {&hr, bnd.rt}}};
+        for (const auto &e : tl) {
+            if (static_cast<int64_t>(e.second.first->inst.size()) > e.second.second)
+                return fail(GFORS_E_OOM, "internal: tile bound exceeded");
+            carve_tiles(cv, *e.first, static_cast<int64_t>(e.second.first->inst.size()), e.second.second, T);
+        }
+    }
+    // nothing has touched the device yet: check the size before any copy
+    if (cv.off > ws_bytes)
+        return fail(GFORS_E_OOM, "workspace too small: need " + std::to_string(cv.off) + " bytes");
+    if ((rc = upload_tiles(s, P->st, hs, T))) return rc;
+    if ((rc = upload_tiles(s, P->et, he, T))) return rc;
+    if ((rc = upload_tiles(s, P->qt, hq, T))) return rc;
+    if ((rc = upload_tiles(s, P->vt, hv, T))) return rc;
+    if ((rc = upload_tiles(s, P->rtile, hr, T))) return rc;
+
+    // ---- uploads
+    if ((rc = upload(s, P->rp, rp.data(), m + 1))) return rc;
+    if ((rc = upload(s, P->ci, ci.data(), P->nnzK))) return rc;
+    if ((rc = upload(s, P->val, val.data(), P->nnzK))) return rc;
+    if ((rc = upload(s, P->rpT, rpT.data(), n + 1))) return rc;
+    if ((rc = upload(s, P->ciT, ciT.data(), P->nnzK))) return rc;
+    if ((rc = upload(s, P->valT, valT.data(), P->nnzK))) return rc;
+    if (P->hasQ) {
+        if ((rc = upload(s, P->rpQ, rpQ.data(), n + 1))) return rc;
+        if ((rc = upload(s, P->ciQ, ciQ.data(), P->nnzQ))) return rc;
+        if ((rc = upload(s, P->valQ, valQ.data(), P->nnzQ))) return rc;
+    }
+    if ((rc = upload(s, P->rhs, rhs.data(), m))) return rc;
+    if ((rc = upload(s, P->cost, c, n))) return rc;
+    if ((rc = upload(s, P->var_inst, var_inst.data(), n))) return rc;
+    if ((rc = upload(s, P->row_inst, row_inst.data(), m))) return rc;
+    if ((rc = upload(s, P->d_inst_var0, P->inst_var0.data(), T))) return rc;
+    if ((rc = upload(s, P->d_inst_nvar, P->inst_nvar.data(), T))) return rc;
+    if ((rc = upload(s, P->rows, rows_list.data(), m))) return rc;
+    if ((rc = upload(s, P->cover_ids, cover_ids.data(), P->n_cover))) return rc;
+    if ((rc = upload(s, P->general_ids, general_ids.data(), P->n_general))) return rc;
+    if ((rc = upload(s, P->rowinv_d, P->rowinv.data(), m))) return rc;
+    {
+        std::vector<double> r2(m);
+        for (int64_t j = 0; j < m; ++j) r2[j] = P->rowinv[j] * P->rowinv[j];
+        if ((rc = upload(s, P->rowinv2_d, r2.data(), m))) return rc;
+        if ((rc = sync(P))) return rc;   // host vectors die at scope end
+    }
+
+    // ---- Preprocess on the device: spectral norms by FP64 power iteration
+    if ((rc = device_norms(P))) return rc;
+    std::vector<double> kn(T), qn(T);
+    HIP_TRY(hipMemcpyAsync(kn.data(), P->dnorm, T * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(qn.data(), P->dnorm + T, T * sizeof(double), hipMemcpyDeviceToHost, s));
+    if ((rc = sync(P))) return rc;
+
+    P->s_o.resize(T); P->s_K.resize(T); P->qnorm.resize(T); P->tau1.resize(T); P->tau2.resize(T);
+    P->rmin.resize(T); P->rmax.resize(T); P->rdelta.resize(T);
+    std::vector<float> omega(m), rtv(m), ctv(n);
+    std::vector<double> om64(m);
+    std::vector<float> t1f(T), t2f(T), tsof(T);
+    std::vector<double> tsod(T), rT(T, prm->rho_T), rp_(T, prm->rho_p);
+    for (int t = 0; t < T; ++t) {
+        const int64_t v0 = P->inst_var0[t], nv = P->inst_nvar[t];
+        double csq = 0.0;
+        int64_t cm = 0;
+        for (int64_t i = v0; i < v0 + nv; ++i) {
+            csq += static_cast<double>(c[i]) * static_cast<double>(c[i]);
+            cm = std::max<int64_t>(cm, std::llabs(c[i]));
+        }
+        P->qnorm[t] = qn[t];
+        P->s_K[t] = kn[t];
+        P->s_o[t] = qn[t] + std::sqrt(csq);
+        const double so = P->s_o[t];
+        const double Qn = so > 0 ? qn[t] / so : 0.0;
+        const double cinf = so > 0 ? static_cast<double>(cm) / so : static_cast<double>(cm);
+        const double g = cinf + Qn;
+        P->rmin[t] = prm->rho_min >= 0 ? prm->rho_min : 1e-3 * g;
+        P->rmax[t] = prm->rho_max >= 0 ? prm->rho_max : g;
+        P->rdelta[t] = prm->rho_delta >= 0 ? prm->rho_delta : 1e-4 * g;
+        const double sq = std::sqrt(prm->sigma);
+        bool q_here = false;
+        if (P->hasQ) q_here = rpQ[v0 + nv] > rpQ[v0];
+        if (!q_here) {
+            P->tau1[t] = P->tau2[t] = sq;
+        } else {
+            const double L = 2.0 * (Qn + P->rmax[t]);
+            P->tau1[t] = std::min(sq, 1.0 / (2.0 * L));
+            P->tau2[t] = prm->sigma / P->tau1[t];
+        }
+        if (prm->tau1 > 0) P->tau1[t] = prm->tau1;
+        if (prm->tau2 > 0) P->tau2[t] = prm->tau2;
+        for (int64_t i = v0; i < v0 + nv; ++i)
+            ctv[i] = static_cast<float>(so > 0 ? static_cast<double>(c[i]) / so : static_cast<double>(c[i]));
+        t1f[t] = static_cast<float>(P->tau1[t]);
+        t2f[t] = static_cast<float>(P->tau2[t]);
+        tsod[t] = so > 0 ? 2.0 / so : 2.0;
+        tsof[t] = static_cast<float>(tsod[t]);
+    }
+    for (int64_t j = 0; j < m; ++j) {
+        const double sk = P->s_K[row_inst[j]];
+        const double w64 = sk > 0 ? P->rowinv[j] / sk : P->rowinv[j];
+        om64[j] = w64;
+        omega[j] = static_cast<float>(w64);
+        const double rr = static_cast<double>(rhs[j]) * P->rowinv[j];
+        rtv[j] = static_cast<float>(sk > 0 ? rr / sk : rr);
+    }
+    if ((rc = upload(s, P->omega, omega.data(), m))) return rc;
+    if ((rc = upload(s, P->rt, rtv.data(), m))) return rc;
+    if ((rc = upload(s, P->omega64, om64.data(), m))) return rc;
+    if ((rc = upload(s, P->ct, ctv.data(), n))) return rc;
+    DevInst &di = P->di;
+    if ((rc = upload(s, di.rho_min, P->rmin.data(), T))) return rc;
+    if ((rc = upload(s, di.rho_max, P->rmax.data(), T))) return rc;
+    if ((rc = upload(s, di.rho_delta, P->rdelta.data(), T))) return rc;
+    if ((rc = upload(s, di.rho_T, rT.data(), T))) return rc;
+    if ((rc = upload(s, di.rho_p, rp_.data(), T))) return rc;
+    if ((rc = upload(s, di.rho, P->rmin.data(), T))) return rc;
+    if ((rc = upload(s, di.tau1, t1f.data(), T))) return rc;
+    if ((rc = upload(s, di.tau2, t2f.data(), T))) return rc;
+    if ((rc = upload(s, di.two_so, tsof.data(), T))) return rc;
+    if ((rc = upload(s, di.tau1d, P->tau1.data(), T))) return rc;
+    if ((rc = upload(s, di.tau2d, P->tau2.data(), T))) return rc;
+    if ((rc = upload(s, di.two_sod, tsod.data(), T))) return rc;
+    {
+        std::vector<int64_t> zeros(T, 0), big(T, INT64_MAX), neg(T, -2);
+        std::vector<int32_t> z32(T, 0);
+        if ((rc = upload(s, di.ntrig, zeros.data(), T))) return rc;
+        if ((rc = upload(s, di.zbest, big.data(), T))) return rc;
+        if ((rc = upload(s, di.inc_k, neg.data(), T))) return rc;
+        if ((rc = upload(s, di.inc_round, neg.data(), T))) return rc;
+        if ((rc = upload(s, di.inc_l, neg.data(), T))) return rc;
+        if ((rc = upload(s, di.improved, z32.data(), T))) return rc;
+        if ((rc = upload(s, di.inc_W, z32.data(), T))) return rc;
+        std::vector<int64_t> h(static_cast<size_t>(T) * di.hist_cap, INT64_MAX);
+        if ((rc = upload(s, di.hist, h.data(), static_cast<int64_t>(h.size())))) return rc;
+        DevCounters c0{};
+        if ((rc = upload(s, P->ctr, &c0, 1))) return rc;
+        std::vector<uint8_t> xb(n, 0);
+        if ((rc = upload(s, P->xbest, xb.data(), n))) return rc;
+        if ((rc = sync(P))) return rc;
+    }
+    launch_fill_f32(s, P->xbuf[0], static_cast<float>(prm->x0), n);
+    launch_fill_f32(s, P->xbuf[1], static_cast<float>(prm->x0), n);
+    launch_fill_f32(s, P->xbar, static_cast<float>(prm->x0), n);
+    launch_fill_f32(s, P->ybuf[0], 0.f, m);
+    launch_fill_f32(s, P->ybuf[1], 0.f, m);
+    launch_fill_f32(s, P->wy, 0.f, m);
+    HIP_TRY(hipGetLastError());
+    // launch shapes: lanes per row ~ average row length (rounded to a power of two)
+    auto pick = [](double avg) {
+        int l = 1;
+        while (l < 64 && l * 2 <= avg) l *= 2;
+        return l;
+    };
+    P->cfg.lpr_dual = pick(m ? static_cast<double>(P->nnzK) / m : 1.0);
+    P->cfg.lpr_primal = pick(static_cast<double>(P->nnzK + P->nnzQ) / n);
+    if ((rc = sync(P))) return rc;
+    *out = guard.release();
+    return GFORS_OK;
+}
+
+// FP64 power iterations (Preprocess, Sec. 3): per instance,
+//   ||K||_2 of the row-normalised K and ||Q||_2, from v0 = 1/sqrt(n_t) 1.
+static int device_norms(gfors_problem *P) {
+    hipStream_t s = P->stream;
+    const int T = P->T;
+    auto init_v = [&](double *v) {
+        for (int t = 0; t < T; ++t)
+            launch_fill64(s, v + P->inst_var0[t], 1.0 / std::sqrt(static_cast<double>(P->inst_nvar[t])), P->inst_nvar[t]);
+    };
+    // constraint matrix: M = -diag(rowinv) [A;B]; M^T M v = A^T (rowinv^2 o (A v))
+    if (P->nnzK) {
+        double *v = P->pv, *u = P->pu;
+        init_v(v);
+        for (int it = 0; it < P->prm.power_iters; ++it) {
+            launch_spmv64(s, static_cast<int>(P->m), P->rp, P->ci, P->unitK ? nullptr : P->val, P->rowinv2_d, v, P->pw);
+            launch_spmv64(s, static_cast<int>(P->n), P->rpT, P->ciT, P->unitK ? nullptr : P->valT, nullptr, P->pw, u);
+            launch_tile_sumsq(s, P->vt, u, P->part);
+            launch_inst_sum(s, T, P->vt, P->part, 1, 0, P->dnorm, 1, true);
+            launch_tile_scale_inv(s, P->vt, u, P->dnorm);
+            std::swap(u, v);
+        }
+        launch_spmv64(s, static_cast<int>(P->m), P->rp, P->ci, P->unitK ? nullptr : P->val, P->rowinv_d, v, P->pw);
+        launch_tile_sumsq(s, P->rtile, P->pw, P->part);
+        launch_inst_sum(s, T, P->rtile, P->part, 1, 0, P->dnorm, 1, true);
+    } else {
+        launch_fill64(s, P->dnorm, 0.0, T);
+    }
+    if (P->hasQ) {
+        double *v = P->pv, *u = P->pu;
+        init_v(v);
+        for (int it = 0; it < P->prm.power_iters; ++it) {
+            launch_spmv64(s, static_cast<int>(P->n), P->rpQ, P->ciQ, P->valQ, nullptr, v, P->pw);
+            launch_spmv64(s, static_cast<int>(P->n), P->rpQ, P->ciQ, P->valQ, nullptr, P->pw, u);
+            launch_tile_sumsq(s, P->vt, u, P->part);
+            launch_inst_sum(s, T, P->vt, P->part, 1, 0, P->dnorm + T, 1, true);
+            launch_tile_scale_inv(s, P->vt, u, P->dnorm + T);
+            std::swap(u, v);
+        }
+        launch_spmv64(s, static_cast<int>(P->n), P->rpQ, P->ciQ, P->valQ, nullptr, v, P->pw);
+        launch_tile_sumsq(s, P->vt, P->pw, P->part);
+        launch_inst_sum(s, T, P->vt, P->part, 1, 0, P->dnorm + T, 1, true);
+    } else {
+        launch_fill64(s, P->dnorm + T, 0.0, T);
+    }
+    HIP_TRY(hipGetLastError());
+    return GFORS_OK;
+}
+
+static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res) {
+    hipStream_t s = P->stream;
+    const bool batched = P->T > 1;
+    const int kmode = P->m == 0 ? 0 : (P->unitK ? 1 : 2);
+    for (int it = 0; it < nsteps; ++it) {
+        const bool res = want_res && it == nsteps - 1;
+        if (res) launch_copy_f32(s, P->xsave, P->xbar, P->n);
+        const int a = P->cur, bnext = 1 - P->cur;
+        if (P->m > 0)
+            launch_dual(s, P->cfg.lpr_dual, P->unitK, batched, static_cast<int>(P->m),
+                        static_cast<int>(P->m1), P->rp, P->ci, P->val, P->omega, P->rt, P->xbar,
+                        P->ybuf[a], P->ybuf[bnext], P->wy, static_cast<float>(P->tau2[0]),
+                        P->di.tau2, P->row_inst);
+        launch_primal(s, P->cfg.lpr_primal, kmode, P->hasQ, batched, static_cast<int>(P->n),
+                      P->rpT, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, P->xbuf[a],
+                      P->xbuf[bnext], P->xbar, P->ct, static_cast<float>(P->tau1[0]),
+                      static_cast<float>(P->s_o[0] > 0 ? 2.0 / P->s_o[0] : 2.0), P->di.tau1,
+                      P->di.two_so, P->di.rho, P->var_inst, P->ctr);
+        if (res) {
+            const int T = P->T;
+            launch_res_vars(s, P->vt, P->hasQ ? P->rpQ : nullptr, P->ciQ, P->valQ, P->xbuf[bnext],
+                            P->xbuf[a], P->di.rho, P->di.tau1d, P->di.two_sod, P->part);
+            launch_inst_sum(s, T, P->vt, P->part, 2, 0, P->res + 0, 4, true);
+            launch_inst_sum(s, T, P->vt, P->part, 2, 1, P->res + 3, 4, false);
+            if (P->m > 0) {
+                launch_res_rows(s, P->rtile, static_cast<int>(P->m1), P->rp, P->ci,
+                                P->unitK ? nullptr : P->val, P->omega64, P->rhs, P->xsave,
+                                P->xbuf[bnext], P->ybuf[a], P->ybuf[bnext], P->di.tau2d, P->part);
+                launch_inst_sum(s, T, P->rtile, P->part, 2, 0, P->res + 1, 4, true);
+                launch_inst_sum(s, T, P->rtile, P->part, 2, 1, P->res + 2, 4, true);
+            } else {
+                for (int t = 0; t < T; ++t) {
+                    launch_fill64(s, P->res + 4 * t + 1, 0.0, 2);
+                }
+            }
+        }
+        P->cur = bnext;
+    }
+}
+
+static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override, int threshold) {
+    hipStream_t s = P->stream;
+    const int W = K / 64;
+    const float *p = p_override ? p_override : P->xbuf[P->cur];
+    launch_sample(s, W, P->obj64, p, P->cost, P->X, P->st, P->d_inst_var0, P->d_inst_nvar,
+                  P->zpart, K, static_cast<uint32_t>(P->prm.seed & 0xffffffffu),
+                  static_cast<uint32_t>(P->prm.seed >> 32), P->ctr, threshold);
+    launch_eval_cover(s, P->n_cover, P->cover_ids, P->et, P->rows, P->rp, P->ci, P->X, W, P->vpart, K);
+    launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
+                        P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X, W,
+                        P->vpart, K);
+    if (P->hasQ) launch_eval_quad(s, P->qt, P->d_inst_var0, P->rpQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K);
+    launch_reduce_cand(s, P->T, K, P->et, P->vpart, P->st, P->zpart, P->qt, P->zqpart,
+                       P->hasQ ? 1 : 0, P->viol, P->z);
+    launch_argmin_update(s, P->T, K, W, P->viol, P->z, P->di, P->ctr, threshold ? 0 : 1);
+    launch_extract_best(s, P->n, P->T, P->var_inst, P->d_inst_var0, P->X, P->di, P->xbest);
+    P->lastK = K;
+}
+
+int gfors_pdhg_steps(gfors_problem *P, int32_t nsteps, int32_t want_residuals) {
+    if (!P || nsteps < 0) return fail(GFORS_E_ARG, "gfors_pdhg_steps: bad argument");
+    if (nsteps == 0) return GFORS_OK;
+    enqueue_steps(P, nsteps, want_residuals != 0);
+    HIP_TRY(hipGetLastError());
+    return GFORS_OK;
+}
+
+int gfors_sample_eval(gfors_problem *P, int32_t K, const float *p_override, int32_t *viol_dev,
+                      int64_t *obj_dev) {
+    if (!P) return fail(GFORS_E_ARG, "NULL handle");
+    if (!check_K(K) || K > P->prm.K_max)
+        return fail(GFORS_E_ARG, "K must be a multiple of 64 in [64, K_max] (multiple of 1024 above 1024)");
+    enqueue_sample_eval(P, K, p_override, 0);
+    const size_t cnt = static_cast<size_t>(P->T) * K;
+    if (viol_dev) HIP_TRY(hipMemcpyAsync(viol_dev, P->viol, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice, P->stream));
+    if (obj_dev) HIP_TRY(hipMemcpyAsync(obj_dev, P->z, cnt * sizeof(int64_t), hipMemcpyDeviceToDevice, P->stream));
+    HIP_TRY(hipGetLastError());
+    return GFORS_OK;
+}
+
+int gfors_final_round(gfors_problem *P) {
+    if (!P) return fail(GFORS_E_ARG, "NULL handle");
+    enqueue_sample_eval(P, 64, nullptr, 1);
+    HIP_TRY(hipGetLastError());
+    return GFORS_OK;
+}
+
+int gfors_run_rounds(gfors_problem *P, int32_t nrounds, int32_t K, int32_t use_graph) {
+    if (!P || nrounds < 0) return fail(GFORS_E_ARG, "gfors_run_rounds: bad argument");
+    if (!check_K(K) || K > P->prm.K_max) return fail(GFORS_E_ARG, "bad K");
+    for (int r = 0; r < nrounds; ++r) {
+        if (!use_graph) {
+            enqueue_steps(P, P->prm.k_int, false);
+            enqueue_sample_eval(P, K, nullptr, 0);
+            continue;
+        }
+        const auto key = std::make_pair(static_cast<int>(K), P->cur);
+        auto it = P->graphs.find(key);
+        const int cur0 = P->cur;
+        if (it == P->graphs.end()) {
+            hipGraph_t g;
+            HIP_TRY(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+            enqueue_steps(P, P->prm.k_int, false);
+            enqueue_sample_eval(P, K, nullptr, 0);
+            HIP_TRY(hipStreamEndCapture(P->stream, &g));
+            hipGraphExec_t ge;
+            HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+            HIP_TRY(hipGraphDestroy(g));
+            it = P->graphs.emplace(key, ge).first;
+            P->cur = cur0;   // capture did not execute; replay below advances the state
+        }
+        HIP_TRY(hipGraphLaunch(it->second, P->stream));
+        P->cur = (cur0 + P->prm.k_int) & 1;
+        P->lastK = K;
+    }
+    HIP_TRY(hipGetLastError());
+    return GFORS_OK;
+}
+
+int gfors_best(gfors_problem *P, int32_t inst, int64_t *z_best, uint8_t *x_best_host,
+               int32_t *found, int64_t *info) {
+    if (!P || inst < 0 || inst >= P->T) return fail(GFORS_E_ARG, "gfors_best: bad instance");
+    int64_t zb, k, r, l, nt;
+    hipStream_t s = P->stream;
+    HIP_TRY(hipMemcpyAsync(&zb, P->di.zbest + inst, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&k, P->di.inc_k + inst, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&r, P->di.inc_round + inst, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&l, P->di.inc_l + inst, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&nt, P->di.ntrig + inst, 8, hipMemcpyDeviceToHost, s));
+    if (x_best_host)
+        HIP_TRY(hipMemcpyAsync(x_best_host, P->xbest + P->inst_var0[inst], P->inst_nvar[inst],
+                               hipMemcpyDeviceToHost, s));
+    int rc = sync(P);
+    if (rc) return rc;
+    if (z_best) *z_best = zb;
+    if (found) *found = zb != INT64_MAX ? 1 : 0;
+    if (info) { info[0] = k; info[1] = r; info[2] = l; info[3] = nt; }
+    return GFORS_OK;
+}
+
+int gfors_get_residuals(gfors_problem *P, double *out) {
+    if (!P || !out) return fail(GFORS_E_ARG, "bad argument");
+    HIP_TRY(hipMemcpyAsync(out, P->res, 4 * P->T * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    return sync(P);
+}
+
+int gfors_get_history(gfors_problem *P, int32_t inst, int64_t *z_hist, int32_t cap, int32_t *count) {
+    if (!P || inst < 0 || inst >= P->T || !z_hist || cap < 0) return fail(GFORS_E_ARG, "bad argument");
+    DevCounters c;
+    HIP_TRY(hipMemcpyAsync(&c, P->ctr, sizeof(c), hipMemcpyDeviceToHost, P->stream));
+    const int32_t ncopy = std::min<int32_t>(cap, P->di.hist_cap);
+    HIP_TRY(hipMemcpyAsync(z_hist, P->di.hist + static_cast<int64_t>(inst) * P->di.hist_cap,
+                           ncopy * sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+    int rc = sync(P);
+    if (rc) return rc;
+    if (count) *count = static_cast<int32_t>(c.round);
+    return GFORS_OK;
+}
+
+int gfors_get_state(gfors_problem *P, float *x, float *x_prev, float *y, double *rho,
+                    int64_t *k, int64_t *round, int64_t *ntrig) {
+    if (!P) return fail(GFORS_E_ARG, "NULL handle");
+    hipStream_t s = P->stream;
+    if (x) HIP_TRY(hipMemcpyAsync(x, P->xbuf[P->cur], P->n * 4, hipMemcpyDeviceToHost, s));
+    if (x_prev) HIP_TRY(hipMemcpyAsync(x_prev, P->xbuf[1 - P->cur], P->n * 4, hipMemcpyDeviceToHost, s));
+    if (y && P->m) HIP_TRY(hipMemcpyAsync(y, P->ybuf[P->cur], P->m * 4, hipMemcpyDeviceToHost, s));
+    if (rho) HIP_TRY(hipMemcpyAsync(rho, P->di.rho, P->T * 8, hipMemcpyDeviceToHost, s));
+    DevCounters c;
+    int64_t nt = 0;
+    HIP_TRY(hipMemcpyAsync(&c, P->ctr, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&nt, P->di.ntrig, 8, hipMemcpyDeviceToHost, s));
+    int rc = sync(P);
+    if (rc) return rc;
+    if (k) *k = c.k;
+    if (round) *round = c.round;
+    if (ntrig) *ntrig = nt;
+    return GFORS_OK;
+}
+
+int gfors_set_state(gfors_problem *P, const float *x, const float *x_prev, const float *y,
+                    const double *rho, int64_t k, int64_t round, int64_t ntrig) {
+    if (!P || !x || !x_prev || (P->m && !y) || !rho) return fail(GFORS_E_ARG, "bad argument");
+    hipStream_t s = P->stream;
+    HIP_TRY(hipMemcpyAsync(P->xbuf[P->cur], x, P->n * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(P->xbuf[1 - P->cur], x_prev, P->n * 4, hipMemcpyHostToDevice, s));
+    if (P->m) HIP_TRY(hipMemcpyAsync(P->ybuf[P->cur], y, P->m * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(P->di.rho, rho, P->T * 8, hipMemcpyHostToDevice, s));
+    std::vector<int64_t> nt(P->T, ntrig);
+    HIP_TRY(hipMemcpyAsync(P->di.ntrig, nt.data(), P->T * 8, hipMemcpyHostToDevice, s));
+    DevCounters c{};
+    c.k = k;
+    c.round = round;
+    HIP_TRY(hipMemcpyAsync(P->ctr, &c, sizeof(c), hipMemcpyHostToDevice, s));
+    launch_set_xbar(s, P->n, P->xbuf[P->cur], P->xbuf[1 - P->cur], P->xbar);
+    HIP_TRY(hipGetLastError());
+    return sync(P);
+}
+
+int gfors_get_candidates(gfors_problem *P, uint64_t *bits_host, int32_t *K_out) {
+    if (!P) return fail(GFORS_E_ARG, "NULL handle");
+    if (!P->lastK) return fail(GFORS_E_STATE, "no sampling round yet");
+    if (K_out) *K_out = P->lastK;
+    if (bits_host)
+        HIP_TRY(hipMemcpyAsync(bits_host, P->X, P->n * (P->lastK / 64) * 8, hipMemcpyDeviceToHost, P->stream));
+    return sync(P);
+}
+
+int gfors_get_scales(gfors_problem *P, double *row_scale, double *obj_scale, double *K_norm,
+                     double *Q_norm, double *tau1, double *tau2, double *rho_min, double *rho_max,
+                     double *rho_delta) {
+    if (!P) return fail(GFORS_E_ARG, "NULL handle");
+    const size_t T = P->T;
+    if (row_scale) std::copy(P->rowinv.begin(), P->rowinv.end(), row_scale);
+    if (obj_scale) std::copy(P->s_o.begin(), P->s_o.begin() + T, obj_scale);
+    if (K_norm) std::copy(P->s_K.begin(), P->s_K.begin() + T, K_norm);
+    if (Q_norm) std::copy(P->qnorm.begin(), P->qnorm.begin() + T, Q_norm);
+    if (tau1) std::copy(P->tau1.begin(), P->tau1.begin() + T, tau1);
+    if (tau2) std::copy(P->tau2.begin(), P->tau2.begin() + T, tau2);
+    if (rho_min) std::copy(P->rmin.begin(), P->rmin.begin() + T, rho_min);
+    if (rho_max) std::copy(P->rmax.begin(), P->rmax.begin() + T, rho_max);
+    if (rho_delta) std::copy(P->rdelta.begin(), P->rdelta.begin() + T, rho_delta);
+    return GFORS_OK;
+}
+
+int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32_t *T) {
+    if (!P) return fail(GFORS_E_ARG, "NULL handle");
+    if (n) *n = P->n;
+    if (m1) *m1 = P->m1;
+    if (m2) *m2 = P->m2;
+    if (T) *T = P->T;
+    return GFORS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal declarations shared by the gfors host code and its HIP kernels.
+// Device data layout (all carved from the caller's workspace):
+//   constraint rows  : CSR of the ORIGINAL integer coefficients of [A; B]
+//                      (inequality rows first), int32 row_ptr / col / val
+//                      (val absent when every coefficient is 1); its
+//                      transpose (one row per variable) for K^T y without
+//                      atomics; Q in full symmetric CSR.
+//   PDHG vectors     : x double-buffered (x_{k-1}, x_k), xbar, y double-
+//                      buffered, wy = omega o y, FP32; omega_j = 1/(||a_j|| s_K)
+//                      and rt_j = r_j omega_j per row; ct = c / s_o per variable.
+//   candidates       : bit-packed, variable-major uint64 [n][K/64].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gfors {
+
+// Philox4x32-10 constants (Salmon et al., SC'11).
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+// Per-problem scalars that kernels read from device memory (so that captured
+// graphs stay valid as the loop advances).
+struct DevCounters {
+    int64_t k;       // PDHG iterations done
+    int64_t round;   // Philox sampling rounds done
+    int64_t pad[6];
+};
+
+// Per-instance device arrays.
+struct DevInst {
+    double *rho;          // current penalty rho_n
+    int64_t *ntrig;       // triggers so far (n of UpdatePenalty)
+    int64_t *zbest;       // incumbent objective (INT64_MAX = none)
+    int64_t *inc_k, *inc_round, *inc_l;
+    int32_t *improved;    // set by the last incumbent update
+    int32_t *inc_W;       // words-per-variable of the round that produced the incumbent
+    double *rho_min, *rho_max, *rho_T, *rho_p, *rho_delta;
+    float *tau1, *tau2, *two_so;   // per-instance FP32 scalars (batched kernels)
+    double *tau1d, *tau2d, *two_sod;
+    int64_t *hist;        // [T][hist_cap] incumbent after each round
+    int32_t hist_cap;
+};
+
+// Tile tables.  A tile is a piece of work that never crosses an instance.
+struct Tiles {
+    int32_t count = 0;
+    int32_t *inst = nullptr;   // instance of each tile
+    int32_t *b0 = nullptr;     // begin (quad / list position / row / var)
+    int32_t *b1 = nullptr;     // end
+    int32_t *first = nullptr;  // [T+1] first tile of each instance (tiles sorted by instance)
+};
+
+struct LaunchCfg {
+    int lpr_dual = 16;     // lanes per row for the dual SpMV
+    int lpr_primal = 4;    // lanes per row for the transposed SpMV (+Q)
+};
+
+// ------------------------------------------------------------------ PDHG
+void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
+                 const int *rp, const int *ci, const int *val, const float *omega,
+                 const float *rt, const float *xbar, const float *y_in, float *y_out,
+                 float *wy, float tau2, const float *tau2_inst, const int *row_inst);
+
+void launch_primal(hipStream_t s, int lpr, int kmode, bool hasq, bool batched, int n,
+                   const int *rpT, const int *ciT, const int *valT, const float *wy,
+                   const int *rpQ, const int *ciQ, const int *valQ, const float *x_in,
+                   float *x_out, float *xbar, const float *ct, float tau1, float two_so,
+                   const float *tau1_inst, const float *two_so_inst, const double *rho,
+                   const int *var_inst, DevCounters *ctr);
+
+void launch_copy_f32(hipStream_t s, float *dst, const float *src, int64_t n);
+void launch_set_xbar(hipStream_t s, int64_t n, const float *x, const float *xp, float *xbar);
+void launch_fill_f32(hipStream_t s, float *dst, float v, int64_t n);
+
+// ------------------------------------------------- FP64 (Preprocess, residuals)
+void launch_spmv64(hipStream_t s, int nrows, const int *rp, const int *ci, const int *val,
+                   const double *rowscale, const double *v, double *w);
+void launch_scale64(hipStream_t s, int64_t n, double *x, const double *a, double sign);
+void launch_fill64(hipStream_t s, double *x, double v, int64_t n);
+void launch_tile_sumsq(hipStream_t s, const Tiles &t, const double *x, double *part);
+void launch_inst_sum(hipStream_t s, int T, const Tiles &t, const double *part, int stride,
+                     int comp, double *out, int out_stride, bool take_sqrt);
+void launch_tile_scale_inv(hipStream_t s, const Tiles &t, double *x, const double *nrm);
+
+void launch_res_rows(hipStream_t s, const Tiles &rt, int m1, const int *rp, const int *ci,
+                     const int *val, const double *omega64, const int64_t *rhs,
+                     const float *xsave, const float *x, const float *y_prev,
+                     const float *y, const double *tau2d, double *part);
+void launch_res_vars(hipStream_t s, const Tiles &vt, const int *rpQ, const int *ciQ,
+                     const int *valQ, const float *x, const float *xp, const double *rho,
+                     const double *tau1d, const double *two_sod, double *part);
+
+// --------------------------------------------------------- sampling / eval
+void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64_t *cost,
+                   uint64_t *X, const Tiles &st, const int64_t *inst_var0,
+                   const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,
+                   uint32_t key1, const DevCounters *ctr, int threshold_mode);
+
+void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
+                       const int *rows, const int *rp, const int *ci, const uint64_t *X,
+                       int W, int *vpart, int K);
+void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
+                         bool acc64, const int *rows, const int *rp, const int *ci,
+                         const int *val, const int64_t *rhs, int m1, const uint64_t *X,
+                         int W, int *vpart, int K);
+void launch_eval_quad(hipStream_t s, const Tiles &qt, const int64_t *inst_var0,
+                      const int *rpQ, const int *ciQ, const int *valQ, const uint64_t *X,
+                      int W, int64_t *zqpart, int K);
+void launch_reduce_cand(hipStream_t s, int T, int K, const Tiles &et, const int *vpart,
+                        const Tiles &st, const int64_t *zpart, const Tiles &qt,
+                        const int64_t *zqpart, int has_q, int32_t *viol, int64_t *z);
+void launch_argmin_update(hipStream_t s, int T, int K, int W, const int32_t *viol,
+                          const int64_t *z, DevInst di, DevCounters *ctr, int advance);
+void launch_extract_best(hipStream_t s, int64_t n, int T, const int *var_inst,
+                         const int64_t *inst_var0, const uint64_t *X, DevInst di,
+                         uint8_t *xbest);
+
+}  // namespace gfors

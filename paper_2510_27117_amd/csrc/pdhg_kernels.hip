@@ -1,0 +1,417 @@
+// PDHG kernels (Algorithm 2), the FP64 power iteration of Preprocess (Sec. 3)
+// and the FP64 residuals of Theorem 2 / CheckHalt (Sec. 3), for gfx950.
+//
+// SpMV mapping: a group of LPR lanes (a power of two, LPR | 64) owns one CSR
+// row; the lanes stride through the row so that consecutive lanes read
+// consecutive column indices (coalesced), partial sums are combined with
+// cross-lane xor-shuffles inside the wavefront.  No atomics anywhere: the
+// transposed product K^T y runs over a second CSR holding K^T.
+#include "gfors_internal.h"
+
+namespace gfors {
+
+template <int LPR, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LPR);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Dual step: y_k = Pi( y_{k-1} + tau2 (K~ xbar_{k-1} + r~) ).
+// With K~_j = -omega_j a_j and r~_j = omega_j r_j this is
+//   t_j = rt_j - omega_j * sum_i a_ji xbar_i,   y_j <- y_j + tau2 t_j,
+// projected onto R_+ for inequality rows (j < m1).  Also writes
+// wy_j = omega_j y_j, which the primal step multiplies by the integer a_ji.
+// ---------------------------------------------------------------------------
+template <int LPR, bool UNIT, bool BATCH>
+__global__ void __launch_bounds__(256)
+k_dual(int m, int m1, const int *__restrict__ rp, const int *__restrict__ ci,
+       const int *__restrict__ val, const float *__restrict__ omega,
+       const float *__restrict__ rt, const float *__restrict__ xbar,
+       const float *__restrict__ y_in, float *__restrict__ y_out, float *__restrict__ wy,
+       float tau2, const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = tid / LPR;
+    const int sub = tid & (LPR - 1);
+    float s = 0.f;
+    if (row < m) {
+        const int e1 = rp[row + 1];
+        for (int e = rp[row] + sub; e < e1; e += LPR) {
+            const float xv = xbar[ci[e]];
+            if (UNIT) s += xv;
+            else s = fmaf(static_cast<float>(val[e]), xv, s);
+        }
+    }
+    s = group_sum<LPR>(s);
+    if (row < m && sub == 0) {
+        const float om = omega[row];
+        const float t = rt[row] - om * s;
+        const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
+        float y = y_in[row] + ta * t;
+        if (row < m1) y = fmaxf(y, 0.f);
+        y_out[row] = y;
+        wy[row] = om * y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Primal step:
+//   delta_i = c~_i + rho - sum_j a_ji wy_j + (2/s_o) sum_k Q_ik x_k - 2 rho x_i
+//   x_k = clip(x_{k-1} - tau1 delta, 0, 1),   xbar_k = 2 x_k - x_{k-1}
+// (K~^T y = -sum_j a_ji omega_j y_j; Q~ = Q / s_o.)  The gradient uses x_{k-1},
+// read from x_in while x_out receives x_k (double buffer).
+// KMODE: 0 = no constraint rows, 1 = unit coefficients, 2 = int32 values.
+// ---------------------------------------------------------------------------
+template <int LPR, int KMODE, bool HASQ, bool BATCH>
+__global__ void __launch_bounds__(256)
+k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ ciT,
+         const int *__restrict__ valT, const float *__restrict__ wy,
+         const int *__restrict__ rpQ, const int *__restrict__ ciQ, const int *__restrict__ valQ,
+         const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ xbar,
+         const float *__restrict__ ct, float tau1, float two_so,
+         const float *__restrict__ tau1_inst, const float *__restrict__ two_so_inst,
+         const double *__restrict__ rho, const int *__restrict__ var_inst,
+         DevCounters *__restrict__ ctr) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = tid / LPR;
+    const int sub = tid & (LPR - 1);
+    float s1 = 0.f, s2 = 0.f;
+    if (i < n) {
+        if (KMODE != 0) {
+            const int e1 = rpT[i + 1];
+            for (int e = rpT[i] + sub; e < e1; e += LPR) {
+                const float w = wy[ciT[e]];
+                if (KMODE == 1) s1 += w;
+                else s1 = fmaf(static_cast<float>(valT[e]), w, s1);
+            }
+        }
+        if (HASQ) {
+            const int e1 = rpQ[i + 1];
+            for (int e = rpQ[i] + sub; e < e1; e += LPR)
+                s2 = fmaf(static_cast<float>(valQ[e]), x_in[ciQ[e]], s2);
+        }
+    }
+    if (KMODE != 0) s1 = group_sum<LPR>(s1);
+    if (HASQ) s2 = group_sum<LPR>(s2);
+    if (i < n && sub == 0) {
+        const int t = BATCH ? var_inst[i] : 0;
+        const float rh = static_cast<float>(rho[t]);
+        const float ta = BATCH ? tau1_inst[t] : tau1;
+        const float xi = x_in[i];
+        float g = ct[i] + rh;
+        if (KMODE != 0) g -= s1;
+        if (HASQ) g = fmaf(BATCH ? two_so_inst[t] : two_so, s2, g);
+        g -= 2.f * rh * xi;
+        const float xn = fminf(fmaxf(xi - ta * g, 0.f), 1.f);
+        x_out[i] = xn;
+        xbar[i] = 2.f * xn - xi;
+    }
+    if (tid == 0) ctr->k += 1;
+}
+
+template <int LPR>
+static void dual_lpr(hipStream_t s, bool unit, bool batched, int m, int m1, const int *rp,
+                     const int *ci, const int *val, const float *omega, const float *rt,
+                     const float *xbar, const float *y_in, float *y_out, float *wy, float tau2,
+                     const float *tau2_inst, const int *row_inst) {
+    const int64_t threads = static_cast<int64_t>(m) * LPR;
+    const int blocks = static_cast<int>((threads + 255) / 256);
+    if (blocks == 0) return;
+#define GF_DUAL(U, B) \
+    k_dual<LPR, U, B><<<blocks, 256, 0, s>>>(m, m1, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
+    if (unit) { if (batched) GF_DUAL(true, true); else GF_DUAL(true, false); }
+    else { if (batched) GF_DUAL(false, true); else GF_DUAL(false, false); }
+#undef GF_DUAL
+}
+
+void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
+                 const int *rp, const int *ci, const int *val, const float *omega,
+                 const float *rt, const float *xbar, const float *y_in, float *y_out,
+                 float *wy, float tau2, const float *tau2_inst, const int *row_inst) {
+    switch (lpr) {
+#define GF_CASE(L) case L: dual_lpr<L>(s, unit, batched, m, m1, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst); break;
+        GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
+#undef GF_CASE
+        default: break;
+    }
+}
+
+template <int LPR, int KMODE, bool HASQ>
+static void primal_k(hipStream_t s, bool batched, int n, const int *rpT, const int *ciT,
+                     const int *valT, const float *wy, const int *rpQ, const int *ciQ,
+                     const int *valQ, const float *x_in, float *x_out, float *xbar,
+                     const float *ct, float tau1, float two_so, const float *tau1_inst,
+                     const float *two_so_inst, const double *rho, const int *var_inst,
+                     DevCounters *ctr) {
+    const int64_t threads = static_cast<int64_t>(n) * LPR;
+    const int blocks = static_cast<int>((threads + 255) / 256);
+    if (blocks == 0) return;
+    if (batched)
+        k_primal<LPR, KMODE, HASQ, true><<<blocks, 256, 0, s>>>(n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr);
+    else
+        k_primal<LPR, KMODE, HASQ, false><<<blocks, 256, 0, s>>>(n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr);
+}
+
+template <int LPR>
+static void primal_lpr(hipStream_t s, int kmode, bool hasq, bool batched, int n,
+                       const int *rpT, const int *ciT, const int *valT, const float *wy,
+                       const int *rpQ, const int *ciQ, const int *valQ, const float *x_in,
+                       float *x_out, float *xbar, const float *ct, float tau1, float two_so,
+                       const float *tau1_inst, const float *two_so_inst, const double *rho,
+                       const int *var_inst, DevCounters *ctr) {
+#define GF_P(KM, HQ) primal_k<LPR, KM, HQ>(s, batched, n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr)
+    if (hasq) {
+        if (kmode == 0) GF_P(0, true); else if (kmode == 1) GF_P(1, true); else GF_P(2, true);
+    } else {
+        if (kmode == 0) GF_P(0, false); else if (kmode == 1) GF_P(1, false); else GF_P(2, false);
+    }
+#undef GF_P
+}
+
+void launch_primal(hipStream_t s, int lpr, int kmode, bool hasq, bool batched, int n,
+                   const int *rpT, const int *ciT, const int *valT, const float *wy,
+                   const int *rpQ, const int *ciQ, const int *valQ, const float *x_in,
+                   float *x_out, float *xbar, const float *ct, float tau1, float two_so,
+                   const float *tau1_inst, const float *two_so_inst, const double *rho,
+                   const int *var_inst, DevCounters *ctr) {
+    switch (lpr) {
+#define GF_CASE(L) case L: primal_lpr<L>(s, kmode, hasq, batched, n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr); break;
+        GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
+#undef GF_CASE
+        default: break;
+    }
+}
+
+// ------------------------------------------------------------ small helpers
+__global__ void k_copy_f32(float *__restrict__ d, const float *__restrict__ s, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = s[i];
+}
+__global__ void k_fill_f32(float *__restrict__ d, float v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = v;
+}
+__global__ void k_set_xbar(int64_t n, const float *__restrict__ x, const float *__restrict__ xp,
+                           float *__restrict__ xbar) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        xbar[i] = 2.f * x[i] - xp[i];
+}
+static int grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    return static_cast<int>(b < 1 ? 1 : b);
+}
+void launch_copy_f32(hipStream_t s, float *dst, const float *src, int64_t n) {
+    if (n > 0) k_copy_f32<<<grid_for(n), 256, 0, s>>>(dst, src, n);
+}
+void launch_fill_f32(hipStream_t s, float *dst, float v, int64_t n) {
+    if (n > 0) k_fill_f32<<<grid_for(n), 256, 0, s>>>(dst, v, n);
+}
+void launch_set_xbar(hipStream_t s, int64_t n, const float *x, const float *xp, float *xbar) {
+    if (n > 0) k_set_xbar<<<grid_for(n), 256, 0, s>>>(n, x, xp, xbar);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 pieces of Preprocess: w_r = rowscale_r * sum_e val_e v[col_e]
+// (rowscale NULL = 1), one wavefront per row.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_spmv64(int nrows, const int *__restrict__ rp, const int *__restrict__ ci,
+         const int *__restrict__ val, const double *__restrict__ rowscale,
+         const double *__restrict__ v, double *__restrict__ w) {
+    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int sub = threadIdx.x & 15;
+    double s = 0.0;
+    if (row < nrows) {
+        const int e1 = rp[row + 1];
+        for (int e = rp[row] + sub; e < e1; e += 16)
+            s += (val ? static_cast<double>(val[e]) : 1.0) * v[ci[e]];
+    }
+    s = group_sum<16>(s);
+    if (row < nrows && sub == 0) w[row] = rowscale ? rowscale[row] * s : s;
+}
+void launch_spmv64(hipStream_t s, int nrows, const int *rp, const int *ci, const int *val,
+                   const double *rowscale, const double *v, double *w) {
+    const int64_t threads = static_cast<int64_t>(nrows) * 16;
+    const int blocks = static_cast<int>((threads + 255) / 256);
+    if (blocks) k_spmv64<<<blocks, 256, 0, s>>>(nrows, rp, ci, val, rowscale, v, w);
+}
+
+__global__ void k_scale64(int64_t n, double *__restrict__ x, const double *__restrict__ a,
+                          double sign) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = sign * a[i] * x[i];
+}
+void launch_scale64(hipStream_t s, int64_t n, double *x, const double *a, double sign) {
+    if (n > 0) k_scale64<<<grid_for(n), 256, 0, s>>>(n, x, a, sign);
+}
+__global__ void k_fill64(double *__restrict__ x, double v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+void launch_fill64(hipStream_t s, double *x, double v, int64_t n) {
+    if (n > 0) k_fill64<<<grid_for(n), 256, 0, s>>>(x, v, n);
+}
+
+// Block reduction of a double over 256 threads.
+__device__ __forceinline__ double block_sum256(double v, double *sh) {
+    v = group_sum<64>(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return r;
+}
+
+// Sum of squares over each tile's contiguous range [b0, b1): part[tile].
+__global__ void __launch_bounds__(256)
+k_tile_sumsq(const int *__restrict__ b0, const int *__restrict__ b1,
+             const double *__restrict__ x, double *__restrict__ part) {
+    __shared__ double sh[4];
+    const int t = blockIdx.x;
+    double acc = 0.0;
+    for (int i = b0[t] + threadIdx.x; i < b1[t]; i += 256) acc += x[i] * x[i];
+    acc = block_sum256(acc, sh);
+    if (threadIdx.x == 0) part[t] = acc;
+}
+void launch_tile_sumsq(hipStream_t s, const Tiles &t, const double *x, double *part) {
+    if (t.count) k_tile_sumsq<<<t.count, 256, 0, s>>>(t.b0, t.b1, x, part);
+}
+
+// out[inst*out_stride] = sum over the instance's tiles of part[tile*stride + comp]
+// (square-rooted if take_sqrt).  Fixed summation order: deterministic.
+__global__ void __launch_bounds__(256)
+k_inst_sum(int T, const int *__restrict__ first, const double *__restrict__ part, int stride,
+           int comp, double *__restrict__ out, int out_stride, int take_sqrt) {
+    __shared__ double sh[4];
+    const int inst = blockIdx.x;
+    double acc = 0.0;
+    for (int t = first[inst] + threadIdx.x; t < first[inst + 1]; t += 256)
+        acc += part[(int64_t)t * stride + comp];
+    acc = block_sum256(acc, sh);
+    if (threadIdx.x == 0) out[(int64_t)inst * out_stride] = take_sqrt ? sqrt(acc) : acc;
+}
+void launch_inst_sum(hipStream_t s, int T, const Tiles &t, const double *part, int stride,
+                     int comp, double *out, int out_stride, bool take_sqrt) {
+    if (T) k_inst_sum<<<T, 256, 0, s>>>(T, t.first, part, stride, comp, out, out_stride, take_sqrt ? 1 : 0);
+}
+
+// x[i] /= nrm[inst(tile)] for each tile's range; a zero norm leaves x untouched.
+__global__ void __launch_bounds__(256)
+k_tile_scale_inv(const int *__restrict__ inst, const int *__restrict__ b0,
+                 const int *__restrict__ b1, double *__restrict__ x,
+                 const double *__restrict__ nrm) {
+    const int t = blockIdx.x;
+    const double v = nrm[inst[t]];
+    if (v == 0.0) return;
+    for (int i = b0[t] + threadIdx.x; i < b1[t]; i += 256) x[i] = x[i] / v;
+}
+void launch_tile_scale_inv(hipStream_t s, const Tiles &t, double *x, const double *nrm) {
+    if (t.count) k_tile_scale_inv<<<t.count, 256, 0, s>>>(t.inst, t.b0, t.b1, x, nrm);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residuals (Theorem 2; CheckHalt of Sec. 3), per row tile:
+//   s^y_j   = (y_{k-1} - y_k)_j / tau2 + K~_j (xbar_{k-1} - x_k)
+//   gap_j   = (K~ x_k + r~)_j, positive part on inequality rows
+// part[tile*2 + {0,1}] = {sum (s^y)^2, sum gap^2}.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_res_rows(const int *__restrict__ tinst, const int *__restrict__ tb0,
+           const int *__restrict__ tb1, int m1, const int *__restrict__ rp,
+           const int *__restrict__ ci, const int *__restrict__ val,
+           const double *__restrict__ omega64, const int64_t *__restrict__ rhs,
+           const float *__restrict__ xsave, const float *__restrict__ x,
+           const float *__restrict__ y_prev, const float *__restrict__ y,
+           const double *__restrict__ tau2d, double *__restrict__ part) {
+    __shared__ double sh[4];
+    const int t = blockIdx.x;
+    const double tau2 = tau2d[tinst[t]];
+    const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+    double a1 = 0.0, a2 = 0.0;
+    for (int j0 = tb0[t]; j0 < tb1[t]; j0 += 16) {
+        const int j = j0 + grp;
+        double d1 = 0.0, d2 = 0.0;
+        if (j < tb1[t]) {
+            const int e1 = rp[j + 1];
+            for (int e = rp[j] + sub; e < e1; e += 16) {
+                const double a = val ? static_cast<double>(val[e]) : 1.0;
+                const int c = ci[e];
+                d1 += a * (static_cast<double>(xsave[c]) - static_cast<double>(x[c]));
+                d2 += a * static_cast<double>(x[c]);
+            }
+        }
+        d1 = group_sum<16>(d1);
+        d2 = group_sum<16>(d2);
+        if (j < tb1[t] && sub == 0) {
+            const double om = omega64[j];
+            const double sy = (static_cast<double>(y_prev[j]) - static_cast<double>(y[j])) / tau2 - om * d1;
+            double g = om * (static_cast<double>(rhs[j]) - d2);
+            if (j < m1 && g < 0.0) g = 0.0;
+            a1 += sy * sy;
+            a2 += g * g;
+        }
+    }
+    a1 = block_sum256(a1, sh);
+    a2 = block_sum256(a2, sh);
+    if (threadIdx.x == 0) { part[2 * t] = a1; part[2 * t + 1] = a2; }
+}
+void launch_res_rows(hipStream_t s, const Tiles &rt, int m1, const int *rp, const int *ci,
+                     const int *val, const double *omega64, const int64_t *rhs,
+                     const float *xsave, const float *x, const float *y_prev,
+                     const float *y, const double *tau2d, double *part) {
+    if (rt.count)
+        k_res_rows<<<rt.count, 256, 0, s>>>(rt.inst, rt.b0, rt.b1, m1, rp, ci, val, omega64, rhs,
+                                             xsave, x, y_prev, y, tau2d, part);
+}
+
+// Per variable tile:  s^x_i = -dx_i/tau1 - 2 rho dx_i + (2/s_o) (Q dx)_i, dx = x_k - x_{k-1};
+// binary gap x_i (1 - x_i).  part[tile*2 + {0,1}] = {sum (s^x)^2, sum x(1-x)}.
+__global__ void __launch_bounds__(256)
+k_res_vars(const int *__restrict__ tinst, const int *__restrict__ tb0,
+           const int *__restrict__ tb1, const int *__restrict__ rpQ,
+           const int *__restrict__ ciQ, const int *__restrict__ valQ,
+           const float *__restrict__ x, const float *__restrict__ xp,
+           const double *__restrict__ rho, const double *__restrict__ tau1d,
+           const double *__restrict__ two_sod, double *__restrict__ part) {
+    __shared__ double sh[4];
+    const int t = blockIdx.x;
+    const int inst = tinst[t];
+    const double r = rho[inst], tau1 = tau1d[inst], tso = two_sod[inst];
+    double a1 = 0.0, a2 = 0.0;
+    for (int i = tb0[t] + threadIdx.x; i < tb1[t]; i += 256) {
+        const double xi = x[i];
+        const double dx = xi - static_cast<double>(xp[i]);
+        double sx = -dx / tau1 - 2.0 * r * dx;
+        if (rpQ) {
+            double q = 0.0;
+            for (int e = rpQ[i]; e < rpQ[i + 1]; ++e) {
+                const int c = ciQ[e];
+                q += static_cast<double>(valQ[e]) * (static_cast<double>(x[c]) - static_cast<double>(xp[c]));
+            }
+            sx += tso * q;
+        }
+        a1 += sx * sx;
+        a2 += xi * (1.0 - xi);
+    }
+    a1 = block_sum256(a1, sh);
+    a2 = block_sum256(a2, sh);
+    if (threadIdx.x == 0) { part[2 * t] = a1; part[2 * t + 1] = a2; }
+}
+void launch_res_vars(hipStream_t s, const Tiles &vt, const int *rpQ, const int *ciQ,
+                     const int *valQ, const float *x, const float *xp, const double *rho,
+                     const double *tau1d, const double *two_sod, double *part) {
+    if (vt.count)
+        k_res_vars<<<vt.count, 256, 0, s>>>(vt.inst, vt.b0, vt.b1, rpQ, ciQ, valQ, x, xp, rho,
+                                             tau1d, two_sod, part);
+}
+
+}  // namespace gfors

@@ -1,0 +1,453 @@
+// Bernoulli sampling (Algorithm 3) with Philox4x32-10 uniforms and exact
+// candidate evaluation (EvalBest, Sec. 3) for gfx950.
+//
+// Candidate layout: uint64 X[i * W + w] holds candidates 64w .. 64w+63 of
+// variable i (bit b = candidate 64w + b); W = K / 64.
+//
+// Sampler: a wavefront works on one quad of variables (4i .. 4i+3) and one
+// 64-candidate word; lane = candidate.  One Philox call per lane yields the
+// four uniforms of the quad (counter = (l, quad, round, instance), word =
+// i & 3), the four comparisons are packed by wave64 ballots into the four
+// words directly, staged in LDS and written back as one contiguous block.
+// The linear objective sum_i c_i x_i of each candidate is accumulated on the
+// fly (each lane owns its candidate), so X is never re-read for it.
+//
+// Evaluation: rows whose coefficients are all one with right-hand side 1
+// (covering rows) are checked with bitwise OR over 64 candidates at a time;
+// any other row is summed exactly in integers, one candidate per lane.
+#include "gfors_internal.h"
+
+namespace gfors {
+
+__device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
+                                         uint32_t &c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(kPhiloxM1) * c2;
+        const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+        const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+}
+
+// u = (U >> 8) 2^-24 < p  <=>  (U >> 8) < ceil(p 2^24) for p in [0, 1]
+// (p 2^24 is exact in FP32); p <= 0 or NaN never samples, p >= 1 always does.
+__device__ __forceinline__ uint32_t bern_threshold(float p) {
+    if (!(p > 0.f)) return 0u;
+    if (p >= 1.f) return 1u << 24;
+    return static_cast<uint32_t>(ceilf(p * 16777216.0f));
+}
+
+template <int WPW, typename ACC>
+__global__ void __launch_bounds__(1024)
+k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
+         uint64_t *__restrict__ X, int W, const int *__restrict__ tile_inst,
+         const int *__restrict__ tile_q0, const int *__restrict__ tile_q1,
+         const int64_t *__restrict__ inst_var0, const int64_t *__restrict__ inst_nvar,
+         int64_t *__restrict__ zpart, int K, uint32_t key0, uint32_t key1,
+         const DevCounters *__restrict__ ctr, int threshold_mode) {
+    extern __shared__ uint64_t lds[];   // [64 variables][W words]
+    const int tile = blockIdx.x;
+    const int inst = tile_inst[tile];
+    const int q0 = tile_q0[tile], q1 = tile_q1[tile];
+    const int64_t v0 = inst_var0[inst];
+    const int64_t nv = inst_nvar[inst];
+    const uint32_t round = static_cast<uint32_t>(ctr->round);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int NW = blockDim.x >> 6;
+    ACC zacc[WPW];
+#pragma unroll
+    for (int s = 0; s < WPW; ++s) zacc[s] = 0;
+
+    for (int sq = q0; sq < q1; sq += 16) {
+        const int nq = min(16, q1 - sq);
+        for (int qq = 0; qq < nq; ++qq) {
+            const int q = sq + qq;
+            const int64_t ib = 4LL * q;
+            uint32_t thr[4];
+            ACC cc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (ib + j < nv) {
+                    thr[j] = bern_threshold(p[v0 + ib + j]);
+                    cc[j] = static_cast<ACC>(cost[v0 + ib + j]);
+                } else {
+                    thr[j] = 0u;
+                    cc[j] = 0;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < WPW; ++s) {
+                const int w = wave + s * NW;
+                uint32_t r0, r1, r2, r3;
+                if (threshold_mode) {
+                    r0 = r1 = r2 = r3 = 0x80000000u;   // u = 1/2: candidate = [p > 1/2]
+                } else {
+                    r0 = 64u * static_cast<uint32_t>(w) + static_cast<uint32_t>(lane);
+                    r1 = static_cast<uint32_t>(q);
+                    r2 = round;
+                    r3 = static_cast<uint32_t>(inst);
+                    philox10(r0, r1, r2, r3, key0, key1);
+                }
+                const bool b0 = (r0 >> 8) < thr[0];
+                const bool b1 = (r1 >> 8) < thr[1];
+                const bool b2 = (r2 >> 8) < thr[2];
+                const bool b3 = (r3 >> 8) < thr[3];
+                const uint64_t m0 = __ballot(b0);
+                const uint64_t m1 = __ballot(b1);
+                const uint64_t m2 = __ballot(b2);
+                const uint64_t m3 = __ballot(b3);
+                ACC add = 0;
+                if (b0) add += cc[0];
+                if (b1) add += cc[1];
+                if (b2) add += cc[2];
+                if (b3) add += cc[3];
+                zacc[s] += add;
+                if (lane < 4) {
+                    const uint64_t mm = lane == 0 ? m0 : lane == 1 ? m1 : lane == 2 ? m2 : m3;
+                    lds[(qq * 4 + lane) * W + w] = mm;
+                }
+            }
+        }
+        __syncthreads();
+        const int64_t nvars = min<int64_t>(4LL * nq, nv - 4LL * sq);
+        const int total = static_cast<int>(nvars) * W;
+        uint64_t *dst = X + (v0 + 4LL * sq) * W;
+        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) dst[idx] = lds[idx];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < WPW; ++s) {
+        const int w = wave + s * NW;
+        zpart[static_cast<int64_t>(tile) * K + 64 * w + lane] = static_cast<int64_t>(zacc[s]);
+    }
+}
+
+void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64_t *cost,
+                   uint64_t *X, const Tiles &st, const int64_t *inst_var0,
+                   const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,
+                   uint32_t key1, const DevCounters *ctr, int threshold_mode) {
+    if (!st.count) return;
+    const int NW = W <= 16 ? W : 16;
+    const int wpw = W / NW;
+    const size_t lds = static_cast<size_t>(64) * W * sizeof(uint64_t);
+#define GF_S(WP, ACCT) \
+    k_sample<WP, ACCT><<<st.count, NW * 64, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode)
+    if (obj64) {
+        switch (wpw) { case 1: GF_S(1, int64_t); break; case 2: GF_S(2, int64_t); break;
+                       case 3: GF_S(3, int64_t); break; case 4: GF_S(4, int64_t); break; default: break; }
+    } else {
+        switch (wpw) { case 1: GF_S(1, int32_t); break; case 2: GF_S(2, int32_t); break;
+                       case 3: GF_S(3, int32_t); break; case 4: GF_S(4, int32_t); break; default: break; }
+    }
+#undef GF_S
+}
+
+// ---------------------------------------------------------------------------
+// Covering rows (coefficients all 1, inequality, rhs 1): row violated by a
+// candidate iff none of its variables is set = ~OR of the words.  A group of
+// Wp (power of two >= W) lanes owns a row, lane w of the group word w.  Each
+// lane keeps per-candidate violation counts bit-sliced in 8 planes (ripple-
+// carry adds of 64-bit masks) and flushes them to LDS counters every 255 rows.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void flush_planes(uint64_t (&c)[8], int *cnt, int w) {
+    for (int b = 0; b < 64; ++b) {
+        int v = 0;
+#pragma unroll
+        for (int pl = 0; pl < 8; ++pl) v |= static_cast<int>((c[pl] >> b) & 1ull) << pl;
+        if (v) atomicAdd(&cnt[64 * w + b], v);
+    }
+#pragma unroll
+    for (int pl = 0; pl < 8; ++pl) c[pl] = 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
+             const int *__restrict__ tb1, const int *__restrict__ rows,
+             const int *__restrict__ rp, const int *__restrict__ ci,
+             const uint64_t *__restrict__ X, int W, int lgWp, int *__restrict__ vpart, int K) {
+    __shared__ int cnt[4096];
+    const int tile = tile_ids[blockIdx.x];
+    const int r0 = tb0[tile], r1 = tb1[tile];
+    for (int l = threadIdx.x; l < K; l += blockDim.x) cnt[l] = 0;
+    __syncthreads();
+    const int sub = threadIdx.x & ((1 << lgWp) - 1);
+    const int grp = threadIdx.x >> lgWp;
+    const int ngrp = blockDim.x >> lgWp;
+    uint64_t c[8];
+#pragma unroll
+    for (int pl = 0; pl < 8; ++pl) c[pl] = 0;
+    int since = 0;
+    for (int rr = r0 + grp; rr < r1; rr += ngrp) {
+        if (sub < W) {
+            const int j = rows[rr];
+            uint64_t acc = 0;
+            const int e1 = rp[j + 1];
+            for (int e = rp[j]; e < e1; ++e) acc |= X[static_cast<int64_t>(ci[e]) * W + sub];
+            uint64_t carry = ~acc;
+#pragma unroll
+            for (int pl = 0; pl < 8; ++pl) {
+                const uint64_t t = c[pl] & carry;
+                c[pl] ^= carry;
+                carry = t;
+            }
+            if (++since == 255) { flush_planes(c, cnt, sub); since = 0; }
+        }
+    }
+    if (sub < W && since) flush_planes(c, cnt, sub);
+    __syncthreads();
+    for (int l = threadIdx.x; l < K; l += blockDim.x)
+        vpart[static_cast<int64_t>(tile) * K + l] = cnt[l];
+}
+
+void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
+                       const int *rows, const int *rp, const int *ci, const uint64_t *X,
+                       int W, int *vpart, int K) {
+    if (!ntiles) return;
+    int lg = 0;
+    while ((1 << lg) < W) ++lg;
+    k_eval_cover<<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, X, W, lg, vpart, K);
+}
+
+// ---------------------------------------------------------------------------
+// General rows: lane = candidate.  For row j and word w the wavefront walks
+// the row (column index, coefficient and candidate word are uniform across
+// the wave, so they are scalar loads) and each lane adds a_ji when its bit is
+// set.  Violation: sum < rhs on inequality rows, sum != rhs on equality rows.
+// ---------------------------------------------------------------------------
+template <typename ACC>
+__global__ void __launch_bounds__(1024)
+k_eval_general(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
+               const int *__restrict__ tb1, const int *__restrict__ rows,
+               const int *__restrict__ rp, const int *__restrict__ ci,
+               const int *__restrict__ val, const int64_t *__restrict__ rhs, int m1,
+               const uint64_t *__restrict__ X, int W, int *__restrict__ vpart, int K) {
+    const int tile = tile_ids[blockIdx.x];
+    const int r0 = tb0[tile], r1 = tb1[tile];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int NW = blockDim.x >> 6;
+    const int sh = lane & 31;
+    const bool hi = lane >= 32;
+    for (int w = wave; w < W; w += NW) {
+        int cntv = 0;
+        for (int rr = r0; rr < r1; ++rr) {
+            const int j = rows[rr];
+            ACC acc = 0;
+            const int e1 = rp[j + 1];
+            for (int e = rp[j]; e < e1; ++e) {
+                const uint64_t word = X[static_cast<int64_t>(ci[e]) * W + w];
+                const uint32_t half = hi ? static_cast<uint32_t>(word >> 32) : static_cast<uint32_t>(word);
+                const int bit = static_cast<int>((half >> sh) & 1u);
+                const int a = val ? val[e] : 1;
+                acc += static_cast<ACC>(bit * a);
+            }
+            const int64_t b = rhs[j];
+            const bool bad = (j < m1) ? (static_cast<int64_t>(acc) < b) : (static_cast<int64_t>(acc) != b);
+            cntv += bad ? 1 : 0;
+        }
+        vpart[static_cast<int64_t>(tile) * K + 64 * w + lane] = cntv;
+    }
+}
+
+void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
+                         bool acc64, const int *rows, const int *rp, const int *ci,
+                         const int *val, const int64_t *rhs, int m1, const uint64_t *X,
+                         int W, int *vpart, int K) {
+    if (!ntiles) return;
+    const int NW = W <= 16 ? W : 16;
+    if (acc64)
+        k_eval_general<int64_t><<<ntiles, NW * 64, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, W, vpart, K);
+    else
+        k_eval_general<int32_t><<<ntiles, NW * 64, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, W, vpart, K);
+}
+
+// ---------------------------------------------------------------------------
+// Quadratic objective <x, Q x> per candidate, lane = candidate:
+//   sum_i x_i (sum_k Q_ik x_k) over the variables i of a tile.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024)
+k_eval_quad(const int *__restrict__ tinst, const int *__restrict__ tb0,
+            const int *__restrict__ tb1, const int *__restrict__ rpQ,
+            const int *__restrict__ ciQ, const int *__restrict__ valQ,
+            const uint64_t *__restrict__ X, int W, int64_t *__restrict__ zq, int K) {
+    const int tile = blockIdx.x;
+    const int i0 = tb0[tile], i1 = tb1[tile];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int NW = blockDim.x >> 6;
+    const int sh = lane & 31;
+    const bool hi = lane >= 32;
+    for (int w = wave; w < W; w += NW) {
+        int64_t z = 0;
+        for (int i = i0; i < i1; ++i) {
+            const uint64_t wi = X[static_cast<int64_t>(i) * W + w];
+            if (wi == 0) continue;           // no candidate of this word sets x_i
+            const uint32_t hw = hi ? static_cast<uint32_t>(wi >> 32) : static_cast<uint32_t>(wi);
+            const int xi = static_cast<int>((hw >> sh) & 1u);
+            int64_t acc = 0;
+            const int e1 = rpQ[i + 1];
+            for (int e = rpQ[i]; e < e1; ++e) {
+                const uint64_t word = X[static_cast<int64_t>(ciQ[e]) * W + w];
+                const uint32_t half = hi ? static_cast<uint32_t>(word >> 32) : static_cast<uint32_t>(word);
+                acc += static_cast<int64_t>(((half >> sh) & 1u) * static_cast<int64_t>(valQ[e]));
+            }
+            z += xi ? acc : 0;
+        }
+        zq[static_cast<int64_t>(tile) * K + 64 * w + lane] = z;
+    }
+}
+
+void launch_eval_quad(hipStream_t s, const Tiles &qt, const int64_t *inst_var0,
+                      const int *rpQ, const int *ciQ, const int *valQ, const uint64_t *X,
+                      int W, int64_t *zqpart, int K) {
+    (void)inst_var0;
+    if (!qt.count) return;
+    const int NW = W <= 16 ? W : 16;
+    k_eval_quad<<<qt.count, NW * 64, 0, s>>>(qt.inst, qt.b0, qt.b1, rpQ, ciQ, valQ, X, W, zqpart, K);
+}
+
+// ---------------------------------------------------------------------------
+// Per (instance, candidate): viol = sum of the instance's violation partials,
+// z = linear partials (+ quadratic partials).  Fixed summation order.
+// grid = (T, ceil(K/64)), block 256 = 4 slices x 64 candidates.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_reduce_cand(int K, const int *__restrict__ efirst, const int *__restrict__ vpart,
+              const int *__restrict__ sfirst, const int64_t *__restrict__ zpart,
+              const int *__restrict__ qfirst, const int64_t *__restrict__ zqpart, int has_q,
+              int32_t *__restrict__ viol, int64_t *__restrict__ z) {
+    __shared__ int sv[4][64];
+    __shared__ int64_t sz[4][64];
+    const int inst = blockIdx.x;
+    const int l = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int slice = threadIdx.x >> 6;
+    int v = 0;
+    int64_t zz = 0;
+    if (l < K) {
+        for (int t = efirst[inst] + slice; t < efirst[inst + 1]; t += 4)
+            v += vpart[static_cast<int64_t>(t) * K + l];
+        for (int t = sfirst[inst] + slice; t < sfirst[inst + 1]; t += 4)
+            zz += zpart[static_cast<int64_t>(t) * K + l];
+        if (has_q)
+            for (int t = qfirst[inst] + slice; t < qfirst[inst + 1]; t += 4)
+                zz += zqpart[static_cast<int64_t>(t) * K + l];
+    }
+    sv[slice][threadIdx.x & 63] = v;
+    sz[slice][threadIdx.x & 63] = zz;
+    __syncthreads();
+    if (slice == 0 && l < K) {
+        const int c = threadIdx.x & 63;
+        viol[static_cast<int64_t>(inst) * K + l] = sv[0][c] + sv[1][c] + sv[2][c] + sv[3][c];
+        z[static_cast<int64_t>(inst) * K + l] = sz[0][c] + sz[1][c] + sz[2][c] + sz[3][c];
+    }
+}
+
+void launch_reduce_cand(hipStream_t s, int T, int K, const Tiles &et, const int *vpart,
+                        const Tiles &st, const int64_t *zpart, const Tiles &qt,
+                        const int64_t *zqpart, int has_q, int32_t *viol, int64_t *z) {
+    dim3 grid(T, (K + 63) / 64);
+    k_reduce_cand<<<grid, 256, 0, s>>>(K, et.first, vpart, st.first, zpart,
+                                         has_q ? qt.first : st.first, zqpart, has_q, viol, z);
+}
+
+// ---------------------------------------------------------------------------
+// EvalBest: l* = lowest index attaining min{z_l : viol_l = 0}; replace the
+// incumbent on strict improvement.  With advance != 0 the trigger counter n
+// grows and rho follows UpdatePenalty (Sec. 3):
+//   rho_n = min(max(rho_min (1 + n/T)^p, rho_{n-1} + delta), rho_max).
+// One block per instance.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_argmin_update(int K, int W, const int32_t *__restrict__ viol, const int64_t *__restrict__ z,
+                DevInst di, DevCounters *__restrict__ ctr, int advance) {
+    __shared__ int64_t bz[256];
+    __shared__ int bl[256];
+    const int inst = blockIdx.x;
+    int64_t best = INT64_MAX;
+    int bi = 0x7fffffff;
+    for (int l = threadIdx.x; l < K; l += 256) {
+        const int64_t zl = z[static_cast<int64_t>(inst) * K + l];
+        if (viol[static_cast<int64_t>(inst) * K + l] == 0 && (zl < best || (zl == best && l < bi))) {
+            best = zl;
+            bi = l;
+        }
+    }
+    bz[threadIdx.x] = best;
+    bl[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const int64_t z2 = bz[threadIdx.x + o];
+            const int l2 = bl[threadIdx.x + o];
+            if (z2 < bz[threadIdx.x] || (z2 == bz[threadIdx.x] && l2 < bl[threadIdx.x])) {
+                bz[threadIdx.x] = z2;
+                bl[threadIdx.x] = l2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t round = ctr->round;
+        int imp = 0;
+        if (bl[0] != 0x7fffffff && bz[0] < di.zbest[inst]) {
+            di.zbest[inst] = bz[0];
+            di.inc_l[inst] = bl[0];
+            di.inc_round[inst] = advance ? round : -1;
+            di.inc_k[inst] = ctr->k;
+            di.inc_W[inst] = W;
+            imp = 1;
+        }
+        di.improved[inst] = imp;
+        if (advance) {
+            if (round < di.hist_cap) di.hist[static_cast<int64_t>(inst) * di.hist_cap + round] = di.zbest[inst];
+            const int64_t nn = di.ntrig[inst] + 1;
+            di.ntrig[inst] = nn;
+            const double rt = di.rho_min[inst] * pow(1.0 + static_cast<double>(nn) / di.rho_T[inst], di.rho_p[inst]);
+            const double prev = di.rho[inst];
+            di.rho[inst] = fmin(fmax(rt, prev + di.rho_delta[inst]), di.rho_max[inst]);
+        }
+    }
+}
+
+__global__ void k_round_bump(DevCounters *ctr) { ctr->round += 1; }
+
+void launch_argmin_update(hipStream_t s, int T, int K, int W, const int32_t *viol,
+                          const int64_t *z, DevInst di, DevCounters *ctr, int advance) {
+    k_argmin_update<<<T, 256, 0, s>>>(K, W, viol, z, di, ctr, advance);
+    if (advance) k_round_bump<<<1, 1, 0, s>>>(ctr);
+}
+
+// x_best of every instance whose incumbent just improved: byte per variable.
+__global__ void __launch_bounds__(256)
+k_extract_best(int64_t n, int T, const int *__restrict__ var_inst,
+               const int64_t *__restrict__ inst_var0, const uint64_t *__restrict__ X,
+               DevInst di, uint8_t *__restrict__ xbest) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int t = T > 1 ? var_inst[i] : 0;
+        if (!di.improved[t]) continue;
+        const int l = static_cast<int>(di.inc_l[t]);
+        const int W = di.inc_W[t];
+        const uint64_t word = X[i * W + (l >> 6)];
+        xbest[i] = static_cast<uint8_t>((word >> (l & 63)) & 1ull);
+    }
+}
+
+void launch_extract_best(hipStream_t s, int64_t n, int T, const int *var_inst,
+                         const int64_t *inst_var0, const uint64_t *X, DevInst di,
+                         uint8_t *xbest) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    k_extract_best<<<static_cast<int>(b), 256, 0, s>>>(n, T, var_inst, inst_var0, X, di, xbest);
+}
+
+}  // namespace gfors

@@ -1,0 +1,297 @@
+"""Thin Python binding of libgfors (include/gfors.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies the device workspace (one uint8 tensor) and the HIP stream.
+If the shared library is not built this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgfors.so")
+
+GFORS_OK = 0
+_ERRS = {-1: "GFORS_E_ARG", -2: "GFORS_E_NONINT", -3: "GFORS_E_OOM", -4: "GFORS_E_HIP",
+         -5: "GFORS_E_STATE", -6: "GFORS_E_INFEAS_ROW"}
+
+c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
+
+
+class gfors_csr(ctypes.Structure):
+    _fields_ = [("nrows", c_i64), ("ncols", c_i64), ("row_ptr", c_vp), ("col_idx", c_vp), ("val", c_vp)]
+
+
+class gfors_params(ctypes.Structure):
+    _fields_ = [("sigma", c_dbl), ("tau1", c_dbl), ("tau2", c_dbl),
+                ("rho_min", c_dbl), ("rho_max", c_dbl), ("rho_T", c_dbl), ("rho_p", c_dbl),
+                ("rho_delta", c_dbl), ("k_int", c_i32), ("K_max", c_i32), ("power_iters", c_i32),
+                ("hist_cap", c_i32), ("x0", c_dbl), ("seed", c_u64)]
+
+
+EXPORTS = [
+    "gfors_default_params", "gfors_workspace_bytes", "gfors_create_problem",
+    "gfors_destroy_problem", "gfors_last_error", "gfors_pdhg_steps", "gfors_sample_eval",
+    "gfors_final_round", "gfors_run_rounds", "gfors_best", "gfors_get_residuals",
+    "gfors_get_history", "gfors_get_state", "gfors_set_state", "gfors_get_candidates",
+    "gfors_get_scales", "gfors_get_dims",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgfors.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    L.gfors_default_params.argtypes = [P(gfors_params)]
+    L.gfors_default_params.restype = None
+    L.gfors_workspace_bytes.argtypes = [c_i64, c_i64, c_i64, c_i64, c_i64, c_i64, c_i32,
+                                        P(gfors_params), P(ctypes.c_size_t)]
+    L.gfors_create_problem.argtypes = [P(gfors_csr), c_vp, P(gfors_csr), c_vp, P(gfors_csr), c_vp,
+                                       c_i64, c_i32, c_vp, P(gfors_params), c_vp, ctypes.c_size_t,
+                                       c_vp, P(c_vp)]
+    L.gfors_destroy_problem.argtypes = [c_vp]
+    L.gfors_destroy_problem.restype = None
+    L.gfors_last_error.argtypes = []
+    L.gfors_last_error.restype = ctypes.c_char_p
+    L.gfors_pdhg_steps.argtypes = [c_vp, c_i32, c_i32]
+    L.gfors_sample_eval.argtypes = [c_vp, c_i32, c_vp, c_vp, c_vp]
+    L.gfors_final_round.argtypes = [c_vp]
+    L.gfors_run_rounds.argtypes = [c_vp, c_i32, c_i32, c_i32]
+    L.gfors_best.argtypes = [c_vp, c_i32, P(c_i64), c_vp, P(c_i32), c_vp]
+    L.gfors_get_residuals.argtypes = [c_vp, c_vp]
+    L.gfors_get_history.argtypes = [c_vp, c_i32, c_vp, c_i32, P(c_i32)]
+    L.gfors_get_state.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, P(c_i64), P(c_i64), P(c_i64)]
+    L.gfors_set_state.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64]
+    L.gfors_get_candidates.argtypes = [c_vp, c_vp, P(c_i32)]
+    L.gfors_get_scales.argtypes = [c_vp] + [c_vp] * 9
+    L.gfors_get_dims.argtypes = [c_vp, P(c_i64), P(c_i64), P(c_i64), P(c_i32)]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("gfors_default_params", "gfors_destroy_problem", "gfors_last_error"):
+            f.restype = c_i32
+    _lib = L
+    return L
+
+
+class GforsError(RuntimeError):
+    pass
+
+
+def _check(rc: int):
+    if rc != GFORS_OK:
+        msg = load_library().gfors_last_error().decode(errors="replace")
+        raise GforsError(f"{_ERRS.get(rc, rc)}: {msg}")
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def default_params(**overrides) -> gfors_params:
+    p = gfors_params()
+    load_library().gfors_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _csr(M, keep: list):
+    if M is None:
+        return None
+    rp = np.ascontiguousarray(M.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(M.col, dtype=np.int32)
+    val = None if M.val is None else np.ascontiguousarray(M.val, dtype=np.int32)
+    keep += [rp, col, val]
+    s = gfors_csr(M.nrows, M.ncols, rp.ctypes.data, col.ctypes.data if col.size else None,
+                  None if val is None else (val.ctypes.data if val.size else None))
+    keep.append(s)
+    return s
+
+
+class Problem:
+    """One GFORS problem bound to a device workspace and a HIP stream.
+
+    ``bip`` is a paper_2510_27117_amd.instances.BIP (integer CSR data)."""
+
+    def __init__(self, bip, params: Optional[gfors_params] = None, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        L = load_library()
+        self.torch = torch
+        self.params = params if params is not None else default_params()
+        self.n = int(bip.n)
+        self.m1, self.m2 = int(bip.m1), int(bip.m2)
+        self.T = int(bip.num_instances)
+        self.device = torch.device(device)
+        nnzA = 0 if bip.A is None else bip.A.nnz
+        nnzB = 0 if bip.B is None else bip.B.nnz
+        nnzQ = 0 if bip.Q is None else bip.Q.nnz
+        nbytes = ctypes.c_size_t(0)
+        _check(L.gfors_workspace_bytes(self.n, self.m1, self.m2, nnzA, nnzB, nnzQ, self.T,
+                                       ctypes.byref(self.params), ctypes.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        # a dedicated stream: the legacy null stream cannot be captured into graphs
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        keep: list = []
+        A = _csr(bip.A, keep)
+        B = _csr(bip.B, keep)
+        Q = _csr(bip.Q, keep)
+        b = None if bip.b is None else np.ascontiguousarray(bip.b, dtype=np.int64)
+        d = None if bip.d is None else np.ascontiguousarray(bip.d, dtype=np.int64)
+        c = np.ascontiguousarray(bip.c, dtype=np.int64)
+        off = None
+        if self.T > 1:
+            off = np.ascontiguousarray(bip.inst_offsets, dtype=np.int64).reshape(-1)
+        self.inst_offsets = (np.asarray(bip.inst_offsets, dtype=np.int64) if bip.inst_offsets is not None
+                             else np.array([[0, 0, 0], [self.n, self.m1, self.m2]], dtype=np.int64))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.gfors_create_problem(
+                ctypes.byref(A) if A else None, _ptr(b), ctypes.byref(B) if B else None, _ptr(d),
+                ctypes.byref(Q) if Q else None, _ptr(c), self.n, self.T, _ptr(off),
+                ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()),
+                ctypes.c_size_t(self.ws_bytes), ctypes.c_void_p(self.stream.cuda_stream),
+                ctypes.byref(h)))
+        self.handle = h
+        self.m = self.m1 + self.m2
+
+    # --------------------------------------------------------------- calls
+    def _h(self):
+        if not self.handle:
+            raise GforsError("problem already destroyed")
+        return self.handle
+
+    def pdhg_steps(self, nsteps: int, want_residuals: bool = False):
+        _check(load_library().gfors_pdhg_steps(self._h(), int(nsteps), 1 if want_residuals else 0))
+
+    def sample_eval(self, K: int, p_override=None, outputs: bool = False):
+        """One sampling round of K candidates per instance.  p_override: a float32
+        device tensor of length n (values in [0,1]).  With outputs=True returns
+        device tensors (viol int32 [T,K], obj int64 [T,K])."""
+        torch = self.torch
+        pp = None
+        if p_override is not None:
+            assert p_override.dtype == torch.float32 and p_override.is_cuda and p_override.numel() == self.n
+            pp = ctypes.c_void_p(p_override.contiguous().data_ptr())
+            self._p_keep = p_override
+        v = z = None
+        if outputs:
+            v = torch.empty((self.T, K), dtype=torch.int32, device=self.device)
+            z = torch.empty((self.T, K), dtype=torch.int64, device=self.device)
+        _check(load_library().gfors_sample_eval(self._h(), int(K), pp,
+                                                None if v is None else ctypes.c_void_p(v.data_ptr()),
+                                                None if z is None else ctypes.c_void_p(z.data_ptr())))
+        if outputs:
+            self.synchronize()
+            return v, z
+        return None
+
+    def final_round(self):
+        _check(load_library().gfors_final_round(self._h()))
+
+    def run_rounds(self, nrounds: int, K: int, use_graph: bool = True):
+        _check(load_library().gfors_run_rounds(self._h(), int(nrounds), int(K), 1 if use_graph else 0))
+
+    def best(self, inst: int = 0, want_x: bool = True):
+        z = c_i64(0)
+        found = c_i32(0)
+        info = np.zeros(4, dtype=np.int64)
+        nv = int(self.inst_offsets[inst + 1, 0] - self.inst_offsets[inst, 0])
+        x = np.zeros(nv, dtype=np.uint8) if want_x else None
+        _check(load_library().gfors_best(self._h(), int(inst), ctypes.byref(z), _ptr(x),
+                                         ctypes.byref(found), _ptr(info)))
+        return {"z": int(z.value), "found": bool(found.value), "x": x, "k": int(info[0]),
+                "round": int(info[1]), "l": int(info[2]), "ntrig": int(info[3])}
+
+    def residuals(self) -> np.ndarray:
+        out = np.zeros((self.T, 4), dtype=np.float64)
+        _check(load_library().gfors_get_residuals(self._h(), _ptr(out)))
+        return out
+
+    def history(self, inst: int = 0, cap: int = 4096):
+        h = np.zeros(cap, dtype=np.int64)
+        cnt = c_i32(0)
+        _check(load_library().gfors_get_history(self._h(), int(inst), _ptr(h), int(cap), ctypes.byref(cnt)))
+        return h[: min(cap, cnt.value)]
+
+    def get_state(self):
+        x = np.zeros(self.n, dtype=np.float32)
+        xp = np.zeros(self.n, dtype=np.float32)
+        y = np.zeros(max(self.m, 1), dtype=np.float32)
+        rho = np.zeros(self.T, dtype=np.float64)
+        k, r, nt = c_i64(0), c_i64(0), c_i64(0)
+        _check(load_library().gfors_get_state(self._h(), _ptr(x), _ptr(xp), _ptr(y), _ptr(rho),
+                                              ctypes.byref(k), ctypes.byref(r), ctypes.byref(nt)))
+        return {"x": x, "x_prev": xp, "y": y[: self.m], "rho": rho, "k": k.value,
+                "round": r.value, "ntrig": nt.value}
+
+    def set_state(self, x, x_prev, y, rho, k: int = 0, round: int = 0, ntrig: int = 0):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        xp = np.ascontiguousarray(x_prev, dtype=np.float32)
+        yy = np.ascontiguousarray(y if self.m else np.zeros(1), dtype=np.float32)
+        rr = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, dtype=np.float64), (self.T,)))
+        _check(load_library().gfors_set_state(self._h(), _ptr(x), _ptr(xp), _ptr(yy), _ptr(rr),
+                                              int(k), int(round), int(ntrig)))
+
+    def candidates(self) -> np.ndarray:
+        K = c_i32(0)
+        _check(load_library().gfors_get_candidates(self._h(), None, ctypes.byref(K)))
+        out = np.zeros((self.n, K.value // 64), dtype=np.uint64)
+        _check(load_library().gfors_get_candidates(self._h(), _ptr(out), ctypes.byref(K)))
+        return out
+
+    def scales(self) -> dict:
+        T = self.T
+        arrs = {k: np.zeros(T) for k in ["obj_scale", "K_norm", "Q_norm", "tau1", "tau2",
+                                          "rho_min", "rho_max", "rho_delta"]}
+        row = np.zeros(max(self.m, 1))
+        _check(load_library().gfors_get_scales(self._h(), _ptr(row), *[_ptr(arrs[k]) for k in [
+            "obj_scale", "K_norm", "Q_norm", "tau1", "tau2", "rho_min", "rho_max", "rho_delta"]]))
+        arrs["row_scale"] = row[: self.m]
+        return arrs
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if self.handle:
+            self.synchronize()
+            load_library().gfors_destroy_problem(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# Module-level names mirroring the C entry points.
+def gfors_create_problem(bip, params=None, device="cuda:0", stream=None) -> Problem:
+    return Problem(bip, params, device, stream)
+
+
+def gfors_pdhg_steps(P: Problem, nsteps: int, want_residuals: bool = False):
+    P.pdhg_steps(nsteps, want_residuals)
+
+
+def gfors_sample_eval(P: Problem, K: int, p_override=None, outputs: bool = False):
+    return P.sample_eval(K, p_override, outputs)
+
+
+def gfors_best(P: Problem, inst: int = 0):
+    return P.best(inst)
