@@ -1,0 +1,218 @@
+"""Benchmark of the GFORS hot path on one MI355X.
+
+A step = one trigger period of Algorithm 1: k_int PDHG iterations (Algorithm 2)
+followed by one sampling round of K candidates (Algorithm 3) with exact
+evaluation and incumbent update (EvalBest), replayed from a captured HIP graph.
+Inputs are resident in HBM before the timed region starts.
+
+Prints ONE JSON line (see the keys below).  Also measured:
+  * per-kernel HIP-event durations -> roofline of the dominant kernel;
+  * time-to-incumbent: wall time (HIP events) until the incumbent is within
+    0.1% of the best value reached in a fixed budget of rounds;
+  * the CPU oracle on a bounded sample of the same workload (cpu_baseline).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PDHG iter/s + candidates/s; time-to-incumbent at fixed gap, learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="setcover_large")
+    ap.add_argument("--K", type=int, default=1024)
+    ap.add_argument("--k-int", type=int, default=100)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tti-rounds", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+    return ap.parse_args()
+
+
+def kernel_bytes(bip, K):
+    """Algorithmic HBM bytes per launch: every array the kernel must touch,
+    counted once (gathered vectors by their unique size)."""
+    n, m = bip.n, bip.m1 + bip.m2
+    nnzK = (0 if bip.A is None else bip.A.nnz) + (0 if bip.B is None else bip.B.nnz)
+    unit = (bip.A is None or bip.A.val is None) and (bip.B is None or bip.B.val is None)
+    nnzQ = 0 if bip.Q is None else bip.Q.nnz
+    vb = 0 if unit else 4
+    W = K // 64
+    out = {}
+    if m:
+        # row_ptr + col (+val) + xbar (unique) + omega, rt, y_in, y_out, wy
+        out["dual"] = 4 * (m + 1) + (4 + vb) * nnzK + 4 * n + 20 * m
+    prim = 16 * n  # x_in, ct read; x_out, xbar written
+    if m:
+        prim += 4 * (n + 1) + (4 + vb) * nnzK + 4 * m
+    if nnzQ:
+        prim += 4 * (n + 1) + 8 * nnzQ
+    out["primal"] = prim
+    out["sample"] = 8 * n * W + 4 * n + 8 * n          # candidate words + p + cost
+    if m:
+        out["eval_cover"] = 4 * (m + 1) + 4 * nnzK + 8 * n * W
+        out["eval_general"] = 4 * (m + 1) + (4 + vb) * nnzK + 8 * n * W + 8 * m
+    if nnzQ:
+        out["eval_quad"] = 4 * (n + 1) + 8 * nnzQ + 8 * n * W
+    return out
+
+
+def cpu_baseline(bip, k_int, K):
+    """The oracle as it stands, on a bounded sample of the same workload:
+    3 FP64 PDHG iterations and one sampling round of 16 candidates (exact
+    evaluation), scaled to the same step definition."""
+    from oracle import gfors_oracle as O
+    prm = O.Params(k_int=k_int, power_iters=3)
+    S = O.preprocess(bip, prm)
+    st = O.init_state(S)
+    rho = O.rho_value(S, 0)
+    st = O.pdhg_step(S, st, rho)
+    t0 = time.perf_counter()
+    iters = 3
+    for _ in range(iters):
+        st = O.pdhg_step(S, st, rho)
+    t_iter = (time.perf_counter() - t0) / iters
+    kc = 16
+    t0 = time.perf_counter()
+    X = O.sample_bits(st.x, kc, 0, 0)
+    viol, z = O.evaluate(bip, X)
+    inc = O.Incumbent()
+    O.incumbent_update(inc, X, viol, z, 0, st.k)
+    t_cand = (time.perf_counter() - t0) / kc
+    step = k_int * t_iter + K * t_cand
+    return {"value": k_int / step, "unit": "PDHG iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} FP64 PDHG iterations + 1 sampling round of {kc} candidates "
+                      f"(exact eval) on the full workload, scaled to a step of {k_int} "
+                      f"iterations + {K} candidates",
+            "candidates_per_s": 1.0 / t_cand, "iter_per_s_pdhg_only": 1.0 / t_iter,
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
+              f"multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2510_27117_amd import gfors, instances
+
+    t0 = time.perf_counter()
+    bip = instances.workload(a.workload, seed=a.seed)
+    t_gen = time.perf_counter() - t0
+    prm = gfors.default_params(k_int=a.k_int, K_max=max(a.K, 1024))
+    t0 = time.perf_counter()
+    G = gfors.Problem(bip, prm)
+    t_pre = time.perf_counter() - t0
+    use_graph = not a.no_graph
+    stream = G.stream
+
+    # warmup + timed region (graph replay of whole rounds)
+    for _ in range(a.warmup):
+        G.run_rounds(1, a.K, use_graph)
+    G.synchronize()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    G.run_rounds(a.steps, a.K, use_graph)
+    ev1.record(stream)
+    G.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / a.steps
+    iters_per_s = a.steps * a.k_int / (gpu_ms / 1e3)
+    cands_per_s = a.steps * a.K * bip.num_instances / (gpu_ms / 1e3)
+
+    # per-kernel HIP-event durations (eager launches, same stream, state advances)
+    kt = G.kernel_times(a.k_int, a.K)
+    per_step = {k: ms * (a.k_int if k in ("dual", "primal") else 1) for k, (ms, cnt) in kt.items() if cnt}
+    kb = kernel_bytes(bip, a.K)
+    dom = max((k for k in per_step if k in kb), key=lambda k: per_step[k])
+    avg_ms = kt[dom][0]
+    achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    try:
+        with open(a.traffic_file) as f:
+            tr = json.load(f)
+        ent = tr.get(a.workload, {}).get(dom)
+        if ent and ent.get("K") == a.K:
+            traffic = ent.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": kb[dom], "avg_launch_ms": avg_ms}
+    kernels = {k: {"avg_ms": round(ms, 5), "launches": cnt,
+                   "gbs": (round(kb[k] / (ms * 1e-3) / 1e9, 1) if k in kb and ms > 0 else None)}
+               for k, (ms, cnt) in kt.items() if cnt}
+
+    # time-to-incumbent from a fresh start (same problem, reset)
+    G.reset()
+    R = a.tti_rounds
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(R + 1)]
+    evs[0].record(stream)
+    for r in range(R):
+        G.run_rounds(1, a.K, use_graph)
+        evs[r + 1].record(stream)
+    G.synchronize()
+    times = [evs[0].elapsed_time(evs[r + 1]) for r in range(R)]
+    tti = {}
+    for t in range(min(bip.num_instances, 1)):
+        hist = G.history(t, R)
+        feas = np.nonzero(hist != np.iinfo(np.int64).max)[0]
+        if feas.size:
+            zf = int(hist[-1])
+            target = zf + 0.001 * abs(zf)
+            r_hit = int(np.nonzero(hist <= target)[0][0])
+            tti = {"rounds": R, "z_final": zf, "target_gap": 0.001, "round_hit": r_hit,
+                   "ms_to_target": round(times[r_hit], 3), "first_feasible_round": int(feas[0]),
+                   "ms_to_first_feasible": round(times[int(feas[0])], 3),
+                   "ms_total": round(times[-1], 3)}
+        else:
+            tti = {"rounds": R, "z_final": None, "note": "no feasible candidate"}
+
+    base = None
+    if not a.no_cpu_baseline:
+        base = cpu_baseline(bip, a.k_int, a.K)
+
+    nnzK = (0 if bip.A is None else bip.A.nnz) + (0 if bip.B is None else bip.B.nnz)
+    out = {
+        "metric": METRIC, "value": round(iters_per_s, 2), "unit": "PDHG iter/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "n": bip.n, "m1": bip.m1, "m2": bip.m2,
+                   "nnz_constraints": nnzK, "nnz_Q": 0 if bip.Q is None else bip.Q.nnz,
+                   "instances": bip.num_instances, "K": a.K, "k_int": a.k_int,
+                   "step": f"{a.k_int} PDHG iterations + 1 round of {a.K} candidates",
+                   "graph": use_graph, "seed": a.seed},
+        "candidates_per_s": round(cands_per_s, 1),
+        "wall_s_timed": round(wall, 4),
+        "preprocess_s": round(t_pre, 3), "generate_s": round(t_gen, 3),
+        "roofline": roofline, "kernels": kernels,
+        "time_to_incumbent": tti,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out))
+    G.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,11 @@ int gfors_get_state(gfors_problem *P, float *x, float *x_prev, float *y, double 
 int gfors_set_state(gfors_problem *P, const float *x, const float *x_prev, const float *y,
                     const double *rho, int64_t k, int64_t round, int64_t ntrig);
 
+/* Restart Algorithm 1 on the same data: x = x_{-1} = xbar = x0, y = 0,
+ * rho = rho_min, counters zero, incumbent cleared (z_best = +inf), history
+ * cleared.  Preprocess results are kept.  Synchronises. */
+int gfors_reset(gfors_problem *P);
+
 /* Candidates of the last sampling round: uint64[n * K/64], word w of variable
  * i at [i*(K/64) + w] holding candidates 64w..64w+63 (bit b = candidate 64w+b). */
 int gfors_get_candidates(gfors_problem *P, uint64_t *bits_host, int32_t *K_out);
@@ -177,6 +182,19 @@ int gfors_get_candidates(gfors_problem *P, uint64_t *bits_host, int32_t *K_out);
 int gfors_get_scales(gfors_problem *P, double *row_scale, double *obj_scale, double *K_norm,
                      double *Q_norm, double *tau1, double *tau2, double *rho_min,
                      double *rho_max, double *rho_delta);
+
+/* Profiling support: runs nsteps PDHG steps and one sampling round of K
+ * candidates (advancing the state exactly like gfors_pdhg_steps +
+ * gfors_sample_eval) with HIP events around every launch on the problem's
+ * stream, synchronises, and writes the average duration in milliseconds of
+ * each kernel kind to avg_ms[GFORS_NUM_KERNEL_TIMERS] (and the number of
+ * launches timed to launches[], if not NULL).  Kernel kinds, in order: dual
+ * step, primal step, sampler, covering-row evaluation, general-row evaluation,
+ * quadratic objective, candidate reduction, incumbent update, x_best copy.
+ * A kind that did not run reports 0. */
+#define GFORS_NUM_KERNEL_TIMERS 9
+int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_ms,
+                       int32_t *launches);
 
 /* Dimensions: n, m1, m2, number of instances. */
 int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32_t *T);

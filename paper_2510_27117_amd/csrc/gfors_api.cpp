@@ -129,6 +129,29 @@ struct gfors_problem {
 
 namespace {
 
+// Optional per-launch HIP-event timing (kernel ids of gfors_kernel_times).
+struct KTimer {
+    hipStream_t s;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[GFORS_NUM_KERNEL_TIMERS];
+    void b(int id) {
+        hipEvent_t a, z;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&z);
+        ev[id].push_back({a, z});
+        (void)hipEventRecord(a, s);
+    }
+    void e(int id) { (void)hipEventRecord(ev[id].back().second, s); }
+    ~KTimer() {
+        for (auto &v : ev)
+            for (auto &p : v) {
+                (void)hipEventDestroy(p.first);
+                (void)hipEventDestroy(p.second);
+            }
+    }
+};
+#define TB(id) do { if (tm) tm->b(id); } while (0)
+#define TE(id) do { if (tm) tm->e(id); } while (0)
+
 int validate_csr(const gfors_csr *M, int64_t ncols_expect, const char *name) {
     if (!M) return GFORS_OK;
     if (M->nrows < 0 || M->ncols != ncols_expect)
@@ -750,7 +773,7 @@ static int device_norms(gfors_problem *P) {
     return GFORS_OK;
 }
 
-static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res) {
+static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *tm = nullptr) {
     hipStream_t s = P->stream;
     const bool batched = P->T > 1;
     const int kmode = P->m == 0 ? 0 : (P->unitK ? 1 : 2);
@@ -758,16 +781,20 @@ static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res) {
         const bool res = want_res && it == nsteps - 1;
         if (res) launch_copy_f32(s, P->xsave, P->xbar, P->n);
         const int a = P->cur, bnext = 1 - P->cur;
+        TB(0);
         if (P->m > 0)
             launch_dual(s, P->cfg.lpr_dual, P->unitK, batched, static_cast<int>(P->m),
                         static_cast<int>(P->m1), P->rp, P->ci, P->val, P->omega, P->rt, P->xbar,
                         P->ybuf[a], P->ybuf[bnext], P->wy, static_cast<float>(P->tau2[0]),
                         P->di.tau2, P->row_inst);
+        TE(0);
+        TB(1);
         launch_primal(s, P->cfg.lpr_primal, kmode, P->hasQ, batched, static_cast<int>(P->n),
                       P->rpT, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, P->xbuf[a],
                       P->xbuf[bnext], P->xbar, P->ct, static_cast<float>(P->tau1[0]),
                       static_cast<float>(P->s_o[0] > 0 ? 2.0 / P->s_o[0] : 2.0), P->di.tau1,
                       P->di.two_so, P->di.rho, P->var_inst, P->ctr);
+        TE(1);
         if (res) {
             const int T = P->T;
             launch_res_vars(s, P->vt, P->hasQ ? P->rpQ : nullptr, P->ciQ, P->valQ, P->xbuf[bnext],
@@ -790,22 +817,37 @@ static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res) {
     }
 }
 
-static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override, int threshold) {
+static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override, int threshold,
+                                KTimer *tm = nullptr) {
     hipStream_t s = P->stream;
     const int W = K / 64;
     const float *p = p_override ? p_override : P->xbuf[P->cur];
+    TB(2);
     launch_sample(s, W, P->obj64, p, P->cost, P->X, P->st, P->d_inst_var0, P->d_inst_nvar,
                   P->zpart, K, static_cast<uint32_t>(P->prm.seed & 0xffffffffu),
                   static_cast<uint32_t>(P->prm.seed >> 32), P->ctr, threshold);
+    TE(2);
+    TB(3);
     launch_eval_cover(s, P->n_cover, P->cover_ids, P->et, P->rows, P->rp, P->ci, P->X, W, P->vpart, K);
+    TE(3);
+    TB(4);
     launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
                         P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X, W,
                         P->vpart, K);
+    TE(4);
+    TB(5);
     if (P->hasQ) launch_eval_quad(s, P->qt, P->d_inst_var0, P->rpQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K);
+    TE(5);
+    TB(6);
     launch_reduce_cand(s, P->T, K, P->et, P->vpart, P->st, P->zpart, P->qt, P->zqpart,
                        P->hasQ ? 1 : 0, P->viol, P->z);
+    TE(6);
+    TB(7);
     launch_argmin_update(s, P->T, K, W, P->viol, P->z, P->di, P->ctr, threshold ? 0 : 1);
+    TE(7);
+    TB(8);
     launch_extract_best(s, P->n, P->T, P->var_inst, P->d_inst_var0, P->X, P->di, P->xbest);
+    TE(8);
     P->lastK = K;
 }
 
@@ -948,6 +990,37 @@ int gfors_set_state(gfors_problem *P, const float *x, const float *x_prev, const
     return sync(P);
 }
 
+int gfors_reset(gfors_problem *P) {
+    if (!P) return fail(GFORS_E_ARG, "NULL handle");
+    hipStream_t s = P->stream;
+    const int T = P->T;
+    int rc;
+    const float x0 = static_cast<float>(P->prm.x0);
+    launch_fill_f32(s, P->xbuf[0], x0, P->n);
+    launch_fill_f32(s, P->xbuf[1], x0, P->n);
+    launch_fill_f32(s, P->xbar, x0, P->n);
+    launch_fill_f32(s, P->ybuf[0], 0.f, P->m);
+    launch_fill_f32(s, P->ybuf[1], 0.f, P->m);
+    launch_fill_f32(s, P->wy, 0.f, P->m);
+    std::vector<int64_t> zeros(T, 0), big(T, INT64_MAX), neg(T, -2);
+    std::vector<int32_t> z32(T, 0);
+    std::vector<int64_t> h(static_cast<size_t>(T) * P->di.hist_cap, INT64_MAX);
+    std::vector<uint8_t> xb(P->n, 0);
+    DevCounters c0{};
+    if ((rc = upload(s, P->di.rho, P->rmin.data(), T))) return rc;
+    if ((rc = upload(s, P->di.ntrig, zeros.data(), T))) return rc;
+    if ((rc = upload(s, P->di.zbest, big.data(), T))) return rc;
+    if ((rc = upload(s, P->di.inc_k, neg.data(), T))) return rc;
+    if ((rc = upload(s, P->di.inc_round, neg.data(), T))) return rc;
+    if ((rc = upload(s, P->di.inc_l, neg.data(), T))) return rc;
+    if ((rc = upload(s, P->di.improved, z32.data(), T))) return rc;
+    if ((rc = upload(s, P->di.hist, h.data(), static_cast<int64_t>(h.size())))) return rc;
+    if ((rc = upload(s, P->xbest, xb.data(), P->n))) return rc;
+    if ((rc = upload(s, P->ctr, &c0, 1))) return rc;
+    HIP_TRY(hipGetLastError());
+    return sync(P);
+}
+
 int gfors_get_candidates(gfors_problem *P, uint64_t *bits_host, int32_t *K_out) {
     if (!P) return fail(GFORS_E_ARG, "NULL handle");
     if (!P->lastK) return fail(GFORS_E_STATE, "no sampling round yet");
@@ -971,6 +1044,30 @@ int gfors_get_scales(gfors_problem *P, double *row_scale, double *obj_scale, dou
     if (rho_min) std::copy(P->rmin.begin(), P->rmin.begin() + T, rho_min);
     if (rho_max) std::copy(P->rmax.begin(), P->rmax.begin() + T, rho_max);
     if (rho_delta) std::copy(P->rdelta.begin(), P->rdelta.begin() + T, rho_delta);
+    return GFORS_OK;
+}
+
+int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_ms, int32_t *launches) {
+    if (!P || nsteps < 1 || !avg_ms) return fail(GFORS_E_ARG, "bad argument");
+    if (!check_K(K) || K > P->prm.K_max) return fail(GFORS_E_ARG, "bad K");
+    KTimer tm;
+    tm.s = P->stream;
+    enqueue_steps(P, nsteps, false, &tm);
+    enqueue_sample_eval(P, K, nullptr, 0, &tm);
+    HIP_TRY(hipGetLastError());
+    int rc = sync(P);
+    if (rc) return rc;
+    for (int id = 0; id < GFORS_NUM_KERNEL_TIMERS; ++id) {
+        double tot = 0.0;
+        for (auto &p : tm.ev[id]) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, p.first, p.second));
+            tot += ms;
+        }
+        const size_t cnt = tm.ev[id].size();
+        avg_ms[id] = cnt ? tot / static_cast<double>(cnt) : 0.0;
+        if (launches) launches[id] = static_cast<int32_t>(cnt);
+    }
     return GFORS_OK;
 }
 

@@ -38,8 +38,11 @@ EXPORTS = [
     "gfors_destroy_problem", "gfors_last_error", "gfors_pdhg_steps", "gfors_sample_eval",
     "gfors_final_round", "gfors_run_rounds", "gfors_best", "gfors_get_residuals",
     "gfors_get_history", "gfors_get_state", "gfors_set_state", "gfors_get_candidates",
-    "gfors_get_scales", "gfors_get_dims",
+    "gfors_get_scales", "gfors_get_dims", "gfors_kernel_times", "gfors_reset",
 ]
+
+KERNEL_NAMES = ["dual", "primal", "sample", "eval_cover", "eval_general", "eval_quad",
+                "reduce_cand", "argmin_update", "extract_best"]
 
 _lib = None
 
@@ -76,6 +79,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_get_candidates.argtypes = [c_vp, c_vp, P(c_i32)]
     L.gfors_get_scales.argtypes = [c_vp] + [c_vp] * 9
     L.gfors_get_dims.argtypes = [c_vp, P(c_i64), P(c_i64), P(c_i64), P(c_i32)]
+    L.gfors_kernel_times.argtypes = [c_vp, c_i32, c_i32, c_vp, c_vp]
+    L.gfors_reset.argtypes = [c_vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("gfors_default_params", "gfors_destroy_problem", "gfors_last_error"):
@@ -263,6 +268,18 @@ class Problem:
             "obj_scale", "K_norm", "Q_norm", "tau1", "tau2", "rho_min", "rho_max", "rho_delta"]]))
         arrs["row_scale"] = row[: self.m]
         return arrs
+
+    def kernel_times(self, nsteps: int, K: int) -> dict:
+        """HIP-event average duration (ms) and launch count of each kernel kind
+        over nsteps PDHG steps + one sampling round (state advances)."""
+        ms = np.zeros(len(KERNEL_NAMES), dtype=np.float64)
+        cnt = np.zeros(len(KERNEL_NAMES), dtype=np.int32)
+        _check(load_library().gfors_kernel_times(self._h(), int(nsteps), int(K), _ptr(ms), _ptr(cnt)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+    def reset(self):
+        """Restart from x0 with a cleared incumbent (Preprocess kept)."""
+        _check(load_library().gfors_reset(self._h()))
 
     def synchronize(self):
         self.stream.synchronize()
