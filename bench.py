@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--k-int", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--tti-rounds", type=int, default=60)
+    ap.add_argument("--tti-rounds", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
     return ap.parse_args()
@@ -140,6 +140,17 @@ def main():
     iters_per_s = a.steps * a.k_int / (gpu_ms / 1e3)
     cands_per_s = a.steps * a.K * bip.num_instances / (gpu_ms / 1e3)
 
+    # iterate statistics at the measured state (what the sampler sees)
+    stt = G.get_state()
+    xs = stt["x"]
+    xbar = 2.0 * xs - stt["x_prev"]
+    q = np.pad(xs, (0, (-xs.size) % 4), constant_values=0.0).reshape(-1, 4)
+    xstats = {"frac_zero": float(np.mean(xs == 0.0)), "frac_one": float(np.mean(xs == 1.0)),
+              "frac_fractional": float(np.mean((xs > 0) & (xs < 1))),
+              "quads_without_draws": float(np.mean(np.all((q == 0.0) | (q == 1.0), axis=1))),
+              "xbar_zero": float(np.mean(xbar == 0.0)),
+              "y_zero": float(np.mean(stt["y"] == 0.0)) if stt["y"].size else None}
+
     # per-kernel HIP-event durations (eager launches, same stream, state advances)
     kt = G.kernel_times(a.k_int, a.K)
     per_step = {k: ms * (a.k_int if k in ("dual", "primal") else 1) for k, (ms, cnt) in kt.items() if cnt}
@@ -184,9 +195,12 @@ def main():
             tti = {"rounds": R, "z_final": zf, "target_gap": 0.001, "round_hit": r_hit,
                    "ms_to_target": round(times[r_hit], 3), "first_feasible_round": int(feas[0]),
                    "ms_to_first_feasible": round(times[int(feas[0])], 3),
-                   "ms_total": round(times[-1], 3)}
+                   "ms_total": round(times[-1], 3),
+                   "avg_ms_per_round": round(times[-1] / R, 4),
+                   "iter_per_s_over_run": round(R * a.k_int / (times[-1] / 1e3), 1)}
         else:
-            tti = {"rounds": R, "z_final": None, "note": "no feasible candidate"}
+            tti = {"rounds": R, "z_final": None, "note": "no feasible candidate",
+                   "avg_ms_per_round": round(times[-1] / R, 4)}
 
     base = None
     if not a.no_cpu_baseline:
@@ -206,7 +220,8 @@ def main():
         "candidates_per_s": round(cands_per_s, 1),
         "wall_s_timed": round(wall, 4),
         "preprocess_s": round(t_pre, 3), "generate_s": round(t_gen, 3),
-        "roofline": roofline, "kernels": kernels,
+        "roofline": roofline, "kernels": kernels, "launch_cfg": G.launch_cfg(),
+        "iterate_stats": xstats,
         "time_to_incumbent": tti,
         "cpu_baseline": base,
     }

@@ -71,12 +71,15 @@ typedef struct {
  *   K_max        largest K accepted by gfors_sample_eval (multiple of 64, <= 4096)
  *   power_iters  power-iteration count for the spectral norms of Preprocess
  *   hist_cap     rounds of incumbent history kept on the device
+ *   autotune     1: time the candidate SpMV launch shapes (lanes per row, fused
+ *                or XCD-sliced) on the problem at creation and keep the fastest;
+ *                0: use the size heuristic (deterministic choice)
  *   x0           starting point x_0 = x0 * 1 (in [0,1])
  *   seed         Philox4x32-10 key (low 32 bits = key word 0, high = key word 1) */
 typedef struct {
     double sigma, tau1, tau2;
     double rho_min, rho_max, rho_T, rho_p, rho_delta;
-    int32_t k_int, K_max, power_iters, hist_cap;
+    int32_t k_int, K_max, power_iters, hist_cap, autotune;
     double x0;
     uint64_t seed;
 } gfors_params;
@@ -195,6 +198,19 @@ int gfors_get_scales(gfors_problem *P, double *row_scale, double *obj_scale, dou
 #define GFORS_NUM_KERNEL_TIMERS 9
 int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_ms,
                        int32_t *launches);
+
+/* Launch shapes in use: out[6] = {lanes per row of the dual SpMV, lanes per row
+ * of the primal SpMV, column slices of the dual SpMV, slices of the primal,
+ * SELL-64 layout for the dual (0/1), SELL-64 layout for the primal (0/1)}
+ * (1 slice = fused kernel; with SELL the lanes-per-row entry is unused). */
+int gfors_get_launch_cfg(gfors_problem *P, int32_t *out);
+
+/* Force launch shapes (same 6-entry layout as gfors_get_launch_cfg).  Lanes per
+ * row: a power of two in [1, 64]; slices: 1, or 8 when the problem holds the
+ * column-sliced copy (then lanes <= 16; the primal also needs Q = 0); SELL only
+ * where the problem holds the SELL copy.  E_ARG otherwise.  Drops captured
+ * graphs. */
+int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg);
 
 /* Dimensions: n, m1, m2, number of instances. */
 int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32_t *T);

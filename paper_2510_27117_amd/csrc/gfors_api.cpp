@@ -122,9 +122,27 @@ struct gfors_problem {
     int *rows = nullptr;
     double *pv = nullptr, *pu = nullptr, *pw = nullptr, *part = nullptr, *res = nullptr;
     double *dnorm = nullptr;
+    // column-sliced copies for the XCD-sliced SpMV (see k_spmv_part)
+    bool slicedK = false, slicedT = false;
+    int *rpS = nullptr, *ciS = nullptr, *valS = nullptr;      // Kc, 8 column slices of x
+    int *rpST = nullptr, *ciST = nullptr, *valST = nullptr;   // Kc^T, 8 slices of the rows
+    float *spart = nullptr;
+    DevCounters *ctr_scratch = nullptr;
+    // SELL-64 copies: dual fused (rows of K), dual sliced (8 column slices), primal fused
+    bool sellK_want = false, sellKS_want = false, sellT_want = false;
+    SellView sellK, sellKS, sellT;
+    int64_t sellK_cap = 0, sellKS_cap = 0, sellT_cap = 0;
+    int *sellK_buf[4] = {}, *sellKS_buf[4] = {}, *sellT_buf[4] = {};
+    int red_S = 1;                  // tile slices of the candidate reduction
+    int32_t *red_v = nullptr;
+    int64_t *red_z = nullptr;
 
     // graphs: key = (K, parity)
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    void graphs_clear() {
+        for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
 };
 
 namespace {
@@ -243,6 +261,7 @@ void gfors_default_params(gfors_params *p) {
     p->K_max = 1024;
     p->power_iters = 200;
     p->hist_cap = 4096;
+    p->autotune = 1;
     p->x0 = 0.0;
     p->seed = 0;
 }
@@ -252,6 +271,12 @@ const char *gfors_last_error(void) { return g_err.c_str(); }
 static int check_K(int64_t K) {
     if (K < 64 || K > 4096 || K % 64 != 0 || (K > 1024 && K % 1024 != 0)) return 0;
     return 1;
+}
+
+// The XCD-sliced SpMV pays when a row's random gathers span a vector larger than
+// one XCD's L2 and rows are long enough to keep ~2+ entries per slice.
+static bool want_slices(int64_t rows, int64_t vec_len, int64_t nnz) {
+    return nnz > 0 && vec_len >= (int64_t{1} << 19) && nnz >= 16 * rows;
 }
 
 // Carve every device buffer; with base == null only measures the size.
@@ -283,11 +308,11 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->d_inst_nvar = cv.take<int64_t>(T);
     P->xbuf[0] = cv.take<float>(n);
     P->xbuf[1] = cv.take<float>(n);
-    P->xbar = cv.take<float>(n);
+    P->xbar = cv.take<float>(n + 1);   // [n] stays 0: target of SELL padding
     P->xsave = cv.take<float>(n);
     P->ybuf[0] = cv.take<float>(m);
     P->ybuf[1] = cv.take<float>(m);
-    P->wy = cv.take<float>(m);
+    P->wy = cv.take<float>(m + 1);     // [m] stays 0: target of SELL padding
     P->X = cv.take<uint64_t>(n * Wmax);
     P->xbest = cv.take<uint8_t>(n);
     P->zpart = cv.take<int64_t>(b.st * prm->K_max);
@@ -305,6 +330,41 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->res = cv.take<double>(4 * static_cast<int64_t>(T));
     P->dnorm = cv.take<double>(2 * static_cast<int64_t>(T));
     P->ctr = cv.take<DevCounters>(1);
+    P->ctr_scratch = cv.take<DevCounters>(1);
+    // stage-1 reduction buffers: T * S <= max(T, 64) slices of K_max candidates
+    P->red_v = cv.take<int32_t>(std::max<int64_t>(T, 64) * prm->K_max);
+    P->red_z = cv.take<int64_t>(std::max<int64_t>(T, 64) * prm->K_max);
+    P->slicedK = want_slices(m, n, nnzK);
+    P->slicedT = want_slices(n, m, nnzK);
+    if (P->slicedK) {
+        P->rpS = cv.take<int>(static_cast<int64_t>(kXcdSlices) * (m + 1));
+        P->ciS = cv.take<int>(nnzK);
+        P->valS = cv.take<int>(nnzK);
+    }
+    if (P->slicedT) {
+        P->rpST = cv.take<int>(static_cast<int64_t>(kXcdSlices) * (n + 1));
+        P->ciST = cv.take<int>(nnzK);
+        P->valST = cv.take<int>(nnzK);
+    }
+    // SELL-64 copies for short rows (lane = row); the entry budget allows 50%
+    // padding (a larger need disables the layout for that matrix)
+    auto sell_carve = [&](bool want, int64_t rows, int Pn, int64_t nnz, int64_t &cap, int *(&buf)[4]) {
+        if (!want) return;
+        const int64_t nch = ceil_div(rows, 64);
+        cap = nnz + nnz / 2 + 2 * 64 * Pn * nch;
+        buf[0] = cv.take<int>(Pn * (nch + 1));
+        buf[1] = cv.take<int>(cap);
+        buf[2] = cv.take<int>(cap);
+        buf[3] = cv.take<int>(Pn * nch * 64);
+    };
+    P->sellK_want = m > 0 && nnzK <= 32 * m;
+    P->sellKS_want = P->slicedK;
+    P->sellT_want = m > 0 && nnzK <= 32 * n && nnzQ == 0;
+    sell_carve(P->sellK_want, m, 1, nnzK, P->sellK_cap, P->sellK_buf);
+    sell_carve(P->sellKS_want, m, kXcdSlices, nnzK, P->sellKS_cap, P->sellKS_buf);
+    sell_carve(P->sellT_want, n, 1, nnzK, P->sellT_cap, P->sellT_buf);
+    if (P->slicedK || P->slicedT)
+        P->spart = cv.take<float>(static_cast<int64_t>(kXcdSlices) * std::max(P->slicedK ? m : 0, P->slicedT ? n : 0));
     DevInst &d = P->di;
     d.rho = cv.take<double>(T);
     d.ntrig = cv.take<int64_t>(T);
@@ -364,6 +424,7 @@ void gfors_destroy_problem(gfors_problem *P) {
 }
 
 static int device_norms(gfors_problem *P);
+static int autotune(gfors_problem *P);
 
 int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *B,
                          const int64_t *d, const gfors_csr *Q, const int64_t *c, int64_t n,
@@ -551,6 +612,14 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         }
     }
     for (HostTiles *h : {&hs, &he, &hq, &hv, &hr}) finish_first(*h, T);
+    {
+        int maxt = 1;
+        for (int t = 0; t < T; ++t)
+            for (HostTiles *h : {&hs, &he, &hq})
+                maxt = std::max(maxt, h->first[t + 1] - h->first[t]);
+        const int cap = T >= 64 ? 1 : std::max(1, 64 / T);
+        P->red_S = std::max(1, std::min(cap, static_cast<int>(ceil_div(maxt, 32))));
+    }
     P->n_cover = static_cast<int>(cover_ids.size());
     P->n_general = static_cast<int>(general_ids.size());
 
@@ -595,6 +664,102 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         if ((rc = upload(s, P->ciQ, ciQ.data(), P->nnzQ))) return rc;
         if ((rc = upload(s, P->valQ, valQ.data(), P->nnzQ))) return rc;
     }
+    // column-sliced copies: slice q of the variables is [q*ns, (q+1)*ns)
+    auto build_sliced = [&](int64_t rows, int64_t cols, const std::vector<int> &rpx,
+                            const std::vector<int> &cix, const std::vector<int> &valx,
+                            int *d_rp, int *d_ci, int *d_val) -> int {
+        const int64_t ns = ceil_div(cols, kXcdSlices);
+        std::vector<int> srp(static_cast<size_t>(kXcdSlices) * (rows + 1));
+        std::vector<int> sci(cix.size()), sval(cix.size());
+        std::vector<int64_t> cnt(kXcdSlices, 0);
+        for (size_t e = 0; e < cix.size(); ++e) cnt[cix[e] / ns]++;
+        std::vector<int64_t> base(kXcdSlices + 1, 0);
+        for (int q = 0; q < kXcdSlices; ++q) base[q + 1] = base[q] + cnt[q];
+        std::vector<int64_t> pos(base.begin(), base.end() - 1);
+        for (int64_t r = 0; r < rows; ++r) {
+            for (int q = 0; q < kXcdSlices; ++q) srp[q * (rows + 1) + r] = static_cast<int>(pos[q]);
+            for (int e = rpx[r]; e < rpx[r + 1]; ++e) {
+                const int q = static_cast<int>(cix[e] / ns);
+                sci[pos[q]] = cix[e];
+                sval[pos[q]] = valx[e];
+                pos[q]++;
+            }
+        }
+        for (int q = 0; q < kXcdSlices; ++q) srp[q * (rows + 1) + rows] = static_cast<int>(pos[q]);
+        int r2;
+        if ((r2 = upload(s, d_rp, srp.data(), static_cast<int64_t>(srp.size())))) return r2;
+        if ((r2 = upload(s, d_ci, sci.data(), static_cast<int64_t>(sci.size())))) return r2;
+        if ((r2 = upload(s, d_val, sval.data(), static_cast<int64_t>(sval.size())))) return r2;
+        return sync(P);
+    };
+    // SELL-64: per column slice, rows sorted by length (descending, stable) inside
+    // windows of 8192 rows, chunks of 64 rows padded to the longest row
+    auto build_sell = [&](int64_t rows, int64_t cols, int Pn, const std::vector<int> &rpx,
+                          const std::vector<int> &cix, const std::vector<int> &valx, int pad_col,
+                          int64_t cap, int *(&buf)[4], SellView &sv) -> int {
+        const int64_t nch = ceil_div(rows, 64);
+        const int64_t ns = ceil_div(std::max<int64_t>(cols, 1), Pn);
+        std::vector<int> sptr(static_cast<size_t>(Pn) * (nch + 1)), srow(static_cast<size_t>(Pn) * nch * 64, -1);
+        std::vector<int> sci, sval;
+        sci.reserve(static_cast<size_t>(cix.size() * 1.2) + 64);
+        sval.reserve(sci.capacity());
+        std::vector<int> len(rows), order(rows);
+        std::vector<std::vector<int>> ent(0);
+        for (int q = 0; q < Pn; ++q) {
+            for (int64_t r = 0; r < rows; ++r) {
+                int cnt = 0;
+                for (int e = rpx[r]; e < rpx[r + 1]; ++e) cnt += (cix[e] / ns) == q;
+                len[r] = cnt;
+                order[r] = static_cast<int>(r);
+            }
+            const int64_t win = 8192;
+            for (int64_t w0 = 0; w0 < rows; w0 += win) {
+                const int64_t w1 = std::min(rows, w0 + win);
+                std::stable_sort(order.begin() + w0, order.begin() + w1,
+                                 [&](int a, int b2) { return len[a] > len[b2]; });
+            }
+            for (int64_t c = 0; c < nch; ++c) {
+                sptr[q * (nch + 1) + c] = static_cast<int>(sci.size());
+                int L = 0;
+                for (int l = 0; l < 64 && c * 64 + l < rows; ++l) L = std::max(L, len[order[c * 64 + l]]);
+                const size_t base = sci.size();
+                if (static_cast<int64_t>(base) + 64LL * L > cap) { sv = SellView(); return GFORS_OK; }
+                sci.resize(base + 64 * static_cast<size_t>(L), pad_col);
+                sval.resize(base + 64 * static_cast<size_t>(L), 0);
+                for (int l = 0; l < 64 && c * 64 + l < rows; ++l) {
+                    const int r = order[c * 64 + l];
+                    srow[(static_cast<size_t>(q) * nch + c) * 64 + l] = r;
+                    int k = 0;
+                    for (int e = rpx[r]; e < rpx[r + 1]; ++e)
+                        if ((cix[e] / ns) == q) {
+                            sci[base + 64 * k + l] = cix[e];
+                            sval[base + 64 * k + l] = valx[e];
+                            ++k;
+                        }
+                }
+            }
+            sptr[q * (nch + 1) + nch] = static_cast<int>(sci.size());
+        }
+        int r2;
+        if ((r2 = upload(s, buf[0], sptr.data(), static_cast<int64_t>(sptr.size())))) return r2;
+        if ((r2 = upload(s, buf[1], sci.data(), static_cast<int64_t>(sci.size())))) return r2;
+        if ((r2 = upload(s, buf[2], sval.data(), static_cast<int64_t>(sval.size())))) return r2;
+        if ((r2 = upload(s, buf[3], srow.data(), static_cast<int64_t>(srow.size())))) return r2;
+        if ((r2 = sync(P))) return r2;
+        sv.nrows = static_cast<int>(rows);
+        sv.P = Pn;
+        sv.nchunk = static_cast<int>(nch);
+        sv.ptr = buf[0];
+        sv.ci = buf[1];
+        sv.val = buf[2];
+        sv.row_of = buf[3];
+        return GFORS_OK;
+    };
+    if (P->sellK_want && (rc = build_sell(m, n, 1, rp, ci, val, static_cast<int>(n), P->sellK_cap, P->sellK_buf, P->sellK))) return rc;
+    if (P->sellKS_want && (rc = build_sell(m, n, kXcdSlices, rp, ci, val, static_cast<int>(n), P->sellKS_cap, P->sellKS_buf, P->sellKS))) return rc;
+    if (P->sellT_want && (rc = build_sell(n, m, 1, rpT, ciT, valT, static_cast<int>(m), P->sellT_cap, P->sellT_buf, P->sellT))) return rc;
+    if (P->slicedK && (rc = build_sliced(m, n, rp, ci, val, P->rpS, P->ciS, P->valS))) return rc;
+    if (P->slicedT && (rc = build_sliced(n, m, rpT, ciT, valT, P->rpST, P->ciST, P->valST))) return rc;
     if ((rc = upload(s, P->rhs, rhs.data(), m))) return rc;
     if ((rc = upload(s, P->cost, c, n))) return rc;
     if ((rc = upload(s, P->var_inst, var_inst.data(), n))) return rc;
@@ -710,7 +875,8 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     launch_fill_f32(s, P->xbar, static_cast<float>(prm->x0), n);
     launch_fill_f32(s, P->ybuf[0], 0.f, m);
     launch_fill_f32(s, P->ybuf[1], 0.f, m);
-    launch_fill_f32(s, P->wy, 0.f, m);
+    launch_fill_f32(s, P->wy, 0.f, m + 1);
+    launch_fill_f32(s, P->xbar + n, 0.f, 1);
     HIP_TRY(hipGetLastError());
     // launch shapes: lanes per row ~ average row length (rounded to a power of two)
     auto pick = [](double avg) {
@@ -720,7 +886,12 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     };
     P->cfg.lpr_dual = pick(m ? static_cast<double>(P->nnzK) / m : 1.0);
     P->cfg.lpr_primal = pick(static_cast<double>(P->nnzK + P->nnzQ) / n);
+    if (P->slicedK) {
+        P->cfg.slices_dual = kXcdSlices;
+        P->cfg.lpr_dual = pick(static_cast<double>(P->nnzK) / m / kXcdSlices);
+    }
     if ((rc = sync(P))) return rc;
+    if (prm->autotune && (rc = autotune(P))) return rc;
     *out = guard.release();
     return GFORS_OK;
 }
@@ -773,6 +944,116 @@ static int device_norms(gfors_problem *P) {
     return GFORS_OK;
 }
 
+static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, const float *y_in,
+                            float *y_out) {
+    hipStream_t s = P->stream;
+    const bool batched = P->T > 1;
+    const float tau2 = static_cast<float>(P->tau2[0]);
+    if (sell && slices > 1) {
+        launch_sell(s, P->sellKS, 0, P->unitK, batched, P->xbar, P->spart, 0, nullptr, nullptr,
+                    nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, nullptr, nullptr, nullptr,
+                    nullptr, 0.f, nullptr, nullptr, nullptr, nullptr);
+        launch_dual_combine(s, batched, static_cast<int>(P->m), static_cast<int>(P->m1), slices,
+                            P->spart, P->omega, P->rt, y_in, y_out, P->wy, tau2, P->di.tau2,
+                            P->row_inst);
+    } else if (sell) {
+        launch_sell(s, P->sellK, 1, P->unitK, batched, P->xbar, nullptr, static_cast<int>(P->m1),
+                    P->omega, P->rt, y_in, y_out, P->wy, tau2, P->di.tau2, P->row_inst, nullptr,
+                    nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, nullptr, nullptr);
+    } else if (slices > 1) {
+        launch_spmv_part(s, lpr, P->unitK, static_cast<int>(P->m), slices, P->rpS, P->ciS,
+                         P->valS, P->xbar, P->spart);
+        launch_dual_combine(s, batched, static_cast<int>(P->m), static_cast<int>(P->m1), slices,
+                            P->spart, P->omega, P->rt, y_in, y_out, P->wy,
+                            static_cast<float>(P->tau2[0]), P->di.tau2, P->row_inst);
+    } else {
+        launch_dual(s, lpr, P->unitK, batched, static_cast<int>(P->m), static_cast<int>(P->m1),
+                    P->rp, P->ci, P->val, P->omega, P->rt, P->xbar, y_in, y_out, P->wy,
+                    static_cast<float>(P->tau2[0]), P->di.tau2, P->row_inst);
+    }
+}
+
+static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, const float *x_in,
+                              float *x_out, float *xbar, DevCounters *ctr) {
+    hipStream_t s = P->stream;
+    const bool batched = P->T > 1;
+    const int kmode = P->m == 0 ? 0 : (P->unitK ? 1 : 2);
+    if (sell) {
+        launch_sell(s, P->sellT, 2, P->unitK, batched, P->wy, nullptr, 0, nullptr, nullptr, nullptr,
+                    nullptr, nullptr, 0.f, nullptr, nullptr, x_in, x_out, xbar, P->ct,
+                    static_cast<float>(P->tau1[0]), P->di.tau1, P->di.rho, P->var_inst, ctr);
+    } else if (slices > 1) {
+        launch_spmv_part(s, lpr, P->unitK, static_cast<int>(P->n), slices, P->rpST, P->ciST,
+                         P->valST, P->wy, P->spart);
+        launch_primal_combine(s, batched, static_cast<int>(P->n), slices, P->spart, x_in, x_out,
+                              xbar, P->ct, static_cast<float>(P->tau1[0]), P->di.tau1, P->di.rho,
+                              P->var_inst, ctr);
+    } else {
+        launch_primal(s, lpr, kmode, P->hasQ, batched, static_cast<int>(P->n), P->rpT, P->ciT,
+                      P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct,
+                      static_cast<float>(P->tau1[0]),
+                      static_cast<float>(P->s_o[0] > 0 ? 2.0 / P->s_o[0] : 2.0), P->di.tau1,
+                      P->di.two_so, P->di.rho, P->var_inst, ctr);
+    }
+}
+
+// Autotuner: time every candidate launch shape of the dual and primal SpMV on
+// this problem's own data (HIP events, 1 warm-up + 5 timed launches each) and
+// keep the fastest.  Outputs go to buffers that carry no state at this point.
+static int autotune(gfors_problem *P) {
+    hipStream_t s = P->stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto timeit = [&](const std::function<void()> &f) -> float {
+        f();
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 5; ++r) f();
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms / 5.f;
+    };
+    const int lprs[] = {1, 2, 4, 8, 16, 32, 64};
+    if (P->m > 0) {
+        float best = 1e30f;
+        auto consider = [&](int l, int sl, int se) {
+            const float t = timeit([&] { launch_dual_cfg(P, l, sl, se, P->ybuf[P->cur], P->ybuf[1 - P->cur]); });
+            if (t < best) { best = t; P->cfg.lpr_dual = l; P->cfg.slices_dual = sl; P->cfg.sell_dual = se; }
+        };
+        for (int sl : {1, kXcdSlices}) {
+            if (sl > 1 && !P->slicedK) continue;
+            for (int l : lprs) {
+                if (sl > 1 && l > 16) continue;
+                consider(l, sl, 0);
+            }
+        }
+        if (P->sellK.ptr) consider(1, 1, 1);
+        if (P->sellKS.ptr) consider(1, kXcdSlices, 1);
+    }
+    {
+        float best = 1e30f;
+        float *xs = P->xsave, *xb = reinterpret_cast<float *>(P->pv);
+        auto consider = [&](int l, int sl, int se) {
+            const float t = timeit([&] { launch_primal_cfg(P, l, sl, se, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
+            if (t < best) { best = t; P->cfg.lpr_primal = l; P->cfg.slices_primal = sl; P->cfg.sell_primal = se; }
+        };
+        for (int sl : {1, kXcdSlices}) {
+            if (sl > 1 && (!P->slicedT || P->hasQ)) continue;
+            for (int l : lprs) {
+                if (sl > 1 && l > 16) continue;
+                consider(l, sl, 0);
+            }
+        }
+        if (P->sellT.ptr) consider(1, 1, 1);
+    }
+    HIP_TRY(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return sync(P);
+}
+
 static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *tm = nullptr) {
     hipStream_t s = P->stream;
     const bool batched = P->T > 1;
@@ -783,17 +1064,12 @@ static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *t
         const int a = P->cur, bnext = 1 - P->cur;
         TB(0);
         if (P->m > 0)
-            launch_dual(s, P->cfg.lpr_dual, P->unitK, batched, static_cast<int>(P->m),
-                        static_cast<int>(P->m1), P->rp, P->ci, P->val, P->omega, P->rt, P->xbar,
-                        P->ybuf[a], P->ybuf[bnext], P->wy, static_cast<float>(P->tau2[0]),
-                        P->di.tau2, P->row_inst);
+            launch_dual_cfg(P, P->cfg.lpr_dual, P->cfg.slices_dual, P->cfg.sell_dual, P->ybuf[a],
+                            P->ybuf[bnext]);
         TE(0);
         TB(1);
-        launch_primal(s, P->cfg.lpr_primal, kmode, P->hasQ, batched, static_cast<int>(P->n),
-                      P->rpT, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, P->xbuf[a],
-                      P->xbuf[bnext], P->xbar, P->ct, static_cast<float>(P->tau1[0]),
-                      static_cast<float>(P->s_o[0] > 0 ? 2.0 / P->s_o[0] : 2.0), P->di.tau1,
-                      P->di.two_so, P->di.rho, P->var_inst, P->ctr);
+        launch_primal_cfg(P, P->cfg.lpr_primal, P->cfg.slices_primal, P->cfg.sell_primal,
+                          P->xbuf[a], P->xbuf[bnext], P->xbar, P->ctr);
         TE(1);
         if (res) {
             const int T = P->T;
@@ -839,8 +1115,8 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     if (P->hasQ) launch_eval_quad(s, P->qt, P->d_inst_var0, P->rpQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K);
     TE(5);
     TB(6);
-    launch_reduce_cand(s, P->T, K, P->et, P->vpart, P->st, P->zpart, P->qt, P->zqpart,
-                       P->hasQ ? 1 : 0, P->viol, P->z);
+    launch_reduce_cand(s, P->T, K, P->red_S, P->et, P->vpart, P->st, P->zpart, P->qt, P->zqpart,
+                       P->hasQ ? 1 : 0, P->red_v, P->red_z, P->viol, P->z);
     TE(6);
     TB(7);
     launch_argmin_update(s, P->T, K, W, P->viol, P->z, P->di, P->ctr, threshold ? 0 : 1);
@@ -1001,7 +1277,8 @@ int gfors_reset(gfors_problem *P) {
     launch_fill_f32(s, P->xbar, x0, P->n);
     launch_fill_f32(s, P->ybuf[0], 0.f, P->m);
     launch_fill_f32(s, P->ybuf[1], 0.f, P->m);
-    launch_fill_f32(s, P->wy, 0.f, P->m);
+    launch_fill_f32(s, P->wy, 0.f, P->m + 1);
+    launch_fill_f32(s, P->xbar + P->n, 0.f, 1);
     std::vector<int64_t> zeros(T, 0), big(T, INT64_MAX), neg(T, -2);
     std::vector<int32_t> z32(T, 0);
     std::vector<int64_t> h(static_cast<size_t>(T) * P->di.hist_cap, INT64_MAX);
@@ -1068,6 +1345,39 @@ int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_
         avg_ms[id] = cnt ? tot / static_cast<double>(cnt) : 0.0;
         if (launches) launches[id] = static_cast<int32_t>(cnt);
     }
+    return GFORS_OK;
+}
+
+int gfors_get_launch_cfg(gfors_problem *P, int32_t *out) {
+    if (!P || !out) return fail(GFORS_E_ARG, "bad argument");
+    out[0] = P->cfg.lpr_dual;
+    out[1] = P->cfg.lpr_primal;
+    out[2] = P->cfg.slices_dual;
+    out[3] = P->cfg.slices_primal;
+    out[4] = P->cfg.sell_dual;
+    out[5] = P->cfg.sell_primal;
+    return GFORS_OK;
+}
+
+int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
+    if (!P || !cfg) return fail(GFORS_E_ARG, "bad argument");
+    auto pow2 = [](int v) { return v >= 1 && v <= 64 && (v & (v - 1)) == 0; };
+    if (!pow2(cfg[0]) || !pow2(cfg[1])) return fail(GFORS_E_ARG, "lanes per row must be a power of two in [1, 64]");
+    if (cfg[2] != 1 && !(cfg[2] == kXcdSlices && (P->slicedK || P->sellKS.ptr) && cfg[0] <= 16))
+        return fail(GFORS_E_ARG, "dual slices must be 1, or 8 when the sliced copy exists (lanes <= 16)");
+    if (cfg[3] != 1 && !(cfg[3] == kXcdSlices && P->slicedT && !P->hasQ && cfg[1] <= 16))
+        return fail(GFORS_E_ARG, "primal slices must be 1, or 8 when the sliced copy exists, Q = 0 (lanes <= 16)");
+    if (cfg[4] && !((cfg[2] == 1 && P->sellK.ptr) || (cfg[2] == kXcdSlices && P->sellKS.ptr)))
+        return fail(GFORS_E_ARG, "no SELL copy of the constraint rows for this slicing");
+    if (cfg[5] && !(cfg[3] == 1 && P->sellT.ptr))
+        return fail(GFORS_E_ARG, "no SELL copy of the transposed rows");
+    P->cfg.lpr_dual = cfg[0];
+    P->cfg.lpr_primal = cfg[1];
+    P->cfg.slices_dual = cfg[2];
+    P->cfg.slices_primal = cfg[3];
+    P->cfg.sell_dual = cfg[4] ? 1 : 0;
+    P->cfg.sell_primal = cfg[5] ? 1 : 0;
+    P->graphs_clear();
     return GFORS_OK;
 }
 

@@ -54,10 +54,24 @@ struct Tiles {
     int32_t *first = nullptr;  // [T+1] first tile of each instance (tiles sorted by instance)
 };
 
+// Launch shapes picked per problem (heuristic or timed by the autotuner).
+// slices: 1 = fused CSR kernel; > 1 = XCD-sliced partial SpMV + combine.
 struct LaunchCfg {
     int lpr_dual = 16;     // lanes per row for the dual SpMV
     int lpr_primal = 4;    // lanes per row for the transposed SpMV (+Q)
+    int slices_dual = 1;
+    int slices_primal = 1;
+    int sell_dual = 0;     // 1: SELL-64 layout (lane = row) instead of CSR
+    int sell_primal = 0;
 };
+
+// A SELL-64 matrix (possibly cut into P column slices, each with nchunk chunks).
+struct SellView {
+    int nrows = 0, P = 1, nchunk = 0;
+    const int *ptr = nullptr, *ci = nullptr, *val = nullptr, *row_of = nullptr;
+};
+
+constexpr int kXcdSlices = 8;   // XCDs per MI355X
 
 // ------------------------------------------------------------------ PDHG
 void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
@@ -71,6 +85,23 @@ void launch_primal(hipStream_t s, int lpr, int kmode, bool hasq, bool batched, i
                    float *x_out, float *xbar, const float *ct, float tau1, float two_so,
                    const float *tau1_inst, const float *two_so_inst, const double *rho,
                    const int *var_inst, DevCounters *ctr);
+
+void launch_spmv_part(hipStream_t s, int lpr, bool unit, int nrows, int P, const int *rpP,
+                      const int *ci, const int *val, const float *v, float *part);
+void launch_dual_combine(hipStream_t s, bool batched, int m, int m1, int P, const float *part,
+                         const float *omega, const float *rt, const float *y_in, float *y_out,
+                         float *wy, float tau2, const float *tau2_inst, const int *row_inst);
+void launch_primal_combine(hipStream_t s, bool batched, int n, int P, const float *part,
+                           const float *x_in, float *x_out, float *xbar, const float *ct,
+                           float tau1, const float *tau1_inst, const double *rho,
+                           const int *var_inst, DevCounters *ctr);
+
+void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool batched,
+                 const float *v, float *part, int m1, const float *omega, const float *rt,
+                 const float *y_in, float *y_out, float *wy, float tau2, const float *tau2_inst,
+                 const int *row_inst, const float *x_in, float *x_out, float *xbar,
+                 const float *ct, float tau1, const float *tau1_inst, const double *rho,
+                 const int *var_inst, DevCounters *ctr);
 
 void launch_copy_f32(hipStream_t s, float *dst, const float *src, int64_t n);
 void launch_set_xbar(hipStream_t s, int64_t n, const float *x, const float *xp, float *xbar);
@@ -110,9 +141,10 @@ void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const T
 void launch_eval_quad(hipStream_t s, const Tiles &qt, const int64_t *inst_var0,
                       const int *rpQ, const int *ciQ, const int *valQ, const uint64_t *X,
                       int W, int64_t *zqpart, int K);
-void launch_reduce_cand(hipStream_t s, int T, int K, const Tiles &et, const int *vpart,
+void launch_reduce_cand(hipStream_t s, int T, int K, int S, const Tiles &et, const int *vpart,
                         const Tiles &st, const int64_t *zpart, const Tiles &qt,
-                        const int64_t *zqpart, int has_q, int32_t *viol, int64_t *z);
+                        const int64_t *zqpart, int has_q, int32_t *rv, int64_t *rz,
+                        int32_t *viol, int64_t *z);
 void launch_argmin_update(hipStream_t s, int T, int K, int W, const int32_t *viol,
                           const int64_t *z, DevInst di, DevCounters *ctr, int advance);
 void launch_extract_best(hipStream_t s, int64_t n, int T, const int *var_inst,

@@ -77,6 +77,14 @@ k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ ciT,
     const int i = tid / LPR;
     const int sub = tid & (LPR - 1);
     float s1 = 0.f, s2 = 0.f;
+    // per-row operands are independent of the gathers: load them first
+    float xi = 0.f, cti = 0.f;
+    int t = 0;
+    if (i < n) {
+        xi = x_in[i];
+        cti = ct[i];
+        if (BATCH) t = var_inst[i];
+    }
     if (i < n) {
         if (KMODE != 0) {
             const int e1 = rpT[i + 1];
@@ -95,11 +103,9 @@ k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ ciT,
     if (KMODE != 0) s1 = group_sum<LPR>(s1);
     if (HASQ) s2 = group_sum<LPR>(s2);
     if (i < n && sub == 0) {
-        const int t = BATCH ? var_inst[i] : 0;
         const float rh = static_cast<float>(rho[t]);
         const float ta = BATCH ? tau1_inst[t] : tau1;
-        const float xi = x_in[i];
-        float g = ct[i] + rh;
+        float g = cti + rh;
         if (KMODE != 0) g -= s1;
         if (HASQ) g = fmaf(BATCH ? two_so_inst[t] : two_so, s2, g);
         g -= 2.f * rh * xi;
@@ -181,6 +187,204 @@ void launch_primal(hipStream_t s, int lpr, int kmode, bool hasq, bool batched, i
 #undef GF_CASE
         default: break;
     }
+}
+
+// ---------------------------------------------------------------------------
+// XCD-sliced SpMV.  The columns are cut into P slices and the matrix is stored
+// as P CSR matrices (slice-major).  Workgroup b works on slice b % P: the
+// hardware hands consecutive workgroups to consecutive XCDs, so with P = 8 every
+// XCD gathers from one slice of the vector only and that slice stays resident
+// in the XCD's own L2.  Each slice writes its partial row sums; the combine
+// kernels below add the P partials in a fixed order and apply the PDHG update.
+// ---------------------------------------------------------------------------
+template <int LPR, bool UNIT>
+__global__ void __launch_bounds__(256)
+k_spmv_part(int nrows, int P, const int *__restrict__ rpP, const int *__restrict__ ci,
+            const int *__restrict__ val, const float *__restrict__ v, float *__restrict__ part) {
+    const int sl = blockIdx.x % P;
+    const int chunk = blockIdx.x / P;
+    const int row = chunk * (256 / LPR) + static_cast<int>(threadIdx.x) / LPR;
+    const int sub = threadIdx.x & (LPR - 1);
+    const int *rp = rpP + static_cast<int64_t>(sl) * (nrows + 1);
+    float acc = 0.f;
+    if (row < nrows) {
+        const int e1 = rp[row + 1];
+        for (int e = rp[row] + sub; e < e1; e += LPR) {
+            const int c = __builtin_nontemporal_load(ci + e);
+            const float xv = v[c];
+            if (UNIT) acc += xv;
+            else acc = fmaf(static_cast<float>(__builtin_nontemporal_load(val + e)), xv, acc);
+        }
+    }
+    acc = group_sum<LPR>(acc);
+    if (row < nrows && sub == 0) part[static_cast<int64_t>(sl) * nrows + row] = acc;
+}
+
+template <bool BATCH>
+__global__ void __launch_bounds__(256)
+k_dual_combine(int m, int m1, int P, const float *__restrict__ part,
+               const float *__restrict__ omega, const float *__restrict__ rt,
+               const float *__restrict__ y_in, float *__restrict__ y_out, float *__restrict__ wy,
+               float tau2, const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= m) return;
+    float s = 0.f;
+    for (int q = 0; q < P; ++q) s += part[static_cast<int64_t>(q) * m + row];
+    const float om = omega[row];
+    const float t = rt[row] - om * s;
+    const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
+    float y = y_in[row] + ta * t;
+    if (row < m1) y = fmaxf(y, 0.f);
+    y_out[row] = y;
+    wy[row] = om * y;
+}
+
+template <bool BATCH>
+__global__ void __launch_bounds__(256)
+k_primal_combine(int n, int P, const float *__restrict__ part, const float *__restrict__ x_in,
+                 float *__restrict__ x_out, float *__restrict__ xbar, const float *__restrict__ ct,
+                 float tau1, const float *__restrict__ tau1_inst, const double *__restrict__ rho,
+                 const int *__restrict__ var_inst, DevCounters *__restrict__ ctr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) ctr->k += 1;
+    if (i >= n) return;
+    const int t = BATCH ? var_inst[i] : 0;
+    const float xi = x_in[i];
+    float s1 = 0.f;
+    for (int q = 0; q < P; ++q) s1 += part[static_cast<int64_t>(q) * n + i];
+    const float rh = static_cast<float>(rho[t]);
+    const float ta = BATCH ? tau1_inst[t] : tau1;
+    const float g = ct[i] + rh - s1 - 2.f * rh * xi;
+    const float xn = fminf(fmaxf(xi - ta * g, 0.f), 1.f);
+    x_out[i] = xn;
+    xbar[i] = 2.f * xn - xi;
+}
+
+template <int LPR>
+static void spmv_part_lpr(hipStream_t s, bool unit, int nrows, int P, const int *rpP,
+                          const int *ci, const int *val, const float *v, float *part) {
+    const int rows_per_block = 256 / LPR;
+    const int64_t chunks = (static_cast<int64_t>(nrows) + rows_per_block - 1) / rows_per_block;
+    const int64_t blocks = chunks * P;
+    if (blocks == 0) return;
+    if (unit) k_spmv_part<LPR, true><<<static_cast<int>(blocks), 256, 0, s>>>(nrows, P, rpP, ci, val, v, part);
+    else k_spmv_part<LPR, false><<<static_cast<int>(blocks), 256, 0, s>>>(nrows, P, rpP, ci, val, v, part);
+}
+
+void launch_spmv_part(hipStream_t s, int lpr, bool unit, int nrows, int P, const int *rpP,
+                      const int *ci, const int *val, const float *v, float *part) {
+    switch (lpr) {
+#define GF_CASE(L) case L: spmv_part_lpr<L>(s, unit, nrows, P, rpP, ci, val, v, part); break;
+        GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
+#undef GF_CASE
+        default: break;
+    }
+}
+
+void launch_dual_combine(hipStream_t s, bool batched, int m, int m1, int P, const float *part,
+                         const float *omega, const float *rt, const float *y_in, float *y_out,
+                         float *wy, float tau2, const float *tau2_inst, const int *row_inst) {
+    const int blocks = (m + 255) / 256;
+    if (!blocks) return;
+    if (batched) k_dual_combine<true><<<blocks, 256, 0, s>>>(m, m1, P, part, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst);
+    else k_dual_combine<false><<<blocks, 256, 0, s>>>(m, m1, P, part, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst);
+}
+
+void launch_primal_combine(hipStream_t s, bool batched, int n, int P, const float *part,
+                           const float *x_in, float *x_out, float *xbar, const float *ct,
+                           float tau1, const float *tau1_inst, const double *rho,
+                           const int *var_inst, DevCounters *ctr) {
+    const int blocks = (n + 255) / 256;
+    if (!blocks) return;
+    if (batched) k_primal_combine<true><<<blocks, 256, 0, s>>>(n, P, part, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr);
+    else k_primal_combine<false><<<blocks, 256, 0, s>>>(n, P, part, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr);
+}
+
+// ---------------------------------------------------------------------------
+// SELL-64 (sliced ELLPACK, chunk = one wavefront).  Rows are sorted by length
+// inside windows, cut into chunks of 64 rows, and every chunk is padded to its
+// longest row and stored column-major: entry k of the chunk's lane-th row sits
+// at ptr[c] + 64 k + lane.  Lane = row, so a wavefront issues its column-index
+// loads back to back, each one fully coalesced, and the chunk's extent is a
+// single uniform (scalar) load.  Padding entries point at a zero element
+// placed one past the end of the gathered vector.  row_of maps (chunk, lane)
+// to the original row (-1 for an empty slot).  With P > 1 the matrix is cut
+// into P column slices (as for k_spmv_part), slice = workgroup index % P.
+// MODE 0 writes the slice's partial sums; MODE 1 applies the dual update;
+// MODE 2 the primal update (no Q).
+// ---------------------------------------------------------------------------
+template <bool UNIT, int MODE, bool BATCH>
+__global__ void __launch_bounds__(256)
+k_sell(int nrows, int P, int nchunk, const int *__restrict__ ptr, const int *__restrict__ ci,
+       const int *__restrict__ val, const int *__restrict__ row_of, const float *__restrict__ v,
+       float *__restrict__ part,
+       // dual epilogue
+       int m1, const float *__restrict__ omega, const float *__restrict__ rt,
+       const float *__restrict__ y_in, float *__restrict__ y_out, float *__restrict__ wy,
+       float tau2, const float *__restrict__ tau2_inst, const int *__restrict__ row_inst,
+       // primal epilogue
+       const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ xbar,
+       const float *__restrict__ ct, float tau1, const float *__restrict__ tau1_inst,
+       const double *__restrict__ rho, const int *__restrict__ var_inst,
+       DevCounters *__restrict__ ctr) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = blockIdx.x % P;
+    const int c = (blockIdx.x / P) * 4 + wave;
+    if (MODE == 2 && blockIdx.x == 0 && threadIdx.x == 0) ctr->k += 1;
+    if (c >= nchunk) return;
+    const int64_t pb = static_cast<int64_t>(sl) * (nchunk + 1);
+    const int e0 = ptr[pb + c];
+    const int L = (ptr[pb + c + 1] - e0) >> 6;
+    const int *cic = ci + e0 + lane;
+    float acc = 0.f;
+    if (UNIT) {
+#pragma unroll 4
+        for (int k = 0; k < L; ++k) acc += v[__builtin_nontemporal_load(cic + 64 * k)];
+    } else {
+        const int *vc = val + e0 + lane;
+#pragma unroll 4
+        for (int k = 0; k < L; ++k)
+            acc = fmaf(static_cast<float>(__builtin_nontemporal_load(vc + 64 * k)),
+                       v[__builtin_nontemporal_load(cic + 64 * k)], acc);
+    }
+    const int row = row_of[(static_cast<int64_t>(sl) * nchunk + c) * 64 + lane];
+    if (row < 0) return;
+    if (MODE == 0) {
+        part[static_cast<int64_t>(sl) * nrows + row] = acc;
+    } else if (MODE == 1) {
+        const float om = omega[row];
+        const float t = rt[row] - om * acc;
+        const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
+        float y = y_in[row] + ta * t;
+        if (row < m1) y = fmaxf(y, 0.f);
+        y_out[row] = y;
+        wy[row] = om * y;
+    } else {
+        const int t = BATCH ? var_inst[row] : 0;
+        const float xi = x_in[row];
+        const float rh = static_cast<float>(rho[t]);
+        const float ta = BATCH ? tau1_inst[t] : tau1;
+        const float g = ct[row] + rh - acc - 2.f * rh * xi;
+        const float xn = fminf(fmaxf(xi - ta * g, 0.f), 1.f);
+        x_out[row] = xn;
+        xbar[row] = 2.f * xn - xi;
+    }
+}
+
+void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool batched,
+                 const float *v, float *part, int m1, const float *omega, const float *rt,
+                 const float *y_in, float *y_out, float *wy, float tau2, const float *tau2_inst,
+                 const int *row_inst, const float *x_in, float *x_out, float *xbar,
+                 const float *ct, float tau1, const float *tau1_inst, const double *rho,
+                 const int *var_inst, DevCounters *ctr) {
+    const int64_t blocks = static_cast<int64_t>((sv.nchunk + 3) / 4) * sv.P;
+    if (blocks == 0) return;
+#define GF_SELL(U, M, B)     k_sell<U, M, B><<<static_cast<int>(blocks), 256, 0, s>>>(sv.nrows, sv.P, sv.nchunk, sv.ptr, sv.ci, sv.val, sv.row_of, v, part, m1, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
+#define GF_SELL_M(U, B)     if (mode == 0) GF_SELL(U, 0, B); else if (mode == 1) GF_SELL(U, 1, B); else GF_SELL(U, 2, B)
+    if (unit) { if (batched) { GF_SELL_M(true, true); } else { GF_SELL_M(true, false); } }
+    else { if (batched) { GF_SELL_M(false, true); } else { GF_SELL_M(false, false); } }
+#undef GF_SELL_M
+#undef GF_SELL
 }
 
 // ------------------------------------------------------------ small helpers

@@ -53,6 +53,8 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
          int64_t *__restrict__ zpart, int K, uint32_t key0, uint32_t key1,
          const DevCounters *__restrict__ ctr, int threshold_mode) {
     extern __shared__ uint64_t lds[];   // [64 variables][W words]
+    __shared__ uint32_t sthr[64];       // thresholds of the sub-tile's 64 variables
+    __shared__ ACC scost[64];
     const int tile = blockIdx.x;
     const int inst = tile_inst[tile];
     const int q0 = tile_q0[tile], q1 = tile_q1[tile];
@@ -68,27 +70,38 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
 
     for (int sq = q0; sq < q1; sq += 16) {
         const int nq = min(16, q1 - sq);
+        // one coalesced load of the sub-tile's probabilities and costs
+        if (threadIdx.x < 64) {
+            const int64_t il = 4LL * sq + threadIdx.x;
+            const bool in = threadIdx.x < 4 * nq && il < nv;
+            sthr[threadIdx.x] = in ? bern_threshold(p[v0 + il]) : 0u;
+            scost[threadIdx.x] = in ? static_cast<ACC>(cost[v0 + il]) : static_cast<ACC>(0);
+        }
+        __syncthreads();
         for (int qq = 0; qq < nq; ++qq) {
             const int q = sq + qq;
-            const int64_t ib = 4LL * q;
             uint32_t thr[4];
             ACC cc[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                if (ib + j < nv) {
-                    thr[j] = bern_threshold(p[v0 + ib + j]);
-                    cc[j] = static_cast<ACC>(cost[v0 + ib + j]);
-                } else {
-                    thr[j] = 0u;
-                    cc[j] = 0;
-                }
+                thr[j] = sthr[4 * qq + j];
+                cc[j] = scost[4 * qq + j];
             }
+            // p_i in {0, 1} for all four variables: every draw is decided without
+            // looking at the uniform (u < 0 never, u < 1 always), so the Philox call
+            // is skipped; the bits are identical to the ones it would give.
+            const bool det = ((thr[0] == 0u) | (thr[0] == (1u << 24))) &
+                             ((thr[1] == 0u) | (thr[1] == (1u << 24))) &
+                             ((thr[2] == 0u) | (thr[2] == (1u << 24))) &
+                             ((thr[3] == 0u) | (thr[3] == (1u << 24)));
 #pragma unroll
             for (int s = 0; s < WPW; ++s) {
                 const int w = wave + s * NW;
                 uint32_t r0, r1, r2, r3;
                 if (threshold_mode) {
                     r0 = r1 = r2 = r3 = 0x80000000u;   // u = 1/2: candidate = [p > 1/2]
+                } else if (det) {
+                    r0 = r1 = r2 = r3 = 0u;
                 } else {
                     r0 = 64u * static_cast<uint32_t>(w) + static_cast<uint32_t>(lane);
                     r1 = static_cast<uint32_t>(q);
@@ -316,46 +329,68 @@ void launch_eval_quad(hipStream_t s, const Tiles &qt, const int64_t *inst_var0,
 
 // ---------------------------------------------------------------------------
 // Per (instance, candidate): viol = sum of the instance's violation partials,
-// z = linear partials (+ quadratic partials).  Fixed summation order.
-// grid = (T, ceil(K/64)), block 256 = 4 slices x 64 candidates.
+// z = linear partials (+ quadratic partials).  Two stages with a fixed
+// summation order: stage 1 splits each instance's tile range into S slices
+// (grid T x K/256 x S), stage 2 adds the S slice sums.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-k_reduce_cand(int K, const int *__restrict__ efirst, const int *__restrict__ vpart,
-              const int *__restrict__ sfirst, const int64_t *__restrict__ zpart,
-              const int *__restrict__ qfirst, const int64_t *__restrict__ zqpart, int has_q,
-              int32_t *__restrict__ viol, int64_t *__restrict__ z) {
-    __shared__ int sv[4][64];
-    __shared__ int64_t sz[4][64];
-    const int inst = blockIdx.x;
-    const int l = blockIdx.y * 64 + (threadIdx.x & 63);
-    const int slice = threadIdx.x >> 6;
-    int v = 0;
-    int64_t zz = 0;
-    if (l < K) {
-        for (int t = efirst[inst] + slice; t < efirst[inst + 1]; t += 4)
-            v += vpart[static_cast<int64_t>(t) * K + l];
-        for (int t = sfirst[inst] + slice; t < sfirst[inst + 1]; t += 4)
-            zz += zpart[static_cast<int64_t>(t) * K + l];
-        if (has_q)
-            for (int t = qfirst[inst] + slice; t < qfirst[inst + 1]; t += 4)
-                zz += zqpart[static_cast<int64_t>(t) * K + l];
-    }
-    sv[slice][threadIdx.x & 63] = v;
-    sz[slice][threadIdx.x & 63] = zz;
-    __syncthreads();
-    if (slice == 0 && l < K) {
-        const int c = threadIdx.x & 63;
-        viol[static_cast<int64_t>(inst) * K + l] = sv[0][c] + sv[1][c] + sv[2][c] + sv[3][c];
-        z[static_cast<int64_t>(inst) * K + l] = sz[0][c] + sz[1][c] + sz[2][c] + sz[3][c];
-    }
+__device__ __forceinline__ void slice_range(const int *first, int inst, int sl, int S, int &a, int &b) {
+    const int t0 = first[inst], t1 = first[inst + 1];
+    const int len = (t1 - t0 + S - 1) / S;
+    a = min(t1, t0 + sl * len);
+    b = min(t1, a + len);
 }
 
-void launch_reduce_cand(hipStream_t s, int T, int K, const Tiles &et, const int *vpart,
+__global__ void __launch_bounds__(256)
+k_reduce_cand1(int K, int S, const int *__restrict__ efirst, const int *__restrict__ vpart,
+               const int *__restrict__ sfirst, const int64_t *__restrict__ zpart,
+               const int *__restrict__ qfirst, const int64_t *__restrict__ zqpart, int has_q,
+               int32_t *__restrict__ rv, int64_t *__restrict__ rz) {
+    const int inst = blockIdx.x;
+    const int l = blockIdx.y * 256 + threadIdx.x;
+    const int sl = blockIdx.z;
+    if (l >= K) return;
+    int v = 0;
+    int64_t zz = 0;
+    int a, b;
+    slice_range(efirst, inst, sl, S, a, b);
+    for (int t = a; t < b; ++t) v += vpart[static_cast<int64_t>(t) * K + l];
+    slice_range(sfirst, inst, sl, S, a, b);
+    for (int t = a; t < b; ++t) zz += zpart[static_cast<int64_t>(t) * K + l];
+    if (has_q) {
+        slice_range(qfirst, inst, sl, S, a, b);
+        for (int t = a; t < b; ++t) zz += zqpart[static_cast<int64_t>(t) * K + l];
+    }
+    const int64_t o = (static_cast<int64_t>(inst) * S + sl) * K + l;
+    rv[o] = v;
+    rz[o] = zz;
+}
+
+__global__ void __launch_bounds__(256)
+k_reduce_cand2(int K, int S, const int32_t *__restrict__ rv, const int64_t *__restrict__ rz,
+               int32_t *__restrict__ viol, int64_t *__restrict__ z) {
+    const int inst = blockIdx.x;
+    const int l = blockIdx.y * 256 + threadIdx.x;
+    if (l >= K) return;
+    int v = 0;
+    int64_t zz = 0;
+    for (int sl = 0; sl < S; ++sl) {
+        const int64_t o = (static_cast<int64_t>(inst) * S + sl) * K + l;
+        v += rv[o];
+        zz += rz[o];
+    }
+    viol[static_cast<int64_t>(inst) * K + l] = v;
+    z[static_cast<int64_t>(inst) * K + l] = zz;
+}
+
+void launch_reduce_cand(hipStream_t s, int T, int K, int S, const Tiles &et, const int *vpart,
                         const Tiles &st, const int64_t *zpart, const Tiles &qt,
-                        const int64_t *zqpart, int has_q, int32_t *viol, int64_t *z) {
-    dim3 grid(T, (K + 63) / 64);
-    k_reduce_cand<<<grid, 256, 0, s>>>(K, et.first, vpart, st.first, zpart,
-                                         has_q ? qt.first : st.first, zqpart, has_q, viol, z);
+                        const int64_t *zqpart, int has_q, int32_t *rv, int64_t *rz,
+                        int32_t *viol, int64_t *z) {
+    dim3 g1(T, (K + 255) / 256, S);
+    k_reduce_cand1<<<g1, 256, 0, s>>>(K, S, et.first, vpart, st.first, zpart,
+                                       has_q ? qt.first : st.first, zqpart, has_q, rv, rz);
+    dim3 g2(T, (K + 255) / 256);
+    k_reduce_cand2<<<g2, 256, 0, s>>>(K, S, rv, rz, viol, z);
 }
 
 // ---------------------------------------------------------------------------

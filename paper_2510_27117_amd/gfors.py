@@ -30,7 +30,7 @@ class gfors_params(ctypes.Structure):
     _fields_ = [("sigma", c_dbl), ("tau1", c_dbl), ("tau2", c_dbl),
                 ("rho_min", c_dbl), ("rho_max", c_dbl), ("rho_T", c_dbl), ("rho_p", c_dbl),
                 ("rho_delta", c_dbl), ("k_int", c_i32), ("K_max", c_i32), ("power_iters", c_i32),
-                ("hist_cap", c_i32), ("x0", c_dbl), ("seed", c_u64)]
+                ("hist_cap", c_i32), ("autotune", c_i32), ("x0", c_dbl), ("seed", c_u64)]
 
 
 EXPORTS = [
@@ -39,6 +39,7 @@ EXPORTS = [
     "gfors_final_round", "gfors_run_rounds", "gfors_best", "gfors_get_residuals",
     "gfors_get_history", "gfors_get_state", "gfors_set_state", "gfors_get_candidates",
     "gfors_get_scales", "gfors_get_dims", "gfors_kernel_times", "gfors_reset",
+    "gfors_get_launch_cfg", "gfors_set_launch_cfg",
 ]
 
 KERNEL_NAMES = ["dual", "primal", "sample", "eval_cover", "eval_general", "eval_quad",
@@ -81,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_get_dims.argtypes = [c_vp, P(c_i64), P(c_i64), P(c_i64), P(c_i32)]
     L.gfors_kernel_times.argtypes = [c_vp, c_i32, c_i32, c_vp, c_vp]
     L.gfors_reset.argtypes = [c_vp]
+    L.gfors_get_launch_cfg.argtypes = [c_vp, c_vp]
+    L.gfors_set_launch_cfg.argtypes = [c_vp, c_vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("gfors_default_params", "gfors_destroy_problem", "gfors_last_error"):
@@ -276,6 +279,19 @@ class Problem:
         cnt = np.zeros(len(KERNEL_NAMES), dtype=np.int32)
         _check(load_library().gfors_kernel_times(self._h(), int(nsteps), int(K), _ptr(ms), _ptr(cnt)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+    def launch_cfg(self) -> dict:
+        out = np.zeros(6, dtype=np.int32)
+        _check(load_library().gfors_get_launch_cfg(self._h(), _ptr(out)))
+        return {"lpr_dual": int(out[0]), "lpr_primal": int(out[1]),
+                "slices_dual": int(out[2]), "slices_primal": int(out[3]),
+                "sell_dual": int(out[4]), "sell_primal": int(out[5])}
+
+    def set_launch_cfg(self, lpr_dual, lpr_primal, slices_dual=1, slices_primal=1,
+                       sell_dual=0, sell_primal=0):
+        cfg = np.array([lpr_dual, lpr_primal, slices_dual, slices_primal, sell_dual, sell_primal],
+                       dtype=np.int32)
+        _check(load_library().gfors_set_launch_cfg(self._h(), _ptr(cfg)))
 
     def reset(self):
         """Restart from x0 with a cleared incumbent (Preprocess kept)."""

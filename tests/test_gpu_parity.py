@@ -206,8 +206,10 @@ def test_residuals_match_oracle(G, name):
 
 def test_graph_rounds_match_eager(G):
     P = I.set_cover_bernoulli(1037, 301, 0.02, seed=1)
-    a = G.Problem(P, _params(G, k_int=7))
-    b = G.Problem(P, _params(G, k_int=7))
+    # same launch shapes on both (the autotuner may pick differently per problem,
+    # which changes the FP32 summation order)
+    a = G.Problem(P, _params(G, k_int=7, autotune=0))
+    b = G.Problem(P, _params(G, k_int=7, autotune=0))
     a.run_rounds(5, 512, use_graph=False)
     b.run_rounds(5, 512, use_graph=True)
     sa, sb = a.get_state(), b.get_state()
@@ -294,3 +296,79 @@ def test_error_paths(G):
     rc = L.gfors_create_problem(None, None, None, None, None, c.ctypes.data_as(ctypes.c_void_p), 2, 1, None,
                                 ctypes.byref(prm), ctypes.c_void_p(ws.data_ptr()), 1024, None, ctypes.byref(h))
     assert rc == -3 and b"workspace too small" in L.gfors_last_error()
+
+
+@pytest.mark.parametrize("which", ["dual", "primal"])
+def test_every_launch_shape_matches_oracle(G, which):
+    """Every lanes-per-row choice and both the fused and the XCD-sliced SpMV
+    give a teacher-forced step within tolerance (instances large enough that
+    the sliced copies exist)."""
+    if which == "dual":
+        P = I.set_cover_columns(600_000, 60_000, 5, seed=3)        # rows ~50 nnz, n >= 2^19
+    else:
+        P = I.set_cover_columns(50_000, 600_000, 24, seed=4)       # columns ~24 nnz, m >= 2^19
+    prm = O.Params(k_int=20, power_iters=200)
+    S, traj = oracle_trajectory(P, prm, steps=41, keep_every=40)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+    shapes = []
+    for lpr in [1, 2, 4, 8, 16, 32, 64]:
+        for sl in [1, 8]:
+            if sl == 8 and lpr > 16:
+                continue
+            shapes.append((lpr, sl, 0))
+    shapes += [(1, 1, 1), (1, 8, 1)]
+    tested_sliced = tested_sell = False
+    for lpr, sl, se in shapes:
+        try:
+            if which == "dual":
+                prob.set_launch_cfg(lpr, 4, sl, 1, se, 0)
+            else:
+                prob.set_launch_cfg(16, lpr, 1, sl, 0, se)
+        except G.GforsError:
+            assert sl == 8 or se == 1
+            continue
+        tested_sliced |= sl == 8
+        tested_sell |= se == 1
+        prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+        prob.pdhg_steps(1)
+        got = prob.get_state()
+        assert rel_inf(got["x"], ref.x) <= TOL_PDHG and rel_inf(got["y"], ref.y) <= TOL_PDHG, (lpr, sl, se)
+    assert tested_sliced and tested_sell
+    prob.close()
+
+
+def test_sell_layouts_on_small_instances(G):
+    """SELL-64 (sorted windows, padded chunks, ragged last chunk) on instances
+    with empty rows, uneven row lengths and integer coefficients."""
+    for P in [mixed_problem(150, seed=9), I.knapsack_multi(333, 4, seed=1),
+              I.set_cover_bernoulli(1037, 301, 0.02, seed=1), I.facility_location(5, 19, seed=2)]:
+        S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=25, keep_every=24)
+        st, rho = traj[-1]
+        s32 = f32_state(st)
+        ref = O.pdhg_step(S, s32, rho)
+        prob = G.Problem(P, _params(G, autotune=0))
+        cfgs = [(16, 4, 1, 1, 1, 0)]
+        if P.Q is None:
+            cfgs += [(16, 4, 1, 1, 0, 1), (16, 4, 1, 1, 1, 1)]
+        for cfg in cfgs:
+            try:
+                prob.set_launch_cfg(*cfg)
+            except G.GforsError:
+                continue
+            prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+            prob.pdhg_steps(1)
+            got = prob.get_state()
+            assert rel_inf(got["x"], ref.x) <= TOL_PDHG and rel_inf(got["y"], ref.y) <= TOL_PDHG, (P.name, cfg)
+        prob.close()
+
+
+def test_autotuned_shape_is_valid(G):
+    P = I.set_cover_columns(600_000, 60_000, 5, seed=3)
+    prob = G.Problem(P, _params(G, autotune=1))
+    cfg = prob.launch_cfg()
+    assert cfg["slices_dual"] in (1, 8) and cfg["lpr_dual"] in (1, 2, 4, 8, 16, 32, 64)
+    prob.set_launch_cfg(cfg["lpr_dual"], cfg["lpr_primal"], cfg["slices_dual"], cfg["slices_primal"])
+    prob.close()
