@@ -199,18 +199,79 @@ int gfors_get_scales(gfors_problem *P, double *row_scale, double *obj_scale, dou
 int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_ms,
                        int32_t *launches);
 
-/* Launch shapes in use: out[6] = {lanes per row of the dual SpMV, lanes per row
+/* Launch shapes in use: out[8] = {lanes per row of the dual SpMV, lanes per row
  * of the primal SpMV, column slices of the dual SpMV, slices of the primal,
- * SELL-64 layout for the dual (0/1), SELL-64 layout for the primal (0/1)}
+ * SELL-64 layout for the dual (0/1), SELL-64 layout for the primal (0/1),
+ * zero-operand bitmap skipping in the dual (0/1), in the primal (0/1)}
  * (1 slice = fused kernel; with SELL the lanes-per-row entry is unused). */
 int gfors_get_launch_cfg(gfors_problem *P, int32_t *out);
 
-/* Force launch shapes (same 6-entry layout as gfors_get_launch_cfg).  Lanes per
+/* Re-run the autotuner on the current iterate (the zero-operand bitmap
+ * variants only show their speed once x and y have reached the box bounds /
+ * inactive duals).  The timed launches write no state.  Synchronises; drops
+ * captured graphs. */
+int gfors_autotune(gfors_problem *P);
+
+/* Force launch shapes (same 8-entry layout as gfors_get_launch_cfg).  Lanes per
  * row: a power of two in [1, 64]; slices: 1, or 8 when the problem holds the
  * column-sliced copy (then lanes <= 16; the primal also needs Q = 0); SELL only
- * where the problem holds the SELL copy.  E_ARG otherwise.  Drops captured
+ * where the problem holds the SELL copy; bitmap skipping only for the sliced SELL
+ * dual / the fused CSR primal without Q, with bitmaps of at most 64 KB.  E_ARG
+ * otherwise.  Drops captured
  * graphs. */
 int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg);
+
+/* ---------------------------------------------------------------------------
+ * Learned sampling proposal.  The paper allows any GPU-compatible routine as
+ * RandSampleStep (customized sampling, Sec. 2.4.2); this one draws the same
+ * Philox Bernoulli candidates (pass its p as p_override to gfors_sample_eval)
+ * from probabilities p = sigmoid(logit) of a bipartite message-passing network
+ * over the constraint graph (hidden 64, 3 rounds, BF16 MFMA with FP32
+ * accumulation), trained on the GPU against incumbents the method found:
+ *   E     = diag(1/||a_j||) [A; B]   (a zero row has no edges)
+ *   Fv_i  = [x_i, 4 x_i (1 - x_i), c~_i / max|c~|, 1]
+ *   Fc_j  = [y_j / (1 + |y_j|), r~_j / max|r~|, [row j is an equality], 1]
+ *   Hv = relu(Fv Uv + uv),  Hc = relu(Fc Uc + uc)
+ *   3 times: Hc = relu([Hc | E Hv] [Wcc; Wcv] + bc); Hv = relu([Hv | E^T Hc] [Wvv; Wvc] + bv)
+ *   logit = Hv wo + bo;  loss = mean_i softplus(logit_i) - t_i logit_i
+ * Parameters: one flat float vector of GFORS_GNN_NUM_PARAMS entries in the order
+ * Uv[4][64], uv[64], Uc[4][64], uc[64], 3 x {Wcc, Wcv [64][64], bc[64],
+ * Wvv, Wvc [64][64], bv[64]} (W[in][out]), wo[64], bo.  All calls below run on
+ * the problem's stream (gfors_gnn_create's stream for create/get/set/adam);
+ * single-instance problems only (E_ARG otherwise). */
+#define GFORS_GNN_NUM_PARAMS 50241
+typedef struct gfors_gnn gfors_gnn;
+
+/* Device workspace of a network (parameters, gradient, Adam moments, BF16
+ * operand copies, reduction scratch). */
+int gfors_gnn_workspace_bytes(size_t *bytes);
+/* Create a network from host parameters (FP32 master copy on the device). */
+int gfors_gnn_create(const float *params_host, void *ws, size_t ws_bytes, void *stream,
+                     gfors_gnn **out);
+void gfors_gnn_destroy(gfors_gnn *G);
+/* Activation workspace for running the network on problem P (training = 1
+ * keeps every round's activations and gradients). */
+int gfors_gnn_act_bytes(gfors_problem *P, int32_t training, size_t *bytes);
+/* Forward pass on P with iterate x_dev (float[n]) and duals y_dev (float[m]);
+ * NULL takes P's current x_k / y_k.  p_dev (float[n]) receives sigmoid(logit),
+ * logit_dev (float[n] or NULL) the logits.  Async. */
+int gfors_gnn_forward(gfors_gnn *G, gfors_problem *P, const float *x_dev, const float *y_dev,
+                      void *act, size_t act_bytes, float *p_dev, float *logit_dev);
+/* Loss and gradient against target_dev (float[n] of 0/1); the gradient stays on
+ * the device (gfors_gnn_get_grad).  loss_host (or NULL): synchronises. */
+int gfors_gnn_grad(gfors_gnn *G, gfors_problem *P, const float *x_dev, const float *y_dev,
+                   const float *target_dev, void *act, size_t act_bytes, float *loss_host);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with the current gradient. Async. */
+int gfors_gnn_adam(gfors_gnn *G, float lr);
+/* gfors_gnn_grad followed by gfors_gnn_adam. */
+int gfors_gnn_train_step(gfors_gnn *G, gfors_problem *P, const float *x_dev, const float *y_dev,
+                         const float *target_dev, void *act, size_t act_bytes, float lr,
+                         float *loss_host);
+/* Host copies of the parameters / gradient (synchronise). */
+int gfors_gnn_get_params(gfors_gnn *G, float *host);
+int gfors_gnn_set_params(gfors_gnn *G, const float *host);
+int gfors_gnn_get_grad(gfors_gnn *G, float *host);
+int gfors_gnn_set_grad(gfors_gnn *G, const float *host);
 
 /* Dimensions: n, m1, m2, number of instances. */
 int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32_t *T);

@@ -3,6 +3,7 @@
 // power iterations on the device, the Algorithm 1 loop pieces and HIP-graph
 // replay of whole rounds, and the C ABI declared in include/gfors.h.
 #include "gfors_internal.h"
+#include "gnn.h"
 #include "../../include/gfors.h"
 
 #include <algorithm>
@@ -133,6 +134,10 @@ struct gfors_problem {
     SellView sellK, sellKS, sellT;
     int64_t sellK_cap = 0, sellKS_cap = 0, sellT_cap = 0;
     int *sellK_buf[4] = {}, *sellKS_buf[4] = {}, *sellT_buf[4] = {};
+    float *rowinv32 = nullptr;          // 1/||a_j|| (0 for a zero row): the GNN's edge weights
+    float gnn_ictmax = 1.f, gnn_irtmax = 1.f;
+    uint64_t *bx = nullptr, *by = nullptr;   // nonzero bitmaps of xbar and wy
+    int64_t bx_words = 0, by_words = 0;
     int red_S = 1;                  // tile slices of the candidate reduction
     int32_t *red_v = nullptr;
     int64_t *red_z = nullptr;
@@ -363,6 +368,11 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     sell_carve(P->sellK_want, m, 1, nnzK, P->sellK_cap, P->sellK_buf);
     sell_carve(P->sellKS_want, m, kXcdSlices, nnzK, P->sellKS_cap, P->sellKS_buf);
     sell_carve(P->sellT_want, n, 1, nnzK, P->sellT_cap, P->sellT_buf);
+    P->rowinv32 = cv.take<float>(m);
+    P->bx_words = ceil_div(n + 64 * kXcdSlices, 64) + 1;
+    P->by_words = ceil_div(m + 64, 64) + 1;
+    P->bx = cv.take<uint64_t>(P->bx_words);
+    P->by = cv.take<uint64_t>(P->by_words);
     if (P->slicedK || P->slicedT)
         P->spart = cv.take<float>(static_cast<int64_t>(kXcdSlices) * std::max(P->slicedK ? m : 0, P->slicedT ? n : 0));
     DevInst &d = P->di;
@@ -698,7 +708,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
                           const std::vector<int> &cix, const std::vector<int> &valx, int pad_col,
                           int64_t cap, int *(&buf)[4], SellView &sv) -> int {
         const int64_t nch = ceil_div(rows, 64);
-        const int64_t ns = ceil_div(std::max<int64_t>(cols, 1), Pn);
+        const int64_t ns = ceil_div(ceil_div(std::max<int64_t>(cols, 1), Pn), 64) * 64;
         std::vector<int> sptr(static_cast<size_t>(Pn) * (nch + 1)), srow(static_cast<size_t>(Pn) * nch * 64, -1);
         std::vector<int> sci, sval;
         sci.reserve(static_cast<size_t>(cix.size() * 1.2) + 64);
@@ -749,6 +759,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         sv.nrows = static_cast<int>(rows);
         sv.P = Pn;
         sv.nchunk = static_cast<int>(nch);
+        sv.ns = static_cast<int>(ns);
         sv.ptr = buf[0];
         sv.ci = buf[1];
         sv.val = buf[2];
@@ -835,6 +846,19 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         const double rr = static_cast<double>(rhs[j]) * P->rowinv[j];
         rtv[j] = static_cast<float>(sk > 0 ? rr / sk : rr);
     }
+    {
+        std::vector<float> ri(m);
+        double rtm = 0.0, ctm = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+            ri[j] = rp[j + 1] > rp[j] ? static_cast<float>(P->rowinv[j]) : 0.f;
+            rtm = std::max(rtm, std::fabs(static_cast<double>(rtv[j])));
+        }
+        for (int64_t i = 0; i < n; ++i) ctm = std::max(ctm, std::fabs(static_cast<double>(ctv[i])));
+        P->gnn_ictmax = ctm > 0 ? static_cast<float>(1.0 / ctm) : 1.f;
+        P->gnn_irtmax = rtm > 0 ? static_cast<float>(1.0 / rtm) : 1.f;
+        if ((rc = upload(s, P->rowinv32, ri.data(), m))) return rc;
+        if ((rc = sync(P))) return rc;
+    }
     if ((rc = upload(s, P->omega, omega.data(), m))) return rc;
     if ((rc = upload(s, P->rt, rtv.data(), m))) return rc;
     if ((rc = upload(s, P->omega64, om64.data(), m))) return rc;
@@ -877,6 +901,8 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     launch_fill_f32(s, P->ybuf[1], 0.f, m);
     launch_fill_f32(s, P->wy, 0.f, m + 1);
     launch_fill_f32(s, P->xbar + n, 0.f, 1);
+    launch_fill_f32(s, reinterpret_cast<float *>(P->bx), 0.f, 2 * P->bx_words);
+    launch_fill_f32(s, reinterpret_cast<float *>(P->by), 0.f, 2 * P->by_words);
     HIP_TRY(hipGetLastError());
     // launch shapes: lanes per row ~ average row length (rounded to a power of two)
     auto pick = [](double avg) {
@@ -949,7 +975,14 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
     hipStream_t s = P->stream;
     const bool batched = P->T > 1;
     const float tau2 = static_cast<float>(P->tau2[0]);
-    if (sell && slices > 1) {
+    if (sell && slices > 1 && P->cfg.bits_dual) {
+        launch_nzbits(s, P->xbar, P->n, ceil_div(P->n, 64), P->bx);
+        launch_sell_part_bits(s, P->sellKS, P->sellKS.ns, static_cast<int>(P->n), P->unitK, P->xbar,
+                              reinterpret_cast<const uint32_t *>(P->bx), P->spart);
+        launch_dual_combine(s, batched, static_cast<int>(P->m), static_cast<int>(P->m1), slices,
+                            P->spart, P->omega, P->rt, y_in, y_out, P->wy, tau2, P->di.tau2,
+                            P->row_inst);
+    } else if (sell && slices > 1) {
         launch_sell(s, P->sellKS, 0, P->unitK, batched, P->xbar, P->spart, 0, nullptr, nullptr,
                     nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, nullptr, nullptr, nullptr,
                     nullptr, 0.f, nullptr, nullptr, nullptr, nullptr);
@@ -978,7 +1011,13 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
     hipStream_t s = P->stream;
     const bool batched = P->T > 1;
     const int kmode = P->m == 0 ? 0 : (P->unitK ? 1 : 2);
-    if (sell) {
+    if (P->cfg.bits_primal && !sell && slices == 1 && kmode != 0 && !P->hasQ) {
+        launch_nzbits(s, P->wy, P->m, ceil_div(P->m, 64), P->by);
+        launch_primal_bits(s, lpr, P->unitK, batched, static_cast<int>(P->n), static_cast<int>(P->m),
+                           P->rpT, P->ciT, P->valT, P->wy, reinterpret_cast<const uint32_t *>(P->by),
+                           x_in, x_out, xbar, P->ct, static_cast<float>(P->tau1[0]), P->di.tau1,
+                           P->di.rho, P->var_inst, ctr);
+    } else if (sell) {
         launch_sell(s, P->sellT, 2, P->unitK, batched, P->wy, nullptr, 0, nullptr, nullptr, nullptr,
                     nullptr, nullptr, 0.f, nullptr, nullptr, x_in, x_out, xbar, P->ct,
                     static_cast<float>(P->tau1[0]), P->di.tau1, P->di.rho, P->var_inst, ctr);
@@ -995,6 +1034,13 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
                       static_cast<float>(P->s_o[0] > 0 ? 2.0 / P->s_o[0] : 2.0), P->di.tau1,
                       P->di.two_so, P->di.rho, P->var_inst, ctr);
     }
+}
+
+static int bits_ok_dual(gfors_problem *P, int slices, int sell) {
+    return (sell && slices > 1 && P->sellKS.ptr && P->sellKS.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
+}
+static int bits_ok_primal(gfors_problem *P, int slices, int sell) {
+    return (!sell && slices == 1 && P->m > 0 && !P->hasQ && (P->m + 31) / 32 * 4 <= kMaxLdsBitmapBytes) ? 1 : 0;
 }
 
 // Autotuner: time every candidate launch shape of the dual and primal SpMV on
@@ -1016,6 +1062,7 @@ static int autotune(gfors_problem *P) {
         return ms / 5.f;
     };
     const int lprs[] = {1, 2, 4, 8, 16, 32, 64};
+    P->cfg.bits_dual = P->cfg.bits_primal = 0;
     if (P->m > 0) {
         float best = 1e30f;
         auto consider = [&](int l, int sl, int se) {
@@ -1031,6 +1078,12 @@ static int autotune(gfors_problem *P) {
         }
         if (P->sellK.ptr) consider(1, 1, 1);
         if (P->sellKS.ptr) consider(1, kXcdSlices, 1);
+        if (bits_ok_dual(P, kXcdSlices, 1)) {
+            P->cfg.bits_dual = 1;
+            const float t = timeit([&] { launch_dual_cfg(P, 1, kXcdSlices, 1, P->ybuf[P->cur], P->ybuf[1 - P->cur]); });
+            if (t < best) { best = t; P->cfg.lpr_dual = 1; P->cfg.slices_dual = kXcdSlices; P->cfg.sell_dual = 1; }
+            else P->cfg.bits_dual = 0;
+        }
     }
     {
         float best = 1e30f;
@@ -1047,6 +1100,16 @@ static int autotune(gfors_problem *P) {
             }
         }
         if (P->sellT.ptr) consider(1, 1, 1);
+        if (bits_ok_primal(P, 1, 0)) {
+            P->cfg.bits_primal = 1;
+            int bl = -1;
+            for (int l : {1, 2, 4, 8, 16}) {
+                const float t = timeit([&] { launch_primal_cfg(P, l, 1, 0, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
+                if (t < best) { best = t; bl = l; }
+            }
+            if (bl > 0) { P->cfg.lpr_primal = bl; P->cfg.slices_primal = 1; P->cfg.sell_primal = 0; }
+            else P->cfg.bits_primal = 0;
+        }
     }
     HIP_TRY(hipGetLastError());
     (void)hipEventDestroy(e0);
@@ -1348,6 +1411,12 @@ int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_
     return GFORS_OK;
 }
 
+int gfors_autotune(gfors_problem *P) {
+    if (!P) return fail(GFORS_E_ARG, "NULL handle");
+    P->graphs_clear();
+    return autotune(P);
+}
+
 int gfors_get_launch_cfg(gfors_problem *P, int32_t *out) {
     if (!P || !out) return fail(GFORS_E_ARG, "bad argument");
     out[0] = P->cfg.lpr_dual;
@@ -1356,6 +1425,8 @@ int gfors_get_launch_cfg(gfors_problem *P, int32_t *out) {
     out[3] = P->cfg.slices_primal;
     out[4] = P->cfg.sell_dual;
     out[5] = P->cfg.sell_primal;
+    out[6] = P->cfg.bits_dual;
+    out[7] = P->cfg.bits_primal;
     return GFORS_OK;
 }
 
@@ -1375,9 +1446,260 @@ int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
     P->cfg.lpr_primal = cfg[1];
     P->cfg.slices_dual = cfg[2];
     P->cfg.slices_primal = cfg[3];
+    if (cfg[6] && !bits_ok_dual(P, cfg[2], cfg[4]))
+        return fail(GFORS_E_ARG, "bitmap dual needs the sliced SELL layout and a slice bitmap that fits in LDS");
+    if (cfg[7] && !bits_ok_primal(P, cfg[3], cfg[5]))
+        return fail(GFORS_E_ARG, "bitmap primal needs the fused CSR layout, Q = 0 and a dual bitmap that fits in LDS");
     P->cfg.sell_dual = cfg[4] ? 1 : 0;
     P->cfg.sell_primal = cfg[5] ? 1 : 0;
+    P->cfg.bits_dual = cfg[6] ? 1 : 0;
+    P->cfg.bits_primal = cfg[7] ? 1 : 0;
     P->graphs_clear();
+    return GFORS_OK;
+}
+
+// ===========================================================================
+// Learned sampling proposal (network defined in gnn.h)
+// ===========================================================================
+}  // extern "C"
+
+struct gfors_gnn {
+    float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+    uint16_t *wf = nullptr, *wb = nullptr;     // BF16 operand copies (see k_gnn_pack)
+    float *part = nullptr, *loss = nullptr;
+    int64_t t = 0;                             // Adam steps taken
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+struct GnnAct {
+    uint16_t *Hv[kGnnL + 1], *Hc[kGnnL + 1], *Sc[kGnnL], *Sv[kGnnL];
+    float *dHv, *dHvp, *dHc, *dHcp, *dS;
+    uint16_t *dZ;
+    float *logit, *p;
+};
+
+size_t gnn_ws_carve(gfors_gnn *G, Carver &cv) {
+    G->theta = cv.take<float>(kGnnNumParams);
+    G->grad = cv.take<float>(kGnnNumParams);
+    G->m = cv.take<float>(kGnnNumParams);
+    G->v = cv.take<float>(kGnnNumParams);
+    G->wf = cv.take<uint16_t>(kGnnL * 2 * 128 * 64);
+    G->wb = cv.take<uint16_t>(kGnnL * 2 * 128 * 64);
+    G->part = cv.take<float>(static_cast<int64_t>(kGnnMaxParts) * 128 * 64);
+    G->loss = cv.take<float>(4);
+    return cv.off;
+}
+
+// Training keeps every round's activations; inference ping-pongs two buffers.
+size_t gnn_act_carve(gfors_problem *P, bool training, GnnAct &a, Carver &cv) {
+    const int64_t n = P->n, m = P->m, H = kGnnH;
+    const int keep = training ? kGnnL + 1 : 2;
+    for (int l = 0; l <= kGnnL; ++l) {
+        a.Hv[l] = l < keep ? cv.take<uint16_t>(n * H) : a.Hv[l % 2];
+        a.Hc[l] = l < keep ? cv.take<uint16_t>(std::max<int64_t>(m, 1) * H) : a.Hc[l % 2];
+    }
+    for (int l = 0; l < kGnnL; ++l) {
+        a.Sc[l] = (training || l == 0) ? cv.take<uint16_t>(std::max<int64_t>(m, 1) * H) : a.Sc[0];
+        a.Sv[l] = (training || l == 0) ? cv.take<uint16_t>(n * H) : a.Sv[0];
+    }
+    if (training) {
+        a.dHv = cv.take<float>(n * H);
+        a.dHvp = cv.take<float>(n * H);
+        a.dHc = cv.take<float>(std::max<int64_t>(m, 1) * H);
+        a.dHcp = cv.take<float>(std::max<int64_t>(m, 1) * H);
+        a.dS = cv.take<float>(std::max(n, m) * H);
+        a.dZ = cv.take<uint16_t>(std::max(n, m) * H);
+    } else {
+        a.dHv = a.dHvp = a.dHc = a.dHcp = a.dS = nullptr;
+        a.dZ = nullptr;
+    }
+    a.logit = cv.take<float>(n);
+    a.p = cv.take<float>(n);
+    return cv.off;
+}
+
+// Forward pass; in training mode also the loss and the full backward pass
+// (gradient left in G->grad).
+int gnn_run(gfors_gnn *G, gfors_problem *P, const float *x, const float *y, const float *target,
+            void *act, size_t act_bytes, bool training, float *p_out, float *logit_out) {
+    GnnAct a;
+    Carver cv{static_cast<char *>(act), 0, act_bytes};
+    const uintptr_t al = reinterpret_cast<uintptr_t>(act);
+    cv.off = (256 - (al & 255)) & 255;
+    gnn_act_carve(P, training, a, cv);
+    if (cv.off > act_bytes) return fail(GFORS_E_OOM, "GNN activation workspace too small");
+    hipStream_t s = P->stream;
+    const int64_t n = P->n, m = P->m;
+    const float *xs = x ? x : P->xbuf[P->cur];
+    const float *ys = y ? y : P->ybuf[P->cur];
+    const int *val = P->unitK ? nullptr : P->val;
+    const int *valT = P->unitK ? nullptr : P->valT;
+    launch_gnn_embed(s, n, m, static_cast<int>(P->m1), xs, ys, P->ct, P->rt, P->gnn_ictmax,
+                     P->gnn_irtmax, G->theta, a.Hv[0], a.Hc[0]);
+    for (int l = 0; l < kGnnL; ++l) {
+        const float *lay = G->theta + kGnnOffLayer + l * kGnnLayerSize;
+        const uint16_t *wfc = G->wf + static_cast<int64_t>(2 * l) * 128 * 64;
+        const uint16_t *wfv = G->wf + static_cast<int64_t>(2 * l + 1) * 128 * 64;
+        // constraint side: Hc = relu([Hc | E Hv] W + bc)
+        launch_gnn_spmm(s, true, true, 0, m, P->rp, P->ci, val, P->rowinv32, a.Hv[l], a.Sc[l]);
+        launch_gnn_dense_fwd(s, m, a.Hc[l], a.Sc[l], wfc, lay + 2 * 4096, a.Hc[l + 1]);
+        // variable side: Hv = relu([Hv | E^T Hc] W + bv)
+        launch_gnn_spmm(s, false, true, 0, n, P->rpT, P->ciT, valT, P->rowinv32, a.Hc[l + 1], a.Sv[l]);
+        launch_gnn_dense_fwd(s, n, a.Hv[l], a.Sv[l], wfv, lay + 8256 + 2 * 4096, a.Hv[l + 1]);
+    }
+    launch_gnn_out(s, n, a.Hv[kGnnL], G->theta, logit_out ? logit_out : a.logit, p_out ? p_out : a.p,
+                   training ? target : nullptr, a.dHv, G->part, kGnnMaxParts, G->grad, G->loss);
+    if (!training) {
+        HIP_TRY(hipGetLastError());
+        return GFORS_OK;
+    }
+    launch_fill_f32(s, a.dHc, 0.f, std::max<int64_t>(m, 1) * kGnnH);
+    for (int l = kGnnL - 1; l >= 0; --l) {
+        float *glay = G->grad + kGnnOffLayer + l * kGnnLayerSize;
+        const uint16_t *wbc = G->wb + static_cast<int64_t>(2 * l) * 128 * 64;
+        const uint16_t *wbv = G->wb + static_cast<int64_t>(2 * l + 1) * 128 * 64;
+        // variable side of round l
+        launch_gnn_mask(s, n, a.dHv, a.Hv[l + 1], a.dZ, G->part, kGnnMaxParts, glay + 8256 + 2 * 4096);
+        launch_gnn_wgrad(s, n, a.Hv[l], a.Sv[l], a.dZ, G->part, kGnnMaxParts, glay + 8256, glay + 8256 + 4096);
+        launch_gnn_dense_bwd_in(s, n, a.dZ, wbv, a.dHvp, a.dS, 0);
+        launch_gnn_spmm(s, true, false, 2, m, P->rp, P->ci, val, P->rowinv32, a.dS, a.dHc);
+        // constraint side of round l
+        launch_gnn_mask(s, m, a.dHc, a.Hc[l + 1], a.dZ, G->part, kGnnMaxParts, glay + 2 * 4096);
+        launch_gnn_wgrad(s, m, a.Hc[l], a.Sc[l], a.dZ, G->part, kGnnMaxParts, glay, glay + 4096);
+        launch_gnn_dense_bwd_in(s, m, a.dZ, wbc, a.dHcp, a.dS, 0);
+        launch_gnn_spmm(s, false, false, 2, n, P->rpT, P->ciT, valT, P->rowinv32, a.dS, a.dHvp);
+        std::swap(a.dHv, a.dHvp);
+        std::swap(a.dHc, a.dHcp);
+    }
+    launch_gnn_embed_bwd(s, n, 1, static_cast<int>(P->m1), xs, P->ct, P->gnn_ictmax, a.Hv[0], a.dHv,
+                         G->part, kGnnMaxParts, G->grad + kGnnOffUv, G->grad + kGnnOffuv);
+    launch_gnn_embed_bwd(s, m, 0, static_cast<int>(P->m1), ys, P->rt, P->gnn_irtmax, a.Hc[0], a.dHc,
+                         G->part, kGnnMaxParts, G->grad + kGnnOffUc, G->grad + kGnnOffuc);
+    HIP_TRY(hipGetLastError());
+    return GFORS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gfors_gnn_workspace_bytes(size_t *bytes) {
+    if (!bytes) return fail(GFORS_E_ARG, "NULL argument");
+    gfors_gnn tmp;
+    Carver cv{nullptr, 0, 0};
+    *bytes = gnn_ws_carve(&tmp, cv) + 256;
+    return GFORS_OK;
+}
+
+int gfors_gnn_create(const float *params_host, void *ws, size_t ws_bytes, void *stream,
+                     gfors_gnn **out) {
+    if (!params_host || !ws || !out) return fail(GFORS_E_ARG, "NULL argument");
+    auto *G = new gfors_gnn();
+    G->stream = static_cast<hipStream_t>(stream);
+    Carver cv{static_cast<char *>(ws), 0, ws_bytes};
+    cv.off = (256 - (reinterpret_cast<uintptr_t>(ws) & 255)) & 255;
+    if (gnn_ws_carve(G, cv) > ws_bytes) {
+        delete G;
+        return fail(GFORS_E_OOM, "GNN workspace too small");
+    }
+    hipStream_t s = G->stream;
+    std::vector<float> zero(kGnnNumParams, 0.f);
+    int rc;
+    if ((rc = upload(s, G->theta, params_host, kGnnNumParams)) ||
+        (rc = upload(s, G->m, zero.data(), kGnnNumParams)) ||
+        (rc = upload(s, G->v, zero.data(), kGnnNumParams)) ||
+        (rc = upload(s, G->grad, zero.data(), kGnnNumParams))) {
+        delete G;
+        return rc;
+    }
+    launch_gnn_pack(s, G->theta, G->wf, G->wb);
+    if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
+        delete G;
+        return fail(GFORS_E_HIP, "GNN creation failed");
+    }
+    *out = G;
+    return GFORS_OK;
+}
+
+void gfors_gnn_destroy(gfors_gnn *G) { delete G; }
+
+int gfors_gnn_act_bytes(gfors_problem *P, int32_t training, size_t *bytes) {
+    if (!P || !bytes) return fail(GFORS_E_ARG, "NULL argument");
+    if (P->T != 1) return fail(GFORS_E_ARG, "the learned proposal runs on single-instance problems");
+    GnnAct a;
+    Carver cv{nullptr, 0, 0};
+    *bytes = gnn_act_carve(P, training != 0, a, cv) + 256;
+    return GFORS_OK;
+}
+
+int gfors_gnn_forward(gfors_gnn *G, gfors_problem *P, const float *x_dev, const float *y_dev,
+                      void *act, size_t act_bytes, float *p_dev, float *logit_dev) {
+    if (!G || !P || !act || !p_dev) return fail(GFORS_E_ARG, "NULL argument");
+    if (P->T != 1) return fail(GFORS_E_ARG, "the learned proposal runs on single-instance problems");
+    return gnn_run(G, P, x_dev, y_dev, nullptr, act, act_bytes, false, p_dev, logit_dev);
+}
+
+int gfors_gnn_grad(gfors_gnn *G, gfors_problem *P, const float *x_dev, const float *y_dev,
+                   const float *target_dev, void *act, size_t act_bytes, float *loss_host) {
+    if (!G || !P || !act || !target_dev) return fail(GFORS_E_ARG, "NULL argument");
+    if (P->T != 1) return fail(GFORS_E_ARG, "the learned proposal runs on single-instance problems");
+    int rc = gnn_run(G, P, x_dev, y_dev, target_dev, act, act_bytes, true, nullptr, nullptr);
+    if (rc) return rc;
+    if (loss_host) {
+        HIP_TRY(hipMemcpyAsync(loss_host, G->loss, sizeof(float), hipMemcpyDeviceToHost, P->stream));
+        return sync(P);
+    }
+    return GFORS_OK;
+}
+
+int gfors_gnn_adam(gfors_gnn *G, float lr) {
+    if (!G || !(lr > 0.f)) return fail(GFORS_E_ARG, "bad argument");
+    G->t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = static_cast<float>(1.0 - std::pow(b1, static_cast<double>(G->t)));
+    const float c2 = static_cast<float>(1.0 - std::pow(b2, static_cast<double>(G->t)));
+    launch_gnn_adam(G->stream, kGnnNumParams, G->theta, G->grad, G->m, G->v, lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+    launch_gnn_pack(G->stream, G->theta, G->wf, G->wb);
+    HIP_TRY(hipGetLastError());
+    return GFORS_OK;
+}
+
+int gfors_gnn_train_step(gfors_gnn *G, gfors_problem *P, const float *x_dev, const float *y_dev,
+                         const float *target_dev, void *act, size_t act_bytes, float lr,
+                         float *loss_host) {
+    int rc = gfors_gnn_grad(G, P, x_dev, y_dev, target_dev, act, act_bytes, loss_host);
+    if (rc) return rc;
+    return gfors_gnn_adam(G, lr);
+}
+
+int gfors_gnn_get_params(gfors_gnn *G, float *host) {
+    if (!G || !host) return fail(GFORS_E_ARG, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(host, G->theta, kGnnNumParams * sizeof(float), hipMemcpyDeviceToHost, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    return GFORS_OK;
+}
+
+int gfors_gnn_set_params(gfors_gnn *G, const float *host) {
+    if (!G || !host) return fail(GFORS_E_ARG, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(G->theta, host, kGnnNumParams * sizeof(float), hipMemcpyHostToDevice, G->stream));
+    launch_gnn_pack(G->stream, G->theta, G->wf, G->wb);
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    return GFORS_OK;
+}
+
+int gfors_gnn_get_grad(gfors_gnn *G, float *host) {
+    if (!G || !host) return fail(GFORS_E_ARG, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(host, G->grad, kGnnNumParams * sizeof(float), hipMemcpyDeviceToHost, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    return GFORS_OK;
+}
+
+int gfors_gnn_set_grad(gfors_gnn *G, const float *host) {
+    if (!G || !host) return fail(GFORS_E_ARG, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(G->grad, host, kGnnNumParams * sizeof(float), hipMemcpyHostToDevice, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
     return GFORS_OK;
 }
 

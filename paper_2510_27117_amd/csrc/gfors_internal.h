@@ -63,11 +63,15 @@ struct LaunchCfg {
     int slices_primal = 1;
     int sell_dual = 0;     // 1: SELL-64 layout (lane = row) instead of CSR
     int sell_primal = 0;
+    int bits_dual = 0;     // 1: skip zero operands through an LDS bitmap
+    int bits_primal = 0;
 };
+
+constexpr int64_t kMaxLdsBitmapBytes = 64 * 1024;
 
 // A SELL-64 matrix (possibly cut into P column slices, each with nchunk chunks).
 struct SellView {
-    int nrows = 0, P = 1, nchunk = 0;
+    int nrows = 0, P = 1, nchunk = 0, ns = 0;   // ns: columns per slice (multiple of 64)
     const int *ptr = nullptr, *ci = nullptr, *val = nullptr, *row_of = nullptr;
 };
 
@@ -102,6 +106,15 @@ void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool ba
                  const int *row_inst, const float *x_in, float *x_out, float *xbar,
                  const float *ct, float tau1, const float *tau1_inst, const double *rho,
                  const int *var_inst, DevCounters *ctr);
+
+void launch_nzbits(hipStream_t s, const float *v, int64_t n, int64_t nwords64, uint64_t *bits);
+void launch_sell_part_bits(hipStream_t s, const SellView &sv, int ns, int ncols, bool unit,
+                           const float *v, const uint32_t *bits, float *part);
+void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, int m,
+                        const int *rpT, const int *ciT, const int *valT, const float *wy,
+                        const uint32_t *bits, const float *x_in, float *x_out, float *xbar,
+                        const float *ct, float tau1, const float *tau1_inst, const double *rho,
+                        const int *var_inst, DevCounters *ctr);
 
 void launch_copy_f32(hipStream_t s, float *dst, const float *src, int64_t n);
 void launch_set_xbar(hipStream_t s, int64_t n, const float *x, const float *xp, float *xbar);

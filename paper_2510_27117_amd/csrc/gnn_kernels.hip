@@ -1,0 +1,483 @@
+// Learned sampling proposal: a bipartite message-passing network over the
+// constraint graph (variables <-> rows), trained and run on the GPU.  Dense
+// 64-wide layers run on MFMA (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32
+// accumulation); messages are sparse-times-dense products, one wavefront per
+// node with lane = feature (each neighbour's 64 BF16 features are one 128-byte
+// line).  Network, features and loss are defined in gnn.h.
+#include "gnn.h"
+
+namespace gfors {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+    return static_cast<uint16_t>(r >> 16);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------ features
+// Hv0 = relu(Fv Uv + uv), Fv_i = [x_i, 4 x_i (1 - x_i), ct_i / ctmax, 1]
+// Hc0 = relu(Fc Uc + uc), Fc_j = [y_j / (1 + |y_j|), rt_j / rtmax, [j >= m1], 1]
+// One wavefront per node, lane = hidden unit.
+__global__ void __launch_bounds__(256)
+k_gnn_embed(int64_t n, int64_t m, int m1, const float *__restrict__ x, const float *__restrict__ y,
+            const float *__restrict__ ct, const float *__restrict__ rt, float ictmax, float irtmax,
+            const float *__restrict__ theta, uint16_t *__restrict__ Hv, uint16_t *__restrict__ Hc) {
+    const int lane = threadIdx.x & 63;
+    const float *Uv = theta + kGnnOffUv, *uv = theta + kGnnOffuv;
+    const float *Uc = theta + kGnnOffUc, *uc = theta + kGnnOffuc;
+    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t node = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+         node < n + m; node += nw) {
+        if (node < n) {
+            const float xi = x[node];
+            const float f0 = xi, f1 = 4.f * xi * (1.f - xi), f2 = ct[node] * ictmax;
+            float z = uv[lane] + Uv[3 * kGnnH + lane];
+            z = fmaf(f0, Uv[lane], z);
+            z = fmaf(f1, Uv[kGnnH + lane], z);
+            z = fmaf(f2, Uv[2 * kGnnH + lane], z);
+            Hv[node * kGnnH + lane] = f2bf(fmaxf(z, 0.f));
+        } else {
+            const int64_t j = node - n;
+            const float yj = y[j];
+            const float f0 = yj / (1.f + fabsf(yj)), f1 = rt[j] * irtmax, f2 = j >= m1 ? 1.f : 0.f;
+            float z = uc[lane] + Uc[3 * kGnnH + lane];
+            z = fmaf(f0, Uc[lane], z);
+            z = fmaf(f1, Uc[kGnnH + lane], z);
+            z = fmaf(f2, Uc[2 * kGnnH + lane], z);
+            Hc[j * kGnnH + lane] = f2bf(fmaxf(z, 0.f));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ SpMM
+// out_r = sum_e E_e in[col_e] with E_e = val_e * rowinv[row of the entry]:
+//   ROWS = true : CSR of [A; B]  (r = constraint row, col = variable, rowinv[r])
+//   ROWS = false: CSR of [A; B]^T (r = variable, col = row j,        rowinv[j])
+// IN_BF16: input features BF16 (else FP32); OUT: 0 store BF16, 1 store FP32,
+// 2 add into FP32.
+template <bool ROWS, bool IN_BF16, int OUT>
+__global__ void __launch_bounds__(256)
+k_gnn_spmm(int64_t nrows, const int *__restrict__ rp, const int *__restrict__ ci,
+           const int *__restrict__ val, const float *__restrict__ rowinv,
+           const void *__restrict__ in, void *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t r = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6; r < nrows;
+         r += nw) {
+        float acc = 0.f;
+        const int e1 = rp[r + 1];
+        for (int e = rp[r]; e < e1; ++e) {
+            const int c = ci[e];
+            const float a = (val ? static_cast<float>(val[e]) : 1.f) * (ROWS ? rowinv[r] : rowinv[c]);
+            const float h = IN_BF16 ? bf2f(static_cast<const uint16_t *>(in)[static_cast<int64_t>(c) * kGnnH + lane])
+                                    : static_cast<const float *>(in)[static_cast<int64_t>(c) * kGnnH + lane];
+            acc = fmaf(a, h, acc);
+        }
+        const int64_t o = r * kGnnH + lane;
+        if (OUT == 0) static_cast<uint16_t *>(out)[o] = f2bf(acc);
+        else if (OUT == 1) static_cast<float *>(out)[o] = acc;
+        else static_cast<float *>(out)[o] += acc;
+    }
+}
+
+void launch_gnn_spmm(hipStream_t s, bool rows, bool in_bf16, int out_mode, int64_t nrows,
+                     const int *rp, const int *ci, const int *val, const float *rowinv,
+                     const void *in, void *out) {
+    if (nrows <= 0) return;
+    int64_t blocks = (nrows * 64 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+#define GF_SP(R, IB, O) k_gnn_spmm<R, IB, O><<<static_cast<int>(blocks), 256, 0, s>>>(nrows, rp, ci, val, rowinv, in, out)
+#define GF_SP2(R, IB) if (out_mode == 0) GF_SP(R, IB, 0); else if (out_mode == 1) GF_SP(R, IB, 1); else GF_SP(R, IB, 2)
+    if (rows) { if (in_bf16) { GF_SP2(true, true); } else { GF_SP2(true, false); } }
+    else { if (in_bf16) { GF_SP2(false, true); } else { GF_SP2(false, false); } }
+#undef GF_SP2
+#undef GF_SP
+}
+
+// ------------------------------------------------------------------ MFMA GEMM
+// C[N x NO] = [A1 | A2][N x KD] * B[KD x NO]  (BF16 operands, FP32 accumulate)
+// A1 holds columns [0, K1), A2 columns [K1, KD) (row stride 64 each); B is
+// given transposed, BT[NO][KD] (BF16), and staged in LDS.  Each wavefront
+// owns 16 rows and all NO columns (NO/16 MFMA tiles).  Operand layout of
+// v_mfma_f32_16x16x16_bf16: lane l supplies A[l%16][4(l/16)+j] and
+// B[4(l/16)+j][l%16], j = 0..3, and receives D[4(l/16)+j][l%16].
+// Epilogue: + bias[col] (if bias), relu (if RELU); columns [0,64) go to out1,
+// [64,128) to out2, as BF16 (OUTB) or FP32 (store or add).
+template <int KD, int NO, bool RELU, int OUTM>
+__global__ void __launch_bounds__(256)
+k_gnn_gemm(int64_t N, const uint16_t *__restrict__ A1, const uint16_t *__restrict__ A2, int K1,
+           const uint16_t *__restrict__ BT, const float *__restrict__ bias, void *__restrict__ out1,
+           void *__restrict__ out2) {
+    __shared__ uint16_t sB[NO * KD];
+    for (int i = threadIdx.x; i < NO * KD / 4; i += blockDim.x)
+        reinterpret_cast<uint2 *>(sB)[i] = reinterpret_cast<const uint2 *>(BT)[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = 4 * (lane >> 4);
+    constexpr int NT = NO / 16;
+    for (int64_t row0 = (static_cast<int64_t>(blockIdx.x) * 4 + wave) * 16; row0 < N;
+         row0 += static_cast<int64_t>(gridDim.x) * 64) {
+        f32x4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int64_t ra = row0 + li;
+#pragma unroll
+        for (int k0 = 0; k0 < KD; k0 += 16) {
+            bf16x4 a = bf16x4{0, 0, 0, 0};
+            if (ra < N) {
+                const int kk = k0 + lk;
+                const uint16_t *src = kk < K1 ? A1 + ra * kGnnH + kk : A2 + ra * kGnnH + (kk - K1);
+                a = *reinterpret_cast<const bf16x4 *>(src);
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&sB[(t * 16 + li) * KD + k0 + lk]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int col = t * 16 + li;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t r = row0 + lk + j;
+                if (r >= N) continue;
+                float v = acc[t][j];
+                if (bias) v += bias[col];
+                if (RELU) v = fmaxf(v, 0.f);
+                void *o = col < 64 ? out1 : out2;
+                const int64_t idx = r * kGnnH + (col & 63);
+                if (OUTM == 0) static_cast<uint16_t *>(o)[idx] = f2bf(v);
+                else if (OUTM == 1) static_cast<float *>(o)[idx] = v;
+                else static_cast<float *>(o)[idx] += v;
+            }
+        }
+    }
+}
+
+static int gemm_grid(int64_t N) {
+    int64_t b = (N + 63) / 64;
+    if (b > 4096) b = 4096;
+    return static_cast<int>(b < 1 ? 1 : b);
+}
+
+// Forward dense layer: out = relu([A1|A2] W + bias), W given as BT[64][128].
+void launch_gnn_dense_fwd(hipStream_t s, int64_t N, const uint16_t *A1, const uint16_t *A2,
+                          const uint16_t *BT, const float *bias, uint16_t *out) {
+    if (N <= 0) return;
+    k_gnn_gemm<128, 64, true, 0><<<gemm_grid(N), 256, 0, s>>>(N, A1, A2, 64, BT, bias, out, nullptr);
+}
+
+// Backward through a dense layer: [dA1 | dA2] (+)= dZ W^T, with W^T given as
+// BT = W [128][64]; dA1/dA2 FP32 (add when accumulate != 0).
+void launch_gnn_dense_bwd_in(hipStream_t s, int64_t N, const uint16_t *dZ, const uint16_t *Wrm,
+                             float *dA1, float *dA2, int accumulate) {
+    if (N <= 0) return;
+    if (accumulate)
+        k_gnn_gemm<64, 128, false, 2><<<gemm_grid(N), 256, 0, s>>>(N, dZ, dZ, 64, Wrm, nullptr, dA1, dA2);
+    else
+        k_gnn_gemm<64, 128, false, 1><<<gemm_grid(N), 256, 0, s>>>(N, dZ, dZ, 64, Wrm, nullptr, dA1, dA2);
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient dW[128 x 64] = [A1 | A2]^T dZ (reduction over N on MFMA).
+// Each workgroup walks 64-row chunks (LDS-staged), keeps its 128x64 partial
+// in registers (4 waves x 8 tiles) and writes it to part[block]; a second
+// kernel adds the partials in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_gnn_wgrad(int64_t N, const uint16_t *__restrict__ A1, const uint16_t *__restrict__ A2,
+            const uint16_t *__restrict__ dZ, float *__restrict__ part) {
+    __shared__ uint16_t sA[64 * 128];
+    __shared__ uint16_t sZ[64 * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = 4 * (lane >> 4);
+    // wave w owns dW rows [32 w, 32 w + 32) (2 m-tiles) x all 64 columns (4 n-tiles)
+    f32x4 acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t c0 = static_cast<int64_t>(blockIdx.x) * 64; c0 < N; c0 += static_cast<int64_t>(gridDim.x) * 64) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * 32; i += 256) {      // A: 64 rows x 128 cols, 4 per thread
+            const int r = i >> 5, q = (i & 31) * 4;
+            uint2 v = {0u, 0u};
+            if (c0 + r < N) {
+                const uint16_t *src = q < 64 ? A1 + (c0 + r) * kGnnH + q : A2 + (c0 + r) * kGnnH + (q - 64);
+                v = *reinterpret_cast<const uint2 *>(src);
+            }
+            *reinterpret_cast<uint2 *>(&sA[r * 128 + q]) = v;
+        }
+        for (int i = threadIdx.x; i < 64 * 16; i += 256) {      // dZ: 64 rows x 64 cols
+            const int r = i >> 4, q = (i & 15) * 4;
+            uint2 v = {0u, 0u};
+            if (c0 + r < N) v = *reinterpret_cast<const uint2 *>(dZ + (c0 + r) * kGnnH + q);
+            *reinterpret_cast<uint2 *>(&sZ[r * 64 + q]) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 64; ks += 16) {
+            bf16x4 a[2], b[4];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const int col = 32 * wave + 16 * mt + li;   // dW row = input feature
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[mt][j] = static_cast<short>(sA[(ks + lk + j) * 128 + col]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[nt][j] = static_cast<short>(sZ[(ks + lk + j) * 64 + 16 * nt + li]);
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[mt * 4 + nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mt], b[nt], acc[mt * 4 + nt], 0, 0, 0);
+        }
+    }
+    float *P = part + static_cast<int64_t>(blockIdx.x) * 128 * 64;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                P[(32 * wave + 16 * mt + lk + j) * 64 + 16 * nt + li] = acc[mt * 4 + nt][j];
+}
+
+// out[i] (+)= sum_b part[b][i], i < len; dst split: rows [0,64) -> dst1, [64,128) -> dst2.
+__global__ void k_gnn_sum_parts(int nparts, int len, const float *__restrict__ part,
+                                float *__restrict__ dst1, float *__restrict__ dst2, int half) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * len + i];
+    if (i < half) dst1[i] = s;
+    else dst2[i - half] = s;
+}
+
+void launch_gnn_wgrad(hipStream_t s, int64_t N, const uint16_t *A1, const uint16_t *A2,
+                      const uint16_t *dZ, float *part, int max_parts, float *dW1, float *dW2) {
+    int g = static_cast<int>((N + 63) / 64);
+    if (g > max_parts) g = max_parts;
+    if (g < 1) g = 1;
+    k_gnn_wgrad<<<g, 256, 0, s>>>(N, A1, A2, dZ, part);
+    k_gnn_sum_parts<<<(128 * 64 + 255) / 256, 256, 0, s>>>(g, 128 * 64, part, dW1, dW2, 64 * 64);
+}
+
+// ---------------------------------------------------------------------------
+// dZ = dOut o [Out > 0] (BF16, for MFMA) and column sums of dZ (bias gradient)
+// as per-workgroup partials.  One wavefront per row, lane = column.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_gnn_mask(int64_t N, const float *__restrict__ dOut, const uint16_t *__restrict__ Out,
+           uint16_t *__restrict__ dZ, float *__restrict__ part) {
+    __shared__ float sh[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float cs = 0.f;
+    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t r = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6; r < N; r += nw) {
+        const int64_t o = r * kGnnH + lane;
+        const float v = (Out[o] != 0 && bf2f(Out[o]) > 0.f) ? dOut[o] : 0.f;
+        dZ[o] = f2bf(v);
+        cs += v;
+    }
+    sh[wave][lane] = cs;
+    __syncthreads();
+    if (wave == 0) part[static_cast<int64_t>(blockIdx.x) * 64 + lane] = sh[0][lane] + sh[1][lane] + sh[2][lane] + sh[3][lane];
+}
+
+void launch_gnn_mask(hipStream_t s, int64_t N, const float *dOut, const uint16_t *Out,
+                     uint16_t *dZ, float *part, int max_parts, float *db) {
+    int g = static_cast<int>((N * 64 + 255) / 256);
+    if (g > max_parts) g = max_parts;
+    if (g < 1) g = 1;
+    k_gnn_mask<<<g, 256, 0, s>>>(N, dOut, Out, dZ, part);
+    k_gnn_sum_parts<<<1, 64, 0, s>>>(g, 64, part, db, db, 64);
+}
+
+// ---------------------------------------------------------------------------
+// Output layer: logit_i = Hv_i . wo + bo; p_i = sigmoid(logit_i).  With a
+// target: loss partials (softplus(z) - t z), dlogit = (p - t)/n, dHv = dlogit wo^T
+// (FP32), and partials of dwo = sum_i dlogit_i Hv_i, dbo = sum dlogit.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_gnn_out(int64_t n, const uint16_t *__restrict__ Hv, const float *__restrict__ theta,
+          float *__restrict__ logit, float *__restrict__ p, const float *__restrict__ target,
+          float *__restrict__ dHv, float *__restrict__ part) {
+    __shared__ float sh[4][66];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float wo = theta[kGnnOffwo + lane];
+    const float bo = theta[kGnnOffbo];
+    float gw = 0.f, gb = 0.f, ls = 0.f;
+    const float inv_n = 1.f / static_cast<float>(n);
+    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6; i < n; i += nw) {
+        const float h = bf2f(Hv[i * kGnnH + lane]);
+        const float z = wave_sum(h * wo) + bo;
+        const float pz = 1.f / (1.f + __expf(-z));
+        if (lane == 0) {
+            if (logit) logit[i] = z;
+            if (p) p[i] = pz;
+        }
+        if (target) {
+            const float t = target[i];
+            const float dz = (pz - t) * inv_n;
+            dHv[i * kGnnH + lane] = dz * wo;
+            gw += dz * h;
+            gb += dz;
+            ls += fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z))) - t * z;
+        }
+    }
+    if (!target) return;
+    sh[wave][lane] = gw;
+    if (lane == 0) { sh[wave][64] = gb; sh[wave][65] = ls; }
+    __syncthreads();
+    if (wave == 0) {
+        float* P = part + static_cast<int64_t>(blockIdx.x) * 66;
+        P[lane] = sh[0][lane] + sh[1][lane] + sh[2][lane] + sh[3][lane];
+        if (lane < 2) P[64 + lane] = sh[0][64 + lane] + sh[1][64 + lane] + sh[2][64 + lane] + sh[3][64 + lane];
+    }
+}
+
+// loss_out[0] = mean loss; grad[wo], grad[bo].
+__global__ void k_gnn_out_reduce(int nparts, int64_t n, const float *__restrict__ part,
+                                 float *__restrict__ grad, float *__restrict__ loss_out) {
+    const int i = threadIdx.x;   // 66 threads
+    if (i >= 66) return;
+    float s = 0.f;
+    for (int b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * 66 + i];
+    if (i < 64) grad[kGnnOffwo + i] = s;
+    else if (i == 64) grad[kGnnOffbo] = s;
+    else loss_out[0] = s / static_cast<float>(n);
+}
+
+void launch_gnn_out(hipStream_t s, int64_t n, const uint16_t *Hv, const float *theta, float *logit,
+                    float *p, const float *target, float *dHv, float *part, int max_parts,
+                    float *grad, float *loss_out) {
+    int g = static_cast<int>((n * 64 + 255) / 256);
+    if (g > max_parts) g = max_parts;
+    if (g < 1) g = 1;
+    k_gnn_out<<<g, 256, 0, s>>>(n, Hv, theta, logit, p, target, dHv, part);
+    if (target) k_gnn_out_reduce<<<1, 128, 0, s>>>(g, n, part, grad, loss_out);
+}
+
+// ---------------------------------------------------------------------------
+// Embedding backward: dZ0 = dH o [H0 > 0]; dU[k][h] = sum F[k] dZ0[h], du = sum dZ0.
+// part[block][5*64] = {dU rows 0..3, du}.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_gnn_embed_bwd(int64_t N, int is_var, int m1, const float *__restrict__ xy,
+                const float *__restrict__ crt, float iscale, const uint16_t *__restrict__ H0,
+                const float *__restrict__ dH, float *__restrict__ part) {
+    __shared__ float sh[4][5][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t r = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6; r < N; r += nw) {
+        const int64_t o = r * kGnnH + lane;
+        const float dz = bf2f(H0[o]) > 0.f ? dH[o] : 0.f;
+        float f0, f1, f2;
+        if (is_var) {
+            const float xi = xy[r];
+            f0 = xi; f1 = 4.f * xi * (1.f - xi); f2 = crt[r] * iscale;
+        } else {
+            const float yj = xy[r];
+            f0 = yj / (1.f + fabsf(yj)); f1 = crt[r] * iscale; f2 = r >= m1 ? 1.f : 0.f;
+        }
+        acc[0] += f0 * dz; acc[1] += f1 * dz; acc[2] += f2 * dz; acc[3] += dz; acc[4] += dz;
+    }
+    for (int k = 0; k < 5; ++k) sh[wave][k][lane] = acc[k];
+    __syncthreads();
+    if (wave == 0)
+        for (int k = 0; k < 5; ++k)
+            part[static_cast<int64_t>(blockIdx.x) * 320 + k * 64 + lane] = sh[0][k][lane] + sh[1][k][lane] + sh[2][k][lane] + sh[3][k][lane];
+}
+
+// dU (4x64) then du (64) contiguous in grad: U at offU, u at offu.
+__global__ void k_gnn_embed_bwd_reduce(int nparts, const float *__restrict__ part,
+                                       float *__restrict__ gU, float *__restrict__ gu) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // 320
+    if (i >= 320) return;
+    float s = 0.f;
+    for (int b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * 320 + i];
+    if (i < 256) gU[i] = s;
+    else gu[i - 256] = s;
+}
+
+void launch_gnn_embed_bwd(hipStream_t s, int64_t N, int is_var, int m1, const float *xy,
+                          const float *crt, float iscale, const uint16_t *H0, const float *dH,
+                          float *part, int max_parts, float *gU, float *gu) {
+    if (N <= 0) {   // no nodes of this kind: zero gradient (fill kernel, no memset node)
+        k_gnn_sum_parts<<<2, 256, 0, s>>>(0, 320, part, gU, gu, 256);
+        return;
+    }
+    int g = static_cast<int>((N * 64 + 255) / 256);
+    if (g > max_parts) g = max_parts;
+    if (g < 1) g = 1;
+    k_gnn_embed_bwd<<<g, 256, 0, s>>>(N, is_var, m1, xy, crt, iscale, H0, dH, part);
+    k_gnn_embed_bwd_reduce<<<2, 256, 0, s>>>(g, part, gU, gu);
+}
+
+void launch_gnn_embed(hipStream_t s, int64_t n, int64_t m, int m1, const float *x, const float *y,
+                      const float *ct, const float *rt, float ictmax, float irtmax,
+                      const float *theta, uint16_t *Hv, uint16_t *Hc) {
+    int64_t blocks = ((n + m) * 64 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks > 0)
+        k_gnn_embed<<<static_cast<int>(blocks), 256, 0, s>>>(n, m, m1, x, y, ct, rt, ictmax, irtmax, theta, Hv, Hc);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 operand copies of the layer weights from the FP32 master:
+//   fwd[l][side] = W^T [64 out][128 in] (in = [self | message]),
+//   bwd[l][side] = W   [128 in][64 out].
+// ---------------------------------------------------------------------------
+__global__ void k_gnn_pack(const float *__restrict__ theta, uint16_t *__restrict__ wf,
+                           uint16_t *__restrict__ wb) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // over L*2*128*64
+    if (idx >= kGnnL * 2 * 128 * 64) return;
+    const int blk = idx / (128 * 64);      // l*2 + side (0 = constraint side, 1 = variable side)
+    const int r = idx % (128 * 64);
+    const int in = r / 64, o = r % 64;     // W[in][o]
+    const int l = blk >> 1, side = blk & 1;
+    const float *base = theta + kGnnOffLayer + l * kGnnLayerSize + side * (2 * 64 * 64 + 64);
+    const float w = in < 64 ? base[in * 64 + o] : base[64 * 64 + (in - 64) * 64 + o];
+    wb[static_cast<int64_t>(blk) * 128 * 64 + in * 64 + o] = f2bf(w);
+    wf[static_cast<int64_t>(blk) * 128 * 64 + o * 128 + in] = f2bf(w);
+}
+
+void launch_gnn_pack(hipStream_t s, const float *theta, uint16_t *wf, uint16_t *wb) {
+    k_gnn_pack<<<(kGnnL * 2 * 128 * 64 + 255) / 256, 256, 0, s>>>(theta, wf, wb);
+}
+
+// Adam (Kingma & Ba) on the flat FP32 parameter vector.
+__global__ void k_gnn_adam(int np, float *__restrict__ theta, const float *__restrict__ g,
+                           float *__restrict__ m, float *__restrict__ v, float lr, float b1,
+                           float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+void launch_gnn_adam(hipStream_t s, int np, float *theta, const float *g, float *m, float *v,
+                     float lr, float b1, float b2, float eps, float c1, float c2) {
+    k_gnn_adam<<<(np + 255) / 256, 256, 0, s>>>(np, theta, g, m, v, lr, b1, b2, eps, c1, c2);
+}
+
+}  // namespace gfors

@@ -387,6 +387,155 @@ void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool ba
 #undef GF_SELL
 }
 
+// ---------------------------------------------------------------------------
+// Nonzero bitmaps.  PDHG iterates sit on the box bounds for most variables and
+// many duals stay at 0, so most gathered operands of the two SpMVs are zeros.
+// bits[i/32] bit i%32 = (v_i != 0); the SpMV variants below keep the bitmap of
+// their slice in LDS and only issue the gather for set bits (skipping zero
+// terms leaves the FP32 sums unchanged).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_nzbits(const float *__restrict__ v, int64_t n, int64_t nwords64, uint64_t *__restrict__ bits) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; w < nwords64;
+         w += (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6) {
+        const int64_t i = w * 64 + lane;
+        const bool nz = i < n && v[i] != 0.f;
+        const uint64_t mask = __ballot(nz);
+        if (lane == 0) bits[w] = mask;
+    }
+}
+
+void launch_nzbits(hipStream_t s, const float *v, int64_t n, int64_t nwords64, uint64_t *bits) {
+    int64_t blocks = (nwords64 * 64 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks > 0) k_nzbits<<<static_cast<int>(blocks), 256, 0, s>>>(v, n, nwords64, bits);
+}
+
+// Sliced SELL partial SpMV with the slice's bitmap in LDS (persistent: G
+// workgroups per slice loop over the slice's chunks).
+template <bool UNIT>
+__global__ void __launch_bounds__(1024)
+k_sell_part_bits(int nrows, int P, int nchunk, int ns, int ncols, int G,
+                 const int *__restrict__ ptr, const int *__restrict__ ci,
+                 const int *__restrict__ val, const int *__restrict__ row_of,
+                 const float *__restrict__ v, const uint32_t *__restrict__ bits,
+                 float *__restrict__ part) {
+    extern __shared__ uint32_t sb[];
+    const int sl = blockIdx.x % P;
+    const int gb = blockIdx.x / P;
+    const int base = sl * ns;
+    const int nw = ns >> 5;
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) sb[w] = bits[(base >> 5) + w];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwv = blockDim.x >> 6;
+    const int64_t pb = static_cast<int64_t>(sl) * (nchunk + 1);
+    for (int c = gb * nwv + wave; c < nchunk; c += G * nwv) {
+        const int e0 = ptr[pb + c];
+        const int L = (ptr[pb + c + 1] - e0) >> 6;
+        const int *cic = ci + e0 + lane;
+        float acc = 0.f;
+#pragma unroll 4
+        for (int k = 0; k < L; ++k) {
+            const int col = __builtin_nontemporal_load(cic + 64 * k);
+            if (col < ncols) {
+                const int loc = col - base;
+                if ((sb[loc >> 5] >> (loc & 31)) & 1u) {
+                    if (UNIT) acc += v[col];
+                    else acc = fmaf(static_cast<float>(val[e0 + lane + 64 * k]), v[col], acc);
+                }
+            }
+        }
+        const int row = row_of[(static_cast<int64_t>(sl) * nchunk + c) * 64 + lane];
+        if (row >= 0) part[static_cast<int64_t>(sl) * nrows + row] = acc;
+    }
+}
+
+void launch_sell_part_bits(hipStream_t s, const SellView &sv, int ns, int ncols, bool unit,
+                           const float *v, const uint32_t *bits, float *part) {
+    const int G = 64;   // 8 slices x 64 workgroups x 16 wavefronts
+    const size_t lds = static_cast<size_t>(ns / 32) * 4;
+    if (unit) k_sell_part_bits<true><<<G * sv.P, 1024, lds, s>>>(sv.nrows, sv.P, sv.nchunk, ns, ncols, G, sv.ptr, sv.ci, sv.val, sv.row_of, v, bits, part);
+    else k_sell_part_bits<false><<<G * sv.P, 1024, lds, s>>>(sv.nrows, sv.P, sv.nchunk, ns, ncols, G, sv.ptr, sv.ci, sv.val, sv.row_of, v, bits, part);
+}
+
+// Primal step with the whole dual bitmap in LDS (persistent grid-stride over
+// virtual blocks of 256 threads; no Q).
+template <int LPR, bool UNIT, bool BATCH>
+__global__ void __launch_bounds__(1024)
+k_primal_bits(int n, int m, int nvb, const int *__restrict__ rpT, const int *__restrict__ ciT,
+              const int *__restrict__ valT, const float *__restrict__ wy,
+              const uint32_t *__restrict__ bits, const float *__restrict__ x_in,
+              float *__restrict__ x_out, float *__restrict__ xbar, const float *__restrict__ ct,
+              float tau1, const float *__restrict__ tau1_inst, const double *__restrict__ rho,
+              const int *__restrict__ var_inst, DevCounters *__restrict__ ctr) {
+    extern __shared__ uint32_t sb[];
+    const int nw = (m + 31) >> 5;
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) sb[w] = bits[w];
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->k += 1;
+    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const int tid = vb * 1024 + threadIdx.x;
+        const int i = tid / LPR;
+        const int sub = tid & (LPR - 1);
+        float xi = 0.f, cti = 0.f, s1 = 0.f;
+        int t = 0;
+        if (i < n) {
+            xi = x_in[i];
+            cti = ct[i];
+            if (BATCH) t = var_inst[i];
+            const int e1 = rpT[i + 1];
+            for (int e = rpT[i] + sub; e < e1; e += LPR) {
+                const int j = ciT[e];
+                if ((sb[j >> 5] >> (j & 31)) & 1u) {
+                    if (UNIT) s1 += wy[j];
+                    else s1 = fmaf(static_cast<float>(valT[e]), wy[j], s1);
+                }
+            }
+        }
+        s1 = group_sum<LPR>(s1);
+        if (i < n && sub == 0) {
+            const float rh = static_cast<float>(rho[t]);
+            const float ta = BATCH ? tau1_inst[t] : tau1;
+            const float g = cti + rh - s1 - 2.f * rh * xi;
+            const float xn = fminf(fmaxf(xi - ta * g, 0.f), 1.f);
+            x_out[i] = xn;
+            xbar[i] = 2.f * xn - xi;
+        }
+    }
+}
+
+template <int LPR>
+static void primal_bits_lpr(hipStream_t s, bool unit, bool batched, int n, int m,
+                            const int *rpT, const int *ciT, const int *valT, const float *wy,
+                            const uint32_t *bits, const float *x_in, float *x_out, float *xbar,
+                            const float *ct, float tau1, const float *tau1_inst,
+                            const double *rho, const int *var_inst, DevCounters *ctr) {
+    const int64_t nvb64 = (static_cast<int64_t>(n) * LPR + 1023) / 1024;
+    const int nvb = static_cast<int>(nvb64);
+    const int grid = nvb < 512 ? nvb : 512;   // two 16-wave workgroups per CU
+    const size_t lds = static_cast<size_t>((m + 31) / 32) * 4;
+    if (grid <= 0) return;
+#define GF_PB(U, B) k_primal_bits<LPR, U, B><<<grid, 1024, lds, s>>>(n, m, nvb, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
+    if (unit) { if (batched) GF_PB(true, true); else GF_PB(true, false); }
+    else { if (batched) GF_PB(false, true); else GF_PB(false, false); }
+#undef GF_PB
+}
+
+void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, int m,
+                        const int *rpT, const int *ciT, const int *valT, const float *wy,
+                        const uint32_t *bits, const float *x_in, float *x_out, float *xbar,
+                        const float *ct, float tau1, const float *tau1_inst, const double *rho,
+                        const int *var_inst, DevCounters *ctr) {
+    switch (lpr) {
+#define GF_CASE(L) case L: primal_bits_lpr<L>(s, unit, batched, n, m, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr); break;
+        GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
+#undef GF_CASE
+        default: break;
+    }
+}
+
 // ------------------------------------------------------------ small helpers
 __global__ void k_copy_f32(float *__restrict__ d, const float *__restrict__ s, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;

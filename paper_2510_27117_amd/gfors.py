@@ -39,7 +39,10 @@ EXPORTS = [
     "gfors_final_round", "gfors_run_rounds", "gfors_best", "gfors_get_residuals",
     "gfors_get_history", "gfors_get_state", "gfors_set_state", "gfors_get_candidates",
     "gfors_get_scales", "gfors_get_dims", "gfors_kernel_times", "gfors_reset",
-    "gfors_get_launch_cfg", "gfors_set_launch_cfg",
+    "gfors_get_launch_cfg", "gfors_set_launch_cfg", "gfors_autotune",
+    "gfors_gnn_workspace_bytes", "gfors_gnn_create", "gfors_gnn_destroy", "gfors_gnn_act_bytes",
+    "gfors_gnn_forward", "gfors_gnn_grad", "gfors_gnn_adam", "gfors_gnn_train_step",
+    "gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad",
 ]
 
 KERNEL_NAMES = ["dual", "primal", "sample", "eval_cover", "eval_general", "eval_quad",
@@ -84,9 +87,23 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_reset.argtypes = [c_vp]
     L.gfors_get_launch_cfg.argtypes = [c_vp, c_vp]
     L.gfors_set_launch_cfg.argtypes = [c_vp, c_vp]
+    L.gfors_autotune.argtypes = [c_vp]
+    L.gfors_gnn_workspace_bytes.argtypes = [P(ctypes.c_size_t)]
+    L.gfors_gnn_create.argtypes = [c_vp, c_vp, ctypes.c_size_t, c_vp, P(c_vp)]
+    L.gfors_gnn_destroy.argtypes = [c_vp]
+    L.gfors_gnn_destroy.restype = None
+    L.gfors_gnn_act_bytes.argtypes = [c_vp, c_i32, P(ctypes.c_size_t)]
+    L.gfors_gnn_forward.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp, c_vp]
+    L.gfors_gnn_grad.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]
+    L.gfors_gnn_adam.argtypes = [c_vp, ctypes.c_float]
+    L.gfors_gnn_train_step.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t,
+                                       ctypes.c_float, c_vp]
+    for nm in ("gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad"):
+        getattr(L, nm).argtypes = [c_vp, c_vp]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("gfors_default_params", "gfors_destroy_problem", "gfors_last_error"):
+        if name not in ("gfors_default_params", "gfors_destroy_problem", "gfors_last_error",
+                        "gfors_gnn_destroy"):
             f.restype = c_i32
     _lib = L
     return L
@@ -281,17 +298,22 @@ class Problem:
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_NAMES)}
 
     def launch_cfg(self) -> dict:
-        out = np.zeros(6, dtype=np.int32)
+        out = np.zeros(8, dtype=np.int32)
         _check(load_library().gfors_get_launch_cfg(self._h(), _ptr(out)))
         return {"lpr_dual": int(out[0]), "lpr_primal": int(out[1]),
                 "slices_dual": int(out[2]), "slices_primal": int(out[3]),
-                "sell_dual": int(out[4]), "sell_primal": int(out[5])}
+                "sell_dual": int(out[4]), "sell_primal": int(out[5]),
+                "bits_dual": int(out[6]), "bits_primal": int(out[7])}
 
     def set_launch_cfg(self, lpr_dual, lpr_primal, slices_dual=1, slices_primal=1,
-                       sell_dual=0, sell_primal=0):
-        cfg = np.array([lpr_dual, lpr_primal, slices_dual, slices_primal, sell_dual, sell_primal],
-                       dtype=np.int32)
+                       sell_dual=0, sell_primal=0, bits_dual=0, bits_primal=0):
+        cfg = np.array([lpr_dual, lpr_primal, slices_dual, slices_primal, sell_dual, sell_primal,
+                        bits_dual, bits_primal], dtype=np.int32)
         _check(load_library().gfors_set_launch_cfg(self._h(), _ptr(cfg)))
+
+    def autotune(self):
+        """Re-time the SpMV launch shapes on the current iterate and keep the fastest."""
+        _check(load_library().gfors_autotune(self._h()))
 
     def reset(self):
         """Restart from x0 with a cleared incumbent (Preprocess kept)."""
@@ -328,3 +350,130 @@ def gfors_sample_eval(P: Problem, K: int, p_override=None, outputs: bool = False
 
 def gfors_best(P: Problem, inst: int = 0):
     return P.best(inst)
+
+
+# ---------------------------------------------------------------------------
+# Learned sampling proposal
+# ---------------------------------------------------------------------------
+GNN_NUM_PARAMS = 50241
+GNN_H, GNN_L = 64, 3
+
+
+def gnn_param_shapes():
+    """Flat parameter layout of include/gfors.h (order matters)."""
+    shp = [("Uv", (4, GNN_H)), ("uv", (GNN_H,)), ("Uc", (4, GNN_H)), ("uc", (GNN_H,))]
+    for l in range(GNN_L):
+        shp += [(f"Wcc{l}", (GNN_H, GNN_H)), (f"Wcv{l}", (GNN_H, GNN_H)), (f"bc{l}", (GNN_H,)),
+                (f"Wvv{l}", (GNN_H, GNN_H)), (f"Wvc{l}", (GNN_H, GNN_H)), (f"bv{l}", (GNN_H,))]
+    shp += [("wo", (GNN_H,)), ("bo", (1,))]
+    return shp
+
+
+def gnn_init_params(seed: int = 0) -> np.ndarray:
+    """Glorot-uniform weights, zero biases (seeded), as the flat FP32 vector."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, shp in gnn_param_shapes():
+        if len(shp) == 2:
+            lim = np.sqrt(6.0 / (shp[0] + shp[1]))
+            out.append(rng.uniform(-lim, lim, size=shp).reshape(-1))
+        elif name == "wo":
+            lim = np.sqrt(6.0 / (GNN_H + 1))
+            out.append(rng.uniform(-lim, lim, size=shp))
+        else:
+            out.append(np.zeros(shp))
+    v = np.concatenate(out).astype(np.float32)
+    assert v.size == GNN_NUM_PARAMS
+    return v
+
+
+class GNN:
+    """A learned-proposal network living on the device."""
+
+    def __init__(self, params: Optional[np.ndarray] = None, seed: int = 0, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        L = load_library()
+        nb = ctypes.c_size_t(0)
+        _check(L.gfors_gnn_workspace_bytes(ctypes.byref(nb)))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        p = gnn_init_params(seed) if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == GNN_NUM_PARAMS
+        h = ctypes.c_void_p()
+        _check(L.gfors_gnn_create(_ptr(p), ctypes.c_void_p(self.ws.data_ptr()), nb.value,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        self._acts = {}
+
+    def _act(self, prob: "Problem", training: bool):
+        key = (id(prob), training)
+        if key not in self._acts:
+            nb = ctypes.c_size_t(0)
+            _check(load_library().gfors_gnn_act_bytes(prob._h(), 1 if training else 0, ctypes.byref(nb)))
+            self._acts[key] = self.torch.empty(int(nb.value), dtype=self.torch.uint8, device=prob.device)
+        a = self._acts[key]
+        return ctypes.c_void_p(a.data_ptr()), a.numel()
+
+    @staticmethod
+    def _dptr(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    def forward(self, prob: "Problem", x=None, y=None, with_logits: bool = False):
+        """p = sigmoid(logit) (device float32 [n]); x, y: device float32 or None (current state)."""
+        torch = self.torch
+        p = torch.empty(prob.n, dtype=torch.float32, device=prob.device)
+        lg = torch.empty(prob.n, dtype=torch.float32, device=prob.device) if with_logits else None
+        a, nb = self._act(prob, False)
+        _check(load_library().gfors_gnn_forward(self.handle, prob._h(), self._dptr(x), self._dptr(y),
+                                                a, nb, self._dptr(p), self._dptr(lg)))
+        return (p, lg) if with_logits else p
+
+    def grad(self, prob, target, x=None, y=None) -> float:
+        loss = ctypes.c_float(0)
+        a, nb = self._act(prob, True)
+        _check(load_library().gfors_gnn_grad(self.handle, prob._h(), self._dptr(x), self._dptr(y),
+                                             self._dptr(target), a, nb, ctypes.byref(loss)))
+        return float(loss.value)
+
+    def train_step(self, prob, target, lr: float, x=None, y=None, want_loss: bool = True):
+        loss = ctypes.c_float(0)
+        a, nb = self._act(prob, True)
+        _check(load_library().gfors_gnn_train_step(self.handle, prob._h(), self._dptr(x), self._dptr(y),
+                                                   self._dptr(target), a, nb, ctypes.c_float(lr),
+                                                   ctypes.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def adam(self, lr: float):
+        _check(load_library().gfors_gnn_adam(self.handle, ctypes.c_float(lr)))
+
+    def params(self) -> np.ndarray:
+        v = np.zeros(GNN_NUM_PARAMS, dtype=np.float32)
+        _check(load_library().gfors_gnn_get_params(self.handle, _ptr(v)))
+        return v
+
+    def set_params(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        _check(load_library().gfors_gnn_set_params(self.handle, _ptr(v)))
+
+    def get_grad(self) -> np.ndarray:
+        v = np.zeros(GNN_NUM_PARAMS, dtype=np.float32)
+        _check(load_library().gfors_gnn_get_grad(self.handle, _ptr(v)))
+        return v
+
+    def set_grad(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        _check(load_library().gfors_gnn_set_grad(self.handle, _ptr(v)))
+
+    def close(self):
+        if self.handle:
+            self.stream.synchronize()
+            load_library().gfors_gnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -372,3 +372,33 @@ def test_autotuned_shape_is_valid(G):
     assert cfg["slices_dual"] in (1, 8) and cfg["lpr_dual"] in (1, 2, 4, 8, 16, 32, 64)
     prob.set_launch_cfg(cfg["lpr_dual"], cfg["lpr_primal"], cfg["slices_dual"], cfg["slices_primal"])
     prob.close()
+
+
+def test_bitmap_skip_variants_match_oracle(G):
+    """Zero-operand skipping through LDS bitmaps (sliced SELL dual, fused CSR
+    primal) gives the same teacher-forced step; the state has zeros in xbar and
+    y so that both skip paths are taken."""
+    P = I.set_cover_columns(600_000, 60_000, 5, seed=3)
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=61, keep_every=60)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    assert np.mean(s32.xbar == 0) > 0.2 and np.mean(s32.y == 0) > 0.05
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+    cfgs = [(1, 4, 8, 1, 1, 0, 1, 0)] + [(1, l, 8, 1, 1, 0, 1, 1) for l in (1, 2, 4, 8, 16)]
+    for cfg in cfgs:
+        prob.set_launch_cfg(*cfg)
+        assert prob.launch_cfg()["bits_dual"] == 1
+        prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+        prob.pdhg_steps(1)
+        got = prob.get_state()
+        assert rel_inf(got["x"], ref.x) <= TOL_PDHG and rel_inf(got["y"], ref.y) <= TOL_PDHG, cfg
+    # two consecutive steps through the graph path keep using the fresh bitmaps
+    prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+    prob.pdhg_steps(2)
+    g2 = prob.get_state()
+    r2 = O.pdhg_step(S, O.pdhg_step(S, s32, rho), rho)
+    assert rel_inf(g2["x"], r2.x) <= 2 * TOL_PDHG and rel_inf(g2["y"], r2.y) <= 2 * TOL_PDHG
+    with pytest.raises(G.GforsError):
+        prob.set_launch_cfg(4, 4, 1, 1, 0, 0, 1, 0)     # bitmap dual needs the sliced SELL layout
+    prob.close()
