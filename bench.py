@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--tti-rounds", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+    ap.add_argument("--train-instances", type=int, default=200)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--seq-sample", type=int, default=8,
+                    help="batched workloads: instances run one by one for the comparison")
     return ap.parse_args()
 
 
@@ -102,6 +106,129 @@ def cpu_baseline(bip, k_int, K):
             "host_cpus": os.cpu_count()}
 
 
+def batched_tti(G, bip, R, times):
+    """Per-instance rounds (and wall ms of the batched launch) until the
+    incumbent is within 0.1% of the instance's best after R rounds."""
+    hits, feas = [], 0
+    for t in range(bip.num_instances):
+        hist = G.history(t, R)
+        ok = np.nonzero(hist != np.iinfo(np.int64).max)[0]
+        if not ok.size:
+            continue
+        feas += 1
+        zf = int(hist[-1])
+        hits.append(int(np.nonzero(hist <= zf + 0.001 * abs(zf))[0][0]))
+    if not hits:
+        return {"rounds": R, "instances_with_incumbent": 0}
+    med = int(np.median(hits))
+    return {"rounds": R, "instances_with_incumbent": feas, "target_gap": 0.001,
+            "median_round_hit": med, "max_round_hit": int(max(hits)),
+            "ms_to_all_targets": round(times[int(max(hits))], 3),
+            "ms_total": round(times[-1], 3), "avg_ms_per_round": round(times[-1] / R, 4)}
+
+
+def sequential_compare(bip, prm, a, R, batched_ms):
+    """The same R rounds run instance by instance (each its own problem, graph
+    replay) on a sample of instances; the per-instance mean is scaled to the
+    whole batch and set against the batched launch."""
+    import torch
+    from paper_2510_27117_amd import gfors, instances
+    off = bip.inst_offsets
+    rng = np.random.default_rng(0)
+    pick = rng.choice(bip.num_instances, size=min(a.seq_sample, bip.num_instances), replace=False)
+    ms = []
+    for t in pick:
+        sub = instances.BIP(n=int(off[t + 1, 0] - off[t, 0]), c=bip.c[off[t, 0]:off[t + 1, 0]])
+        r0, r1 = int(off[t, 1]), int(off[t + 1, 1])
+        rp = bip.A.row_ptr[r0:r1 + 1] - bip.A.row_ptr[r0]
+        e0, e1 = int(bip.A.row_ptr[r0]), int(bip.A.row_ptr[r1])
+        sub.A = instances.CSR(r1 - r0, sub.n, rp, bip.A.col[e0:e1] - int(off[t, 0]),
+                              None if bip.A.val is None else bip.A.val[e0:e1])
+        sub.b = bip.b[r0:r1]
+        P = gfors.Problem(sub, prm)
+        P.run_rounds(1, a.K, True)
+        P.synchronize()
+        e0_, e1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0_.record(P.stream)
+        P.run_rounds(R - 1, a.K, True)
+        e1_.record(P.stream)
+        P.synchronize()
+        ms.append(e0_.elapsed_time(e1_) * R / (R - 1))
+        P.close()
+    per = float(np.mean(ms))
+    return {"sampled_instances": int(len(pick)), "mean_ms_per_instance": round(per, 3),
+            "sequential_ms_estimate": round(per * bip.num_instances, 1),
+            "batched_ms": round(batched_ms, 1),
+            "speedup": round(per * bip.num_instances / batched_ms, 2)}
+
+
+def learned_experiment(a):
+    """Learned vs plain proposal on uncapacitated facility location (TU
+    reformulated: one assignment per customer eliminated, B_JI = I).
+
+    Training: the plain method runs on `--train-instances` small instances
+    (40 facilities x 400 customers, seeds 1000..); iterates at 6 triggers are
+    paired with the run's final incumbent; the network is trained on the GPU.
+    Evaluation: the full instance (1,000 x 10,000) runs `--tti-rounds` triggers
+    plain (K per round from x_k) and, after a reset, learned (K/2 from x_k +
+    K/2 from the network per trigger).  Time-to-incumbent = HIP-event time until
+    the incumbent is within 0.1% of the plain run's final value."""
+    import torch
+    from paper_2510_27117_amd import gfors, instances, learned
+    t0 = time.perf_counter()
+    train_prm = gfors.default_params(k_int=50, K_max=256)
+    bips = []
+    for sd in range(1000, 1000 + a.train_instances):
+        P = instances.facility_location(40, 400, seed=sd)
+        bips.append(gfors.TUReformulation(P, P.meta["tu_pivots"]).model)
+    samples = learned.collect(bips, train_prm, rounds=60, K=256, snapshots=6)
+    t_collect = time.perf_counter() - t0
+    net = gfors.GNN(seed=a.seed)
+    loss0 = learned.mean_loss(net, samples[:64])
+    t0 = time.perf_counter()
+    learned.train(net, samples, steps=a.train_steps, lr=3e-3, seed=a.seed)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    loss1 = learned.mean_loss(net, samples[:64])
+
+    full = instances.facility_location(1000, 10000, seed=a.seed)
+    tu = gfors.TUReformulation(full, full.meta["tu_pivots"])
+    prm = gfors.default_params(k_int=a.k_int, K_max=a.K)
+    G = gfors.Problem(tu.model, prm)
+    R = a.tti_rounds
+    plain = learned.run_plain(G, R, a.K)
+    G.reset()
+    lrn = learned.run_learned(G, net, R, a.K)
+    G.final_round()
+    best = G.best(0)
+    xfull = tu.recover(best["x"]) if best["found"] else None
+    c0 = tu.constant
+    zp = [z + c0 if z != learned.INT64_MAX else None for z in plain.z]
+    zl = [z + c0 if z != learned.INT64_MAX else None for z in lrn.z]
+    res = {"metric": METRIC, "workload": "ufl_learned",
+           "config": {"workload": "facility location 1000 x 10000 (TU: 10k assignments eliminated)",
+                      "n_reduced": tu.model.n, "rows": tu.model.m1,
+                      "nnz": int(tu.model.A.nnz), "K": a.K, "k_int": a.k_int, "rounds": R,
+                      "train": f"{a.train_instances} instances 40 x 400, {len(samples)} pairs, {a.train_steps} Adam steps"},
+           "collect_s": round(t_collect, 2), "train_s": round(t_train, 2),
+           "train_loss_before": round(loss0, 5), "train_loss_after": round(loss1, 5),
+           "plain": {"first_feasible_round": next((i for i, z in enumerate(zp) if z is not None), None),
+                     "z_final": zp[-1], "ms_total": round(plain.ms[-1], 2)},
+           "learned": {"first_feasible_round": next((i for i, z in enumerate(zl) if z is not None), None),
+                       "z_final": zl[-1], "ms_total": round(lrn.ms[-1], 2)}}
+    if zp[-1] is not None:
+        target = zp[-1] + 0.001 * abs(zp[-1])
+        tp = plain.time_to(int(np.floor(target - c0)))
+        tl = lrn.time_to(int(np.floor(target - c0)))
+        res["time_to_incumbent"] = {"target": target, "plain_ms": tp, "learned_ms": tl,
+                                    "speedup": (round(tp / tl, 3) if tp and tl else None)}
+    if xfull is not None:
+        res["recovered_point_objective"] = int(full.c @ xfull.astype(np.int64))
+    G.close()
+    net.close()
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -114,6 +241,9 @@ def main():
     t0 = time.perf_counter()
     bip = instances.workload(a.workload, seed=a.seed)
     t_gen = time.perf_counter() - t0
+    if a.workload == "ufl_learned":
+        print(json.dumps(learned_experiment(a)))
+        return
     prm = gfors.default_params(k_int=a.k_int, K_max=max(a.K, 1024))
     t0 = time.perf_counter()
     G = gfors.Problem(bip, prm)
@@ -190,7 +320,9 @@ def main():
     G.synchronize()
     times = [evs[0].elapsed_time(evs[r + 1]) for r in range(R)]
     tti = {}
-    for t in range(min(bip.num_instances, 1)):
+    if bip.num_instances > 1:
+        tti = batched_tti(G, bip, R, times)
+    for t in range(min(bip.num_instances, 1) if bip.num_instances == 1 else 0):
         hist = G.history(t, R)
         feas = np.nonzero(hist != np.iinfo(np.int64).max)[0]
         if feas.size:
@@ -206,6 +338,10 @@ def main():
         else:
             tti = {"rounds": R, "z_final": None, "note": "no feasible candidate",
                    "avg_ms_per_round": round(times[-1] / R, 4)}
+
+    seq = None
+    if bip.num_instances > 1 and a.seq_sample:
+        seq = sequential_compare(bip, prm, a, R, times[-1])
 
     base = None
     if not a.no_cpu_baseline:
@@ -230,6 +366,9 @@ def main():
         "time_to_incumbent": tti,
         "cpu_baseline": base,
     }
+    if bip.num_instances > 1:
+        out["instance_iter_per_s"] = round(iters_per_s * bip.num_instances, 1)
+        out["batched_vs_sequential"] = seq
     print(json.dumps(out))
     G.close()
 

@@ -138,6 +138,14 @@ int gfors_pdhg_steps(gfors_problem *P, int32_t nsteps, int32_t want_residuals);
 int gfors_sample_eval(gfors_problem *P, int32_t K, const float *p_override,
                       int32_t *viol_dev, int64_t *obj_dev);
 
+/* As gfors_sample_eval; flags = GFORS_SAMPLE_NO_TRIGGER draws an additional
+ * round inside the current trigger: it consumes a Philox round id and updates
+ * the incumbent but neither advances the trigger counter nor changes rho
+ * (k_r > 1 rounds per trigger of Algorithm 1, e.g. from a second proposal). */
+#define GFORS_SAMPLE_NO_TRIGGER 1
+int gfors_sample_eval_ex(gfors_problem *P, int32_t K, const float *p_override,
+                         int32_t *viol_dev, int64_t *obj_dev, int32_t flags);
+
 /* Evaluate round(x_k) = [x_k > 1/2] (last step of Algorithm 1) and merge it
  * into the incumbent (round id -1).  Does not advance rho.  Async. */
 int gfors_final_round(gfors_problem *P);
@@ -272,6 +280,37 @@ int gfors_gnn_get_params(gfors_gnn *G, float *host);
 int gfors_gnn_set_params(gfors_gnn *G, const float *host);
 int gfors_gnn_get_grad(gfors_gnn *G, float *host);
 int gfors_gnn_set_grad(gfors_gnn *G, const float *host);
+
+/* ---------------------------------------------------------------------------
+ * TU reformulation (Theorem of Sec. 2.4.1), host only, for pivot blocks B_JI
+ * that are a signed identity (each pivot equality row r holds its pivot column
+ * p with coefficient +-1 and no other pivot column) and Q = 0.  With
+ * x_p = s_p + S_p x_Ibar (s_p = b_rp d_r, S_p = -b_rp B_{r,Ibar}) it forms
+ *   A' = A_.I S + A_.Ibar, b' = b - A_.I s, B' = B_JbarI S + B_JbarIbar,
+ *   d' = d_Jbar - B_JbarI s, c' = S^T c_I + c_Ibar, constant c'_0 = <c_I, s>,
+ * and appends the bound rows S_p x >= -s_p (all pivots, in pivot order) then
+ * -S_p x >= s_p - 1, leaving out a bound row that every point of [0,1]^n'
+ * satisfies.  Kept variables keep their relative order.
+ *   pivots  int64[m2]: pivot column of equality row r, or -1 to keep row r.
+ * Errors: E_ARG (pivot coefficient not +-1, column pivot of two rows, block
+ * not a signed identity, Q != 0, int32 overflow of a coefficient). */
+typedef struct gfors_tu gfors_tu;
+int gfors_tu_create(const gfors_csr *A, const int64_t *b, const gfors_csr *B, const int64_t *d,
+                    const gfors_csr *Q, const int64_t *c, int64_t n, const int64_t *pivots,
+                    gfors_tu **out);
+/* dims[6] = {n', m1', m2', nnz(A'), nnz(B'), c'_0}. */
+int gfors_tu_dims(gfors_tu *U, int64_t *dims);
+/* Copy the reformulated model into caller arrays sized from gfors_tu_dims
+ * (row pointers int64[m+1]; any pointer may be NULL); kept_vars int64[n']
+ * gives the original index of each new variable. */
+int gfors_tu_export(gfors_tu *U, int64_t *A_rp, int32_t *A_ci, int32_t *A_val, int64_t *b,
+                    int64_t *B_rp, int32_t *B_ci, int32_t *B_val, int64_t *d, int64_t *c,
+                    int64_t *kept_vars);
+/* x_full (uint8[n]) from x_reduced (uint8[n']): x_I = s + S x_Ibar; E_STATE if
+ * some x_p falls outside {0,1} (the reduced point violates a bound row). */
+int gfors_tu_recover(gfors_tu *U, const uint8_t *x_reduced, uint8_t *x_full);
+void gfors_tu_destroy(gfors_tu *U);
+const char *gfors_tu_last_error(void);
 
 /* Dimensions: n, m1, m2, number of instances. */
 int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32_t *T);

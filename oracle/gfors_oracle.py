@@ -488,3 +488,77 @@ def run_gfors(P, params: Params, iters: int, K: int, instance: int = 0,
         viol, z = evaluate(P, X)
         incumbent_update(inc, X, viol, z, -1, st.k)
     return inc, st, S, hist
+
+
+# ----------------------------------------------------------------------------
+# TU reformulation (Theorem of Sec. 2.4.1), Q = 0
+# ----------------------------------------------------------------------------
+
+def tu_reformulate(P, pivots):
+    """Eliminate x_I through x_I = s + S x_Ibar for the equality rows J that
+    carry a pivot (pivots[r] = column, or -1 to keep row r), following the
+    theorem's formulas with the matrix inverse written out:
+        s = B_JI^{-1} d_J,  S = -B_JI^{-1} B_JIbar,
+        A' = A_.I S + A_.Ibar, b' = b - A_.I s, B' = B_JbarI S + B_JbarIbar,
+        d' = d_Jbar - B_JbarI s, c' = S^T c_I + c_Ibar, c'_0 = <c_I, s>,
+    plus the rows S x >= -s and -S x >= s - 1 (0 <= x_I <= 1), of which a row
+    satisfied by every point of the box is left out (reading: it removes no
+    point of the relaxation or of the binary problem).  Returns
+    (P', c'_0, recover) with recover(x') = full binary point."""
+    from paper_2510_27117_amd import instances as Inst   # data containers only
+    assert P.Q is None
+    pivots = np.asarray(pivots, dtype=np.int64)
+    n = P.n
+    Bs = _int_csr(P.B).astype(np.float64).tocsc()
+    J = np.nonzero(pivots >= 0)[0]
+    Jbar = np.nonzero(pivots < 0)[0]
+    I = pivots[J]
+    Ibar = np.setdiff1d(np.arange(n), I)
+    BJ = Bs.tocsr()[J]
+    BJI = BJ[:, I].toarray()
+    BJIinv = np.linalg.inv(BJI)
+    S = -(BJIinv @ BJ[:, Ibar].toarray())
+    s = BJIinv @ P.d[J].astype(np.float64)
+    Sr, sr = np.rint(S), np.rint(s)
+    assert np.allclose(S, Sr) and np.allclose(s, sr), "B_JI^{-1} must be integral"
+    S, s = Sr.astype(np.int64), sr.astype(np.int64)
+    rows, rhs = [], []
+    if P.A is not None:
+        Ad = I_dense(P.A)
+        Ap = Ad[:, I] @ S + Ad[:, Ibar]
+        rows.append(Ap)
+        rhs.append(P.b.astype(np.int64) - Ad[:, I] @ s)
+    low, lowr, up, upr = [], [], [], []
+    for q in range(I.size):
+        for coef, r, lst, rl in ((S[q], -s[q], low, lowr), (-S[q], s[q] - 1, up, upr)):
+            if coef[coef < 0].sum() >= r:
+                continue
+            lst.append(coef)
+            rl.append(r)
+    if low:
+        rows.append(np.array(low))
+        rhs.append(np.array(lowr))
+    if up:
+        rows.append(np.array(up))
+        rhs.append(np.array(upr))
+    Pn = Inst.BIP(n=Ibar.size, c=(S.T @ P.c[I] + P.c[Ibar]).astype(np.int64), name=P.name + "_tu")
+    if rows:
+        Pn.A = Inst.csr_from_dense(np.vstack(rows))
+        Pn.b = np.concatenate(rhs).astype(np.int64)
+    if Jbar.size:
+        Bd = I_dense(P.B)
+        Pn.B = Inst.csr_from_dense(Bd[Jbar][:, I] @ S + Bd[Jbar][:, Ibar])
+        Pn.d = (P.d[Jbar] - Bd[Jbar][:, I] @ s).astype(np.int64)
+    c0 = int(P.c[I] @ s)
+
+    def recover(xr):
+        x = np.zeros(n, dtype=np.int64)
+        x[Ibar] = np.asarray(xr, dtype=np.int64)
+        x[I] = s + S @ x[Ibar]
+        return x
+
+    return Pn, c0, recover
+
+
+def I_dense(M) -> np.ndarray:
+    return _int_csr(M).toarray()

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgfors.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["gfors_api.cpp", "pdhg_kernels.hip", "sample_eval_kernels.hip", "gnn_kernels.hip"]
+SOURCES = ["gfors_api.cpp", "pdhg_kernels.hip", "sample_eval_kernels.hip", "gnn_kernels.hip",
+           "gfors_tu.cpp"]
 ARCH = os.environ.get("GFORS_ARCH", "gfx950")
 
 

@@ -1157,7 +1157,7 @@ static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *t
 }
 
 static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override, int threshold,
-                                KTimer *tm = nullptr) {
+                                KTimer *tm = nullptr, int trigger = 1) {
     hipStream_t s = P->stream;
     const int W = K / 64;
     const float *p = p_override ? p_override : P->xbuf[P->cur];
@@ -1182,7 +1182,7 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
                        P->hasQ ? 1 : 0, P->red_v, P->red_z, P->viol, P->z);
     TE(6);
     TB(7);
-    launch_argmin_update(s, P->T, K, W, P->viol, P->z, P->di, P->ctr, threshold ? 0 : 1);
+    launch_argmin_update(s, P->T, K, W, P->viol, P->z, P->di, P->ctr, threshold ? 0 : (trigger ? 1 : 2));
     TE(7);
     TB(8);
     launch_extract_best(s, P->n, P->T, P->var_inst, P->d_inst_var0, P->X, P->di, P->xbest);
@@ -1200,10 +1200,16 @@ int gfors_pdhg_steps(gfors_problem *P, int32_t nsteps, int32_t want_residuals) {
 
 int gfors_sample_eval(gfors_problem *P, int32_t K, const float *p_override, int32_t *viol_dev,
                       int64_t *obj_dev) {
+    return gfors_sample_eval_ex(P, K, p_override, viol_dev, obj_dev, 0);
+}
+
+int gfors_sample_eval_ex(gfors_problem *P, int32_t K, const float *p_override, int32_t *viol_dev,
+                         int64_t *obj_dev, int32_t flags) {
     if (!P) return fail(GFORS_E_ARG, "NULL handle");
     if (!check_K(K) || K > P->prm.K_max)
         return fail(GFORS_E_ARG, "K must be a multiple of 64 in [64, K_max] (multiple of 1024 above 1024)");
-    enqueue_sample_eval(P, K, p_override, 0);
+    if (flags & ~GFORS_SAMPLE_NO_TRIGGER) return fail(GFORS_E_ARG, "unknown flag");
+    enqueue_sample_eval(P, K, p_override, 0, nullptr, (flags & GFORS_SAMPLE_NO_TRIGGER) ? 0 : 1);
     const size_t cnt = static_cast<size_t>(P->T) * K;
     if (viol_dev) HIP_TRY(hipMemcpyAsync(viol_dev, P->viol, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice, P->stream));
     if (obj_dev) HIP_TRY(hipMemcpyAsync(obj_dev, P->z, cnt * sizeof(int64_t), hipMemcpyDeviceToDevice, P->stream));
@@ -1469,6 +1475,20 @@ struct gfors_gnn {
     float *part = nullptr, *loss = nullptr;
     int64_t t = 0;                             // Adam steps taken
     hipStream_t stream = nullptr;
+    // the parameters are shared by problems on different streams: every call
+    // waits for the previous one (event) and records its own completion
+    hipEvent_t ev = nullptr;
+    bool ev_valid = false;
+    void begin(hipStream_t s) {
+        if (ev_valid) (void)hipStreamWaitEvent(s, ev, 0);
+    }
+    void end(hipStream_t s) {
+        (void)hipEventRecord(ev, s);
+        ev_valid = true;
+    }
+    ~gfors_gnn() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
 };
 
 namespace {
@@ -1531,6 +1551,7 @@ int gnn_run(gfors_gnn *G, gfors_problem *P, const float *x, const float *y, cons
     gnn_act_carve(P, training, a, cv);
     if (cv.off > act_bytes) return fail(GFORS_E_OOM, "GNN activation workspace too small");
     hipStream_t s = P->stream;
+    G->begin(s);
     const int64_t n = P->n, m = P->m;
     const float *xs = x ? x : P->xbuf[P->cur];
     const float *ys = y ? y : P->ybuf[P->cur];
@@ -1552,6 +1573,7 @@ int gnn_run(gfors_gnn *G, gfors_problem *P, const float *x, const float *y, cons
     launch_gnn_out(s, n, a.Hv[kGnnL], G->theta, logit_out ? logit_out : a.logit, p_out ? p_out : a.p,
                    training ? target : nullptr, a.dHv, G->part, kGnnMaxParts, G->grad, G->loss);
     if (!training) {
+        G->end(s);
         HIP_TRY(hipGetLastError());
         return GFORS_OK;
     }
@@ -1577,6 +1599,7 @@ int gnn_run(gfors_gnn *G, gfors_problem *P, const float *x, const float *y, cons
                          G->part, kGnnMaxParts, G->grad + kGnnOffUv, G->grad + kGnnOffuv);
     launch_gnn_embed_bwd(s, m, 0, static_cast<int>(P->m1), ys, P->rt, P->gnn_irtmax, a.Hc[0], a.dHc,
                          G->part, kGnnMaxParts, G->grad + kGnnOffUc, G->grad + kGnnOffuc);
+    G->end(s);
     HIP_TRY(hipGetLastError());
     return GFORS_OK;
 }
@@ -1598,6 +1621,10 @@ int gfors_gnn_create(const float *params_host, void *ws, size_t ws_bytes, void *
     if (!params_host || !ws || !out) return fail(GFORS_E_ARG, "NULL argument");
     auto *G = new gfors_gnn();
     G->stream = static_cast<hipStream_t>(stream);
+    if (hipEventCreateWithFlags(&G->ev, hipEventDisableTiming) != hipSuccess) {
+        delete G;
+        return fail(GFORS_E_HIP, "hipEventCreate failed");
+    }
     Carver cv{static_cast<char *>(ws), 0, ws_bytes};
     cv.off = (256 - (reinterpret_cast<uintptr_t>(ws) & 255)) & 255;
     if (gnn_ws_carve(G, cv) > ws_bytes) {
@@ -1654,14 +1681,22 @@ int gfors_gnn_grad(gfors_gnn *G, gfors_problem *P, const float *x_dev, const flo
     return GFORS_OK;
 }
 
+static int gnn_adam_on(gfors_gnn *G, hipStream_t s, float lr);
+
 int gfors_gnn_adam(gfors_gnn *G, float lr) {
     if (!G || !(lr > 0.f)) return fail(GFORS_E_ARG, "bad argument");
+    return gnn_adam_on(G, G->stream, lr);
+}
+
+static int gnn_adam_on(gfors_gnn *G, hipStream_t s, float lr) {
+    G->begin(s);
     G->t += 1;
     const double b1 = 0.9, b2 = 0.999;
     const float c1 = static_cast<float>(1.0 - std::pow(b1, static_cast<double>(G->t)));
     const float c2 = static_cast<float>(1.0 - std::pow(b2, static_cast<double>(G->t)));
-    launch_gnn_adam(G->stream, kGnnNumParams, G->theta, G->grad, G->m, G->v, lr, 0.9f, 0.999f, 1e-8f, c1, c2);
-    launch_gnn_pack(G->stream, G->theta, G->wf, G->wb);
+    launch_gnn_adam(s, kGnnNumParams, G->theta, G->grad, G->m, G->v, lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+    launch_gnn_pack(s, G->theta, G->wf, G->wb);
+    G->end(s);
     HIP_TRY(hipGetLastError());
     return GFORS_OK;
 }
@@ -1669,13 +1704,15 @@ int gfors_gnn_adam(gfors_gnn *G, float lr) {
 int gfors_gnn_train_step(gfors_gnn *G, gfors_problem *P, const float *x_dev, const float *y_dev,
                          const float *target_dev, void *act, size_t act_bytes, float lr,
                          float *loss_host) {
+    if (!(lr > 0.f)) return fail(GFORS_E_ARG, "bad learning rate");
     int rc = gfors_gnn_grad(G, P, x_dev, y_dev, target_dev, act, act_bytes, loss_host);
     if (rc) return rc;
-    return gfors_gnn_adam(G, lr);
+    return gnn_adam_on(G, P->stream, lr);
 }
 
 int gfors_gnn_get_params(gfors_gnn *G, float *host) {
     if (!G || !host) return fail(GFORS_E_ARG, "NULL argument");
+    G->begin(G->stream);
     HIP_TRY(hipMemcpyAsync(host, G->theta, kGnnNumParams * sizeof(float), hipMemcpyDeviceToHost, G->stream));
     HIP_TRY(hipStreamSynchronize(G->stream));
     return GFORS_OK;
@@ -1683,6 +1720,7 @@ int gfors_gnn_get_params(gfors_gnn *G, float *host) {
 
 int gfors_gnn_set_params(gfors_gnn *G, const float *host) {
     if (!G || !host) return fail(GFORS_E_ARG, "NULL argument");
+    G->begin(G->stream);
     HIP_TRY(hipMemcpyAsync(G->theta, host, kGnnNumParams * sizeof(float), hipMemcpyHostToDevice, G->stream));
     launch_gnn_pack(G->stream, G->theta, G->wf, G->wb);
     HIP_TRY(hipStreamSynchronize(G->stream));
@@ -1691,6 +1729,7 @@ int gfors_gnn_set_params(gfors_gnn *G, const float *host) {
 
 int gfors_gnn_get_grad(gfors_gnn *G, float *host) {
     if (!G || !host) return fail(GFORS_E_ARG, "NULL argument");
+    G->begin(G->stream);
     HIP_TRY(hipMemcpyAsync(host, G->grad, kGnnNumParams * sizeof(float), hipMemcpyDeviceToHost, G->stream));
     HIP_TRY(hipStreamSynchronize(G->stream));
     return GFORS_OK;
@@ -1698,6 +1737,7 @@ int gfors_gnn_get_grad(gfors_gnn *G, float *host) {
 
 int gfors_gnn_set_grad(gfors_gnn *G, const float *host) {
     if (!G || !host) return fail(GFORS_E_ARG, "NULL argument");
+    G->begin(G->stream);
     HIP_TRY(hipMemcpyAsync(G->grad, host, kGnnNumParams * sizeof(float), hipMemcpyHostToDevice, G->stream));
     HIP_TRY(hipStreamSynchronize(G->stream));
     return GFORS_OK;

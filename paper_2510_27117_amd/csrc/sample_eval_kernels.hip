@@ -398,7 +398,9 @@ void launch_reduce_cand(hipStream_t s, int T, int K, int S, const Tiles &et, con
 // incumbent on strict improvement.  With advance != 0 the trigger counter n
 // grows and rho follows UpdatePenalty (Sec. 3):
 //   rho_n = min(max(rho_min (1 + n/T)^p, rho_{n-1} + delta), rho_max).
-// One block per instance.
+// advance: 0 = final rounding (no round consumed), 1 = sampling trigger (round
+// consumed, rho advances), 2 = extra round within a trigger (round consumed,
+// rho unchanged).  One block per instance.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_argmin_update(int K, int W, const int32_t *__restrict__ viol, const int64_t *__restrict__ z,
@@ -443,6 +445,8 @@ k_argmin_update(int K, int W, const int32_t *__restrict__ viol, const int64_t *_
         di.improved[inst] = imp;
         if (advance) {
             if (round < di.hist_cap) di.hist[static_cast<int64_t>(inst) * di.hist_cap + round] = di.zbest[inst];
+        }
+        if (advance == 1) {   // a sampling trigger: UpdatePenalty
             const int64_t nn = di.ntrig[inst] + 1;
             di.ntrig[inst] = nn;
             const double rt = di.rho_min[inst] * pow(1.0 + static_cast<double>(nn) / di.rho_T[inst], di.rho_p[inst]);

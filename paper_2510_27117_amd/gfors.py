@@ -34,7 +34,7 @@ class gfors_params(ctypes.Structure):
 
 
 EXPORTS = [
-    "gfors_default_params", "gfors_workspace_bytes", "gfors_create_problem",
+    "gfors_default_params", "gfors_workspace_bytes", "gfors_create_problem", "gfors_sample_eval_ex",
     "gfors_destroy_problem", "gfors_last_error", "gfors_pdhg_steps", "gfors_sample_eval",
     "gfors_final_round", "gfors_run_rounds", "gfors_best", "gfors_get_residuals",
     "gfors_get_history", "gfors_get_state", "gfors_set_state", "gfors_get_candidates",
@@ -43,6 +43,8 @@ EXPORTS = [
     "gfors_gnn_workspace_bytes", "gfors_gnn_create", "gfors_gnn_destroy", "gfors_gnn_act_bytes",
     "gfors_gnn_forward", "gfors_gnn_grad", "gfors_gnn_adam", "gfors_gnn_train_step",
     "gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad",
+    "gfors_tu_create", "gfors_tu_dims", "gfors_tu_export", "gfors_tu_recover", "gfors_tu_destroy",
+    "gfors_tu_last_error",
 ]
 
 KERNEL_NAMES = ["dual", "primal", "sample", "eval_cover", "eval_general", "eval_quad",
@@ -74,6 +76,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_pdhg_steps.argtypes = [c_vp, c_i32, c_i32]
     L.gfors_sample_eval.argtypes = [c_vp, c_i32, c_vp, c_vp, c_vp]
     L.gfors_final_round.argtypes = [c_vp]
+    L.gfors_sample_eval_ex.argtypes = [c_vp, c_i32, c_vp, c_vp, c_vp, c_i32]
     L.gfors_run_rounds.argtypes = [c_vp, c_i32, c_i32, c_i32]
     L.gfors_best.argtypes = [c_vp, c_i32, P(c_i64), c_vp, P(c_i32), c_vp]
     L.gfors_get_residuals.argtypes = [c_vp, c_vp]
@@ -100,10 +103,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.c_float, c_vp]
     for nm in ("gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad"):
         getattr(L, nm).argtypes = [c_vp, c_vp]
+    L.gfors_tu_create.argtypes = [P(gfors_csr), c_vp, P(gfors_csr), c_vp, P(gfors_csr), c_vp, c_i64,
+                                  c_vp, P(c_vp)]
+    L.gfors_tu_dims.argtypes = [c_vp, c_vp]
+    L.gfors_tu_export.argtypes = [c_vp] + [c_vp] * 10
+    L.gfors_tu_recover.argtypes = [c_vp, c_vp, c_vp]
+    L.gfors_tu_destroy.argtypes = [c_vp]
+    L.gfors_tu_destroy.restype = None
+    L.gfors_tu_last_error.argtypes = []
+    L.gfors_tu_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("gfors_default_params", "gfors_destroy_problem", "gfors_last_error",
-                        "gfors_gnn_destroy"):
+                        "gfors_gnn_destroy", "gfors_tu_destroy", "gfors_tu_last_error"):
             f.restype = c_i32
     _lib = L
     return L
@@ -203,7 +215,7 @@ class Problem:
     def pdhg_steps(self, nsteps: int, want_residuals: bool = False):
         _check(load_library().gfors_pdhg_steps(self._h(), int(nsteps), 1 if want_residuals else 0))
 
-    def sample_eval(self, K: int, p_override=None, outputs: bool = False):
+    def sample_eval(self, K: int, p_override=None, outputs: bool = False, trigger: bool = True):
         """One sampling round of K candidates per instance.  p_override: a float32
         device tensor of length n (values in [0,1]).  With outputs=True returns
         device tensors (viol int32 [T,K], obj int64 [T,K])."""
@@ -217,9 +229,10 @@ class Problem:
         if outputs:
             v = torch.empty((self.T, K), dtype=torch.int32, device=self.device)
             z = torch.empty((self.T, K), dtype=torch.int64, device=self.device)
-        _check(load_library().gfors_sample_eval(self._h(), int(K), pp,
-                                                None if v is None else ctypes.c_void_p(v.data_ptr()),
-                                                None if z is None else ctypes.c_void_p(z.data_ptr())))
+        _check(load_library().gfors_sample_eval_ex(self._h(), int(K), pp,
+                                                   None if v is None else ctypes.c_void_p(v.data_ptr()),
+                                                   None if z is None else ctypes.c_void_p(z.data_ptr()),
+                                                   0 if trigger else 1))
         if outputs:
             self.synchronize()
             return v, z
@@ -470,6 +483,74 @@ class GNN:
         if self.handle:
             self.stream.synchronize()
             load_library().gfors_gnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# TU reformulation (host-side C++ in the library)
+# ---------------------------------------------------------------------------
+class TUReformulation:
+    """Eliminates one pivot variable per chosen equality row (B_JI a signed
+    identity, Q = 0).  ``model`` is the reformulated BIP (instances.BIP);
+    ``constant`` is c'_0; ``recover(x_reduced)`` maps a reduced 0/1 point back."""
+
+    def __init__(self, bip, pivots):
+        from . import instances as _inst
+        L = load_library()
+        keep: list = []
+        A = _csr(bip.A, keep)
+        B = _csr(bip.B, keep)
+        piv = np.ascontiguousarray(pivots, dtype=np.int64)
+        assert bip.B is not None and piv.size == bip.B.nrows
+        b = None if bip.b is None else np.ascontiguousarray(bip.b, dtype=np.int64)
+        d = np.ascontiguousarray(bip.d, dtype=np.int64)
+        c = np.ascontiguousarray(bip.c, dtype=np.int64)
+        h = ctypes.c_void_p()
+        rc = L.gfors_tu_create(ctypes.byref(A) if A else None, _ptr(b), ctypes.byref(B), _ptr(d),
+                               None, _ptr(c), int(bip.n), _ptr(piv), ctypes.byref(h))
+        if rc != GFORS_OK:
+            raise GforsError(f"{_ERRS.get(rc, rc)}: {L.gfors_tu_last_error().decode()}")
+        self.handle = h
+        dims = np.zeros(6, dtype=np.int64)
+        L.gfors_tu_dims(h, _ptr(dims))
+        n2, m1, m2, nA, nB, c0 = (int(v) for v in dims)
+        Arp, Aci, Aval, bb = (np.zeros(m1 + 1, np.int64), np.zeros(max(nA, 1), np.int32),
+                              np.zeros(max(nA, 1), np.int32), np.zeros(max(m1, 1), np.int64))
+        Brp, Bci, Bval, dd = (np.zeros(m2 + 1, np.int64), np.zeros(max(nB, 1), np.int32),
+                              np.zeros(max(nB, 1), np.int32), np.zeros(max(m2, 1), np.int64))
+        cc = np.zeros(n2, np.int64)
+        kept = np.zeros(n2, np.int64)
+        L.gfors_tu_export(h, _ptr(Arp), _ptr(Aci), _ptr(Aval), _ptr(bb), _ptr(Brp), _ptr(Bci),
+                          _ptr(Bval), _ptr(dd), _ptr(cc), _ptr(kept))
+        model = _inst.BIP(n=n2, c=cc, name=bip.name + "_tu")
+        if m1:
+            model.A = _inst.CSR(m1, n2, Arp, Aci[:nA], Aval[:nA])
+            model.b = bb[:m1]
+        if m2:
+            model.B = _inst.CSR(m2, n2, Brp, Bci[:nB], Bval[:nB])
+            model.d = dd[:m2]
+        self.model = model
+        self.constant = c0
+        self.kept = kept
+        self.n_full = int(bip.n)
+
+    def recover(self, x_reduced) -> np.ndarray:
+        xr = np.ascontiguousarray(x_reduced, dtype=np.uint8)
+        xf = np.zeros(self.n_full, dtype=np.uint8)
+        rc = load_library().gfors_tu_recover(self.handle, _ptr(xr), _ptr(xf))
+        if rc != GFORS_OK:
+            raise GforsError(f"{_ERRS.get(rc, rc)}: {load_library().gfors_tu_last_error().decode()}")
+        return xf
+
+    def close(self):
+        if self.handle:
+            load_library().gfors_tu_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

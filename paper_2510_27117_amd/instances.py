@@ -191,12 +191,12 @@ def knapsack_multi(n: int, m: int, seed: int, wmax: int = 1000, pmax: int = 1000
     max <profit, x> s.t. W x <= cap, written as  -W x >= -cap,  c = -profit.
     W ~ U{1..wmax} dense, cap = floor(row sum / 2), profit ~ U{1..pmax}."""
     rng = np.random.default_rng(seed)
-    W = rng.integers(1, wmax + 1, size=(m, n)).astype(np.int64)
+    W = rng.integers(1, wmax + 1, size=(m, n), dtype=np.int32)
     profit = rng.integers(1, pmax + 1, size=n).astype(np.int64)
-    cap = W.sum(axis=1) // 2
-    r = np.repeat(np.arange(m, dtype=np.int64), n)
-    cc = np.tile(np.arange(n, dtype=np.int64), m)
-    A = csr_from_coo(m, n, r, cc, (-W).reshape(-1))
+    cap = W.sum(axis=1, dtype=np.int64) // 2
+    # dense rows: CSR written directly (row j holds columns 0..n-1)
+    A = CSR(m, n, np.arange(m + 1, dtype=np.int64) * n,
+            np.tile(np.arange(n, dtype=np.int32), m), (-W).reshape(-1))
     return BIP(n=n, c=-profit, A=A, b=-cap, name=f"knapsack_n{n}_m{m}_s{seed}")
 
 
@@ -267,9 +267,14 @@ def facility_location(n_f: int, n_c: int, seed: int, scale: int = 1000,
     cols = np.concatenate([open_col, assign_col])
     vals = np.concatenate([np.ones(npair, np.int64), -np.ones(npair, np.int64)])
     A = csr_from_coo(npair, n, rows, cols, vals)
+    # one assignment per customer to eliminate by a TU reformulation: the
+    # customer's nearest facility (ties to the lowest index)
+    nearest = np.argmin(assign_cost, axis=1)
+    pivots = n_f + np.arange(n_c, dtype=np.int64) * n_f + nearest
     return BIP(n=n, c=c, A=A, b=np.zeros(npair, dtype=np.int64), B=B,
                d=np.ones(n_c, dtype=np.int64),
-               name=f"ufl_f{n_f}_c{n_c}_s{seed}", meta={"n_f": n_f, "n_c": n_c})
+               name=f"ufl_f{n_f}_c{n_c}_s{seed}",
+               meta={"n_f": n_f, "n_c": n_c, "tu_pivots": pivots})
 
 
 def knapsack_batch(num: int, seed: int, n_lo: int = 1000, n_hi: int = 50000,

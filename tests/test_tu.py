@@ -1,0 +1,78 @@
+"""TU reformulation (Theorem of Sec. 2.4.1): the oracle's version is pinned by
+brute force (same optimum, exact objective shift, recovered points feasible),
+and the library's host implementation equals it exactly."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import gfors_oracle as O
+from paper_2510_27117_amd import instances as I
+
+
+def _all(n):
+    return np.array(list(itertools.product([0, 1], repeat=n)), dtype=bool)
+
+
+@pytest.mark.parametrize("nf,nc,seed", [(2, 3, 0), (3, 3, 1), (2, 5, 2)])
+def test_oracle_tu_preserves_the_problem(nf, nc, seed):
+    P = I.facility_location(nf, nc, seed)
+    piv = P.meta["tu_pivots"]
+    Pn, c0, rec = O.tu_reformulate(P, piv)
+    assert Pn.n == P.n - nc and Pn.B is None
+    Xo, Xn = _all(P.n), _all(Pn.n)
+    vo, zo = O.evaluate(P, Xo)
+    vn, zn = O.evaluate(Pn, Xn)
+    # same optimum (objective shifted by c'_0)
+    assert int(zo[vo == 0].min()) == int(zn[vn == 0].min()) + c0
+    # every feasible reduced point maps to a feasible original point, same value
+    for l in np.nonzero(vn == 0)[0]:
+        x = rec(Xn[l])
+        assert set(np.unique(x)) <= {0, 1}
+        v1, z1 = O.evaluate(P, x[None, :].astype(bool))
+        assert v1[0] == 0 and z1[0] == zn[l] + c0
+    # and every feasible original point is hit by its reduced image
+    feas_o = Xo[vo == 0]
+    keep = np.setdiff1d(np.arange(P.n), piv)
+    vk, zk = O.evaluate(Pn, feas_o[:, keep])
+    assert np.all(vk == 0) and np.array_equal(zk + c0, zo[vo == 0])
+
+
+def test_oracle_tu_general_block_and_dropped_rows():
+    """A 2x2 pivot block that is not diagonal (inverse computed) and a kept row."""
+    B = [[1, 1, 0, 1, 0], [0, 1, 0, 0, 1], [1, 0, 1, 1, 1]]
+    P = I.from_dense([3, -2, 4, 1, 5], A=[[1, 1, 1, 1, 1]], b=[1], B=B, d=[1, 1, 2])
+    Pn, c0, rec = O.tu_reformulate(P, np.array([0, 1, -1]))
+    X = _all(P.n)
+    vo, zo = O.evaluate(P, X)
+    vn, zn = O.evaluate(Pn, _all(Pn.n))
+    assert int(zo[vo == 0].min()) == int(zn[vn == 0].min()) + c0
+
+
+@pytest.mark.parametrize("nf,nc,seed", [(2, 3, 0), (4, 7, 3), (6, 40, 5)])
+def test_library_tu_equals_oracle(nf, nc, seed):
+    from paper_2510_27117_amd import gfors
+    P = I.facility_location(nf, nc, seed)
+    piv = P.meta["tu_pivots"]
+    Pn, c0, rec = O.tu_reformulate(P, piv)
+    T = gfors.TUReformulation(P, piv)
+    M = T.model
+    assert T.constant == c0 and M.n == Pn.n
+    assert np.array_equal(M.c, Pn.c)
+    assert np.array_equal(I.csr_to_dense(M.A), I.csr_to_dense(Pn.A)) and np.array_equal(M.b, Pn.b)
+    assert M.B is None and Pn.B is None
+    rng = np.random.default_rng(seed)
+    X = _all(M.n) if M.n <= 12 else (rng.random((64, M.n)) < 0.1)
+    v, _ = O.evaluate(Pn, X)
+    for l in np.nonzero(v == 0)[0][:20]:
+        assert np.array_equal(T.recover(X[l].astype(np.uint8)), rec(X[l]).astype(np.uint8))
+
+
+def test_library_tu_rejects_bad_pivots():
+    from paper_2510_27117_amd import gfors
+    P = I.from_dense([1, 2, 3], B=[[2, 1, 0], [0, 1, 1]], d=[2, 1])
+    with pytest.raises(gfors.GforsError, match="pivot coefficient"):
+        gfors.TUReformulation(P, [0, -1])
+    P2 = I.from_dense([1, 2, 3], B=[[1, 1, 0], [0, 1, 1]], d=[1, 1])
+    with pytest.raises(gfors.GforsError, match="signed identity"):
+        gfors.TUReformulation(P2, [1, 2])
