@@ -40,6 +40,12 @@ def parse():
     ap.add_argument("--tti-rounds", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+    ap.add_argument("--launch-cfg", default=None,
+                    help="pin the SpMV launch shapes (8 comma-separated ints: lpr_dual, lpr_primal, "
+                         "slices_dual, slices_primal, sell_dual, sell_primal, bits_dual, "
+                         "bits_primal) instead of autotuning them")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 512 MiB device copy first (scale for HBM byte counters)")
     ap.add_argument("--train-instances", type=int, default=200)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--seq-sample", type=int, default=8,
@@ -238,16 +244,29 @@ def main():
     import torch
     from paper_2510_27117_amd import gfors, instances
 
+    if a.calib_copy:
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
     bip = instances.workload(a.workload, seed=a.seed)
     t_gen = time.perf_counter() - t0
     if a.workload == "ufl_learned":
         print(json.dumps(learned_experiment(a)))
         return
-    prm = gfors.default_params(k_int=a.k_int, K_max=max(a.K, 1024))
+    pinned = [int(v) for v in a.launch_cfg.split(",")] if a.launch_cfg else None
+    if pinned is not None and len(pinned) != 8:
+        raise SystemExit("--launch-cfg takes 8 integers")
+    prm = gfors.default_params(k_int=a.k_int, K_max=max(a.K, 1024),
+                               autotune=0 if pinned else 1)
     t0 = time.perf_counter()
     G = gfors.Problem(bip, prm)
     t_pre = time.perf_counter() - t0
+    if pinned:
+        G.set_launch_cfg(*pinned)
     use_graph = not a.no_graph
     stream = G.stream
 
@@ -256,7 +275,7 @@ def main():
     for _ in range(a.warmup):
         G.run_rounds(1, a.K, use_graph)
     G.synchronize()
-    if a.warmup:
+    if a.warmup and not pinned:
         G.autotune()
         G.run_rounds(1, a.K, use_graph)
         G.synchronize()

@@ -975,7 +975,24 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
     hipStream_t s = P->stream;
     const bool batched = P->T > 1;
     const float tau2 = static_cast<float>(P->tau2[0]);
-    if (sell && slices > 1 && P->cfg.bits_dual) {
+    if (sell && P->cfg.bits_dual == 2) {
+        const uint32_t *bx32 = reinterpret_cast<const uint32_t *>(P->bx);
+        launch_nzbits(s, P->xbar, P->n, ceil_div(P->n, 64), P->bx);
+        if (slices > 1) {
+            launch_sell_bits(s, P->sellKS, 0, P->unitK, batched, static_cast<int>(P->n), P->xbar,
+                             bx32, P->spart, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f,
+                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr,
+                             nullptr, nullptr, nullptr);
+            launch_dual_combine(s, batched, static_cast<int>(P->m), static_cast<int>(P->m1), slices,
+                                P->spart, P->omega, P->rt, y_in, y_out, P->wy, tau2, P->di.tau2,
+                                P->row_inst);
+        } else {
+            launch_sell_bits(s, P->sellK, 1, P->unitK, batched, static_cast<int>(P->n), P->xbar,
+                             bx32, nullptr, static_cast<int>(P->m1), P->omega, P->rt, y_in, y_out,
+                             P->wy, tau2, P->di.tau2, P->row_inst, nullptr, nullptr, nullptr,
+                             nullptr, 0.f, nullptr, nullptr, nullptr, nullptr);
+        }
+    } else if (sell && slices > 1 && P->cfg.bits_dual) {
         launch_nzbits(s, P->xbar, P->n, ceil_div(P->n, 64), P->bx);
         launch_sell_part_bits(s, P->sellKS, P->sellKS.ns, static_cast<int>(P->n), P->unitK, P->xbar,
                               reinterpret_cast<const uint32_t *>(P->bx), P->spart);
@@ -1011,7 +1028,14 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
     hipStream_t s = P->stream;
     const bool batched = P->T > 1;
     const int kmode = P->m == 0 ? 0 : (P->unitK ? 1 : 2);
-    if (P->cfg.bits_primal && !sell && slices == 1 && kmode != 0 && !P->hasQ) {
+    if (P->cfg.bits_primal == 2 && sell && kmode != 0 && !P->hasQ) {
+        launch_nzbits(s, P->wy, P->m, ceil_div(P->m, 64), P->by);
+        launch_sell_bits(s, P->sellT, 2, P->unitK, batched, static_cast<int>(P->m), P->wy,
+                         reinterpret_cast<const uint32_t *>(P->by), nullptr, 0, nullptr, nullptr,
+                         nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, x_in, x_out, xbar,
+                         P->ct, static_cast<float>(P->tau1[0]), P->di.tau1, P->di.rho,
+                         P->var_inst, ctr);
+    } else if (P->cfg.bits_primal == 1 && !sell && slices == 1 && kmode != 0 && !P->hasQ) {
         launch_nzbits(s, P->wy, P->m, ceil_div(P->m, 64), P->by);
         launch_primal_bits(s, lpr, P->unitK, batched, static_cast<int>(P->n), static_cast<int>(P->m),
                            P->rpT, P->ciT, P->valT, P->wy, reinterpret_cast<const uint32_t *>(P->by),
@@ -1036,11 +1060,24 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
     }
 }
 
-static int bits_ok_dual(gfors_problem *P, int slices, int sell) {
-    return (sell && slices > 1 && P->sellKS.ptr && P->sellKS.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
+// Zero-operand skipping variants.  bits = 1: sliced SELL dual with the slice
+// bitmap in LDS, or fused-CSR primal with the dual bitmap in LDS; bits = 2:
+// k_sell_bits on any SELL copy (batched load issue).  Each needs its bitmap to
+// fit in LDS.
+static int bits_ok_dual(gfors_problem *P, int slices, int sell, int bits) {
+    if (bits == 0) return 1;
+    if (!sell) return 0;
+    if (bits == 1) return (slices > 1 && P->sellKS.ptr && P->sellKS.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
+    if (bits != 2) return 0;
+    const SellView &sv = slices > 1 ? P->sellKS : P->sellK;
+    return (sv.ptr && sv.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
 }
-static int bits_ok_primal(gfors_problem *P, int slices, int sell) {
-    return (!sell && slices == 1 && P->m > 0 && !P->hasQ && (P->m + 31) / 32 * 4 <= kMaxLdsBitmapBytes) ? 1 : 0;
+static int bits_ok_primal(gfors_problem *P, int slices, int sell, int bits) {
+    if (bits == 0) return 1;
+    if (P->m == 0 || P->hasQ || slices != 1) return 0;
+    if (bits == 1) return (!sell && (P->m + 31) / 32 * 4 <= kMaxLdsBitmapBytes) ? 1 : 0;
+    if (bits != 2) return 0;
+    return (sell && P->sellT.ptr && P->sellT.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
 }
 
 // Autotuner: time every candidate launch shape of the dual and primal SpMV on
@@ -1078,12 +1115,17 @@ static int autotune(gfors_problem *P) {
         }
         if (P->sellK.ptr) consider(1, 1, 1);
         if (P->sellKS.ptr) consider(1, kXcdSlices, 1);
-        if (bits_ok_dual(P, kXcdSlices, 1)) {
-            P->cfg.bits_dual = 1;
-            const float t = timeit([&] { launch_dual_cfg(P, 1, kXcdSlices, 1, P->ybuf[P->cur], P->ybuf[1 - P->cur]); });
-            if (t < best) { best = t; P->cfg.lpr_dual = 1; P->cfg.slices_dual = kXcdSlices; P->cfg.sell_dual = 1; }
-            else P->cfg.bits_dual = 0;
+        // zero-operand skipping: each variant is kept only when it is faster
+        int best_bits = 0;
+        for (int b : {1, 2}) {
+            for (int sl : {kXcdSlices, 1}) {
+                if (!bits_ok_dual(P, sl, 1, b)) continue;
+                P->cfg.bits_dual = b;
+                const float t = timeit([&] { launch_dual_cfg(P, 1, sl, 1, P->ybuf[P->cur], P->ybuf[1 - P->cur]); });
+                if (t < best) { best = t; best_bits = b; P->cfg.lpr_dual = 1; P->cfg.slices_dual = sl; P->cfg.sell_dual = 1; }
+            }
         }
+        P->cfg.bits_dual = best_bits;
     }
     {
         float best = 1e30f;
@@ -1100,16 +1142,20 @@ static int autotune(gfors_problem *P) {
             }
         }
         if (P->sellT.ptr) consider(1, 1, 1);
-        if (bits_ok_primal(P, 1, 0)) {
+        int best_bits = 0;
+        if (bits_ok_primal(P, 1, 0, 1)) {
             P->cfg.bits_primal = 1;
-            int bl = -1;
             for (int l : {1, 2, 4, 8, 16}) {
                 const float t = timeit([&] { launch_primal_cfg(P, l, 1, 0, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
-                if (t < best) { best = t; bl = l; }
+                if (t < best) { best = t; best_bits = 1; P->cfg.lpr_primal = l; P->cfg.slices_primal = 1; P->cfg.sell_primal = 0; }
             }
-            if (bl > 0) { P->cfg.lpr_primal = bl; P->cfg.slices_primal = 1; P->cfg.sell_primal = 0; }
-            else P->cfg.bits_primal = 0;
         }
+        if (bits_ok_primal(P, 1, 1, 2)) {
+            P->cfg.bits_primal = 2;
+            const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 1, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
+            if (t < best) { best = t; best_bits = 2; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 1; }
+        }
+        P->cfg.bits_primal = best_bits;
     }
     HIP_TRY(hipGetLastError());
     (void)hipEventDestroy(e0);
@@ -1448,18 +1494,18 @@ int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
         return fail(GFORS_E_ARG, "no SELL copy of the constraint rows for this slicing");
     if (cfg[5] && !(cfg[3] == 1 && P->sellT.ptr))
         return fail(GFORS_E_ARG, "no SELL copy of the transposed rows");
+    if (cfg[6] < 0 || cfg[6] > 2 || !bits_ok_dual(P, cfg[2], cfg[4], cfg[6]))
+        return fail(GFORS_E_ARG, "bitmap dual: 1 needs the sliced SELL layout, 2 a SELL layout, and the slice bitmap must fit in LDS");
+    if (cfg[7] < 0 || cfg[7] > 2 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
+        return fail(GFORS_E_ARG, "bitmap primal: 1 needs the fused CSR layout, 2 the SELL layout; both need Q = 0 and a dual bitmap that fits in LDS");
     P->cfg.lpr_dual = cfg[0];
     P->cfg.lpr_primal = cfg[1];
     P->cfg.slices_dual = cfg[2];
     P->cfg.slices_primal = cfg[3];
-    if (cfg[6] && !bits_ok_dual(P, cfg[2], cfg[4]))
-        return fail(GFORS_E_ARG, "bitmap dual needs the sliced SELL layout and a slice bitmap that fits in LDS");
-    if (cfg[7] && !bits_ok_primal(P, cfg[3], cfg[5]))
-        return fail(GFORS_E_ARG, "bitmap primal needs the fused CSR layout, Q = 0 and a dual bitmap that fits in LDS");
     P->cfg.sell_dual = cfg[4] ? 1 : 0;
     P->cfg.sell_primal = cfg[5] ? 1 : 0;
-    P->cfg.bits_dual = cfg[6] ? 1 : 0;
-    P->cfg.bits_primal = cfg[7] ? 1 : 0;
+    P->cfg.bits_dual = cfg[6];
+    P->cfg.bits_primal = cfg[7];
     P->graphs_clear();
     return GFORS_OK;
 }

@@ -108,6 +108,14 @@ void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool ba
                  const int *var_inst, DevCounters *ctr);
 
 void launch_nzbits(hipStream_t s, const float *v, int64_t n, int64_t nwords64, uint64_t *bits);
+void launch_sell_bits(hipStream_t s, const SellView &sv, int mode, bool unit, bool batched,
+                      int ncols, const float *v, const uint32_t *bits, float *part, int m1,
+                      const float *omega, const float *rt, const float *y_in, float *y_out,
+                      float *wy, float tau2, const float *tau2_inst, const int *row_inst,
+                      const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                      const float *tau1_inst, const double *rho, const int *var_inst,
+                      DevCounters *ctr);
+int sell_bits_blocks(const SellView &sv);
 void launch_sell_part_bits(hipStream_t s, const SellView &sv, int ns, int ncols, bool unit,
                            const float *v, const uint32_t *bits, float *part);
 void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, int m,

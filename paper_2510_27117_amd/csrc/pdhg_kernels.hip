@@ -460,6 +460,135 @@ void launch_sell_part_bits(hipStream_t s, const SellView &sv, int ns, int ncols,
     else k_sell_part_bits<false><<<G * sv.P, 1024, lds, s>>>(sv.nrows, sv.P, sv.nchunk, ns, ncols, G, sv.ptr, sv.ci, sv.val, sv.row_of, v, bits, part);
 }
 
+// SELL-64 SpMV that skips zero operands, any epilogue (MODE as in k_sell).
+// Persistent: G workgroups per column slice, each holding the slice's nonzero
+// bitmap of v in LDS, walk the slice's chunks.  Within a chunk the column
+// indices of 8 consecutive entries are loaded together, then their bits are
+// looked up, then the gathers of the nonzero operands are issued together, so
+// a wavefront keeps up to 16 loads in flight.  The terms are added in the same
+// order as k_sell and the skipped terms are zeros, so the sums equal k_sell's.
+template <bool UNIT, int MODE, bool BATCH>
+__global__ void __launch_bounds__(512)
+k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *__restrict__ ptr,
+            const int *__restrict__ ci, const int *__restrict__ val,
+            const int *__restrict__ row_of, const float *__restrict__ v,
+            const uint32_t *__restrict__ bits, float *__restrict__ part,
+            int m1, const float *__restrict__ omega, const float *__restrict__ rt,
+            const float *__restrict__ y_in, float *__restrict__ y_out, float *__restrict__ wy,
+            float tau2, const float *__restrict__ tau2_inst, const int *__restrict__ row_inst,
+            const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ xbar,
+            const float *__restrict__ ct, float tau1, const float *__restrict__ tau1_inst,
+            const double *__restrict__ rho, const int *__restrict__ var_inst,
+            DevCounters *__restrict__ ctr) {
+    extern __shared__ uint32_t sb[];
+    const int sl = blockIdx.x % P;
+    const int gb = blockIdx.x / P;
+    const int base = sl * ns;
+    const int nw = ns >> 5;
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) sb[w] = bits[(base >> 5) + w];
+    if (MODE == 2 && blockIdx.x == 0 && threadIdx.x == 0) ctr->k += 1;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwv = blockDim.x >> 6;
+    const int64_t pb = static_cast<int64_t>(sl) * (nchunk + 1);
+    for (int c = gb * nwv + wave; c < nchunk; c += G * nwv) {
+        const int e0 = ptr[pb + c];
+        const int L = (ptr[pb + c + 1] - e0) >> 6;
+        const int *cic = ci + e0 + lane;
+        const int *vc = val + e0 + lane;
+        const int row = row_of[(static_cast<int64_t>(sl) * nchunk + c) * 64 + lane];
+        float acc = 0.f;
+        for (int k0 = 0; k0 < L; k0 += 8) {
+            int col[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                col[u] = k0 + u < L ? __builtin_nontemporal_load(cic + 64 * (k0 + u)) : ncols;
+            int a[8];
+            if (!UNIT) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    a[u] = k0 + u < L ? __builtin_nontemporal_load(vc + 64 * (k0 + u)) : 0;
+            }
+            bool nz[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                // padding (col = ncols) and anything outside the slice read word 0
+                const int loc = col[u] - base;
+                const bool in = col[u] < ncols && static_cast<unsigned>(loc) < static_cast<unsigned>(ns);
+                const int li = in ? loc : 0;
+                nz[u] = in && ((sb[li >> 5] >> (li & 31)) & 1u);
+            }
+            float g[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                g[u] = 0.f;
+                if (nz[u]) g[u] = v[col[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (nz[u]) {
+                    if (UNIT) acc += g[u];
+                    else acc = fmaf(static_cast<float>(a[u]), g[u], acc);
+                }
+            }
+        }
+        if (row < 0) continue;
+        if (MODE == 0) {
+            part[static_cast<int64_t>(sl) * nrows + row] = acc;
+        } else if (MODE == 1) {
+            const float om = omega[row];
+            const float t = rt[row] - om * acc;
+            const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
+            float y = y_in[row] + ta * t;
+            if (row < m1) y = fmaxf(y, 0.f);
+            y_out[row] = y;
+            wy[row] = om * y;
+        } else {
+            const int t = BATCH ? var_inst[row] : 0;
+            const float xi = x_in[row];
+            const float rh = static_cast<float>(rho[t]);
+            const float ta = BATCH ? tau1_inst[t] : tau1;
+            const float gr = ct[row] + rh - acc - 2.f * rh * xi;
+            const float xn = fminf(fmaxf(xi - ta * gr, 0.f), 1.f);
+            x_out[row] = xn;
+            xbar[row] = 2.f * xn - xi;
+        }
+    }
+}
+
+int sell_bits_blocks(const SellView &sv) {
+    // workgroups of 8 wavefronts; per CU as many as the bitmap (LDS) and
+    // 32 resident wavefronts allow; the grid is a multiple of P so that
+    // workgroup b (slice b % P) runs on XCD b % 8 when P = 8
+    const int64_t bytes = static_cast<int64_t>(sv.ns / 32) * 4 + 1024;
+    int per_cu = static_cast<int>((160 * 1024) / bytes);
+    if (per_cu > 4) per_cu = 4;
+    if (per_cu < 1) per_cu = 1;
+    int G = 256 * per_cu / sv.P;
+    const int need = (sv.nchunk + 7) / 8;
+    if (G > need) G = need;
+    return G < 1 ? 1 : G;
+}
+
+void launch_sell_bits(hipStream_t s, const SellView &sv, int mode, bool unit, bool batched,
+                      int ncols, const float *v, const uint32_t *bits, float *part, int m1,
+                      const float *omega, const float *rt, const float *y_in, float *y_out,
+                      float *wy, float tau2, const float *tau2_inst, const int *row_inst,
+                      const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                      const float *tau1_inst, const double *rho, const int *var_inst,
+                      DevCounters *ctr) {
+    if (sv.nchunk <= 0 || sv.P <= 0) return;
+    const int G = sell_bits_blocks(sv);
+    const size_t lds = static_cast<size_t>(sv.ns / 32) * 4;
+    const int blocks = G * sv.P;
+#define GF_SB(U, M, B) k_sell_bits<U, M, B><<<blocks, 512, lds, s>>>(sv.nrows, sv.P, sv.nchunk, sv.ns, ncols, G, sv.ptr, sv.ci, sv.val, sv.row_of, v, bits, part, m1, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
+#define GF_SB_M(U, B) if (mode == 0) GF_SB(U, 0, B); else if (mode == 1) GF_SB(U, 1, B); else GF_SB(U, 2, B)
+    if (unit) { if (batched) { GF_SB_M(true, true); } else { GF_SB_M(true, false); } }
+    else { if (batched) { GF_SB_M(false, true); } else { GF_SB_M(false, false); } }
+#undef GF_SB_M
+#undef GF_SB
+}
+
 // Primal step with the whole dual bitmap in LDS (persistent grid-stride over
 // virtual blocks of 256 threads; no Q).
 template <int LPR, bool UNIT, bool BATCH>

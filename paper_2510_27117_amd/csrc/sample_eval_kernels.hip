@@ -270,11 +270,74 @@ k_eval_general(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
     }
 }
 
+// General rows, all words at once: a wavefront owns one row and all W words
+// (lane = candidate 64w + lane, W accumulators per lane), so the row's column
+// indices and coefficients are read once and a variable's W candidate words
+// come in one wide uniform load.  Four wavefronts per workgroup share LDS
+// counters for the tile.
+template <int WW, typename ACC>
+__global__ void __launch_bounds__(256)
+k_eval_rows_allw(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
+                 const int *__restrict__ tb1, const int *__restrict__ rows,
+                 const int *__restrict__ rp, const int *__restrict__ ci,
+                 const int *__restrict__ val, const int64_t *__restrict__ rhs, int m1,
+                 const uint64_t *__restrict__ X, int *__restrict__ vpart, int K) {
+    __shared__ int cnt[64 * WW];
+    const int tile = tile_ids[blockIdx.x];
+    const int r0 = tb0[tile], r1 = tb1[tile];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sh = lane & 31;
+    const bool hi = lane >= 32;
+    for (int l = threadIdx.x; l < 64 * WW; l += blockDim.x) cnt[l] = 0;
+    __syncthreads();
+    int vc[WW];
+#pragma unroll
+    for (int w = 0; w < WW; ++w) vc[w] = 0;
+    for (int rr = r0 + wave; rr < r1; rr += 4) {
+        const int j = rows[rr];
+        ACC acc[WW];
+#pragma unroll
+        for (int w = 0; w < WW; ++w) acc[w] = 0;
+        const int e1 = rp[j + 1];
+        for (int e = rp[j]; e < e1; ++e) {
+            const uint64_t *xr = X + static_cast<int64_t>(ci[e]) * WW;
+            const int a = val ? val[e] : 1;
+#pragma unroll
+            for (int w = 0; w < WW; ++w) {
+                const uint64_t word = xr[w];
+                const uint32_t half = hi ? static_cast<uint32_t>(word >> 32) : static_cast<uint32_t>(word);
+                acc[w] += static_cast<ACC>(static_cast<int>((half >> sh) & 1u) * a);
+            }
+        }
+        const int64_t b = rhs[j];
+#pragma unroll
+        for (int w = 0; w < WW; ++w) {
+            const bool bad = (j < m1) ? (static_cast<int64_t>(acc[w]) < b) : (static_cast<int64_t>(acc[w]) != b);
+            vc[w] += bad ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < WW; ++w)
+        if (vc[w]) atomicAdd(&cnt[64 * w + lane], vc[w]);
+    __syncthreads();
+    for (int l = threadIdx.x; l < K; l += blockDim.x)
+        vpart[static_cast<int64_t>(tile) * K + l] = cnt[l];
+}
+
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,
                          int W, int *vpart, int K) {
     if (!ntiles) return;
+    if (W <= 16 && (W & (W - 1)) == 0) {
+#define GF_RA(WW, ACCT) k_eval_rows_allw<WW, ACCT><<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, vpart, K)
+#define GF_RAW(ACCT) switch (W) { case 1: GF_RA(1, ACCT); break; case 2: GF_RA(2, ACCT); break; \
+        case 4: GF_RA(4, ACCT); break; case 8: GF_RA(8, ACCT); break; default: GF_RA(16, ACCT); break; }
+        if (acc64) { GF_RAW(int64_t) } else { GF_RAW(int32_t) }
+#undef GF_RAW
+#undef GF_RA
+        return;
+    }
     const int NW = W <= 16 ? W : 16;
     if (acc64)
         k_eval_general<int64_t><<<ntiles, NW * 64, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, W, vpart, K);

@@ -350,9 +350,10 @@ def test_sell_layouts_on_small_instances(G):
         s32 = f32_state(st)
         ref = O.pdhg_step(S, s32, rho)
         prob = G.Problem(P, _params(G, autotune=0))
-        cfgs = [(16, 4, 1, 1, 1, 0)]
+        cfgs = [(16, 4, 1, 1, 1, 0), (16, 4, 1, 1, 1, 0, 2, 0)]
         if P.Q is None:
-            cfgs += [(16, 4, 1, 1, 0, 1), (16, 4, 1, 1, 1, 1)]
+            cfgs += [(16, 4, 1, 1, 0, 1), (16, 4, 1, 1, 1, 1), (16, 4, 1, 1, 0, 1, 0, 2),
+                     (16, 4, 1, 1, 1, 1, 2, 2)]
         for cfg in cfgs:
             try:
                 prob.set_launch_cfg(*cfg)
@@ -401,4 +402,32 @@ def test_bitmap_skip_variants_match_oracle(G):
     assert rel_inf(g2["x"], r2.x) <= 2 * TOL_PDHG and rel_inf(g2["y"], r2.y) <= 2 * TOL_PDHG
     with pytest.raises(G.GforsError):
         prob.set_launch_cfg(4, 4, 1, 1, 0, 0, 1, 0)     # bitmap dual needs the sliced SELL layout
+    with pytest.raises(G.GforsError):
+        prob.set_launch_cfg(4, 4, 1, 1, 0, 0, 0, 2)     # batched-issue primal needs the SELL layout
+    prob.close()
+
+
+def test_batched_issue_bitmap_kernels_equal_plain_sell(G):
+    """k_sell_bits adds the same terms in the same order as k_sell and skips
+    only zeros, so a step through it equals the plain SELL step exactly (dual
+    sliced and unsliced, primal), and both are within tolerance of the oracle."""
+    P = I.set_cover_columns(600_000, 60_000, 5, seed=3)
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=61, keep_every=60)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    assert np.mean(s32.xbar == 0) > 0.2 and np.mean(s32.y == 0) > 0.05
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+    pairs = [((1, 4, 8, 1, 1, 0, 0, 0), (1, 4, 8, 1, 1, 0, 2, 0)),
+             ((16, 1, 1, 1, 0, 1, 0, 0), (16, 1, 1, 1, 0, 1, 0, 2)),
+             ((1, 1, 8, 1, 1, 1, 0, 0), (1, 1, 8, 1, 1, 1, 2, 2))]
+    for plain, bits in pairs:
+        out = []
+        for cfg in (plain, bits):
+            prob.set_launch_cfg(*cfg)
+            prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+            prob.pdhg_steps(1)
+            out.append(prob.get_state())
+        assert np.array_equal(out[0]["x"], out[1]["x"]) and np.array_equal(out[0]["y"], out[1]["y"]), bits
+        assert rel_inf(out[1]["x"], ref.x) <= TOL_PDHG and rel_inf(out[1]["y"], ref.y) <= TOL_PDHG, bits
     prob.close()
