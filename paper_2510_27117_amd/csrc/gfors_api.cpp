@@ -137,6 +137,9 @@ struct gfors_problem {
     float *rowinv32 = nullptr;          // 1/||a_j|| (0 for a zero row): the GNN's edge weights
     float gnn_ictmax = 1.f, gnn_irtmax = 1.f;
     uint64_t *bx = nullptr, *by = nullptr;   // nonzero bitmaps of xbar and wy
+    // host-side record, while a sequence of steps is being enqueued, of
+    // whether bx / by already describe the xbar / wy that the next kernel reads
+    bool bx_fresh = false, by_fresh = false;
     int64_t bx_words = 0, by_words = 0;
     int red_S = 1;                  // tile slices of the candidate reduction
     int32_t *red_v = nullptr;
@@ -970,57 +973,66 @@ static int device_norms(gfors_problem *P) {
     return GFORS_OK;
 }
 
+// The dual and primal steps in the launch shape of the configuration.  The
+// zero-skipping variants read the nonzero bitmap of the vector they gather;
+// it is rebuilt (k_nzbits) unless the kernel that last wrote the vector, in
+// the same enqueued sequence, already wrote the bitmap with it.
 static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, const float *y_in,
                             float *y_out) {
     hipStream_t s = P->stream;
     const bool batched = P->T > 1;
     const float tau2 = static_cast<float>(P->tau2[0]);
+    const int m = static_cast<int>(P->m), m1 = static_cast<int>(P->m1);
+    const uint32_t *bx32 = reinterpret_cast<const uint32_t *>(P->bx);
+    auto need_bx = [&] {
+        if (!P->bx_fresh) launch_nzbits(s, P->xbar, P->n, ceil_div(P->n, 64), P->bx);
+        P->bx_fresh = true;
+    };
+    auto combine = [&] {
+        launch_dual_combine(s, batched, m, m1, slices, P->spart, P->omega, P->rt, y_in, y_out,
+                            P->wy, tau2, P->di.tau2, P->row_inst, P->by);
+    };
+    bool wy_bits = false;
     if (sell && P->cfg.bits_dual == 2) {
-        const uint32_t *bx32 = reinterpret_cast<const uint32_t *>(P->bx);
-        launch_nzbits(s, P->xbar, P->n, ceil_div(P->n, 64), P->bx);
+        need_bx();
         if (slices > 1) {
             launch_sell_bits(s, P->sellKS, 0, P->unitK, batched, static_cast<int>(P->n), P->xbar,
                              bx32, P->spart, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f,
                              nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr,
                              nullptr, nullptr, nullptr);
-            launch_dual_combine(s, batched, static_cast<int>(P->m), static_cast<int>(P->m1), slices,
-                                P->spart, P->omega, P->rt, y_in, y_out, P->wy, tau2, P->di.tau2,
-                                P->row_inst);
+            combine();
+            wy_bits = true;
         } else {
             launch_sell_bits(s, P->sellK, 1, P->unitK, batched, static_cast<int>(P->n), P->xbar,
-                             bx32, nullptr, static_cast<int>(P->m1), P->omega, P->rt, y_in, y_out,
-                             P->wy, tau2, P->di.tau2, P->row_inst, nullptr, nullptr, nullptr,
-                             nullptr, 0.f, nullptr, nullptr, nullptr, nullptr);
+                             bx32, nullptr, m1, P->omega, P->rt, y_in, y_out, P->wy, tau2,
+                             P->di.tau2, P->row_inst, nullptr, nullptr, nullptr, nullptr, 0.f,
+                             nullptr, nullptr, nullptr, nullptr);
         }
     } else if (sell && slices > 1 && P->cfg.bits_dual) {
-        launch_nzbits(s, P->xbar, P->n, ceil_div(P->n, 64), P->bx);
+        need_bx();
         launch_sell_part_bits(s, P->sellKS, P->sellKS.ns, static_cast<int>(P->n), P->unitK, P->xbar,
-                              reinterpret_cast<const uint32_t *>(P->bx), P->spart);
-        launch_dual_combine(s, batched, static_cast<int>(P->m), static_cast<int>(P->m1), slices,
-                            P->spart, P->omega, P->rt, y_in, y_out, P->wy, tau2, P->di.tau2,
-                            P->row_inst);
+                              bx32, P->spart);
+        combine();
+        wy_bits = true;
     } else if (sell && slices > 1) {
         launch_sell(s, P->sellKS, 0, P->unitK, batched, P->xbar, P->spart, 0, nullptr, nullptr,
                     nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, nullptr, nullptr, nullptr,
                     nullptr, 0.f, nullptr, nullptr, nullptr, nullptr);
-        launch_dual_combine(s, batched, static_cast<int>(P->m), static_cast<int>(P->m1), slices,
-                            P->spart, P->omega, P->rt, y_in, y_out, P->wy, tau2, P->di.tau2,
-                            P->row_inst);
+        combine();
+        wy_bits = true;
     } else if (sell) {
-        launch_sell(s, P->sellK, 1, P->unitK, batched, P->xbar, nullptr, static_cast<int>(P->m1),
-                    P->omega, P->rt, y_in, y_out, P->wy, tau2, P->di.tau2, P->row_inst, nullptr,
-                    nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, nullptr, nullptr);
+        launch_sell(s, P->sellK, 1, P->unitK, batched, P->xbar, nullptr, m1, P->omega, P->rt,
+                    y_in, y_out, P->wy, tau2, P->di.tau2, P->row_inst, nullptr, nullptr, nullptr,
+                    nullptr, 0.f, nullptr, nullptr, nullptr, nullptr);
     } else if (slices > 1) {
-        launch_spmv_part(s, lpr, P->unitK, static_cast<int>(P->m), slices, P->rpS, P->ciS,
-                         P->valS, P->xbar, P->spart);
-        launch_dual_combine(s, batched, static_cast<int>(P->m), static_cast<int>(P->m1), slices,
-                            P->spart, P->omega, P->rt, y_in, y_out, P->wy,
-                            static_cast<float>(P->tau2[0]), P->di.tau2, P->row_inst);
+        launch_spmv_part(s, lpr, P->unitK, m, slices, P->rpS, P->ciS, P->valS, P->xbar, P->spart);
+        combine();
+        wy_bits = true;
     } else {
-        launch_dual(s, lpr, P->unitK, batched, static_cast<int>(P->m), static_cast<int>(P->m1),
-                    P->rp, P->ci, P->val, P->omega, P->rt, P->xbar, y_in, y_out, P->wy,
-                    static_cast<float>(P->tau2[0]), P->di.tau2, P->row_inst);
+        launch_dual(s, lpr, P->unitK, batched, m, m1, P->rp, P->ci, P->val, P->omega, P->rt,
+                    P->xbar, y_in, y_out, P->wy, tau2, P->di.tau2, P->row_inst);
     }
+    P->by_fresh = wy_bits;
 }
 
 static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, const float *x_in,
@@ -1028,42 +1040,48 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
     hipStream_t s = P->stream;
     const bool batched = P->T > 1;
     const int kmode = P->m == 0 ? 0 : (P->unitK ? 1 : 2);
+    const float tau1 = static_cast<float>(P->tau1[0]);
+    // the bitmap of xbar is written with it only when xbar is the problem's own
+    uint64_t *xbits = xbar == P->xbar ? P->bx : nullptr;
+    auto need_by = [&] {
+        if (!P->by_fresh) launch_nzbits(s, P->wy, P->m, ceil_div(P->m, 64), P->by);
+        P->by_fresh = true;
+    };
+    bool xbar_bits = false;
     if (P->cfg.bits_primal == 2 && sell && kmode != 0 && !P->hasQ) {
-        launch_nzbits(s, P->wy, P->m, ceil_div(P->m, 64), P->by);
+        need_by();
         launch_sell_bits(s, P->sellT, 2, P->unitK, batched, static_cast<int>(P->m), P->wy,
                          reinterpret_cast<const uint32_t *>(P->by), nullptr, 0, nullptr, nullptr,
                          nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, x_in, x_out, xbar,
-                         P->ct, static_cast<float>(P->tau1[0]), P->di.tau1, P->di.rho,
-                         P->var_inst, ctr);
+                         P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst, ctr);
     } else if (P->cfg.bits_primal == 1 && !sell && slices == 1 && kmode != 0 && !P->hasQ) {
-        launch_nzbits(s, P->wy, P->m, ceil_div(P->m, 64), P->by);
+        need_by();
+        uint64_t *xb_out = lpr <= 8 ? xbits : nullptr;
         launch_primal_bits(s, lpr, P->unitK, batched, static_cast<int>(P->n), static_cast<int>(P->m),
                            P->rpT, P->ciT, P->valT, P->wy, reinterpret_cast<const uint32_t *>(P->by),
-                           x_in, x_out, xbar, P->ct, static_cast<float>(P->tau1[0]), P->di.tau1,
-                           P->di.rho, P->var_inst, ctr);
+                           x_in, x_out, xbar, P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst, ctr,
+                           xb_out);
+        xbar_bits = xb_out != nullptr;
     } else if (sell) {
         launch_sell(s, P->sellT, 2, P->unitK, batched, P->wy, nullptr, 0, nullptr, nullptr, nullptr,
-                    nullptr, nullptr, 0.f, nullptr, nullptr, x_in, x_out, xbar, P->ct,
-                    static_cast<float>(P->tau1[0]), P->di.tau1, P->di.rho, P->var_inst, ctr);
+                    nullptr, nullptr, 0.f, nullptr, nullptr, x_in, x_out, xbar, P->ct, tau1,
+                    P->di.tau1, P->di.rho, P->var_inst, ctr);
     } else if (slices > 1) {
         launch_spmv_part(s, lpr, P->unitK, static_cast<int>(P->n), slices, P->rpST, P->ciST,
                          P->valST, P->wy, P->spart);
         launch_primal_combine(s, batched, static_cast<int>(P->n), slices, P->spart, x_in, x_out,
-                              xbar, P->ct, static_cast<float>(P->tau1[0]), P->di.tau1, P->di.rho,
-                              P->var_inst, ctr);
+                              xbar, P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst, ctr, xbits);
+        xbar_bits = xbits != nullptr;
     } else {
         launch_primal(s, lpr, kmode, P->hasQ, batched, static_cast<int>(P->n), P->rpT, P->ciT,
-                      P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct,
-                      static_cast<float>(P->tau1[0]),
+                      P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct, tau1,
                       static_cast<float>(P->s_o[0] > 0 ? 2.0 / P->s_o[0] : 2.0), P->di.tau1,
                       P->di.two_so, P->di.rho, P->var_inst, ctr);
     }
+    // the problem's xbar changed: its bitmap is current only if written with it
+    if (xbar == P->xbar) P->bx_fresh = xbar_bits;
 }
 
-// Zero-operand skipping variants.  bits = 1: sliced SELL dual with the slice
-// bitmap in LDS, or fused-CSR primal with the dual bitmap in LDS; bits = 2:
-// k_sell_bits on any SELL copy (batched load issue).  Each needs its bitmap to
-// fit in LDS.
 static int bits_ok_dual(gfors_problem *P, int slices, int sell, int bits) {
     if (bits == 0) return 1;
     if (!sell) return 0;
@@ -1100,6 +1118,7 @@ static int autotune(gfors_problem *P) {
     };
     const int lprs[] = {1, 2, 4, 8, 16, 32, 64};
     P->cfg.bits_dual = P->cfg.bits_primal = 0;
+    P->bx_fresh = P->by_fresh = false;
     if (P->m > 0) {
         float best = 1e30f;
         auto consider = [&](int l, int sl, int se) {
@@ -1165,6 +1184,8 @@ static int autotune(gfors_problem *P) {
 
 static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *tm = nullptr) {
     hipStream_t s = P->stream;
+    // a sequence never relies on bitmaps written before it
+    P->bx_fresh = P->by_fresh = false;
     const bool batched = P->T > 1;
     const int kmode = P->m == 0 ? 0 : (P->unitK ? 1 : 2);
     for (int it = 0; it < nsteps; ++it) {

@@ -94,11 +94,12 @@ void launch_spmv_part(hipStream_t s, int lpr, bool unit, int nrows, int P, const
                       const int *ci, const int *val, const float *v, float *part);
 void launch_dual_combine(hipStream_t s, bool batched, int m, int m1, int P, const float *part,
                          const float *omega, const float *rt, const float *y_in, float *y_out,
-                         float *wy, float tau2, const float *tau2_inst, const int *row_inst);
+                         float *wy, float tau2, const float *tau2_inst, const int *row_inst,
+                         uint64_t *wybits);
 void launch_primal_combine(hipStream_t s, bool batched, int n, int P, const float *part,
                            const float *x_in, float *x_out, float *xbar, const float *ct,
                            float tau1, const float *tau1_inst, const double *rho,
-                           const int *var_inst, DevCounters *ctr);
+                           const int *var_inst, DevCounters *ctr, uint64_t *xbits);
 
 void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool batched,
                  const float *v, float *part, int m1, const float *omega, const float *rt,
@@ -122,7 +123,7 @@ void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, 
                         const int *rpT, const int *ciT, const int *valT, const float *wy,
                         const uint32_t *bits, const float *x_in, float *x_out, float *xbar,
                         const float *ct, float tau1, const float *tau1_inst, const double *rho,
-                        const int *var_inst, DevCounters *ctr);
+                        const int *var_inst, DevCounters *ctr, uint64_t *xbits);
 
 void launch_copy_f32(hipStream_t s, float *dst, const float *src, int64_t n);
 void launch_set_xbar(hipStream_t s, int64_t n, const float *x, const float *xp, float *xbar);

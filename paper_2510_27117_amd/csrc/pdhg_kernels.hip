@@ -225,18 +225,28 @@ __global__ void __launch_bounds__(256)
 k_dual_combine(int m, int m1, int P, const float *__restrict__ part,
                const float *__restrict__ omega, const float *__restrict__ rt,
                const float *__restrict__ y_in, float *__restrict__ y_out, float *__restrict__ wy,
-               float tau2, const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
+               float tau2, const float *__restrict__ tau2_inst, const int *__restrict__ row_inst,
+               uint64_t *__restrict__ wybits) {
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= m) return;
-    float s = 0.f;
-    for (int q = 0; q < P; ++q) s += part[static_cast<int64_t>(q) * m + row];
-    const float om = omega[row];
-    const float t = rt[row] - om * s;
-    const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
-    float y = y_in[row] + ta * t;
-    if (row < m1) y = fmaxf(y, 0.f);
-    y_out[row] = y;
-    wy[row] = om * y;
+    float w = 0.f;
+    if (row < m) {
+        float s = 0.f;
+        for (int q = 0; q < P; ++q) s += part[static_cast<int64_t>(q) * m + row];
+        const float om = omega[row];
+        const float t = rt[row] - om * s;
+        const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
+        float y = y_in[row] + ta * t;
+        if (row < m1) y = fmaxf(y, 0.f);
+        y_out[row] = y;
+        w = om * y;
+        wy[row] = w;
+    }
+    // nonzero bitmap of wy for the next primal step: a wavefront holds 64
+    // consecutive rows (64-aligned)
+    if (wybits) {
+        const uint64_t b = __ballot(row < m && w != 0.f);
+        if ((threadIdx.x & 63) == 0 && row < m) wybits[row >> 6] = b;
+    }
 }
 
 template <bool BATCH>
@@ -244,20 +254,28 @@ __global__ void __launch_bounds__(256)
 k_primal_combine(int n, int P, const float *__restrict__ part, const float *__restrict__ x_in,
                  float *__restrict__ x_out, float *__restrict__ xbar, const float *__restrict__ ct,
                  float tau1, const float *__restrict__ tau1_inst, const double *__restrict__ rho,
-                 const int *__restrict__ var_inst, DevCounters *__restrict__ ctr) {
+                 const int *__restrict__ var_inst, DevCounters *__restrict__ ctr,
+                 uint64_t *__restrict__ xbits) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) ctr->k += 1;
-    if (i >= n) return;
-    const int t = BATCH ? var_inst[i] : 0;
-    const float xi = x_in[i];
-    float s1 = 0.f;
-    for (int q = 0; q < P; ++q) s1 += part[static_cast<int64_t>(q) * n + i];
-    const float rh = static_cast<float>(rho[t]);
-    const float ta = BATCH ? tau1_inst[t] : tau1;
-    const float g = ct[i] + rh - s1 - 2.f * rh * xi;
-    const float xn = fminf(fmaxf(xi - ta * g, 0.f), 1.f);
-    x_out[i] = xn;
-    xbar[i] = 2.f * xn - xi;
+    float xb = 0.f;
+    if (i < n) {
+        const int t = BATCH ? var_inst[i] : 0;
+        const float xi = x_in[i];
+        float s1 = 0.f;
+        for (int q = 0; q < P; ++q) s1 += part[static_cast<int64_t>(q) * n + i];
+        const float rh = static_cast<float>(rho[t]);
+        const float ta = BATCH ? tau1_inst[t] : tau1;
+        const float g = ct[i] + rh - s1 - 2.f * rh * xi;
+        const float xn = fminf(fmaxf(xi - ta * g, 0.f), 1.f);
+        x_out[i] = xn;
+        xb = 2.f * xn - xi;
+        xbar[i] = xb;
+    }
+    if (xbits) {
+        const uint64_t b = __ballot(i < n && xb != 0.f);
+        if ((threadIdx.x & 63) == 0 && i < n) xbits[i >> 6] = b;
+    }
 }
 
 template <int LPR>
@@ -283,21 +301,22 @@ void launch_spmv_part(hipStream_t s, int lpr, bool unit, int nrows, int P, const
 
 void launch_dual_combine(hipStream_t s, bool batched, int m, int m1, int P, const float *part,
                          const float *omega, const float *rt, const float *y_in, float *y_out,
-                         float *wy, float tau2, const float *tau2_inst, const int *row_inst) {
+                         float *wy, float tau2, const float *tau2_inst, const int *row_inst,
+                         uint64_t *wybits) {
     const int blocks = (m + 255) / 256;
     if (!blocks) return;
-    if (batched) k_dual_combine<true><<<blocks, 256, 0, s>>>(m, m1, P, part, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst);
-    else k_dual_combine<false><<<blocks, 256, 0, s>>>(m, m1, P, part, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst);
+    if (batched) k_dual_combine<true><<<blocks, 256, 0, s>>>(m, m1, P, part, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, wybits);
+    else k_dual_combine<false><<<blocks, 256, 0, s>>>(m, m1, P, part, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, wybits);
 }
 
 void launch_primal_combine(hipStream_t s, bool batched, int n, int P, const float *part,
                            const float *x_in, float *x_out, float *xbar, const float *ct,
                            float tau1, const float *tau1_inst, const double *rho,
-                           const int *var_inst, DevCounters *ctr) {
+                           const int *var_inst, DevCounters *ctr, uint64_t *xbits) {
     const int blocks = (n + 255) / 256;
     if (!blocks) return;
-    if (batched) k_primal_combine<true><<<blocks, 256, 0, s>>>(n, P, part, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr);
-    else k_primal_combine<false><<<blocks, 256, 0, s>>>(n, P, part, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr);
+    if (batched) k_primal_combine<true><<<blocks, 256, 0, s>>>(n, P, part, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr, xbits);
+    else k_primal_combine<false><<<blocks, 256, 0, s>>>(n, P, part, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr, xbits);
 }
 
 // ---------------------------------------------------------------------------
@@ -412,6 +431,23 @@ void launch_nzbits(hipStream_t s, const float *v, int64_t n, int64_t nwords64, u
     if (blocks > 0) k_nzbits<<<static_cast<int>(blocks), 256, 0, s>>>(v, n, nwords64, bits);
 }
 
+// Copy nw bitmap words into LDS: 8 independent loads per thread are issued
+// before any of them is waited for (the address of an out-of-range slot is
+// clamped to the last word; its value is not stored).
+__device__ __forceinline__ void load_bitmap_lds(uint32_t *sb, const uint32_t *__restrict__ src,
+                                                int nw) {
+    for (int w0 = threadIdx.x; w0 < nw; w0 += 8 * blockDim.x) {
+        uint32_t t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = src[min(w0 + u * static_cast<int>(blockDim.x), nw - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int w = w0 + u * static_cast<int>(blockDim.x);
+            if (w < nw) sb[w] = t[u];
+        }
+    }
+}
+
 // Sliced SELL partial SpMV with the slice's bitmap in LDS (persistent: G
 // workgroups per slice loop over the slice's chunks).
 template <bool UNIT>
@@ -426,7 +462,7 @@ k_sell_part_bits(int nrows, int P, int nchunk, int ns, int ncols, int G,
     const int gb = blockIdx.x / P;
     const int base = sl * ns;
     const int nw = ns >> 5;
-    for (int w = threadIdx.x; w < nw; w += blockDim.x) sb[w] = bits[(base >> 5) + w];
+    load_bitmap_lds(sb, bits + (base >> 5), nw);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwv = blockDim.x >> 6;
@@ -485,73 +521,106 @@ k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *_
     const int gb = blockIdx.x / P;
     const int base = sl * ns;
     const int nw = ns >> 5;
-    for (int w = threadIdx.x; w < nw; w += blockDim.x) sb[w] = bits[(base >> 5) + w];
+    load_bitmap_lds(sb, bits + (base >> 5), nw);
     if (MODE == 2 && blockIdx.x == 0 && threadIdx.x == 0) ctr->k += 1;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwv = blockDim.x >> 6;
     const int64_t pb = static_cast<int64_t>(sl) * (nchunk + 1);
-    for (int c = gb * nwv + wave; c < nchunk; c += G * nwv) {
-        const int e0 = ptr[pb + c];
-        const int L = (ptr[pb + c + 1] - e0) >> 6;
-        const int *cic = ci + e0 + lane;
-        const int *vc = val + e0 + lane;
-        const int row = row_of[(static_cast<int64_t>(sl) * nchunk + c) * 64 + lane];
-        float acc = 0.f;
-        for (int k0 = 0; k0 < L; k0 += 8) {
-            int col[8];
+    const int stride = G * nwv;
+    // Two chunks per pass (c and c + stride), so that a wavefront has twice
+    // as many independent loads in flight.  Each chunk's terms are still
+    // added in its own order.  Branch-free: slots past a chunk's end load
+    // (clamped) entry L-1 and are masked; the bitmap word is read for every
+    // slot (index clamped into the slice); a zero operand gathers the padding
+    // element v[ncols] instead, one address shared by the wavefront (one cache
+    // line, no extra L2 traffic), and its term is not added.
+    for (int c0 = gb * nwv + wave; c0 < nchunk; c0 += 2 * stride) {
+        int cc[2], e0[2], L[2], row[2];
+        float acc[2] = {0.f, 0.f};
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                col[u] = k0 + u < L ? __builtin_nontemporal_load(cic + 64 * (k0 + u)) : ncols;
-            int a[8];
-            if (!UNIT) {
+        for (int h = 0; h < 2; ++h) {
+            cc[h] = c0 + h * stride;
+            const bool live = cc[h] < nchunk;
+            const int cx = live ? cc[h] : c0;
+            e0[h] = ptr[pb + cx];
+            L[h] = live ? (ptr[pb + cx + 1] - e0[h]) >> 6 : 0;
+            row[h] = live ? row_of[(static_cast<int64_t>(sl) * nchunk + cx) * 64 + lane] : -1;
+        }
+        const int Lm = max(L[0], L[1]);
+        for (int k0 = 0; k0 < Lm; k0 += 8) {
+            int col[2][8];
+            int a[2][8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    a[u] = k0 + u < L ? __builtin_nontemporal_load(vc + 64 * (k0 + u)) : 0;
+            for (int h = 0; h < 2; ++h) {
+                if (k0 < L[h]) {                   // uniform across the wavefront
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int k = min(k0 + u, L[h] - 1);
+                        const int cv = __builtin_nontemporal_load(ci + e0[h] + lane + 64 * k);
+                        col[h][u] = k0 + u < L[h] ? cv : ncols;
+                        a[h][u] = UNIT ? 0 : __builtin_nontemporal_load(val + e0[h] + lane + 64 * k);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        col[h][u] = ncols;
+                        a[h][u] = 0;
+                    }
+                }
             }
-            bool nz[8];
+            bool nz[2][8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                // padding (col = ncols) and anything outside the slice read word 0
-                const int loc = col[u] - base;
-                const bool in = col[u] < ncols && static_cast<unsigned>(loc) < static_cast<unsigned>(ns);
-                const int li = in ? loc : 0;
-                nz[u] = in && ((sb[li >> 5] >> (li & 31)) & 1u);
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int loc = col[h][u] - base;
+                    const bool in = (col[h][u] < ncols) & (static_cast<unsigned>(loc) < static_cast<unsigned>(ns));
+                    const int li = in ? loc : 0;
+                    const uint32_t word = sb[li >> 5];
+                    nz[h][u] = in & (((word >> (li & 31)) & 1u) != 0u);
+                }
             }
-            float g[8];
+            float g[2][8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                g[u] = 0.f;
-                if (nz[u]) g[u] = v[col[u]];
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) g[h][u] = v[nz[h][u] ? col[h][u] : ncols];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (nz[u]) {
-                    if (UNIT) acc += g[u];
-                    else acc = fmaf(static_cast<float>(a[u]), g[u], acc);
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float t = UNIT ? acc[h] + g[h][u] : fmaf(static_cast<float>(a[h][u]), g[h][u], acc[h]);
+                    acc[h] = nz[h][u] ? t : acc[h];
                 }
             }
         }
-        if (row < 0) continue;
-        if (MODE == 0) {
-            part[static_cast<int64_t>(sl) * nrows + row] = acc;
-        } else if (MODE == 1) {
-            const float om = omega[row];
-            const float t = rt[row] - om * acc;
-            const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
-            float y = y_in[row] + ta * t;
-            if (row < m1) y = fmaxf(y, 0.f);
-            y_out[row] = y;
-            wy[row] = om * y;
-        } else {
-            const int t = BATCH ? var_inst[row] : 0;
-            const float xi = x_in[row];
-            const float rh = static_cast<float>(rho[t]);
-            const float ta = BATCH ? tau1_inst[t] : tau1;
-            const float gr = ct[row] + rh - acc - 2.f * rh * xi;
-            const float xn = fminf(fmaxf(xi - ta * gr, 0.f), 1.f);
-            x_out[row] = xn;
-            xbar[row] = 2.f * xn - xi;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = row[h];
+            if (r < 0) continue;
+            const float sum = acc[h];
+            if (MODE == 0) {
+                part[static_cast<int64_t>(sl) * nrows + r] = sum;
+            } else if (MODE == 1) {
+                const float om = omega[r];
+                const float t = rt[r] - om * sum;
+                const float ta = BATCH ? tau2_inst[row_inst[r]] : tau2;
+                float y = y_in[r] + ta * t;
+                if (r < m1) y = fmaxf(y, 0.f);
+                y_out[r] = y;
+                wy[r] = om * y;
+            } else {
+                const int t = BATCH ? var_inst[r] : 0;
+                const float xi = x_in[r];
+                const float rh = static_cast<float>(rho[t]);
+                const float ta = BATCH ? tau1_inst[t] : tau1;
+                const float gr = ct[r] + rh - sum - 2.f * rh * xi;
+                const float xn = fminf(fmaxf(xi - ta * gr, 0.f), 1.f);
+                x_out[r] = xn;
+                xbar[r] = 2.f * xn - xi;
+            }
         }
     }
 }
@@ -598,10 +667,11 @@ k_primal_bits(int n, int m, int nvb, const int *__restrict__ rpT, const int *__r
               const uint32_t *__restrict__ bits, const float *__restrict__ x_in,
               float *__restrict__ x_out, float *__restrict__ xbar, const float *__restrict__ ct,
               float tau1, const float *__restrict__ tau1_inst, const double *__restrict__ rho,
-              const int *__restrict__ var_inst, DevCounters *__restrict__ ctr) {
+              const int *__restrict__ var_inst, DevCounters *__restrict__ ctr,
+              uint64_t *__restrict__ xbits) {
     extern __shared__ uint32_t sb[];
     const int nw = (m + 31) >> 5;
-    for (int w = threadIdx.x; w < nw; w += blockDim.x) sb[w] = bits[w];
+    load_bitmap_lds(sb, bits, nw);
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->k += 1;
     for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
@@ -615,22 +685,63 @@ k_primal_bits(int n, int m, int nvb, const int *__restrict__ rpT, const int *__r
             cti = ct[i];
             if (BATCH) t = var_inst[i];
             const int e1 = rpT[i + 1];
-            for (int e = rpT[i] + sub; e < e1; e += LPR) {
-                const int j = ciT[e];
-                if ((sb[j >> 5] >> (j & 31)) & 1u) {
-                    if (UNIT) s1 += wy[j];
-                    else s1 = fmaf(static_cast<float>(valT[e]), wy[j], s1);
+            // batches of 4 entries per lane, branch-free: row indices first,
+            // then their bits, then the gathers of the nonzero operands (a
+            // zero operand reads the padding element wy[m], shared by the
+            // wavefront); terms are added in entry order
+            for (int eb = rpT[i] + sub; eb < e1; eb += 4 * LPR) {
+                int j[4], a[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = eb + u * LPR;
+                    const int ec = min(e, e1 - 1);
+                    const int jj = ciT[ec];
+                    j[u] = e < e1 ? jj : m;
+                    a[u] = UNIT ? 1 : valT[ec];
+                }
+                bool nz[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int jc = j[u] < m ? j[u] : 0;
+                    nz[u] = (j[u] < m) & (((sb[jc >> 5] >> (jc & 31)) & 1u) != 0u);
+                }
+                float g[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) g[u] = wy[nz[u] ? j[u] : m];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float tt = UNIT ? s1 + g[u] : fmaf(static_cast<float>(a[u]), g[u], s1);
+                    s1 = nz[u] ? tt : s1;
                 }
             }
         }
         s1 = group_sum<LPR>(s1);
+        float xb = 0.f;
         if (i < n && sub == 0) {
             const float rh = static_cast<float>(rho[t]);
             const float ta = BATCH ? tau1_inst[t] : tau1;
             const float g = cti + rh - s1 - 2.f * rh * xi;
             const float xn = fminf(fmaxf(xi - ta * g, 0.f), 1.f);
             x_out[i] = xn;
-            xbar[i] = 2.f * xn - xi;
+            xb = 2.f * xn - xi;
+            xbar[i] = xb;
+        }
+        // nonzero bitmap of xbar for the next dual step: the wavefront's 64/LPR
+        // consecutive variables (variable i0 + l sits in lane l * LPR) become
+        // 64/LPR bits, stored as whole bytes at bit offset i0
+        if (LPR <= 8 && xbits) {
+            constexpr int VW = 64 / LPR;
+            const int lane = threadIdx.x & 63;
+            const float vv = __shfl(xb, (lane % VW) * LPR, 64);
+            const uint64_t bal = __ballot(lane < VW && vv != 0.f);
+            const int64_t i0 = (static_cast<int64_t>(vb) * 1024 + (threadIdx.x & ~63)) / LPR;
+            if (lane == 0 && i0 < n) {
+                uint8_t *dst = reinterpret_cast<uint8_t *>(xbits) + (i0 >> 3);
+                if (VW == 64) *reinterpret_cast<uint64_t *>(dst) = bal;
+                else if (VW == 32) *reinterpret_cast<uint32_t *>(dst) = static_cast<uint32_t>(bal);
+                else if (VW == 16) *reinterpret_cast<uint16_t *>(dst) = static_cast<uint16_t>(bal);
+                else *dst = static_cast<uint8_t>(bal);
+            }
         }
     }
 }
@@ -640,13 +751,14 @@ static void primal_bits_lpr(hipStream_t s, bool unit, bool batched, int n, int m
                             const int *rpT, const int *ciT, const int *valT, const float *wy,
                             const uint32_t *bits, const float *x_in, float *x_out, float *xbar,
                             const float *ct, float tau1, const float *tau1_inst,
-                            const double *rho, const int *var_inst, DevCounters *ctr) {
+                            const double *rho, const int *var_inst, DevCounters *ctr,
+                            uint64_t *xbits) {
     const int64_t nvb64 = (static_cast<int64_t>(n) * LPR + 1023) / 1024;
     const int nvb = static_cast<int>(nvb64);
     const int grid = nvb < 512 ? nvb : 512;   // two 16-wave workgroups per CU
     const size_t lds = static_cast<size_t>((m + 31) / 32) * 4;
     if (grid <= 0) return;
-#define GF_PB(U, B) k_primal_bits<LPR, U, B><<<grid, 1024, lds, s>>>(n, m, nvb, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
+#define GF_PB(U, B) k_primal_bits<LPR, U, B><<<grid, 1024, lds, s>>>(n, m, nvb, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr, xbits)
     if (unit) { if (batched) GF_PB(true, true); else GF_PB(true, false); }
     else { if (batched) GF_PB(false, true); else GF_PB(false, false); }
 #undef GF_PB
@@ -656,9 +768,9 @@ void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, 
                         const int *rpT, const int *ciT, const int *valT, const float *wy,
                         const uint32_t *bits, const float *x_in, float *x_out, float *xbar,
                         const float *ct, float tau1, const float *tau1_inst, const double *rho,
-                        const int *var_inst, DevCounters *ctr) {
+                        const int *var_inst, DevCounters *ctr, uint64_t *xbits) {
     switch (lpr) {
-#define GF_CASE(L) case L: primal_bits_lpr<L>(s, unit, batched, n, m, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr); break;
+#define GF_CASE(L) case L: primal_bits_lpr<L>(s, unit, batched, n, m, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr, xbits); break;
         GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
 #undef GF_CASE
         default: break;

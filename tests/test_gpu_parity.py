@@ -431,3 +431,36 @@ def test_batched_issue_bitmap_kernels_equal_plain_sell(G):
         assert np.array_equal(out[0]["x"], out[1]["x"]) and np.array_equal(out[0]["y"], out[1]["y"]), bits
         assert rel_inf(out[1]["x"], ref.x) <= TOL_PDHG and rel_inf(out[1]["y"], ref.y) <= TOL_PDHG, bits
     prob.close()
+
+
+def test_fused_bitmaps_over_many_steps(G):
+    """The primal kernel writes the nonzero bitmap of xbar and the dual combine
+    the bitmap of wy, which the next step's zero-skipping kernels read.  Over
+    20 steps (one enqueued sequence) the zero-skipping dual equals the plain
+    SELL dual exactly with the same primal, and the fully zero-skipping
+    configuration stays with the plain fused-CSR configuration."""
+    P = I.set_cover_columns(600_000, 60_000, 5, seed=3)
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=61, keep_every=60)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    prob = G.Problem(P, _params(G, autotune=0))
+
+    def run(cfg, steps=20):
+        prob.set_launch_cfg(*cfg)
+        prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+        prob.pdhg_steps(steps)
+        return prob.get_state()
+
+    a = run((1, 2, 8, 1, 1, 0, 0, 1))
+    b = run((1, 2, 8, 1, 1, 0, 2, 1))
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+    c = run((16, 2, 1, 1, 0, 0, 0, 0))
+    for cfg in [(1, 2, 8, 1, 1, 0, 2, 1), (1, 4, 8, 1, 1, 0, 2, 1), (1, 8, 8, 1, 1, 0, 2, 1),
+                (1, 16, 8, 1, 1, 0, 2, 1), (1, 1, 8, 1, 1, 1, 2, 2), (1, 2, 8, 8, 1, 0, 2, 0)]:
+        try:
+            d = run(cfg)
+        except G.GforsError:
+            assert cfg[3] == 8       # the sliced primal copy may not exist here
+            continue
+        assert rel_inf(d["x"], c["x"]) <= 1e-4 and rel_inf(d["y"], c["y"]) <= 1e-4, cfg
+    prob.close()
