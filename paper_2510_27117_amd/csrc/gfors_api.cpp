@@ -120,7 +120,9 @@ struct gfors_problem {
     Tiles st, et, qt, vt, rtile;
     int *cover_ids = nullptr, *general_ids = nullptr;
     int n_cover = 0, n_general = 0;
+    bool general_long = false;   // general rows average >= 256 entries: split rows over wavefronts
     int *rows = nullptr;
+    int *dual_order = nullptr;   // constraint rows, longest first (block-per-row dual)
     double *pv = nullptr, *pu = nullptr, *pw = nullptr, *part = nullptr, *res = nullptr;
     double *dnorm = nullptr;
     // column-sliced copies for the XCD-sliced SpMV (see k_spmv_part)
@@ -329,6 +331,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->viol = cv.take<int32_t>(static_cast<int64_t>(T) * prm->K_max);
     P->z = cv.take<int64_t>(static_cast<int64_t>(T) * prm->K_max);
     P->rows = cv.take<int>(m);
+    P->dual_order = cv.take<int>(m);
     P->cover_ids = cv.take<int>(b.et);
     P->general_ids = cv.take<int>(b.et);
     P->pv = cv.take<double>(n);
@@ -635,6 +638,12 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     }
     P->n_cover = static_cast<int>(cover_ids.size());
     P->n_general = static_cast<int>(general_ids.size());
+    {
+        int64_t grows = 0, gnnz = 0;
+        for (int64_t j = 0; j < m; ++j)
+            if (cls[j] != kCover) { ++grows; gnnz += rp[j + 1] - rp[j]; }
+        P->general_long = grows > 0 && gnnz >= 256 * grows;
+    }
 
     // ---- carve the workspace
     Carver cv{static_cast<char *>(ws), 0, ws_bytes};
@@ -783,6 +792,13 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     if ((rc = upload(s, P->rows, rows_list.data(), m))) return rc;
     if ((rc = upload(s, P->cover_ids, cover_ids.data(), P->n_cover))) return rc;
     if ((rc = upload(s, P->general_ids, general_ids.data(), P->n_general))) return rc;
+    {
+        std::vector<int> ord(m);
+        for (int64_t j = 0; j < m; ++j) ord[j] = static_cast<int>(j);
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int a, int b2) { return rp[a + 1] - rp[a] > rp[b2 + 1] - rp[b2]; });
+        if ((rc = upload(s, P->dual_order, ord.data(), m))) return rc;
+    }
     if ((rc = upload(s, P->rowinv_d, P->rowinv.data(), m))) return rc;
     {
         std::vector<double> r2(m);
@@ -1028,6 +1044,10 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
         launch_spmv_part(s, lpr, P->unitK, m, slices, P->rpS, P->ciS, P->valS, P->xbar, P->spart);
         combine();
         wy_bits = true;
+    } else if (lpr == kLprBlock) {
+        launch_dual_long(s, P->unitK, batched, m, m1, P->dual_order, P->rp, P->ci, P->val,
+                         P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2, P->di.tau2,
+                         P->row_inst);
     } else {
         launch_dual(s, lpr, P->unitK, batched, m, m1, P->rp, P->ci, P->val, P->omega, P->rt,
                     P->xbar, y_in, y_out, P->wy, tau2, P->di.tau2, P->row_inst);
@@ -1134,6 +1154,7 @@ static int autotune(gfors_problem *P) {
         }
         if (P->sellK.ptr) consider(1, 1, 1);
         if (P->sellKS.ptr) consider(1, kXcdSlices, 1);
+        if (P->nnzK >= 512 * P->m) consider(kLprBlock, 1, 0);   // long rows: a workgroup per row
         // zero-operand skipping: each variant is kept only when it is faster
         int best_bits = 0;
         for (int b : {1, 2}) {
@@ -1239,7 +1260,7 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     TB(4);
     launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
                         P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X, W,
-                        P->vpart, K);
+                        P->vpart, K, P->general_long);
     TE(4);
     TB(5);
     if (P->hasQ) launch_eval_quad(s, P->qt, P->d_inst_var0, P->rpQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K);
@@ -1506,7 +1527,9 @@ int gfors_get_launch_cfg(gfors_problem *P, int32_t *out) {
 int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
     if (!P || !cfg) return fail(GFORS_E_ARG, "bad argument");
     auto pow2 = [](int v) { return v >= 1 && v <= 64 && (v & (v - 1)) == 0; };
-    if (!pow2(cfg[0]) || !pow2(cfg[1])) return fail(GFORS_E_ARG, "lanes per row must be a power of two in [1, 64]");
+    const bool block_dual = cfg[0] == kLprBlock && cfg[2] == 1 && cfg[4] == 0 && cfg[6] == 0;
+    if ((!pow2(cfg[0]) && !block_dual) || !pow2(cfg[1]))
+        return fail(GFORS_E_ARG, "lanes per row must be a power of two in [1, 64] (dual: or 256, a workgroup per row, fused CSR only)");
     if (cfg[2] != 1 && !(cfg[2] == kXcdSlices && (P->slicedK || P->sellKS.ptr) && cfg[0] <= 16))
         return fail(GFORS_E_ARG, "dual slices must be 1, or 8 when the sliced copy exists (lanes <= 16)");
     if (cfg[3] != 1 && !(cfg[3] == kXcdSlices && P->slicedT && !P->hasQ && cfg[1] <= 16))

@@ -76,6 +76,7 @@ struct SellView {
 };
 
 constexpr int kXcdSlices = 8;   // XCDs per MI355X
+constexpr int kLprBlock = 256;  // dual launch shape "a workgroup of 256 lanes per row"
 
 // ------------------------------------------------------------------ PDHG
 void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
@@ -109,6 +110,10 @@ void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool ba
                  const int *var_inst, DevCounters *ctr);
 
 void launch_nzbits(hipStream_t s, const float *v, int64_t n, int64_t nwords64, uint64_t *bits);
+void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, const int *order,
+                      const int *rp, const int *ci, const int *val, const float *omega,
+                      const float *rt, const float *xbar, const float *y_in, float *y_out,
+                      float *wy, float tau2, const float *tau2_inst, const int *row_inst);
 void launch_sell_bits(hipStream_t s, const SellView &sv, int mode, bool unit, bool batched,
                       int ncols, const float *v, const uint32_t *bits, float *part, int m1,
                       const float *omega, const float *rt, const float *y_in, float *y_out,
@@ -159,7 +164,7 @@ void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Til
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,
-                         int W, int *vpart, int K);
+                         int W, int *vpart, int K, bool long_rows);
 void launch_eval_quad(hipStream_t s, const Tiles &qt, const int64_t *inst_var0,
                       const int *rpQ, const int *ciQ, const int *valQ, const uint64_t *X,
                       int W, int64_t *zqpart, int K);

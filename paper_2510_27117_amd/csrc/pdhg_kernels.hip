@@ -55,6 +55,66 @@ k_dual(int m, int m1, const int *__restrict__ rp, const int *__restrict__ ci,
     }
 }
 
+// Dual step for long rows: a workgroup of 256 lanes per row (rows taken
+// longest first from `order`, so that the longest rows do not trail), lanes
+// strided over the row with four independent loads in flight each, partial
+// sums combined by shuffles inside each wavefront and then across the four
+// wavefronts in a fixed order.
+template <bool UNIT, bool BATCH>
+__global__ void __launch_bounds__(256)
+k_dual_long(int m1, const int *__restrict__ order, const int *__restrict__ rp,
+            const int *__restrict__ ci, const int *__restrict__ val,
+            const float *__restrict__ omega, const float *__restrict__ rt,
+            const float *__restrict__ xbar, const float *__restrict__ y_in,
+            float *__restrict__ y_out, float *__restrict__ wy, float tau2,
+            const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
+    __shared__ float ws[4];
+    const int row = order[blockIdx.x];
+    const int e0 = rp[row], e1 = rp[row + 1];
+    float s = 0.f;
+    for (int eb = e0 + static_cast<int>(threadIdx.x); eb < e1; eb += 4 * 256) {
+        float xv[4];
+        int a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = min(eb + 256 * u, e1 - 1);
+            const float v = xbar[ci[e]];
+            const bool in = eb + 256 * u < e1;
+            xv[u] = in ? v : 0.f;
+            a[u] = UNIT ? 1 : (in ? val[e] : 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (UNIT) s += xv[u];
+            else s = fmaf(static_cast<float>(a[u]), xv[u], s);
+        }
+    }
+    s = group_sum<64>(s);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float tot = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+        const float om = omega[row];
+        const float t = rt[row] - om * tot;
+        const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
+        float y = y_in[row] + ta * t;
+        if (row < m1) y = fmaxf(y, 0.f);
+        y_out[row] = y;
+        wy[row] = om * y;
+    }
+}
+
+void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, const int *order,
+                      const int *rp, const int *ci, const int *val, const float *omega,
+                      const float *rt, const float *xbar, const float *y_in, float *y_out,
+                      float *wy, float tau2, const float *tau2_inst, const int *row_inst) {
+    if (m <= 0) return;
+#define GF_DL(U, B) k_dual_long<U, B><<<m, 256, 0, s>>>(m1, order, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
+    if (unit) { if (batched) GF_DL(true, true); else GF_DL(true, false); }
+    else { if (batched) GF_DL(false, true); else GF_DL(false, false); }
+#undef GF_DL
+}
+
 // ---------------------------------------------------------------------------
 // Primal step:
 //   delta_i = c~_i + rho - sum_j a_ji wy_j + (2/s_o) sum_k Q_ik x_k - 2 rho x_i

@@ -324,11 +324,102 @@ k_eval_rows_allw(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
         vpart[static_cast<int64_t>(tile) * K + l] = cnt[l];
 }
 
+// Long general rows (hundreds of entries and more): the workgroup's four
+// wavefronts split each row's entries into four contiguous quarters, each
+// wavefront adds its quarter for all W words (lane = candidate; entries in
+// groups of four, whose indices, coefficients and candidate words are uniform
+// loads issued together), and wavefront 0 adds the four partial sums (exact
+// integers) and tests the row.
+template <int WW, typename ACC>
+__global__ void __launch_bounds__(256)
+k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
+                  const int *__restrict__ tb1, const int *__restrict__ rows,
+                  const int *__restrict__ rp, const int *__restrict__ ci,
+                  const int *__restrict__ val, const int64_t *__restrict__ rhs, int m1,
+                  const uint64_t *__restrict__ X, int *__restrict__ vpart, int K) {
+    __shared__ ACC part[4][WW][64];
+    const int tile = tile_ids[blockIdx.x];
+    const int r0 = tb0[tile], r1 = tb1[tile];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sh = lane & 31;
+    const bool hi = lane >= 32;
+    int vc[WW];
+#pragma unroll
+    for (int w = 0; w < WW; ++w) vc[w] = 0;
+    for (int rr = r0; rr < r1; ++rr) {
+        const int j = rows[rr];
+        const int e0 = rp[j], len = rp[j + 1] - e0;
+        const int q0 = e0 + static_cast<int>((static_cast<int64_t>(len) * wave) / 4);
+        const int q1 = e0 + static_cast<int>((static_cast<int64_t>(len) * (wave + 1)) / 4);
+        ACC acc[WW];
+#pragma unroll
+        for (int w = 0; w < WW; ++w) acc[w] = 0;
+        int e = q0;
+        for (; e + 4 <= q1; e += 4) {
+            int c[4], a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = ci[e + u];
+                a[u] = val ? val[e + u] : 1;
+            }
+            uint64_t xw[4][WW];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w = 0; w < WW; ++w) xw[u][w] = X[static_cast<int64_t>(c[u]) * WW + w];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w = 0; w < WW; ++w) {
+                    const uint32_t half = hi ? static_cast<uint32_t>(xw[u][w] >> 32) : static_cast<uint32_t>(xw[u][w]);
+                    acc[w] += static_cast<ACC>(static_cast<int>((half >> sh) & 1u) * a[u]);
+                }
+        }
+        for (; e < q1; ++e) {
+            const int c = ci[e];
+            const int a = val ? val[e] : 1;
+#pragma unroll
+            for (int w = 0; w < WW; ++w) {
+                const uint64_t word = X[static_cast<int64_t>(c) * WW + w];
+                const uint32_t half = hi ? static_cast<uint32_t>(word >> 32) : static_cast<uint32_t>(word);
+                acc[w] += static_cast<ACC>(static_cast<int>((half >> sh) & 1u) * a);
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < WW; ++w) part[wave][w][lane] = acc[w];
+        __syncthreads();
+        if (wave == 0) {
+            const int64_t b = rhs[j];
+#pragma unroll
+            for (int w = 0; w < WW; ++w) {
+                const int64_t sum = static_cast<int64_t>(part[0][w][lane]) + part[1][w][lane] +
+                                    part[2][w][lane] + part[3][w][lane];
+                vc[w] += ((j < m1) ? (sum < b) : (sum != b)) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+    }
+    if (wave == 0) {
+#pragma unroll
+        for (int w = 0; w < WW; ++w)
+            if (64 * w + lane < K) vpart[static_cast<int64_t>(tile) * K + 64 * w + lane] = vc[w];
+    }
+}
+
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,
-                         int W, int *vpart, int K) {
+                         int W, int *vpart, int K, bool long_rows) {
     if (!ntiles) return;
+    if (long_rows && W <= 16 && (W & (W - 1)) == 0) {
+#define GF_RS(WW, ACCT) k_eval_rows_split<WW, ACCT><<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, vpart, K)
+#define GF_RSW(ACCT) switch (W) { case 1: GF_RS(1, ACCT); break; case 2: GF_RS(2, ACCT); break; \
+        case 4: GF_RS(4, ACCT); break; case 8: GF_RS(8, ACCT); break; default: GF_RS(16, ACCT); break; }
+        if (acc64) { GF_RSW(int64_t) } else { GF_RSW(int32_t) }
+#undef GF_RSW
+#undef GF_RS
+        return;
+    }
     if (W <= 16 && (W & (W - 1)) == 0) {
 #define GF_RA(WW, ACCT) k_eval_rows_allw<WW, ACCT><<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, vpart, K)
 #define GF_RAW(ACCT) switch (W) { case 1: GF_RA(1, ACCT); break; case 2: GF_RA(2, ACCT); break; \
@@ -370,10 +461,29 @@ k_eval_quad(const int *__restrict__ tinst, const int *__restrict__ tb0,
             const int xi = static_cast<int>((hw >> sh) & 1u);
             int64_t acc = 0;
             const int e1 = rpQ[i + 1];
-            for (int e = rpQ[i]; e < e1; ++e) {
+            int e = rpQ[i];
+            // entries in groups of 8: indices, coefficients and candidate words
+            // are uniform loads issued together
+            for (; e + 8 <= e1; e += 8) {
+                int c[8], q[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    c[u] = ciQ[e + u];
+                    q[u] = valQ[e + u];
+                }
+                uint64_t xw[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xw[u] = X[static_cast<int64_t>(c[u]) * W + w];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t half = hi ? static_cast<uint32_t>(xw[u] >> 32) : static_cast<uint32_t>(xw[u]);
+                    acc += ((half >> sh) & 1u) ? static_cast<int64_t>(q[u]) : 0;
+                }
+            }
+            for (; e < e1; ++e) {
                 const uint64_t word = X[static_cast<int64_t>(ciQ[e]) * W + w];
                 const uint32_t half = hi ? static_cast<uint32_t>(word >> 32) : static_cast<uint32_t>(word);
-                acc += static_cast<int64_t>(((half >> sh) & 1u) * static_cast<int64_t>(valQ[e]));
+                acc += ((half >> sh) & 1u) ? static_cast<int64_t>(valQ[e]) : 0;
             }
             z += xi ? acc : 0;
         }

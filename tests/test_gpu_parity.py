@@ -37,6 +37,7 @@ def problems():
         "setcover_bern": lambda: I.set_cover_bernoulli(1037, 301, 0.02, seed=1),
         "setcover_cols": lambda: I.set_cover_columns(5003, 997, 5, seed=2),
         "knapsack": lambda: I.knapsack_multi(777, 7, seed=3),
+        "knapsack_long": lambda: I.knapsack_multi(3001, 5, seed=9),   # dense rows of 3001
         "maxcut": lambda: I.max_cut_er(2001, 10.0, seed=4),
         "ufl": lambda: I.facility_location(7, 23, seed=5),
         "mixed": lambda: mixed_problem(150, seed=6),
@@ -134,7 +135,7 @@ def test_sampler_bit_exact_and_eval(G, K):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["setcover_bern", "knapsack", "maxcut", "ufl", "mixed"])
+@pytest.mark.parametrize("name", ["setcover_bern", "knapsack", "knapsack_long", "maxcut", "ufl", "mixed"])
 def test_round_from_iterate_and_incumbent(G, name):
     """Sample from the (oracle) iterate x_k held in the GPU state, evaluate, and
     merge into the incumbent exactly as the oracle's EvalBest does."""
@@ -463,4 +464,25 @@ def test_fused_bitmaps_over_many_steps(G):
             assert cfg[3] == 8       # the sliced primal copy may not exist here
             continue
         assert rel_inf(d["x"], c["x"]) <= 1e-4 and rel_inf(d["y"], c["y"]) <= 1e-4, cfg
+    prob.close()
+
+
+@pytest.mark.parametrize("name", ["knapsack_long", "knapsack", "mixed", "setcover_bern"])
+def test_workgroup_per_row_dual(G, name):
+    """The dual with a workgroup per row (rows longest first, four loads in
+    flight per lane) gives the teacher-forced step within tolerance, also on
+    short and empty rows."""
+    P = problems()[name]()
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=31, keep_every=30)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+    prob.set_launch_cfg(256, 4, 1, 1, 0, 0, 0, 0)
+    prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+    prob.pdhg_steps(1)
+    got = prob.get_state()
+    assert rel_inf(got["x"], ref.x) <= TOL_PDHG and rel_inf(got["y"], ref.y) <= TOL_PDHG
+    with pytest.raises(G.GforsError):
+        prob.set_launch_cfg(256, 4, 1, 1, 1, 0, 0, 0)     # not with the SELL layout
     prob.close()
