@@ -46,6 +46,8 @@ def parse():
                          "bits_primal) instead of autotuning them")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 512 MiB device copy first (scale for HBM byte counters)")
+    ap.add_argument("--ufl-eval", default="1000,10000",
+                    help="ufl_learned: facilities,customers of the evaluation instance")
     ap.add_argument("--train-instances", type=int, default=200)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--seq-sample", type=int, default=8,
@@ -197,7 +199,8 @@ def learned_experiment(a):
     t_train = time.perf_counter() - t0
     loss1 = learned.mean_loss(net, samples[:64])
 
-    full = instances.facility_location(1000, 10000, seed=a.seed)
+    nf, nc = (int(v) for v in a.ufl_eval.split(","))
+    full = instances.facility_location(nf, nc, seed=a.seed)
     tu = gfors.TUReformulation(full, full.meta["tu_pivots"])
     prm = gfors.default_params(k_int=a.k_int, K_max=a.K)
     G = gfors.Problem(tu.model, prm)
@@ -212,7 +215,7 @@ def learned_experiment(a):
     zp = [z + c0 if z != learned.INT64_MAX else None for z in plain.z]
     zl = [z + c0 if z != learned.INT64_MAX else None for z in lrn.z]
     res = {"metric": METRIC, "workload": "ufl_learned",
-           "config": {"workload": "facility location 1000 x 10000 (TU: 10k assignments eliminated)",
+           "config": {"workload": f"facility location {nf} x {nc} (TU: {nc} assignments eliminated)",
                       "n_reduced": tu.model.n, "rows": tu.model.m1,
                       "nnz": int(tu.model.A.nnz), "K": a.K, "k_int": a.k_int, "rounds": R,
                       "train": f"{a.train_instances} instances 40 x 400, {len(samples)} pairs, {a.train_steps} Adam steps"},

@@ -36,7 +36,8 @@ int fail(int code, const std::string &msg) {
 
 constexpr int kSampleTQ = 256;        // quads per sample tile (1024 variables)
 constexpr int kEvalNnz = 4096;        // nnz budget of an evaluation tile
-constexpr int kCoverRows = 128;       // rows per covering tile (max)
+constexpr int kCoverRows = 8192;      // rows per bitwise-evaluated tile (max)
+constexpr int kBitwiseNnz = 8192;     // nnz budget of a bitwise-evaluated tile
 constexpr int kGeneralRows = 4096;    // rows per general tile (max)
 constexpr int kQuadNnz = 4096;        // nnz budget of a Q tile
 constexpr int kQuadRows = 256;
@@ -61,7 +62,7 @@ Bounds tile_bounds(int64_t n, int64_t m, int64_t nnzK, int64_t nnzQ, int64_t T) 
     b.st = ceil_div(n / 4 + T, kSampleTQ) + T + 1;
     // a tile closes when its weight (nnz + rows) reaches the budget or its row
     // count reaches the cap, so tiles <= weight/budget + rows/cap + 1 per run
-    b.et = m / kCoverRows + (nnzK + m) / kEvalNnz + 4 * T + 4;
+    b.et = m / kCoverRows + (nnzK + m) / kEvalNnz + (nnzK + m) / kBitwiseNnz + 8 * T + 8;
     b.qt = n / kQuadRows + (nnzQ + n) / kQuadNnz + 2 * T + 2;
     b.vt = n / kVarTile + T + 1;
     b.rt = m / kRowRows + (nnzK + m) / kRowNnz + 4 * T + 4;
@@ -95,6 +96,7 @@ struct gfors_problem {
     // host copies
     std::vector<int64_t> inst_var0, inst_nvar;
     std::vector<double> rowinv, s_o, s_K, qnorm, tau1, tau2, rmin, rmax, rdelta;
+    std::vector<uint8_t> rkind_host;
 
     // device buffers
     int *rp = nullptr, *ci = nullptr, *val = nullptr;
@@ -122,7 +124,10 @@ struct gfors_problem {
     int n_cover = 0, n_general = 0;
     bool general_long = false;   // general rows average >= 256 entries: split rows over wavefronts
     int *rows = nullptr;
+    uint8_t *rkind = nullptr;    // per row: evaluation kind << 4 | truth table (pair rows)
     int *dual_order = nullptr;   // constraint rows, longest first (block-per-row dual)
+    int *primal_order = nullptr; // variables, most rows first (block-per-variable primal)
+    int heavy_rows = 0, heavy_cols = 0;   // rows / variables with kHeavyLen+ entries
     double *pv = nullptr, *pu = nullptr, *pw = nullptr, *part = nullptr, *res = nullptr;
     double *dnorm = nullptr;
     // column-sliced copies for the XCD-sliced SpMV (see k_spmv_part)
@@ -331,7 +336,9 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->viol = cv.take<int32_t>(static_cast<int64_t>(T) * prm->K_max);
     P->z = cv.take<int64_t>(static_cast<int64_t>(T) * prm->K_max);
     P->rows = cv.take<int>(m);
+    P->rkind = cv.take<uint8_t>(m);
     P->dual_order = cv.take<int>(m);
+    P->primal_order = cv.take<int>(n);
     P->cover_ids = cv.take<int>(b.et);
     P->general_ids = cv.take<int>(b.et);
     P->pv = cv.take<double>(n);
@@ -540,14 +547,16 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     // row norms, infeasible zero rows, classes
     P->rowinv.assign(m, 1.0);
     std::vector<uint8_t> cls(m);
+    P->rkind_host.assign(m, 0);
     for (int64_t j = 0; j < m; ++j) {
         double sq = 0.0;
         int64_t absum = 0;
-        bool allone = true;
+        bool allone = true, allneg = true;
         for (int e = rp[j]; e < rp[j + 1]; ++e) {
             sq += static_cast<double>(val[e]) * static_cast<double>(val[e]);
             absum += std::llabs(static_cast<int64_t>(val[e]));
             allone = allone && val[e] == 1;
+            allneg = allneg && val[e] == -1;
         }
         if (rp[j + 1] == rp[j]) {
             const bool bad = (j < P->m1) ? (rhs[j] > 0) : (rhs[j] != 0);
@@ -555,7 +564,28 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         }
         const double nrm = std::sqrt(sq);
         P->rowinv[j] = nrm > 0.0 ? 1.0 / nrm : 1.0;
-        cls[j] = (j < P->m1 && allone && rhs[j] == 1 && rp[j + 1] > rp[j]) ? kCover : kGeneral;
+        // rows whose violation is a bitwise function of the candidate words
+        const int64_t len = rp[j + 1] - rp[j];
+        const bool ineq = j < P->m1;
+        int kind = -1, tt = 0;
+        if (len > 0 && ineq && allone && rhs[j] == 1) kind = kEvalCover;              // sum >= 1
+        else if (len > 0 && ineq && allneg && rhs[j] == -1) kind = kEvalAtMostOne;     // sum <= 1
+        else if (len > 0 && !ineq && ((allone && rhs[j] == 1) || (allneg && rhs[j] == -1)))
+            kind = kEvalExactlyOne;                                                    // sum == 1
+        else if (len == 1 || len == 2) {
+            // truth table over (x_p, x_q), bit 2 bp + bq set when violated
+            const int64_t ap = val[rp[j]], aq = len == 2 ? val[rp[j] + 1] : 0;
+            for (int bp = 0; bp < 2; ++bp)
+                for (int bq = 0; bq < 2; ++bq) {
+                    const int bqe = len == 2 ? bq : bp;   // one entry: both read x_p
+                    const int64_t v = ap * bp + aq * bqe;
+                    const bool bad = ineq ? v < rhs[j] : v != rhs[j];
+                    if (bad) tt |= 1 << (2 * bp + bq);
+                }
+            kind = kEvalPair;
+        }
+        cls[j] = kind >= 0 ? kCover : kGeneral;
+        P->rkind_host[j] = static_cast<uint8_t>(kind >= 0 ? (kind << 4) | tt : 0);
         if (cls[j] == kGeneral && absum > 2147483647LL) P->acc64 = true;
     }
     // transpose (counting sort by column; rows ascending within a column)
@@ -609,7 +639,8 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             rows_list.insert(rows_list.end(), L.begin(), L.end());
             std::function<int64_t(int64_t)> wfun = [&](int64_t q) -> int64_t { return rp[L[q] + 1] - rp[L[q]]; };
             const size_t before = he.inst.size();
-            build_tiles_items(he, t, static_cast<int64_t>(L.size()), &wfun, kEvalNnz,
+            build_tiles_items(he, t, static_cast<int64_t>(L.size()), &wfun,
+                              k == kCover ? kBitwiseNnz : kEvalNnz,
                               k == kCover ? kCoverRows : kGeneralRows, base);
             for (size_t q = before; q < he.inst.size(); ++q)
                 (k == kCover ? cover_ids : general_ids).push_back(static_cast<int>(q));
@@ -790,6 +821,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     if ((rc = upload(s, P->d_inst_var0, P->inst_var0.data(), T))) return rc;
     if ((rc = upload(s, P->d_inst_nvar, P->inst_nvar.data(), T))) return rc;
     if ((rc = upload(s, P->rows, rows_list.data(), m))) return rc;
+    if ((rc = upload(s, P->rkind, P->rkind_host.data(), m))) return rc;
     if ((rc = upload(s, P->cover_ids, cover_ids.data(), P->n_cover))) return rc;
     if ((rc = upload(s, P->general_ids, general_ids.data(), P->n_general))) return rc;
     {
@@ -798,6 +830,15 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         std::stable_sort(ord.begin(), ord.end(),
                          [&](int a, int b2) { return rp[a + 1] - rp[a] > rp[b2 + 1] - rp[b2]; });
         if ((rc = upload(s, P->dual_order, ord.data(), m))) return rc;
+        P->heavy_rows = 0;
+        while (P->heavy_rows < m && rp[ord[P->heavy_rows] + 1] - rp[ord[P->heavy_rows]] >= kHeavyLen) ++P->heavy_rows;
+        std::vector<int> ordT(n);
+        for (int64_t i = 0; i < n; ++i) ordT[i] = static_cast<int>(i);
+        std::stable_sort(ordT.begin(), ordT.end(),
+                         [&](int a, int b2) { return rpT[a + 1] - rpT[a] > rpT[b2 + 1] - rpT[b2]; });
+        if ((rc = upload(s, P->primal_order, ordT.data(), n))) return rc;
+        P->heavy_cols = 0;
+        while (P->heavy_cols < n && rpT[ordT[P->heavy_cols] + 1] - rpT[ordT[P->heavy_cols]] >= kHeavyLen) ++P->heavy_cols;
     }
     if ((rc = upload(s, P->rowinv_d, P->rowinv.data(), m))) return rc;
     {
@@ -1044,13 +1085,20 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
         launch_spmv_part(s, lpr, P->unitK, m, slices, P->rpS, P->ciS, P->valS, P->xbar, P->spart);
         combine();
         wy_bits = true;
-    } else if (lpr == kLprBlock) {
-        launch_dual_long(s, P->unitK, batched, m, m1, P->dual_order, P->rp, P->ci, P->val,
-                         P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2, P->di.tau2,
-                         P->row_inst);
+    } else if (lpr >= kLprBlock) {
+        // a workgroup per row for all rows (256) or for the heavy rows only,
+        // the others with lpr - 256 lanes each
+        const bool all = lpr == kLprBlock;
+        launch_dual_long(s, P->unitK, batched, all ? m : P->heavy_rows, m1, P->dual_order, P->rp,
+                         P->ci, P->val, P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2,
+                         P->di.tau2, P->row_inst);
+        if (!all)
+            launch_dual(s, lpr - kLprBlock, P->unitK, batched, m, m1, P->rp, P->ci, P->val,
+                        P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2, P->di.tau2,
+                        P->row_inst, kHeavyLen);
     } else {
         launch_dual(s, lpr, P->unitK, batched, m, m1, P->rp, P->ci, P->val, P->omega, P->rt,
-                    P->xbar, y_in, y_out, P->wy, tau2, P->di.tau2, P->row_inst);
+                    P->xbar, y_in, y_out, P->wy, tau2, P->di.tau2, P->row_inst, 0);
     }
     P->by_fresh = wy_bits;
 }
@@ -1092,11 +1140,19 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
         launch_primal_combine(s, batched, static_cast<int>(P->n), slices, P->spart, x_in, x_out,
                               xbar, P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst, ctr, xbits);
         xbar_bits = xbits != nullptr;
+    } else if (lpr > kLprBlock) {
+        // heavy variables a workgroup each, the others lpr - 256 lanes (no Q)
+        launch_primal_long(s, P->unitK, batched, P->heavy_cols, P->primal_order, P->rpT, P->ciT,
+                           P->valT, P->wy, x_in, x_out, xbar, P->ct, tau1, P->di.tau1, P->di.rho,
+                           P->var_inst);
+        launch_primal(s, lpr - kLprBlock, kmode, false, batched, static_cast<int>(P->n), P->rpT,
+                      P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct,
+                      tau1, 0.f, P->di.tau1, P->di.two_so, P->di.rho, P->var_inst, ctr, kHeavyLen);
     } else {
         launch_primal(s, lpr, kmode, P->hasQ, batched, static_cast<int>(P->n), P->rpT, P->ciT,
                       P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct, tau1,
                       static_cast<float>(P->s_o[0] > 0 ? 2.0 / P->s_o[0] : 2.0), P->di.tau1,
-                      P->di.two_so, P->di.rho, P->var_inst, ctr);
+                      P->di.two_so, P->di.rho, P->var_inst, ctr, 0);
     }
     // the problem's xbar changed: its bitmap is current only if written with it
     if (xbar == P->xbar) P->bx_fresh = xbar_bits;
@@ -1155,6 +1211,8 @@ static int autotune(gfors_problem *P) {
         if (P->sellK.ptr) consider(1, 1, 1);
         if (P->sellKS.ptr) consider(1, kXcdSlices, 1);
         if (P->nnzK >= 512 * P->m) consider(kLprBlock, 1, 0);   // long rows: a workgroup per row
+        if (P->heavy_rows > 0 && P->heavy_rows < P->m)           // heavy rows apart
+            for (int l : {1, 2, 4, 8, 16}) consider(kLprBlock + l, 1, 0);
         // zero-operand skipping: each variant is kept only when it is faster
         int best_bits = 0;
         for (int b : {1, 2}) {
@@ -1182,6 +1240,8 @@ static int autotune(gfors_problem *P) {
             }
         }
         if (P->sellT.ptr) consider(1, 1, 1);
+        if (!P->hasQ && P->m > 0 && P->heavy_cols > 0 && P->heavy_cols < P->n)   // heavy variables apart
+            for (int l : {1, 2, 4, 8, 16}) consider(kLprBlock + l, 1, 0);
         int best_bits = 0;
         if (bits_ok_primal(P, 1, 0, 1)) {
             P->cfg.bits_primal = 1;
@@ -1255,7 +1315,8 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
                   static_cast<uint32_t>(P->prm.seed >> 32), P->ctr, threshold);
     TE(2);
     TB(3);
-    launch_eval_cover(s, P->n_cover, P->cover_ids, P->et, P->rows, P->rp, P->ci, P->X, W, P->vpart, K);
+    launch_eval_cover(s, P->n_cover, P->cover_ids, P->et, P->rows, P->rkind, P->rp, P->ci, P->X, W,
+                      P->vpart, K);
     TE(3);
     TB(4);
     launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
@@ -1527,9 +1588,14 @@ int gfors_get_launch_cfg(gfors_problem *P, int32_t *out) {
 int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
     if (!P || !cfg) return fail(GFORS_E_ARG, "bad argument");
     auto pow2 = [](int v) { return v >= 1 && v <= 64 && (v & (v - 1)) == 0; };
-    const bool block_dual = cfg[0] == kLprBlock && cfg[2] == 1 && cfg[4] == 0 && cfg[6] == 0;
-    if ((!pow2(cfg[0]) && !block_dual) || !pow2(cfg[1]))
-        return fail(GFORS_E_ARG, "lanes per row must be a power of two in [1, 64] (dual: or 256, a workgroup per row, fused CSR only)");
+    const bool fused_dual = cfg[2] == 1 && cfg[4] == 0 && cfg[6] == 0;
+    const bool block_dual = fused_dual && (cfg[0] == kLprBlock || pow2(cfg[0] - kLprBlock));
+    const bool block_primal = cfg[3] == 1 && cfg[5] == 0 && cfg[7] == 0 && !P->hasQ && P->m > 0 &&
+                              pow2(cfg[1] - kLprBlock);
+    if ((!pow2(cfg[0]) && !block_dual) || (!pow2(cfg[1]) && !block_primal))
+        return fail(GFORS_E_ARG, "lanes per row must be a power of two in [1, 64], or 256 (dual only) / "
+                                 "256 + a power of two (heavy rows a workgroup each) with the fused CSR "
+                                 "layout, no skipping, and for the primal Q = 0");
     if (cfg[2] != 1 && !(cfg[2] == kXcdSlices && (P->slicedK || P->sellKS.ptr) && cfg[0] <= 16))
         return fail(GFORS_E_ARG, "dual slices must be 1, or 8 when the sliced copy exists (lanes <= 16)");
     if (cfg[3] != 1 && !(cfg[3] == kXcdSlices && P->slicedT && !P->hasQ && cfg[1] <= 16))

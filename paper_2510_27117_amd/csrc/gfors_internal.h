@@ -76,20 +76,33 @@ struct SellView {
 };
 
 constexpr int kXcdSlices = 8;   // XCDs per MI355X
-constexpr int kLprBlock = 256;  // dual launch shape "a workgroup of 256 lanes per row"
+// Evaluation kinds of rows whose violation is a bitwise function of the
+// candidate words (per-row byte: kind << 4 | truth table of pair rows).
+constexpr int kEvalCover = 0;        // inequality, coefficients 1, rhs 1:  violated iff none set
+constexpr int kEvalAtMostOne = 1;    // inequality, coefficients -1, rhs -1: violated iff >= 2 set
+constexpr int kEvalExactlyOne = 2;   // equality, coefficients +-1, rhs +-1: violated iff != 1 set
+constexpr int kEvalPair = 3;         // one or two entries: truth table over (x_p, x_q)
+constexpr int kLprBlock = 256;  // launch shape "a workgroup of 256 lanes per row"; 256 + L:
+                                // rows of kHeavyLen+ entries a workgroup each, others L lanes
+constexpr int kHeavyLen = 256;
 
 // ------------------------------------------------------------------ PDHG
 void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
                  const int *rp, const int *ci, const int *val, const float *omega,
                  const float *rt, const float *xbar, const float *y_in, float *y_out,
-                 float *wy, float tau2, const float *tau2_inst, const int *row_inst);
+                 float *wy, float tau2, const float *tau2_inst, const int *row_inst,
+                 int skip_len);
 
 void launch_primal(hipStream_t s, int lpr, int kmode, bool hasq, bool batched, int n,
                    const int *rpT, const int *ciT, const int *valT, const float *wy,
                    const int *rpQ, const int *ciQ, const int *valQ, const float *x_in,
                    float *x_out, float *xbar, const float *ct, float tau1, float two_so,
                    const float *tau1_inst, const float *two_so_inst, const double *rho,
-                   const int *var_inst, DevCounters *ctr);
+                   const int *var_inst, DevCounters *ctr, int skip_len);
+void launch_primal_long(hipStream_t s, bool unit, bool batched, int count, const int *order,
+                        const int *rpT, const int *ciT, const int *valT, const float *wy,
+                        const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                        const float *tau1_inst, const double *rho, const int *var_inst);
 
 void launch_spmv_part(hipStream_t s, int lpr, bool unit, int nrows, int P, const int *rpP,
                       const int *ci, const int *val, const float *v, float *part);
@@ -159,8 +172,8 @@ void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64
                    uint32_t key1, const DevCounters *ctr, int threshold_mode);
 
 void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
-                       const int *rows, const int *rp, const int *ci, const uint64_t *X,
-                       int W, int *vpart, int K);
+                       const int *rows, const uint8_t *rkind, const int *rp, const int *ci,
+                       const uint64_t *X, int W, int *vpart, int K);
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,

@@ -30,21 +30,25 @@ k_dual(int m, int m1, const int *__restrict__ rp, const int *__restrict__ ci,
        const int *__restrict__ val, const float *__restrict__ omega,
        const float *__restrict__ rt, const float *__restrict__ xbar,
        const float *__restrict__ y_in, float *__restrict__ y_out, float *__restrict__ wy,
-       float tau2, const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
+       float tau2, const float *__restrict__ tau2_inst, const int *__restrict__ row_inst,
+       int skip_len) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = tid / LPR;
     const int sub = tid & (LPR - 1);
     float s = 0.f;
-    if (row < m) {
-        const int e1 = rp[row + 1];
-        for (int e = rp[row] + sub; e < e1; e += LPR) {
+    bool own = row < m;
+    if (own) {
+        const int e0 = rp[row], e1 = rp[row + 1];
+        // rows of skip_len entries or more belong to the workgroup-per-row kernel
+        if (skip_len > 0 && e1 - e0 >= skip_len) own = false;
+        for (int e = e0 + sub; own && e < e1; e += LPR) {
             const float xv = xbar[ci[e]];
             if (UNIT) s += xv;
             else s = fmaf(static_cast<float>(val[e]), xv, s);
         }
     }
     s = group_sum<LPR>(s);
-    if (row < m && sub == 0) {
+    if (own && sub == 0) {
         const float om = omega[row];
         const float t = rt[row] - om * s;
         const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
@@ -115,6 +119,65 @@ void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, con
 #undef GF_DL
 }
 
+// Primal step for variables in many rows (no Q): a workgroup per variable,
+// taken from `order` (most rows first), same summation structure as
+// k_dual_long.  The iteration counter is advanced by the companion kernel.
+template <bool UNIT, bool BATCH>
+__global__ void __launch_bounds__(256)
+k_primal_long(const int *__restrict__ order, const int *__restrict__ rpT,
+              const int *__restrict__ ciT, const int *__restrict__ valT,
+              const float *__restrict__ wy, const float *__restrict__ x_in,
+              float *__restrict__ x_out, float *__restrict__ xbar, const float *__restrict__ ct,
+              float tau1, const float *__restrict__ tau1_inst, const double *__restrict__ rho,
+              const int *__restrict__ var_inst) {
+    __shared__ float ws[4];
+    const int i = order[blockIdx.x];
+    const int e0 = rpT[i], e1 = rpT[i + 1];
+    float s = 0.f;
+    for (int eb = e0 + static_cast<int>(threadIdx.x); eb < e1; eb += 4 * 256) {
+        float w[4];
+        int a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = min(eb + 256 * u, e1 - 1);
+            const float v = wy[ciT[e]];
+            const bool in = eb + 256 * u < e1;
+            w[u] = in ? v : 0.f;
+            a[u] = UNIT ? 1 : (in ? valT[e] : 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (UNIT) s += w[u];
+            else s = fmaf(static_cast<float>(a[u]), w[u], s);
+        }
+    }
+    s = group_sum<64>(s);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float tot = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+        const int t = BATCH ? var_inst[i] : 0;
+        const float xi = x_in[i];
+        const float rh = static_cast<float>(rho[t]);
+        const float ta = BATCH ? tau1_inst[t] : tau1;
+        const float g = ct[i] + rh - tot - 2.f * rh * xi;
+        const float xn = fminf(fmaxf(xi - ta * g, 0.f), 1.f);
+        x_out[i] = xn;
+        xbar[i] = 2.f * xn - xi;
+    }
+}
+
+void launch_primal_long(hipStream_t s, bool unit, bool batched, int count, const int *order,
+                        const int *rpT, const int *ciT, const int *valT, const float *wy,
+                        const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                        const float *tau1_inst, const double *rho, const int *var_inst) {
+    if (count <= 0) return;
+#define GF_PL(U, B) k_primal_long<U, B><<<count, 256, 0, s>>>(order, rpT, ciT, valT, wy, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst)
+    if (unit) { if (batched) GF_PL(true, true); else GF_PL(true, false); }
+    else { if (batched) GF_PL(false, true); else GF_PL(false, false); }
+#undef GF_PL
+}
+
 // ---------------------------------------------------------------------------
 // Primal step:
 //   delta_i = c~_i + rho - sum_j a_ji wy_j + (2/s_o) sum_k Q_ik x_k - 2 rho x_i
@@ -132,7 +195,7 @@ k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ ciT,
          const float *__restrict__ ct, float tau1, float two_so,
          const float *__restrict__ tau1_inst, const float *__restrict__ two_so_inst,
          const double *__restrict__ rho, const int *__restrict__ var_inst,
-         DevCounters *__restrict__ ctr) {
+         DevCounters *__restrict__ ctr, int skip_len) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = tid / LPR;
     const int sub = tid & (LPR - 1);
@@ -140,12 +203,15 @@ k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ ciT,
     // per-row operands are independent of the gathers: load them first
     float xi = 0.f, cti = 0.f;
     int t = 0;
-    if (i < n) {
+    bool own = i < n;
+    // variables in skip_len or more rows belong to the workgroup-per-variable kernel
+    if (own && KMODE != 0 && skip_len > 0 && rpT[i + 1] - rpT[i] >= skip_len) own = false;
+    if (own) {
         xi = x_in[i];
         cti = ct[i];
         if (BATCH) t = var_inst[i];
     }
-    if (i < n) {
+    if (own) {
         if (KMODE != 0) {
             const int e1 = rpT[i + 1];
             for (int e = rpT[i] + sub; e < e1; e += LPR) {
@@ -162,7 +228,7 @@ k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ ciT,
     }
     if (KMODE != 0) s1 = group_sum<LPR>(s1);
     if (HASQ) s2 = group_sum<LPR>(s2);
-    if (i < n && sub == 0) {
+    if (own && sub == 0) {
         const float rh = static_cast<float>(rho[t]);
         const float ta = BATCH ? tau1_inst[t] : tau1;
         float g = cti + rh;
@@ -180,12 +246,12 @@ template <int LPR>
 static void dual_lpr(hipStream_t s, bool unit, bool batched, int m, int m1, const int *rp,
                      const int *ci, const int *val, const float *omega, const float *rt,
                      const float *xbar, const float *y_in, float *y_out, float *wy, float tau2,
-                     const float *tau2_inst, const int *row_inst) {
+                     const float *tau2_inst, const int *row_inst, int skip_len) {
     const int64_t threads = static_cast<int64_t>(m) * LPR;
     const int blocks = static_cast<int>((threads + 255) / 256);
     if (blocks == 0) return;
 #define GF_DUAL(U, B) \
-    k_dual<LPR, U, B><<<blocks, 256, 0, s>>>(m, m1, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
+    k_dual<LPR, U, B><<<blocks, 256, 0, s>>>(m, m1, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst, skip_len)
     if (unit) { if (batched) GF_DUAL(true, true); else GF_DUAL(true, false); }
     else { if (batched) GF_DUAL(false, true); else GF_DUAL(false, false); }
 #undef GF_DUAL
@@ -194,9 +260,10 @@ static void dual_lpr(hipStream_t s, bool unit, bool batched, int m, int m1, cons
 void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
                  const int *rp, const int *ci, const int *val, const float *omega,
                  const float *rt, const float *xbar, const float *y_in, float *y_out,
-                 float *wy, float tau2, const float *tau2_inst, const int *row_inst) {
+                 float *wy, float tau2, const float *tau2_inst, const int *row_inst,
+                 int skip_len) {
     switch (lpr) {
-#define GF_CASE(L) case L: dual_lpr<L>(s, unit, batched, m, m1, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst); break;
+#define GF_CASE(L) case L: dual_lpr<L>(s, unit, batched, m, m1, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst, skip_len); break;
         GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
 #undef GF_CASE
         default: break;
@@ -209,14 +276,14 @@ static void primal_k(hipStream_t s, bool batched, int n, const int *rpT, const i
                      const int *valQ, const float *x_in, float *x_out, float *xbar,
                      const float *ct, float tau1, float two_so, const float *tau1_inst,
                      const float *two_so_inst, const double *rho, const int *var_inst,
-                     DevCounters *ctr) {
+                     DevCounters *ctr, int skip_len) {
     const int64_t threads = static_cast<int64_t>(n) * LPR;
     const int blocks = static_cast<int>((threads + 255) / 256);
     if (blocks == 0) return;
     if (batched)
-        k_primal<LPR, KMODE, HASQ, true><<<blocks, 256, 0, s>>>(n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr);
+        k_primal<LPR, KMODE, HASQ, true><<<blocks, 256, 0, s>>>(n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len);
     else
-        k_primal<LPR, KMODE, HASQ, false><<<blocks, 256, 0, s>>>(n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr);
+        k_primal<LPR, KMODE, HASQ, false><<<blocks, 256, 0, s>>>(n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len);
 }
 
 template <int LPR>
@@ -225,8 +292,8 @@ static void primal_lpr(hipStream_t s, int kmode, bool hasq, bool batched, int n,
                        const int *rpQ, const int *ciQ, const int *valQ, const float *x_in,
                        float *x_out, float *xbar, const float *ct, float tau1, float two_so,
                        const float *tau1_inst, const float *two_so_inst, const double *rho,
-                       const int *var_inst, DevCounters *ctr) {
-#define GF_P(KM, HQ) primal_k<LPR, KM, HQ>(s, batched, n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr)
+                       const int *var_inst, DevCounters *ctr, int skip_len) {
+#define GF_P(KM, HQ) primal_k<LPR, KM, HQ>(s, batched, n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len)
     if (hasq) {
         if (kmode == 0) GF_P(0, true); else if (kmode == 1) GF_P(1, true); else GF_P(2, true);
     } else {
@@ -240,9 +307,9 @@ void launch_primal(hipStream_t s, int lpr, int kmode, bool hasq, bool batched, i
                    const int *rpQ, const int *ciQ, const int *valQ, const float *x_in,
                    float *x_out, float *xbar, const float *ct, float tau1, float two_so,
                    const float *tau1_inst, const float *two_so_inst, const double *rho,
-                   const int *var_inst, DevCounters *ctr) {
+                   const int *var_inst, DevCounters *ctr, int skip_len) {
     switch (lpr) {
-#define GF_CASE(L) case L: primal_lpr<L>(s, kmode, hasq, batched, n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr); break;
+#define GF_CASE(L) case L: primal_lpr<L>(s, kmode, hasq, batched, n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len); break;
         GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
 #undef GF_CASE
         default: break;

@@ -164,11 +164,18 @@ void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64
 }
 
 // ---------------------------------------------------------------------------
-// Covering rows (coefficients all 1, inequality, rhs 1): row violated by a
-// candidate iff none of its variables is set = ~OR of the words.  A group of
-// Wp (power of two >= W) lanes owns a row, lane w of the group word w.  Each
-// lane keeps per-candidate violation counts bit-sliced in 8 planes (ripple-
-// carry adds of 64-bit masks) and flushes them to LDS counters every 255 rows.
+// Rows whose violation is a bitwise function of the candidate words (64
+// candidates per word):
+//   covering     (sum x >= 1, coefficients 1):   violated = ~OR
+//   at-most-one  (-sum x >= -1):                  violated = "two or more"
+//   exactly-one  (sum x == 1, coefficients +-1):  violated = ~one | two
+//   pair         (one or two entries, any integer coefficients, >= or =):
+//                violated = the row's truth table over (x_p, x_q)
+// where one / two are the running "at least one / at least two set" masks.
+// A group of Wp (power of two >= W) lanes owns a row, lane w of the group word
+// w.  Each lane keeps per-candidate violation counts bit-sliced in 8 planes
+// (ripple-carry adds of 64-bit masks) and flushes them to LDS counters every
+// 255 rows.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void flush_planes(uint64_t (&c)[8], int *cnt, int w) {
     for (int b = 0; b < 64; ++b) {
@@ -184,8 +191,9 @@ __device__ __forceinline__ void flush_planes(uint64_t (&c)[8], int *cnt, int w) 
 __global__ void __launch_bounds__(256)
 k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
              const int *__restrict__ tb1, const int *__restrict__ rows,
-             const int *__restrict__ rp, const int *__restrict__ ci,
-             const uint64_t *__restrict__ X, int W, int lgWp, int *__restrict__ vpart, int K) {
+             const uint8_t *__restrict__ rkind, const int *__restrict__ rp,
+             const int *__restrict__ ci, const uint64_t *__restrict__ X, int W, int lgWp,
+             int *__restrict__ vpart, int K) {
     __shared__ int cnt[4096];
     const int tile = tile_ids[blockIdx.x];
     const int r0 = tb0[tile], r1 = tb1[tile];
@@ -201,10 +209,25 @@ k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
     for (int rr = r0 + grp; rr < r1; rr += ngrp) {
         if (sub < W) {
             const int j = rows[rr];
-            uint64_t acc = 0;
-            const int e1 = rp[j + 1];
-            for (int e = rp[j]; e < e1; ++e) acc |= X[static_cast<int64_t>(ci[e]) * W + sub];
-            uint64_t carry = ~acc;
+            const int kd = rkind[j];
+            const int kind = kd >> 4;
+            const int e0 = rp[j], e1 = rp[j + 1];
+            uint64_t viol;
+            if (kind == kEvalPair) {
+                const uint64_t P = X[static_cast<int64_t>(ci[e0]) * W + sub];
+                const uint64_t Q = X[static_cast<int64_t>(ci[e1 - 1]) * W + sub];
+                viol = ((kd & 1) ? (~P & ~Q) : 0ull) | ((kd & 2) ? (~P & Q) : 0ull) |
+                       ((kd & 4) ? (P & ~Q) : 0ull) | ((kd & 8) ? (P & Q) : 0ull);
+            } else {
+                uint64_t one = 0, two = 0;
+                for (int e = e0; e < e1; ++e) {
+                    const uint64_t x = X[static_cast<int64_t>(ci[e]) * W + sub];
+                    two |= one & x;
+                    one |= x;
+                }
+                viol = kind == kEvalCover ? ~one : (kind == kEvalAtMostOne ? two : (~one | two));
+            }
+            uint64_t carry = viol;
 #pragma unroll
             for (int pl = 0; pl < 8; ++pl) {
                 const uint64_t t = c[pl] & carry;
@@ -221,12 +244,12 @@ k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
 }
 
 void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
-                       const int *rows, const int *rp, const int *ci, const uint64_t *X,
-                       int W, int *vpart, int K) {
+                       const int *rows, const uint8_t *rkind, const int *rp, const int *ci,
+                       const uint64_t *X, int W, int *vpart, int K) {
     if (!ntiles) return;
     int lg = 0;
     while ((1 << lg) < W) ++lg;
-    k_eval_cover<<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, X, W, lg, vpart, K);
+    k_eval_cover<<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rkind, rp, ci, X, W, lg, vpart, K);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,8 +364,10 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
     const int tile = tile_ids[blockIdx.x];
     const int r0 = tb0[tile], r1 = tb1[tile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int sh = lane & 31;
-    const bool hi = lane >= 32;
+    const unsigned sh = lane & 31;
+    // lanes 0-31 read the low halves of the candidate words, lanes 32-63 the
+    // high halves; sbfe turns bit sh into a 0 / -1 mask for the coefficient
+    const uint32_t *X32 = reinterpret_cast<const uint32_t *>(X) + (lane >> 5);
     int vc[WW];
 #pragma unroll
     for (int w = 0; w < WW; ++w) vc[w] = 0;
@@ -362,27 +387,33 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
                 c[u] = ci[e + u];
                 a[u] = val ? val[e + u] : 1;
             }
-            uint64_t xw[4][WW];
+            uint32_t xh[4][WW];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t *xr = X32 + static_cast<int64_t>(c[u]) * (2 * WW);
 #pragma unroll
-                for (int w = 0; w < WW; ++w) xw[u][w] = X[static_cast<int64_t>(c[u]) * WW + w];
+                for (int w = 0; w < WW; ++w) xh[u][w] = xr[2 * w];
+            }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int w = 0; w < WW; ++w) {
+                int t[4];
 #pragma unroll
-                for (int w = 0; w < WW; ++w) {
-                    const uint32_t half = hi ? static_cast<uint32_t>(xw[u][w] >> 32) : static_cast<uint32_t>(xw[u][w]);
-                    acc[w] += static_cast<ACC>(static_cast<int>((half >> sh) & 1u) * a[u]);
+                for (int u = 0; u < 4; ++u) t[u] = a[u] & __builtin_amdgcn_sbfe(static_cast<int>(xh[u][w]), sh, 1u);
+                if (sizeof(ACC) == 4) {
+                    acc[w] += (t[0] + t[1]) + (t[2] + t[3]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[w] += static_cast<ACC>(t[u]);
                 }
+            }
         }
         for (; e < q1; ++e) {
             const int c = ci[e];
             const int a = val ? val[e] : 1;
 #pragma unroll
             for (int w = 0; w < WW; ++w) {
-                const uint64_t word = X[static_cast<int64_t>(c) * WW + w];
-                const uint32_t half = hi ? static_cast<uint32_t>(word >> 32) : static_cast<uint32_t>(word);
-                acc[w] += static_cast<ACC>(static_cast<int>((half >> sh) & 1u) * a);
+                const uint32_t xh = X32[(static_cast<int64_t>(c) * WW + w) * 2];
+                acc[w] += static_cast<ACC>(a & __builtin_amdgcn_sbfe(static_cast<int>(xh), sh, 1u));
             }
         }
 #pragma unroll

@@ -486,3 +486,101 @@ def test_workgroup_per_row_dual(G, name):
     with pytest.raises(G.GforsError):
         prob.set_launch_cfg(256, 4, 1, 1, 1, 0, 0, 0)     # not with the SELL layout
     prob.close()
+
+
+def _bitwise_rows_problem(n=120, seed=0):
+    """Every bitwise-evaluated row kind next to general rows: covering rows,
+    at-most-one rows (-sum >= -1), exactly-one rows (+1 / -1 forms), rows of one
+    or two entries with assorted coefficients, both senses, and long general
+    rows."""
+    rng = np.random.default_rng(seed)
+    A, b, Bm, d = [], [], [], []
+    for _ in range(8):
+        cols = rng.choice(n, size=int(rng.integers(2, 15)), replace=False)
+        r = np.zeros(n, dtype=np.int64)
+        r[cols] = 1
+        A.append(r); b.append(1)                     # covering
+        r2 = np.zeros(n, dtype=np.int64)
+        r2[cols] = -1
+        A.append(r2); b.append(-1)                   # at most one
+        r3 = np.zeros(n, dtype=np.int64)
+        r3[cols] = 1 if rng.random() < 0.5 else -1
+        Bm.append(r3); d.append(int(r3[cols[0]]))    # exactly one (+1 or -1 form)
+    for _ in range(40):
+        k = int(rng.integers(1, 3))
+        cols = rng.choice(n, size=k, replace=False)
+        r = np.zeros(n, dtype=np.int64)
+        r[cols] = rng.choice([-3, -2, -1, 1, 2, 3], size=k)
+        if rng.random() < 0.7:
+            A.append(r); b.append(int(rng.integers(-3, 3)))
+        else:
+            Bm.append(r); d.append(int(rng.integers(-2, 3)))
+    for _ in range(4):
+        r = rng.integers(-5, 6, size=n)
+        A.append(r); b.append(int(rng.integers(-20, 5)))   # long general rows
+    c = rng.integers(-30, 40, size=n)
+    return I.from_dense(c, A=np.array(A), b=np.array(b), B=np.array(Bm), d=np.array(d),
+                        name=f"bitwise{seed}")
+
+
+@pytest.mark.parametrize("K", [192, 1024, 4096])
+def test_bitwise_row_kinds_bit_exact(G, K):
+    """Covering, at-most-one, exactly-one and one/two-entry rows evaluated as
+    bitwise functions of the candidate words give the oracle's exact
+    violation counts, next to general rows in the same problem."""
+    import torch
+    P = _bitwise_rows_problem(seed=K)
+    prob = G.Problem(P, _params(G))
+    rng = np.random.default_rng(K + 1)
+    p = f32(rng.random(P.n))
+    prob.set_state(p, p, np.zeros(P.m1 + P.m2), 0.0, k=0, round=2)
+    v, z = prob.sample_eval(K, p_override=torch.from_numpy(p).to("cuda:0"), outputs=True)
+    X = O.sample_bits(p.astype(np.float64), K, seed=0, rnd=2)
+    vo, zo = O.evaluate(P, X)
+    assert np.array_equal(v.cpu().numpy()[0], vo) and np.array_equal(z.cpu().numpy()[0], zo)
+    prob.close()
+
+
+def test_tu_facility_location_round(G):
+    """The TU-reformulated facility location (pair rows, covering rows of the
+    pivots' facilities, at-most-one rows) evaluated on the GPU equals the
+    oracle's evaluation of the same reduced model."""
+    import torch
+    F = I.facility_location(9, 31, seed=4)
+    tu = G.TUReformulation(F, F.meta["tu_pivots"])
+    P = tu.model
+    prob = G.Problem(P, _params(G))
+    rng = np.random.default_rng(3)
+    p = f32(rng.random(P.n) * 0.3)
+    prob.set_state(p, p, np.zeros(P.m1 + P.m2), 0.0, k=0, round=0)
+    v, z = prob.sample_eval(1024, p_override=torch.from_numpy(p).to("cuda:0"), outputs=True)
+    X = O.sample_bits(p.astype(np.float64), 1024, seed=0, rnd=0)
+    vo, zo = O.evaluate(P, X)
+    assert np.array_equal(v.cpu().numpy()[0], vo) and np.array_equal(z.cpu().numpy()[0], zo)
+    prob.close()
+
+
+@pytest.mark.parametrize("which", ["rows", "vars"])
+def test_heavy_light_split(G, which):
+    """Rows (variables) with 256+ entries handled by a workgroup each, the
+    others by groups of lanes skipping them: the teacher-forced step stays
+    within tolerance for every light lane count."""
+    if which == "rows":
+        P = _bitwise_rows_problem(n=400, seed=5)         # four long general rows
+        cfgs = [(256 + l, 4, 1, 1, 0, 0, 0, 0) for l in (1, 2, 8, 64)]
+    else:
+        P = I.facility_location(30, 300, seed=6)          # facilities in 300 rows each
+        cfgs = [(16, 256 + l, 1, 1, 0, 0, 0, 0) for l in (1, 2, 8, 64)] + [(258, 258, 1, 1, 0, 0, 0, 0)]
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=31, keep_every=30)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+    for cfg in cfgs:
+        prob.set_launch_cfg(*cfg)
+        prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+        prob.pdhg_steps(1)
+        got = prob.get_state()
+        assert got["k"] == st.k + 1
+        assert rel_inf(got["x"], ref.x) <= TOL_PDHG and rel_inf(got["y"], ref.y) <= TOL_PDHG, cfg
+    prob.close()
