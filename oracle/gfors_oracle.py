@@ -353,13 +353,15 @@ def uniforms24(seed: int, rnd: int, instance: int, i: np.ndarray, l: np.ndarray)
     """24-bit uniforms U(inst, round, i, l) in [0, 1) as exact FP64 values.
 
     Counter map (reading): key = (seed lo32, seed hi32),
-    counter = (l, i >> 2, round, instance), output word = i & 3;  u = (U >> 8) 2^-24."""
+    counter = (l >> 2, i, round, instance), output word = l & 3, i.e. one
+    Philox call serves four consecutive candidates of one variable;
+    u = (U >> 8) 2^-24."""
     i = np.asarray(i, dtype=np.int64)
     l = np.asarray(l, dtype=np.int64)
     i, l = np.broadcast_arrays(i, l)
-    w = philox4x32_10(l, i >> 2, np.full(i.shape, rnd), np.full(i.shape, instance),
+    w = philox4x32_10(l >> 2, i, np.full(i.shape, rnd), np.full(i.shape, instance),
                       seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
-    sel = (i & 3)
+    sel = (l & 3)
     U = np.choose(sel, w)
     return (U >> np.uint32(8)).astype(np.float64) * (2.0 ** -24)
 

@@ -4,13 +4,16 @@
 // Candidate layout: uint64 X[i * W + w] holds candidates 64w .. 64w+63 of
 // variable i (bit b = candidate 64w + b); W = K / 64.
 //
-// Sampler: a wavefront works on one quad of variables (4i .. 4i+3) and one
-// 64-candidate word; lane = candidate.  One Philox call per lane yields the
-// four uniforms of the quad (counter = (l, quad, round, instance), word =
-// i & 3), the four comparisons are packed by wave64 ballots into the four
-// words directly, staged in LDS and written back as one contiguous block.
-// The linear objective sum_i c_i x_i of each candidate is accumulated on the
-// fly (each lane owns its candidate), so X is never re-read for it.
+// Sampler: one Philox call gives the uniforms of four consecutive candidates
+// 4g .. 4g+3 of one variable i (counter = (g, i, round, instance), word =
+// candidate & 3).  A variable whose p is 0 or 1 needs no uniform at all (its
+// candidates are all 0 / all 1), so only the fractional variables cost Philox
+// calls.  A workgroup handles 64 variables at a time; its four wavefronts
+// split the candidates, lane = group of four candidates; the four bits of a
+// lane and of its neighbour form one byte of the variable's candidate row in
+// LDS, and the block is written back contiguously.  The linear objective
+// sum_i c_i x_i of each candidate is accumulated on the fly, so X is never
+// re-read for it.
 //
 // Evaluation: rows whose coefficients are all one with right-hand side 1
 // (covering rows) are checked with bitwise OR over 64 candidates at a time;
@@ -44,8 +47,8 @@ __device__ __forceinline__ uint32_t bern_threshold(float p) {
     return static_cast<uint32_t>(ceilf(p * 16777216.0f));
 }
 
-template <int WPW, typename ACC>
-__global__ void __launch_bounds__(1024)
+template <typename ACC>
+__global__ void __launch_bounds__(256)
 k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
          uint64_t *__restrict__ X, int W, const int *__restrict__ tile_inst,
          const int *__restrict__ tile_q0, const int *__restrict__ tile_q1,
@@ -55,6 +58,7 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
     extern __shared__ uint64_t lds[];   // [64 variables][W words]
     __shared__ uint32_t sthr[64];       // thresholds of the sub-tile's 64 variables
     __shared__ ACC scost[64];
+    __shared__ uint8_t sdet[64];        // 0: fractional, 1: all zero, 2: all one
     const int tile = blockIdx.x;
     const int inst = tile_inst[tile];
     const int q0 = tile_q0[tile], q1 = tile_q1[tile];
@@ -63,83 +67,84 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
     const uint32_t round = static_cast<uint32_t>(ctr->round);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int NW = blockDim.x >> 6;
-    ACC zacc[WPW];
+    // candidate groups (4 candidates each) of this wavefront: [gb, ge)
+    const int G4 = K >> 2;
+    const int per = G4 >> 2;            // K is a multiple of 64, so per is a multiple of 4
+    const int gb = wave * per, ge = gb + per;
+    constexpr int SMAX = 4;             // groups per lane: per <= 256 (K <= 4096)
+    ACC zacc[SMAX][4];
 #pragma unroll
-    for (int s = 0; s < WPW; ++s) zacc[s] = 0;
+    for (int t = 0; t < SMAX; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) zacc[t][j] = 0;
+    ACC zconst = 0;                     // variables sampled as all ones
 
     for (int sq = q0; sq < q1; sq += 16) {
         const int nq = min(16, q1 - sq);
-        // one coalesced load of the sub-tile's probabilities and costs
+        const int64_t il0 = 4LL * sq;
+        const int nvars = static_cast<int>(min<int64_t>(4LL * nq, nv - il0));
         if (threadIdx.x < 64) {
-            const int64_t il = 4LL * sq + threadIdx.x;
-            const bool in = threadIdx.x < 4 * nq && il < nv;
-            sthr[threadIdx.x] = in ? bern_threshold(p[v0 + il]) : 0u;
-            scost[threadIdx.x] = in ? static_cast<ACC>(cost[v0 + il]) : static_cast<ACC>(0);
+            const bool in = threadIdx.x < nvars;
+            const uint32_t th = in ? bern_threshold(p[v0 + il0 + threadIdx.x]) : 0u;
+            sthr[threadIdx.x] = th;
+            scost[threadIdx.x] = in ? static_cast<ACC>(cost[v0 + il0 + threadIdx.x]) : static_cast<ACC>(0);
+            uint8_t d;
+            if (threshold_mode) d = (0x800000u < th) ? 2 : 1;     // u = 1/2: [p > 1/2]
+            else d = th == 0u ? 1 : (th == (1u << 24) ? 2 : 0);
+            sdet[threadIdx.x] = in ? d : 1;
         }
         __syncthreads();
-        for (int qq = 0; qq < nq; ++qq) {
-            const int q = sq + qq;
-            uint32_t thr[4];
-            ACC cc[4];
+        // all-one variables add their cost to every candidate
+        {
+            const ACC c = (lane < nvars && sdet[lane] == 2) ? scost[lane] : static_cast<ACC>(0);
+            ACC t = c;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                thr[j] = sthr[4 * qq + j];
-                cc[j] = scost[4 * qq + j];
-            }
-            // p_i in {0, 1} for all four variables: every draw is decided without
-            // looking at the uniform (u < 0 never, u < 1 always), so the Philox call
-            // is skipped; the bits are identical to the ones it would give.
-            const bool det = ((thr[0] == 0u) | (thr[0] == (1u << 24))) &
-                             ((thr[1] == 0u) | (thr[1] == (1u << 24))) &
-                             ((thr[2] == 0u) | (thr[2] == (1u << 24))) &
-                             ((thr[3] == 0u) | (thr[3] == (1u << 24)));
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+            zconst += t;
+        }
+        uint8_t *lrow = reinterpret_cast<uint8_t *>(lds);
+        for (int v = 0; v < nvars; ++v) {
+            if (sdet[v] != 0) continue;                            // uniform
+            const uint32_t th = sthr[v];
+            const ACC c = scost[v];
+            const uint32_t il = static_cast<uint32_t>(il0 + v);
 #pragma unroll
-            for (int s = 0; s < WPW; ++s) {
-                const int w = wave + s * NW;
-                uint32_t r0, r1, r2, r3;
-                if (threshold_mode) {
-                    r0 = r1 = r2 = r3 = 0x80000000u;   // u = 1/2: candidate = [p > 1/2]
-                } else if (det) {
-                    r0 = r1 = r2 = r3 = 0u;
-                } else {
-                    r0 = 64u * static_cast<uint32_t>(w) + static_cast<uint32_t>(lane);
-                    r1 = static_cast<uint32_t>(q);
-                    r2 = round;
-                    r3 = static_cast<uint32_t>(inst);
-                    philox10(r0, r1, r2, r3, key0, key1);
-                }
-                const bool b0 = (r0 >> 8) < thr[0];
-                const bool b1 = (r1 >> 8) < thr[1];
-                const bool b2 = (r2 >> 8) < thr[2];
-                const bool b3 = (r3 >> 8) < thr[3];
-                const uint64_t m0 = __ballot(b0);
-                const uint64_t m1 = __ballot(b1);
-                const uint64_t m2 = __ballot(b2);
-                const uint64_t m3 = __ballot(b3);
-                ACC add = 0;
-                if (b0) add += cc[0];
-                if (b1) add += cc[1];
-                if (b2) add += cc[2];
-                if (b3) add += cc[3];
-                zacc[s] += add;
-                if (lane < 4) {
-                    const uint64_t mm = lane == 0 ? m0 : lane == 1 ? m1 : lane == 2 ? m2 : m3;
-                    lds[(qq * 4 + lane) * W + w] = mm;
-                }
+            for (int t = 0; t < SMAX; ++t) {
+                const int g = gb + lane + 64 * t;
+                if (64 * t >= per) break;                          // uniform
+                uint32_t r0 = static_cast<uint32_t>(g), r1 = il, r2 = round, r3 = static_cast<uint32_t>(inst);
+                philox10(r0, r1, r2, r3, key0, key1);
+                const uint32_t b0 = (r0 >> 8) < th, b1 = (r1 >> 8) < th;
+                const uint32_t b2 = (r2 >> 8) < th, b3 = (r3 >> 8) < th;
+                if (b0) zacc[t][0] += c;
+                if (b1) zacc[t][1] += c;
+                if (b2) zacc[t][2] += c;
+                if (b3) zacc[t][3] += c;
+                const uint32_t nib = b0 | (b1 << 1) | (b2 << 2) | (b3 << 3);
+                const uint32_t other = __shfl_xor(nib, 1, 64);
+                if (g < ge && (g & 1) == 0)
+                    lrow[static_cast<size_t>(v) * W * 8 + (g >> 1)] = static_cast<uint8_t>(nib | (other << 4));
             }
         }
         __syncthreads();
-        const int64_t nvars = min<int64_t>(4LL * nq, nv - 4LL * sq);
-        const int total = static_cast<int>(nvars) * W;
-        uint64_t *dst = X + (v0 + 4LL * sq) * W;
-        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) dst[idx] = lds[idx];
+        const int total = nvars * W;
+        uint64_t *dst = X + (v0 + il0) * W;
+        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+            const int v = idx / W;
+            const uint8_t d = sdet[v];
+            dst[idx] = d == 0 ? lds[idx] : (d == 2 ? ~0ull : 0ull);
+        }
         __syncthreads();
     }
 #pragma unroll
-    for (int s = 0; s < WPW; ++s) {
-        const int w = wave + s * NW;
-        zpart[static_cast<int64_t>(tile) * K + 64 * w + lane] = static_cast<int64_t>(zacc[s]);
+    for (int t = 0; t < SMAX; ++t) {
+        const int g = gb + lane + 64 * t;
+        if (64 * t >= per) break;
+        if (g < ge) {
+            int64_t *zp = zpart + static_cast<int64_t>(tile) * K + 4 * static_cast<int64_t>(g);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) zp[j] = static_cast<int64_t>(zacc[t][j] + zconst);
+        }
     }
 }
 
@@ -148,19 +153,11 @@ void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64
                    const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,
                    uint32_t key1, const DevCounters *ctr, int threshold_mode) {
     if (!st.count) return;
-    const int NW = W <= 16 ? W : 16;
-    const int wpw = W / NW;
     const size_t lds = static_cast<size_t>(64) * W * sizeof(uint64_t);
-#define GF_S(WP, ACCT) \
-    k_sample<WP, ACCT><<<st.count, NW * 64, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode)
-    if (obj64) {
-        switch (wpw) { case 1: GF_S(1, int64_t); break; case 2: GF_S(2, int64_t); break;
-                       case 3: GF_S(3, int64_t); break; case 4: GF_S(4, int64_t); break; default: break; }
-    } else {
-        switch (wpw) { case 1: GF_S(1, int32_t); break; case 2: GF_S(2, int32_t); break;
-                       case 3: GF_S(3, int32_t); break; case 4: GF_S(4, int32_t); break; default: break; }
-    }
-#undef GF_S
+    if (obj64)
+        k_sample<int64_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode);
+    else
+        k_sample<int32_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode);
 }
 
 // ---------------------------------------------------------------------------

@@ -54,14 +54,14 @@ def test_philox_matches_rocrand_engine(rocrand_ref):
 
 
 def test_uniform_counter_map_matches_rocrand(rocrand_ref):
-    """u(inst, round, i, l) uses counter (l, i>>2, round, inst), word i&3."""
+    """u(inst, round, i, l) uses counter (l>>2, i, round, inst), word l&3."""
     seed, rnd, inst = 77, 5, 3
     i = np.array([0, 1, 2, 3, 4, 9, 1001])
     l = np.array([0, 0, 7, 63, 64, 1000, 5])
     u = O.uniforms24(seed, rnd, inst, i, l)
     for k in range(i.size):
-        words = _rocrand4(rocrand_ref, seed, int(l[k]), int(i[k]) >> 2, rnd, inst)[0]
-        U = words[int(i[k]) & 3]
+        words = _rocrand4(rocrand_ref, seed, int(l[k]) >> 2, int(i[k]), rnd, inst)[0]
+        U = words[int(l[k]) & 3]
         assert u[k] == (U >> 8) * 2.0 ** -24
 
 
