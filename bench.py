@@ -328,8 +328,11 @@ def main():
     try:
         with open(a.traffic_file) as f:
             tr = json.load(f)
-        ent = tr.get(a.workload, {}).get(dom)
-        if ent and ent.get("K") == a.K:
+        # counters taken on the same workload, K and launch shape only
+        wl = tr.get(a.workload, {})
+        cfg_now = list(G.launch_cfg().values())
+        ent = wl.get(dom)
+        if ent and ent.get("K") == a.K and wl.get("launch_cfg") == cfg_now:
             traffic = ent.get("bytes_per_launch")
     except (OSError, ValueError):
         pass

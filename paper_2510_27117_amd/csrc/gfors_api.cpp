@@ -40,7 +40,7 @@ constexpr int kCoverRows = 8192;      // rows per bitwise-evaluated tile (max)
 constexpr int kBitwiseNnz = 8192;     // nnz budget of a bitwise-evaluated tile
 constexpr int kGeneralRows = 4096;    // rows per general tile (max)
 constexpr int kQuadNnz = 4096;        // nnz budget of a Q tile
-constexpr int kQuadRows = 256;
+constexpr int kQuadRows = 64;          // variables per Q tile (max): many tiles keep enough wavefronts in flight
 constexpr int kVarTile = 4096;        // variables per FP64 reduction tile
 constexpr int kRowNnz = 16384;        // nnz budget of a residual row tile
 constexpr int kRowRows = 2048;
