@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--k-int", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--tti-rounds", type=int, default=200)
+    ap.add_argument("--tti-rounds", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
     ap.add_argument("--launch-cfg", default=None,

@@ -125,6 +125,7 @@ struct gfors_problem {
     bool general_long = false;   // general rows average >= 256 entries: split rows over wavefronts
     int *rows = nullptr;
     uint8_t *rkind = nullptr;    // per row: evaluation kind << 4 | truth table (pair rows)
+    uint8_t *xkind = nullptr;    // per variable, last round: 0 sampled, 1 all zero, 2 all one
     int *dual_order = nullptr;   // constraint rows, longest first (block-per-row dual)
     int *primal_order = nullptr; // variables, most rows first (block-per-variable primal)
     int heavy_rows = 0, heavy_cols = 0;   // rows / variables with kHeavyLen+ entries
@@ -337,6 +338,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->z = cv.take<int64_t>(static_cast<int64_t>(T) * prm->K_max);
     P->rows = cv.take<int>(m);
     P->rkind = cv.take<uint8_t>(m);
+    P->xkind = cv.take<uint8_t>(n);
     P->dual_order = cv.take<int>(m);
     P->primal_order = cv.take<int>(n);
     P->cover_ids = cv.take<int>(b.et);
@@ -1312,11 +1314,11 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     TB(2);
     launch_sample(s, W, P->obj64, p, P->cost, P->X, P->st, P->d_inst_var0, P->d_inst_nvar,
                   P->zpart, K, static_cast<uint32_t>(P->prm.seed & 0xffffffffu),
-                  static_cast<uint32_t>(P->prm.seed >> 32), P->ctr, threshold);
+                  static_cast<uint32_t>(P->prm.seed >> 32), P->ctr, threshold, P->xkind);
     TE(2);
     TB(3);
-    launch_eval_cover(s, P->n_cover, P->cover_ids, P->et, P->rows, P->rkind, P->rp, P->ci, P->X, W,
-                      P->vpart, K);
+    launch_eval_cover(s, P->n_cover, P->cover_ids, P->et, P->rows, P->rkind, P->rp, P->ci, P->X,
+                      P->xkind, W, P->vpart, K);
     TE(3);
     TB(4);
     launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,

@@ -169,11 +169,11 @@ void launch_res_vars(hipStream_t s, const Tiles &vt, const int *rpQ, const int *
 void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64_t *cost,
                    uint64_t *X, const Tiles &st, const int64_t *inst_var0,
                    const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,
-                   uint32_t key1, const DevCounters *ctr, int threshold_mode);
+                   uint32_t key1, const DevCounters *ctr, int threshold_mode, uint8_t *xkind);
 
 void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                        const int *rows, const uint8_t *rkind, const int *rp, const int *ci,
-                       const uint64_t *X, int W, int *vpart, int K);
+                       const uint64_t *X, const uint8_t *xkind, int W, int *vpart, int K);
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,

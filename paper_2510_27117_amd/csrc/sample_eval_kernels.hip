@@ -54,7 +54,7 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
          const int *__restrict__ tile_q0, const int *__restrict__ tile_q1,
          const int64_t *__restrict__ inst_var0, const int64_t *__restrict__ inst_nvar,
          int64_t *__restrict__ zpart, int K, uint32_t key0, uint32_t key1,
-         const DevCounters *__restrict__ ctr, int threshold_mode) {
+         const DevCounters *__restrict__ ctr, int threshold_mode, uint8_t *__restrict__ xkind) {
     extern __shared__ uint64_t lds[];   // [64 variables][W words]
     __shared__ uint32_t sthr[64];       // thresholds of the sub-tile's 64 variables
     __shared__ ACC scost[64];
@@ -92,6 +92,7 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
             if (threshold_mode) d = (0x800000u < th) ? 2 : 1;     // u = 1/2: [p > 1/2]
             else d = th == 0u ? 1 : (th == (1u << 24) ? 2 : 0);
             sdet[threadIdx.x] = in ? d : 1;
+            if (in) xkind[v0 + il0 + threadIdx.x] = d;
         }
         __syncthreads();
         // all-one variables add their cost to every candidate
@@ -151,13 +152,13 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
 void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64_t *cost,
                    uint64_t *X, const Tiles &st, const int64_t *inst_var0,
                    const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,
-                   uint32_t key1, const DevCounters *ctr, int threshold_mode) {
+                   uint32_t key1, const DevCounters *ctr, int threshold_mode, uint8_t *xkind) {
     if (!st.count) return;
     const size_t lds = static_cast<size_t>(64) * W * sizeof(uint64_t);
     if (obj64)
-        k_sample<int64_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode);
+        k_sample<int64_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode, xkind);
     else
-        k_sample<int32_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode);
+        k_sample<int32_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode, xkind);
 }
 
 // ---------------------------------------------------------------------------
@@ -185,12 +186,25 @@ __device__ __forceinline__ void flush_planes(uint64_t (&c)[8], int *cnt, int w) 
     for (int pl = 0; pl < 8; ++pl) c[pl] = 0;
 }
 
+// Word `sub` of variable c's candidates: variables the sampler found
+// deterministic (p = 0 / p = 1: all candidates 0 / 1) are answered from the
+// per-variable kind byte (an L2-resident n-byte array) instead of the 8n W-byte
+// candidate block.
+__device__ __forceinline__ uint64_t cand_word(const uint64_t *__restrict__ X,
+                                              const uint8_t *__restrict__ xkind, int c, int W,
+                                              int sub) {
+    const uint8_t k = xkind[c];
+    if (k == 1) return 0ull;
+    if (k == 2) return ~0ull;
+    return X[static_cast<int64_t>(c) * W + sub];
+}
+
 __global__ void __launch_bounds__(256)
 k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
              const int *__restrict__ tb1, const int *__restrict__ rows,
              const uint8_t *__restrict__ rkind, const int *__restrict__ rp,
-             const int *__restrict__ ci, const uint64_t *__restrict__ X, int W, int lgWp,
-             int *__restrict__ vpart, int K) {
+             const int *__restrict__ ci, const uint64_t *__restrict__ X,
+             const uint8_t *__restrict__ xkind, int W, int lgWp, int *__restrict__ vpart, int K) {
     __shared__ int cnt[4096];
     const int tile = tile_ids[blockIdx.x];
     const int r0 = tb0[tile], r1 = tb1[tile];
@@ -211,14 +225,14 @@ k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
             const int e0 = rp[j], e1 = rp[j + 1];
             uint64_t viol;
             if (kind == kEvalPair) {
-                const uint64_t P = X[static_cast<int64_t>(ci[e0]) * W + sub];
-                const uint64_t Q = X[static_cast<int64_t>(ci[e1 - 1]) * W + sub];
+                const uint64_t P = cand_word(X, xkind, ci[e0], W, sub);
+                const uint64_t Q = cand_word(X, xkind, ci[e1 - 1], W, sub);
                 viol = ((kd & 1) ? (~P & ~Q) : 0ull) | ((kd & 2) ? (~P & Q) : 0ull) |
                        ((kd & 4) ? (P & ~Q) : 0ull) | ((kd & 8) ? (P & Q) : 0ull);
             } else {
                 uint64_t one = 0, two = 0;
                 for (int e = e0; e < e1; ++e) {
-                    const uint64_t x = X[static_cast<int64_t>(ci[e]) * W + sub];
+                    const uint64_t x = cand_word(X, xkind, ci[e], W, sub);
                     two |= one & x;
                     one |= x;
                 }
@@ -242,11 +256,11 @@ k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
 
 void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                        const int *rows, const uint8_t *rkind, const int *rp, const int *ci,
-                       const uint64_t *X, int W, int *vpart, int K) {
+                       const uint64_t *X, const uint8_t *xkind, int W, int *vpart, int K) {
     if (!ntiles) return;
     int lg = 0;
     while ((1 << lg) < W) ++lg;
-    k_eval_cover<<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rkind, rp, ci, X, W, lg, vpart, K);
+    k_eval_cover<<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rkind, rp, ci, X, xkind, W, lg, vpart, K);
 }
 
 // ---------------------------------------------------------------------------
