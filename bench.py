@@ -48,6 +48,8 @@ def parse():
                     help="run a plain 512 MiB device copy first (scale for HBM byte counters)")
     ap.add_argument("--ufl-eval", default="1000,10000",
                     help="ufl_learned: facilities,customers of the evaluation instance")
+    ap.add_argument("--snap-window", default=None,
+                    help="ufl_learned: first,last fraction of each training run to take iterates from")
     ap.add_argument("--train-instances", type=int, default=200)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--seq-sample", type=int, default=8,
@@ -189,7 +191,8 @@ def learned_experiment(a):
     for sd in range(1000, 1000 + a.train_instances):
         P = instances.facility_location(40, 400, seed=sd)
         bips.append(gfors.TUReformulation(P, P.meta["tu_pivots"]).model)
-    samples = learned.collect(bips, train_prm, rounds=60, K=256, snapshots=6)
+    win = tuple(float(v) for v in a.snap_window.split(",")) if a.snap_window else (None, None)
+    samples = learned.collect(bips, train_prm, rounds=60, K=256, snapshots=6, window=win)
     t_collect = time.perf_counter() - t0
     net = gfors.GNN(seed=a.seed)
     loss0 = learned.mean_loss(net, samples[:64])
@@ -218,7 +221,8 @@ def learned_experiment(a):
            "config": {"workload": f"facility location {nf} x {nc} (TU: {nc} assignments eliminated)",
                       "n_reduced": tu.model.n, "rows": tu.model.m1,
                       "nnz": int(tu.model.A.nnz), "K": a.K, "k_int": a.k_int, "rounds": R,
-                      "train": f"{a.train_instances} instances 40 x 400, {len(samples)} pairs, {a.train_steps} Adam steps"},
+                      "train": f"{a.train_instances} instances 40 x 400, {len(samples)} pairs, {a.train_steps} Adam steps",
+           "snapshot_window": list(win)},
            "collect_s": round(t_collect, 2), "train_s": round(t_train, 2),
            "train_loss_before": round(loss0, 5), "train_loss_after": round(loss1, 5),
            "plain": {"first_feasible_round": next((i for i, z in enumerate(zp) if z is not None), None),

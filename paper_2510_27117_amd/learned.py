@@ -91,12 +91,16 @@ def run_learned(prob: "gfors.Problem", net: "gfors.GNN", rounds: int, K: int) ->
 
 
 def collect(bips, params, rounds: int, K: int, snapshots: int = 6, device: str = "cuda:0",
-            log=None) -> List[Sample]:
+            log=None, window=(None, None)) -> List[Sample]:
     """Run the plain method on each instance and pair the iterate (x_k, y_k) at
-    `snapshots` evenly spaced triggers with the run's final incumbent."""
+    `snapshots` evenly spaced triggers with the run's final incumbent.
+    `window` = (first, last) fractions of the run to take snapshots from
+    (default: from rounds/snapshots to the end)."""
     torch = _torch()
     out: List[Sample] = []
-    snap_at = set(np.linspace(rounds // snapshots, rounds - 1, snapshots).astype(int).tolist())
+    lo = rounds // snapshots if window[0] is None else int(window[0] * rounds)
+    hi = rounds - 1 if window[1] is None else max(lo, int(window[1] * rounds))
+    snap_at = set(np.linspace(lo, hi, snapshots).astype(int).tolist())
     for idx, bip in enumerate(bips):
         prob = gfors.Problem(bip, params, device=device)
         xs = []
