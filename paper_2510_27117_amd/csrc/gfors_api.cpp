@@ -1322,11 +1322,12 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     TE(3);
     TB(4);
     launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
-                        P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X, W,
-                        P->vpart, K, P->general_long);
+                        P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X,
+                        P->xkind, W, P->vpart, K, P->general_long);
     TE(4);
     TB(5);
-    if (P->hasQ) launch_eval_quad(s, P->qt, P->d_inst_var0, P->rpQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K);
+    if (P->hasQ)
+        launch_eval_quad(s, P->qt, P->d_inst_var0, P->rpQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K);
     TE(5);
     TB(6);
     launch_reduce_cand(s, P->T, K, P->red_S, P->et, P->vpart, P->st, P->zpart, P->qt, P->zqpart,

@@ -370,7 +370,8 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
                   const int *__restrict__ tb1, const int *__restrict__ rows,
                   const int *__restrict__ rp, const int *__restrict__ ci,
                   const int *__restrict__ val, const int64_t *__restrict__ rhs, int m1,
-                  const uint64_t *__restrict__ X, int *__restrict__ vpart, int K) {
+                  const uint64_t *__restrict__ X, const uint8_t *__restrict__ xkind,
+                  int *__restrict__ vpart, int K) {
     __shared__ ACC part[4][WW][64];
     const int tile = tile_ids[blockIdx.x];
     const int r0 = tb0[tile], r1 = tb1[tile];
@@ -398,12 +399,19 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
                 c[u] = ci[e + u];
                 a[u] = val ? val[e + u] : 1;
             }
+            // deterministic variables (all candidates 0 / 1) need no load
             uint32_t xh[4][WW];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const uint32_t *xr = X32 + static_cast<int64_t>(c[u]) * (2 * WW);
+                const uint8_t kd = xkind[c[u]];
+                if (kd == 0) {
+                    const uint32_t *xr = X32 + static_cast<int64_t>(c[u]) * (2 * WW);
 #pragma unroll
-                for (int w = 0; w < WW; ++w) xh[u][w] = xr[2 * w];
+                    for (int w = 0; w < WW; ++w) xh[u][w] = xr[2 * w];
+                } else {
+#pragma unroll
+                    for (int w = 0; w < WW; ++w) xh[u][w] = kd == 2 ? 0xFFFFFFFFu : 0u;
+                }
             }
 #pragma unroll
             for (int w = 0; w < WW; ++w) {
@@ -421,9 +429,11 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
         for (; e < q1; ++e) {
             const int c = ci[e];
             const int a = val ? val[e] : 1;
+            const uint8_t kd = xkind[c];
 #pragma unroll
             for (int w = 0; w < WW; ++w) {
-                const uint32_t xh = X32[(static_cast<int64_t>(c) * WW + w) * 2];
+                const uint32_t xh = kd == 0 ? X32[(static_cast<int64_t>(c) * WW + w) * 2]
+                                            : (kd == 2 ? 0xFFFFFFFFu : 0u);
                 acc[w] += static_cast<ACC>(a & __builtin_amdgcn_sbfe(static_cast<int>(xh), sh, 1u));
             }
         }
@@ -451,10 +461,10 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,
-                         int W, int *vpart, int K, bool long_rows) {
+                         const uint8_t *xkind, int W, int *vpart, int K, bool long_rows) {
     if (!ntiles) return;
     if (long_rows && W <= 16 && (W & (W - 1)) == 0) {
-#define GF_RS(WW, ACCT) k_eval_rows_split<WW, ACCT><<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, vpart, K)
+#define GF_RS(WW, ACCT) k_eval_rows_split<WW, ACCT><<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, xkind, vpart, K)
 #define GF_RSW(ACCT) switch (W) { case 1: GF_RS(1, ACCT); break; case 2: GF_RS(2, ACCT); break; \
         case 4: GF_RS(4, ACCT); break; case 8: GF_RS(8, ACCT); break; default: GF_RS(16, ACCT); break; }
         if (acc64) { GF_RSW(int64_t) } else { GF_RSW(int32_t) }
