@@ -210,12 +210,13 @@ int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_
 /* Launch shapes in use: out[8] = {lanes per row of the dual SpMV, lanes per row
  * of the primal SpMV, column slices of the dual SpMV, slices of the primal,
  * SELL-64 layout for the dual (0/1), SELL-64 layout for the primal (0/1),
- * zero-operand skipping in the dual (0/1/2), in the primal (0/1/2)}
+ * zero-operand skipping in the dual (0..3), in the primal (0..3)}
  * (1 slice = fused kernel; with SELL the lanes-per-row entry is unused; dual
  * lanes per row 256 = a workgroup per row, longest rows first).  Skipping
  * keeps the nonzero bitmap of the gathered vector in LDS and issues only the
  * gathers of nonzero operands: 1 = sliced SELL dual / fused CSR primal,
- * 2 = batched-issue kernel on any SELL layout. */
+ * 2 / 3 = batched-issue kernel on any SELL layout, two / four row chunks per
+ * wavefront at once. */
 int gfors_get_launch_cfg(gfors_problem *P, int32_t *out);
 
 /* Re-run the autotuner on the current iterate (the zero-operand bitmap
@@ -229,7 +230,7 @@ int gfors_autotune(gfors_problem *P);
  * no skipping; slices: 1, or 8 when the problem holds the column-sliced copy
  * (then lanes <= 16; the primal also needs Q = 0); SELL only where the problem
  * holds the SELL copy; skipping 1 only for the sliced SELL dual / the fused CSR
- * primal, 2 only with a SELL layout, both without Q and with bitmaps of at most
+ * primal, 2 and 3 only with a SELL layout, all without Q and with bitmaps of at most
  * 64 KB.  E_ARG otherwise (nothing is changed).  Drops captured graphs. */
 int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg);
 

@@ -1052,20 +1052,21 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
                             P->wy, tau2, P->di.tau2, P->row_inst, P->by);
     };
     bool wy_bits = false;
-    if (sell && P->cfg.bits_dual == 2) {
+    if (sell && P->cfg.bits_dual >= 2) {
+        const int nc = P->cfg.bits_dual == 3 ? 4 : 2;
         need_bx();
         if (slices > 1) {
             launch_sell_bits(s, P->sellKS, 0, P->unitK, batched, static_cast<int>(P->n), P->xbar,
                              bx32, P->spart, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f,
                              nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr,
-                             nullptr, nullptr, nullptr);
+                             nullptr, nullptr, nullptr, nc);
             combine();
             wy_bits = true;
         } else {
             launch_sell_bits(s, P->sellK, 1, P->unitK, batched, static_cast<int>(P->n), P->xbar,
                              bx32, nullptr, m1, P->omega, P->rt, y_in, y_out, P->wy, tau2,
                              P->di.tau2, P->row_inst, nullptr, nullptr, nullptr, nullptr, 0.f,
-                             nullptr, nullptr, nullptr, nullptr);
+                             nullptr, nullptr, nullptr, nullptr, nc);
         }
     } else if (sell && slices > 1 && P->cfg.bits_dual) {
         need_bx();
@@ -1118,12 +1119,13 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
         P->by_fresh = true;
     };
     bool xbar_bits = false;
-    if (P->cfg.bits_primal == 2 && sell && kmode != 0 && !P->hasQ) {
+    if (P->cfg.bits_primal >= 2 && sell && kmode != 0 && !P->hasQ) {
         need_by();
         launch_sell_bits(s, P->sellT, 2, P->unitK, batched, static_cast<int>(P->m), P->wy,
                          reinterpret_cast<const uint32_t *>(P->by), nullptr, 0, nullptr, nullptr,
                          nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, x_in, x_out, xbar,
-                         P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst, ctr);
+                         P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst, ctr,
+                         P->cfg.bits_primal == 3 ? 4 : 2);
     } else if (P->cfg.bits_primal == 1 && !sell && slices == 1 && kmode != 0 && !P->hasQ) {
         need_by();
         uint64_t *xb_out = lpr <= 8 ? xbits : nullptr;
@@ -1160,11 +1162,15 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
     if (xbar == P->xbar) P->bx_fresh = xbar_bits;
 }
 
+// Zero-operand skipping variants.  bits = 1: sliced SELL dual with the slice
+// bitmap in LDS, or fused-CSR primal with the dual bitmap in LDS; bits = 2 / 3:
+// k_sell_bits on any SELL copy (batched load issue, 2 / 4 chunks per pass).
+// Each needs its bitmap to fit in LDS.
 static int bits_ok_dual(gfors_problem *P, int slices, int sell, int bits) {
     if (bits == 0) return 1;
     if (!sell) return 0;
     if (bits == 1) return (slices > 1 && P->sellKS.ptr && P->sellKS.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
-    if (bits != 2) return 0;
+    if (bits != 2 && bits != 3) return 0;
     const SellView &sv = slices > 1 ? P->sellKS : P->sellK;
     return (sv.ptr && sv.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
 }
@@ -1172,7 +1178,7 @@ static int bits_ok_primal(gfors_problem *P, int slices, int sell, int bits) {
     if (bits == 0) return 1;
     if (P->m == 0 || P->hasQ || slices != 1) return 0;
     if (bits == 1) return (!sell && (P->m + 31) / 32 * 4 <= kMaxLdsBitmapBytes) ? 1 : 0;
-    if (bits != 2) return 0;
+    if (bits != 2 && bits != 3) return 0;
     return (sell && P->sellT.ptr && P->sellT.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
 }
 
@@ -1217,7 +1223,7 @@ static int autotune(gfors_problem *P) {
             for (int l : {1, 2, 4, 8, 16}) consider(kLprBlock + l, 1, 0);
         // zero-operand skipping: each variant is kept only when it is faster
         int best_bits = 0;
-        for (int b : {1, 2}) {
+        for (int b : {1, 2, 3}) {
             for (int sl : {kXcdSlices, 1}) {
                 if (!bits_ok_dual(P, sl, 1, b)) continue;
                 P->cfg.bits_dual = b;
@@ -1252,10 +1258,11 @@ static int autotune(gfors_problem *P) {
                 if (t < best) { best = t; best_bits = 1; P->cfg.lpr_primal = l; P->cfg.slices_primal = 1; P->cfg.sell_primal = 0; }
             }
         }
-        if (bits_ok_primal(P, 1, 1, 2)) {
-            P->cfg.bits_primal = 2;
+        for (int b : {2, 3}) {
+            if (!bits_ok_primal(P, 1, 1, b)) continue;
+            P->cfg.bits_primal = b;
             const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 1, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
-            if (t < best) { best = t; best_bits = 2; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 1; }
+            if (t < best) { best = t; best_bits = b; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 1; }
         }
         P->cfg.bits_primal = best_bits;
     }
@@ -1607,9 +1614,9 @@ int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
         return fail(GFORS_E_ARG, "no SELL copy of the constraint rows for this slicing");
     if (cfg[5] && !(cfg[3] == 1 && P->sellT.ptr))
         return fail(GFORS_E_ARG, "no SELL copy of the transposed rows");
-    if (cfg[6] < 0 || cfg[6] > 2 || !bits_ok_dual(P, cfg[2], cfg[4], cfg[6]))
+    if (cfg[6] < 0 || cfg[6] > 3 || !bits_ok_dual(P, cfg[2], cfg[4], cfg[6]))
         return fail(GFORS_E_ARG, "bitmap dual: 1 needs the sliced SELL layout, 2 a SELL layout, and the slice bitmap must fit in LDS");
-    if (cfg[7] < 0 || cfg[7] > 2 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
+    if (cfg[7] < 0 || cfg[7] > 3 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
         return fail(GFORS_E_ARG, "bitmap primal: 1 needs the fused CSR layout, 2 the SELL layout; both need Q = 0 and a dual bitmap that fits in LDS");
     P->cfg.lpr_dual = cfg[0];
     P->cfg.lpr_primal = cfg[1];

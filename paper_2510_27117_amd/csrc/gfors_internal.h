@@ -133,8 +133,8 @@ void launch_sell_bits(hipStream_t s, const SellView &sv, int mode, bool unit, bo
                       float *wy, float tau2, const float *tau2_inst, const int *row_inst,
                       const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
                       const float *tau1_inst, const double *rho, const int *var_inst,
-                      DevCounters *ctr);
-int sell_bits_blocks(const SellView &sv);
+                      DevCounters *ctr, int nc);
+int sell_bits_blocks(const SellView &sv, int nc);
 void launch_sell_part_bits(hipStream_t s, const SellView &sv, int ns, int ncols, bool unit,
                            const float *v, const uint32_t *bits, float *part);
 void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, int m,

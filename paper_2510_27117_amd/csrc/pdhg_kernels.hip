@@ -630,7 +630,7 @@ void launch_sell_part_bits(hipStream_t s, const SellView &sv, int ns, int ncols,
 // looked up, then the gathers of the nonzero operands are issued together, so
 // a wavefront keeps up to 16 loads in flight.  The terms are added in the same
 // order as k_sell and the skipped terms are zeros, so the sums equal k_sell's.
-template <bool UNIT, int MODE, bool BATCH>
+template <bool UNIT, int MODE, bool BATCH, int NC>
 __global__ void __launch_bounds__(512)
 k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *__restrict__ ptr,
             const int *__restrict__ ci, const int *__restrict__ val,
@@ -655,18 +655,19 @@ k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *_
     const int nwv = blockDim.x >> 6;
     const int64_t pb = static_cast<int64_t>(sl) * (nchunk + 1);
     const int stride = G * nwv;
-    // Two chunks per pass (c and c + stride), so that a wavefront has twice
-    // as many independent loads in flight.  Each chunk's terms are still
+    // NC chunks per pass (c, c + stride, ...), so that a wavefront has NC
+    // times as many independent loads in flight.  Each chunk's terms are still
     // added in its own order.  Branch-free: slots past a chunk's end load
     // (clamped) entry L-1 and are masked; the bitmap word is read for every
     // slot (index clamped into the slice); a zero operand gathers the padding
     // element v[ncols] instead, one address shared by the wavefront (one cache
     // line, no extra L2 traffic), and its term is not added.
-    for (int c0 = gb * nwv + wave; c0 < nchunk; c0 += 2 * stride) {
-        int cc[2], e0[2], L[2], row[2];
-        float acc[2] = {0.f, 0.f};
+    for (int c0 = gb * nwv + wave; c0 < nchunk; c0 += NC * stride) {
+        int cc[NC], e0[NC], L[NC], row[NC];
+        float acc[NC];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < NC; ++h) {
+            acc[h] = 0.f;
             cc[h] = c0 + h * stride;
             const bool live = cc[h] < nchunk;
             const int cx = live ? cc[h] : c0;
@@ -674,12 +675,14 @@ k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *_
             L[h] = live ? (ptr[pb + cx + 1] - e0[h]) >> 6 : 0;
             row[h] = live ? row_of[(static_cast<int64_t>(sl) * nchunk + cx) * 64 + lane] : -1;
         }
-        const int Lm = max(L[0], L[1]);
-        for (int k0 = 0; k0 < Lm; k0 += 8) {
-            int col[2][8];
-            int a[2][8];
+        int Lm = 0;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < NC; ++h) Lm = max(Lm, L[h]);
+        for (int k0 = 0; k0 < Lm; k0 += 8) {
+            int col[NC][8];
+            int a[NC][8];
+#pragma unroll
+            for (int h = 0; h < NC; ++h) {
                 if (k0 < L[h]) {                   // uniform across the wavefront
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
@@ -696,9 +699,9 @@ k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *_
                     }
                 }
             }
-            bool nz[2][8];
+            bool nz[NC][8];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < NC; ++h) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int loc = col[h][u] - base;
@@ -708,14 +711,14 @@ k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *_
                     nz[h][u] = in & (((word >> (li & 31)) & 1u) != 0u);
                 }
             }
-            float g[2][8];
+            float g[NC][8];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < NC; ++h) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) g[h][u] = v[nz[h][u] ? col[h][u] : ncols];
             }
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < NC; ++h) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const float t = UNIT ? acc[h] + g[h][u] : fmaf(static_cast<float>(a[h][u]), g[h][u], acc[h]);
@@ -724,7 +727,7 @@ k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *_
             }
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < NC; ++h) {
             const int r = row[h];
             if (r < 0) continue;
             const float sum = acc[h];
@@ -752,16 +755,18 @@ k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *_
     }
 }
 
-int sell_bits_blocks(const SellView &sv) {
-    // workgroups of 8 wavefronts; per CU as many as the bitmap (LDS) and
-    // 32 resident wavefronts allow; the grid is a multiple of P so that
+int sell_bits_blocks(const SellView &sv, int nc) {
+    // workgroups of 8 wavefronts; per CU as many as the bitmap (LDS) and the
+    // resident wavefronts allow (32, or 16 for four chunks per pass, which
+    // holds twice the registers); the grid is a multiple of P so that
     // workgroup b (slice b % P) runs on XCD b % 8 when P = 8
     const int64_t bytes = static_cast<int64_t>(sv.ns / 32) * 4 + 1024;
     int per_cu = static_cast<int>((160 * 1024) / bytes);
-    if (per_cu > 4) per_cu = 4;
+    const int cap = nc >= 4 ? 2 : 4;
+    if (per_cu > cap) per_cu = cap;
     if (per_cu < 1) per_cu = 1;
     int G = 256 * per_cu / sv.P;
-    const int need = (sv.nchunk + 7) / 8;
+    const int need = (sv.nchunk + 8 * nc - 1) / (8 * nc);
     if (G > need) G = need;
     return G < 1 ? 1 : G;
 }
@@ -772,16 +777,18 @@ void launch_sell_bits(hipStream_t s, const SellView &sv, int mode, bool unit, bo
                       float *wy, float tau2, const float *tau2_inst, const int *row_inst,
                       const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
                       const float *tau1_inst, const double *rho, const int *var_inst,
-                      DevCounters *ctr) {
+                      DevCounters *ctr, int nc) {
     if (sv.nchunk <= 0 || sv.P <= 0) return;
-    const int G = sell_bits_blocks(sv);
+    const int G = sell_bits_blocks(sv, nc);
     const size_t lds = static_cast<size_t>(sv.ns / 32) * 4;
     const int blocks = G * sv.P;
-#define GF_SB(U, M, B) k_sell_bits<U, M, B><<<blocks, 512, lds, s>>>(sv.nrows, sv.P, sv.nchunk, sv.ns, ncols, G, sv.ptr, sv.ci, sv.val, sv.row_of, v, bits, part, m1, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
-#define GF_SB_M(U, B) if (mode == 0) GF_SB(U, 0, B); else if (mode == 1) GF_SB(U, 1, B); else GF_SB(U, 2, B)
+#define GF_SB(U, M, B, N) k_sell_bits<U, M, B, N><<<blocks, 512, lds, s>>>(sv.nrows, sv.P, sv.nchunk, sv.ns, ncols, G, sv.ptr, sv.ci, sv.val, sv.row_of, v, bits, part, m1, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
+#define GF_SB_N(U, M, B) if (nc >= 4) GF_SB(U, M, B, 4); else GF_SB(U, M, B, 2)
+#define GF_SB_M(U, B) if (mode == 0) { GF_SB_N(U, 0, B); } else if (mode == 1) { GF_SB_N(U, 1, B); } else { GF_SB_N(U, 2, B); }
     if (unit) { if (batched) { GF_SB_M(true, true); } else { GF_SB_M(true, false); } }
     else { if (batched) { GF_SB_M(false, true); } else { GF_SB_M(false, false); } }
 #undef GF_SB_M
+#undef GF_SB_N
 #undef GF_SB
 }
 

@@ -421,7 +421,8 @@ def test_batched_issue_bitmap_kernels_equal_plain_sell(G):
     prob = G.Problem(P, _params(G, autotune=0))
     pairs = [((1, 4, 8, 1, 1, 0, 0, 0), (1, 4, 8, 1, 1, 0, 2, 0)),
              ((16, 1, 1, 1, 0, 1, 0, 0), (16, 1, 1, 1, 0, 1, 0, 2)),
-             ((1, 1, 8, 1, 1, 1, 0, 0), (1, 1, 8, 1, 1, 1, 2, 2))]
+             ((1, 1, 8, 1, 1, 1, 0, 0), (1, 1, 8, 1, 1, 1, 2, 2)),
+             ((1, 1, 8, 1, 1, 1, 0, 0), (1, 1, 8, 1, 1, 1, 3, 3))]
     for plain, bits in pairs:
         out = []
         for cfg in (plain, bits):
