@@ -33,6 +33,7 @@ __all__ = [
     "power_norm", "rho_sequence", "rho_value", "init_state", "pdhg_step",
     "residuals", "philox4x32_10", "uniforms24", "sample_bits", "pack_bits",
     "unpack_bits", "evaluate", "incumbent_update", "round_candidate", "run_gfors",
+    "tu_reformulate", "monotone_rows", "monotone_relax", "monotone_repair",
     "M0", "M1", "W0", "W1",
 ]
 
@@ -564,3 +565,79 @@ def tu_reformulate(P, pivots):
 
 def I_dense(M) -> np.ndarray:
     return _int_csr(M).toarray()
+
+
+# ----------------------------------------------------------------------------
+# Monotone relaxation (Sec. 2.4, "Monotone Relaxation"), Q = 0
+# ----------------------------------------------------------------------------
+
+def monotone_rows(P) -> np.ndarray:
+    """Which equality rows may be relaxed from "= 1" to ">= 1" (reading of the
+    monotone relaxation for set-partitioning rows, with the repair below).
+
+    Equality row j qualifies when all its coefficients are +1 and d_j = 1,
+    every variable in it has c_i >= 0, no variable of it lies in another
+    qualifying row, and every other row holding one of its variables is an
+    inequality row with a non-positive coefficient on it.  Then lowering a
+    variable of the row to 0 keeps every other row satisfied and does not raise
+    the objective, so the relaxed problem has the same optimum.  Q must be 0.
+    Returns a bool mask over the equality rows."""
+    m2 = 0 if P.B is None else P.B.nrows
+    ok = np.zeros(m2, dtype=bool)
+    if m2 == 0 or P.Q is not None:
+        return ok
+    Bd = I_dense(P.B)
+    Ad = I_dense(P.A) if P.A is not None else np.zeros((0, P.n), dtype=np.int64)
+    cand = np.array([np.all(Bd[j][Bd[j] != 0] == 1) and P.d[j] == 1 and np.any(Bd[j] != 0)
+                     for j in range(m2)], dtype=bool)
+    use = np.zeros(P.n, dtype=np.int64)               # qualifying rows per variable
+    for j in np.nonzero(cand)[0]:
+        use[Bd[j] != 0] += 1
+    for j in np.nonzero(cand)[0]:
+        vs = np.nonzero(Bd[j])[0]
+        good = bool(np.all(P.c[vs] >= 0) and np.all(use[vs] == 1))
+        # other equality rows must not hold these variables
+        others = [k for k in range(m2) if k != j]
+        if others and np.any(Bd[others][:, vs] != 0):
+            good = False
+        if Ad.shape[0] and np.any(Ad[:, vs] > 0):
+            good = False
+        ok[j] = good
+    return ok
+
+
+def monotone_relax(P):
+    """The relaxed problem: qualifying equality rows become inequality rows
+    ">= 1", appended after the inequality rows.  Returns (P', mask)."""
+    from paper_2510_27117_amd import instances as Inst   # data containers only
+    mask = monotone_rows(P)
+    if not np.any(mask):
+        return P, mask
+    Ad = I_dense(P.A) if P.A is not None else np.zeros((0, P.n), dtype=np.int64)
+    Bd = I_dense(P.B)
+    Anew = np.vstack([Ad, Bd[mask]])
+    bnew = np.concatenate([P.b if P.A is not None else np.zeros(0, np.int64), P.d[mask]])
+    Pn = Inst.BIP(n=P.n, c=P.c.copy(), name=P.name + "_mono")
+    Pn.A = Inst.csr_from_dense(Anew)
+    Pn.b = bnew.astype(np.int64)
+    keep = ~mask
+    if np.any(keep):
+        Pn.B = Inst.csr_from_dense(Bd[keep])
+        Pn.d = P.d[keep].astype(np.int64)
+    return Pn, mask
+
+
+def monotone_repair(P, mask, x) -> np.ndarray:
+    """Map a point of the relaxed problem back: in every relaxed row with
+    more than one variable set, keep the cheapest (lowest cost, then lowest
+    index) and set the others to 0.  A row with none set is left as it is."""
+    x = np.asarray(x, dtype=np.int64).copy()
+    Bd = I_dense(P.B)
+    for j in np.nonzero(mask)[0]:
+        vs = np.nonzero(Bd[j])[0]
+        on = vs[x[vs] == 1]
+        if on.size > 1:
+            keep = on[np.lexsort((on, P.c[on]))[0]]
+            x[on] = 0
+            x[keep] = 1
+    return x
