@@ -48,6 +48,8 @@ def parse():
                     help="run a plain 512 MiB device copy first (scale for HBM byte counters)")
     ap.add_argument("--ufl-eval", default="1000,10000",
                     help="ufl_learned: facilities,customers of the evaluation instance")
+    ap.add_argument("--relax", choices=["tu", "mono"], default="tu",
+                    help="ufl_learned: TU reformulation or monotone relaxation of the customer rows")
     ap.add_argument("--snap-window", default=None,
                     help="ufl_learned: first,last fraction of each training run to take iterates from")
     ap.add_argument("--train-instances", type=int, default=200)
@@ -55,6 +57,14 @@ def parse():
     ap.add_argument("--seq-sample", type=int, default=8,
                     help="batched workloads: instances run one by one for the comparison")
     return ap.parse_args()
+
+
+def _csr_dot(M, x):
+    """Row sums M x of an integer CSR (reporting only)."""
+    import scipy.sparse as sp
+    val = np.ones(M.nnz, dtype=np.int64) if M.val is None else np.asarray(M.val, dtype=np.int64)
+    S = sp.csr_matrix((val, np.asarray(M.col), np.asarray(M.row_ptr)), shape=(M.nrows, M.ncols))
+    return S @ np.asarray(x, dtype=np.int64)
 
 
 def kernel_bytes(bip, K):
@@ -187,10 +197,17 @@ def learned_experiment(a):
     from paper_2510_27117_amd import gfors, instances, learned
     t0 = time.perf_counter()
     train_prm = gfors.default_params(k_int=50, K_max=256)
+    def reform(P):
+        if a.relax == "mono":
+            m = gfors.MonotoneRelaxation(P)
+            return m.model, m, 0
+        t = gfors.TUReformulation(P, P.meta["tu_pivots"])
+        return t.model, t, t.constant
+
     bips = []
     for sd in range(1000, 1000 + a.train_instances):
         P = instances.facility_location(40, 400, seed=sd)
-        bips.append(gfors.TUReformulation(P, P.meta["tu_pivots"]).model)
+        bips.append(reform(P)[0])
     win = tuple(float(v) for v in a.snap_window.split(",")) if a.snap_window else (None, None)
     samples = learned.collect(bips, train_prm, rounds=60, K=256, snapshots=6, window=win)
     t_collect = time.perf_counter() - t0
@@ -204,23 +221,27 @@ def learned_experiment(a):
 
     nf, nc = (int(v) for v in a.ufl_eval.split(","))
     full = instances.facility_location(nf, nc, seed=a.seed)
-    tu = gfors.TUReformulation(full, full.meta["tu_pivots"])
+    model, rf, c0 = reform(full)
     prm = gfors.default_params(k_int=a.k_int, K_max=a.K)
-    G = gfors.Problem(tu.model, prm)
+    G = gfors.Problem(model, prm)
     R = a.tti_rounds
     plain = learned.run_plain(G, R, a.K)
     G.reset()
     lrn = learned.run_learned(G, net, R, a.K)
     G.final_round()
     best = G.best(0)
-    xfull = tu.recover(best["x"]) if best["found"] else None
-    c0 = tu.constant
+    if best["found"]:
+        xfull = rf.repair(best["x"]) if a.relax == "mono" else rf.recover(best["x"])
+    else:
+        xfull = None
     zp = [z + c0 if z != learned.INT64_MAX else None for z in plain.z]
     zl = [z + c0 if z != learned.INT64_MAX else None for z in lrn.z]
     res = {"metric": METRIC, "workload": "ufl_learned",
-           "config": {"workload": f"facility location {nf} x {nc} (TU: {nc} assignments eliminated)",
-                      "n_reduced": tu.model.n, "rows": tu.model.m1,
-                      "nnz": int(tu.model.A.nnz), "K": a.K, "k_int": a.k_int, "rounds": R,
+           "config": {"workload": (f"facility location {nf} x {nc} (TU: {nc} assignments eliminated)"
+                                   if a.relax == "tu" else
+                                   f"facility location {nf} x {nc} (customer rows relaxed to >= 1)"),
+                      "n_reduced": model.n, "rows": model.m1,
+                      "nnz": int(model.A.nnz), "K": a.K, "k_int": a.k_int, "rounds": R,
                       "train": f"{a.train_instances} instances 40 x 400, {len(samples)} pairs, {a.train_steps} Adam steps",
            "snapshot_window": list(win)},
            "collect_s": round(t_collect, 2), "train_s": round(t_train, 2),
@@ -263,7 +284,14 @@ def main():
         return
     t0 = time.perf_counter()
     tu = None
-    if a.workload == "ufl_tu":
+    mono = None
+    if a.workload == "ufl_mono":
+        # facility location with the customer rows relaxed to ">= 1" (monotone
+        # relaxation); incumbents are repaired to the original problem below
+        full = instances.workload("ufl", seed=a.seed)
+        mono = gfors.MonotoneRelaxation(full)
+        bip = mono.model
+    elif a.workload == "ufl_tu":
         # facility location after the TU reformulation (one assignment per
         # customer eliminated); objective values below are of the reduced model
         # and differ from the original ones by the constant c0
@@ -404,6 +432,17 @@ def main():
         "time_to_incumbent": tti,
         "cpu_baseline": base,
     }
+    if mono is not None:
+        out["config"]["relaxed_rows"] = int(mono.relaxed.sum())
+        G.final_round()
+        b = G.best(0)
+        if b["found"]:
+            xr = mono.repair(b["x"]).astype(np.int64)
+            orig = mono.source
+            viol = int(np.sum(_csr_dot(orig.A, xr) < orig.b)) if orig.A is not None else 0
+            viol += int(np.sum(_csr_dot(orig.B, xr) != orig.d)) if orig.B is not None else 0
+            tti["repaired"] = {"z_relaxed": int(b["z"]), "z_original": int(orig.c @ xr),
+                               "violated_original_rows": viol}
     if tu is not None:
         out["config"]["objective_constant"] = int(tu.constant)
         if tti.get("z_final") is not None:

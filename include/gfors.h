@@ -317,6 +317,28 @@ int gfors_tu_recover(gfors_tu *U, const uint8_t *x_reduced, uint8_t *x_full);
 void gfors_tu_destroy(gfors_tu *U);
 const char *gfors_tu_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Monotone relaxation (Sec. 2.4, "Monotone Relaxation"), host only, for
+ * set-partitioning equality rows  sum_{i in R} x_i = 1.  With a monotone
+ * objective such a row may become  >= 1  without changing the optimum, and a
+ * point of the relaxed problem is mapped back by a repair.
+ *
+ * gfors_mono_rows: relax[j] (uint8[m2], out) = 1 when equality row j has all
+ * coefficients +1, d_j = 1, each of its variables has c_i >= 0, lies in no
+ * other equality row and has no positive coefficient in any inequality row,
+ * and Q = 0; else 0.  The caller moves the marked rows into the inequality
+ * block with right-hand side 1 (the rows keep their coefficients).
+ * gfors_mono_repair: x (uint8[n], in/out): in every marked row with more than
+ * one variable set, the cheapest (lowest c, then lowest index) stays set and
+ * the others are cleared.  A relaxed-feasible point becomes feasible for the
+ * original rows with no larger objective.
+ * Errors: E_ARG (NULL pointer, bad CSR). */
+int gfors_mono_rows(const gfors_csr *A, const gfors_csr *B, const int64_t *d, const gfors_csr *Q,
+                    const int64_t *c, int64_t n, uint8_t *relax);
+int gfors_mono_repair(const gfors_csr *B, const uint8_t *relax, const int64_t *c, int64_t n,
+                      uint8_t *x);
+const char *gfors_mono_last_error(void);
+
 /* Dimensions: n, m1, m2, number of instances. */
 int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32_t *T);
 

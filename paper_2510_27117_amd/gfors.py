@@ -44,7 +44,7 @@ EXPORTS = [
     "gfors_gnn_forward", "gfors_gnn_grad", "gfors_gnn_adam", "gfors_gnn_train_step",
     "gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad",
     "gfors_tu_create", "gfors_tu_dims", "gfors_tu_export", "gfors_tu_recover", "gfors_tu_destroy",
-    "gfors_tu_last_error",
+    "gfors_tu_last_error", "gfors_mono_rows", "gfors_mono_repair", "gfors_mono_last_error",
 ]
 
 KERNEL_NAMES = ["dual", "primal", "sample", "eval_cover", "eval_general", "eval_quad",
@@ -112,10 +112,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_tu_destroy.restype = None
     L.gfors_tu_last_error.argtypes = []
     L.gfors_tu_last_error.restype = ctypes.c_char_p
+    L.gfors_mono_rows.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_int64, c_vp]
+    L.gfors_mono_repair.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int64, c_vp]
+    L.gfors_mono_last_error.argtypes = []
+    L.gfors_mono_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("gfors_default_params", "gfors_destroy_problem", "gfors_last_error",
-                        "gfors_gnn_destroy", "gfors_tu_destroy", "gfors_tu_last_error"):
+                        "gfors_gnn_destroy", "gfors_tu_destroy", "gfors_tu_last_error",
+                        "gfors_mono_last_error"):
             f.restype = c_i32
     _lib = L
     return L
@@ -495,6 +500,86 @@ class GNN:
 # ---------------------------------------------------------------------------
 # TU reformulation (host-side C++ in the library)
 # ---------------------------------------------------------------------------
+class MonotoneRelaxation:
+    """Monotone relaxation of set-partitioning equality rows (see
+    gfors_mono_rows): ``model`` is the relaxed BIP, the relaxed rows appended
+    to the inequality block with right-hand side 1; ``relaxed`` marks them
+    among the original equality rows; ``repair(x)`` maps a relaxed point back
+    (cheapest variable of each relaxed row kept).  The library decides and
+    repairs; this class only moves rows between the two blocks."""
+
+    def __init__(self, bip):
+        from . import instances as _inst
+        L = load_library()
+        keep: list = []
+        A = _csr(bip.A, keep)
+        B = _csr(bip.B, keep)
+        Q = _csr(bip.Q, keep)
+        m2 = 0 if bip.B is None else bip.B.nrows
+        d = None if bip.d is None else np.ascontiguousarray(bip.d, dtype=np.int64)
+        c = np.ascontiguousarray(bip.c, dtype=np.int64)
+        relax = np.zeros(max(m2, 1), dtype=np.uint8)
+        rc = L.gfors_mono_rows(ctypes.byref(A) if A else None, ctypes.byref(B) if B else None,
+                               _ptr(d), ctypes.byref(Q) if Q else None, _ptr(c), int(bip.n),
+                               _ptr(relax))
+        if rc != GFORS_OK:
+            raise GforsError(f"{_ERRS.get(rc, rc)}: {L.gfors_mono_last_error().decode()}")
+        self.relaxed = relax[:m2].astype(bool)
+        self.source = bip
+        self._c = c
+        model = _inst.BIP(n=bip.n, c=bip.c.copy(), Q=bip.Q, name=bip.name + "_mono")
+        if not self.relaxed.any():
+            model.A, model.b, model.B, model.d = bip.A, bip.b, bip.B, bip.d
+        else:
+            rel = np.nonzero(self.relaxed)[0]
+            kept = np.nonzero(~self.relaxed)[0]
+
+            def take(M, rows):
+                lens = np.array([M.row_ptr[r + 1] - M.row_ptr[r] for r in rows], dtype=np.int64)
+                rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+                idx = np.concatenate([np.arange(M.row_ptr[r], M.row_ptr[r + 1]) for r in rows]) \
+                    if len(rows) else np.zeros(0, np.int64)
+                col = np.asarray(M.col)[idx]
+                val = None if M.val is None else np.asarray(M.val)[idx]
+                return rp, col, val
+
+            rpR, colR, valR = take(bip.B, rel)
+            if bip.A is not None:
+                rpA = np.asarray(bip.A.row_ptr, dtype=np.int64)
+                colA = np.asarray(bip.A.col)
+                valA = np.ones(bip.A.nnz, np.int32) if bip.A.val is None else np.asarray(bip.A.val)
+                rp = np.concatenate([rpA, rpA[-1] + rpR[1:]])
+                col = np.concatenate([colA, colR])
+                val = np.concatenate([valA, np.ones(colR.size, np.int32) if valR is None else valR])
+                b = np.concatenate([np.asarray(bip.b, np.int64), np.asarray(bip.d, np.int64)[rel]])
+            else:
+                rp, col = rpR, colR
+                val = None if valR is None else valR
+                b = np.asarray(bip.d, np.int64)[rel]
+            model.A = _inst.CSR(len(rp) - 1, bip.n, rp, col.astype(np.int32),
+                                None if val is None else val.astype(np.int32))
+            model.b = b
+            if kept.size:
+                rpK, colK, valK = take(bip.B, kept)
+                model.B = _inst.CSR(kept.size, bip.n, rpK, colK.astype(np.int32),
+                                    None if valK is None else valK.astype(np.int32))
+                model.d = np.asarray(bip.d, np.int64)[kept]
+        self.model = model
+
+    def repair(self, x) -> np.ndarray:
+        xr = np.ascontiguousarray(np.asarray(x) != 0, dtype=np.uint8).copy()
+        if not self.relaxed.any():
+            return xr
+        keep: list = []
+        B = _csr(self.source.B, keep)
+        relax = np.ascontiguousarray(self.relaxed, dtype=np.uint8)
+        rc = load_library().gfors_mono_repair(ctypes.byref(B), _ptr(relax), _ptr(self._c),
+                                              int(self.source.n), _ptr(xr))
+        if rc != GFORS_OK:
+            raise GforsError(f"{_ERRS.get(rc, rc)}: {load_library().gfors_mono_last_error().decode()}")
+        return xr
+
+
 class TUReformulation:
     """Eliminates one pivot variable per chosen equality row (B_JI a signed
     identity, Q = 0).  ``model`` is the reformulated BIP (instances.BIP);
