@@ -47,6 +47,22 @@ __device__ __forceinline__ uint32_t bern_threshold(float p) {
     return static_cast<uint32_t>(ceilf(p * 16777216.0f));
 }
 
+// Lane v's 64-bit value as a wave-uniform one.
+__device__ __forceinline__ int64_t readlane64(int64_t x, int v) {
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint64_t>(x)), v);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint64_t>(x) >> 32), v);
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// A workgroup samples one tile of variables, 64 variables (a sub-tile) at a
+// time.  Every wavefront loads the sub-tile's p and costs itself (lane =
+// variable, one sub-tile ahead), so the variables' kinds are wave-uniform
+// ballots: the candidate loop visits only the fractional variables, whose
+// threshold and cost come from their lane.  The four wavefronts split the
+// candidate groups (4 candidates per Philox call); a lane's 4 bits and its
+// neighbour's form one byte of the variable's row in LDS.  Rows of
+// deterministic variables are written as constants during the copy-out.  The
+// LDS rows are double-buffered (one barrier per sub-tile) when two buffers fit.
 template <typename ACC>
 __global__ void __launch_bounds__(256)
 k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
@@ -54,11 +70,9 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
          const int *__restrict__ tile_q0, const int *__restrict__ tile_q1,
          const int64_t *__restrict__ inst_var0, const int64_t *__restrict__ inst_nvar,
          int64_t *__restrict__ zpart, int K, uint32_t key0, uint32_t key1,
-         const DevCounters *__restrict__ ctr, int threshold_mode, uint8_t *__restrict__ xkind) {
-    extern __shared__ uint64_t lds[];   // [64 variables][W words]
-    __shared__ uint32_t sthr[64];       // thresholds of the sub-tile's 64 variables
-    __shared__ ACC scost[64];
-    __shared__ uint8_t sdet[64];        // 0: fractional, 1: all zero, 2: all one
+         const DevCounters *__restrict__ ctr, int threshold_mode, uint8_t *__restrict__ xkind,
+         uint64_t wdiv, int nbuf) {
+    extern __shared__ uint64_t lds[];   // nbuf buffers of [64 variables][W words]
     const int tile = blockIdx.x;
     const int inst = tile_inst[tile];
     const int q0 = tile_q0[tile], q1 = tile_q1[tile];
@@ -78,36 +92,51 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
 #pragma unroll
         for (int j = 0; j < 4; ++j) zacc[t][j] = 0;
     ACC zconst = 0;                     // variables sampled as all ones
+    const size_t bufw = static_cast<size_t>(64) * W;
 
+    float pn = 0.f;
+    int64_t cn = 0;
+    {
+        const int64_t il = 4LL * q0 + lane;
+        if (q0 < q1 && il < nv) { pn = p[v0 + il]; cn = cost[v0 + il]; }
+    }
+    int buf = 0;
     for (int sq = q0; sq < q1; sq += 16) {
         const int nq = min(16, q1 - sq);
         const int64_t il0 = 4LL * sq;
         const int nvars = static_cast<int>(min<int64_t>(4LL * nq, nv - il0));
-        if (threadIdx.x < 64) {
-            const bool in = threadIdx.x < nvars;
-            const uint32_t th = in ? bern_threshold(p[v0 + il0 + threadIdx.x]) : 0u;
-            sthr[threadIdx.x] = th;
-            scost[threadIdx.x] = in ? static_cast<ACC>(cost[v0 + il0 + threadIdx.x]) : static_cast<ACC>(0);
-            uint8_t d;
-            if (threshold_mode) d = (0x800000u < th) ? 2 : 1;     // u = 1/2: [p > 1/2]
-            else d = th == 0u ? 1 : (th == (1u << 24) ? 2 : 0);
-            sdet[threadIdx.x] = in ? d : 1;
-            if (in) xkind[v0 + il0 + threadIdx.x] = d;
-        }
-        __syncthreads();
-        // all-one variables add their cost to every candidate
+        const float pv = pn;
+        const int64_t cv = cn;
         {
-            const ACC c = (lane < nvars && sdet[lane] == 2) ? scost[lane] : static_cast<ACC>(0);
-            ACC t = c;
+            const int64_t il = il0 + 64 + lane;
+            const bool nx = sq + 16 < q1 && il < nv;
+            pn = nx ? p[v0 + il] : 0.f;
+            cn = nx ? cost[v0 + il] : 0;
+        }
+        const bool in = lane < nvars;
+        const uint32_t th = in ? bern_threshold(pv) : 0u;
+        int d;                          // 0: fractional, 1: all zero, 2: all one
+        if (threshold_mode) d = (0x800000u < th) ? 2 : 1;     // u = 1/2: [p > 1/2]
+        else d = th == 0u ? 1 : (th == (1u << 24) ? 2 : 0);
+        if (!in) d = 1;
+        const uint64_t fmask = __ballot(d == 0);
+        const uint64_t omask = __ballot(d == 2);
+        if (wave == 0 && in) xkind[v0 + il0 + lane] = static_cast<uint8_t>(d);
+        if (omask) {                                              // uniform
+            // all-one variables add their cost to every candidate
+            ACC t = d == 2 ? static_cast<ACC>(cv) : static_cast<ACC>(0);
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
             zconst += t;
         }
-        uint8_t *lrow = reinterpret_cast<uint8_t *>(lds);
-        for (int v = 0; v < nvars; ++v) {
-            if (sdet[v] != 0) continue;                            // uniform
-            const uint32_t th = sthr[v];
-            const ACC c = scost[v];
+        uint64_t *rows = lds + (nbuf == 2 ? buf : 0) * bufw;
+        uint8_t *lrow = reinterpret_cast<uint8_t *>(rows);
+        uint64_t fm = fmask;
+        while (fm) {                                              // uniform
+            const int v = __builtin_ctzll(fm);
+            fm &= fm - 1;
+            const uint32_t thv = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(th), v));
+            const ACC c = static_cast<ACC>(readlane64(cv, v));
             const uint32_t il = static_cast<uint32_t>(il0 + v);
 #pragma unroll
             for (int t = 0; t < SMAX; ++t) {
@@ -115,8 +144,8 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
                 if (64 * t >= per) break;                          // uniform
                 uint32_t r0 = static_cast<uint32_t>(g), r1 = il, r2 = round, r3 = static_cast<uint32_t>(inst);
                 philox10(r0, r1, r2, r3, key0, key1);
-                const uint32_t b0 = (r0 >> 8) < th, b1 = (r1 >> 8) < th;
-                const uint32_t b2 = (r2 >> 8) < th, b3 = (r3 >> 8) < th;
+                const uint32_t b0 = (r0 >> 8) < thv, b1 = (r1 >> 8) < thv;
+                const uint32_t b2 = (r2 >> 8) < thv, b3 = (r3 >> 8) < thv;
                 if (b0) zacc[t][0] += c;
                 if (b1) zacc[t][1] += c;
                 if (b2) zacc[t][2] += c;
@@ -131,11 +160,12 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
         const int total = nvars * W;
         uint64_t *dst = X + (v0 + il0) * W;
         for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-            const int v = idx / W;
-            const uint8_t d = sdet[v];
-            dst[idx] = d == 0 ? lds[idx] : (d == 2 ? ~0ull : 0ull);
+            const int v = static_cast<int>((static_cast<uint64_t>(idx) * wdiv) >> 32);   // idx / W
+            const bool fr = (fmask >> v) & 1ull, one = (omask >> v) & 1ull;
+            dst[idx] = fr ? rows[idx] : (one ? ~0ull : 0ull);
         }
-        __syncthreads();
+        if (nbuf == 2) buf ^= 1;
+        else __syncthreads();
     }
 #pragma unroll
     for (int t = 0; t < SMAX; ++t) {
@@ -153,12 +183,16 @@ void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64
                    uint64_t *X, const Tiles &st, const int64_t *inst_var0,
                    const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,
                    uint32_t key1, const DevCounters *ctr, int threshold_mode, uint8_t *xkind) {
-    if (!st.count) return;
-    const size_t lds = static_cast<size_t>(64) * W * sizeof(uint64_t);
+    if (!st.count || W < 1 || W > 64) return;
+    // idx / W = (idx * ceil(2^32 / W)) >> 32, exact for idx < 64 W <= 4096
+    const uint64_t wdiv = ((1ull << 32) + static_cast<uint64_t>(W) - 1) / static_cast<uint64_t>(W);
+    const size_t one = static_cast<size_t>(64) * W * sizeof(uint64_t);
+    const int nbuf = 2 * one <= 32 * 1024 ? 2 : 1;
+    const size_t lds = nbuf * one;
     if (obj64)
-        k_sample<int64_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode, xkind);
+        k_sample<int64_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode, xkind, wdiv, nbuf);
     else
-        k_sample<int32_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode, xkind);
+        k_sample<int32_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode, xkind, wdiv, nbuf);
 }
 
 // ---------------------------------------------------------------------------
