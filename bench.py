@@ -342,10 +342,8 @@ def main():
     stt = G.get_state()
     xs = stt["x"]
     xbar = 2.0 * xs - stt["x_prev"]
-    q = np.pad(xs, (0, (-xs.size) % 4), constant_values=0.0).reshape(-1, 4)
     xstats = {"frac_zero": float(np.mean(xs == 0.0)), "frac_one": float(np.mean(xs == 1.0)),
               "frac_fractional": float(np.mean((xs > 0) & (xs < 1))),
-              "quads_without_draws": float(np.mean(np.all((q == 0.0) | (q == 1.0), axis=1))),
               "xbar_zero": float(np.mean(xbar == 0.0)),
               "y_zero": float(np.mean(stt["y"] == 0.0)) if stt["y"].size else None}
 
@@ -361,11 +359,11 @@ def main():
         with open(a.traffic_file) as f:
             tr = json.load(f)
         # counters taken on the same workload, K and launch shape only
-        wl = tr.get(a.workload, {})
         cfg_now = list(G.launch_cfg().values())
-        ent = wl.get(dom)
-        if ent and ent.get("K") == a.K and wl.get("launch_cfg") == cfg_now:
-            traffic = ent.get("bytes_per_launch")
+        for wl in tr.get(a.workload, {}).get("runs", []):
+            ent = wl.get(dom)
+            if ent and ent.get("K") == a.K and wl.get("launch_cfg") == cfg_now:
+                traffic = ent.get("bytes_per_launch")
     except (OSError, ValueError):
         pass
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
