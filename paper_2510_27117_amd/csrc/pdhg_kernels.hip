@@ -59,28 +59,42 @@ k_dual(int m, int m1, const int *__restrict__ rp, const int *__restrict__ ci,
     }
 }
 
+// Slot of workgroup b in a list processed one item per workgroup: groups of
+// 16 consecutive slots run on one XCD (workgroup b runs on XCD b % 8) and the
+// groups are dealt to the XCDs in turn.  Consecutive heavy rows or variables
+// often gather neighbouring elements (one cache line serves up to 16 of them),
+// which then meet in one L2 instead of eight.  A bijection on [0, 128 k).
+__device__ __forceinline__ int xcd_grouped_slot(int b) {
+    const int x = b & 7, k = b >> 3;
+    return ((((k >> 4) << 3) + x) << 4) + (k & 15);
+}
+
+constexpr int kLongUnroll = 4;   // loads in flight per lane in the heavy kernels
+
 // Dual step for long rows: a workgroup of 256 lanes per row (rows taken
-// longest first from `order`, so that the longest rows do not trail), lanes
-// strided over the row with four independent loads in flight each, partial
-// sums combined by shuffles inside each wavefront and then across the four
-// wavefronts in a fixed order.
+// longest first from `order`, so that the longest rows do not trail; slots
+// grouped per XCD), lanes strided over the row with four independent loads
+// in flight each, partial sums combined by shuffles inside each wavefront and
+// then across the four wavefronts in a fixed order.
 template <bool UNIT, bool BATCH>
 __global__ void __launch_bounds__(256)
-k_dual_long(int m1, const int *__restrict__ order, const int *__restrict__ rp,
+k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restrict__ rp,
             const int *__restrict__ ci, const int *__restrict__ val,
             const float *__restrict__ omega, const float *__restrict__ rt,
             const float *__restrict__ xbar, const float *__restrict__ y_in,
             float *__restrict__ y_out, float *__restrict__ wy, float tau2,
             const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
     __shared__ float ws[4];
-    const int row = order[blockIdx.x];
+    const int slot = xcd_grouped_slot(blockIdx.x);
+    if (slot >= count) return;                          // uniform per workgroup
+    const int row = order[slot];
     const int e0 = rp[row], e1 = rp[row + 1];
     float s = 0.f;
-    for (int eb = e0 + static_cast<int>(threadIdx.x); eb < e1; eb += 4 * 256) {
-        float xv[4];
-        int a[4];
+    for (int eb = e0 + static_cast<int>(threadIdx.x); eb < e1; eb += kLongUnroll * 256) {
+        float xv[kLongUnroll];
+        int a[kLongUnroll];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kLongUnroll; ++u) {
             const int e = min(eb + 256 * u, e1 - 1);
             const float v = xbar[ci[e]];
             const bool in = eb + 256 * u < e1;
@@ -88,7 +102,7 @@ k_dual_long(int m1, const int *__restrict__ order, const int *__restrict__ rp,
             a[u] = UNIT ? 1 : (in ? val[e] : 0);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kLongUnroll; ++u) {
             if (UNIT) s += xv[u];
             else s = fmaf(static_cast<float>(a[u]), xv[u], s);
         }
@@ -113,7 +127,8 @@ void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, con
                       const float *rt, const float *xbar, const float *y_in, float *y_out,
                       float *wy, float tau2, const float *tau2_inst, const int *row_inst) {
     if (m <= 0) return;
-#define GF_DL(U, B) k_dual_long<U, B><<<m, 256, 0, s>>>(m1, order, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
+    const int grid = ((m + 127) / 128) * 128;
+#define GF_DL(U, B) k_dual_long<U, B><<<grid, 256, 0, s>>>(m, m1, order, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
     if (unit) { if (batched) GF_DL(true, true); else GF_DL(true, false); }
     else { if (batched) GF_DL(false, true); else GF_DL(false, false); }
 #undef GF_DL
@@ -124,21 +139,23 @@ void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, con
 // k_dual_long.  The iteration counter is advanced by the companion kernel.
 template <bool UNIT, bool BATCH>
 __global__ void __launch_bounds__(256)
-k_primal_long(const int *__restrict__ order, const int *__restrict__ rpT,
+k_primal_long(int count, const int *__restrict__ order, const int *__restrict__ rpT,
               const int *__restrict__ ciT, const int *__restrict__ valT,
               const float *__restrict__ wy, const float *__restrict__ x_in,
               float *__restrict__ x_out, float *__restrict__ xbar, const float *__restrict__ ct,
               float tau1, const float *__restrict__ tau1_inst, const double *__restrict__ rho,
               const int *__restrict__ var_inst) {
     __shared__ float ws[4];
-    const int i = order[blockIdx.x];
+    const int slot = xcd_grouped_slot(blockIdx.x);
+    if (slot >= count) return;                          // uniform per workgroup
+    const int i = order[slot];
     const int e0 = rpT[i], e1 = rpT[i + 1];
     float s = 0.f;
-    for (int eb = e0 + static_cast<int>(threadIdx.x); eb < e1; eb += 4 * 256) {
-        float w[4];
-        int a[4];
+    for (int eb = e0 + static_cast<int>(threadIdx.x); eb < e1; eb += kLongUnroll * 256) {
+        float w[kLongUnroll];
+        int a[kLongUnroll];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kLongUnroll; ++u) {
             const int e = min(eb + 256 * u, e1 - 1);
             const float v = wy[ciT[e]];
             const bool in = eb + 256 * u < e1;
@@ -146,7 +163,7 @@ k_primal_long(const int *__restrict__ order, const int *__restrict__ rpT,
             a[u] = UNIT ? 1 : (in ? valT[e] : 0);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kLongUnroll; ++u) {
             if (UNIT) s += w[u];
             else s = fmaf(static_cast<float>(a[u]), w[u], s);
         }
@@ -172,7 +189,8 @@ void launch_primal_long(hipStream_t s, bool unit, bool batched, int count, const
                         const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
                         const float *tau1_inst, const double *rho, const int *var_inst) {
     if (count <= 0) return;
-#define GF_PL(U, B) k_primal_long<U, B><<<count, 256, 0, s>>>(order, rpT, ciT, valT, wy, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst)
+    const int grid = ((count + 127) / 128) * 128;
+#define GF_PL(U, B) k_primal_long<U, B><<<grid, 256, 0, s>>>(count, order, rpT, ciT, valT, wy, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst)
     if (unit) { if (batched) GF_PL(true, true); else GF_PL(true, false); }
     else { if (batched) GF_PL(false, true); else GF_PL(false, false); }
 #undef GF_PL
