@@ -369,6 +369,19 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": kb[dom], "avg_launch_ms": avg_ms}
+    # the sampler is integer-ALU bound (Philox): its generator calls per second
+    # at the measured state (fractional variables x K/4 calls per launch)
+    # against the generator's own throughput on this device
+    sampler_alu = None
+    if kt.get("sample", (0.0, 0))[1]:
+        calls = int(round(xstats["frac_fractional"] * bip.n)) * (a.K // 4)
+        peak = gfors.philox_throughput()
+        ach = calls / (kt["sample"][0] * 1e-3)
+        sampler_alu = {"bound": "alu", "kernel": "sample", "achieved": round(ach, 1),
+                       "peak": round(peak, 1), "unit": "Philox4x32-10 calls/s",
+                       "frac": round(ach / peak, 4) if peak > 0 else None,
+                       "calls_per_launch": calls, "avg_launch_ms": kt["sample"][0],
+                       "peak_source": "gfors_philox_throughput (generator alone, same counter shape)"}
     kernels = {k: {"avg_ms": round(ms, 5), "launches": cnt,
                    "gbs": (round(kb[k] / (ms * 1e-3) / 1e9, 1) if k in kb and ms > 0 else None)}
                for k, (ms, cnt) in kt.items() if cnt}
@@ -425,7 +438,7 @@ def main():
         "candidates_per_s": round(cands_per_s, 1),
         "wall_s_timed": round(wall, 4),
         "preprocess_s": round(t_pre, 3), "generate_s": round(t_gen, 3),
-        "roofline": roofline, "kernels": kernels, "launch_cfg": G.launch_cfg(),
+        "roofline": roofline, "sampler_alu": sampler_alu, "kernels": kernels, "launch_cfg": G.launch_cfg(),
         "iterate_stats": xstats,
         "time_to_incumbent": tti,
         "cpu_baseline": base,

@@ -207,6 +207,16 @@ int gfors_get_scales(gfors_problem *P, double *row_scale, double *obj_scale, dou
 int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_ms,
                        int32_t *launches);
 
+/* Profiling support: throughput of the sampler's uniform generator alone
+ * (Philox4x32-10 of Algorithm 3's candidate draws, one call = four uniforms),
+ * the peak against which the sampler's achieved rate is reported.  Enqueues a
+ * warm-up and a timed launch of about `calls` generator evaluations on
+ * `hip_stream` (a hipStream_t, NULL = default stream), synchronises, and
+ * writes calls per second.  dev_sink: device memory of at least 4 bytes,
+ * owned by the caller (written at most once, contents meaningless).
+ * Errors: GFORS_E_ARG for calls <= 0 or NULL pointers, GFORS_E_HIP. */
+int gfors_philox_throughput(void *hip_stream, int64_t calls, void *dev_sink, double *calls_per_s);
+
 /* Launch shapes in use: out[8] = {lanes per row of the dual SpMV, lanes per row
  * of the primal SpMV, column slices of the dual SpMV, slices of the primal,
  * SELL-64 layout for the dual (0/1), SELL-64 layout for the primal (0/1),

@@ -1576,6 +1576,32 @@ int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_
     return GFORS_OK;
 }
 
+int gfors_philox_throughput(void *hip_stream, int64_t calls, void *dev_sink, double *calls_per_s) {
+    if (calls <= 0 || !dev_sink || !calls_per_s) return fail(GFORS_E_ARG, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int blocks = 8 * 256;                         // 8 workgroups of 256 lanes per CU
+    const int64_t lanes = static_cast<int64_t>(blocks) * 256;
+    const int64_t it64 = (calls + lanes - 1) / lanes;
+    if (it64 > (1LL << 30)) return fail(GFORS_E_ARG, "calls too large");
+    const int iters = static_cast<int>(it64);
+    uint32_t *sink = static_cast<uint32_t *>(dev_sink);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    launch_philox_peak(s, blocks, iters, sink);        // warm-up
+    HIP_TRY(hipEventRecord(e0, s));
+    launch_philox_peak(s, blocks, iters, sink);
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    HIP_TRY(hipEventDestroy(e0));
+    HIP_TRY(hipEventDestroy(e1));
+    HIP_TRY(hipGetLastError());
+    *calls_per_s = ms > 0.f ? static_cast<double>(lanes) * iters / (ms * 1e-3) : 0.0;
+    return GFORS_OK;
+}
+
 int gfors_autotune(gfors_problem *P) {
     if (!P) return fail(GFORS_E_ARG, "NULL handle");
     P->graphs_clear();

@@ -166,6 +166,7 @@ void launch_res_vars(hipStream_t s, const Tiles &vt, const int *rpQ, const int *
                      const double *tau1d, const double *two_sod, double *part);
 
 // --------------------------------------------------------- sampling / eval
+void launch_philox_peak(hipStream_t s, int blocks, int iters, uint32_t *sink);
 void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64_t *cost,
                    uint64_t *X, const Tiles &st, const int64_t *inst_var0,
                    const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,

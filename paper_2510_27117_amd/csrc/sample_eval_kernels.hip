@@ -195,6 +195,26 @@ void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64
         k_sample<int32_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode, xkind, wdiv, nbuf);
 }
 
+// Throughput of the uniform generator alone (the sampler's ALU roofline): each
+// lane evaluates Philox4x32-10 `iters` times with the sampler's counter shape
+// (one word per lane, three wave-uniform words) and folds the outputs into a
+// word that is stored only if it hits a fixed value, so nothing is skipped.
+__global__ void __launch_bounds__(256)
+k_philox_peak(int iters, uint32_t key0, uint32_t key1, uint32_t *__restrict__ sink) {
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    uint32_t acc = 0u;
+    for (int it = 0; it < iters; ++it) {
+        uint32_t r0 = g, r1 = static_cast<uint32_t>(it), r2 = key1 ^ 0x5bd1e995u, r3 = 0u;
+        philox10(r0, r1, r2, r3, key0, key1);
+        acc ^= (r0 ^ r1) ^ (r2 ^ r3);
+    }
+    if (acc == 0x9e3779b9u) sink[0] = g;
+}
+
+void launch_philox_peak(hipStream_t s, int blocks, int iters, uint32_t *sink) {
+    if (blocks > 0 && iters > 0) k_philox_peak<<<blocks, 256, 0, s>>>(iters, 0x243f6a88u, 0x85a308d3u, sink);
+}
+
 // ---------------------------------------------------------------------------
 // Rows whose violation is a bitwise function of the candidate words (64
 // candidates per word):

@@ -45,6 +45,7 @@ EXPORTS = [
     "gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad",
     "gfors_tu_create", "gfors_tu_dims", "gfors_tu_export", "gfors_tu_recover", "gfors_tu_destroy",
     "gfors_tu_last_error", "gfors_mono_rows", "gfors_mono_repair", "gfors_mono_last_error",
+    "gfors_philox_throughput",
 ]
 
 KERNEL_NAMES = ["dual", "primal", "sample", "eval_cover", "eval_general", "eval_quad",
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_tu_last_error.restype = ctypes.c_char_p
     L.gfors_mono_rows.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_int64, c_vp]
     L.gfors_mono_repair.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int64, c_vp]
+    L.gfors_philox_throughput.argtypes = [c_vp, c_i64, c_vp, P(c_dbl)]
     L.gfors_mono_last_error.argtypes = []
     L.gfors_mono_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -148,6 +150,20 @@ def default_params(**overrides) -> gfors_params:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+def philox_throughput(calls: int = 2_000_000_000, device: str = "cuda:0") -> float:
+    """Calls per second of the sampler's Philox4x32-10 generator alone on the
+    device (the peak for the sampler's ALU roofline)."""
+    import torch
+    L = load_library()
+    dev = torch.device(device)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = c_dbl(0.0)
+    _check(L.gfors_philox_throughput(ctypes.c_void_p(stream.cuda_stream), int(calls),
+                                     ctypes.c_void_p(sink.data_ptr()), ctypes.byref(out)))
+    return float(out.value)
 
 
 def _csr(M, keep: list):
