@@ -22,6 +22,16 @@
 
 namespace gfors {
 
+// Pointers into the constant address space: loads at wave-uniform addresses
+// through them become scalar loads.  Only for data no kernel writes while it
+// is being read.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> to_const(const T *p) {
+    return reinterpret_cast<cptr<T>>(reinterpret_cast<uintptr_t>(p));
+}
+
 __device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
                                          uint32_t &c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -427,13 +437,24 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
                   const uint64_t *__restrict__ X, const uint8_t *__restrict__ xkind,
                   int *__restrict__ vpart, int K) {
     __shared__ ACC part[4][WW][64];
+    // the rows, coefficients, kind bytes and candidate words are read at
+    // wave-uniform addresses and not written by this kernel: through the
+    // constant address space they are scalar loads (no vector address work)
+    const cptr<int> ci_c = to_const(ci);
+    const cptr<int> val_c = to_const(val);
+    // the sampler writes every variable's words, constant rows included, so the
+    // words are loaded unconditionally: no dependent kind lookup per entry
+    (void)xkind;
+    const cptr<uint64_t> X_c = to_const(X);
     const int tile = tile_ids[blockIdx.x];
     const int r0 = tb0[tile], r1 = tb1[tile];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const unsigned sh = lane & 31;
-    // lanes 0-31 read the low halves of the candidate words, lanes 32-63 the
-    // high halves; sbfe turns bit sh into a 0 / -1 mask for the coefficient
-    const uint32_t *X32 = reinterpret_cast<const uint32_t *>(X) + (lane >> 5);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));   // wave-uniform
+    const unsigned sh = lane & 31, hs = lane & 32;
+    // a candidate word is the same for the whole wavefront (lane = candidate):
+    // it is loaded at a uniform address (scalar loads), shifted right by 0 or
+    // 32 for the lane's half, and sbfe turns bit sh into a 0 / -1 mask for the
+    // coefficient
     int vc[WW];
 #pragma unroll
     for (int w = 0; w < WW; ++w) vc[w] = 0;
@@ -450,28 +471,22 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
             int c[4], a[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                c[u] = ci[e + u];
-                a[u] = val ? val[e + u] : 1;
+                c[u] = ci_c[e + u];
+                a[u] = val ? val_c[e + u] : 1;
             }
-            // deterministic variables (all candidates 0 / 1) need no load
-            uint32_t xh[4][WW];
+            uint64_t xw[4][WW];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const uint8_t kd = xkind[c[u]];
-                if (kd == 0) {
-                    const uint32_t *xr = X32 + static_cast<int64_t>(c[u]) * (2 * WW);
+                const cptr<uint64_t> xr = X_c + static_cast<int64_t>(c[u]) * WW;
 #pragma unroll
-                    for (int w = 0; w < WW; ++w) xh[u][w] = xr[2 * w];
-                } else {
-#pragma unroll
-                    for (int w = 0; w < WW; ++w) xh[u][w] = kd == 2 ? 0xFFFFFFFFu : 0u;
-                }
+                for (int w = 0; w < WW; ++w) xw[u][w] = xr[w];
             }
 #pragma unroll
             for (int w = 0; w < WW; ++w) {
                 int t[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) t[u] = a[u] & __builtin_amdgcn_sbfe(static_cast<int>(xh[u][w]), sh, 1u);
+                for (int u = 0; u < 4; ++u)
+                    t[u] = a[u] & __builtin_amdgcn_sbfe(static_cast<int>(static_cast<uint32_t>(xw[u][w] >> hs)), sh, 1u);
                 if (sizeof(ACC) == 4) {
                     acc[w] += (t[0] + t[1]) + (t[2] + t[3]);
                 } else {
@@ -481,14 +496,12 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
             }
         }
         for (; e < q1; ++e) {
-            const int c = ci[e];
-            const int a = val ? val[e] : 1;
-            const uint8_t kd = xkind[c];
+            const int c = ci_c[e];
+            const int a = val ? val_c[e] : 1;
 #pragma unroll
             for (int w = 0; w < WW; ++w) {
-                const uint32_t xh = kd == 0 ? X32[(static_cast<int64_t>(c) * WW + w) * 2]
-                                            : (kd == 2 ? 0xFFFFFFFFu : 0u);
-                acc[w] += static_cast<ACC>(a & __builtin_amdgcn_sbfe(static_cast<int>(xh), sh, 1u));
+                const uint64_t xv = X_c[static_cast<int64_t>(c) * WW + w];
+                acc[w] += static_cast<ACC>(a & __builtin_amdgcn_sbfe(static_cast<int>(static_cast<uint32_t>(xv >> hs)), sh, 1u));
             }
         }
 #pragma unroll
