@@ -567,42 +567,45 @@ k_eval_quad(const int *__restrict__ tinst, const int *__restrict__ tb0,
     const int tile = blockIdx.x;
     const int i0 = tb0[tile], i1 = tb1[tile];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));   // wave-uniform
     const int NW = blockDim.x >> 6;
     const int sh = lane & 31;
-    const bool hi = lane >= 32;
+    const unsigned hs = lane & 32;      // the lane's half of a candidate word
+    // Q's rows and the candidate words are read at wave-uniform addresses and
+    // not written here: scalar loads through the constant address space
+    const cptr<int> rpQ_c = to_const(rpQ), ciQ_c = to_const(ciQ), valQ_c = to_const(valQ);
+    const cptr<uint64_t> X_c = to_const(X);
     for (int w = wave; w < W; w += NW) {
         int64_t z = 0;
         for (int i = i0; i < i1; ++i) {
-            const uint64_t wi = X[static_cast<int64_t>(i) * W + w];
+            const uint64_t wi = X_c[static_cast<int64_t>(i) * W + w];
             if (wi == 0) continue;           // no candidate of this word sets x_i
-            const uint32_t hw = hi ? static_cast<uint32_t>(wi >> 32) : static_cast<uint32_t>(wi);
-            const int xi = static_cast<int>((hw >> sh) & 1u);
+            const int xi = static_cast<int>((static_cast<uint32_t>(wi >> hs) >> sh) & 1u);
             int64_t acc = 0;
-            const int e1 = rpQ[i + 1];
-            int e = rpQ[i];
+            const int e1 = rpQ_c[i + 1];
+            int e = rpQ_c[i];
             // entries in groups of 8: indices, coefficients and candidate words
             // are uniform loads issued together
             for (; e + 8 <= e1; e += 8) {
                 int c[8], q[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    c[u] = ciQ[e + u];
-                    q[u] = valQ[e + u];
+                    c[u] = ciQ_c[e + u];
+                    q[u] = valQ_c[e + u];
                 }
                 uint64_t xw[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) xw[u] = X[static_cast<int64_t>(c[u]) * W + w];
+                for (int u = 0; u < 8; ++u) xw[u] = X_c[static_cast<int64_t>(c[u]) * W + w];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const uint32_t half = hi ? static_cast<uint32_t>(xw[u] >> 32) : static_cast<uint32_t>(xw[u]);
+                    const uint32_t half = static_cast<uint32_t>(xw[u] >> hs);
                     acc += ((half >> sh) & 1u) ? static_cast<int64_t>(q[u]) : 0;
                 }
             }
             for (; e < e1; ++e) {
-                const uint64_t word = X[static_cast<int64_t>(ciQ[e]) * W + w];
-                const uint32_t half = hi ? static_cast<uint32_t>(word >> 32) : static_cast<uint32_t>(word);
-                acc += ((half >> sh) & 1u) ? static_cast<int64_t>(valQ[e]) : 0;
+                const uint64_t word = X_c[static_cast<int64_t>(ciQ_c[e]) * W + w];
+                const uint32_t half = static_cast<uint32_t>(word >> hs);
+                acc += ((half >> sh) & 1u) ? static_cast<int64_t>(valQ_c[e]) : 0;
             }
             z += xi ? acc : 0;
         }
