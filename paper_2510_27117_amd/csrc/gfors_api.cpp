@@ -156,7 +156,7 @@ struct gfors_problem {
     // graphs: key = (K, parity)
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     void graphs_clear() {
-        for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
     }
 };
@@ -444,7 +444,7 @@ int gfors_workspace_bytes(int64_t n, int64_t m1, int64_t m2, int64_t nnzA, int64
 
 void gfors_destroy_problem(gfors_problem *P) {
     if (!P) return;
-    for (auto &kv : P->graphs) hipGraphExecDestroy(kv.second);
+    for (auto &kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
     delete P;
 }
 
@@ -1276,8 +1276,6 @@ static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *t
     hipStream_t s = P->stream;
     // a sequence never relies on bitmaps written before it
     P->bx_fresh = P->by_fresh = false;
-    const bool batched = P->T > 1;
-    const int kmode = P->m == 0 ? 0 : (P->unitK ? 1 : 2);
     for (int it = 0; it < nsteps; ++it) {
         const bool res = want_res && it == nsteps - 1;
         if (res) launch_copy_f32(s, P->xsave, P->xbar, P->n);
@@ -1334,7 +1332,7 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     TE(4);
     TB(5);
     if (P->hasQ)
-        launch_eval_quad(s, P->qt, P->d_inst_var0, P->rpQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K);
+        launch_eval_quad(s, P->qt, P->rpQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K);
     TE(5);
     TB(6);
     launch_reduce_cand(s, P->T, K, P->red_S, P->et, P->vpart, P->st, P->zpart, P->qt, P->zqpart,
@@ -1344,7 +1342,7 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     launch_argmin_update(s, P->T, K, W, P->viol, P->z, P->di, P->ctr, threshold ? 0 : (trigger ? 1 : 2));
     TE(7);
     TB(8);
-    launch_extract_best(s, P->n, P->T, P->var_inst, P->d_inst_var0, P->X, P->di, P->xbest);
+    launch_extract_best(s, P->n, P->T, P->var_inst, P->X, P->di, P->xbest);
     TE(8);
     P->lastK = K;
 }

@@ -179,7 +179,7 @@ void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const T
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,
                          const uint8_t *xkind, int W, int *vpart, int K, bool long_rows);
-void launch_eval_quad(hipStream_t s, const Tiles &qt, const int64_t *inst_var0,
+void launch_eval_quad(hipStream_t s, const Tiles &qt,
                       const int *rpQ, const int *ciQ, const int *valQ, const uint64_t *X,
                       int W, int64_t *zqpart, int K);
 void launch_reduce_cand(hipStream_t s, int T, int K, int S, const Tiles &et, const int *vpart,
@@ -188,8 +188,7 @@ void launch_reduce_cand(hipStream_t s, int T, int K, int S, const Tiles &et, con
                         int32_t *viol, int64_t *z);
 void launch_argmin_update(hipStream_t s, int T, int K, int W, const int32_t *viol,
                           const int64_t *z, DevInst di, DevCounters *ctr, int advance);
-void launch_extract_best(hipStream_t s, int64_t n, int T, const int *var_inst,
-                         const int64_t *inst_var0, const uint64_t *X, DevInst di,
-                         uint8_t *xbest);
+void launch_extract_best(hipStream_t s, int64_t n, int T, const int *var_inst, const uint64_t *X,
+                         DevInst di, uint8_t *xbest);
 
 }  // namespace gfors

@@ -1035,7 +1035,7 @@ void launch_tile_sumsq(hipStream_t s, const Tiles &t, const double *x, double *p
 // out[inst*out_stride] = sum over the instance's tiles of part[tile*stride + comp]
 // (square-rooted if take_sqrt).  Fixed summation order: deterministic.
 __global__ void __launch_bounds__(256)
-k_inst_sum(int T, const int *__restrict__ first, const double *__restrict__ part, int stride,
+k_inst_sum(const int *__restrict__ first, const double *__restrict__ part, int stride,
            int comp, double *__restrict__ out, int out_stride, int take_sqrt) {
     __shared__ double sh[4];
     const int inst = blockIdx.x;
@@ -1047,7 +1047,7 @@ k_inst_sum(int T, const int *__restrict__ first, const double *__restrict__ part
 }
 void launch_inst_sum(hipStream_t s, int T, const Tiles &t, const double *part, int stride,
                      int comp, double *out, int out_stride, bool take_sqrt) {
-    if (T) k_inst_sum<<<T, 256, 0, s>>>(T, t.first, part, stride, comp, out, out_stride, take_sqrt ? 1 : 0);
+    if (T) k_inst_sum<<<T, 256, 0, s>>>(t.first, part, stride, comp, out, out_stride, take_sqrt ? 1 : 0);
 }
 
 // x[i] /= nrm[inst(tile)] for each tile's range; a zero norm leaves x untouched.

@@ -560,7 +560,7 @@ void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const T
 //   sum_i x_i (sum_k Q_ik x_k) over the variables i of a tile.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024)
-k_eval_quad(const int *__restrict__ tinst, const int *__restrict__ tb0,
+k_eval_quad(const int *__restrict__ tb0,
             const int *__restrict__ tb1, const int *__restrict__ rpQ,
             const int *__restrict__ ciQ, const int *__restrict__ valQ,
             const uint64_t *__restrict__ X, int W, int64_t *__restrict__ zq, int K) {
@@ -613,13 +613,12 @@ k_eval_quad(const int *__restrict__ tinst, const int *__restrict__ tb0,
     }
 }
 
-void launch_eval_quad(hipStream_t s, const Tiles &qt, const int64_t *inst_var0,
+void launch_eval_quad(hipStream_t s, const Tiles &qt,
                       const int *rpQ, const int *ciQ, const int *valQ, const uint64_t *X,
                       int W, int64_t *zqpart, int K) {
-    (void)inst_var0;
     if (!qt.count) return;
     const int NW = W <= 16 ? W : 16;
-    k_eval_quad<<<qt.count, NW * 64, 0, s>>>(qt.inst, qt.b0, qt.b1, rpQ, ciQ, valQ, X, W, zqpart, K);
+    k_eval_quad<<<qt.count, NW * 64, 0, s>>>(qt.b0, qt.b1, rpQ, ciQ, valQ, X, W, zqpart, K);
 }
 
 // ---------------------------------------------------------------------------
@@ -716,7 +715,7 @@ k_argmin_update(int K, int W, const int32_t *__restrict__ viol, const int64_t *_
     bl[threadIdx.x] = bi;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+        if (static_cast<int>(threadIdx.x) < o) {
             const int64_t z2 = bz[threadIdx.x + o];
             const int l2 = bl[threadIdx.x + o];
             if (z2 < bz[threadIdx.x] || (z2 == bz[threadIdx.x] && l2 < bl[threadIdx.x])) {
@@ -761,8 +760,7 @@ void launch_argmin_update(hipStream_t s, int T, int K, int W, const int32_t *vio
 
 // x_best of every instance whose incumbent just improved: byte per variable.
 __global__ void __launch_bounds__(256)
-k_extract_best(int64_t n, int T, const int *__restrict__ var_inst,
-               const int64_t *__restrict__ inst_var0, const uint64_t *__restrict__ X,
+k_extract_best(int64_t n, int T, const int *__restrict__ var_inst, const uint64_t *__restrict__ X,
                DevInst di, uint8_t *__restrict__ xbest) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -775,13 +773,12 @@ k_extract_best(int64_t n, int T, const int *__restrict__ var_inst,
     }
 }
 
-void launch_extract_best(hipStream_t s, int64_t n, int T, const int *var_inst,
-                         const int64_t *inst_var0, const uint64_t *X, DevInst di,
+void launch_extract_best(hipStream_t s, int64_t n, int T, const int *var_inst, const uint64_t *X, DevInst di,
                          uint8_t *xbest) {
     int64_t b = (n + 255) / 256;
     if (b > 8192) b = 8192;
     if (b < 1) b = 1;
-    k_extract_best<<<static_cast<int>(b), 256, 0, s>>>(n, T, var_inst, inst_var0, X, di, xbest);
+    k_extract_best<<<static_cast<int>(b), 256, 0, s>>>(n, T, var_inst, X, di, xbest);
 }
 
 }  // namespace gfors
