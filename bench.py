@@ -13,7 +13,6 @@ Prints ONE JSON line (see the keys below).  Also measured:
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time

@@ -22,7 +22,7 @@ the rocRAND Philox engine, or the theorems' inequalities).
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field, replace
+from dataclasses import dataclass
 from typing import Optional
 
 import numpy as np

@@ -12,7 +12,6 @@ candidate goes through the same exact evaluation and incumbent update.
 """
 from __future__ import annotations
 
-import time
 from dataclasses import dataclass, field
 from typing import List, Optional
 
