@@ -468,12 +468,12 @@ def test_fused_bitmaps_over_many_steps(G):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["knapsack_long", "knapsack", "mixed", "setcover_bern"])
+@pytest.mark.parametrize("name", ["knapsack_long", "knapsack", "mixed", "setcover_bern", "knapsack_xl"])
 def test_workgroup_per_row_dual(G, name):
     """The dual with a workgroup per row (rows longest first, four loads in
     flight per lane) gives the teacher-forced step within tolerance, also on
-    short and empty rows."""
-    P = problems()[name]()
+    short and empty rows, and on rows of 9000 entries."""
+    P = (lambda: I.knapsack_multi(9000, 3, seed=12))() if name == "knapsack_xl" else problems()[name]()
     S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=31, keep_every=30)
     st, rho = traj[-1]
     s32 = f32_state(st)
@@ -561,14 +561,40 @@ def test_tu_facility_location_round(G):
     prob.close()
 
 
-@pytest.mark.parametrize("which", ["rows", "vars"])
+def _long_and_short_rows(n=9000, seed=7):
+    """Three dense general rows over all n variables next to 200 rows of 2-5
+    entries, both senses."""
+    rng = np.random.default_rng(seed)
+    A = [rng.integers(-9, 10, size=n) for _ in range(3)]
+    b = [int(rng.integers(-50, 50)) for _ in range(3)]
+    Bm, d = [], []
+    for t in range(200):
+        r = np.zeros(n, dtype=np.int64)
+        cols = rng.choice(n, size=int(rng.integers(2, 6)), replace=False)
+        r[cols] = rng.choice([-2, -1, 1, 2], size=cols.size)
+        if t % 4:
+            A.append(r); b.append(int(rng.integers(-2, 2)))
+        else:
+            Bm.append(r); d.append(int(rng.integers(-1, 2)))
+    c = rng.integers(-20, 30, size=n)
+    return I.from_dense(c, A=np.array(A), b=np.array(b), B=np.array(Bm), d=np.array(d), name="longshort")
+
+
+@pytest.mark.parametrize("which", ["rows", "vars", "rows_chunked", "vars_chunked"])
 def test_heavy_light_split(G, which):
     """Rows (variables) with 256+ entries handled by a workgroup each, the
     others by groups of lanes skipping them: the teacher-forced step stays
-    within tolerance for every light lane count."""
+    within tolerance for every light lane count, also for rows of 9000 entries
+    and facilities in 5000 rows."""
     if which == "rows":
         P = _bitwise_rows_problem(n=400, seed=5)         # four long general rows
         cfgs = [(256 + l, 4, 1, 1, 0, 0, 0, 0) for l in (1, 2, 8, 64)]
+    elif which == "rows_chunked":
+        P = _long_and_short_rows()
+        cfgs = [(256 + l, 4, 1, 1, 0, 0, 0, 0) for l in (1, 8)] + [(256, 4, 1, 1, 0, 0, 0, 0)]
+    elif which == "vars_chunked":
+        P = I.facility_location(3, 5000, seed=8)          # facilities in 5000 rows each
+        cfgs = [(16, 256 + l, 1, 1, 0, 0, 0, 0) for l in (1, 8)] + [(258, 258, 1, 1, 0, 0, 0, 0)]
     else:
         P = I.facility_location(30, 300, seed=6)          # facilities in 300 rows each
         cfgs = [(16, 256 + l, 1, 1, 0, 0, 0, 0) for l in (1, 2, 8, 64)] + [(258, 258, 1, 1, 0, 0, 0, 0)]
