@@ -30,7 +30,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "Params", "Scaled", "State", "Incumbent", "preprocess", "csr_to_scipy",
-    "power_norm", "rho_sequence", "rho_value", "init_state", "pdhg_step",
+    "power_norm", "rho_next", "rho_sequence", "rho_value", "init_state", "pdhg_step",
     "residuals", "philox4x32_10", "uniforms24", "sample_bits", "pack_bits",
     "unpack_bits", "evaluate", "incumbent_update", "round_candidate", "run_gfors",
     "tu_reformulate", "monotone_rows", "monotone_relax", "monotone_repair",
@@ -215,29 +215,33 @@ def preprocess(P, params: Params = Params()) -> Scaled:
 # UpdatePenalty (Sec. 3)
 # ----------------------------------------------------------------------------
 
-def rho_sequence(S_or_consts, count: int) -> list:
-    """rho_0 .. rho_{count-1} of UpdatePenalty (Sec. 3):
+def _rho_consts(S_or_consts):
+    if isinstance(S_or_consts, Scaled):
+        return (S_or_consts.rho_min, S_or_consts.rho_max, S_or_consts.rho_T,
+                S_or_consts.rho_p, S_or_consts.rho_delta)
+    return tuple(S_or_consts)
+
+
+def rho_next(S_or_consts, n: int, prev: float) -> float:
+    """One UpdatePenalty step (Sec. 3), n >= 1 sampling triggers so far:
 
       rho~_n = rho_min (1 + n/T)^p
-      rho_n  = clip(rho~_n, rho_{n-1} + delta, rho_max),  rho_0 = rho_min
+      rho_n  = clip(rho~_n, rho_{n-1} + delta, rho_max)
 
     clip(v, lo, hi) = min(max(v, lo), hi): the upper bound wins when the
-    increment floor passes rho_max (reading).  n counts sampling triggers."""
-    if isinstance(S_or_consts, Scaled):
-        rmin, rmax, T, p, delta = (S_or_consts.rho_min, S_or_consts.rho_max,
-                                   S_or_consts.rho_T, S_or_consts.rho_p, S_or_consts.rho_delta)
-    else:
-        rmin, rmax, T, p, delta = S_or_consts
+    increment floor passes rho_max (reading)."""
+    rmin, rmax, T, p, delta = _rho_consts(S_or_consts)
+    rt = rmin * (1.0 + n / T) ** p
+    return min(max(rt, prev + delta), rmax)
+
+
+def rho_sequence(S_or_consts, count: int) -> list:
+    """rho_0 .. rho_{count-1} of UpdatePenalty: rho_0 = rho_min, then
+    rho_next; n counts sampling triggers."""
+    rmin = _rho_consts(S_or_consts)[0]
     out = []
-    prev = None
     for nn in range(count):
-        if prev is None:
-            rho = rmin
-        else:
-            rt = rmin * (1.0 + nn / T) ** p
-            rho = min(max(rt, prev + delta), rmax)
-        out.append(rho)
-        prev = rho
+        out.append(rmin if nn == 0 else rho_next(S_or_consts, nn, out[-1]))
     return out
 
 

@@ -160,7 +160,7 @@ def test_round_from_iterate_and_incumbent(G, name):
             assert np.array_equal(b["x"].astype(bool), inc.x)
         # rho after the trigger follows UpdatePenalty from the value set
         got_rho = prob.get_state()["rho"][0]
-        exp_rho = min(max(S.rho_min * (1 + (r + 1) / S.rho_T) ** S.rho_p, rho + S.rho_delta), S.rho_max)
+        exp_rho = O.rho_next(S, r + 1, rho)
         assert abs(got_rho - exp_rho) <= 1e-12 * max(1.0, exp_rho)
     prob.close()
 
