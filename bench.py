@@ -24,6 +24,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PDHG iter/s + candidates/s; time-to-incumbent at fixed gap, learned vs plain"
 HBM_PEAK_GBS = 8000.0
+# single-instance workloads generated as they are (no reformulation), whose
+# time-to-incumbent is also taken over other instance seeds
+PLAIN_WORKLOADS = ("setcover_small", "setcover_large", "maxcut", "ufl")
 
 
 def parse():
@@ -38,6 +41,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tti-rounds", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tti-seeds", default="0,1,2,3,4",
+                    help="instance seeds whose time-to-incumbent is reported (median over them); "
+                         "single-instance plain workloads only, '' for the main seed alone")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
     ap.add_argument("--launch-cfg", default=None,
                     help="pin the SpMV launch shapes (8 comma-separated ints: lpr_dual, lpr_primal, "
@@ -94,6 +100,73 @@ def kernel_bytes(bip, K):
     return out
 
 
+VALU_LANE_OPS = 256 * 64 * 2.4e9   # lanes x clock of the 256 CUs: one integer op per lane per clock
+
+
+def general_row_nnz(bip):
+    """Entries of the rows evaluated lane = candidate (not as bitwise functions
+    of the candidate words: covering, at-most-one, exactly-one and rows of one
+    or two entries are)."""
+    tot = 0
+    for M, rhs in ((bip.A, bip.b), (bip.B, bip.d)):
+        if M is None or M.nrows == 0:
+            continue
+        rp = np.asarray(M.row_ptr, dtype=np.int64)
+        ln = np.diff(rp)
+        v = np.ones(int(rp[-1]), dtype=np.int64) if M.val is None else np.asarray(M.val, dtype=np.int64)
+        rows = np.repeat(np.arange(M.nrows), ln)
+        allone = np.bincount(rows, weights=(v == 1), minlength=M.nrows) == ln
+        allneg = np.bincount(rows, weights=(v == -1), minlength=M.nrows) == ln
+        r = np.asarray(rhs, dtype=np.int64)
+        # covering / at-most-one (inequalities), exactly-one (equalities), pairs
+        bitwise = (ln > 0) & (((allone & (r == 1)) | (allneg & (r == -1))) | (ln <= 2))
+        tot += int(ln[~bitwise].sum())
+    return tot
+
+
+def run_tti_rounds(G, R, K, use_graph):
+    """R sampling rounds from a reset; elapsed ms after each (HIP events)."""
+    import torch
+    G.reset()
+    stream = G.stream
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(R + 1)]
+    evs[0].record(stream)
+    for r in range(R):
+        G.run_rounds(1, K, use_graph)
+        evs[r + 1].record(stream)
+    G.synchronize()
+    return [evs[0].elapsed_time(evs[r + 1]) for r in range(R)]
+
+
+def single_tti(G, R, times, k_int):
+    """Time to an incumbent within 0.1 % of the value after R rounds."""
+    hist = G.history(0, R)
+    feas = np.nonzero(hist != np.iinfo(np.int64).max)[0]
+    if not feas.size:
+        return {"rounds": R, "z_final": None, "note": "no feasible candidate",
+                "avg_ms_per_round": round(times[-1] / R, 4)}
+    zf = int(hist[-1])
+    target = zf + 0.001 * abs(zf)
+    r_hit = int(np.nonzero(hist <= target)[0][0])
+    return {"rounds": R, "z_final": zf, "target_gap": 0.001, "round_hit": r_hit,
+            "ms_to_target": round(times[r_hit], 3), "first_feasible_round": int(feas[0]),
+            "ms_to_first_feasible": round(times[int(feas[0])], 3),
+            "ms_total": round(times[-1], 3),
+            "avg_ms_per_round": round(times[-1] / R, 4),
+            "iter_per_s_over_run": round(R * k_int / (times[-1] / 1e3), 1)}
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(bip, k_int, K):
     """The oracle as it stands, on a bounded sample of the same workload:
     3 FP64 PDHG iterations and one sampling round of 16 candidates (exact
@@ -122,7 +195,7 @@ def cpu_baseline(bip, k_int, K):
                       f"(exact eval) on the full workload, scaled to a step of {k_int} "
                       f"iterations + {K} candidates",
             "candidates_per_s": 1.0 / t_cand, "iter_per_s_pdhg_only": 1.0 / t_iter,
-            "host_cpus": os.cpu_count()}
+            "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model()}
 
 
 def batched_tti(G, bip, R, times):
@@ -381,39 +454,51 @@ def main():
                        "frac": round(ach / peak, 4) if peak > 0 else None,
                        "calls_per_launch": calls, "avg_launch_ms": kt["sample"][0],
                        "peak_source": "gfors_philox_throughput (generator alone, same counter shape)"}
+    # integer evaluation (general rows, quadratic objective): entry x candidate
+    # products per second against the VALU lane rate (each product costs at
+    # least one lane operation, so frac is an upper bound of VALU use)
+    eval_alu = None
+    cand = [(k, prods) for k, prods in (("eval_general", general_row_nnz(bip) * a.K),
+                                        ("eval_quad", (0 if bip.Q is None else bip.Q.nnz) * a.K))
+            if prods and kt.get(k, (0.0, 0))[1] and kt[k][0] > 0]
+    if cand:
+        k, prods = max(cand, key=lambda kp: kt[kp[0]][0])
+        ach = prods / (kt[k][0] * 1e-3)
+        eval_alu = {"bound": "alu", "kernel": k, "achieved": round(ach, 1), "peak": VALU_LANE_OPS,
+                    "unit": "entry-candidate products/s", "frac": round(ach / VALU_LANE_OPS, 4),
+                    "products_per_launch": prods, "avg_launch_ms": kt[k][0]}
     kernels = {k: {"avg_ms": round(ms, 5), "launches": cnt,
                    "gbs": (round(kb[k] / (ms * 1e-3) / 1e9, 1) if k in kb and ms > 0 else None)}
                for k, (ms, cnt) in kt.items() if cnt}
 
     # time-to-incumbent from a fresh start (same problem, reset)
-    G.reset()
     R = a.tti_rounds
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(R + 1)]
-    evs[0].record(stream)
-    for r in range(R):
-        G.run_rounds(1, a.K, use_graph)
-        evs[r + 1].record(stream)
-    G.synchronize()
-    times = [evs[0].elapsed_time(evs[r + 1]) for r in range(R)]
+    times = run_tti_rounds(G, R, a.K, use_graph)
     tti = {}
     if bip.num_instances > 1:
         tti = batched_tti(G, bip, R, times)
-    for t in range(min(bip.num_instances, 1) if bip.num_instances == 1 else 0):
-        hist = G.history(t, R)
-        feas = np.nonzero(hist != np.iinfo(np.int64).max)[0]
-        if feas.size:
-            zf = int(hist[-1])
-            target = zf + 0.001 * abs(zf)
-            r_hit = int(np.nonzero(hist <= target)[0][0])
-            tti = {"rounds": R, "z_final": zf, "target_gap": 0.001, "round_hit": r_hit,
-                   "ms_to_target": round(times[r_hit], 3), "first_feasible_round": int(feas[0]),
-                   "ms_to_first_feasible": round(times[int(feas[0])], 3),
-                   "ms_total": round(times[-1], 3),
-                   "avg_ms_per_round": round(times[-1] / R, 4),
-                   "iter_per_s_over_run": round(R * a.k_int / (times[-1] / 1e3), 1)}
-        else:
-            tti = {"rounds": R, "z_final": None, "note": "no feasible candidate",
-                   "avg_ms_per_round": round(times[-1] / R, 4)}
+    else:
+        tti = single_tti(G, R, times, a.k_int)
+    # the same for other instance seeds (same launch shapes), median reported
+    seeds = [int(v) for v in a.tti_seeds.split(",") if v.strip()] if a.tti_seeds else []
+    if (seeds and bip.num_instances == 1 and a.workload in PLAIN_WORKLOADS
+            and tti.get("z_final") is not None):
+        per = {str(a.seed): {k: tti[k] for k in ("z_final", "round_hit", "ms_to_target", "first_feasible_round")}}
+        cfg = list(G.launch_cfg().values())
+        for sd in seeds:
+            if sd == a.seed:
+                continue
+            Bs = instances.workload(a.workload, seed=sd)
+            Gs = gfors.Problem(Bs, gfors.default_params(k_int=a.k_int, K_max=max(a.K, 1024), autotune=0))
+            Gs.set_launch_cfg(*cfg)
+            ts = single_tti(Gs, R, run_tti_rounds(Gs, R, a.K, use_graph), a.k_int)
+            Gs.close()
+            del Gs
+            per[str(sd)] = {k: ts.get(k) for k in ("z_final", "round_hit", "ms_to_target", "first_feasible_round")}
+        hits = [v["ms_to_target"] for v in per.values() if v.get("ms_to_target") is not None]
+        tti["seeds"] = per
+        tti["median_ms_to_target"] = round(float(np.median(hits)), 3) if hits else None
+        tti["median_round_hit"] = float(np.median([v["round_hit"] for v in per.values() if v.get("round_hit") is not None])) if hits else None
 
     seq = None
     if bip.num_instances > 1 and a.seq_sample:
@@ -437,7 +522,7 @@ def main():
         "candidates_per_s": round(cands_per_s, 1),
         "wall_s_timed": round(wall, 4),
         "preprocess_s": round(t_pre, 3), "generate_s": round(t_gen, 3),
-        "roofline": roofline, "sampler_alu": sampler_alu, "kernels": kernels, "launch_cfg": G.launch_cfg(),
+        "roofline": roofline, "sampler_alu": sampler_alu, "eval_alu": eval_alu, "kernels": kernels, "launch_cfg": G.launch_cfg(),
         "iterate_stats": xstats,
         "time_to_incumbent": tti,
         "cpu_baseline": base,
