@@ -91,6 +91,7 @@ struct gfors_problem {
     int64_t n = 0, m1 = 0, m2 = 0, m = 0, nnzK = 0, nnzQ = 0;
     int T = 1;
     bool unitK = true, hasQ = false, obj64 = false, acc64 = false;
+    bool coef24 = true;   // every coefficient of the general rows fits in 24 signed bits
     LaunchCfg cfg;
 
     // host copies
@@ -552,11 +553,12 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     P->rkind_host.assign(m, 0);
     for (int64_t j = 0; j < m; ++j) {
         double sq = 0.0;
-        int64_t absum = 0;
+        int64_t absum = 0, amax = 0;
         bool allone = true, allneg = true;
         for (int e = rp[j]; e < rp[j + 1]; ++e) {
             sq += static_cast<double>(val[e]) * static_cast<double>(val[e]);
             absum += std::llabs(static_cast<int64_t>(val[e]));
+            amax = std::max<int64_t>(amax, std::llabs(static_cast<int64_t>(val[e])));
             allone = allone && val[e] == 1;
             allneg = allneg && val[e] == -1;
         }
@@ -589,6 +591,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         cls[j] = kind >= 0 ? kCover : kGeneral;
         P->rkind_host[j] = static_cast<uint8_t>(kind >= 0 ? (kind << 4) | tt : 0);
         if (cls[j] == kGeneral && absum > 2147483647LL) P->acc64 = true;
+        if (cls[j] == kGeneral && amax >= (1LL << 23)) P->coef24 = false;
     }
     // transpose (counting sort by column; rows ascending within a column)
     std::vector<int> rpT(n + 1, 0), ciT(P->nnzK), valT(P->nnzK);
@@ -1328,7 +1331,7 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     TB(4);
     launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
                         P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X,
-                        P->xkind, W, P->vpart, K, P->general_long);
+                        P->xkind, W, P->vpart, K, P->general_long, P->coef24);
     TE(4);
     TB(5);
     if (P->hasQ)

@@ -178,7 +178,8 @@ void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Til
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,
-                         const uint8_t *xkind, int W, int *vpart, int K, bool long_rows);
+                         const uint8_t *xkind, int W, int *vpart, int K, bool long_rows,
+                         bool coef24);
 void launch_eval_quad(hipStream_t s, const Tiles &qt,
                       const int *rpQ, const int *ciQ, const int *valQ, const uint64_t *X,
                       int W, int64_t *zqpart, int K);

@@ -424,85 +424,104 @@ k_eval_rows_allw(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
 
 // Long general rows (hundreds of entries and more): the workgroup's four
 // wavefronts split each row's entries into four contiguous quarters, each
-// wavefront adds its quarter for all W words (lane = candidate; entries in
-// groups of four, whose indices, coefficients and candidate words are uniform
-// loads issued together), and wavefront 0 adds the four partial sums (exact
-// integers) and tests the row.
-template <int WW, typename ACC>
+// wavefront adds its quarter for all W words (lane = candidate), and
+// wavefront 0 adds the four partial sums (exact integers) and tests the row.
+// A wavefront walks its quarter in blocks of B = 512 / W entries: the block's
+// candidate words (a variable's W words contiguous, lane = (entry, word)) are
+// fetched with vector loads into registers while the previous block is summed
+// from the wavefront's LDS buffer, then stored to the other buffer as two
+// planes, low and high 32-bit halves; lanes 0-31 read the low plane, lanes
+// 32-63 the high one, four words per 16-byte read (two addresses per
+// wavefront).  Bit (lane & 31) of the half times the coefficient (a scalar
+// load) is added: one 24-bit multiply-add when every coefficient fits in 24
+// signed bits and the sums in 32 (MAD24), else a 0 / -1 mask and an add.  The
+// sampler writes every variable's words, constant rows included, so no kind
+// lookup is needed.
+template <int WW, typename ACC, bool MAD24>
 __global__ void __launch_bounds__(256)
 k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
                   const int *__restrict__ tb1, const int *__restrict__ rows,
                   const int *__restrict__ rp, const int *__restrict__ ci,
                   const int *__restrict__ val, const int64_t *__restrict__ rhs, int m1,
-                  const uint64_t *__restrict__ X, const uint8_t *__restrict__ xkind,
-                  int *__restrict__ vpart, int K) {
+                  const uint64_t *__restrict__ X, int *__restrict__ vpart, int K) {
+    constexpr int B = 512 / WW;                  // entries per block
     __shared__ ACC part[4][WW][64];
-    // the rows, coefficients, kind bytes and candidate words are read at
-    // wave-uniform addresses and not written by this kernel: through the
-    // constant address space they are scalar loads (no vector address work)
-    const cptr<int> ci_c = to_const(ci);
-    const cptr<int> val_c = to_const(val);
-    // the sampler writes every variable's words, constant rows included, so the
-    // words are loaded unconditionally: no dependent kind lookup per entry
-    (void)xkind;
-    const cptr<uint64_t> X_c = to_const(X);
+    __shared__ uint32_t stage[4][2][2][512];     // per wavefront: two blocks, low / high planes
     const int tile = tile_ids[blockIdx.x];
     const int r0 = tb0[tile], r1 = tb1[tile];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));   // wave-uniform
-    const unsigned sh = lane & 31, hs = lane & 32;
-    // a candidate word is the same for the whole wavefront (lane = candidate):
-    // it is loaded at a uniform address (scalar loads), shifted right by 0 or
-    // 32 for the lane's half, and sbfe turns bit sh into a 0 / -1 mask for the
-    // coefficient
+    const unsigned sh = lane & 31;
+    const int half = lane >> 5;                  // plane this lane reads
+    const cptr<int> val_c = to_const(val), rows_c = to_const(rows), rp_c = to_const(rp);
     int vc[WW];
 #pragma unroll
     for (int w = 0; w < WW; ++w) vc[w] = 0;
     for (int rr = r0; rr < r1; ++rr) {
-        const int j = rows[rr];
-        const int e0 = rp[j], len = rp[j + 1] - e0;
+        const int j = rows_c[rr];
+        const int e0 = rp_c[j], len = rp_c[j + 1] - e0;
         const int q0 = e0 + static_cast<int>((static_cast<int64_t>(len) * wave) / 4);
         const int q1 = e0 + static_cast<int>((static_cast<int64_t>(len) * (wave + 1)) / 4);
         ACC acc[WW];
 #pragma unroll
         for (int w = 0; w < WW; ++w) acc[w] = 0;
-        int e = q0;
-        for (; e + 4 <= q1; e += 4) {
-            int c[4], a[4];
+        uint64_t reg[8];
+        // words of the block starting at entry blk: pair 64 t + lane is
+        // (entry (64 t + lane) / WW, word (64 t + lane) % WW); entries past
+        // q1 load a clamped (valid) index and are never read
+        auto load_block = [&](int blk) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                c[u] = ci_c[e + u];
-                a[u] = val ? val_c[e + u] : 1;
+            for (int t = 0; t < 8; ++t) {
+                const int idx = 64 * t + lane;
+                const int e = min(blk + idx / WW, q1 - 1);
+                reg[t] = X[static_cast<int64_t>(ci[e]) * WW + (idx % WW)];
             }
-            uint64_t xw[4][WW];
+        };
+        auto store_block = [&](int b) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const cptr<uint64_t> xr = X_c + static_cast<int64_t>(c[u]) * WW;
-#pragma unroll
-                for (int w = 0; w < WW; ++w) xw[u][w] = xr[w];
+            for (int t = 0; t < 8; ++t) {
+                stage[wave][b][0][64 * t + lane] = static_cast<uint32_t>(reg[t]);
+                stage[wave][b][1][64 * t + lane] = static_cast<uint32_t>(reg[t] >> 32);
             }
+        };
+        if (q0 < q1) {
+            load_block(q0);
+            store_block(0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        int cur = 0;
+        for (int blk = q0; blk < q1; blk += B) {
+            const int nxt = blk + B;
+            if (nxt < q1) load_block(nxt);                       // in flight during the sum
+            const uint32_t *pl = stage[wave][cur][half];
+            const int ne = min(B, q1 - blk);
+#pragma unroll 4
+            for (int e = 0; e < ne; ++e) {
+                const int a = val ? val_c[blk + e] : 1;
+                uint32_t hw[WW];
+                if constexpr (WW >= 4) {
 #pragma unroll
-            for (int w = 0; w < WW; ++w) {
-                int t[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    t[u] = a[u] & __builtin_amdgcn_sbfe(static_cast<int>(static_cast<uint32_t>(xw[u][w] >> hs)), sh, 1u);
-                if (sizeof(ACC) == 4) {
-                    acc[w] += (t[0] + t[1]) + (t[2] + t[3]);
+                    for (int w = 0; w < WW; w += 4) {
+                        const uint4 q4 = *reinterpret_cast<const uint4 *>(pl + e * WW + w);
+                        hw[w] = q4.x; hw[w + 1] = q4.y; hw[w + 2] = q4.z; hw[w + 3] = q4.w;
+                    }
                 } else {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[w] += static_cast<ACC>(t[u]);
+                    for (int w = 0; w < WW; ++w) hw[w] = pl[e * WW + w];
+                }
+#pragma unroll
+                for (int w = 0; w < WW; ++w) {
+                    if constexpr (MAD24) {
+                        acc[w] += __mul24(a, static_cast<int>(__builtin_amdgcn_ubfe(hw[w], sh, 1u)));
+                    } else {
+                        acc[w] += static_cast<ACC>(a & __builtin_amdgcn_sbfe(static_cast<int>(hw[w]), sh, 1u));
+                    }
                 }
             }
-        }
-        for (; e < q1; ++e) {
-            const int c = ci_c[e];
-            const int a = val ? val_c[e] : 1;
-#pragma unroll
-            for (int w = 0; w < WW; ++w) {
-                const uint64_t xv = X_c[static_cast<int64_t>(c) * WW + w];
-                acc[w] += static_cast<ACC>(a & __builtin_amdgcn_sbfe(static_cast<int>(static_cast<uint32_t>(xv >> hs)), sh, 1u));
-            }
+            __builtin_amdgcn_wave_barrier();
+            if (nxt < q1) store_block(cur ^ 1);
+            __builtin_amdgcn_wave_barrier();
+            cur ^= 1;
         }
 #pragma unroll
         for (int w = 0; w < WW; ++w) part[wave][w][lane] = acc[w];
@@ -528,13 +547,14 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,
-                         const uint8_t *xkind, int W, int *vpart, int K, bool long_rows) {
+                         const uint8_t *xkind, int W, int *vpart, int K, bool long_rows,
+                         bool coef24) {
     if (!ntiles) return;
     if (long_rows && W <= 16 && (W & (W - 1)) == 0) {
-#define GF_RS(WW, ACCT) k_eval_rows_split<WW, ACCT><<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, xkind, vpart, K)
-#define GF_RSW(ACCT) switch (W) { case 1: GF_RS(1, ACCT); break; case 2: GF_RS(2, ACCT); break; \
-        case 4: GF_RS(4, ACCT); break; case 8: GF_RS(8, ACCT); break; default: GF_RS(16, ACCT); break; }
-        if (acc64) { GF_RSW(int64_t) } else { GF_RSW(int32_t) }
+#define GF_RS(WW, ACCT, M) k_eval_rows_split<WW, ACCT, M><<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rp, ci, val, rhs, m1, X, vpart, K)
+#define GF_RSW(ACCT, M) switch (W) { case 1: GF_RS(1, ACCT, M); break; case 2: GF_RS(2, ACCT, M); break; \
+        case 4: GF_RS(4, ACCT, M); break; case 8: GF_RS(8, ACCT, M); break; default: GF_RS(16, ACCT, M); break; }
+        if (acc64) { GF_RSW(int64_t, false) } else if (coef24) { GF_RSW(int32_t, true) } else { GF_RSW(int32_t, false) }
 #undef GF_RSW
 #undef GF_RS
         return;
