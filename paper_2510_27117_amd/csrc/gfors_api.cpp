@@ -92,6 +92,7 @@ struct gfors_problem {
     int T = 1;
     bool unitK = true, hasQ = false, obj64 = false, acc64 = false;
     bool coef24 = true;   // every coefficient of the general rows fits in 24 signed bits
+    bool q24 = true;      // every Q entry fits in 24 signed bits and every row sum of |Q| in 31
     LaunchCfg cfg;
 
     // host copies
@@ -103,6 +104,7 @@ struct gfors_problem {
     int *rp = nullptr, *ci = nullptr, *val = nullptr;
     int *rpT = nullptr, *ciT = nullptr, *valT = nullptr;
     int *rpQ = nullptr, *ciQ = nullptr, *valQ = nullptr;
+    int *rowQ = nullptr;   // row of each Q entry (quadratic objective)
     float *omega = nullptr, *rt = nullptr, *ct = nullptr;
     double *omega64 = nullptr, *rowinv2_d = nullptr, *rowinv_d = nullptr;
     int64_t *rhs = nullptr, *cost = nullptr;
@@ -311,6 +313,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->rpQ = cv.take<int>(n + 1);
     P->ciQ = cv.take<int>(nnzQ);
     P->valQ = cv.take<int>(nnzQ);
+    P->rowQ = cv.take<int>(nnzQ);
     P->omega = cv.take<float>(m);
     P->rt = cv.take<float>(m);
     P->omega64 = cv.take<double>(m);
@@ -619,6 +622,12 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             valQ[e] = Q->val ? Q->val[e] : 1;
             if (ciQ[e] < P->inst_var0[t] || ciQ[e] >= P->inst_var0[t] + P->inst_nvar[t])
                 return fail(GFORS_E_ARG, "Q entry crosses instances");
+            if (std::llabs(static_cast<int64_t>(valQ[e])) >= (1LL << 23)) P->q24 = false;
+        }
+        for (int64_t i = 0; i < n && P->q24; ++i) {
+            int64_t sa = 0;
+            for (int e = rpQ[i]; e < rpQ[i + 1]; ++e) sa += std::llabs(static_cast<int64_t>(valQ[e]));
+            if (sa >= (1LL << 31)) P->q24 = false;
         }
     }
     // objective accumulation width in the sampler
@@ -721,6 +730,11 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         if ((rc = upload(s, P->rpQ, rpQ.data(), n + 1))) return rc;
         if ((rc = upload(s, P->ciQ, ciQ.data(), P->nnzQ))) return rc;
         if ((rc = upload(s, P->valQ, valQ.data(), P->nnzQ))) return rc;
+        std::vector<int> rowQ(P->nnzQ);
+        for (int64_t i = 0; i < n; ++i)
+            for (int e = rpQ[i]; e < rpQ[i + 1]; ++e) rowQ[e] = static_cast<int>(i);
+        if ((rc = upload(s, P->rowQ, rowQ.data(), P->nnzQ))) return rc;
+        if ((rc = sync(P))) return rc;
     }
     // column-sliced copies: slice q of the variables is [q*ns, (q+1)*ns)
     auto build_sliced = [&](int64_t rows, int64_t cols, const std::vector<int> &rpx,
@@ -1335,7 +1349,7 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     TE(4);
     TB(5);
     if (P->hasQ)
-        launch_eval_quad(s, P->qt, P->rpQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K);
+        launch_eval_quad(s, P->qt, P->rpQ, P->rowQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K, P->q24);
     TE(5);
     TB(6);
     launch_reduce_cand(s, P->T, K, P->red_S, P->et, P->vpart, P->st, P->zpart, P->qt, P->zqpart,

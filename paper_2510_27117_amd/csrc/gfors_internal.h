@@ -180,9 +180,9 @@ void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const T
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,
                          const uint8_t *xkind, int W, int *vpart, int K, bool long_rows,
                          bool coef24);
-void launch_eval_quad(hipStream_t s, const Tiles &qt,
-                      const int *rpQ, const int *ciQ, const int *valQ, const uint64_t *X,
-                      int W, int64_t *zqpart, int K);
+void launch_eval_quad(hipStream_t s, const Tiles &qt, const int *rpQ, const int *rowQ,
+                      const int *ciQ, const int *valQ, const uint64_t *X, int W, int64_t *zqpart,
+                      int K, bool q24);
 void launch_reduce_cand(hipStream_t s, int T, int K, int S, const Tiles &et, const int *vpart,
                         const Tiles &st, const int64_t *zpart, const Tiles &qt,
                         const int64_t *zqpart, int has_q, int32_t *rv, int64_t *rz,

@@ -577,68 +577,77 @@ void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const T
 
 // ---------------------------------------------------------------------------
 // Quadratic objective <x, Q x> per candidate, lane = candidate:
-//   sum_i x_i (sum_k Q_ik x_k) over the variables i of a tile.
+//   sum over the entries (i, k) of a tile's rows of Q_ik [x_i and x_k].
+// Four wavefronts per tile, each taking every fourth candidate word.  For a
+// word, a wavefront stages, per entry of the tile (up to kQuadStage at a
+// time; lane = entry), the AND of the words of x_i and x_k (the entry's row i
+// from rowQ) as low / high 32-bit planes plus Q_ik into LDS, then sums the
+// staged entries in one flat loop: bit (lane & 31) of the lane's half times
+// Q_ik, read as wave-uniform LDS broadcasts (one 24-bit multiply-add when Q's
+// entries fit in 24 signed bits and a row's sum of |Q| in 31, else a mask and
+// an add).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024)
-k_eval_quad(const int *__restrict__ tb0,
-            const int *__restrict__ tb1, const int *__restrict__ rpQ,
-            const int *__restrict__ ciQ, const int *__restrict__ valQ,
-            const uint64_t *__restrict__ X, int W, int64_t *__restrict__ zq, int K) {
+constexpr int kQuadStage = 1024;
+
+template <bool MAD24>
+__global__ void __launch_bounds__(256)
+k_eval_quad(const int *__restrict__ tb0, const int *__restrict__ tb1,
+            const int *__restrict__ rpQ, const int *__restrict__ rowQ, const int *__restrict__ ciQ,
+            const int *__restrict__ valQ, const uint64_t *__restrict__ X, int W,
+            int64_t *__restrict__ zq, int K) {
+    __shared__ uint32_t stage[4][3][kQuadStage];   // low / high halves of x_i & x_k, Q values
     const int tile = blockIdx.x;
     const int i0 = tb0[tile], i1 = tb1[tile];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));   // wave-uniform
-    const int NW = blockDim.x >> 6;
-    const int sh = lane & 31;
-    const unsigned hs = lane & 32;      // the lane's half of a candidate word
-    // Q's rows and the candidate words are read at wave-uniform addresses and
-    // not written here: scalar loads through the constant address space
-    const cptr<int> rpQ_c = to_const(rpQ), ciQ_c = to_const(ciQ), valQ_c = to_const(valQ);
-    const cptr<uint64_t> X_c = to_const(X);
-    for (int w = wave; w < W; w += NW) {
+    const unsigned sh = lane & 31;
+    const int half = lane >> 5;
+    const cptr<int> rpQ_c = to_const(rpQ);
+    const int E0 = rpQ_c[i0], E1 = rpQ_c[i1];
+    const uint32_t *pl = stage[wave][half];
+    const int *qv = reinterpret_cast<const int *>(stage[wave][2]);
+    for (int w = wave; w < W; w += 4) {
         int64_t z = 0;
-        for (int i = i0; i < i1; ++i) {
-            const uint64_t wi = X_c[static_cast<int64_t>(i) * W + w];
-            if (wi == 0) continue;           // no candidate of this word sets x_i
-            const int xi = static_cast<int>((static_cast<uint32_t>(wi >> hs) >> sh) & 1u);
-            int64_t acc = 0;
-            const int e1 = rpQ_c[i + 1];
-            int e = rpQ_c[i];
-            // entries in groups of 8: indices, coefficients and candidate words
-            // are uniform loads issued together
-            for (; e + 8 <= e1; e += 8) {
-                int c[8], q[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    c[u] = ciQ_c[e + u];
-                    q[u] = valQ_c[e + u];
-                }
-                uint64_t xw[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) xw[u] = X_c[static_cast<int64_t>(c[u]) * W + w];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t half = static_cast<uint32_t>(xw[u] >> hs);
-                    acc += ((half >> sh) & 1u) ? static_cast<int64_t>(q[u]) : 0;
+        for (int cb = E0; cb < E1; cb += kQuadStage) {
+            const int ce = min(E1, cb + kQuadStage);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+            for (int t = 0; t < kQuadStage / 64; ++t) {
+                const int e = cb + 64 * t + lane;
+                if (e < ce) {
+                    const uint64_t xw = X[static_cast<int64_t>(ciQ[e]) * W + w] &
+                                        X[static_cast<int64_t>(rowQ[e]) * W + w];
+                    stage[wave][0][e - cb] = static_cast<uint32_t>(xw);
+                    stage[wave][1][e - cb] = static_cast<uint32_t>(xw >> 32);
+                    stage[wave][2][e - cb] = static_cast<uint32_t>(valQ[e]);
                 }
             }
-            for (; e < e1; ++e) {
-                const uint64_t word = X_c[static_cast<int64_t>(ciQ_c[e]) * W + w];
-                const uint32_t half = static_cast<uint32_t>(word >> hs);
-                acc += ((half >> sh) & 1u) ? static_cast<int64_t>(valQ_c[e]) : 0;
+            __builtin_amdgcn_wave_barrier();
+            const int ne = ce - cb;
+            if (MAD24) {
+                int acc = 0;
+#pragma unroll 8
+                for (int e = 0; e < ne; ++e)
+                    acc += __mul24(qv[e], static_cast<int>(__builtin_amdgcn_ubfe(pl[e], sh, 1u)));
+                z += acc;
+            } else {
+                int64_t acc = 0;
+#pragma unroll 8
+                for (int e = 0; e < ne; ++e)
+                    acc += static_cast<int64_t>(qv[e] & __builtin_amdgcn_sbfe(static_cast<int>(pl[e]), sh, 1u));
+                z += acc;
             }
-            z += xi ? acc : 0;
         }
         zq[static_cast<int64_t>(tile) * K + 64 * w + lane] = z;
     }
 }
 
-void launch_eval_quad(hipStream_t s, const Tiles &qt,
-                      const int *rpQ, const int *ciQ, const int *valQ, const uint64_t *X,
-                      int W, int64_t *zqpart, int K) {
+void launch_eval_quad(hipStream_t s, const Tiles &qt, const int *rpQ, const int *rowQ,
+                      const int *ciQ, const int *valQ, const uint64_t *X, int W, int64_t *zqpart,
+                      int K, bool q24) {
     if (!qt.count) return;
-    const int NW = W <= 16 ? W : 16;
-    k_eval_quad<<<qt.count, NW * 64, 0, s>>>(qt.b0, qt.b1, rpQ, ciQ, valQ, X, W, zqpart, K);
+    if (q24) k_eval_quad<true><<<qt.count, 256, 0, s>>>(qt.b0, qt.b1, rpQ, rowQ, ciQ, valQ, X, W, zqpart, K);
+    else k_eval_quad<false><<<qt.count, 256, 0, s>>>(qt.b0, qt.b1, rpQ, rowQ, ciQ, valQ, X, W, zqpart, K);
 }
 
 // ---------------------------------------------------------------------------
