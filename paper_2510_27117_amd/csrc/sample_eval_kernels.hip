@@ -294,8 +294,29 @@ k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
                 viol = ((kd & 1) ? (~P & ~Q) : 0ull) | ((kd & 2) ? (~P & Q) : 0ull) |
                        ((kd & 4) ? (P & ~Q) : 0ull) | ((kd & 8) ? (P & Q) : 0ull);
             } else {
+                // "at least one / at least two set" do not depend on the
+                // order of the entries: eight at a time, their column
+                // indices, kind bytes and words each loaded together
                 uint64_t one = 0, two = 0;
-                for (int e = e0; e < e1; ++e) {
+                int e = e0;
+                for (; e + 8 <= e1; e += 8) {
+                    int cc[8];
+                    uint8_t kk[8];
+                    uint64_t xx[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) cc[u] = ci[e + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) kk[u] = xkind[cc[u]];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        xx[u] = kk[u] == 0 ? X[static_cast<int64_t>(cc[u]) * W + sub] : (kk[u] == 2 ? ~0ull : 0ull);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        two |= one & xx[u];
+                        one |= xx[u];
+                    }
+                }
+                for (; e < e1; ++e) {
                     const uint64_t x = cand_word(X, xkind, ci[e], W, sub);
                     two |= one & x;
                     one |= x;
