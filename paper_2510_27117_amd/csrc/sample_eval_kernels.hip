@@ -254,6 +254,8 @@ __device__ __forceinline__ void flush_planes(uint64_t (&c)[8], int *cnt, int w) 
 // deterministic (p = 0 / p = 1: all candidates 0 / 1) are answered from the
 // per-variable kind byte (an L2-resident n-byte array) instead of the 8n W-byte
 // candidate block.
+constexpr int kCoverBatch = 8;    // entries per load stage in the bitwise row evaluation (16 is slower)
+
 __device__ __forceinline__ uint64_t cand_word(const uint64_t *__restrict__ X,
                                               const uint8_t *__restrict__ xkind, int c, int W,
                                               int sub) {
@@ -295,23 +297,23 @@ k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
                        ((kd & 4) ? (P & ~Q) : 0ull) | ((kd & 8) ? (P & Q) : 0ull);
             } else {
                 // "at least one / at least two set" do not depend on the
-                // order of the entries: eight at a time, their column
+                // order of the entries: kCoverBatch at a time, their column
                 // indices, kind bytes and words each loaded together
                 uint64_t one = 0, two = 0;
                 int e = e0;
-                for (; e + 8 <= e1; e += 8) {
-                    int cc[8];
-                    uint8_t kk[8];
-                    uint64_t xx[8];
+                for (; e + kCoverBatch <= e1; e += kCoverBatch) {
+                    int cc[kCoverBatch];
+                    uint8_t kk[kCoverBatch];
+                    uint64_t xx[kCoverBatch];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) cc[u] = ci[e + u];
+                    for (int u = 0; u < kCoverBatch; ++u) cc[u] = ci[e + u];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) kk[u] = xkind[cc[u]];
+                    for (int u = 0; u < kCoverBatch; ++u) kk[u] = xkind[cc[u]];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
+                    for (int u = 0; u < kCoverBatch; ++u)
                         xx[u] = kk[u] == 0 ? X[static_cast<int64_t>(cc[u]) * W + sub] : (kk[u] == 2 ? ~0ull : 0ull);
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
+                    for (int u = 0; u < kCoverBatch; ++u) {
                         two |= one & xx[u];
                         one |= xx[u];
                     }
