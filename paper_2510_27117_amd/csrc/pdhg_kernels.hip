@@ -365,7 +365,8 @@ k_spmv_part(int nrows, int P, const int *__restrict__ rpP, const int *__restrict
     if (row < nrows && sub == 0) part[static_cast<int64_t>(sl) * nrows + row] = acc;
 }
 
-template <bool BATCH>
+// PP > 0: the slice count as a compile-time constant (all loads in flight).
+template <bool BATCH, int PP>
 __global__ void __launch_bounds__(256)
 k_dual_combine(int m, int m1, int P, const float *__restrict__ part,
                const float *__restrict__ omega, const float *__restrict__ rt,
@@ -376,7 +377,15 @@ k_dual_combine(int m, int m1, int P, const float *__restrict__ part,
     float w = 0.f;
     if (row < m) {
         float s = 0.f;
-        for (int q = 0; q < P; ++q) s += part[static_cast<int64_t>(q) * m + row];
+        if (PP > 0) {
+            float pv[PP > 0 ? PP : 1];
+#pragma unroll
+            for (int q = 0; q < PP; ++q) pv[q] = part[static_cast<int64_t>(q) * m + row];
+#pragma unroll
+            for (int q = 0; q < PP; ++q) s += pv[q];
+        } else {
+            for (int q = 0; q < P; ++q) s += part[static_cast<int64_t>(q) * m + row];
+        }
         const float om = omega[row];
         const float t = rt[row] - om * s;
         const float ta = BATCH ? tau2_inst[row_inst[row]] : tau2;
@@ -450,8 +459,10 @@ void launch_dual_combine(hipStream_t s, bool batched, int m, int m1, int P, cons
                          uint64_t *wybits) {
     const int blocks = (m + 255) / 256;
     if (!blocks) return;
-    if (batched) k_dual_combine<true><<<blocks, 256, 0, s>>>(m, m1, P, part, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, wybits);
-    else k_dual_combine<false><<<blocks, 256, 0, s>>>(m, m1, P, part, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, wybits);
+#define GF_DC(B, PPV) k_dual_combine<B, PPV><<<blocks, 256, 0, s>>>(m, m1, P, part, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, wybits)
+    if (P == kXcdSlices) { if (batched) GF_DC(true, kXcdSlices); else GF_DC(false, kXcdSlices); }
+    else { if (batched) GF_DC(true, 0); else GF_DC(false, 0); }
+#undef GF_DC
 }
 
 void launch_primal_combine(hipStream_t s, bool batched, int n, int P, const float *part,
