@@ -823,6 +823,7 @@ void launch_sell_bits(hipStream_t s, const SellView &sv, int mode, bool unit, bo
 
 // Primal step with the whole dual bitmap in LDS (persistent grid-stride over
 // virtual blocks of 256 threads; no Q).
+constexpr int kPrimalBatch = 8;   // entries per lane and load stage
 template <int LPR, bool UNIT, bool BATCH>
 __global__ void __launch_bounds__(1024)
 k_primal_bits(int n, int m, int nvb, const int *__restrict__ rpT, const int *__restrict__ ciT,
@@ -848,31 +849,31 @@ k_primal_bits(int n, int m, int nvb, const int *__restrict__ rpT, const int *__r
             cti = ct[i];
             if (BATCH) t = var_inst[i];
             const int e1 = rpT[i + 1];
-            // batches of 4 entries per lane, branch-free: row indices first,
-            // then their bits, then the gathers of the nonzero operands (a
-            // zero operand reads the padding element wy[m], shared by the
-            // wavefront); terms are added in entry order
-            for (int eb = rpT[i] + sub; eb < e1; eb += 4 * LPR) {
-                int j[4], a[4];
+            // batches of kPrimalBatch entries per lane, branch-free: row
+            // indices first, then their bits, then the gathers of the nonzero
+            // operands (a zero operand reads the padding element wy[m], shared
+            // by the wavefront); terms are added in entry order
+            for (int eb = rpT[i] + sub; eb < e1; eb += kPrimalBatch * LPR) {
+                int j[kPrimalBatch], a[kPrimalBatch];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kPrimalBatch; ++u) {
                     const int e = eb + u * LPR;
                     const int ec = min(e, e1 - 1);
                     const int jj = ciT[ec];
                     j[u] = e < e1 ? jj : m;
                     a[u] = UNIT ? 1 : valT[ec];
                 }
-                bool nz[4];
+                bool nz[kPrimalBatch];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kPrimalBatch; ++u) {
                     const int jc = j[u] < m ? j[u] : 0;
                     nz[u] = (j[u] < m) & (((sb[jc >> 5] >> (jc & 31)) & 1u) != 0u);
                 }
-                float g[4];
+                float g[kPrimalBatch];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) g[u] = wy[nz[u] ? j[u] : m];
+                for (int u = 0; u < kPrimalBatch; ++u) g[u] = wy[nz[u] ? j[u] : m];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kPrimalBatch; ++u) {
                     const float tt = UNIT ? s1 + g[u] : fmaf(static_cast<float>(a[u]), g[u], s1);
                     s1 = nz[u] ? tt : s1;
                 }
