@@ -130,6 +130,7 @@ struct gfors_problem {
     uint8_t *rkind = nullptr;    // per row: evaluation kind << 4 | truth table (pair rows)
     uint8_t *xkind = nullptr;    // per variable, last round: 0 sampled, 1 all zero, 2 all one
     int *dual_order = nullptr;   // constraint rows, longest first (block-per-row dual)
+    int *rowc0 = nullptr;        // first column of a row whose columns are one contiguous range, else -1
     int *primal_order = nullptr; // variables, most rows first (block-per-variable primal)
     int heavy_rows = 0, heavy_cols = 0;   // rows / variables with kHeavyLen+ entries
     double *pv = nullptr, *pu = nullptr, *pw = nullptr, *part = nullptr, *res = nullptr;
@@ -344,6 +345,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->rkind = cv.take<uint8_t>(m);
     P->xkind = cv.take<uint8_t>(n);
     P->dual_order = cv.take<int>(m);
+    P->rowc0 = cv.take<int>(std::max<int64_t>(m, 1));
     P->primal_order = cv.take<int>(n);
     P->cover_ids = cv.take<int>(b.et);
     P->general_ids = cv.take<int>(b.et);
@@ -849,6 +851,15 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         std::stable_sort(ord.begin(), ord.end(),
                          [&](int a, int b2) { return rp[a + 1] - rp[a] > rp[b2 + 1] - rp[b2]; });
         if ((rc = upload(s, P->dual_order, ord.data(), m))) return rc;
+        std::vector<int> c0v(m, -1);
+        for (int64_t j = 0; j < m; ++j) {
+            const int b0 = rp[j], b1 = rp[j + 1];
+            bool dense = b1 > b0;
+            for (int e = b0 + 1; e < b1 && dense; ++e) dense = ci[e] == ci[b0] + (e - b0);
+            if (dense) c0v[j] = ci[b0];
+        }
+        if ((rc = upload(s, P->rowc0, c0v.data(), m))) return rc;
+        if ((rc = sync(P))) return rc;
         P->heavy_rows = 0;
         while (P->heavy_rows < m && rp[ord[P->heavy_rows] + 1] - rp[ord[P->heavy_rows]] >= kHeavyLen) ++P->heavy_rows;
         std::vector<int> ordT(n);
@@ -1110,7 +1121,7 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
         // the others with lpr - 256 lanes each
         const bool all = lpr == kLprBlock;
         launch_dual_long(s, P->unitK, batched, all ? m : P->heavy_rows, m1, P->dual_order, P->rp,
-                         P->ci, P->val, P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2,
+                         P->rowc0, P->ci, P->val, P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2,
                          P->di.tau2, P->row_inst);
         if (!all)
             launch_dual(s, lpr - kLprBlock, P->unitK, batched, m, m1, P->rp, P->ci, P->val,

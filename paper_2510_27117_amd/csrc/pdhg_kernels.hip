@@ -76,19 +76,12 @@ constexpr int kLongUnroll = 4;   // loads in flight per lane in the heavy kernel
 // grouped per XCD), lanes strided over the row with four independent loads
 // in flight each, partial sums combined by shuffles inside each wavefront and
 // then across the four wavefronts in a fixed order.
-template <bool UNIT, bool BATCH>
-__global__ void __launch_bounds__(256)
-k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restrict__ rp,
-            const int *__restrict__ ci, const int *__restrict__ val,
-            const float *__restrict__ omega, const float *__restrict__ rt,
-            const float *__restrict__ xbar, const float *__restrict__ y_in,
-            float *__restrict__ y_out, float *__restrict__ wy, float tau2,
-            const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
-    __shared__ float ws[4];
-    const int slot = xcd_grouped_slot(blockIdx.x);
-    if (slot >= count) return;                          // uniform per workgroup
-    const int row = order[slot];
-    const int e0 = rp[row], e1 = rp[row + 1];
+// Sum of a_e xbar[col_e] over the row's entries by the workgroup's 256 lanes
+// (four loads in flight per lane); DENSE: the row's columns are the range
+// c0, c0 + 1, ..., so no column index is loaded.
+template <bool UNIT, bool DENSE>
+__device__ __forceinline__ float long_row_sum(int e0, int e1, int c0, const int *__restrict__ ci,
+                                              const int *__restrict__ val, const float *__restrict__ xbar) {
     float s = 0.f;
     for (int eb = e0 + static_cast<int>(threadIdx.x); eb < e1; eb += kLongUnroll * 256) {
         float xv[kLongUnroll];
@@ -96,7 +89,7 @@ k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restr
 #pragma unroll
         for (int u = 0; u < kLongUnroll; ++u) {
             const int e = min(eb + 256 * u, e1 - 1);
-            const float v = xbar[ci[e]];
+            const float v = xbar[DENSE ? c0 + (e - e0) : ci[e]];
             const bool in = eb + 256 * u < e1;
             xv[u] = in ? v : 0.f;
             a[u] = UNIT ? 1 : (in ? val[e] : 0);
@@ -107,6 +100,25 @@ k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restr
             else s = fmaf(static_cast<float>(a[u]), xv[u], s);
         }
     }
+    return s;
+}
+
+template <bool UNIT, bool BATCH>
+__global__ void __launch_bounds__(256)
+k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restrict__ rp,
+            const int *__restrict__ rowc0, const int *__restrict__ ci, const int *__restrict__ val,
+            const float *__restrict__ omega, const float *__restrict__ rt,
+            const float *__restrict__ xbar, const float *__restrict__ y_in,
+            float *__restrict__ y_out, float *__restrict__ wy, float tau2,
+            const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
+    __shared__ float ws[4];
+    const int slot = xcd_grouped_slot(blockIdx.x);
+    if (slot >= count) return;                          // uniform per workgroup
+    const int row = order[slot];
+    const int e0 = rp[row], e1 = rp[row + 1];
+    const int c0 = rowc0[row];                          // first column of a dense row, else -1
+    float s = c0 >= 0 ? long_row_sum<UNIT, true>(e0, e1, c0, ci, val, xbar)
+                      : long_row_sum<UNIT, false>(e0, e1, c0, ci, val, xbar);
     s = group_sum<64>(s);
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -123,12 +135,12 @@ k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restr
 }
 
 void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, const int *order,
-                      const int *rp, const int *ci, const int *val, const float *omega,
+                      const int *rp, const int *rowc0, const int *ci, const int *val, const float *omega,
                       const float *rt, const float *xbar, const float *y_in, float *y_out,
                       float *wy, float tau2, const float *tau2_inst, const int *row_inst) {
     if (m <= 0) return;
     const int grid = ((m + 127) / 128) * 128;
-#define GF_DL(U, B) k_dual_long<U, B><<<grid, 256, 0, s>>>(m, m1, order, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
+#define GF_DL(U, B) k_dual_long<U, B><<<grid, 256, 0, s>>>(m, m1, order, rp, rowc0, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
     if (unit) { if (batched) GF_DL(true, true); else GF_DL(true, false); }
     else { if (batched) GF_DL(false, true); else GF_DL(false, false); }
 #undef GF_DL
