@@ -131,6 +131,7 @@ struct gfors_problem {
     uint8_t *xkind = nullptr;    // per variable, last round: 0 sampled, 1 all zero, 2 all one
     int *dual_order = nullptr;   // constraint rows, longest first (block-per-row dual)
     int *rowc0 = nullptr;        // first column of a row whose columns are one contiguous range, else -1
+    int *colT0 = nullptr;        // first row of a variable whose rows are one contiguous range, else -1
     int *primal_order = nullptr; // variables, most rows first (block-per-variable primal)
     int heavy_rows = 0, heavy_cols = 0;   // rows / variables with kHeavyLen+ entries
     double *pv = nullptr, *pu = nullptr, *pw = nullptr, *part = nullptr, *res = nullptr;
@@ -145,7 +146,7 @@ struct gfors_problem {
     bool sellK_want = false, sellKS_want = false, sellT_want = false;
     SellView sellK, sellKS, sellT;
     int64_t sellK_cap = 0, sellKS_cap = 0, sellT_cap = 0;
-    int *sellK_buf[4] = {}, *sellKS_buf[4] = {}, *sellT_buf[4] = {};
+    int *sellK_buf[6] = {}, *sellKS_buf[6] = {}, *sellT_buf[6] = {};
     float *rowinv32 = nullptr;          // 1/||a_j|| (0 for a zero row): the GNN's edge weights
     float gnn_ictmax = 1.f, gnn_irtmax = 1.f;
     uint64_t *bx = nullptr, *by = nullptr;   // nonzero bitmaps of xbar and wy
@@ -346,6 +347,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->xkind = cv.take<uint8_t>(n);
     P->dual_order = cv.take<int>(m);
     P->rowc0 = cv.take<int>(std::max<int64_t>(m, 1));
+    P->colT0 = cv.take<int>(std::max<int64_t>(n, 1));
     P->primal_order = cv.take<int>(n);
     P->cover_ids = cv.take<int>(b.et);
     P->general_ids = cv.take<int>(b.et);
@@ -374,7 +376,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     }
     // SELL-64 copies for short rows (lane = row); the entry budget allows 50%
     // padding (a larger need disables the layout for that matrix)
-    auto sell_carve = [&](bool want, int64_t rows, int Pn, int64_t nnz, int64_t &cap, int *(&buf)[4]) {
+    auto sell_carve = [&](bool want, int64_t rows, int Pn, int64_t nnz, int64_t &cap, int *(&buf)[6]) {
         if (!want) return;
         const int64_t nch = ceil_div(rows, 64);
         cap = nnz + nnz / 2 + 2 * 64 * Pn * nch;
@@ -382,6 +384,8 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
         buf[1] = cv.take<int>(cap);
         buf[2] = cv.take<int>(cap);
         buf[3] = cv.take<int>(Pn * nch * 64);
+        buf[4] = cv.take<int>(Pn * nch * 64);
+        buf[5] = cv.take<int>(Pn * nch * 64);
     };
     P->sellK_want = m > 0 && nnzK <= 32 * m;
     P->sellKS_want = P->slicedK;
@@ -770,10 +774,11 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     // windows of 8192 rows, chunks of 64 rows padded to the longest row
     auto build_sell = [&](int64_t rows, int64_t cols, int Pn, const std::vector<int> &rpx,
                           const std::vector<int> &cix, const std::vector<int> &valx, int pad_col,
-                          int64_t cap, int *(&buf)[4], SellView &sv) -> int {
+                          int64_t cap, int *(&buf)[6], SellView &sv) -> int {
         const int64_t nch = ceil_div(rows, 64);
         const int64_t ns = ceil_div(ceil_div(std::max<int64_t>(cols, 1), Pn), 64) * 64;
         std::vector<int> sptr(static_cast<size_t>(Pn) * (nch + 1)), srow(static_cast<size_t>(Pn) * nch * 64, -1);
+        std::vector<int> sc0(static_cast<size_t>(Pn) * nch * 64, -1), slen(static_cast<size_t>(Pn) * nch * 64, 0);
         std::vector<int> sci, sval;
         sci.reserve(static_cast<size_t>(cix.size() * 1.2) + 64);
         sval.reserve(sci.capacity());
@@ -802,14 +807,20 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
                 sval.resize(base + 64 * static_cast<size_t>(L), 0);
                 for (int l = 0; l < 64 && c * 64 + l < rows; ++l) {
                     const int r = order[c * 64 + l];
-                    srow[(static_cast<size_t>(q) * nch + c) * 64 + l] = r;
-                    int k = 0;
+                    const size_t slot = (static_cast<size_t>(q) * nch + c) * 64 + l;
+                    srow[slot] = r;
+                    int k = 0, first = -1;
+                    bool contiguous = true;
                     for (int e = rpx[r]; e < rpx[r + 1]; ++e)
                         if ((cix[e] / ns) == q) {
                             sci[base + 64 * k + l] = cix[e];
                             sval[base + 64 * k + l] = valx[e];
+                            if (k == 0) first = cix[e];
+                            else contiguous = contiguous && cix[e] == first + k;
                             ++k;
                         }
+                    slen[slot] = k;
+                    if (k > 0 && contiguous) sc0[slot] = first;
                 }
             }
             sptr[q * (nch + 1) + nch] = static_cast<int>(sci.size());
@@ -819,6 +830,8 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         if ((r2 = upload(s, buf[1], sci.data(), static_cast<int64_t>(sci.size())))) return r2;
         if ((r2 = upload(s, buf[2], sval.data(), static_cast<int64_t>(sval.size())))) return r2;
         if ((r2 = upload(s, buf[3], srow.data(), static_cast<int64_t>(srow.size())))) return r2;
+        if ((r2 = upload(s, buf[4], sc0.data(), static_cast<int64_t>(sc0.size())))) return r2;
+        if ((r2 = upload(s, buf[5], slen.data(), static_cast<int64_t>(slen.size())))) return r2;
         if ((r2 = sync(P))) return r2;
         sv.nrows = static_cast<int>(rows);
         sv.P = Pn;
@@ -828,6 +841,8 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         sv.ci = buf[1];
         sv.val = buf[2];
         sv.row_of = buf[3];
+        sv.c0 = buf[4];
+        sv.len = buf[5];
         return GFORS_OK;
     };
     if (P->sellK_want && (rc = build_sell(m, n, 1, rp, ci, val, static_cast<int>(n), P->sellK_cap, P->sellK_buf, P->sellK))) return rc;
@@ -859,6 +874,14 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             if (dense) c0v[j] = ci[b0];
         }
         if ((rc = upload(s, P->rowc0, c0v.data(), m))) return rc;
+        std::vector<int> r0v(n, -1);
+        for (int64_t i = 0; i < n; ++i) {
+            const int b0 = rpT[i], b1 = rpT[i + 1];
+            bool dense = b1 > b0;
+            for (int e = b0 + 1; e < b1 && dense; ++e) dense = ciT[e] == ciT[b0] + (e - b0);
+            if (dense) r0v[i] = ciT[b0];
+        }
+        if ((rc = upload(s, P->colT0, r0v.data(), n))) return rc;
         if ((rc = sync(P))) return rc;
         P->heavy_rows = 0;
         while (P->heavy_rows < m && rp[ord[P->heavy_rows] + 1] - rp[ord[P->heavy_rows]] >= kHeavyLen) ++P->heavy_rows;
@@ -1178,10 +1201,10 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
                            P->valT, P->wy, x_in, x_out, xbar, P->ct, tau1, P->di.tau1, P->di.rho,
                            P->var_inst);
         launch_primal(s, lpr - kLprBlock, kmode, false, batched, static_cast<int>(P->n), P->rpT,
-                      P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct,
+                      P->colT0, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct,
                       tau1, 0.f, P->di.tau1, P->di.two_so, P->di.rho, P->var_inst, ctr, kHeavyLen);
     } else {
-        launch_primal(s, lpr, kmode, P->hasQ, batched, static_cast<int>(P->n), P->rpT, P->ciT,
+        launch_primal(s, lpr, kmode, P->hasQ, batched, static_cast<int>(P->n), P->rpT, P->colT0, P->ciT,
                       P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct, tau1,
                       static_cast<float>(P->s_o[0] > 0 ? 2.0 / P->s_o[0] : 2.0), P->di.tau1,
                       P->di.two_so, P->di.rho, P->var_inst, ctr, 0);

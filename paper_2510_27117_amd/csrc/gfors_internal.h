@@ -73,6 +73,9 @@ constexpr int64_t kMaxLdsBitmapBytes = 64 * 1024;
 struct SellView {
     int nrows = 0, P = 1, nchunk = 0, ns = 0;   // ns: columns per slice (multiple of 64)
     const int *ptr = nullptr, *ci = nullptr, *val = nullptr, *row_of = nullptr;
+    // per slot: first column of a row whose entries in the slice are one
+    // contiguous range (else -1) and the row's entry count in the slice
+    const int *c0 = nullptr, *len = nullptr;
 };
 
 constexpr int kXcdSlices = 8;   // XCDs per MI355X
@@ -94,7 +97,7 @@ void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
                  int skip_len);
 
 void launch_primal(hipStream_t s, int lpr, int kmode, bool hasq, bool batched, int n,
-                   const int *rpT, const int *ciT, const int *valT, const float *wy,
+                   const int *rpT, const int *colT0, const int *ciT, const int *valT, const float *wy,
                    const int *rpQ, const int *ciQ, const int *valQ, const float *x_in,
                    float *x_out, float *xbar, const float *ct, float tau1, float two_so,
                    const float *tau1_inst, const float *two_so_inst, const double *rho,

@@ -218,7 +218,7 @@ void launch_primal_long(hipStream_t s, bool unit, bool batched, int count, const
 // ---------------------------------------------------------------------------
 template <int LPR, int KMODE, bool HASQ, bool BATCH>
 __global__ void __launch_bounds__(256)
-k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ ciT,
+k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ colT0, const int *__restrict__ ciT,
          const int *__restrict__ valT, const float *__restrict__ wy,
          const int *__restrict__ rpQ, const int *__restrict__ ciQ, const int *__restrict__ valQ,
          const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ xbar,
@@ -243,9 +243,16 @@ k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ ciT,
     }
     if (own) {
         if (KMODE != 0) {
-            const int e1 = rpT[i + 1];
-            for (int e = rpT[i] + sub; e < e1; e += LPR) {
-                const float w = wy[ciT[e]];
+            // a variable whose rows are one contiguous range (dense rows of a
+            // batched instance) computes its row indices instead of loading them
+            const int e0 = rpT[i], e1 = rpT[i + 1];
+            const int r0 = colT0[i];
+#pragma unroll 4
+            for (int e = e0 + sub; e < e1; e += LPR) {
+                int j;
+                if (r0 >= 0) j = r0 + (e - e0);
+                else j = ciT[e];
+                const float w = wy[j];
                 if (KMODE == 1) s1 += w;
                 else s1 = fmaf(static_cast<float>(valT[e]), w, s1);
             }
@@ -301,7 +308,7 @@ void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
 }
 
 template <int LPR, int KMODE, bool HASQ>
-static void primal_k(hipStream_t s, bool batched, int n, const int *rpT, const int *ciT,
+static void primal_k(hipStream_t s, bool batched, int n, const int *rpT, const int *colT0, const int *ciT,
                      const int *valT, const float *wy, const int *rpQ, const int *ciQ,
                      const int *valQ, const float *x_in, float *x_out, float *xbar,
                      const float *ct, float tau1, float two_so, const float *tau1_inst,
@@ -311,19 +318,19 @@ static void primal_k(hipStream_t s, bool batched, int n, const int *rpT, const i
     const int blocks = static_cast<int>((threads + 255) / 256);
     if (blocks == 0) return;
     if (batched)
-        k_primal<LPR, KMODE, HASQ, true><<<blocks, 256, 0, s>>>(n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len);
+        k_primal<LPR, KMODE, HASQ, true><<<blocks, 256, 0, s>>>(n, rpT, colT0, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len);
     else
-        k_primal<LPR, KMODE, HASQ, false><<<blocks, 256, 0, s>>>(n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len);
+        k_primal<LPR, KMODE, HASQ, false><<<blocks, 256, 0, s>>>(n, rpT, colT0, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len);
 }
 
 template <int LPR>
 static void primal_lpr(hipStream_t s, int kmode, bool hasq, bool batched, int n,
-                       const int *rpT, const int *ciT, const int *valT, const float *wy,
+                       const int *rpT, const int *colT0, const int *ciT, const int *valT, const float *wy,
                        const int *rpQ, const int *ciQ, const int *valQ, const float *x_in,
                        float *x_out, float *xbar, const float *ct, float tau1, float two_so,
                        const float *tau1_inst, const float *two_so_inst, const double *rho,
                        const int *var_inst, DevCounters *ctr, int skip_len) {
-#define GF_P(KM, HQ) primal_k<LPR, KM, HQ>(s, batched, n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len)
+#define GF_P(KM, HQ) primal_k<LPR, KM, HQ>(s, batched, n, rpT, colT0, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len)
     if (hasq) {
         if (kmode == 0) GF_P(0, true); else if (kmode == 1) GF_P(1, true); else GF_P(2, true);
     } else {
@@ -333,13 +340,13 @@ static void primal_lpr(hipStream_t s, int kmode, bool hasq, bool batched, int n,
 }
 
 void launch_primal(hipStream_t s, int lpr, int kmode, bool hasq, bool batched, int n,
-                   const int *rpT, const int *ciT, const int *valT, const float *wy,
+                   const int *rpT, const int *colT0, const int *ciT, const int *valT, const float *wy,
                    const int *rpQ, const int *ciQ, const int *valQ, const float *x_in,
                    float *x_out, float *xbar, const float *ct, float tau1, float two_so,
                    const float *tau1_inst, const float *two_so_inst, const double *rho,
                    const int *var_inst, DevCounters *ctr, int skip_len) {
     switch (lpr) {
-#define GF_CASE(L) case L: primal_lpr<L>(s, kmode, hasq, batched, n, rpT, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len); break;
+#define GF_CASE(L) case L: primal_lpr<L>(s, kmode, hasq, batched, n, rpT, colT0, ciT, valT, wy, rpQ, ciQ, valQ, x_in, x_out, xbar, ct, tau1, two_so, tau1_inst, two_so_inst, rho, var_inst, ctr, skip_len); break;
         GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
 #undef GF_CASE
         default: break;
@@ -503,7 +510,8 @@ void launch_primal_combine(hipStream_t s, bool batched, int n, int P, const floa
 template <bool UNIT, int MODE, bool BATCH>
 __global__ void __launch_bounds__(256)
 k_sell(int nrows, int P, int nchunk, const int *__restrict__ ptr, const int *__restrict__ ci,
-       const int *__restrict__ val, const int *__restrict__ row_of, const float *__restrict__ v,
+       const int *__restrict__ val, const int *__restrict__ row_of, const int *__restrict__ sc0,
+       const int *__restrict__ slen, const float *__restrict__ v,
        float *__restrict__ part,
        // dual epilogue
        int m1, const float *__restrict__ omega, const float *__restrict__ rt,
@@ -524,7 +532,22 @@ k_sell(int nrows, int P, int nchunk, const int *__restrict__ ptr, const int *__r
     const int L = (ptr[pb + c + 1] - e0) >> 6;
     const int *cic = ci + e0 + lane;
     float acc = 0.f;
-    if (UNIT) {
+    const int64_t slot = (static_cast<int64_t>(sl) * nchunk + c) * 64 + lane;
+    const int cb = sc0[slot];
+    if (cb >= 0) {
+        // the row's entries here are the columns cb, cb + 1, ...: indices are
+        // computed; slots past its length add 0 like the padding entries
+        const int ln = slen[slot];
+        if (UNIT) {
+#pragma unroll 4
+            for (int k = 0; k < L; ++k) acc += k < ln ? v[cb + k] : 0.f;
+        } else {
+            const int *vc = val + e0 + lane;
+#pragma unroll 4
+            for (int k = 0; k < L; ++k)
+                acc = fmaf(static_cast<float>(__builtin_nontemporal_load(vc + 64 * k)), k < ln ? v[cb + k] : 0.f, acc);
+        }
+    } else if (UNIT) {
 #pragma unroll 4
         for (int k = 0; k < L; ++k) acc += v[__builtin_nontemporal_load(cic + 64 * k)];
     } else {
@@ -566,7 +589,7 @@ void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool ba
                  const int *var_inst, DevCounters *ctr) {
     const int64_t blocks = static_cast<int64_t>((sv.nchunk + 3) / 4) * sv.P;
     if (blocks == 0) return;
-#define GF_SELL(U, M, B)     k_sell<U, M, B><<<static_cast<int>(blocks), 256, 0, s>>>(sv.nrows, sv.P, sv.nchunk, sv.ptr, sv.ci, sv.val, sv.row_of, v, part, m1, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
+#define GF_SELL(U, M, B)     k_sell<U, M, B><<<static_cast<int>(blocks), 256, 0, s>>>(sv.nrows, sv.P, sv.nchunk, sv.ptr, sv.ci, sv.val, sv.row_of, sv.c0, sv.len, v, part, m1, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
 #define GF_SELL_M(U, B)     if (mode == 0) GF_SELL(U, 0, B); else if (mode == 1) GF_SELL(U, 1, B); else GF_SELL(U, 2, B)
     if (unit) { if (batched) { GF_SELL_M(true, true); } else { GF_SELL_M(true, false); } }
     else { if (batched) { GF_SELL_M(false, true); } else { GF_SELL_M(false, false); } }
