@@ -72,29 +72,63 @@ def _csr_dot(M, x):
     return S @ np.asarray(x, dtype=np.int64)
 
 
-def kernel_bytes(bip, K):
+def indexed_entries(bip):
+    """Entries of [A; B] whose index must be read: a row whose columns form one
+    contiguous range needs only its first column, and likewise a variable
+    whose rows form one (the transposed products).  Returns (row-major,
+    variable-major) counts."""
+    mats = [M for M in (bip.A, bip.B) if M is not None and M.nrows]
+    if not mats:
+        return 0, 0
+    rp = np.concatenate([np.asarray(mats[0].row_ptr, dtype=np.int64)] +
+                        [np.asarray(M.row_ptr[1:], dtype=np.int64) + sum(P.nnz for P in mats[:i])
+                         for i, M in enumerate(mats) if i])
+    col = np.concatenate([np.asarray(M.col, dtype=np.int64) for M in mats])
+    m, ln = len(rp) - 1, np.diff(rp)
+    rows = np.repeat(np.arange(m, dtype=np.int64), ln)
+    # row-major: a row is contiguous when its last column is first + len - 1
+    first = np.where(ln > 0, col[np.minimum(rp[:-1], len(col) - 1)], 0)
+    last = np.where(ln > 0, col[np.maximum(rp[1:] - 1, 0)], 0)
+    rsorted = np.all(np.diff(col)[np.diff(rows) == 0] > 0) if len(col) > 1 else True
+    rcont = (ln > 0) & (last - first + 1 == ln) & bool(rsorted)
+    row_major = int(ln[~rcont].sum())
+    # variable-major: rows of each variable, by count, min and max
+    n = bip.n
+    cnt = np.bincount(col, minlength=n)
+    lo = np.full(n, np.iinfo(np.int64).max)
+    hi = np.full(n, -1)
+    np.minimum.at(lo, col, rows)
+    np.maximum.at(hi, col, rows)
+    ccont = (cnt > 0) & (hi - lo + 1 == cnt)
+    var_major = int(cnt[~ccont].sum())
+    return row_major, var_major
+
+
+def kernel_bytes(bip, K, idx=None):
     """Algorithmic HBM bytes per launch: every array the kernel must touch,
-    counted once (gathered vectors by their unique size)."""
+    counted once (gathered vectors by their unique size); indices only where
+    the entries are not one contiguous range (idx = indexed_entries)."""
     n, m = bip.n, bip.m1 + bip.m2
     nnzK = (0 if bip.A is None else bip.A.nnz) + (0 if bip.B is None else bip.B.nnz)
     unit = (bip.A is None or bip.A.val is None) and (bip.B is None or bip.B.val is None)
     nnzQ = 0 if bip.Q is None else bip.Q.nnz
     vb = 0 if unit else 4
+    ir, ic = (nnzK, nnzK) if idx is None else idx
     W = K // 64
     out = {}
     if m:
         # row_ptr + col (+val) + xbar (unique) + omega, rt, y_in, y_out, wy
-        out["dual"] = 4 * (m + 1) + (4 + vb) * nnzK + 4 * n + 20 * m
+        out["dual"] = 4 * (m + 1) + 4 * ir + vb * nnzK + 4 * n + 20 * m
     prim = 16 * n  # x_in, ct read; x_out, xbar written
     if m:
-        prim += 4 * (n + 1) + (4 + vb) * nnzK + 4 * m
+        prim += 4 * (n + 1) + 4 * ic + vb * nnzK + 4 * m
     if nnzQ:
         prim += 4 * (n + 1) + 8 * nnzQ
     out["primal"] = prim
     out["sample"] = 8 * n * W + 4 * n + 8 * n          # candidate words + p + cost
     if m:
-        out["eval_cover"] = 4 * (m + 1) + 4 * nnzK + 8 * n * W
-        out["eval_general"] = 4 * (m + 1) + (4 + vb) * nnzK + 8 * n * W + 8 * m
+        out["eval_cover"] = 4 * (m + 1) + 4 * ir + 8 * n * W
+        out["eval_general"] = 4 * (m + 1) + 4 * ir + vb * nnzK + 8 * n * W + 8 * m
     if nnzQ:
         out["eval_quad"] = 4 * (n + 1) + 8 * nnzQ + 8 * n * W
     return out
@@ -422,7 +456,7 @@ def main():
     # per-kernel HIP-event durations (eager launches, same stream, state advances)
     kt = G.kernel_times(a.k_int, a.K)
     per_step = {k: ms * (a.k_int if k in ("dual", "primal") else 1) for k, (ms, cnt) in kt.items() if cnt}
-    kb = kernel_bytes(bip, a.K)
+    kb = kernel_bytes(bip, a.K, indexed_entries(bip))
     dom = max((k for k in per_step if k in kb), key=lambda k: per_step[k])
     avg_ms = kt[dom][0]
     achieved = kb[dom] / (avg_ms * 1e-3) / 1e9

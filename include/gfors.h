@@ -75,13 +75,20 @@ typedef struct {
  *                or XCD-sliced) on the problem at creation and keep the fastest;
  *                0: use the size heuristic (deterministic choice)
  *   x0           starting point x_0 = x0 * 1 (in [0,1])
- *   seed         Philox4x32-10 key (low 32 bits = key word 0, high = key word 1) */
+ *   seed         Philox4x32-10 key (low 32 bits = key word 0, high = key word 1)
+ *   eval_mfma    1: evaluate long general rows (EvalBest, Sec. 3) as dense
+ *                blocks of <= 32 rows on the int8 matrix cores when every block
+ *                is at least half full and every coefficient has at most 3
+ *                signed base-256 digits (results identical to the row-by-row
+ *                sums); 0: always row by row.  The workspace grows by
+ *                3 (2 nnz(A,B) + 48 (m1 + m2)) bytes when 1. */
 typedef struct {
     double sigma, tau1, tau2;
     double rho_min, rho_max, rho_T, rho_p, rho_delta;
     int32_t k_int, K_max, power_iters, hist_cap, autotune;
     double x0;
     uint64_t seed;
+    int32_t eval_mfma;
 } gfors_params;
 
 void gfors_default_params(gfors_params *p);
@@ -351,6 +358,12 @@ const char *gfors_mono_last_error(void);
 
 /* Dimensions: n, m1, m2, number of instances. */
 int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32_t *T);
+
+/* How EvalBest (Sec. 3) evaluates the general rows of this problem: *planes
+ * = 1..3 when they run as dense int8 digit blocks on the matrix cores (the
+ * number of signed base-256 digit planes), 0 when row by row.  Fixed at
+ * creation (see gfors_params.eval_mfma). */
+int gfors_eval_planes(gfors_problem *P, int32_t *planes);
 
 #ifdef __cplusplus
 }

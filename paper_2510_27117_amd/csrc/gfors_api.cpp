@@ -44,6 +44,13 @@ constexpr int kQuadRows = 64;          // variables per Q tile (max): many tiles
 constexpr int kVarTile = 4096;        // variables per FP64 reduction tile
 constexpr int kRowNnz = 16384;        // nnz budget of a residual row tile
 constexpr int kRowRows = 2048;
+constexpr int kMfmaRows = 32;          // rows per dense digit block (one 32 x 32 matrix-core tile)
+constexpr int kMfmaMaxSpan = 1 << 23;  // column span of a block: keeps int32 plane sums exact
+
+// Bytes of the densified digit blocks: 3 planes at most, each block at least
+// half full (rows x span <= 2 nnz) plus 31 padding columns and 16-byte
+// alignment per row.
+int64_t mf_digit_cap(int64_t nnzK, int64_t m) { return 3 * (2 * nnzK + 48 * m); }
 
 enum RowClass { kCover = 0, kGeneral = 1 };
 
@@ -126,6 +133,13 @@ struct gfors_problem {
     int *cover_ids = nullptr, *general_ids = nullptr;
     int n_cover = 0, n_general = 0;
     bool general_long = false;   // general rows average >= 256 entries: split rows over wavefronts
+    // general rows evaluated as dense int8 digit blocks on the matrix cores
+    bool mfma = false;
+    int mf_npl = 0;              // digit planes (1..3)
+    int64_t mf_cap = 0;
+    int8_t *mf_dig = nullptr;
+    int64_t *mf_off = nullptr;   // per tile: byte offset of its block
+    int *mf_c0 = nullptr, *mf_span = nullptr;
     int *rows = nullptr;
     uint8_t *rkind = nullptr;    // per row: evaluation kind << 4 | truth table (pair rows)
     uint8_t *xkind = nullptr;    // per variable, last round: 0 sampled, 1 all zero, 2 all one
@@ -285,6 +299,7 @@ void gfors_default_params(gfors_params *p) {
     p->autotune = 1;
     p->x0 = 0.0;
     p->seed = 0;
+    p->eval_mfma = 1;
 }
 
 const char *gfors_last_error(void) { return g_err.c_str(); }
@@ -351,6 +366,11 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->primal_order = cv.take<int>(n);
     P->cover_ids = cv.take<int>(b.et);
     P->general_ids = cv.take<int>(b.et);
+    P->mf_cap = prm->eval_mfma && m > 0 ? mf_digit_cap(nnzK, m) : 0;
+    P->mf_dig = cv.take<int8_t>(P->mf_cap);
+    P->mf_off = cv.take<int64_t>(b.et);
+    P->mf_c0 = cv.take<int>(b.et);
+    P->mf_span = cv.take<int>(b.et);
     P->pv = cv.take<double>(n);
     P->pu = cv.take<double>(n);
     P->pw = cv.take<double>(std::max(n, m));
@@ -641,6 +661,79 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     for (int64_t i = 0; i < n; ++i) cmax = std::max<int64_t>(cmax, std::llabs(c[i]));
     P->obj64 = cmax > 0 && (static_cast<double>(cmax) * 4.0 * kSampleTQ >= 2147483647.0);
 
+    // general rows as dense digit blocks: per instance, the general rows are
+    // ordered by column range (the order of rows does not change a count) and
+    // cut into greedy runs of at most 32 rows whose entries fill at least
+    // half of rows x column span; used when every block qualifies
+    struct MfTile { int64_t q0, q1; int c0, span; };
+    std::vector<std::vector<MfTile>> mf_tiles(T);
+    std::vector<std::vector<int>> mf_rows(T);
+    {
+        int64_t grows = 0, gnnz = 0;
+        for (int64_t j = 0; j < m; ++j)
+            if (cls[j] != kCover) { ++grows; gnnz += rp[j + 1] - rp[j]; }
+        P->general_long = grows > 0 && gnnz >= 256 * grows;
+        const int64_t mf_cap = prm->eval_mfma && m > 0 ? mf_digit_cap(P->nnzK, m) : 0;   // as carved below
+        P->mfma = mf_cap > 0 && P->general_long;
+        int npl = 1;
+        for (int64_t j = 0; j < m && P->mfma; ++j) {
+            if (cls[j] == kCover) continue;
+            for (int e = rp[j]; e < rp[j + 1]; ++e) {
+                int64_t rem = val[e];
+                int nd = 0;
+                do {
+                    const int64_t dgt = static_cast<int8_t>(rem & 255);
+                    rem = (rem - dgt) >> 8;
+                    ++nd;
+                } while (rem != 0);
+                npl = std::max(npl, nd);
+            }
+        }
+        if (npl > 3) P->mfma = false;
+        P->mf_npl = npl;
+        int64_t count = 0, bytes = 0;
+        for (int t = 0; t < T && P->mfma; ++t) {
+            std::vector<int> L;
+            for (int64_t j = off[3 * t + 1]; j < off[3 * (t + 1) + 1]; ++j)
+                if (cls[j] != kCover) L.push_back(static_cast<int>(j));
+            for (int64_t j = off[3 * t + 2]; j < off[3 * (t + 1) + 2]; ++j)
+                if (cls[P->m1 + j] != kCover) L.push_back(static_cast<int>(P->m1 + j));
+            const int64_t nL = static_cast<int64_t>(L.size());
+            std::vector<int64_t> rlo(nL, INT64_MAX), rhi(nL, -1);
+            for (int64_t q = 0; q < nL; ++q)
+                for (int e = rp[L[q]]; e < rp[L[q] + 1]; ++e) {
+                    rlo[q] = std::min<int64_t>(rlo[q], ci[e]);
+                    rhi[q] = std::max<int64_t>(rhi[q], ci[e]);
+                }
+            std::vector<int64_t> ord(nL);
+            for (int64_t q = 0; q < nL; ++q) ord[q] = q;
+            std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b2) {
+                return rlo[a] != rlo[b2] ? rlo[a] < rlo[b2] : rhi[a] < rhi[b2];
+            });
+            std::vector<int> Ls(nL);
+            for (int64_t q = 0; q < nL; ++q) Ls[q] = L[ord[q]];
+            for (int64_t q = 0; q < nL && P->mfma;) {
+                int64_t lo = INT64_MAX, hi = -1, sum = 0, q1 = q;
+                while (q1 < nL && q1 - q < kMfmaRows) {
+                    const int j = Ls[q1];
+                    const int64_t nlo = std::min(lo, rlo[ord[q1]]), nhi = std::max(hi, rhi[ord[q1]]);
+                    const int64_t nsum = sum + rp[j + 1] - rp[j];
+                    const int64_t nspan = nhi >= nlo ? nhi - nlo + 1 : 0;
+                    if (q1 > q && nspan * (q1 - q + 1) > 2 * nsum) break;
+                    lo = nlo; hi = nhi; sum = nsum; ++q1;
+                }
+                const int64_t span = hi >= lo ? hi - lo + 1 : 0;
+                if (span * (q1 - q) > 2 * sum || span > kMfmaMaxSpan) { P->mfma = false; break; }
+                mf_tiles[t].push_back({q, q1, static_cast<int>(span ? lo : P->inst_var0[t]), static_cast<int>(span)});
+                ++count;
+                bytes += (static_cast<int64_t>(npl) * (q1 - q) * ((span + 31) / 32 * 32) + 15) / 16 * 16;
+                q = q1;
+            }
+            mf_rows[t] = std::move(Ls);
+        }
+        if (count > (P->nnzK + m) / kEvalNnz + 4 * static_cast<int64_t>(T) + 8 || bytes > mf_cap) P->mfma = false;
+    }
+
     // ---- tiles
     HostTiles hs, he, hq, hv, hr;
     std::vector<int> rows_list;
@@ -655,13 +748,21 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         for (int64_t j = off[3 * t + 2]; j < off[3 * (t + 1) + 2]; ++j) rc_list[cls[P->m1 + j]].push_back(static_cast<int>(P->m1 + j));
         for (int k = 0; k < 2; ++k) {
             const int64_t base = static_cast<int64_t>(rows_list.size());
-            const std::vector<int> &L = rc_list[k];
+            const std::vector<int> &L = (k == kGeneral && P->mfma) ? mf_rows[t] : rc_list[k];
             rows_list.insert(rows_list.end(), L.begin(), L.end());
             std::function<int64_t(int64_t)> wfun = [&](int64_t q) -> int64_t { return rp[L[q] + 1] - rp[L[q]]; };
             const size_t before = he.inst.size();
-            build_tiles_items(he, t, static_cast<int64_t>(L.size()), &wfun,
-                              k == kCover ? kBitwiseNnz : kEvalNnz,
-                              k == kCover ? kCoverRows : kGeneralRows, base);
+            if (k == kGeneral && P->mfma) {
+                for (const MfTile &mt : mf_tiles[t]) {
+                    he.inst.push_back(t);
+                    he.b0.push_back(static_cast<int32_t>(base + mt.q0));
+                    he.b1.push_back(static_cast<int32_t>(base + mt.q1));
+                }
+            } else {
+                build_tiles_items(he, t, static_cast<int64_t>(L.size()), &wfun,
+                                  k == kCover ? kBitwiseNnz : kEvalNnz,
+                                  k == kCover ? kCoverRows : kGeneralRows, base);
+            }
             for (size_t q = before; q < he.inst.size(); ++q)
                 (k == kCover ? cover_ids : general_ids).push_back(static_cast<int>(q));
         }
@@ -689,12 +790,6 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     }
     P->n_cover = static_cast<int>(cover_ids.size());
     P->n_general = static_cast<int>(general_ids.size());
-    {
-        int64_t grows = 0, gnnz = 0;
-        for (int64_t j = 0; j < m; ++j)
-            if (cls[j] != kCover) { ++grows; gnnz += rp[j + 1] - rp[j]; }
-        P->general_long = grows > 0 && gnnz >= 256 * grows;
-    }
 
     // ---- carve the workspace
     Carver cv{static_cast<char *>(ws), 0, ws_bytes};
@@ -860,6 +955,45 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     if ((rc = upload(s, P->rkind, P->rkind_host.data(), m))) return rc;
     if ((rc = upload(s, P->cover_ids, cover_ids.data(), P->n_cover))) return rc;
     if ((rc = upload(s, P->general_ids, general_ids.data(), P->n_general))) return rc;
+    if (P->mfma) {
+        // densified digit blocks of the general tiles (signed base-256 digits)
+        const int npl = P->mf_npl;
+        std::vector<int64_t> offh(he.inst.size(), 0);
+        std::vector<int> c0h(he.inst.size(), 0), sph(he.inst.size(), 0);
+        int64_t total = 0;
+        {
+            int ti = 0;
+            for (int t = 0; t < T; ++t)
+                for (const MfTile &mt : mf_tiles[t]) {
+                    const int id = general_ids[ti++];
+                    offh[id] = total;
+                    c0h[id] = mt.c0;
+                    sph[id] = mt.span;
+                    total += (static_cast<int64_t>(npl) * (mt.q1 - mt.q0) * ((mt.span + 31) / 32 * 32) + 15) / 16 * 16;
+                }
+        }
+        std::vector<int8_t> digh(static_cast<size_t>(total), 0);
+        for (int id : general_ids) {
+            const int R = he.b1[id] - he.b0[id];
+            const int64_t pitch = (sph[id] + 31) / 32 * 32;
+            for (int i = 0; i < R; ++i) {
+                const int j = rows_list[he.b0[id] + i];
+                for (int e = rp[j]; e < rp[j + 1]; ++e) {
+                    int64_t rem = val[e];
+                    for (int p = 0; p < npl; ++p) {
+                        const int8_t dgt = static_cast<int8_t>(rem & 255);
+                        rem = (rem - dgt) >> 8;
+                        digh[offh[id] + (static_cast<int64_t>(p) * R + i) * pitch + (ci[e] - c0h[id])] = dgt;
+                    }
+                }
+            }
+        }
+        if ((rc = upload(s, P->mf_dig, digh.data(), total))) return rc;
+        if ((rc = upload(s, P->mf_off, offh.data(), static_cast<int64_t>(offh.size())))) return rc;
+        if ((rc = upload(s, P->mf_c0, c0h.data(), static_cast<int64_t>(c0h.size())))) return rc;
+        if ((rc = upload(s, P->mf_span, sph.data(), static_cast<int64_t>(sph.size())))) return rc;
+        if ((rc = sync(P))) return rc;
+    }
     {
         std::vector<int> ord(m);
         for (int64_t j = 0; j < m; ++j) ord[j] = static_cast<int>(j);
@@ -1377,9 +1511,14 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
                       P->xkind, W, P->vpart, K);
     TE(3);
     TB(4);
-    launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
-                        P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X,
-                        P->xkind, W, P->vpart, K, P->general_long, P->coef24);
+    if (P->mfma)
+        launch_eval_mfma(s, P->n_general, P->general_ids, P->et, P->mf_npl, P->rows, P->mf_off,
+                         P->mf_c0, P->mf_span, P->mf_dig, P->rhs, static_cast<int>(P->m1), P->X, W,
+                         P->vpart, K);
+    else
+        launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
+                            P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X,
+                            P->xkind, W, P->vpart, K, P->general_long, P->coef24);
     TE(4);
     TB(5);
     if (P->hasQ)
@@ -1655,6 +1794,12 @@ int gfors_autotune(gfors_problem *P) {
     if (!P) return fail(GFORS_E_ARG, "NULL handle");
     P->graphs_clear();
     return autotune(P);
+}
+
+int gfors_eval_planes(gfors_problem *P, int32_t *planes) {
+    if (!P || !planes) return fail(GFORS_E_ARG, "bad argument");
+    *planes = P->mfma ? P->mf_npl : 0;
+    return GFORS_OK;
 }
 
 int gfors_get_launch_cfg(gfors_problem *P, int32_t *out) {

@@ -567,6 +567,155 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
     }
 }
 
+// Dense blocks of general rows on the int8 matrix cores.  A tile holds up to
+// 32 rows of one instance whose entries fill at least half of the block
+// rows x [c0, c0 + span); its coefficients are stored once, densified, as
+// NPL planes of signed base-256 digits (a = sum_p d_p 256^p, d_p in
+// [-128, 127]) in int8, plane-major then row-major with the span padded to
+// a multiple of 32.  Then row sums over the candidates of one word are the
+// product  C_p = D_p (R x span) . Xbits (span x 64)  with exact int32
+// accumulation (|C_p| <= 128 span < 2^31), combined as sum_p C_p 256^p in
+// int64: the same integers as the entry-by-entry sums.
+// A workgroup takes one tile and one candidate word; its four wavefronts
+// split the span into quarters of 32-variable k-steps.  Per k-step a lane
+// (row i = lane & 31, k-half g = lane >> 5) loads 16 digits of each plane
+// (one 16-byte load) as the A operand of v_mfma_i32_32x32x32_i8, and builds
+// the B operands of the word's two 32-candidate halves from the candidate
+// bits of the same 16 variables (staged per wavefront in LDS, 64 variables
+// per load): byte b of the lane is bit (32 t + (lane & 31)) of variable
+// 16 g + b.  A and B use the same (g, byte) -> variable map, so the
+// contraction does not depend on how the instruction orders k.  The four
+// partial products are added in LDS and wavefront 0 tests each row for each
+// candidate.  Workgroups of one tile share an XCD (blockIdx % 8) so that the
+// tile's digits are read from HBM once per word group, then from L2.
+typedef int gf_v4i __attribute__((ext_vector_type(4)));
+typedef int gf_v16i __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int gf_bytes_of_bits(uint32_t h0, uint32_t h1, uint32_t h2, uint32_t h3,
+                                                unsigned sh) {
+    return static_cast<int>(__builtin_amdgcn_ubfe(h0, sh, 1u) | (__builtin_amdgcn_ubfe(h1, sh, 1u) << 8) |
+                            (__builtin_amdgcn_ubfe(h2, sh, 1u) << 16) | (__builtin_amdgcn_ubfe(h3, sh, 1u) << 24));
+}
+
+template <int NPL>
+__global__ void __launch_bounds__(256)
+k_eval_mfma(int ntiles, int W, const int *__restrict__ tile_ids, const int *__restrict__ tb0,
+            const int *__restrict__ tb1, const int *__restrict__ rows,
+            const int64_t *__restrict__ mf_off, const int *__restrict__ mf_c0,
+            const int *__restrict__ mf_span, const int8_t *__restrict__ dig,
+            const int64_t *__restrict__ rhs, int m1, const uint64_t *__restrict__ X,
+            int *__restrict__ vpart, int K) {
+    __shared__ uint64_t xs[4][64];
+    __shared__ int64_t red[3][2][16][64];
+    const int b = blockIdx.x;
+    const int r = b >> 3;
+    const int w = r % W;
+    const int ti = (r / W) * 8 + (b & 7);
+    if (ti >= ntiles) return;                      // whole workgroup, before any barrier
+    const int tile = tile_ids[ti];
+    const int r0 = tb0[tile], R = tb1[tile] - r0;
+    const int c0 = mf_c0[tile], span = mf_span[tile];
+    const int nk = (span + 31) >> 5;               // k-steps; digits padded to 32 nk per row
+    const int8_t *dt = dig + mf_off[tile];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int i = lane & 31, g = lane >> 5;
+    const unsigned sh = static_cast<unsigned>(i);
+    const int k0 = (nk * wave) >> 2, k1 = (nk * (wave + 1)) >> 2;
+    const int64_t pitch = static_cast<int64_t>(nk) * 32;
+    gf_v16i acc[2][NPL];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) acc[t][p] = gf_v16i{};
+    const int8_t *arow = dt + static_cast<int64_t>(i) * pitch + 16 * g;
+    const bool live = i < R;
+    for (int ks = k0; ks < k1; ks += 2) {
+        // candidate words of the 64 variables of k-steps ks, ks + 1 (clamped
+        // to the span's last variable; their digits are zero)
+        const int v = min(c0 + 32 * ks + lane, c0 + span - 1);
+        xs[wave][lane] = X[static_cast<int64_t>(v) * W + w];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            if (ks + s2 < k1) {
+                gf_v4i a[NPL];
+#pragma unroll
+                for (int p = 0; p < NPL; ++p)
+                    a[p] = live ? *reinterpret_cast<const gf_v4i *>(arow + p * R * pitch + 32 * (ks + s2))
+                                : gf_v4i{};
+                const uint64_t *xv = &xs[wave][32 * s2 + 16 * g];
+                uint32_t lo[16], hi[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const uint64_t x = xv[q];
+                    lo[q] = static_cast<uint32_t>(x);
+                    hi[q] = static_cast<uint32_t>(x >> 32);
+                }
+                gf_v4i bl, bh;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    bl[d] = gf_bytes_of_bits(lo[4 * d], lo[4 * d + 1], lo[4 * d + 2], lo[4 * d + 3], sh);
+                    bh[d] = gf_bytes_of_bits(hi[4 * d], hi[4 * d + 1], hi[4 * d + 2], hi[4 * d + 3], sh);
+                }
+#pragma unroll
+                for (int p = 0; p < NPL; ++p) {
+                    acc[0][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[p], bl, acc[0][p], 0, 0, 0);
+                    acc[1][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[p], bh, acc[1][p], 0, 0, 0);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // row sums: register q of half t holds row 8 (q / 4) + 4 g + (q % 4),
+    // candidate 64 w + 32 t + (lane & 31)
+    if (wave > 0) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                int64_t sum = 0;
+#pragma unroll
+                for (int p = 0; p < NPL; ++p) sum += static_cast<int64_t>(acc[t][p][q]) << (8 * p);
+                red[wave - 1][t][q][lane] = sum;
+            }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        int cnt[2] = {0, 0};
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int row = 8 * (q >> 2) + 4 * g + (q & 3);
+                if (row < R) {
+                    int64_t sum = red[0][t][q][lane] + red[1][t][q][lane] + red[2][t][q][lane];
+#pragma unroll
+                    for (int p = 0; p < NPL; ++p) sum += static_cast<int64_t>(acc[t][p][q]) << (8 * p);
+                    const int j = rows[r0 + row];
+                    const int64_t bj = rhs[j];
+                    cnt[t] += ((j < m1) ? (sum < bj) : (sum != bj)) ? 1 : 0;
+                }
+            }
+        cnt[0] += __shfl_xor(cnt[0], 32);
+        cnt[1] += __shfl_xor(cnt[1], 32);
+        vpart[static_cast<int64_t>(tile) * K + 64 * w + 32 * g + i] = g ? cnt[1] : cnt[0];
+    }
+}
+
+void launch_eval_mfma(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et, int npl,
+                      const int *rows, const int64_t *mf_off, const int *mf_c0, const int *mf_span,
+                      const int8_t *dig, const int64_t *rhs, int m1, const uint64_t *X, int W,
+                      int *vpart, int K) {
+    if (!ntiles) return;
+    const int64_t blocks = static_cast<int64_t>((ntiles + 7) / 8) * 8 * W;
+#define GF_MF(N) k_eval_mfma<N><<<static_cast<int>(blocks), 256, 0, s>>>(ntiles, W, tile_ids, et.b0, et.b1, rows, mf_off, mf_c0, mf_span, dig, rhs, m1, X, vpart, K)
+    if (npl == 1) GF_MF(1);
+    else if (npl == 2) GF_MF(2);
+    else GF_MF(3);
+#undef GF_MF
+}
+
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,

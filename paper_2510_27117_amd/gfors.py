@@ -30,7 +30,8 @@ class gfors_params(ctypes.Structure):
     _fields_ = [("sigma", c_dbl), ("tau1", c_dbl), ("tau2", c_dbl),
                 ("rho_min", c_dbl), ("rho_max", c_dbl), ("rho_T", c_dbl), ("rho_p", c_dbl),
                 ("rho_delta", c_dbl), ("k_int", c_i32), ("K_max", c_i32), ("power_iters", c_i32),
-                ("hist_cap", c_i32), ("autotune", c_i32), ("x0", c_dbl), ("seed", c_u64)]
+                ("hist_cap", c_i32), ("autotune", c_i32), ("x0", c_dbl), ("seed", c_u64),
+                ("eval_mfma", c_i32)]
 
 
 EXPORTS = [
@@ -45,7 +46,7 @@ EXPORTS = [
     "gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad",
     "gfors_tu_create", "gfors_tu_dims", "gfors_tu_export", "gfors_tu_recover", "gfors_tu_destroy",
     "gfors_tu_last_error", "gfors_mono_rows", "gfors_mono_repair", "gfors_mono_last_error",
-    "gfors_philox_throughput",
+    "gfors_philox_throughput", "gfors_eval_planes",
 ]
 
 KERNEL_NAMES = ["dual", "primal", "sample", "eval_cover", "eval_general", "eval_quad",
@@ -90,6 +91,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_kernel_times.argtypes = [c_vp, c_i32, c_i32, c_vp, c_vp]
     L.gfors_reset.argtypes = [c_vp]
     L.gfors_get_launch_cfg.argtypes = [c_vp, c_vp]
+    L.gfors_eval_planes.argtypes = [c_vp, P(c_i32)]
     L.gfors_set_launch_cfg.argtypes = [c_vp, c_vp]
     L.gfors_autotune.argtypes = [c_vp]
     L.gfors_gnn_workspace_bytes.argtypes = [P(ctypes.c_size_t)]
@@ -330,6 +332,12 @@ class Problem:
         cnt = np.zeros(len(KERNEL_NAMES), dtype=np.int32)
         _check(load_library().gfors_kernel_times(self._h(), int(nsteps), int(K), _ptr(ms), _ptr(cnt)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+    def eval_planes(self) -> int:
+        """Digit planes of the matrix-core evaluation of the general rows (0: row by row)."""
+        out = c_i32()
+        _check(load_library().gfors_eval_planes(self._h(), ctypes.byref(out)))
+        return int(out.value)
 
     def launch_cfg(self) -> dict:
         out = np.zeros(8, dtype=np.int32)
