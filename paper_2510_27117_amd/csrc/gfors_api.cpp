@@ -1512,7 +1512,7 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     TE(3);
     TB(4);
     if (P->mfma)
-        launch_eval_mfma(s, P->n_general, P->general_ids, P->et, P->mf_npl, P->rows, P->mf_off,
+        launch_eval_mfma(s, P->n_general, P->general_ids, P->et, P->mf_npl, P->acc64, P->rows, P->mf_off,
                          P->mf_c0, P->mf_span, P->mf_dig, P->rhs, static_cast<int>(P->m1), P->X, W,
                          P->vpart, K);
     else

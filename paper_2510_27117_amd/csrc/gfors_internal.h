@@ -183,8 +183,9 @@ void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const T
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,
                          const uint8_t *xkind, int W, int *vpart, int K, bool long_rows,
                          bool coef24);
-// Tiles of <= 32 general rows densified as int8 digit planes (npl in 1..3).
-void launch_eval_mfma(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et, int npl,
+// Tiles of <= 32 general rows densified as int8 digit planes (npl in 1..3);
+// acc64: some row's sum of |a| reaches 2^31.
+void launch_eval_mfma(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et, int npl, bool acc64,
                       const int *rows, const int64_t *mf_off, const int *mf_c0, const int *mf_span,
                       const int8_t *dig, const int64_t *rhs, int m1, const uint64_t *X, int W,
                       int *vpart, int K);

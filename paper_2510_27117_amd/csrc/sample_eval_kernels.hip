@@ -19,6 +19,7 @@
 // (covering rows) are checked with bitwise OR over 64 candidates at a time;
 // any other row is summed exactly in integers, one candidate per lane.
 #include "gfors_internal.h"
+#include <type_traits>
 
 namespace gfors {
 
@@ -457,7 +458,7 @@ k_eval_rows_allw(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
 // 32-63 the high one, four words per 16-byte read (two addresses per
 // wavefront).  Bit (lane & 31) of the half times the coefficient (a scalar
 // load) is added: one 24-bit multiply-add when every coefficient fits in 24
-// signed bits and the sums in 32 (MAD24), else a 0 / -1 mask and an add.  The
+// signed bits and the sums in 32 (MAD24), else a select and an add.  The
 // sampler writes every variable's words, constant rows included, so no kind
 // lookup is needed.
 template <int WW, typename ACC, bool MAD24>
@@ -537,7 +538,9 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
                     if constexpr (MAD24) {
                         acc[w] += __mul24(a, static_cast<int>(__builtin_amdgcn_ubfe(hw[w], sh, 1u)));
                     } else {
-                        acc[w] += static_cast<ACC>(a & __builtin_amdgcn_sbfe(static_cast<int>(hw[w]), sh, 1u));
+                        // a select, not a mask: widening (a & sign-extended bit)
+                        // to 64 bits was compiled as a zero extension
+                        acc[w] += __builtin_amdgcn_ubfe(hw[w], sh, 1u) ? static_cast<ACC>(a) : ACC(0);
                     }
                 }
             }
@@ -581,9 +584,9 @@ k_eval_rows_split(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
 // (row i = lane & 31, k-half g = lane >> 5) loads 16 digits of each plane
 // (one 16-byte load) as the A operand of v_mfma_i32_32x32x32_i8, and builds
 // the B operands of the word's two 32-candidate halves from the candidate
-// bits of the same 16 variables (staged per wavefront in LDS, 64 variables
-// per load): byte b of the lane is bit (32 t + (lane & 31)) of variable
-// 16 g + b.  A and B use the same (g, byte) -> variable map, so the
+// bits of the same 16 variables (the k-step's 32 words staged per wavefront
+// in LDS, fetched one k-step ahead with the digits): byte b of the lane is
+// bit (32 t + (lane & 31)) of variable 16 g + b.  A and B use the same (g, byte) -> variable map, so the
 // contraction does not depend on how the instruction orders k.  The four
 // partial products are added in LDS and wavefront 0 tests each row for each
 // candidate.  Workgroups of one tile share an XCD (blockIdx % 8) so that the
@@ -597,7 +600,7 @@ __device__ __forceinline__ int gf_bytes_of_bits(uint32_t h0, uint32_t h1, uint32
                             (__builtin_amdgcn_ubfe(h2, sh, 1u) << 16) | (__builtin_amdgcn_ubfe(h3, sh, 1u) << 24));
 }
 
-template <int NPL>
+template <int NPL, bool W64>
 __global__ void __launch_bounds__(256)
 k_eval_mfma(int ntiles, int W, const int *__restrict__ tile_ids, const int *__restrict__ tb0,
             const int *__restrict__ tb1, const int *__restrict__ rows,
@@ -606,12 +609,17 @@ k_eval_mfma(int ntiles, int W, const int *__restrict__ tile_ids, const int *__re
             const int64_t *__restrict__ rhs, int m1, const uint64_t *__restrict__ X,
             int *__restrict__ vpart, int K) {
     __shared__ uint64_t xs[4][64];
-    __shared__ int64_t red[3][2][16][64];
+    // row sums of the four wavefronts: 64-bit, or 32-bit when every row's sum
+    // of |a| is below 2^31 (then every partial sum and the plane combination
+    // taken modulo 2^32 are the exact values)
+    using RT = typename std::conditional<W64, unsigned long long, unsigned>::type;
+    __shared__ RT red[2][16][64];
     const int b = blockIdx.x;
     const int r = b >> 3;
     const int w = r % W;
     const int ti = (r / W) * 8 + (b & 7);
     if (ti >= ntiles) return;                      // whole workgroup, before any barrier
+    for (int q = threadIdx.x; q < 2 * 16 * 64; q += 256) (&red[0][0][0])[q] = 0;
     const int tile = tile_ids[ti];
     const int r0 = tb0[tile], R = tb1[tile] - r0;
     const int c0 = mf_c0[tile], span = mf_span[tile];
@@ -630,56 +638,57 @@ k_eval_mfma(int ntiles, int W, const int *__restrict__ tile_ids, const int *__re
         for (int p = 0; p < NPL; ++p) acc[t][p] = gf_v16i{};
     const int8_t *arow = dt + static_cast<int64_t>(i) * pitch + 16 * g;
     const bool live = i < R;
-    for (int ks = k0; ks < k1; ks += 2) {
-        // candidate words of the 64 variables of k-steps ks, ks + 1 (clamped
-        // to the span's last variable; their digits are zero)
-        const int v = min(c0 + 32 * ks + lane, c0 + span - 1);
-        xs[wave][lane] = X[static_cast<int64_t>(v) * W + w];
+    // operands of the next k-step are fetched while the current one is
+    // multiplied: the candidate words of its 32 variables (lane & 31;
+    // clamped to the span's last variable, whose digits there are zero) and
+    // the digit fragments
+    uint64_t xn = 0;
+    gf_v4i an[NPL];
+    auto fetch = [&](int kk) {
+        const int v = min(c0 + 32 * kk + i, c0 + span - 1);
+        xn = X[static_cast<int64_t>(v) * W + w];
+#pragma unroll
+        for (int p = 0; p < NPL; ++p)
+            an[p] = live ? *reinterpret_cast<const gf_v4i *>(arow + p * R * pitch + 32 * kk) : gf_v4i{};
+    };
+    if (k0 < k1) fetch(k0);
+    for (int ks = k0; ks < k1; ++ks) {
+        xs[wave][lane] = xn;                       // lanes 32-63 repeat lanes 0-31
+        gf_v4i a[NPL];
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) a[p] = an[p];
+        if (ks + 1 < k1) fetch(ks + 1);
         __builtin_amdgcn_wave_barrier();
+        const uint64_t *xv = &xs[wave][16 * g];
+        gf_v4i bl, bh;
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-            if (ks + s2 < k1) {
-                gf_v4i a[NPL];
+        for (int d = 0; d < 4; ++d) {
+            const uint64_t x0 = xv[4 * d], x1 = xv[4 * d + 1], x2 = xv[4 * d + 2], x3 = xv[4 * d + 3];
+            bl[d] = gf_bytes_of_bits(static_cast<uint32_t>(x0), static_cast<uint32_t>(x1),
+                                     static_cast<uint32_t>(x2), static_cast<uint32_t>(x3), sh);
+            bh[d] = gf_bytes_of_bits(static_cast<uint32_t>(x0 >> 32), static_cast<uint32_t>(x1 >> 32),
+                                     static_cast<uint32_t>(x2 >> 32), static_cast<uint32_t>(x3 >> 32), sh);
+        }
 #pragma unroll
-                for (int p = 0; p < NPL; ++p)
-                    a[p] = live ? *reinterpret_cast<const gf_v4i *>(arow + p * R * pitch + 32 * (ks + s2))
-                                : gf_v4i{};
-                const uint64_t *xv = &xs[wave][32 * s2 + 16 * g];
-                uint32_t lo[16], hi[16];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const uint64_t x = xv[q];
-                    lo[q] = static_cast<uint32_t>(x);
-                    hi[q] = static_cast<uint32_t>(x >> 32);
-                }
-                gf_v4i bl, bh;
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    bl[d] = gf_bytes_of_bits(lo[4 * d], lo[4 * d + 1], lo[4 * d + 2], lo[4 * d + 3], sh);
-                    bh[d] = gf_bytes_of_bits(hi[4 * d], hi[4 * d + 1], hi[4 * d + 2], hi[4 * d + 3], sh);
-                }
-#pragma unroll
-                for (int p = 0; p < NPL; ++p) {
-                    acc[0][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[p], bl, acc[0][p], 0, 0, 0);
-                    acc[1][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[p], bh, acc[1][p], 0, 0, 0);
-                }
-            }
+        for (int p = 0; p < NPL; ++p) {
+            acc[0][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[p], bl, acc[0][p], 0, 0, 0);
+            acc[1][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[p], bh, acc[1][p], 0, 0, 0);
         }
         __builtin_amdgcn_wave_barrier();
     }
     // row sums: register q of half t holds row 8 (q / 4) + 4 g + (q % 4),
-    // candidate 64 w + 32 t + (lane & 31)
-    if (wave > 0) {
+    // candidate 64 w + 32 t + (lane & 31); the wavefronts' exact integer
+    // partial sums meet in LDS (two's-complement adds, order-free)
+    __syncthreads();                               // zeroed buffer visible to every wavefront
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                int64_t sum = 0;
+        for (int q = 0; q < 16; ++q) {
+            RT sum = 0;
 #pragma unroll
-                for (int p = 0; p < NPL; ++p) sum += static_cast<int64_t>(acc[t][p][q]) << (8 * p);
-                red[wave - 1][t][q][lane] = sum;
-            }
-    }
+            for (int p = 0; p < NPL; ++p) sum += static_cast<RT>(static_cast<int64_t>(acc[t][p][q])) << (8 * p);
+            atomicAdd(&red[t][q][lane], sum);
+        }
     __syncthreads();
     if (wave == 0) {
         int cnt[2] = {0, 0};
@@ -689,9 +698,8 @@ k_eval_mfma(int ntiles, int W, const int *__restrict__ tile_ids, const int *__re
             for (int q = 0; q < 16; ++q) {
                 const int row = 8 * (q >> 2) + 4 * g + (q & 3);
                 if (row < R) {
-                    int64_t sum = red[0][t][q][lane] + red[1][t][q][lane] + red[2][t][q][lane];
-#pragma unroll
-                    for (int p = 0; p < NPL; ++p) sum += static_cast<int64_t>(acc[t][p][q]) << (8 * p);
+                    const int64_t sum = W64 ? static_cast<int64_t>(red[t][q][lane])
+                                            : static_cast<int64_t>(static_cast<int32_t>(red[t][q][lane]));
                     const int j = rows[r0 + row];
                     const int64_t bj = rhs[j];
                     cnt[t] += ((j < m1) ? (sum < bj) : (sum != bj)) ? 1 : 0;
@@ -703,16 +711,22 @@ k_eval_mfma(int ntiles, int W, const int *__restrict__ tile_ids, const int *__re
     }
 }
 
-void launch_eval_mfma(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et, int npl,
+void launch_eval_mfma(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et, int npl, bool acc64,
                       const int *rows, const int64_t *mf_off, const int *mf_c0, const int *mf_span,
                       const int8_t *dig, const int64_t *rhs, int m1, const uint64_t *X, int W,
                       int *vpart, int K) {
     if (!ntiles) return;
     const int64_t blocks = static_cast<int64_t>((ntiles + 7) / 8) * 8 * W;
-#define GF_MF(N) k_eval_mfma<N><<<static_cast<int>(blocks), 256, 0, s>>>(ntiles, W, tile_ids, et.b0, et.b1, rows, mf_off, mf_c0, mf_span, dig, rhs, m1, X, vpart, K)
-    if (npl == 1) GF_MF(1);
-    else if (npl == 2) GF_MF(2);
-    else GF_MF(3);
+#define GF_MF(N, B) k_eval_mfma<N, B><<<static_cast<int>(blocks), 256, 0, s>>>(ntiles, W, tile_ids, et.b0, et.b1, rows, mf_off, mf_c0, mf_span, dig, rhs, m1, X, vpart, K)
+    if (acc64) {
+        if (npl == 1) GF_MF(1, true);
+        else if (npl == 2) GF_MF(2, true);
+        else GF_MF(3, true);
+    } else {
+        if (npl == 1) GF_MF(1, false);
+        else if (npl == 2) GF_MF(2, false);
+        else GF_MF(3, false);
+    }
 #undef GF_MF
 }
 
@@ -756,8 +770,8 @@ void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const T
 // from rowQ) as low / high 32-bit planes plus Q_ik into LDS, then sums the
 // staged entries in one flat loop: bit (lane & 31) of the lane's half times
 // Q_ik, read as wave-uniform LDS broadcasts (one 24-bit multiply-add when Q's
-// entries fit in 24 signed bits and a row's sum of |Q| in 31, else a mask and
-// an add).
+// entries fit in 24 signed bits and a row's sum of |Q| in 31, else a 64-bit
+// select and an add).
 // ---------------------------------------------------------------------------
 constexpr int kQuadStage = 1024;
 
@@ -806,7 +820,7 @@ k_eval_quad(const int *__restrict__ tb0, const int *__restrict__ tb1,
                 int64_t acc = 0;
 #pragma unroll 8
                 for (int e = 0; e < ne; ++e)
-                    acc += static_cast<int64_t>(qv[e] & __builtin_amdgcn_sbfe(static_cast<int>(pl[e]), sh, 1u));
+                    acc += __builtin_amdgcn_ubfe(pl[e], sh, 1u) ? static_cast<int64_t>(qv[e]) : int64_t(0);
                 z += acc;
             }
         }

@@ -4,7 +4,8 @@ to the oracle's row-by-row evaluation, with 1, 2 and 3 signed base-256 digit
 planes, several 32-row blocks per instance, blocks cut by the half-full rule,
 zero padding inside blocks, equality rows, batches, and candidate widths from
 one word to 64.  The row-by-row path (eval_mfma = 0) is checked on the same
-draws."""
+draws, and its variants for wide coefficients (64-bit sums; coefficients
+beyond 24 bits) as well as the quadratic objective's."""
 import numpy as np
 import pytest
 
@@ -95,9 +96,12 @@ def _check_round(G, P, parts, K, planes, seed):
     return res
 
 
-@pytest.mark.parametrize("wmax,planes", [(100, 1), (1000, 2), (20000, 2), (3_000_000, 3)])
-def test_digit_planes(G, wmax, planes):
-    P = long_rows_bip(700, 5, 2, wmax, seed=wmax)
+@pytest.mark.parametrize("wmax,planes,n", [(100, 1, 700), (1000, 2, 700), (20000, 2, 700),
+                                           (3_000_000, 3, 700), (3_000_000, 3, 2500)])
+def test_digit_planes(G, wmax, planes, n):
+    """n = 2500 with coefficients up to 3e6: row sums of |a| beyond 2^31
+    (64-bit row sums)."""
+    P = long_rows_bip(n, 5, 2, wmax, seed=wmax + n)
     _check_round(G, P, [P], 512, planes, seed=1)
 
 
@@ -137,3 +141,32 @@ def test_not_eligible_falls_back(G):
     assert prob.eval_planes() == 0
     prob.close()
     _check_round(G, P, [P], 128, 0, seed=2)
+
+
+def test_rowwise_wide_coefficients(G):
+    """A coefficient of 9e6 (beyond 24 bits and beyond three base-256 digits)
+    in each long row: 32-bit row-by-row sums without the 24-bit multiply-add."""
+    P = long_rows_bip(600, 4, 1, 100, seed=11)
+    for M in (P.A, P.B):
+        v = M.val.astype(np.int64)
+        v[M.row_ptr[:-1]] = np.where(np.arange(M.nrows) % 2 == 0, 9_000_000, -9_000_000)
+        M.val = v.astype(np.int32)
+    _check_round(G, P, [P], 512, 0, seed=4)
+
+
+def test_quadratic_wide_weights(G):
+    """Max cut with weights of +-9e6 (beyond 24 bits): the quadratic
+    objective summed with 64-bit selects."""
+    import torch
+    P = I.max_cut_er(3000, 10.0, seed=21)
+    P.Q.val = (P.Q.values().astype(np.int64) * 9_000_000).astype(np.int32)
+    P.c = P.c.astype(np.int64) * 9_000_000
+    prob = G.Problem(P, G.default_params(k_int=20, K_max=1024))
+    p = np.random.default_rng(6).random(P.n).astype(np.float32)
+    prob.set_state(p, p, np.zeros(P.m1 + P.m2), 0.0, k=0, round=1)
+    v, z = prob.sample_eval(1024, p_override=torch.from_numpy(p).to("cuda:0"), outputs=True)
+    X = O.sample_bits(p.astype(np.float64), 1024, seed=0, rnd=1)
+    vo, zo = O.evaluate(P, X)
+    assert np.array_equal(v.cpu().numpy()[0], vo)
+    assert np.array_equal(z.cpu().numpy()[0], zo)
+    prob.close()
