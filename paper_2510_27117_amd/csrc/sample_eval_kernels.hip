@@ -608,7 +608,7 @@ k_eval_mfma(int ntiles, int W, const int *__restrict__ tile_ids, const int *__re
             const int *__restrict__ mf_span, const int8_t *__restrict__ dig,
             const int64_t *__restrict__ rhs, int m1, const uint64_t *__restrict__ X,
             int *__restrict__ vpart, int K) {
-    __shared__ uint64_t xs[4][64];
+    __shared__ uint64_t xs[4][128];
     // row sums of the four wavefronts: 64-bit, or 32-bit when every row's sum
     // of |a| is below 2^31 (then every partial sum and the plane combination
     // taken modulo 2^32 are the exact values)
@@ -638,41 +638,57 @@ k_eval_mfma(int ntiles, int W, const int *__restrict__ tile_ids, const int *__re
         for (int p = 0; p < NPL; ++p) acc[t][p] = gf_v16i{};
     const int8_t *arow = dt + static_cast<int64_t>(i) * pitch + 16 * g;
     const bool live = i < R;
-    // operands of the next k-step are fetched while the current one is
-    // multiplied: the candidate words of its 32 variables (lane & 31;
-    // clamped to the span's last variable, whose digits there are zero) and
-    // the digit fragments
-    uint64_t xn = 0;
-    gf_v4i an[NPL];
+    // operands of the next KS k-steps are fetched while the current KS are
+    // multiplied: the candidate words of their 32 KS variables (clamped to
+    // the span's last variable, whose digits there are zero) and the digit
+    // fragments
+    constexpr int KS = 4;
+    uint64_t xn[KS / 2];
+    gf_v4i an[KS][NPL];
     auto fetch = [&](int kk) {
-        const int v = min(c0 + 32 * kk + i, c0 + span - 1);
-        xn = X[static_cast<int64_t>(v) * W + w];
 #pragma unroll
-        for (int p = 0; p < NPL; ++p)
-            an[p] = live ? *reinterpret_cast<const gf_v4i *>(arow + p * R * pitch + 32 * kk) : gf_v4i{};
-    };
-    if (k0 < k1) fetch(k0);
-    for (int ks = k0; ks < k1; ++ks) {
-        xs[wave][lane] = xn;                       // lanes 32-63 repeat lanes 0-31
-        gf_v4i a[NPL];
-#pragma unroll
-        for (int p = 0; p < NPL; ++p) a[p] = an[p];
-        if (ks + 1 < k1) fetch(ks + 1);
-        __builtin_amdgcn_wave_barrier();
-        const uint64_t *xv = &xs[wave][16 * g];
-        gf_v4i bl, bh;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const uint64_t x0 = xv[4 * d], x1 = xv[4 * d + 1], x2 = xv[4 * d + 2], x3 = xv[4 * d + 3];
-            bl[d] = gf_bytes_of_bits(static_cast<uint32_t>(x0), static_cast<uint32_t>(x1),
-                                     static_cast<uint32_t>(x2), static_cast<uint32_t>(x3), sh);
-            bh[d] = gf_bytes_of_bits(static_cast<uint32_t>(x0 >> 32), static_cast<uint32_t>(x1 >> 32),
-                                     static_cast<uint32_t>(x2 >> 32), static_cast<uint32_t>(x3 >> 32), sh);
+        for (int h = 0; h < KS / 2; ++h) {
+            const int v = min(c0 + 32 * kk + 64 * h + lane, c0 + span - 1);
+            xn[h] = X[static_cast<int64_t>(v) * W + w];
         }
 #pragma unroll
-        for (int p = 0; p < NPL; ++p) {
-            acc[0][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[p], bl, acc[0][p], 0, 0, 0);
-            acc[1][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[p], bh, acc[1][p], 0, 0, 0);
+        for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p)
+                an[s2][p] = (live && kk + s2 < k1)
+                                ? *reinterpret_cast<const gf_v4i *>(arow + p * R * pitch + 32 * (kk + s2))
+                                : gf_v4i{};
+    };
+    if (k0 < k1) fetch(k0);
+    for (int ks = k0; ks < k1; ks += KS) {
+#pragma unroll
+        for (int h = 0; h < KS / 2; ++h) xs[wave][64 * h + lane] = xn[h];
+        gf_v4i a[KS][NPL];
+#pragma unroll
+        for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) a[s2][p] = an[s2][p];
+        if (ks + KS < k1) fetch(ks + KS);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s2 = 0; s2 < KS; ++s2) {
+            if (ks + s2 < k1) {
+                const uint64_t *xv = &xs[wave][32 * s2 + 16 * g];
+                gf_v4i bl, bh;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const uint64_t x0 = xv[4 * d], x1 = xv[4 * d + 1], x2 = xv[4 * d + 2], x3 = xv[4 * d + 3];
+                    bl[d] = gf_bytes_of_bits(static_cast<uint32_t>(x0), static_cast<uint32_t>(x1),
+                                             static_cast<uint32_t>(x2), static_cast<uint32_t>(x3), sh);
+                    bh[d] = gf_bytes_of_bits(static_cast<uint32_t>(x0 >> 32), static_cast<uint32_t>(x1 >> 32),
+                                             static_cast<uint32_t>(x2 >> 32), static_cast<uint32_t>(x3 >> 32), sh);
+                }
+#pragma unroll
+                for (int p = 0; p < NPL; ++p) {
+                    acc[0][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s2][p], bl, acc[0][p], 0, 0, 0);
+                    acc[1][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s2][p], bh, acc[1][p], 0, 0, 0);
+                }
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
