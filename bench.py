@@ -135,6 +135,7 @@ def kernel_bytes(bip, K, idx=None):
 
 
 VALU_LANE_OPS = 256 * 64 * 2.4e9   # lanes x clock of the 256 CUs: one integer op per lane per clock
+MFMA_INT8_TOPS = 5000.0             # dense int8 matrix-core peak of the MI355X (TOP/s)
 
 
 def general_row_nnz(bip):
@@ -495,12 +496,25 @@ def main():
     cand = [(k, prods) for k, prods in (("eval_general", general_row_nnz(bip) * a.K),
                                         ("eval_quad", (0 if bip.Q is None else bip.Q.nnz) * a.K))
             if prods and kt.get(k, (0.0, 0))[1] and kt[k][0] > 0]
+    planes = G.eval_planes()
     if cand:
         k, prods = max(cand, key=lambda kp: kt[kp[0]][0])
         ach = prods / (kt[k][0] * 1e-3)
-        eval_alu = {"bound": "alu", "kernel": k, "achieved": round(ach, 1), "peak": VALU_LANE_OPS,
-                    "unit": "entry-candidate products/s", "frac": round(ach / VALU_LANE_OPS, 4),
-                    "products_per_launch": prods, "avg_launch_ms": kt[k][0]}
+        if k == "eval_general" and planes:
+            # dense digit blocks on the int8 matrix cores: one multiply-add
+            # (2 ops) per entry, candidate and digit plane, against the dense
+            # int8 MFMA peak
+            ops = 2 * prods * planes
+            acho = ops / (kt[k][0] * 1e-3)
+            eval_alu = {"bound": "mfma", "kernel": k, "achieved": round(acho / 1e12, 2),
+                        "peak": MFMA_INT8_TOPS, "unit": "TOP/s (int8)",
+                        "frac": round(acho / 1e12 / MFMA_INT8_TOPS, 4), "digit_planes": planes,
+                        "ops_per_launch": ops, "entry_candidate_products_per_s": round(ach, 1),
+                        "avg_launch_ms": kt[k][0]}
+        else:
+            eval_alu = {"bound": "alu", "kernel": k, "achieved": round(ach, 1), "peak": VALU_LANE_OPS,
+                        "unit": "entry-candidate products/s", "frac": round(ach / VALU_LANE_OPS, 4),
+                        "products_per_launch": prods, "avg_launch_ms": kt[k][0]}
     kernels = {k: {"avg_ms": round(ms, 5), "launches": cnt,
                    "gbs": (round(kb[k] / (ms * 1e-3) / 1e9, 1) if k in kb and ms > 0 else None)}
                for k, (ms, cnt) in kt.items() if cnt}
