@@ -113,6 +113,9 @@ def kernel_bytes(bip, K, idx=None):
     unit = (bip.A is None or bip.A.val is None) and (bip.B is None or bip.B.val is None)
     nnzQ = 0 if bip.Q is None else bip.Q.nnz
     vb = 0 if unit else 4
+    if not unit and all(np.abs(M.values().astype(np.int64)).max(initial=0) <= 32767
+                        for M in (bip.A, bip.B) if M is not None):
+        vb = 2   # the SpMVs read an int16 copy of the coefficients
     ir, ic = (nnzK, nnzK) if idx is None else idx
     W = K // 64
     out = {}
@@ -128,7 +131,7 @@ def kernel_bytes(bip, K, idx=None):
     out["sample"] = 8 * n * W + 4 * n + 8 * n          # candidate words + p + cost
     if m:
         out["eval_cover"] = 4 * (m + 1) + 4 * ir + 8 * n * W
-        out["eval_general"] = 4 * (m + 1) + 4 * ir + vb * nnzK + 8 * n * W + 8 * m
+        out["eval_general"] = 4 * (m + 1) + 4 * ir + (4 if vb else 0) * nnzK + 8 * n * W + 8 * m
     if nnzQ:
         out["eval_quad"] = 4 * (n + 1) + 8 * nnzQ + 8 * n * W
     return out

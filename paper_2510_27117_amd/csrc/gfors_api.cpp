@@ -161,6 +161,10 @@ struct gfors_problem {
     SellView sellK, sellKS, sellT;
     int64_t sellK_cap = 0, sellKS_cap = 0, sellT_cap = 0;
     int *sellK_buf[6] = {}, *sellKS_buf[6] = {}, *sellT_buf[6] = {};
+    // the coefficients as int16 for the SpMVs when every |a| <= 32767
+    // (exact in FP32 either way; half the bytes of the coefficient stream)
+    bool use16 = false;
+    int16_t *val16 = nullptr, *sellT_val16 = nullptr;
     float *rowinv32 = nullptr;          // 1/||a_j|| (0 for a zero row): the GNN's edge weights
     float gnn_ictmax = 1.f, gnn_irtmax = 1.f;
     uint64_t *bx = nullptr, *by = nullptr;   // nonzero bitmaps of xbar and wy
@@ -413,6 +417,8 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     sell_carve(P->sellK_want, m, 1, nnzK, P->sellK_cap, P->sellK_buf);
     sell_carve(P->sellKS_want, m, kXcdSlices, nnzK, P->sellKS_cap, P->sellKS_buf);
     sell_carve(P->sellT_want, n, 1, nnzK, P->sellT_cap, P->sellT_buf);
+    P->val16 = cv.take<int16_t>(nnzK);
+    P->sellT_val16 = cv.take<int16_t>(P->sellT_want ? P->sellT_cap : 0);
     P->rowinv32 = cv.take<float>(m);
     P->bx_words = ceil_div(n + 64 * kXcdSlices, 64) + 1;
     P->by_words = ceil_div(m + 64, 64) + 1;
@@ -824,6 +830,13 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     if ((rc = upload(s, P->rp, rp.data(), m + 1))) return rc;
     if ((rc = upload(s, P->ci, ci.data(), P->nnzK))) return rc;
     if ((rc = upload(s, P->val, val.data(), P->nnzK))) return rc;
+    P->use16 = !P->unitK;
+    for (int64_t e = 0; e < P->nnzK && P->use16; ++e) P->use16 = val[e] >= -32767 && val[e] <= 32767;
+    if (P->use16) {
+        std::vector<int16_t> v16(val.begin(), val.end());
+        if ((rc = upload(s, P->val16, v16.data(), P->nnzK))) return rc;
+        if ((rc = sync(P))) return rc;
+    }
     if ((rc = upload(s, P->rpT, rpT.data(), n + 1))) return rc;
     if ((rc = upload(s, P->ciT, ciT.data(), P->nnzK))) return rc;
     if ((rc = upload(s, P->valT, valT.data(), P->nnzK))) return rc;
@@ -869,7 +882,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     // windows of 8192 rows, chunks of 64 rows padded to the longest row
     auto build_sell = [&](int64_t rows, int64_t cols, int Pn, const std::vector<int> &rpx,
                           const std::vector<int> &cix, const std::vector<int> &valx, int pad_col,
-                          int64_t cap, int *(&buf)[6], SellView &sv) -> int {
+                          int64_t cap, int *(&buf)[6], SellView &sv, int16_t *v16) -> int {
         const int64_t nch = ceil_div(rows, 64);
         const int64_t ns = ceil_div(ceil_div(std::max<int64_t>(cols, 1), Pn), 64) * 64;
         std::vector<int> sptr(static_cast<size_t>(Pn) * (nch + 1)), srow(static_cast<size_t>(Pn) * nch * 64, -1);
@@ -927,7 +940,13 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         if ((r2 = upload(s, buf[3], srow.data(), static_cast<int64_t>(srow.size())))) return r2;
         if ((r2 = upload(s, buf[4], sc0.data(), static_cast<int64_t>(sc0.size())))) return r2;
         if ((r2 = upload(s, buf[5], slen.data(), static_cast<int64_t>(slen.size())))) return r2;
+        std::vector<int16_t> sv16;
+        if (v16 && P->use16) {
+            sv16.assign(sval.begin(), sval.end());
+            if ((r2 = upload(s, v16, sv16.data(), static_cast<int64_t>(sv16.size())))) return r2;
+        }
         if ((r2 = sync(P))) return r2;
+        sv.val16 = (v16 && P->use16) ? v16 : nullptr;
         sv.nrows = static_cast<int>(rows);
         sv.P = Pn;
         sv.nchunk = static_cast<int>(nch);
@@ -940,9 +959,9 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         sv.len = buf[5];
         return GFORS_OK;
     };
-    if (P->sellK_want && (rc = build_sell(m, n, 1, rp, ci, val, static_cast<int>(n), P->sellK_cap, P->sellK_buf, P->sellK))) return rc;
-    if (P->sellKS_want && (rc = build_sell(m, n, kXcdSlices, rp, ci, val, static_cast<int>(n), P->sellKS_cap, P->sellKS_buf, P->sellKS))) return rc;
-    if (P->sellT_want && (rc = build_sell(n, m, 1, rpT, ciT, valT, static_cast<int>(m), P->sellT_cap, P->sellT_buf, P->sellT))) return rc;
+    if (P->sellK_want && (rc = build_sell(m, n, 1, rp, ci, val, static_cast<int>(n), P->sellK_cap, P->sellK_buf, P->sellK, nullptr))) return rc;
+    if (P->sellKS_want && (rc = build_sell(m, n, kXcdSlices, rp, ci, val, static_cast<int>(n), P->sellKS_cap, P->sellKS_buf, P->sellKS, nullptr))) return rc;
+    if (P->sellT_want && (rc = build_sell(n, m, 1, rpT, ciT, valT, static_cast<int>(m), P->sellT_cap, P->sellT_buf, P->sellT, P->sellT_val16))) return rc;
     if (P->slicedK && (rc = build_sliced(m, n, rp, ci, val, P->rpS, P->ciS, P->valS))) return rc;
     if (P->slicedT && (rc = build_sliced(n, m, rpT, ciT, valT, P->rpST, P->ciST, P->valST))) return rc;
     if ((rc = upload(s, P->rhs, rhs.data(), m))) return rc;
@@ -1278,7 +1297,8 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
         // the others with lpr - 256 lanes each
         const bool all = lpr == kLprBlock;
         launch_dual_long(s, P->unitK, batched, all ? m : P->heavy_rows, m1, P->dual_order, P->rp,
-                         P->rowc0, P->ci, P->val, P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2,
+                         P->rowc0, P->ci, P->val, P->use16 ? P->val16 : nullptr, P->omega, P->rt, P->xbar,
+                         y_in, y_out, P->wy, tau2,
                          P->di.tau2, P->row_inst);
         if (!all)
             launch_dual(s, lpr - kLprBlock, P->unitK, batched, m, m1, P->rp, P->ci, P->val,

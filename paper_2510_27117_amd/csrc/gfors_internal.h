@@ -76,6 +76,7 @@ struct SellView {
     // per slot: first column of a row whose entries in the slice are one
     // contiguous range (else -1) and the row's entry count in the slice
     const int *c0 = nullptr, *len = nullptr;
+    const int16_t *val16 = nullptr;   // the coefficients as int16 when all fit (else null)
 };
 
 constexpr int kXcdSlices = 8;   // XCDs per MI355X
@@ -127,7 +128,8 @@ void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool ba
 
 void launch_nzbits(hipStream_t s, const float *v, int64_t n, int64_t nwords64, uint64_t *bits);
 void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, const int *order,
-                      const int *rp, const int *rowc0, const int *ci, const int *val, const float *omega,
+                      const int *rp, const int *rowc0, const int *ci, const int *val,
+                      const int16_t *val16, const float *omega,
                       const float *rt, const float *xbar, const float *y_in, float *y_out,
                       float *wy, float tau2, const float *tau2_inst, const int *row_inst);
 void launch_sell_bits(hipStream_t s, const SellView &sv, int mode, bool unit, bool batched,

@@ -79,9 +79,9 @@ constexpr int kLongUnroll = 4;   // loads in flight per lane in the heavy kernel
 // Sum of a_e xbar[col_e] over the row's entries by the workgroup's 256 lanes
 // (four loads in flight per lane); DENSE: the row's columns are the range
 // c0, c0 + 1, ..., so no column index is loaded.
-template <bool UNIT, bool DENSE>
+template <bool UNIT, bool DENSE, typename VT>
 __device__ __forceinline__ float long_row_sum(int e0, int e1, int c0, const int *__restrict__ ci,
-                                              const int *__restrict__ val, const float *__restrict__ xbar) {
+                                              const VT *__restrict__ val, const float *__restrict__ xbar) {
     float s = 0.f;
     for (int eb = e0 + static_cast<int>(threadIdx.x); eb < e1; eb += kLongUnroll * 256) {
         float xv[kLongUnroll];
@@ -92,7 +92,7 @@ __device__ __forceinline__ float long_row_sum(int e0, int e1, int c0, const int 
             const float v = xbar[DENSE ? c0 + (e - e0) : ci[e]];
             const bool in = eb + 256 * u < e1;
             xv[u] = in ? v : 0.f;
-            a[u] = UNIT ? 1 : (in ? val[e] : 0);
+            a[u] = UNIT ? 1 : (in ? static_cast<int>(val[e]) : 0);
         }
 #pragma unroll
         for (int u = 0; u < kLongUnroll; ++u) {
@@ -107,7 +107,7 @@ template <bool UNIT, bool BATCH>
 __global__ void __launch_bounds__(256)
 k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restrict__ rp,
             const int *__restrict__ rowc0, const int *__restrict__ ci, const int *__restrict__ val,
-            const float *__restrict__ omega, const float *__restrict__ rt,
+            const int16_t *__restrict__ val16, const float *__restrict__ omega, const float *__restrict__ rt,
             const float *__restrict__ xbar, const float *__restrict__ y_in,
             float *__restrict__ y_out, float *__restrict__ wy, float tau2,
             const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
@@ -117,8 +117,14 @@ k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restr
     const int row = order[slot];
     const int e0 = rp[row], e1 = rp[row + 1];
     const int c0 = rowc0[row];                          // first column of a dense row, else -1
-    float s = c0 >= 0 ? long_row_sum<UNIT, true>(e0, e1, c0, ci, val, xbar)
-                      : long_row_sum<UNIT, false>(e0, e1, c0, ci, val, xbar);
+    // val16: the same coefficients as int16 (all fit), half the stream
+    float s;
+    if (!UNIT && val16)
+        s = c0 >= 0 ? long_row_sum<UNIT, true>(e0, e1, c0, ci, val16, xbar)
+                    : long_row_sum<UNIT, false>(e0, e1, c0, ci, val16, xbar);
+    else
+        s = c0 >= 0 ? long_row_sum<UNIT, true>(e0, e1, c0, ci, val, xbar)
+                    : long_row_sum<UNIT, false>(e0, e1, c0, ci, val, xbar);
     s = group_sum<64>(s);
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -135,12 +141,12 @@ k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restr
 }
 
 void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, const int *order,
-                      const int *rp, const int *rowc0, const int *ci, const int *val, const float *omega,
+                      const int *rp, const int *rowc0, const int *ci, const int *val, const int16_t *val16, const float *omega,
                       const float *rt, const float *xbar, const float *y_in, float *y_out,
                       float *wy, float tau2, const float *tau2_inst, const int *row_inst) {
     if (m <= 0) return;
     const int grid = ((m + 127) / 128) * 128;
-#define GF_DL(U, B) k_dual_long<U, B><<<grid, 256, 0, s>>>(m, m1, order, rp, rowc0, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
+#define GF_DL(U, B) k_dual_long<U, B><<<grid, 256, 0, s>>>(m, m1, order, rp, rowc0, ci, val, val16, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
     if (unit) { if (batched) GF_DL(true, true); else GF_DL(true, false); }
     else { if (batched) GF_DL(false, true); else GF_DL(false, false); }
 #undef GF_DL
@@ -510,8 +516,8 @@ void launch_primal_combine(hipStream_t s, bool batched, int n, int P, const floa
 template <bool UNIT, int MODE, bool BATCH>
 __global__ void __launch_bounds__(256)
 k_sell(int nrows, int P, int nchunk, const int *__restrict__ ptr, const int *__restrict__ ci,
-       const int *__restrict__ val, const int *__restrict__ row_of, const int *__restrict__ sc0,
-       const int *__restrict__ slen, const float *__restrict__ v,
+       const int *__restrict__ val, const int16_t *__restrict__ val16, const int *__restrict__ row_of,
+       const int *__restrict__ sc0, const int *__restrict__ slen, const float *__restrict__ v,
        float *__restrict__ part,
        // dual epilogue
        int m1, const float *__restrict__ omega, const float *__restrict__ rt,
@@ -541,6 +547,11 @@ k_sell(int nrows, int P, int nchunk, const int *__restrict__ ptr, const int *__r
         if (UNIT) {
 #pragma unroll 4
             for (int k = 0; k < L; ++k) acc += k < ln ? v[cb + k] : 0.f;
+        } else if (val16) {                      // the coefficients as int16 (all fit)
+            const int16_t *vc = val16 + e0 + lane;
+#pragma unroll 4
+            for (int k = 0; k < L; ++k)
+                acc = fmaf(static_cast<float>(__builtin_nontemporal_load(vc + 64 * k)), k < ln ? v[cb + k] : 0.f, acc);
         } else {
             const int *vc = val + e0 + lane;
 #pragma unroll 4
@@ -589,7 +600,7 @@ void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool ba
                  const int *var_inst, DevCounters *ctr) {
     const int64_t blocks = static_cast<int64_t>((sv.nchunk + 3) / 4) * sv.P;
     if (blocks == 0) return;
-#define GF_SELL(U, M, B)     k_sell<U, M, B><<<static_cast<int>(blocks), 256, 0, s>>>(sv.nrows, sv.P, sv.nchunk, sv.ptr, sv.ci, sv.val, sv.row_of, sv.c0, sv.len, v, part, m1, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
+#define GF_SELL(U, M, B)     k_sell<U, M, B><<<static_cast<int>(blocks), 256, 0, s>>>(sv.nrows, sv.P, sv.nchunk, sv.ptr, sv.ci, sv.val, sv.val16, sv.row_of, sv.c0, sv.len, v, part, m1, omega, rt, y_in, y_out, wy, tau2, tau2_inst, row_inst, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr)
 #define GF_SELL_M(U, B)     if (mode == 0) GF_SELL(U, 0, B); else if (mode == 1) GF_SELL(U, 1, B); else GF_SELL(U, 2, B)
     if (unit) { if (batched) { GF_SELL_M(true, true); } else { GF_SELL_M(true, false); } }
     else { if (batched) { GF_SELL_M(false, true); } else { GF_SELL_M(false, false); } }
