@@ -549,7 +549,7 @@ k_sell(int nrows, int P, int nchunk, const int *__restrict__ ptr, const int *__r
             for (int k = 0; k < L; ++k) acc += k < ln ? v[cb + k] : 0.f;
         } else if (val16) {                      // the coefficients as int16 (all fit)
             const int16_t *vc = val16 + e0 + lane;
-#pragma unroll 4
+#pragma unroll 8
             for (int k = 0; k < L; ++k)
                 acc = fmaf(static_cast<float>(__builtin_nontemporal_load(vc + 64 * k)), k < ln ? v[cb + k] : 0.f, acc);
         } else {
