@@ -7,6 +7,7 @@
 #include "../../include/gfors.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -99,7 +100,8 @@ struct gfors_problem {
     int T = 1;
     bool unitK = true, hasQ = false, obj64 = false, acc64 = false;
     bool coef24 = true;   // every coefficient of the general rows fits in 24 signed bits
-    bool q24 = true;      // every Q entry fits in 24 signed bits and every row sum of |Q| in 31
+    bool q24 = true;      // every evaluated Q entry below 2^21 in magnitude: 24-bit products and
+                          // int32 sums over a staged block of 1024 entries are exact
     LaunchCfg cfg;
 
     // host copies
@@ -112,6 +114,10 @@ struct gfors_problem {
     int *rpT = nullptr, *ciT = nullptr, *valT = nullptr;
     int *rpQ = nullptr, *ciQ = nullptr, *valQ = nullptr;
     int *rowQ = nullptr;   // row of each Q entry (quadratic objective)
+    // the objective's evaluation over the upper triangle of a symmetric Q:
+    // entries (i, k) with k > i doubled, the diagonal once
+    bool qsym = false;
+    int *rpU = nullptr, *ciU = nullptr, *valU = nullptr, *rowU = nullptr;
     float *omega = nullptr, *rt = nullptr, *ct = nullptr;
     double *omega64 = nullptr, *rowinv2_d = nullptr, *rowinv_d = nullptr;
     int64_t *rhs = nullptr, *cost = nullptr;
@@ -335,6 +341,10 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->ciQ = cv.take<int>(nnzQ);
     P->valQ = cv.take<int>(nnzQ);
     P->rowQ = cv.take<int>(nnzQ);
+    P->rpU = cv.take<int>(nnzQ ? n + 1 : 1);
+    P->ciU = cv.take<int>(nnzQ);
+    P->valU = cv.take<int>(nnzQ);
+    P->rowU = cv.take<int>(nnzQ);
     P->omega = cv.take<float>(m);
     P->rt = cv.take<float>(m);
     P->omega64 = cv.take<double>(m);
@@ -654,13 +664,38 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             valQ[e] = Q->val ? Q->val[e] : 1;
             if (ciQ[e] < P->inst_var0[t] || ciQ[e] >= P->inst_var0[t] + P->inst_nvar[t])
                 return fail(GFORS_E_ARG, "Q entry crosses instances");
-            if (std::llabs(static_cast<int64_t>(valQ[e])) >= (1LL << 23)) P->q24 = false;
         }
-        for (int64_t i = 0; i < n && P->q24; ++i) {
-            int64_t sa = 0;
-            for (int e = rpQ[i]; e < rpQ[i + 1]; ++e) sa += std::llabs(static_cast<int64_t>(valQ[e]));
-            if (sa >= (1LL << 31)) P->q24 = false;
+    }
+    // upper triangle of a symmetric Q for the objective's evaluation:
+    // <x, Q x> = 2 sum_{i<k} Q_ik x_i x_k + sum_i Q_ii x_i
+    std::vector<int> rpU, ciU, valU;
+    if (P->hasQ) {
+        std::vector<std::array<int64_t, 3>> a(P->nnzQ), b(P->nnzQ);
+        bool small = true;
+        for (int64_t i = 0; i < n; ++i)
+            for (int e = rpQ[i]; e < rpQ[i + 1]; ++e) {
+                a[e] = {i, ciQ[e], valQ[e]};
+                b[e] = {ciQ[e], i, valQ[e]};
+                small = small && std::llabs(static_cast<int64_t>(valQ[e])) < (1LL << 30);
+            }
+        std::sort(a.begin(), a.end());
+        std::sort(b.begin(), b.end());
+        P->qsym = small && a == b;
+        if (P->qsym) {
+            rpU.assign(n + 1, 0);
+            for (int64_t i = 0; i < n; ++i) {
+                rpU[i + 1] = rpU[i];
+                for (int e = rpQ[i]; e < rpQ[i + 1]; ++e)
+                    if (ciQ[e] >= i) {
+                        ciU.push_back(ciQ[e]);
+                        valU.push_back(ciQ[e] > i ? 2 * valQ[e] : valQ[e]);
+                        ++rpU[i + 1];
+                    }
+            }
         }
+        const std::vector<int> &ve = P->qsym ? valU : valQ;
+        for (int v : ve)
+            if (std::llabs(static_cast<int64_t>(v)) >= (1LL << 21)) P->q24 = false;
     }
     // objective accumulation width in the sampler
     int64_t cmax = 0;
@@ -774,7 +809,8 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         }
         if (P->hasQ) {
             const int64_t v0 = P->inst_var0[t];
-            std::function<int64_t(int64_t)> wq = [&](int64_t q) -> int64_t { return rpQ[v0 + q + 1] - rpQ[v0 + q]; };
+            const std::vector<int> &rpE = P->qsym ? rpU : rpQ;   // the evaluated entries
+            std::function<int64_t(int64_t)> wq = [&](int64_t q) -> int64_t { return rpE[v0 + q + 1] - rpE[v0 + q]; };
             build_tiles_items(hq, t, P->inst_nvar[t], &wq, kQuadNnz, kQuadRows, v0);
         }
         build_tiles_items(hv, t, P->inst_nvar[t], nullptr, kVarTile, kVarTile, P->inst_var0[t]);
@@ -849,6 +885,17 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             for (int e = rpQ[i]; e < rpQ[i + 1]; ++e) rowQ[e] = static_cast<int>(i);
         if ((rc = upload(s, P->rowQ, rowQ.data(), P->nnzQ))) return rc;
         if ((rc = sync(P))) return rc;
+        if (P->qsym) {
+            const int64_t nu = static_cast<int64_t>(ciU.size());
+            std::vector<int> rowU(nu);
+            for (int64_t i = 0; i < n; ++i)
+                for (int e = rpU[i]; e < rpU[i + 1]; ++e) rowU[e] = static_cast<int>(i);
+            if ((rc = upload(s, P->rpU, rpU.data(), n + 1))) return rc;
+            if ((rc = upload(s, P->ciU, ciU.data(), nu))) return rc;
+            if ((rc = upload(s, P->valU, valU.data(), nu))) return rc;
+            if ((rc = upload(s, P->rowU, rowU.data(), nu))) return rc;
+            if ((rc = sync(P))) return rc;
+        }
     }
     // column-sliced copies: slice q of the variables is [q*ns, (q+1)*ns)
     auto build_sliced = [&](int64_t rows, int64_t cols, const std::vector<int> &rpx,
@@ -1542,7 +1589,9 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     TE(4);
     TB(5);
     if (P->hasQ)
-        launch_eval_quad(s, P->qt, P->rpQ, P->rowQ, P->ciQ, P->valQ, P->X, W, P->zqpart, K, P->q24);
+        launch_eval_quad(s, P->qt, P->qsym ? P->rpU : P->rpQ, P->qsym ? P->rowU : P->rowQ,
+                         P->qsym ? P->ciU : P->ciQ, P->qsym ? P->valU : P->valQ, P->X, W, P->zqpart, K,
+                         P->q24);
     TE(5);
     TB(6);
     launch_reduce_cand(s, P->T, K, P->red_S, P->et, P->vpart, P->st, P->zpart, P->qt, P->zqpart,

@@ -785,9 +785,10 @@ void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const T
 // time; lane = entry), the AND of the words of x_i and x_k (the entry's row i
 // from rowQ) as low / high 32-bit planes plus Q_ik into LDS, then sums the
 // staged entries in one flat loop: bit (lane & 31) of the lane's half times
-// Q_ik, read as wave-uniform LDS broadcasts (one 24-bit multiply-add when Q's
-// entries fit in 24 signed bits and a row's sum of |Q| in 31, else a 64-bit
-// select and an add).
+// Q_ik, read as wave-uniform LDS broadcasts (one 24-bit multiply-add into an
+// int32 when every entry is below 2^21 in magnitude, so that a staged block's
+// sum cannot overflow, else a 64-bit select and an add).  For a symmetric Q
+// the entries are those of the upper triangle, off-diagonal ones doubled.
 // ---------------------------------------------------------------------------
 constexpr int kQuadStage = 1024;
 

@@ -170,3 +170,48 @@ def test_quadratic_wide_weights(G):
     assert np.array_equal(v.cpu().numpy()[0], vo)
     assert np.array_equal(z.cpu().numpy()[0], zo)
     prob.close()
+
+
+def _quad_bip(n, seed, symmetric):
+    """Random Q with a diagonal part and entries in [-5, 5]: symmetric, or
+    with (k, i) differing from (i, k)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    E = 6 * n
+    i = rng.integers(0, n, size=E)
+    k = rng.integers(0, n, size=E)
+    v = rng.integers(1, 6, size=E) * rng.choice([-1, 1], size=E)
+    d = rng.choice(n, size=n // 3, replace=False)
+    dv = rng.integers(-5, 6, size=d.size)
+    if symmetric:
+        rows = np.concatenate([i, k, d])
+        cols = np.concatenate([k, i, d])
+        vals = np.concatenate([v, v, dv])
+    else:
+        v2 = rng.integers(1, 6, size=E) * rng.choice([-1, 1], size=E)
+        rows = np.concatenate([i, k, d])
+        cols = np.concatenate([k, i, d])
+        vals = np.concatenate([v, v2, dv])
+    M = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    M.eliminate_zeros()
+    M.sort_indices()
+    Q = I.CSR(n, n, M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data.astype(np.int32))
+    c = rng.integers(-20, 21, size=n).astype(np.int64)
+    return I.BIP(n=n, c=c, Q=Q, name=f"quad_{seed}")
+
+
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_quadratic_triangle(G, symmetric):
+    """<x, Q x> from the upper triangle (off-diagonal entries doubled, the
+    diagonal once) for a symmetric Q; the full storage otherwise."""
+    import torch
+    P = _quad_bip(5000, seed=31 if symmetric else 32, symmetric=symmetric)
+    prob = G.Problem(P, G.default_params(k_int=20, K_max=1024))
+    p = np.random.default_rng(8).random(P.n).astype(np.float32)
+    prob.set_state(p, p, np.zeros(0), 0.0, k=0, round=3)
+    v, z = prob.sample_eval(512, p_override=torch.from_numpy(p).to("cuda:0"), outputs=True)
+    X = O.sample_bits(p.astype(np.float64), 512, seed=0, rnd=3)
+    vo, zo = O.evaluate(P, X)
+    assert np.array_equal(v.cpu().numpy()[0], vo)
+    assert np.array_equal(z.cpu().numpy()[0], zo)
+    prob.close()
