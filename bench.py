@@ -141,6 +141,21 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9   # lanes x clock of the 256 CUs: one integer o
 MFMA_INT8_TOPS = 5000.0             # dense int8 matrix-core peak of the MI355X (TOP/s)
 
 
+def quad_eval_entries(bip):
+    """Q entries the objective's evaluation visits: the upper triangle
+    (diagonal included) of a symmetric Q, else all of them."""
+    if bip.Q is None:
+        return 0
+    import scipy.sparse as sp
+    Q = bip.Q
+    M = sp.csr_matrix((Q.values().astype(np.int64), np.asarray(Q.col), np.asarray(Q.row_ptr)),
+                      shape=(Q.nrows, Q.ncols))
+    if (M != M.T).nnz:
+        return Q.nnz
+    rows = np.repeat(np.arange(Q.nrows), np.diff(np.asarray(Q.row_ptr)))
+    return int(np.count_nonzero(np.asarray(Q.col) >= rows))
+
+
 def general_row_nnz(bip):
     """Entries of the rows evaluated lane = candidate (not as bitwise functions
     of the candidate words: covering, at-most-one, exactly-one and rows of one
@@ -497,7 +512,7 @@ def main():
     # least one lane operation, so frac is an upper bound of VALU use)
     eval_alu = None
     cand = [(k, prods) for k, prods in (("eval_general", general_row_nnz(bip) * a.K),
-                                        ("eval_quad", (0 if bip.Q is None else bip.Q.nnz) * a.K))
+                                        ("eval_quad", quad_eval_entries(bip) * a.K))
             if prods and kt.get(k, (0.0, 0))[1] and kt[k][0] > 0]
     planes = G.eval_planes()
     if cand:
