@@ -489,6 +489,27 @@ def test_workgroup_per_row_dual(G, name):
     prob.close()
 
 
+@pytest.mark.parametrize("wmax", [1000, 100_000])
+@pytest.mark.parametrize("cfg", [(256, 4, 1, 1, 0, 0, 0, 0), (256, 1, 1, 1, 0, 1, 0, 0)])
+def test_dense_range_spmvs_coefficient_widths(G, wmax, cfg):
+    """Dense rows and variables (indices computed from the first one) with
+    coefficients that fit int16 (the SpMVs read the 2-byte copy) and ones
+    that do not (int32): workgroup-per-row dual with the CSR or the SELL-64
+    primal, teacher-forced step within tolerance."""
+    P = I.knapsack_multi(3001, 5, seed=13, wmax=wmax)
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=31, keep_every=30)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+    prob.set_launch_cfg(*cfg)
+    prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+    prob.pdhg_steps(1)
+    got = prob.get_state()
+    assert rel_inf(got["x"], ref.x) <= TOL_PDHG and rel_inf(got["y"], ref.y) <= TOL_PDHG
+    prob.close()
+
+
 def _bitwise_rows_problem(n=120, seed=0):
     """Every bitwise-evaluated row kind next to general rows: covering rows,
     at-most-one rows (-sum >= -1), exactly-one rows (+1 / -1 forms), rows of one
