@@ -170,6 +170,7 @@ struct gfors_problem {
     // the coefficients as int16 for the SpMVs when every |a| <= 32767
     // (exact in FP32 either way; half the bytes of the coefficient stream)
     bool use16 = false;
+    bool dense_cols = false;   // some variable's rows are one contiguous range (colT0 is read)
     int16_t *val16 = nullptr, *sellT_val16 = nullptr;
     float *rowinv32 = nullptr;          // 1/||a_j|| (0 for a zero row): the GNN's edge weights
     float gnn_ictmax = 1.f, gnn_irtmax = 1.f;
@@ -935,6 +936,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         std::vector<int> sptr(static_cast<size_t>(Pn) * (nch + 1)), srow(static_cast<size_t>(Pn) * nch * 64, -1);
         std::vector<int> sc0(static_cast<size_t>(Pn) * nch * 64, -1), slen(static_cast<size_t>(Pn) * nch * 64, 0);
         std::vector<int> sci, sval;
+        bool any_dense = false;
         sci.reserve(static_cast<size_t>(cix.size() * 1.2) + 64);
         sval.reserve(sci.capacity());
         std::vector<int> len(rows), order(rows);
@@ -975,7 +977,10 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
                             ++k;
                         }
                     slen[slot] = k;
-                    if (k > 0 && contiguous) sc0[slot] = first;
+                    if (k > 0 && contiguous) {
+                        sc0[slot] = first;
+                        any_dense = true;
+                    }
                 }
             }
             sptr[q * (nch + 1) + nch] = static_cast<int>(sci.size());
@@ -1002,7 +1007,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         sv.ci = buf[1];
         sv.val = buf[2];
         sv.row_of = buf[3];
-        sv.c0 = buf[4];
+        sv.c0 = any_dense ? buf[4] : nullptr;
         sv.len = buf[5];
         return GFORS_OK;
     };
@@ -1080,6 +1085,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             bool dense = b1 > b0;
             for (int e = b0 + 1; e < b1 && dense; ++e) dense = ciT[e] == ciT[b0] + (e - b0);
             if (dense) r0v[i] = ciT[b0];
+            P->dense_cols = P->dense_cols || dense;
         }
         if ((rc = upload(s, P->colT0, r0v.data(), n))) return rc;
         if ((rc = sync(P))) return rc;
@@ -1349,10 +1355,12 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
                          P->di.tau2, P->row_inst);
         if (!all)
             launch_dual(s, lpr - kLprBlock, P->unitK, batched, m, m1, P->rp, P->ci, P->val,
+                        P->use16 ? P->val16 : nullptr,
                         P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2, P->di.tau2,
                         P->row_inst, kHeavyLen);
     } else {
-        launch_dual(s, lpr, P->unitK, batched, m, m1, P->rp, P->ci, P->val, P->omega, P->rt,
+        launch_dual(s, lpr, P->unitK, batched, m, m1, P->rp, P->ci, P->val,
+                    P->use16 ? P->val16 : nullptr, P->omega, P->rt,
                     P->xbar, y_in, y_out, P->wy, tau2, P->di.tau2, P->row_inst, 0);
     }
     P->by_fresh = wy_bits;
@@ -1402,10 +1410,12 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
                            P->valT, P->wy, x_in, x_out, xbar, P->ct, tau1, P->di.tau1, P->di.rho,
                            P->var_inst);
         launch_primal(s, lpr - kLprBlock, kmode, false, batched, static_cast<int>(P->n), P->rpT,
-                      P->colT0, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct,
-                      tau1, 0.f, P->di.tau1, P->di.two_so, P->di.rho, P->var_inst, ctr, kHeavyLen);
+                      P->dense_cols ? P->colT0 : nullptr, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ,
+                      x_in, x_out, xbar, P->ct, tau1, 0.f, P->di.tau1, P->di.two_so, P->di.rho,
+                      P->var_inst, ctr, kHeavyLen);
     } else {
-        launch_primal(s, lpr, kmode, P->hasQ, batched, static_cast<int>(P->n), P->rpT, P->colT0, P->ciT,
+        launch_primal(s, lpr, kmode, P->hasQ, batched, static_cast<int>(P->n), P->rpT,
+                      P->dense_cols ? P->colT0 : nullptr, P->ciT,
                       P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, x_in, x_out, xbar, P->ct, tau1,
                       static_cast<float>(P->s_o[0] > 0 ? 2.0 / P->s_o[0] : 2.0), P->di.tau1,
                       P->di.two_so, P->di.rho, P->var_inst, ctr, 0);

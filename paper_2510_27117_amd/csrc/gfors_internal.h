@@ -91,8 +91,9 @@ constexpr int kLprBlock = 256;  // launch shape "a workgroup of 256 lanes per ro
 constexpr int kHeavyLen = 256;
 
 // ------------------------------------------------------------------ PDHG
+// val16: the coefficients as int16 when every |a| <= 32767 (else null)
 void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
-                 const int *rp, const int *ci, const int *val, const float *omega,
+                 const int *rp, const int *ci, const int *val, const int16_t *val16, const float *omega,
                  const float *rt, const float *xbar, const float *y_in, float *y_out,
                  float *wy, float tau2, const float *tau2_inst, const int *row_inst,
                  int skip_len);

@@ -24,10 +24,10 @@ __device__ __forceinline__ T group_sum(T v) {
 // projected onto R_+ for inequality rows (j < m1).  Also writes
 // wy_j = omega_j y_j, which the primal step multiplies by the integer a_ji.
 // ---------------------------------------------------------------------------
-template <int LPR, bool UNIT, bool BATCH>
+template <int LPR, bool UNIT, bool BATCH, typename VT>
 __global__ void __launch_bounds__(256)
 k_dual(int m, int m1, const int *__restrict__ rp, const int *__restrict__ ci,
-       const int *__restrict__ val, const float *__restrict__ omega,
+       const VT *__restrict__ val, const float *__restrict__ omega,
        const float *__restrict__ rt, const float *__restrict__ xbar,
        const float *__restrict__ y_in, float *__restrict__ y_out, float *__restrict__ wy,
        float tau2, const float *__restrict__ tau2_inst, const int *__restrict__ row_inst,
@@ -252,7 +252,7 @@ k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ colT0, cons
             // a variable whose rows are one contiguous range (dense rows of a
             // batched instance) computes its row indices instead of loading them
             const int e0 = rpT[i], e1 = rpT[i + 1];
-            const int r0 = colT0[i];
+            const int r0 = colT0 ? colT0[i] : -1;   // null: no variable is a contiguous range
 #pragma unroll 4
             for (int e = e0 + sub; e < e1; e += LPR) {
                 int j;
@@ -287,26 +287,27 @@ k_primal(int n, const int *__restrict__ rpT, const int *__restrict__ colT0, cons
 
 template <int LPR>
 static void dual_lpr(hipStream_t s, bool unit, bool batched, int m, int m1, const int *rp,
-                     const int *ci, const int *val, const float *omega, const float *rt,
+                     const int *ci, const int *val, const int16_t *val16, const float *omega, const float *rt,
                      const float *xbar, const float *y_in, float *y_out, float *wy, float tau2,
                      const float *tau2_inst, const int *row_inst, int skip_len) {
     const int64_t threads = static_cast<int64_t>(m) * LPR;
     const int blocks = static_cast<int>((threads + 255) / 256);
     if (blocks == 0) return;
-#define GF_DUAL(U, B) \
-    k_dual<LPR, U, B><<<blocks, 256, 0, s>>>(m, m1, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst, skip_len)
-    if (unit) { if (batched) GF_DUAL(true, true); else GF_DUAL(true, false); }
-    else { if (batched) GF_DUAL(false, true); else GF_DUAL(false, false); }
+#define GF_DUAL(U, B, VT, V) \
+    k_dual<LPR, U, B, VT><<<blocks, 256, 0, s>>>(m, m1, rp, ci, V, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst, skip_len)
+    if (unit) { if (batched) GF_DUAL(true, true, int, val); else GF_DUAL(true, false, int, val); }
+    else if (val16) { if (batched) GF_DUAL(false, true, int16_t, val16); else GF_DUAL(false, false, int16_t, val16); }
+    else { if (batched) GF_DUAL(false, true, int, val); else GF_DUAL(false, false, int, val); }
 #undef GF_DUAL
 }
 
 void launch_dual(hipStream_t s, int lpr, bool unit, bool batched, int m, int m1,
-                 const int *rp, const int *ci, const int *val, const float *omega,
+                 const int *rp, const int *ci, const int *val, const int16_t *val16, const float *omega,
                  const float *rt, const float *xbar, const float *y_in, float *y_out,
                  float *wy, float tau2, const float *tau2_inst, const int *row_inst,
                  int skip_len) {
     switch (lpr) {
-#define GF_CASE(L) case L: dual_lpr<L>(s, unit, batched, m, m1, rp, ci, val, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst, skip_len); break;
+#define GF_CASE(L) case L: dual_lpr<L>(s, unit, batched, m, m1, rp, ci, val, val16, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst, skip_len); break;
         GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
 #undef GF_CASE
         default: break;
@@ -539,7 +540,7 @@ k_sell(int nrows, int P, int nchunk, const int *__restrict__ ptr, const int *__r
     const int *cic = ci + e0 + lane;
     float acc = 0.f;
     const int64_t slot = (static_cast<int64_t>(sl) * nchunk + c) * 64 + lane;
-    const int cb = sc0[slot];
+    const int cb = sc0 ? sc0[slot] : -1;          // null: no slot is a contiguous range
     if (cb >= 0) {
         // the row's entries here are the columns cb, cb + 1, ...: indices are
         // computed; slots past its length add 0 like the padding entries
