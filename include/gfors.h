@@ -133,12 +133,14 @@ int gfors_pdhg_steps(gfors_problem *P, int32_t nsteps, int32_t want_residuals);
 /* One sampling round (Algorithm 3 + EvalBest): K candidates per instance
  * (K % 64 == 0, 64 <= K <= K_max) drawn from p = x_k, or from the caller's
  * device array p_override (float[n], values in [0,1]; NULL = use x_k).  The
- * uniform of candidate l, local variable i of instance t in round r is word
- * (i & 3) of Philox4x32-10(key = seed, counter = (l, i >> 2, r, t)), taken as
- * (U >> 8) 2^-24; candidate bit = [u < p_i].  Every candidate is evaluated
- * exactly on the original integer data; the feasible candidate with the least
- * objective (lowest index on ties) replaces the incumbent on strict
- * improvement.  Then the trigger counter advances and rho follows
+ * uniform of candidate l, local variable i of instance t in round r is
+ * U = word (l & 3) of Philox4x32-10(key = (seed & 0xffffffff, seed >> 32),
+ * counter = (l >> 2, i, r, t)), taken as u = (U >> 8) 2^-24; candidate bit =
+ * [u < p_i] (strict, so p = 0 never and p = 1 always gives a one).  One
+ * generator call thus serves four consecutive candidates of one variable.
+ * Every candidate is evaluated exactly on the original integer data; the
+ * feasible candidate with the least objective (lowest index on ties) replaces
+ * the incumbent on strict improvement.  Then the trigger counter advances and rho follows
  * UpdatePenalty (Sec. 3).  viol_dev (int32[T*K]) and obj_dev (int64[T*K]),
  * if not NULL, receive the per-candidate violation counts and objectives.
  * Async. */

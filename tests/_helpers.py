@@ -78,3 +78,39 @@ def mixed_problem(n=150, seed=0):
             Qd[j, i] += v
     c = rng.integers(-50, 60, size=n)
     return I.from_dense(c, A=A, b=b, B=Bm, d=d, Q=Qd, name=f"mixed{seed}")
+
+
+# --------------------------------------------------------- learned proposal
+
+def gnn_case(name):
+    """A problem, its scaled data, an oracle iterate (x, y as FP32) and 0/1
+    targets: the inputs of the learned-proposal gradient checks."""
+    if name == "ufl":
+        P = I.facility_location(6, 40, seed=3)
+    elif name == "mixed":
+        P = mixed_problem(150, seed=11)
+    else:
+        P = I.set_cover_bernoulli(700, 260, 0.02, seed=4)
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=61, keep_every=60)
+    st, _ = traj[-1]
+    rng = np.random.default_rng(7)
+    x = st.x.astype(np.float32)
+    y = st.y.astype(np.float32)
+    t = (rng.random(P.n) < 0.3).astype(np.float32)
+    return P, S, x, y, t
+
+
+def gnn_params(seed):
+    """Network parameters at the initialiser's scale (std sqrt(2/(fan_in+fan_out))),
+    small random biases, as FP32."""
+    from oracle import gnn_oracle as N
+    rng = np.random.default_rng(seed)
+    out = {}
+    for k, s in N.param_shapes().items():
+        if len(s) == 2:
+            out[k] = rng.normal(0, np.sqrt(2.0 / (s[0] + s[1])), size=s)
+        elif k == "wo":
+            out[k] = rng.normal(0, np.sqrt(2.0 / 65), size=s)
+        else:
+            out[k] = rng.normal(0, 0.05, size=s)
+    return {k: v.astype(np.float32) for k, v in out.items()}

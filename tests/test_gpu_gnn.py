@@ -1,32 +1,25 @@
 """GPU parity of the learned sampling proposal against the FP64 oracle
 (oracle/gnn_oracle.py), on the same parameters and inputs.
 
-The device keeps the 64x64 layer weights, activations and messages in BF16
+The device keeps the 64x64 layer weights, activations, messages and dZ in BF16
 (MFMA operands) and accumulates in FP32, so the oracle is given the layer
 weights rounded to BF16 (round to nearest even), as the device uses them, and
-the bars bound what BF16 storage of activations, messages and dZ leaves over:
-
-* logits within 3e-2 of the oracle relative to max(1, |logit|_inf);
-* the whole gradient with cosine >= 0.99 and relative L2 error <= 0.15, and
-  every parameter tensor with cosine >= 0.98.
-
-Where these come from: an FP64 model of the network that rounds to BF16 at the
-kernels' storage points, compared with the oracle over five parameter seeds
-on these three problems, reaches logit errors up to 1.7e-2, whole-gradient
-relative errors up to 9.6e-2 and per-tensor cosines down to 0.990; relative
-perturbations of 3e-7 (FP32 accumulation order) before the BF16 roundings
-alone move per-tensor gradients by up to 4 %.  A wrong index, sign or operand
-moves a tensor's cosine far below these bars.  Adam is compared to 1e-6, and
-training lowers the loss.
+the bars (tests/gnn_bars.py) bound what BF16 storage leaves over: logits,
+loss, the whole gradient (cosine and relative L2 error) and, per parameter
+tensor, the relative L2 error and the norm ratio |g_k| / |g_ref_k|.  They are
+derived from an FP64 model that rounds to BF16 at the kernels' storage points
+(tests/gnn_bf16_model.py; checked against the bars in tests/test_gnn_bars.py)
+and reject a tensor whose gradient is off by a factor of 2.  Adam is compared
+to 1e-6, and training lowers the loss.
 """
 import numpy as np
 import pytest
 
-from oracle import gfors_oracle as O
 from oracle import gnn_oracle as N
-from paper_2510_27117_amd import instances as I
 
-from _helpers import mixed_problem, oracle_trajectory
+import gnn_bars as B
+import gnn_bf16_model as M
+from _helpers import gnn_case as _case, gnn_params as _params
 
 pytestmark = pytest.mark.gpu
 
@@ -41,59 +34,22 @@ def G():
     return gfors
 
 
-def _case(name):
-    if name == "ufl":
-        P = I.facility_location(6, 40, seed=3)
-    elif name == "mixed":
-        P = mixed_problem(150, seed=11)
-    else:
-        P = I.set_cover_bernoulli(700, 260, 0.02, seed=4)
-    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=61, keep_every=60)
-    st, _ = traj[-1]
-    rng = np.random.default_rng(7)
-    x = st.x.astype(np.float32)
-    y = st.y.astype(np.float32)
-    t = (rng.random(P.n) < 0.3).astype(np.float32)
-    return P, S, x, y, t
-
-
-def _params(seed):
-    """Weights at the initialiser's scale (std sqrt(2/(fan_in+fan_out))), small
-    random biases, as FP32."""
-    rng = np.random.default_rng(seed)
-    out = {}
-    for k, s in N.param_shapes().items():
-        if len(s) == 2:
-            out[k] = rng.normal(0, np.sqrt(2.0 / (s[0] + s[1])), size=s)
-        elif k == "wo":
-            out[k] = rng.normal(0, np.sqrt(2.0 / 65), size=s)
-        else:
-            out[k] = rng.normal(0, 0.05, size=s)
-    return {k: v.astype(np.float32) for k, v in out.items()}
-
-
-def _bf16(a):
-    """FP32 -> BF16 -> FP32, round to nearest even."""
-    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32)
-
-
 def _oracle(P, S, x, y, t, p32):
     E = N.edge_matrix(P)
     Fv, Fc = N.features(S.c.astype(np.float32), S.r.astype(np.float32), S.m1, x, y)
     # the layer weights as the device holds them (BF16); embeddings, biases and
     # the output layer stay FP32 on the device
-    pd = {k: (_bf16(v) if v.shape == (N.H, N.H) else v).astype(np.float64) for k, v in p32.items()}
+    pd = {k: (M.bf16(v) if v.shape == (N.H, N.H) else v.astype(np.float64)) for k, v in p32.items()}
     loss, g, logit = N.loss_and_grad(pd, E, Fv, Fc, t.astype(np.float64))
     return loss, g, logit
 
 
+@pytest.mark.parametrize("pseed", [1, 2])
 @pytest.mark.parametrize("name", ["ufl", "mixed", "setcover"])
-def test_forward_and_gradient_match_oracle(G, name):
+def test_forward_and_gradient_match_oracle(G, name, pseed):
     import torch
     P, S, x, y, t = _case(name)
-    p32 = _params(1)
+    p32 = _params(pseed)
     loss_ref, g_ref, logit_ref = _oracle(P, S, x, y, t, p32)
     prob = G.Problem(P, G.default_params(k_int=20, K_max=1024))
     net = G.GNN(params=N.flatten(p32).astype(np.float32))
@@ -103,25 +59,15 @@ def test_forward_and_gradient_match_oracle(G, name):
     p, lg = net.forward(prob, xd, yd, with_logits=True)
     prob.synchronize(); net.stream.synchronize()
     lg = lg.cpu().numpy().astype(np.float64)
-    err = np.max(np.abs(lg - logit_ref)) / max(1.0, np.max(np.abs(logit_ref)))
-    assert err <= 3e-2, err
     assert np.allclose(p.cpu().numpy(), 1 / (1 + np.exp(-lg)), atol=1e-6)
     loss = net.grad(prob, td, xd, yd)
-    assert abs(loss - loss_ref) <= 3e-2 * max(1.0, abs(loss_ref))
-    gv = net.get_grad().astype(np.float64)
-    gref = N.flatten(g_ref)
-    gcos = float(gv @ gref / (np.linalg.norm(gv) * np.linalg.norm(gref)))
-    grel = float(np.linalg.norm(gv - gref) / np.linalg.norm(gref))
-    assert gcos >= 0.99 and grel <= 0.15, (gcos, grel)
-    gg = N.unflatten(gv)
+    gg = N.unflatten(net.get_grad().astype(np.float64))
+    c = M.compare(gg, g_ref, lg, logit_ref, loss, loss_ref)
+    bad = B.check(c)
+    assert not bad, (bad, {k: c[k] for k in ("logit", "loss", "cos", "rel")})
     for k in N.PARAM_ORDER:
-        a, b = gg[k].reshape(-1), g_ref[k].reshape(-1)
-        nb = np.linalg.norm(b)
-        if nb < 1e-7:
-            assert np.linalg.norm(a) <= 1e-5, k
-            continue
-        cos = float(a @ b / (np.linalg.norm(a) * nb + 1e-30))
-        assert cos >= 0.98, (k, cos)
+        if np.linalg.norm(g_ref[k]) < B.TENSOR_MIN_NORM:
+            assert np.linalg.norm(gg[k]) <= 1e-5, k
     net.close()
     prob.close()
 

@@ -200,3 +200,100 @@ def test_residual_inclusions_of_theorem2():
     assert np.allclose(dys[: S.m1][pos], 0.0, atol=1e-12)
     assert np.all(dys[: S.m1][~pos] <= 1e-12)
     assert math.isclose(R["binary"], float(np.sum(nxt.x * (1 - nxt.x))), rel_tol=1e-15)
+
+
+# ------------------------------------------------- equality rows (eq. saddle)
+
+def test_pdhg_hand_trace_with_equality_row():
+    """Algorithm 2 with an inequality dual clipped at 0 and an equality dual
+    that goes negative (h_2 of eq. (saddle) constrains only inequality rows),
+    rho > 0; values traced by hand in exact binary fractions."""
+    g = _load("pdhg_trace_eq.json")
+    pr = g["problem"]
+    P = I.from_dense(pr["c"], A=pr["A"], b=pr["b"], B=pr["B"], d=pr["d"])
+    S = O.preprocess(P, O.Params(**g["params"], power_iters=50))
+    # the spectral norm of K = -[e1; e3; e2] is 1 up to the power iteration's rounding
+    assert abs(S.s_K - 1.0) <= 1e-15
+    assert (S.m1, S.m2) == (2, 1)
+    assert S.tau1 == g["scaled"]["tau1"] and S.tau2 == g["scaled"]["tau2"]
+    assert S.c.tolist() == g["scaled"]["c"]
+    assert np.allclose(S.K.toarray(), g["scaled"]["K"], rtol=0, atol=1e-15)
+    assert np.allclose(S.r, g["scaled"]["r"], rtol=0, atol=1e-15)
+    rho = g["rho"]
+    st = O.init_state(S)
+    states = [st]
+    for step in g["trace"]:
+        st = O.pdhg_step(S, st, rho)
+        states.append(st)
+        for key in ("x", "y", "xbar"):
+            assert np.allclose(getattr(st, key), step[key], rtol=0, atol=1e-14), (key, step)
+    ref = g["residuals_after_step3"]
+    R = O.residuals(S, states[2], states[3], rho)
+    assert np.allclose(R["sx_vec"], ref["sx_vec"], rtol=0, atol=1e-14)
+    assert np.allclose(R["sy_vec"], ref["sy_vec"], rtol=0, atol=1e-14)
+    assert abs(R["sx"] - np.linalg.norm(ref["sx_vec"])) <= 1e-14
+    assert abs(R["sy"] - np.linalg.norm(ref["sy_vec"])) <= 1e-14
+    assert abs(R["primal"] - math.sqrt(ref["primal_sq"])) <= 1e-14
+    assert abs(R["binary"] - ref["binary"]) <= 1e-15
+
+
+def test_primal_gap_hand_values():
+    """CheckHalt's primal gap (Sec. 3) at x_k: the positive part of K x + r on
+    inequality rows (a satisfied row contributes 0), the signed residual on
+    equality rows.  Two variables; rows x1 + x2 >= 1 (violated at the point),
+    x1 >= 0 (satisfied), x1 - x2 = 0 (violated, residual of either sign)."""
+    P = I.from_dense([1, 1], A=[[1, 1], [1, 0]], b=[1, 0], B=[[1, -1]], d=[0])
+    S = O.preprocess(P, O.Params(power_iters=300))
+    rn = np.array([math.sqrt(2.0), 1.0, math.sqrt(2.0)]) * S.s_K   # row scale of K
+    for x, xprev in (([0.25, 0.5], [0.5, 0.5]), ([0.5, 0.25], [0.0, 1.0])):
+        x = np.array(x)
+        xprev = np.array(xprev)
+        before = O.State(x=xprev, x_prev=xprev, xbar=xprev.copy(), y=np.zeros(3))
+        after = O.State(x=x, x_prev=xprev, xbar=2 * x - xprev, y=np.zeros(3))
+        R = O.residuals(S, before, after, 0.0)
+        # row 1: 1 - x1 - x2 > 0 (violated); row 2: -x1 < 0 (satisfied -> 0);
+        # equality: x2 - x1, kept with its sign
+        v1 = (1.0 - x[0] - x[1]) / rn[0]
+        v3 = (x[1] - x[0]) / rn[2]
+        assert v1 > 0 and abs(v3) > 0
+        assert abs(R["primal"] - math.hypot(v1, v3)) <= 1e-12 * math.hypot(v1, v3)
+        assert abs(R["binary"] - float(np.sum(x * (1 - x)))) <= 1e-15
+
+
+def _equality_lp_problem():
+    """An LP relaxation whose equality rows bind in both directions: row 1's
+    variables have negative costs (a '>=' reading would raise their sum above
+    its right-hand side), row 2's positive costs (a '<=' reading would lower
+    it); plus one capacity row."""
+    rng = np.random.default_rng(12)
+    n = 16
+    c = np.concatenate([-rng.integers(5, 30, size=8), rng.integers(5, 30, size=8)])
+    B = np.zeros((2, n), dtype=np.int64)
+    B[0, :8] = 1
+    B[1, 8:] = 1
+    B[1, 3] = 1                       # couple the rows through one variable
+    d = np.array([3, 4])
+    w = rng.integers(1, 10, size=n)
+    A = (-w)[None, :]
+    b = np.array([-int(w.sum() // 2)])
+    return I.from_dense(c, A=A, b=b, B=B, d=d)
+
+
+def test_lp_limit_with_equality_rows_matches_highs():
+    """Convex special case (Q = 0, rho = 0) with equality rows: the PDHG limit
+    solves the scaled LP (HiGHS) and satisfies the equalities; the equality
+    duals take both signs at the saddle point."""
+    P = _equality_lp_problem()
+    S = O.preprocess(P, O.Params(rho_min=0.0, rho_max=0.0, rho_delta=0.0))
+    res = _scaled_lp(S)
+    assert res.status == 0
+    marg = res.eqlin.marginals
+    assert np.min(marg) < -1e-6 and np.max(marg) > 1e-6
+    st = O.init_state(S)
+    for _ in range(40000):
+        st = O.pdhg_step(S, st, 0.0)
+    assert abs(S.c @ st.x - res.fun) <= 1e-6 * abs(res.fun)
+    t = S.K @ st.x + S.r
+    assert np.max(t[: S.m1]) <= 1e-7
+    assert np.max(np.abs(t[S.m1:])) <= 1e-7
+    assert np.min(st.y[S.m1:]) < 0 < np.max(st.y[S.m1:])

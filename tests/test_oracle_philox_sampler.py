@@ -120,3 +120,48 @@ def test_pack_unpack_roundtrip():
 def test_round_candidate_threshold():
     x = np.array([0.0, 0.5, np.nextafter(0.5, 1.0), np.nextafter(0.5, 0.0), 1.0])
     assert O.round_candidate(x).tolist() == [[False, False, True, False, True]]
+
+
+def test_strict_threshold_at_equal_uniform(rocrand_ref):
+    """Algorithm 3 with the strict comparison of the sampler's reading: a
+    candidate whose uniform equals p_i exactly samples 0, one ulp of the 24-bit
+    grid above it samples 1.  The uniforms come from rocRAND's engine."""
+    seed, rnd, inst = 3, 4, 1
+    n, K = 6, 8
+    l0 = 5
+    words = [_rocrand4(rocrand_ref, seed, l0 >> 2, i, rnd, inst)[0][l0 & 3] for i in range(n)]
+    u = np.array([(w >> 8) * 2.0 ** -24 for w in words])
+    X_eq = O.sample_bits(u, K, seed, rnd, inst)
+    X_up = O.sample_bits(u + 2.0 ** -24, K, seed, rnd, inst)
+    assert not X_eq[l0].any()
+    assert X_up[l0].all()
+
+
+def test_header_counter_map_replays_the_sampler():
+    """The uniform map stated in include/gfors.h (gfors_sample_eval) is read
+    from the header text, evaluated with the oracle's Philox4x32-10, and must
+    reproduce the oracle's candidates: a caller can replay the uniforms from
+    the documented contract alone."""
+    import re
+    with open(os.path.join(HERE, "..", "include", "gfors.h")) as f:
+        txt = " ".join(ln.strip().lstrip("/*").strip() for ln in f)
+    txt = " ".join(txt.split())
+    m = re.search(r"U = word \(([^)]*)\) of Philox4x32-10\(key = \(([^,]*), ([^)]*)\), "
+                  r"counter = \(([^,]*), ([^,]*), ([^,]*), ([^)]*)\)\), taken as u = "
+                  r"\(U >> (\d+)\) 2\^-(\d+); candidate bit = \[u < p_i\]", txt)
+    assert m, "uniform map sentence not found in gfors.h"
+    word, key0, key1, *ctr = m.groups()[:7]
+    shift, bits = int(m.group(8)), int(m.group(9))
+    seed, rnd, inst = (1 << 33) + 12345, 7, 2
+    rng = np.random.default_rng(4)
+    p = rng.random(9)
+    K = 64
+    X = O.sample_bits(p, K, seed, rnd, inst)
+    for l in (0, 1, 6, 33, 63):
+        for i in range(p.size):
+            env = {"l": l, "i": i, "r": rnd, "t": inst, "seed": seed}
+            c = [eval(e, {}, env) for e in ctr]
+            k0, k1 = eval(key0, {}, env), eval(key1, {}, env)
+            w = O.philox4x32_10(*c, k0, k1)[eval(word, {}, env)]
+            u = (int(w) >> shift) * 2.0 ** -bits
+            assert bool(u < p[i]) == bool(X[l, i]), (l, i)
