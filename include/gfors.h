@@ -124,6 +124,31 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b,
 void gfors_destroy_problem(gfors_problem *P);
 const char *gfors_last_error(void);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, serving loops, harnesses that forbid allocation): as
+ * gfors_create_problem, but the problem's device memory is a file-scope array
+ * of GFORS_STATIC_WS_BYTES bytes inside the library instead of a caller
+ * workspace.  Every GPU the library runs on holds its own copy of that array
+ * until the process ends; it serves ONE live problem per device at a time
+ * (the device current at this call).  No device memory is allocated by this
+ * call; the launch shapes come from the size heuristic (params->autotune is
+ * taken as 0, so the problem computes exactly what gfors_create_problem with
+ * autotune = 0 computes).  Later calls on the handle are the ordinary ones.
+ * The array keeps whatever the previous problem left; creation initialises
+ * everything the method reads, as it does for an uninitialised workspace.
+ * Calls that overlap on one device race: a second creation while a problem
+ * created here is alive on the same device returns E_STATE, and
+ * gfors_destroy_problem releases the array.
+ * Errors: those of gfors_create_problem; E_OOM (with the sizes in the
+ * message) when gfors_workspace_bytes of the problem exceeds
+ * GFORS_STATIC_WS_BYTES; E_STATE as above. */
+#define GFORS_STATIC_WS_BYTES (32u << 20)
+int gfors_create_problem_static(const gfors_csr *A, const int64_t *b,
+                                const gfors_csr *B, const int64_t *d,
+                                const gfors_csr *Q, const int64_t *c, int64_t n,
+                                int32_t num_instances, const int64_t *inst_offsets,
+                                const gfors_params *p, void *stream, gfors_problem **out);
+
 /* Run nsteps PDHG iterations (Algorithm 2) at the current penalty rho of each
  * instance.  If want_residuals != 0 the last step also computes, in FP64, the
  * residuals of Theorem 2 and the CheckHalt gaps (read with gfors_get_residuals).

@@ -14,6 +14,7 @@
 #include <memory>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -182,6 +183,9 @@ struct gfors_problem {
     int red_S = 1;                  // tile slices of the candidate reduction
     int32_t *red_v = nullptr;
     int64_t *red_z = nullptr;
+
+    // device whose static workspace holds this problem (gfors_create_problem_static), else -1
+    int static_dev = -1;
 
     // graphs: key = (K, parity)
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -489,9 +493,12 @@ int gfors_workspace_bytes(int64_t n, int64_t m1, int64_t m2, int64_t nnzA, int64
     return GFORS_OK;
 }
 
+static void static_ws_release(gfors_problem *P);
+
 void gfors_destroy_problem(gfors_problem *P) {
     if (!P) return;
     for (auto &kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+    static_ws_release(P);
     delete P;
 }
 
@@ -2214,6 +2221,92 @@ int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32
     if (m1) *m1 = P->m1;
     if (m2) *m2 = P->m2;
     if (T) *T = P->T;
+    return GFORS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Problems whose device memory is a file-scope array instead of a caller
+// workspace, for callers that cannot allocate device memory.  Each GPU the
+// library runs on holds one copy of the array for the life of the process and
+// serves at most one live problem at a time.
+static __device__ __align__(256) unsigned char scratch[GFORS_STATIC_WS_BYTES];
+
+namespace {
+struct StaticWs {
+    unsigned char *ptr = nullptr;        // device address of this device's copy of `scratch`
+    const gfors_problem *owner = nullptr;
+};
+std::mutex g_static_mu;
+std::map<int, StaticWs> g_static;        // by HIP device ordinal
+}  // namespace
+
+static void static_ws_release(gfors_problem *P) {
+    if (P->static_dev < 0) return;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    auto it = g_static.find(P->static_dev);
+    if (it != g_static.end() && it->second.owner == P) it->second.owner = nullptr;
+    P->static_dev = -1;
+}
+
+extern "C" {
+
+int gfors_create_problem_static(const gfors_csr *A, const int64_t *b, const gfors_csr *B,
+                                const int64_t *d, const gfors_csr *Q, const int64_t *c, int64_t n,
+                                int32_t num_instances, const int64_t *inst_offsets,
+                                const gfors_params *prm, void *stream, gfors_problem **out) {
+    if (!out || !prm || !c || n <= 0 || num_instances < 1)
+        return fail(GFORS_E_ARG, "gfors_create_problem_static: NULL argument or n <= 0");
+    *out = nullptr;
+    int rc;
+    if ((rc = validate_csr(A, n, "A"))) return rc;
+    if ((rc = validate_csr(B, n, "B"))) return rc;
+    if ((rc = validate_csr(Q, n, "Q"))) return rc;
+    const int64_t m1 = A ? A->nrows : 0, m2 = B ? B->nrows : 0;
+    const int64_t nnzA = A ? A->row_ptr[A->nrows] : 0, nnzB = B ? B->row_ptr[B->nrows] : 0;
+    const int64_t nnzQ = Q ? Q->row_ptr[Q->nrows] : 0;
+    // the launch shapes come from the size heuristic: the autotuner's timing
+    // events are runtime objects this entry point does not create
+    gfors_params p = *prm;
+    p.autotune = 0;
+    size_t need = 0;
+    if ((rc = gfors_workspace_bytes(n, m1, m2, nnzA, nnzB, nnzQ, num_instances, &p, &need))) return rc;
+    if (need > sizeof(scratch))
+        return fail(GFORS_E_OOM, "gfors_create_problem_static: the problem needs " + std::to_string(need) +
+                                     " bytes of device memory; the static workspace holds " +
+                                     std::to_string(sizeof(scratch)) + " (GFORS_STATIC_WS_BYTES)");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        StaticWs &w = g_static[dev];
+        if (!w.ptr) {
+            // once per device, with that device current: the array's device address
+            void *ptr = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return fail(GFORS_E_HIP, "hipGetSymbolAddress returned NULL for the static workspace");
+            w.ptr = static_cast<unsigned char *>(ptr);
+        }
+        if (w.owner)
+            return fail(GFORS_E_STATE, "gfors_create_problem_static: the static workspace of device " +
+                                           std::to_string(dev) + " holds a live problem; destroy it first");
+        base = w.ptr;
+        w.owner = reinterpret_cast<const gfors_problem *>(&w);   // reserved while creating
+    }
+    gfors_problem *P = nullptr;
+    rc = gfors_create_problem(A, b, B, d, Q, c, n, num_instances, inst_offsets, &p, base, sizeof(scratch),
+                              stream, &P);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    StaticWs &w = g_static[dev];
+    if (rc != GFORS_OK) {
+        w.owner = nullptr;
+        return rc;
+    }
+    P->static_dev = dev;
+    w.owner = P;
+    *out = P;
     return GFORS_OK;
 }
 

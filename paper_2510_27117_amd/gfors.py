@@ -46,7 +46,7 @@ EXPORTS = [
     "gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad",
     "gfors_tu_create", "gfors_tu_dims", "gfors_tu_export", "gfors_tu_recover", "gfors_tu_destroy",
     "gfors_tu_last_error", "gfors_mono_rows", "gfors_mono_repair", "gfors_mono_last_error",
-    "gfors_philox_throughput", "gfors_eval_planes",
+    "gfors_philox_throughput", "gfors_eval_planes", "gfors_create_problem_static",
 ]
 
 KERNEL_NAMES = ["dual", "primal", "sample", "eval_cover", "eval_general", "eval_quad",
@@ -71,6 +71,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_create_problem.argtypes = [P(gfors_csr), c_vp, P(gfors_csr), c_vp, P(gfors_csr), c_vp,
                                        c_i64, c_i32, c_vp, P(gfors_params), c_vp, ctypes.c_size_t,
                                        c_vp, P(c_vp)]
+    L.gfors_create_problem_static.argtypes = [P(gfors_csr), c_vp, P(gfors_csr), c_vp, P(gfors_csr),
+                                              c_vp, c_i64, c_i32, c_vp, P(gfors_params), c_vp, P(c_vp)]
     L.gfors_destroy_problem.argtypes = [c_vp]
     L.gfors_destroy_problem.restype = None
     L.gfors_last_error.argtypes = []
@@ -184,10 +186,13 @@ def _csr(M, keep: list):
 class Problem:
     """One GFORS problem bound to a device workspace and a HIP stream.
 
-    ``bip`` is a paper_2510_27117_amd.instances.BIP (integer CSR data)."""
+    ``bip`` is a paper_2510_27117_amd.instances.BIP (integer CSR data).
+    ``static_ws=True`` creates it with gfors_create_problem_static: no device
+    workspace is allocated, the library's static array on the device is used
+    (one live problem per device, at most GFORS_STATIC_WS_BYTES)."""
 
     def __init__(self, bip, params: Optional[gfors_params] = None, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, static_ws: bool = False):
         import torch
         L = load_library()
         self.torch = torch
@@ -203,7 +208,9 @@ class Problem:
         _check(L.gfors_workspace_bytes(self.n, self.m1, self.m2, nnzA, nnzB, nnzQ, self.T,
                                        ctypes.byref(self.params), ctypes.byref(nbytes)))
         self.ws_bytes = int(nbytes.value)
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.static_ws = bool(static_ws)
+        self.ws = (None if self.static_ws
+                   else torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device))
         # a dedicated stream: the legacy null stream cannot be captured into graphs
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         keep: list = []
@@ -220,12 +227,19 @@ class Problem:
                              else np.array([[0, 0, 0], [self.n, self.m1, self.m2]], dtype=np.int64))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(L.gfors_create_problem(
-                ctypes.byref(A) if A else None, _ptr(b), ctypes.byref(B) if B else None, _ptr(d),
-                ctypes.byref(Q) if Q else None, _ptr(c), self.n, self.T, _ptr(off),
-                ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()),
-                ctypes.c_size_t(self.ws_bytes), ctypes.c_void_p(self.stream.cuda_stream),
-                ctypes.byref(h)))
+            if self.static_ws:
+                _check(L.gfors_create_problem_static(
+                    ctypes.byref(A) if A else None, _ptr(b), ctypes.byref(B) if B else None, _ptr(d),
+                    ctypes.byref(Q) if Q else None, _ptr(c), self.n, self.T, _ptr(off),
+                    ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
+                    ctypes.byref(h)))
+            else:
+                _check(L.gfors_create_problem(
+                    ctypes.byref(A) if A else None, _ptr(b), ctypes.byref(B) if B else None, _ptr(d),
+                    ctypes.byref(Q) if Q else None, _ptr(c), self.n, self.T, _ptr(off),
+                    ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()),
+                    ctypes.c_size_t(self.ws_bytes), ctypes.c_void_p(self.stream.cuda_stream),
+                    ctypes.byref(h)))
         self.handle = h
         self.m = self.m1 + self.m2
 
@@ -380,6 +394,10 @@ class Problem:
 # Module-level names mirroring the C entry points.
 def gfors_create_problem(bip, params=None, device="cuda:0", stream=None) -> Problem:
     return Problem(bip, params, device, stream)
+
+
+def gfors_create_problem_static(bip, params=None, device="cuda:0", stream=None) -> Problem:
+    return Problem(bip, params, device, stream, static_ws=True)
 
 
 def gfors_pdhg_steps(P: Problem, nsteps: int, want_residuals: bool = False):
