@@ -299,6 +299,43 @@ def test_graph_rounds_match_eager(G):
     b.close()
 
 
+@pytest.mark.parametrize("kind", ["knapsacks", "mixed"])
+def test_batched_graph_replay_matches_eager(G, kind):
+    """A batch of uneven instances replayed from captured graphs equals the
+    same rounds launched one by one, bit for bit, after every replay (state,
+    rho, incumbents, histories), with host reads and synchronisations between
+    the replays.  Batches: knapsacks of uneven sizes (their rows evaluated on
+    the matrix cores), and knapsacks with a set cover and a problem with Q and
+    equality rows (row by row)."""
+    parts = I.knapsack_batch(5, seed=12, n_lo=300, n_hi=3000, m_lo=3, m_hi=9)
+    if kind == "mixed":
+        parts.append(I.set_cover_bernoulli(301, 97, 0.05, seed=3))
+        parts.append(mixed_problem(150, seed=2))
+    Bt = I.concat_instances(parts)
+    T = len(parts)
+    a = G.Problem(Bt, _params(G, k_int=9, autotune=0, K_max=512))
+    b = G.Problem(Bt, _params(G, k_int=9, autotune=0, K_max=512))
+    try:
+        assert (a.eval_planes() > 0) == (kind == "knapsacks")
+        for rep in range(4):
+            a.run_rounds(2, 512, use_graph=False)
+            b.run_rounds(2, 512, use_graph=True)
+            sa, sb = a.get_state(), b.get_state()
+            for k in ("x", "x_prev", "y", "rho"):
+                assert np.array_equal(sa[k], sb[k]), (rep, k)
+            assert sa["k"] == sb["k"] == 18 * (rep + 1) and sa["round"] == sb["round"] == 2 * (rep + 1)
+            for t in range(T):
+                ba, bb = a.best(t), b.best(t)
+                assert (ba["z"], ba["found"], ba["round"], ba["l"]) == (bb["z"], bb["found"], bb["round"], bb["l"]), (rep, t)
+                assert np.array_equal(ba["x"], bb["x"]), (rep, t)
+                assert np.array_equal(a.history(t, 16), b.history(t, 16)), (rep, t)
+        assert np.array_equal(a.candidates(), b.candidates())
+        assert sum(a.best(t)["found"] for t in range(T)) >= 4
+    finally:
+        a.close()
+        b.close()
+
+
 def test_batched_matches_per_instance(G):
     """A block-diagonal batch behaves as independent instances: per-instance
     scales, one teacher-forced step and a sampling round equal the oracle run
