@@ -498,7 +498,7 @@ def run_gfors(P, params: Params, iters: int, K: int, instance: int = 0,
 
 
 # ----------------------------------------------------------------------------
-# TU reformulation (Theorem of Sec. 2.4.1), Q = 0
+# TU reformulation (Theorem of Sec. 2.4.1)
 # ----------------------------------------------------------------------------
 
 def tu_reformulate(P, pivots):
@@ -506,14 +506,17 @@ def tu_reformulate(P, pivots):
     carry a pivot (pivots[r] = column, or -1 to keep row r), following the
     theorem's formulas with the matrix inverse written out:
         s = B_JI^{-1} d_J,  S = -B_JI^{-1} B_JIbar,
+        Q' = S^T Q_II S + S^T Q_IIbar + Q_IIbar^T S + Q_IbarIbar,
         A' = A_.I S + A_.Ibar, b' = b - A_.I s, B' = B_JbarI S + B_JbarIbar,
-        d' = d_Jbar - B_JbarI s, c' = S^T c_I + c_Ibar, c'_0 = <c_I, s>,
+        d' = d_Jbar - B_JbarI s,
+        c' = 2 S^T Q_II s + 2 Q_IIbar^T s + S^T c_I + c_Ibar,
+        c'_0 = <s, Q_II s> + <c_I, s>,
     plus the rows S x >= -s and -S x >= s - 1 (0 <= x_I <= 1), of which a row
     satisfied by every point of the box is left out (reading: it removes no
-    point of the relaxation or of the binary problem).  Returns
+    point of the relaxation or of the binary problem).  Q is the symmetric
+    matrix of the objective <x, Q x> in full storage.  Returns
     (P', c'_0, recover) with recover(x') = full binary point."""
     from paper_2510_27117_amd import instances as Inst   # data containers only
-    assert P.Q is None
     pivots = np.asarray(pivots, dtype=np.int64)
     n = P.n
     Bs = _int_csr(P.B).astype(np.float64).tocsc()
@@ -548,7 +551,18 @@ def tu_reformulate(P, pivots):
     if up:
         rows.append(np.array(up))
         rhs.append(np.array(upr))
-    Pn = Inst.BIP(n=Ibar.size, c=(S.T @ P.c[I] + P.c[Ibar]).astype(np.int64), name=P.name + "_tu")
+    c_new = S.T @ P.c[I] + P.c[Ibar]
+    c0 = int(P.c[I] @ s)
+    Qn = None
+    if P.Q is not None:
+        Qd = I_dense(P.Q)
+        QII, QIb, Qbb = Qd[np.ix_(I, I)], Qd[np.ix_(I, Ibar)], Qd[np.ix_(Ibar, Ibar)]
+        Qn = S.T @ QII @ S + S.T @ QIb + QIb.T @ S + Qbb
+        c_new = c_new + 2 * (S.T @ QII @ s) + 2 * (QIb.T @ s)
+        c0 += int(s @ QII @ s)
+    Pn = Inst.BIP(n=Ibar.size, c=c_new.astype(np.int64), name=P.name + "_tu")
+    if Qn is not None and np.any(Qn):
+        Pn.Q = Inst.csr_from_dense(Qn)
     if rows:
         Pn.A = Inst.csr_from_dense(np.vstack(rows))
         Pn.b = np.concatenate(rhs).astype(np.int64)
@@ -556,7 +570,6 @@ def tu_reformulate(P, pivots):
         Bd = I_dense(P.B)
         Pn.B = Inst.csr_from_dense(Bd[Jbar][:, I] @ S + Bd[Jbar][:, Ibar])
         Pn.d = (P.d[Jbar] - Bd[Jbar][:, I] @ s).astype(np.int64)
-    c0 = int(P.c[I] @ s)
 
     def recover(xr):
         x = np.zeros(n, dtype=np.int64)

@@ -49,6 +49,46 @@ def test_oracle_tu_general_block_and_dropped_rows():
     assert int(zo[vo == 0].min()) == int(zn[vn == 0].min()) + c0
 
 
+def _quad_tu_case(seed):
+    """Equality rows with a TU (interval) matrix whose pivot block is lower
+    triangular, not an identity; an inequality row; a symmetric integer Q with
+    a diagonal."""
+    rng = np.random.default_rng(seed)
+    B = [[1, 1, 0, 0, 1, 0, 0], [0, 1, 1, 0, 0, 1, 0], [0, 0, 1, 1, 0, 0, 1]]
+    Q = rng.integers(-4, 5, size=(7, 7))
+    Q = Q + Q.T
+    np.fill_diagonal(Q, rng.integers(-3, 4, size=7))
+    c = rng.integers(-6, 7, size=7)
+    P = I.from_dense(c, A=[[1, 0, 1, 0, 1, 1, 0]], b=[1], B=B, d=[1, 1, 1], Q=Q)
+    return P, np.array([1, 2, 3])          # B_JI = [[1,0,0],[1,1,0],[0,1,1]]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_oracle_tu_with_quadratic_objective(seed):
+    """With Q != 0 (Q' = S^T Q_II S + S^T Q_IIbar + Q_IIbar^T S + Q_IbarIbar,
+    c' and c'_0 with the quadratic terms): same optimum up to c'_0, and every
+    feasible point on either side maps to a feasible point of equal value."""
+    P, piv = _quad_tu_case(seed)
+    Pn, c0, rec = O.tu_reformulate(P, piv)
+    Xo, Xn = _all(P.n), _all(Pn.n)
+    vo, zo = O.evaluate(P, Xo)
+    vn, zn = O.evaluate(Pn, Xn)
+    assert int(zo[vo == 0].min()) == int(zn[vn == 0].min()) + c0
+    for l in np.nonzero(vn == 0)[0]:
+        x = rec(Xn[l])
+        v1, z1 = O.evaluate(P, x[None, :].astype(bool))
+        assert set(np.unique(x)) <= {0, 1} and v1[0] == 0 and z1[0] == zn[l] + c0
+    keep = np.setdiff1d(np.arange(P.n), piv)
+    vk, zk = O.evaluate(Pn, Xo[vo == 0][:, keep])
+    assert np.all(vk == 0) and np.array_equal(zk + c0, zo[vo == 0])
+    # every point of {0,1}^n' (feasible or not) has the value of its recovery
+    # whenever the recovery is binary: the objective map is exact
+    for l in range(Xn.shape[0]):
+        x = rec(Xn[l])
+        if set(np.unique(x)) <= {0, 1}:
+            assert O.evaluate(P, x[None, :].astype(bool))[1][0] == zn[l] + c0
+
+
 @pytest.mark.parametrize("nf,nc,seed", [(2, 3, 0), (4, 7, 3), (6, 40, 5)])
 def test_library_tu_equals_oracle(nf, nc, seed):
     from paper_2510_27117_amd import gfors
