@@ -277,6 +277,58 @@ def facility_location(n_f: int, n_c: int, seed: int, scale: int = 1000,
                meta={"n_f": n_f, "n_c": n_c, "tu_pivots": pivots})
 
 
+def assignment_qap_like(n: int, seed: int, q_density: float = 0.02, q_max: int = 5) -> BIP:
+    """2D assignment with a sparse symmetric quadratic term and one knapsack row.
+
+    Variables x_ij (index i*n + j); equality rows: sum_j x_ij = 1 (row i) then
+    sum_i x_ij = 1 (column j), a bipartite incidence matrix (totally
+    unimodular).  c_ij ~ U{1..100}; Q symmetric with off-diagonal entries
+    ~ U{-q_max..q_max} w.p. q_density, zero diagonal; one row
+    -sum w_ij x_ij >= -cap with w ~ U{1..20}, cap = 12 n.
+    meta["tu_pivots"]: a spanning tree of the bipartite graph as pivot columns
+    (row i -> x_ii, column j >= 1 -> x_{j-1,j}, column 0 kept), so the pivot
+    block is not a signed identity."""
+    rng = np.random.default_rng(seed)
+    N = n * n
+    c = rng.integers(1, 101, size=N).astype(np.int64)
+    idx = np.arange(N, dtype=np.int64)
+    rows = np.concatenate([idx // n, n + idx % n])
+    cols = np.concatenate([idx, idx])
+    B = csr_from_coo(2 * n, N, rows, cols, None)
+    iu, ju = np.triu_indices(N, k=1)
+    pick = rng.random(iu.size) < q_density
+    iu, ju = iu[pick], ju[pick]
+    w = rng.integers(-q_max, q_max + 1, size=iu.size)
+    nz = w != 0
+    iu, ju, w = iu[nz], ju[nz], w[nz]
+    Q = csr_from_coo(N, N, np.concatenate([iu, ju]), np.concatenate([ju, iu]), np.concatenate([w, w]))
+    wk = rng.integers(1, 21, size=N)
+    A = csr_from_coo(1, N, np.zeros(N, dtype=np.int64), idx, -wk)
+    piv = np.empty(2 * n, dtype=np.int64)
+    piv[:n] = np.arange(n) * n + np.arange(n)
+    piv[n] = -1
+    piv[n + 1:] = (np.arange(1, n) - 1) * n + np.arange(1, n)
+    return BIP(n=N, c=c, A=A, b=np.array([-12 * n], dtype=np.int64), B=B,
+               d=np.ones(2 * n, dtype=np.int64), Q=Q, name=f"assignq_n{n}_s{seed}",
+               meta={"tu_pivots": piv})
+
+
+def assignment_3d(n: int, seed: int, c_hi: int = 100) -> BIP:
+    """3D assignment (Sec. 2.4.2, eq. assign3d): x_ijk at index (i n + j) n + k,
+    c ~ U{1..c_hi}; equality rows sum_{j,k} x_ijk = 1 (i), then
+    sum_{i,k} x_ijk = 1 (j), then sum_{i,j} x_ijk = 1 (k)."""
+    rng = np.random.default_rng(seed)
+    N = n ** 3
+    c = rng.integers(1, c_hi + 1, size=N).astype(np.int64)
+    v = np.arange(N, dtype=np.int64)
+    i, j, k = v // (n * n), (v // n) % n, v % n
+    rows = np.concatenate([i, n + j, 2 * n + k])
+    cols = np.concatenate([v, v, v])
+    B = csr_from_coo(3 * n, N, rows, cols, None)
+    return BIP(n=N, c=c, B=B, d=np.ones(3 * n, dtype=np.int64), name=f"assign3d_n{n}_s{seed}",
+               meta={"assign3d_n": n})
+
+
 def knapsack_batch(num: int, seed: int, n_lo: int = 1000, n_hi: int = 50000,
                    m_lo: int = 5, m_hi: int = 50) -> List[BIP]:
     """Batch of multidimensional knapsacks: n log-uniform in [n_lo, n_hi],
