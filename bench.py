@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--seq-sample", type=int, default=8,
                     help="batched workloads: instances run one by one for the comparison")
+    ap.add_argument("--sub", default="setcover_small_e2e,knapsack_batch,ufl_mono",
+                    help="with the default workload: further workloads measured after it and reported as "
+                         "compact sub-records ('' for none)")
     return ap.parse_args()
 
 
@@ -220,35 +223,181 @@ def host_cpu_model():
     return None
 
 
-def cpu_baseline(bip, k_int, K):
-    """The oracle as it stands, on a bounded sample of the same workload:
-    3 FP64 PDHG iterations and one sampling round of 16 candidates (exact
-    evaluation), scaled to the same step definition."""
+def cpu_baseline(bip, k_int, K, budget_s=8.0):
+    """The oracle as it stands (FP64 PDHG, exact int64 evaluation, one host
+    core) on a bounded sample of the same workload: one warm-up iteration, then
+    up to 10 iterations timed one by one (median); from the resulting iterate
+    one sampling round of Kc candidates (64, or 8 above 4M variables) drawn
+    at once, evaluated in 4 blocks after a warm-up evaluation of 2 candidates
+    (median block time).  Iterations and blocks stop early once budget_s is
+    spent (at least 3 iterations and one block).  Scaled to the step of the
+    GPU record (k_int iterations + K candidates per instance)."""
     from oracle import gfors_oracle as O
     prm = O.Params(k_int=k_int, power_iters=3)
     S = O.preprocess(bip, prm)
     st = O.init_state(S)
     rho = O.rho_value(S, 0)
-    st = O.pdhg_step(S, st, rho)
-    t0 = time.perf_counter()
-    iters = 3
-    for _ in range(iters):
+    st = O.pdhg_step(S, st, rho)                       # warm-up
+    ti = []
+    t_start = time.perf_counter()
+    while len(ti) < 10 and (len(ti) < 3 or time.perf_counter() - t_start < budget_s):
+        t0 = time.perf_counter()
         st = O.pdhg_step(S, st, rho)
-    t_iter = (time.perf_counter() - t0) / iters
-    kc = 16
+        ti.append(time.perf_counter() - t0)
+    t_iter = float(np.median(ti))
+    kc = 64 if bip.n <= 4_000_000 else 8
+    blk = kc // 4
     t0 = time.perf_counter()
     X = O.sample_bits(st.x, kc, 0, 0)
-    viol, z = O.evaluate(bip, X)
+    t_sample = time.perf_counter() - t0
+    O.evaluate(bip, X[:2])                              # warm-up
+    tb = []
     inc = O.Incumbent()
-    O.incumbent_update(inc, X, viol, z, 0, st.k)
-    t_cand = (time.perf_counter() - t0) / kc
-    step = k_int * t_iter + K * t_cand
+    t_start = time.perf_counter()
+    for q in range(4):
+        if q and time.perf_counter() - t_start > budget_s:
+            break
+        t0 = time.perf_counter()
+        viol, z = O.evaluate(bip, X[q * blk:(q + 1) * blk])
+        O.incumbent_update(inc, X[q * blk:(q + 1) * blk], viol, z, 0, st.k)
+        tb.append(time.perf_counter() - t0)
+    t_cand = t_sample / kc + float(np.median(tb)) / blk
+    T = bip.num_instances
+    step = k_int * t_iter + K * T * t_cand
     return {"value": k_int / step, "unit": "PDHG iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} FP64 PDHG iterations + 1 sampling round of {kc} candidates "
-                      f"(exact eval) on the full workload, scaled to a step of {k_int} "
-                      f"iterations + {K} candidates",
+            "sample": (f"1 warm-up + {len(ti)} FP64 PDHG iterations timed one by one (median), "
+                       f"1 sampling round of {kc} candidates drawn at once and evaluated exactly in "
+                       f"{len(tb)} block(s) of {blk} after a warm-up (median), on the full workload; "
+                       f"scaled to a step of {k_int} iterations + {K * T} candidates"),
             "candidates_per_s": 1.0 / t_cand, "iter_per_s_pdhg_only": 1.0 / t_iter,
             "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model()}
+
+
+def _pool_instance(args):
+    """One knapsack of the batch with the oracle (pool worker): seconds for
+    10 FP64 PDHG iterations and for one sampling round of 64 candidates."""
+    bip, k_int = args
+    from oracle import gfors_oracle as O
+    S = O.preprocess(bip, O.Params(k_int=k_int, power_iters=3))
+    st = O.init_state(S)
+    rho = O.rho_value(S, 0)
+    st = O.pdhg_step(S, st, rho)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        st = O.pdhg_step(S, st, rho)
+    t1 = time.perf_counter()
+    X = O.sample_bits(st.x, 64, 0, 0)
+    viol, z = O.evaluate(bip, X)
+    O.incumbent_update(O.Incumbent(), X, viol, z, 0, st.k)
+    return t1 - t0, time.perf_counter() - t1
+
+
+def cpu_baseline_pool(parts, k_int, K=512):
+    """The oracle on the knapsack batch over all host cores: a process pool
+    (one instance per task) runs 10 FP64 iterations and a 64-candidate round
+    on a sample of 4 x cores instances (after one warm-up task per worker);
+    each instance's time for k_int iterations + K candidates is estimated from
+    its own timings, the sample mean is scaled to the whole batch and divided
+    by the core count (the pool keeps every core busy).  Must run before the
+    process touches the GPU (the pool forks)."""
+    import multiprocessing as mp
+    cores = os.cpu_count() or 1
+    pick = parts[:4 * cores]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        pool.map(_pool_instance, [(parts[0], k_int)] * cores, chunksize=1)
+        t0 = time.perf_counter()
+        res = pool.map(_pool_instance, [(P, k_int) for P in pick], chunksize=1)
+        wall = time.perf_counter() - t0
+    step = [k_int * ti / 10.0 + K * tc / 64.0 for ti, tc in res]
+    batch_step = float(np.mean(step)) * len(parts) / cores
+    return {"value": k_int / batch_step, "unit": "PDHG iter/s (batched)", "cores": cores,
+            "kind": "oracle",
+            "sample": (f"{len(pick)} of the {len(parts)} instances, 10 FP64 PDHG iterations + 1 round of "
+                       f"64 candidates each, process pool on {cores} cores ({wall:.1f} s); per-instance "
+                       f"step ({k_int} iterations + {K} candidates) scaled from its timings, batch = "
+                       f"mean x {len(parts)} / {cores}"),
+            "instance_iter_per_s": k_int * len(parts) / batch_step,
+            "candidates_per_s": len(pick) * 64 / sum(tc for _, tc in res) * cores,
+            "host_cpus": cores, "host_cpu_model": host_cpu_model()}
+
+
+def c1_end_to_end(a):
+    """Set cover n=200, m=100 end to end as configured: 2,000 PDHG iterations
+    with a round of K=256 candidates every 100 (20 rounds) and the final
+    rounding.  GPU: one captured graph per round, median of 5 runs from a
+    reset after a warm-up run.  Oracle: the same loop in FP64 on one core.
+    Both incumbents against the exact optimum (HiGHS milp)."""
+    import torch
+    from scipy.optimize import Bounds, LinearConstraint, milp
+    from paper_2510_27117_amd import gfors, instances
+    from oracle import gfors_oracle as O
+    bip = instances.workload("setcover_small", seed=a.seed)
+    G = gfors.Problem(bip, gfors.default_params(k_int=100, K_max=256))
+    G.run_rounds(20, 256, True)
+    G.final_round()
+    G.synchronize()
+    ms = []
+    for _ in range(5):
+        G.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(G.stream)
+        G.run_rounds(20, 256, True)
+        G.final_round()
+        e1.record(G.stream)
+        G.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    bg = G.best(0)
+    G.close()
+    t0 = time.perf_counter()
+    inc, _, _, _ = O.run_gfors(bip, O.Params(k_int=100), 2000, 256)
+    t_or = time.perf_counter() - t0
+    A = np.zeros((bip.m1, bip.n))
+    rows = np.repeat(np.arange(bip.m1), np.diff(np.asarray(bip.A.row_ptr)))
+    A[rows, np.asarray(bip.A.col)] = bip.A.values()
+    res = milp(np.asarray(bip.c, dtype=np.float64), constraints=LinearConstraint(A, lb=np.asarray(bip.b, float)),
+               integrality=np.ones(bip.n), bounds=Bounds(0, 1))
+    zopt = int(round(res.fun)) if res.success else None
+    gap = (lambda z: round((z - zopt) / abs(zopt), 5) if (z is not None and zopt) else None)
+    return {"workload": "set cover n=200, m=100 (density 0.05 + forced cover), 2,000 iterations, "
+                        "20 rounds x K=256 + final rounding",
+            "gpu_ms_end_to_end": round(float(np.median(ms)), 3),
+            "gpu_pdhg_iter_per_s": round(2000 / (float(np.median(ms)) / 1e3), 1),
+            "gpu_candidates_per_s": round(20 * 256 / (float(np.median(ms)) / 1e3), 1),
+            "gpu_z": bg["z"] if bg["found"] else None, "gpu_gap_to_optimum": gap(bg["z"] if bg["found"] else None),
+            "cpu_oracle": {"s_end_to_end": round(t_or, 3), "cores": 1, "kind": "oracle",
+                           "z": inc.z, "gap_to_optimum": gap(inc.z)},
+            "milp_optimum": zopt}
+
+
+SUB_STEPS = {"knapsack_batch": (512, 50), "ufl_mono": (1024, 200)}
+
+
+def sub_records(a, subs, pre):
+    """Compact records of further workloads (same measurement as the main
+    line, fewer steps): the configured small set cover end to end, the
+    knapsack batch and facility location under the monotone relaxation."""
+    import argparse as _ap
+    out = {}
+    keep = ("value", "unit", "ms_per_step", "candidates_per_s", "instance_iter_per_s", "config",
+            "roofline", "eval_alu", "kernels", "time_to_incumbent", "batched_vs_sequential",
+            "cpu_baseline", "preprocess_s", "generate_s")
+    for w in subs:
+        if w == "setcover_small_e2e":
+            out[w] = c1_end_to_end(a)
+            continue
+        if w not in SUB_STEPS:
+            raise SystemExit(f"--sub: unknown workload {w}")
+        b = _ap.Namespace(**vars(a))
+        b.workload, b.steps, b.warmup, b.tti_seeds, b.seq_sample, b.launch_cfg = w, 5, 2, "", 4, None
+        b.K, b.tti_rounds = SUB_STEPS[w]
+        b.pre_baseline = pre.get(w)
+        r = run_workload(b)
+        rec = {k: r[k] for k in keep if k in r}
+        if r.get("sampler_alu"):
+            rec["sampler_alu_frac"] = r["sampler_alu"]["frac"]
+        out[w] = rec
+    return out
 
 
 def batched_tti(G, bip, R, times):
@@ -394,8 +543,13 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
               f"multi-GPU path.", file=sys.stderr)
         sys.exit(2)
+    subs = [w for w in a.sub.split(",") if w.strip()] if (a.sub and a.workload == "setcover_large") else []
+    # CPU baselines that fork a process pool run before anything touches the GPU
+    pre = {}
+    if "knapsack_batch" in subs and not a.no_cpu_baseline:
+        from paper_2510_27117_amd import instances
+        pre["knapsack_batch"] = cpu_baseline_pool(instances.knapsack_batch(512, a.seed), a.k_int)
     import torch
-    from paper_2510_27117_amd import gfors, instances
 
     if a.calib_copy:
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
@@ -407,6 +561,17 @@ def main():
     if a.workload == "ufl_learned":
         print(json.dumps(learned_experiment(a)))
         return
+    out = run_workload(a)
+    if subs:
+        out["sub_records"] = sub_records(a, subs, pre)
+    print(json.dumps(out))
+
+
+def run_workload(a):
+    """One workload: warm-up, the timed steps, per-kernel rooflines,
+    time-to-incumbent and the CPU oracle baseline.  Returns the record."""
+    import torch
+    from paper_2510_27117_amd import gfors, instances
     t0 = time.perf_counter()
     tu = None
     mono = None
@@ -431,6 +596,10 @@ def main():
         raise SystemExit("--launch-cfg takes 8 integers")
     prm = gfors.default_params(k_int=a.k_int, K_max=max(a.K, 1024),
                                autotune=0 if pinned else 1)
+    if mono is not None:
+        # every candidate is repaired on the device before evaluation: the
+        # relaxed rows follow the original inequality rows
+        prm.repair_row0 = mono.source.m1
     t0 = time.perf_counter()
     G = gfors.Problem(bip, prm)
     t_pre = time.perf_counter() - t0
@@ -493,6 +662,9 @@ def main():
         pass
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": ("rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel on the same workload, K "
+                                   "and launch shape, taken from profiles/hbm_traffic.json (not measured in this run)"
+                                   if traffic is not None else None),
                 "algorithmic_bytes_per_launch": kb[dom], "avg_launch_ms": avg_ms}
     # the sampler is integer-ALU bound (Philox): its generator calls per second
     # at the measured state (fractional variables x K/4 calls per launch)
@@ -572,7 +744,7 @@ def main():
 
     base = None
     if not a.no_cpu_baseline:
-        base = cpu_baseline(bip, a.k_int, a.K)
+        base = a.pre_baseline if getattr(a, "pre_baseline", None) else cpu_baseline(bip, a.k_int, a.K)
 
     nnzK = (0 if bip.A is None else bip.A.nnz) + (0 if bip.B is None else bip.B.nnz)
     out = {
@@ -598,12 +770,15 @@ def main():
         G.final_round()
         b = G.best(0)
         if b["found"]:
-            xr = mono.repair(b["x"]).astype(np.int64)
+            # candidates were repaired on the device, so the incumbent is a
+            # point of the original problem; checked here on its rows
+            xr = b["x"].astype(np.int64)
             orig = mono.source
             viol = int(np.sum(_csr_dot(orig.A, xr) < orig.b)) if orig.A is not None else 0
             viol += int(np.sum(_csr_dot(orig.B, xr) != orig.d)) if orig.B is not None else 0
-            tti["repaired"] = {"z_relaxed": int(b["z"]), "z_original": int(orig.c @ xr),
-                               "violated_original_rows": viol}
+            tti["incumbent_original"] = {"z": int(b["z"]), "z_recomputed": int(orig.c @ xr),
+                                         "violated_original_rows": viol,
+                                         "repair": "every candidate, on the device, before evaluation"}
     if tu is not None:
         out["config"]["objective_constant"] = int(tu.constant)
         if tti.get("z_final") is not None:
@@ -611,8 +786,8 @@ def main():
     if bip.num_instances > 1:
         out["instance_iter_per_s"] = round(iters_per_s * bip.num_instances, 1)
         out["batched_vs_sequential"] = seq
-    print(json.dumps(out))
     G.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -81,7 +81,22 @@ typedef struct {
  *                is at least half full and every coefficient has at most 3
  *                signed base-256 digits (results identical to the row-by-row
  *                sums); 0: always row by row.  The workspace grows by
- *                3 (2 nnz(A,B) + 48 (m1 + m2)) bytes when 1. */
+ *                3 (2 nnz(A,B) + 48 (m1 + m2)) bytes when 1.
+ *   repair_row0  -1: off.  Otherwise the inequality rows [repair_row0, m1) are
+ *                set-partitioning rows relaxed from "= 1" to ">= 1" (monotone
+ *                relaxation, Sec. 2.4), and every sampled candidate is repaired
+ *                on the device before it is evaluated: in each such row only the
+ *                cheapest set variable (lowest c, then lowest index) stays set.
+ *                Violation counts, objectives and the incumbent are then those
+ *                of the repaired candidates; they equal the evaluation on the
+ *                original rows "= 1" (after the repair a row holds at most one
+ *                set variable, so ">= 1" holds iff "= 1" does).  Checked at
+ *                creation (E_ARG otherwise): one instance, Q = 0, each row
+ *                non-empty with all coefficients +1, distinct columns and
+ *                b = 1, each of its variables with c >= 0, in no other such row,
+ *                in no equality row and with no positive coefficient in rows
+ *                [0, repair_row0).  The workspace grows by 4 (nnz(A,B) + m1 + 1)
+ *                bytes when >= 0. */
 typedef struct {
     double sigma, tau1, tau2;
     double rho_min, rho_max, rho_T, rho_p, rho_delta;
@@ -89,6 +104,7 @@ typedef struct {
     double x0;
     uint64_t seed;
     int32_t eval_mfma;
+    int64_t repair_row0;
 } gfors_params;
 
 void gfors_default_params(gfors_params *p);
@@ -331,23 +347,29 @@ int gfors_gnn_get_grad(gfors_gnn *G, float *host);
 int gfors_gnn_set_grad(gfors_gnn *G, const float *host);
 
 /* ---------------------------------------------------------------------------
- * TU reformulation (Theorem of Sec. 2.4.1), host only, for pivot blocks B_JI
- * that are a signed identity (each pivot equality row r holds its pivot column
- * p with coefficient +-1 and no other pivot column) and Q = 0.  With
- * x_p = s_p + S_p x_Ibar (s_p = b_rp d_r, S_p = -b_rp B_{r,Ibar}) it forms
+ * TU reformulation (Theorem of Sec. 2.4.1), host only.  pivots[r] names the
+ * pivot column of equality row r (-1 keeps row r); J = the pivot rows, I =
+ * their pivot columns.  B_J must be totally unimodular and B_JI invertible.
+ * With x_I = s + S x_Ibar (s = B_JI^{-1} d_J, S = -B_JI^{-1} B_JIbar, computed
+ * exactly in integers: read off the rows when B_JI is a signed identity, else
+ * by Gauss-Jordan elimination on B_J, whose pivots are then +-1) it forms
+ *   Q' = S^T Q_II S + S^T Q_IIbar + Q_IIbar^T S + Q_IbarIbar,
  *   A' = A_.I S + A_.Ibar, b' = b - A_.I s, B' = B_JbarI S + B_JbarIbar,
- *   d' = d_Jbar - B_JbarI s, c' = S^T c_I + c_Ibar, constant c'_0 = <c_I, s>,
+ *   d' = d_Jbar - B_JbarI s, c' = 2 S^T Q_II s + 2 Q_IIbar^T s + S^T c_I + c_Ibar,
+ *   constant c'_0 = <s, Q_II s> + <c_I, s>  (Q symmetric, full storage, or NULL),
  * and appends the bound rows S_p x >= -s_p (all pivots, in pivot order) then
  * -S_p x >= s_p - 1, leaving out a bound row that every point of [0,1]^n'
- * satisfies.  Kept variables keep their relative order.
+ * satisfies.  Kept variables keep their relative order.  S is stored
+ * explicitly (sparse), not as a factorisation of B_JI.
  *   pivots  int64[m2]: pivot column of equality row r, or -1 to keep row r.
- * Errors: E_ARG (pivot coefficient not +-1, column pivot of two rows, block
- * not a signed identity, Q != 0, int32 overflow of a coefficient). */
+ * Errors: E_ARG (bad CSR, pivot out of range, column pivot of two rows, B_JI
+ * singular, a pivot entry other than +-1 in the elimination (B_J not TU), an
+ * int32 overflow of a reformulated coefficient). */
 typedef struct gfors_tu gfors_tu;
 int gfors_tu_create(const gfors_csr *A, const int64_t *b, const gfors_csr *B, const int64_t *d,
                     const gfors_csr *Q, const int64_t *c, int64_t n, const int64_t *pivots,
                     gfors_tu **out);
-/* dims[6] = {n', m1', m2', nnz(A'), nnz(B'), c'_0}. */
+/* dims[7] = {n', m1', m2', nnz(A'), nnz(B'), c'_0, nnz(Q')}. */
 int gfors_tu_dims(gfors_tu *U, int64_t *dims);
 /* Copy the reformulated model into caller arrays sized from gfors_tu_dims
  * (row pointers int64[m+1]; any pointer may be NULL); kept_vars int64[n']
@@ -355,6 +377,9 @@ int gfors_tu_dims(gfors_tu *U, int64_t *dims);
 int gfors_tu_export(gfors_tu *U, int64_t *A_rp, int32_t *A_ci, int32_t *A_val, int64_t *b,
                     int64_t *B_rp, int32_t *B_ci, int32_t *B_val, int64_t *d, int64_t *c,
                     int64_t *kept_vars);
+/* Q' in full symmetric CSR (row pointers int64[n'+1], columns and values of
+ * nnz(Q') entries); nothing is written when Q' = 0. */
+int gfors_tu_export_q(gfors_tu *U, int64_t *Q_rp, int32_t *Q_ci, int32_t *Q_val);
 /* x_full (uint8[n]) from x_reduced (uint8[n']): x_I = s + S x_Ibar; E_STATE if
  * some x_p falls outside {0,1} (the reduced point violates a bound row). */
 int gfors_tu_recover(gfors_tu *U, const uint8_t *x_reduced, uint8_t *x_full);

@@ -155,6 +155,9 @@ struct gfors_problem {
     int *colT0 = nullptr;        // first row of a variable whose rows are one contiguous range, else -1
     int *primal_order = nullptr; // variables, most rows first (block-per-variable primal)
     int heavy_rows = 0, heavy_cols = 0;   // rows / variables with kHeavyLen+ entries
+    // node classes of the learned proposal's messages (prefixes of dual_order /
+    // primal_order): kGnnHeavyLen+ entries, then more than kGnnShortLen
+    int gnn_rh = 0, gnn_rm = 0, gnn_ch = 0, gnn_cm = 0;
     double *pv = nullptr, *pu = nullptr, *pw = nullptr, *part = nullptr, *res = nullptr;
     double *dnorm = nullptr;
     // column-sliced copies for the XCD-sliced SpMV (see k_spmv_part)
@@ -186,6 +189,10 @@ struct gfors_problem {
 
     // device whose static workspace holds this problem (gfors_create_problem_static), else -1
     int static_dev = -1;
+    // relaxed set-partitioning rows repaired on the device (gfors_params.repair_row0):
+    // per row, its variables in (cost, index) order
+    int n_rep = 0;
+    int *rep_rp = nullptr, *rep_var = nullptr;
 
     // graphs: key = (K, parity)
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -315,6 +322,7 @@ void gfors_default_params(gfors_params *p) {
     p->x0 = 0.0;
     p->seed = 0;
     p->eval_mfma = 1;
+    p->repair_row0 = -1;
 }
 
 const char *gfors_last_error(void) { return g_err.c_str(); }
@@ -385,6 +393,8 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->primal_order = cv.take<int>(n);
     P->cover_ids = cv.take<int>(b.et);
     P->general_ids = cv.take<int>(b.et);
+    P->rep_rp = cv.take<int>(prm->repair_row0 >= 0 ? m1 + 1 : 1);
+    P->rep_var = cv.take<int>(prm->repair_row0 >= 0 ? nnzK : 1);
     P->mf_cap = prm->eval_mfma && m > 0 ? mf_digit_cap(nnzK, m) : 0;
     P->mf_dig = cv.take<int8_t>(P->mf_cap);
     P->mf_off = cv.take<int64_t>(b.et);
@@ -504,6 +514,8 @@ void gfors_destroy_problem(gfors_problem *P) {
 
 static int device_norms(gfors_problem *P);
 static int autotune(gfors_problem *P);
+static int setup_repair(gfors_problem *P, const gfors_csr *A, const int64_t *b, const gfors_csr *B,
+                        const gfors_csr *Q, const int64_t *c);
 
 int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *B,
                          const int64_t *d, const gfors_csr *Q, const int64_t *c, int64_t n,
@@ -1105,6 +1117,15 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         if ((rc = upload(s, P->primal_order, ordT.data(), n))) return rc;
         P->heavy_cols = 0;
         while (P->heavy_cols < n && rpT[ordT[P->heavy_cols] + 1] - rpT[ordT[P->heavy_cols]] >= kHeavyLen) ++P->heavy_cols;
+        auto classes = [](const std::vector<int> &o, const std::vector<int> &ptr, int64_t cnt, int &h, int &md) {
+            int64_t k = 0;
+            while (k < cnt && ptr[o[k] + 1] - ptr[o[k]] >= kGnnHeavyLen) ++k;
+            h = static_cast<int>(k);
+            while (k < cnt && ptr[o[k] + 1] - ptr[o[k]] > kGnnShortLen) ++k;
+            md = static_cast<int>(k) - h;
+        };
+        classes(ord, rp, m, P->gnn_rh, P->gnn_rm);
+        classes(ordT, rpT, n, P->gnn_ch, P->gnn_cm);
     }
     if ((rc = upload(s, P->rowinv_d, P->rowinv.data(), m))) return rc;
     {
@@ -1242,9 +1263,53 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         P->cfg.slices_dual = kXcdSlices;
         P->cfg.lpr_dual = pick(static_cast<double>(P->nnzK) / m / kXcdSlices);
     }
+    if (prm->repair_row0 >= 0 && (rc = setup_repair(P, A, b, B, Q, c))) return rc;
     if ((rc = sync(P))) return rc;
     if (prm->autotune && (rc = autotune(P))) return rc;
     *out = guard.release();
+    return GFORS_OK;
+}
+
+// Relaxed set-partitioning rows [repair_row0, m1) (monotone relaxation,
+// Sec. 2.4): checks the conditions under which keeping one variable per row
+// maps relaxed-feasible points to feasible points of the rows "= 1" without
+// raising the objective, then uploads each row's variables in (c, index) order.
+static int setup_repair(gfors_problem *P, const gfors_csr *A, const int64_t *b, const gfors_csr *B,
+                        const gfors_csr *Q, const int64_t *c) {
+    const int64_t r0 = P->prm.repair_row0, m1 = P->m1, n = P->n;
+    if (P->T != 1) return fail(GFORS_E_ARG, "repair_row0: single-instance problems only");
+    if (r0 > m1) return fail(GFORS_E_ARG, "repair_row0 beyond the inequality rows");
+    if (Q && Q->row_ptr[Q->nrows] > 0) return fail(GFORS_E_ARG, "repair_row0 needs Q = 0");
+    std::vector<int> owner(n, -1);
+    std::vector<int> rrp(1, 0), rvar;
+    for (int64_t j = r0; j < m1; ++j) {
+        const int64_t e0 = A->row_ptr[j], e1 = A->row_ptr[j + 1];
+        if (e1 == e0 || b[j] != 1) return fail(GFORS_E_ARG, "repair row " + std::to_string(j) + ": empty or b != 1");
+        const size_t start = rvar.size();
+        for (int64_t e = e0; e < e1; ++e) {
+            const int i = A->col_idx[e];
+            if ((A->val ? A->val[e] : 1) != 1) return fail(GFORS_E_ARG, "repair row " + std::to_string(j) + ": coefficient != 1");
+            if (c[i] < 0) return fail(GFORS_E_ARG, "repair row " + std::to_string(j) + ": variable with c < 0");
+            if (owner[i] >= 0) return fail(GFORS_E_ARG, "variable " + std::to_string(i) + " in two repair rows (or twice in one)");
+            owner[i] = static_cast<int>(j);
+            rvar.push_back(i);
+        }
+        std::sort(rvar.begin() + static_cast<std::ptrdiff_t>(start), rvar.end(),
+                  [&](int a2, int b2) { return c[a2] != c[b2] ? c[a2] < c[b2] : a2 < b2; });
+        rrp.push_back(static_cast<int>(rvar.size()));
+    }
+    for (int64_t j = 0; j < r0; ++j)
+        for (int64_t e = A->row_ptr[j]; e < A->row_ptr[j + 1]; ++e)
+            if (owner[A->col_idx[e]] >= 0 && (A->val ? A->val[e] : 1) > 0)
+                return fail(GFORS_E_ARG, "a repair-row variable has a positive coefficient in inequality row " + std::to_string(j));
+    if (B)
+        for (int64_t e = 0; e < B->row_ptr[B->nrows]; ++e)
+            if (owner[B->col_idx[e]] >= 0) return fail(GFORS_E_ARG, "a repair-row variable lies in an equality row");
+    int rc;
+    if ((rc = upload(P->stream, P->rep_rp, rrp.data(), static_cast<int64_t>(rrp.size())))) return rc;
+    if (!rvar.empty() && (rc = upload(P->stream, P->rep_var, rvar.data(), static_cast<int64_t>(rvar.size())))) return rc;
+    if ((rc = sync(P))) return rc;
+    P->n_rep = static_cast<int>(m1 - r0);
     return GFORS_OK;
 }
 
@@ -1580,6 +1645,8 @@ static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *t
     }
 }
 
+static void enqueue_eval(gfors_problem *P, int K, int threshold, KTimer *tm, int trigger);
+
 static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override, int threshold,
                                 KTimer *tm = nullptr, int trigger = 1) {
     hipStream_t s = P->stream;
@@ -1589,7 +1656,18 @@ static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override
     launch_sample(s, W, P->obj64, p, P->cost, P->X, P->st, P->d_inst_var0, P->d_inst_nvar,
                   P->zpart, K, static_cast<uint32_t>(P->prm.seed & 0xffffffffu),
                   static_cast<uint32_t>(P->prm.seed >> 32), P->ctr, threshold, P->xkind);
+    if (P->n_rep > 0)
+        launch_mono_repair(s, P->n_rep, W, K, P->rep_rp, P->rep_var, P->cost, P->X, P->xkind, P->zpart);
     TE(2);
+    enqueue_eval(P, K, threshold, tm, trigger);
+}
+
+// EvalBest (Sec. 3) of the K candidates in P->X (objective's linear part in
+// the per-tile partials): constraint rows, quadratic objective, reduction,
+// incumbent update, x_best.
+static void enqueue_eval(gfors_problem *P, int K, int threshold, KTimer *tm, int trigger) {
+    hipStream_t s = P->stream;
+    const int W = K / 64;
     TB(3);
     launch_eval_cover(s, P->n_cover, P->cover_ids, P->et, P->rows, P->rkind, P->rp, P->ci, P->X,
                       P->xkind, W, P->vpart, K);
@@ -2036,10 +2114,12 @@ int gnn_run(gfors_gnn *G, gfors_problem *P, const float *x, const float *y, cons
         const uint16_t *wfc = G->wf + static_cast<int64_t>(2 * l) * 128 * 64;
         const uint16_t *wfv = G->wf + static_cast<int64_t>(2 * l + 1) * 128 * 64;
         // constraint side: Hc = relu([Hc | E Hv] W + bc)
-        launch_gnn_spmm(s, true, true, 0, m, P->rp, P->ci, val, P->rowinv32, a.Hv[l], a.Sc[l]);
+        launch_gnn_spmm(s, true, true, 0, m, P->dual_order, P->gnn_rh, P->gnn_rm, P->rp, P->ci, val,
+                        P->rowinv32, a.Hv[l], a.Sc[l]);
         launch_gnn_dense_fwd(s, m, a.Hc[l], a.Sc[l], wfc, lay + 2 * 4096, a.Hc[l + 1]);
         // variable side: Hv = relu([Hv | E^T Hc] W + bv)
-        launch_gnn_spmm(s, false, true, 0, n, P->rpT, P->ciT, valT, P->rowinv32, a.Hc[l + 1], a.Sv[l]);
+        launch_gnn_spmm(s, false, true, 0, n, P->primal_order, P->gnn_ch, P->gnn_cm, P->rpT, P->ciT, valT,
+                        P->rowinv32, a.Hc[l + 1], a.Sv[l]);
         launch_gnn_dense_fwd(s, n, a.Hv[l], a.Sv[l], wfv, lay + 8256 + 2 * 4096, a.Hv[l + 1]);
     }
     launch_gnn_out(s, n, a.Hv[kGnnL], G->theta, logit_out ? logit_out : a.logit, p_out ? p_out : a.p,
@@ -2058,12 +2138,14 @@ int gnn_run(gfors_gnn *G, gfors_problem *P, const float *x, const float *y, cons
         launch_gnn_mask(s, n, a.dHv, a.Hv[l + 1], a.dZ, G->part, kGnnMaxParts, glay + 8256 + 2 * 4096);
         launch_gnn_wgrad(s, n, a.Hv[l], a.Sv[l], a.dZ, G->part, kGnnMaxParts, glay + 8256, glay + 8256 + 4096);
         launch_gnn_dense_bwd_in(s, n, a.dZ, wbv, a.dHvp, a.dS, 0);
-        launch_gnn_spmm(s, true, false, 2, m, P->rp, P->ci, val, P->rowinv32, a.dS, a.dHc);
+        launch_gnn_spmm(s, true, false, 2, m, P->dual_order, P->gnn_rh, P->gnn_rm, P->rp, P->ci, val,
+                        P->rowinv32, a.dS, a.dHc);
         // constraint side of round l
         launch_gnn_mask(s, m, a.dHc, a.Hc[l + 1], a.dZ, G->part, kGnnMaxParts, glay + 2 * 4096);
         launch_gnn_wgrad(s, m, a.Hc[l], a.Sc[l], a.dZ, G->part, kGnnMaxParts, glay, glay + 4096);
         launch_gnn_dense_bwd_in(s, m, a.dZ, wbc, a.dHcp, a.dS, 0);
-        launch_gnn_spmm(s, false, false, 2, n, P->rpT, P->ciT, valT, P->rowinv32, a.dS, a.dHvp);
+        launch_gnn_spmm(s, false, false, 2, n, P->primal_order, P->gnn_ch, P->gnn_cm, P->rpT, P->ciT, valT,
+                        P->rowinv32, a.dS, a.dHvp);
         std::swap(a.dHv, a.dHvp);
         std::swap(a.dHc, a.dHcp);
     }

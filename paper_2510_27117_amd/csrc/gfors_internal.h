@@ -173,6 +173,12 @@ void launch_res_vars(hipStream_t s, const Tiles &vt, const int *rpQ, const int *
 
 // --------------------------------------------------------- sampling / eval
 void launch_philox_peak(hipStream_t s, int blocks, int iters, uint32_t *sink);
+// Monotone relaxation repair (Sec. 2.4) of the sampled candidates: in each of
+// the nrows relaxed set-partitioning rows (variables var[rp[r]..rp[r+1]) in
+// (cost, index) order) only the first set variable of every candidate stays
+// set; cleared costs are taken off the candidates' objectives in zpart[0..K).
+void launch_mono_repair(hipStream_t s, int nrows, int W, int K, const int *rp, const int *var,
+                        const int64_t *cost, uint64_t *X, uint8_t *xkind, int64_t *zpart);
 void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64_t *cost,
                    uint64_t *X, const Tiles &st, const int64_t *inst_var0,
                    const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,

@@ -29,13 +29,17 @@ constexpr int kGnnOffwo = kGnnOffLayer + kGnnL * kGnnLayerSize;   // 50176
 constexpr int kGnnOffbo = kGnnOffwo + 64;                          // 50240
 constexpr int kGnnNumParams = kGnnOffbo + 1;                       // 50241
 constexpr int kGnnMaxParts = 256;
+constexpr int kGnnHeavyLen = 1024;   // SpMM node classes: heavy from this many entries
+constexpr int kGnnShortLen = 16;     // short up to this many
 
 void launch_gnn_embed(hipStream_t s, int64_t n, int64_t m, int m1, const float *x, const float *y,
                       const float *ct, const float *rt, float ictmax, float irtmax,
                       const float *theta, uint16_t *Hv, uint16_t *Hc);
+// nodes in `order` (longest first): the first nheavy have >= 1024 entries, the
+// next nmedium more than 16, the rest at most 16
 void launch_gnn_spmm(hipStream_t s, bool rows, bool in_bf16, int out_mode, int64_t nrows,
-                     const int *rp, const int *ci, const int *val, const float *rowinv,
-                     const void *in, void *out);
+                     const int *order, int nheavy, int nmedium, const int *rp, const int *ci,
+                     const int *val, const float *rowinv, const void *in, void *out);
 void launch_gnn_dense_fwd(hipStream_t s, int64_t N, const uint16_t *A1, const uint16_t *A2,
                           const uint16_t *BT, const float *bias, uint16_t *out);
 void launch_gnn_dense_bwd_in(hipStream_t s, int64_t N, const uint16_t *dZ, const uint16_t *Wrm,

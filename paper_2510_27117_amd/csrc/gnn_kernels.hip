@@ -1,10 +1,13 @@
 // Learned sampling proposal: a bipartite message-passing network over the
 // constraint graph (variables <-> rows), trained and run on the GPU.  Dense
 // 64-wide layers run on MFMA (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32
-// accumulation); messages are sparse-times-dense products, one wavefront per
-// node with lane = feature (each neighbour's 64 BF16 features are one 128-byte
-// line).  Network, features and loss are defined in gnn.h.
+// accumulation); messages are sparse-times-dense products gathering each
+// neighbour's 64 features (one 128-byte line in BF16), with nodes split into
+// heavy / medium / short classes by degree.  Network, features and loss are
+// defined in gnn.h.
 #include "gnn.h"
+
+#include <algorithm>
 
 namespace gfors {
 
@@ -66,38 +69,208 @@ k_gnn_embed(int64_t n, int64_t m, int m1, const float *__restrict__ x, const flo
 //   ROWS = false: CSR of [A; B]^T (r = variable, col = row j,        rowinv[j])
 // IN_BF16: input features BF16 (else FP32); OUT: 0 store BF16, 1 store FP32,
 // 2 add into FP32.
+//
+// Nodes come in `order`, longest first, in three classes by entry count:
+//   heavy  (>= kGnnHeavy)  a workgroup of 8 wavefronts per node;
+//   medium (> kGnnShort)   one wavefront per node;
+//   short                  16 lanes per node (four nodes per wavefront).
+// In the heavy and medium kernels a lane handles features 4f..4f+3 (f = lane
+// & 15) of entry slot q = lane >> 4, so one load instruction gathers four
+// neighbours' feature rows; eight such loads are issued before any is used.
+// Slots (and wavefronts) are then added in a fixed order.
+struct Feat4 {
+    float v[4];
+};
+
+template <bool IN_BF16>
+__device__ __forceinline__ Feat4 load_feat4(const void *__restrict__ in, int64_t row, int f) {
+    Feat4 r;
+    if (IN_BF16) {
+        const uint2 w = reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(in) + row * kGnnH)[f];
+        r.v[0] = __uint_as_float(w.x << 16);
+        r.v[1] = __uint_as_float(w.x & 0xFFFF0000u);
+        r.v[2] = __uint_as_float(w.y << 16);
+        r.v[3] = __uint_as_float(w.y & 0xFFFF0000u);
+    } else {
+        const float4 w = reinterpret_cast<const float4 *>(static_cast<const float *>(in) + row * kGnnH)[f];
+        r.v[0] = w.x;
+        r.v[1] = w.y;
+        r.v[2] = w.z;
+        r.v[3] = w.w;
+    }
+    return r;
+}
+
+template <int OUT>
+__device__ __forceinline__ void store_feat4(void *__restrict__ out, int64_t row, int f, const float *a) {
+    if (OUT == 0) {
+        uint2 w;
+        w.x = static_cast<uint32_t>(f2bf(a[0])) | (static_cast<uint32_t>(f2bf(a[1])) << 16);
+        w.y = static_cast<uint32_t>(f2bf(a[2])) | (static_cast<uint32_t>(f2bf(a[3])) << 16);
+        reinterpret_cast<uint2 *>(static_cast<uint16_t *>(out) + row * kGnnH)[f] = w;
+    } else {
+        float4 *o = reinterpret_cast<float4 *>(static_cast<float *>(out) + row * kGnnH) + f;
+        float4 w = make_float4(a[0], a[1], a[2], a[3]);
+        if (OUT == 2) {
+            const float4 v = *o;
+            w.x += v.x;
+            w.y += v.y;
+            w.z += v.z;
+            w.w += v.w;
+        }
+        *o = w;
+    }
+}
+
+// Entries [e0, e1) of node r, slot q of this lane, blocks of 32 entries
+// b = b0, b0 + bstep, ...: acc += E_e in[col_e] for e = 32 b + 4 u + q.
+template <bool ROWS, bool IN_BF16>
+__device__ __forceinline__ void gnn_gather_slots(int64_t r, int e0, int e1, int b0, int bstep, int q,
+                                                 int f, const int *__restrict__ ci,
+                                                 const int *__restrict__ val,
+                                                 const float *__restrict__ rowinv,
+                                                 const void *__restrict__ in, float *acc) {
+    const float rs = ROWS ? rowinv[r] : 1.f;
+    for (int eb = e0 + 32 * b0; eb < e1; eb += 32 * bstep) {
+        int c[8];
+        float a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = eb + 4 * u + q;
+            const bool ok = e < e1;
+            const int ee = ok ? e : e0;
+            c[u] = ci[ee];
+            a[u] = ok ? (val ? static_cast<float>(val[ee]) : 1.f) : 0.f;
+        }
+        Feat4 h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (!ROWS) a[u] *= rowinv[c[u]];
+            h[u] = load_feat4<IN_BF16>(in, c[u], f);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float w = ROWS ? a[u] * rs : a[u];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = fmaf(w, h[u].v[k], acc[k]);
+        }
+    }
+}
+
+template <bool ROWS, bool IN_BF16, int OUT>
+__global__ void __launch_bounds__(512)
+k_gnn_spmm_heavy(int nheavy, const int *__restrict__ order, const int *__restrict__ rp,
+                 const int *__restrict__ ci, const int *__restrict__ val,
+                 const float *__restrict__ rowinv, const void *__restrict__ in,
+                 void *__restrict__ out) {
+    __shared__ float red[8][kGnnH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, f = lane & 15;
+    for (int k = blockIdx.x; k < nheavy; k += gridDim.x) {
+        const int64_t r = order[k];
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        gnn_gather_slots<ROWS, IN_BF16>(r, rp[r], rp[r + 1], wave, 8, q, f, ci, val, rowinv, in, acc);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[t] += __shfl_xor(acc[t], 16, 64);
+            acc[t] += __shfl_xor(acc[t], 32, 64);
+        }
+        if (q == 0) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) red[wave][4 * f + t] = acc[t];
+        }
+        __syncthreads();
+        if (wave == 0 && q == 0) {
+            float s4[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                float v = red[0][4 * f + t];
+                for (int w = 1; w < 8; ++w) v += red[w][4 * f + t];
+                s4[t] = v;
+            }
+            store_feat4<OUT>(out, r, f, s4);
+        }
+        __syncthreads();
+    }
+}
+
 template <bool ROWS, bool IN_BF16, int OUT>
 __global__ void __launch_bounds__(256)
-k_gnn_spmm(int64_t nrows, const int *__restrict__ rp, const int *__restrict__ ci,
-           const int *__restrict__ val, const float *__restrict__ rowinv,
-           const void *__restrict__ in, void *__restrict__ out) {
+k_gnn_spmm_medium(int k0, int k1, const int *__restrict__ order, const int *__restrict__ rp,
+                  const int *__restrict__ ci, const int *__restrict__ val,
+                  const float *__restrict__ rowinv, const void *__restrict__ in,
+                  void *__restrict__ out) {
     const int lane = threadIdx.x & 63;
-    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-    for (int64_t r = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6; r < nrows;
-         r += nw) {
-        float acc = 0.f;
-        const int e1 = rp[r + 1];
-        for (int e = rp[r]; e < e1; ++e) {
-            const int c = ci[e];
-            const float a = (val ? static_cast<float>(val[e]) : 1.f) * (ROWS ? rowinv[r] : rowinv[c]);
-            const float h = IN_BF16 ? bf2f(static_cast<const uint16_t *>(in)[static_cast<int64_t>(c) * kGnnH + lane])
-                                    : static_cast<const float *>(in)[static_cast<int64_t>(c) * kGnnH + lane];
-            acc = fmaf(a, h, acc);
+    const int q = lane >> 4, f = lane & 15;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    for (int k = k0 + static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6); k < k1; k += nw) {
+        const int64_t r = order[k];
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        gnn_gather_slots<ROWS, IN_BF16>(r, rp[r], rp[r + 1], 0, 1, q, f, ci, val, rowinv, in, acc);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[t] += __shfl_xor(acc[t], 16, 64);
+            acc[t] += __shfl_xor(acc[t], 32, 64);
         }
-        const int64_t o = r * kGnnH + lane;
-        if (OUT == 0) static_cast<uint16_t *>(out)[o] = f2bf(acc);
-        else if (OUT == 1) static_cast<float *>(out)[o] = acc;
-        else static_cast<float *>(out)[o] += acc;
+        if (q == 0) store_feat4<OUT>(out, r, f, acc);
+    }
+}
+
+template <bool ROWS, bool IN_BF16, int OUT>
+__global__ void __launch_bounds__(256)
+k_gnn_spmm_short(int k0, int k1, const int *__restrict__ order, const int *__restrict__ rp,
+                 const int *__restrict__ ci, const int *__restrict__ val,
+                 const float *__restrict__ rowinv, const void *__restrict__ in,
+                 void *__restrict__ out) {
+    const int f = threadIdx.x & 15;
+    const int ng = (gridDim.x * blockDim.x) >> 4;
+    for (int k = k0 + static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 4); k < k1; k += ng) {
+        const int64_t r = order[k];
+        const int e0 = rp[r], e1 = rp[r + 1];
+        const float rs = ROWS ? rowinv[r] : 1.f;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int eb = e0; eb < e1; eb += 4) {
+            int c[4];
+            float a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = eb + u;
+                const bool ok = e < e1;
+                const int ee = ok ? e : e0;
+                c[u] = ci[ee];
+                a[u] = ok ? (val ? static_cast<float>(val[ee]) : 1.f) : 0.f;
+            }
+            Feat4 h[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] *= ROWS ? rs : rowinv[c[u]];
+                h[u] = load_feat4<IN_BF16>(in, c[u], f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] = fmaf(a[u], h[u].v[t], acc[t]);
+        }
+        store_feat4<OUT>(out, r, f, acc);
     }
 }
 
 void launch_gnn_spmm(hipStream_t s, bool rows, bool in_bf16, int out_mode, int64_t nrows,
-                     const int *rp, const int *ci, const int *val, const float *rowinv,
-                     const void *in, void *out) {
+                     const int *order, int nheavy, int nmedium, const int *rp, const int *ci,
+                     const int *val, const float *rowinv, const void *in, void *out) {
     if (nrows <= 0) return;
-    int64_t blocks = (nrows * 64 + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
-#define GF_SP(R, IB, O) k_gnn_spmm<R, IB, O><<<static_cast<int>(blocks), 256, 0, s>>>(nrows, rp, ci, val, rowinv, in, out)
+    const int k1 = nheavy, k2 = nheavy + nmedium, k3 = static_cast<int>(nrows);
+    const int bh = std::min(nheavy, 1024);
+    int64_t bm = (static_cast<int64_t>(nmedium) * 64 + 255) / 256;
+    if (bm > 8192) bm = 8192;
+    int64_t bs = (static_cast<int64_t>(k3 - k2) * 16 + 255) / 256;
+    if (bs > 16384) bs = 16384;
+#define GF_SP(R, IB, O)                                                                                          \
+    do {                                                                                                         \
+        if (bh > 0) k_gnn_spmm_heavy<R, IB, O><<<bh, 512, 0, s>>>(k1, order, rp, ci, val, rowinv, in, out);      \
+        if (bm > 0) k_gnn_spmm_medium<R, IB, O><<<static_cast<int>(bm), 256, 0, s>>>(k1, k2, order, rp, ci, val, rowinv, in, out); \
+        if (bs > 0) k_gnn_spmm_short<R, IB, O><<<static_cast<int>(bs), 256, 0, s>>>(k2, k3, order, rp, ci, val, rowinv, in, out); \
+    } while (0)
 #define GF_SP2(R, IB) if (out_mode == 0) GF_SP(R, IB, 0); else if (out_mode == 1) GF_SP(R, IB, 1); else GF_SP(R, IB, 2)
     if (rows) { if (in_bf16) { GF_SP2(true, true); } else { GF_SP2(true, false); } }
     else { if (in_bf16) { GF_SP2(false, true); } else { GF_SP2(false, false); } }

@@ -206,6 +206,68 @@ void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64
         k_sample<int32_t><<<st.count, 256, lds, s>>>(p, cost, X, W, st.inst, st.b0, st.b1, inst_var0, inst_nvar, zpart, K, key0, key1, ctr, threshold_mode, xkind, wdiv, nbuf);
 }
 
+// Monotone relaxation repair (Sec. 2.4).  Thread (row r, word w) walks the
+// row's variables in (cost, index) order with a mask of the candidates that
+// already hold a set variable in this row; a later set bit of such a candidate
+// is cleared and its cost added to the candidate's LDS sum.  Each variable lies
+// in one row, so every (variable, word) is read and written by one thread.
+// The LDS sums are then taken off the sampler's partial objectives (one
+// 64-bit atomic per candidate and workgroup; integer sums, order-free).
+__global__ void __launch_bounds__(256)
+k_mono_repair(int nrows, int W, int K, const int *__restrict__ rp, const int *__restrict__ var,
+              const int64_t *__restrict__ cost, uint64_t *__restrict__ X,
+              uint8_t *__restrict__ xkind, int64_t *__restrict__ zpart) {
+    extern __shared__ unsigned long long dz[];   // [K]
+    for (int l = threadIdx.x; l < K; l += blockDim.x) dz[l] = 0ull;
+    __syncthreads();
+    const int rpb = static_cast<int>(blockDim.x) / W;
+    const int lr = static_cast<int>(threadIdx.x) / W, w = static_cast<int>(threadIdx.x) - lr * W;
+    const int r = blockIdx.x * rpb + lr;
+    if (lr < rpb && r < nrows) {
+        uint64_t keep = 0;
+        const int e0 = rp[r], e1 = rp[r + 1];
+        for (int e = e0; e < e1; e += 4) {
+            int iv[4];
+            uint64_t bits[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) iv[u] = var[min(e + u, e1 - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bits[u] = X[static_cast<int64_t>(iv[u]) * W + w];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (e + u >= e1) break;
+                const uint64_t clr = bits[u] & keep;
+                keep |= bits[u];
+                if (clr) {
+                    X[static_cast<int64_t>(iv[u]) * W + w] = bits[u] & ~clr;
+                    xkind[iv[u]] = 0;
+                    const unsigned long long cu = static_cast<unsigned long long>(cost[iv[u]]);
+                    uint64_t mk = clr;
+                    while (mk) {
+                        const int bt = __builtin_ctzll(mk);
+                        mk &= mk - 1;
+                        atomicAdd(&dz[64 * w + bt], cu);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < K; l += blockDim.x) {
+        const unsigned long long d = dz[l];
+        if (d) atomicAdd(reinterpret_cast<unsigned long long *>(zpart) + l, 0ull - d);
+    }
+}
+
+void launch_mono_repair(hipStream_t s, int nrows, int W, int K, const int *rp, const int *var,
+                        const int64_t *cost, uint64_t *X, uint8_t *xkind, int64_t *zpart) {
+    if (nrows <= 0 || W < 1 || W > 64) return;
+    const int rpb = 256 / W;
+    const int blocks = (nrows + rpb - 1) / rpb;
+    k_mono_repair<<<blocks, 256, static_cast<size_t>(K) * sizeof(unsigned long long), s>>>(
+        nrows, W, K, rp, var, cost, X, xkind, zpart);
+}
+
 // Throughput of the uniform generator alone (the sampler's ALU roofline): each
 // lane evaluates Philox4x32-10 `iters` times with the sampler's counter shape
 // (one word per lane, three wave-uniform words) and folds the outputs into a

@@ -31,7 +31,7 @@ class gfors_params(ctypes.Structure):
                 ("rho_min", c_dbl), ("rho_max", c_dbl), ("rho_T", c_dbl), ("rho_p", c_dbl),
                 ("rho_delta", c_dbl), ("k_int", c_i32), ("K_max", c_i32), ("power_iters", c_i32),
                 ("hist_cap", c_i32), ("autotune", c_i32), ("x0", c_dbl), ("seed", c_u64),
-                ("eval_mfma", c_i32)]
+                ("eval_mfma", c_i32), ("repair_row0", c_i64)]
 
 
 EXPORTS = [
@@ -45,6 +45,7 @@ EXPORTS = [
     "gfors_gnn_forward", "gfors_gnn_grad", "gfors_gnn_adam", "gfors_gnn_train_step",
     "gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad",
     "gfors_tu_create", "gfors_tu_dims", "gfors_tu_export", "gfors_tu_recover", "gfors_tu_destroy",
+    "gfors_tu_export_q",
     "gfors_tu_last_error", "gfors_mono_rows", "gfors_mono_repair", "gfors_mono_last_error",
     "gfors_philox_throughput", "gfors_eval_planes", "gfors_create_problem_static",
 ]
@@ -112,6 +113,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   c_vp, P(c_vp)]
     L.gfors_tu_dims.argtypes = [c_vp, c_vp]
     L.gfors_tu_export.argtypes = [c_vp] + [c_vp] * 10
+    L.gfors_tu_export_q.argtypes = [c_vp, c_vp, c_vp, c_vp]
     L.gfors_tu_recover.argtypes = [c_vp, c_vp, c_vp]
     L.gfors_tu_destroy.argtypes = [c_vp]
     L.gfors_tu_destroy.restype = None
@@ -623,9 +625,10 @@ class MonotoneRelaxation:
 
 
 class TUReformulation:
-    """Eliminates one pivot variable per chosen equality row (B_JI a signed
-    identity, Q = 0).  ``model`` is the reformulated BIP (instances.BIP);
-    ``constant`` is c'_0; ``recover(x_reduced)`` maps a reduced 0/1 point back."""
+    """Eliminates one pivot variable per chosen equality row (gfors_tu_create:
+    B_J totally unimodular, B_JI invertible; Q allowed).  ``model`` is the
+    reformulated BIP (instances.BIP); ``constant`` is c'_0;
+    ``recover(x_reduced)`` maps a reduced 0/1 point back."""
 
     def __init__(self, bip, pivots):
         from . import instances as _inst
@@ -639,14 +642,16 @@ class TUReformulation:
         d = np.ascontiguousarray(bip.d, dtype=np.int64)
         c = np.ascontiguousarray(bip.c, dtype=np.int64)
         h = ctypes.c_void_p()
+        Q = _csr(bip.Q, keep)
         rc = L.gfors_tu_create(ctypes.byref(A) if A else None, _ptr(b), ctypes.byref(B), _ptr(d),
-                               None, _ptr(c), int(bip.n), _ptr(piv), ctypes.byref(h))
+                               ctypes.byref(Q) if Q else None, _ptr(c), int(bip.n), _ptr(piv),
+                               ctypes.byref(h))
         if rc != GFORS_OK:
             raise GforsError(f"{_ERRS.get(rc, rc)}: {L.gfors_tu_last_error().decode()}")
         self.handle = h
-        dims = np.zeros(6, dtype=np.int64)
+        dims = np.zeros(7, dtype=np.int64)
         L.gfors_tu_dims(h, _ptr(dims))
-        n2, m1, m2, nA, nB, c0 = (int(v) for v in dims)
+        n2, m1, m2, nA, nB, c0, nQ = (int(v) for v in dims)
         Arp, Aci, Aval, bb = (np.zeros(m1 + 1, np.int64), np.zeros(max(nA, 1), np.int32),
                               np.zeros(max(nA, 1), np.int32), np.zeros(max(m1, 1), np.int64))
         Brp, Bci, Bval, dd = (np.zeros(m2 + 1, np.int64), np.zeros(max(nB, 1), np.int32),
@@ -662,6 +667,10 @@ class TUReformulation:
         if m2:
             model.B = _inst.CSR(m2, n2, Brp, Bci[:nB], Bval[:nB])
             model.d = dd[:m2]
+        if nQ:
+            Qrp, Qci, Qval = np.zeros(n2 + 1, np.int64), np.zeros(nQ, np.int32), np.zeros(nQ, np.int32)
+            L.gfors_tu_export_q(h, _ptr(Qrp), _ptr(Qci), _ptr(Qval))
+            model.Q = _inst.CSR(n2, n2, Qrp, Qci, Qval)
         self.model = model
         self.constant = c0
         self.kept = kept

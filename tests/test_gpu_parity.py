@@ -41,9 +41,20 @@ def problems():
         "maxcut": lambda: I.max_cut_er(2001, 10.0, seed=4),
         "ufl": lambda: I.facility_location(7, 23, seed=5),
         "mixed": lambda: mixed_problem(150, seed=6),
+        "tu_general": lambda: _tu_general_model(),
         "tiny1": lambda: I.from_dense([3], A=[[1]], b=[1]),
         "tiny_unconstrained": lambda: I.from_dense([-1, 2, -3]),
     }
+
+
+def _tu_general_model():
+    """2D assignment with a quadratic term after the TU reformulation whose
+    pivot block is a spanning tree of the bipartite graph (not an identity):
+    reformulated rows, bound rows, a Q' with the theorem's cross terms, and
+    an empty equality row left by the redundant column constraint."""
+    from paper_2510_27117_amd import gfors
+    P = I.assignment_qap_like(12, seed=7)
+    return gfors.TUReformulation(P, P.meta["tu_pivots"]).model
 
 
 PNAMES = list(problems().keys())
@@ -135,7 +146,7 @@ def test_sampler_bit_exact_and_eval(G, K):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["setcover_bern", "knapsack", "knapsack_long", "maxcut", "ufl", "mixed"])
+@pytest.mark.parametrize("name", ["setcover_bern", "knapsack", "knapsack_long", "maxcut", "ufl", "mixed", "tu_general"])
 def test_round_from_iterate_and_incumbent(G, name):
     """Sample from the (oracle) iterate x_k held in the GPU state, evaluate, and
     merge into the incumbent exactly as the oracle's EvalBest does."""
@@ -249,7 +260,7 @@ def test_final_rounding(G, name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["setcover_bern", "maxcut", "ufl", "mixed", "knapsack"])
+@pytest.mark.parametrize("name", ["setcover_bern", "maxcut", "ufl", "mixed", "knapsack", "tu_general"])
 def test_residuals_match_oracle(G, name):
     """Theorem 2's s^x, s^y and CheckHalt's gaps, reduced in FP64 on the device,
     against the oracle's formulas evaluated in FP64 on the very FP32 vectors the
@@ -745,3 +756,69 @@ def test_heavy_light_split(G, which):
         assert got["k"] == st.k + 1
         assert rel_inf(got["x"], ref.x) <= TOL_PDHG and rel_inf(got["y"], ref.y) <= TOL_PDHG, cfg
     prob.close()
+
+
+@pytest.mark.parametrize("K", [64, 1024])
+def test_monotone_repair_on_device(G, K):
+    """Monotone relaxation with the repair on the device (Sec. 2.4): every
+    sampled candidate of the relaxed model is repaired before it is
+    evaluated.  The repaired candidates, their violation counts and
+    objectives on the ORIGINAL problem (customer rows "= 1") and the incumbent
+    equal the oracle's monotone_repair + evaluate, bit for bit, over two
+    rounds and the final rounding."""
+    import torch
+    src = I.facility_location(7, 40, seed=5)
+    M = G.MonotoneRelaxation(src)
+    assert M.relaxed.all()
+    model = M.model
+    prm = _params(G, K_max=max(K, 1024), autotune=0)
+    prm.repair_row0 = src.m1            # the relaxed rows follow the original inequality rows
+    prob = G.Problem(model, prm)
+    try:
+        rng = np.random.default_rng(3)
+        n_f = int(src.meta["n_f"])
+        p = (0.3 + 0.6 * rng.random(model.n)).astype(np.float32)
+        p[rng.random(model.n) < 0.1] = 1.0      # all-one variables get repaired too
+        p[rng.random(model.n) < 0.1] = 0.0
+        p[:n_f] = 1.0                           # every facility open: the pair rows hold
+        inc = O.Incumbent()
+        for rnd in range(2):
+            v, z = prob.sample_eval(K, p_override=torch.from_numpy(p).cuda(), outputs=True)
+            X = O.sample_bits(p.astype(np.float64), K, 0, rnd=rnd).astype(np.int64)
+            Xr = np.array([O.monotone_repair(src, M.relaxed, x) for x in X])
+            assert np.array_equal(prob.candidates(), O.pack_bits(Xr.astype(bool))), rnd
+            vo, zo = O.evaluate(src, Xr)
+            assert np.array_equal(v.cpu().numpy()[0], vo), rnd
+            assert np.array_equal(z.cpu().numpy()[0], zo), rnd
+            assert np.any(vo == 0) and np.any(X.sum(axis=0) != Xr.sum(axis=0))
+            O.incumbent_update(inc, Xr.astype(bool), vo, zo, rnd, 0)
+            b = prob.best(0)
+            assert b["found"] and b["z"] == inc.z and b["l"] == inc.l and b["round"] == inc.rnd
+            assert np.array_equal(b["x"].astype(bool), inc.x)
+        # final rounding of an iterate whose rounded point sets several
+        # assignments per customer: repaired as well
+        x = np.where(rng.random(model.n) < 0.5, 0.75, 0.25).astype(np.float32)
+        x[:n_f] = 0.75
+        prob.set_state(x, x, np.zeros(model.m1, dtype=np.float32), np.array([0.0]), k=0, round=2, ntrig=2)
+        prob.final_round()
+        xr = O.monotone_repair(src, M.relaxed, O.round_candidate(x.astype(np.float64))[0].astype(np.int64))
+        vf, zf = O.evaluate(src, xr[None, :])
+        assert vf[0] == 0
+        O.incumbent_update(inc, xr[None, :].astype(bool), vf, zf, -1, 0)
+        b = prob.best(0)
+        assert b["z"] == inc.z and np.array_equal(b["x"].astype(bool), inc.x)
+    finally:
+        prob.close()
+
+
+def test_monotone_repair_rejects_bad_rows(G):
+    """repair_row0 rows that break a condition of the repair are refused."""
+    bad = [I.from_dense([1, 2], A=[[1, 1], [1, 0]], b=[1, 1]),           # variable in two rows
+           I.from_dense([1, 2], A=[[1, 1]], b=[2]),                       # b != 1
+           I.from_dense([-1, 2], A=[[1, 1]], b=[1]),                      # c < 0
+           I.from_dense([1, 2], A=[[1, 0], [1, 1]], b=[1, 1])]            # positive coefficient before row0
+    for k, P in enumerate(bad):
+        prm = _params(G, autotune=0)
+        prm.repair_row0 = 1 if k == 3 else 0
+        with pytest.raises(G.GforsError, match="GFORS_E_ARG"):
+            G.Problem(P, prm)

@@ -111,8 +111,49 @@ def test_library_tu_equals_oracle(nf, nc, seed):
 def test_library_tu_rejects_bad_pivots():
     from paper_2510_27117_amd import gfors
     P = I.from_dense([1, 2, 3], B=[[2, 1, 0], [0, 1, 1]], d=[2, 1])
-    with pytest.raises(gfors.GforsError, match="pivot coefficient"):
+    with pytest.raises(gfors.GforsError, match="not totally unimodular"):
         gfors.TUReformulation(P, [0, -1])
-    P2 = I.from_dense([1, 2, 3], B=[[1, 1, 0], [0, 1, 1]], d=[1, 1])
-    with pytest.raises(gfors.GforsError, match="signed identity"):
-        gfors.TUReformulation(P2, [1, 2])
+    P2 = I.from_dense([1, 2, 3], B=[[1, 1, 0], [1, 1, 1]], d=[1, 1])
+    with pytest.raises(gfors.GforsError, match="singular"):
+        gfors.TUReformulation(P2, [0, 1])
+    P3 = I.from_dense([1, 2, 3, 4], B=[[1, 1, 0, 0], [0, 1, 1, 0]], d=[1, 1])
+    with pytest.raises(gfors.GforsError, match="pivot of two rows"):
+        gfors.TUReformulation(P3, [1, 1])
+
+
+def _model_dense(M, n):
+    return (I.csr_to_dense(M.A) if M.A is not None else None,
+            I.csr_to_dense(M.B) if M.B is not None else None,
+            I.csr_to_dense(M.Q) if M.Q is not None else np.zeros((n, n), np.int64))
+
+
+@pytest.mark.parametrize("case", ["tri0", "tri1", "tri2", "interval", "kept_row"])
+def test_library_general_tu_equals_oracle(case):
+    """General pivot blocks (Gauss-Jordan in integers) and Q != 0: the library's
+    reformulated model, constant and recovery equal the oracle's exactly."""
+    from paper_2510_27117_amd import gfors
+    if case.startswith("tri"):
+        P, piv = _quad_tu_case(int(case[3:]))
+    elif case == "interval":
+        B = [[1, 1, 0, 1, 0], [0, 1, 0, 0, 1], [1, 0, 1, 1, 1]]
+        P = I.from_dense([3, -2, 4, 1, 5], A=[[1, 1, 1, 1, 1]], b=[1], B=B, d=[1, 1, 2])
+        piv = np.array([0, 1, -1])
+    else:
+        P = I.from_dense([1, 2, 3, 4], A=[[1, 0, 0, 1]], b=[1], B=[[1, 1, 0, 0], [0, 1, 1, 0], [1, 1, 1, 1]],
+                         d=[1, 1, 2])
+        piv = np.array([1, 2, -1])
+    Pn, c0, rec = O.tu_reformulate(P, piv)
+    T = gfors.TUReformulation(P, piv)
+    M = T.model
+    assert T.constant == c0 and M.n == Pn.n and np.array_equal(M.c, Pn.c)
+    got, ref = _model_dense(M, M.n), _model_dense(Pn, Pn.n)
+    for g, r in zip(got, ref):
+        assert (g is None) == (r is None) and (g is None or np.array_equal(g, r))
+    if Pn.A is not None:
+        assert np.array_equal(M.b, Pn.b)
+    if Pn.B is not None:
+        assert np.array_equal(M.d, Pn.d)
+    X = _all(M.n)
+    v, _ = O.evaluate(Pn, X)
+    for l in np.nonzero(v == 0)[0]:
+        assert np.array_equal(T.recover(X[l].astype(np.uint8)), rec(X[l]).astype(np.uint8))
