@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--snap-window", default=None,
                     help="ufl_learned: first,last fraction of each training run to take iterates from")
     ap.add_argument("--train-instances", type=int, default=200)
+    ap.add_argument("--eval-seeds", default="",
+                    help="ufl_learned: instance seeds of the evaluation instance (default: --seed)")
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--seq-sample", type=int, default=8,
                     help="batched workloads: instances run one by one for the comparison")
@@ -107,6 +109,15 @@ def indexed_entries(bip):
     return row_major, var_major
 
 
+def constant_degree(bip):
+    """Every variable has the same number of rows of [A; B] (> 0)."""
+    mats = [M for M in (bip.A, bip.B) if M is not None and M.nrows]
+    if not mats:
+        return False
+    cnt = sum(np.bincount(np.asarray(M.col, dtype=np.int64), minlength=bip.n) for M in mats)
+    return bool(cnt[0] > 0 and np.all(cnt == cnt[0]))
+
+
 def kernel_bytes(bip, K, idx=None):
     """Algorithmic HBM bytes per launch: every array the kernel must touch,
     counted once (gathered vectors by their unique size); indices only where
@@ -127,7 +138,9 @@ def kernel_bytes(bip, K, idx=None):
         out["dual"] = 4 * (m + 1) + 4 * ir + vb * nnzK + 4 * n + 20 * m
     prim = 16 * n  # x_in, ct read; x_out, xbar written
     if m:
-        prim += 4 * (n + 1) + 4 * ic + vb * nnzK + 4 * m
+        # row pointers of the transposed CSR, unless every variable has the
+        # same number of rows (then the kernels compute the ranges)
+        prim += (0 if constant_degree(bip) else 4 * (n + 1)) + 4 * ic + vb * nnzK + 4 * m
     if nnzQ:
         prim += 4 * (n + 1) + 8 * nnzQ
     out["primal"] = prim
@@ -457,20 +470,24 @@ def sequential_compare(bip, prm, a, R, batched_ms):
 
 
 def learned_experiment(a):
-    """Learned vs plain proposal on uncapacitated facility location (TU
-    reformulated: one assignment per customer eliminated, B_JI = I).
+    """Learned vs plain proposal on uncapacitated facility location, after the
+    TU reformulation (one assignment per customer eliminated, B_JI = I) or the
+    monotone relaxation (customer rows relaxed to >= 1, every candidate
+    repaired on the device).
 
     Training: the plain method runs on `--train-instances` small instances
     (40 facilities x 400 customers, seeds 1000..); iterates at 6 triggers are
     paired with the run's final incumbent; the network is trained on the GPU.
-    Evaluation: the full instance (1,000 x 10,000) runs `--tti-rounds` triggers
-    plain (K per round from x_k) and, after a reset, learned (K/2 from x_k +
-    K/2 from the network per trigger).  Time-to-incumbent = HIP-event time until
-    the incumbent is within 0.1% of the plain run's final value."""
+    Evaluation, per instance seed of `--eval-seeds` (the configured 1,000 x
+    10,000 by default): `--tti-rounds` triggers plain (K per round from x_k)
+    and, after a reset, learned (K/2 from x_k + K/2 from the network per
+    trigger).  Time-to-incumbent = HIP-event time until the incumbent is
+    within 0.1% of the plain run's final value; the median over the seeds is
+    reported."""
     import torch
     from paper_2510_27117_amd import gfors, instances, learned
     t0 = time.perf_counter()
-    train_prm = gfors.default_params(k_int=50, K_max=256)
+
     def reform(P):
         if a.relax == "mono":
             m = gfors.MonotoneRelaxation(P)
@@ -478,11 +495,18 @@ def learned_experiment(a):
         t = gfors.TUReformulation(P, P.meta["tu_pivots"])
         return t.model, t, t.constant
 
+    def params(P, k_int, K):
+        prm = gfors.default_params(k_int=k_int, K_max=K)
+        if a.relax == "mono":
+            prm.repair_row0 = P.m1      # relaxed rows follow the original inequality rows
+        return prm
+
     bips = []
     for sd in range(1000, 1000 + a.train_instances):
         P = instances.facility_location(40, 400, seed=sd)
         bips.append(reform(P)[0])
     win = tuple(float(v) for v in a.snap_window.split(",")) if a.snap_window else (None, None)
+    train_prm = params(instances.facility_location(40, 400, seed=1000), 50, 256)
     samples = learned.collect(bips, train_prm, rounds=60, K=256, snapshots=6, window=win)
     t_collect = time.perf_counter() - t0
     net = gfors.GNN(seed=a.seed)
@@ -494,47 +518,56 @@ def learned_experiment(a):
     loss1 = learned.mean_loss(net, samples[:64])
 
     nf, nc = (int(v) for v in a.ufl_eval.split(","))
-    full = instances.facility_location(nf, nc, seed=a.seed)
-    model, rf, c0 = reform(full)
-    prm = gfors.default_params(k_int=a.k_int, K_max=a.K)
-    G = gfors.Problem(model, prm)
+    seeds = [int(v) for v in a.eval_seeds.split(",")] if a.eval_seeds else [a.seed]
     R = a.tti_rounds
-    plain = learned.run_plain(G, R, a.K)
-    G.reset()
-    lrn = learned.run_learned(G, net, R, a.K)
-    G.final_round()
-    best = G.best(0)
-    if best["found"]:
-        xfull = rf.repair(best["x"]) if a.relax == "mono" else rf.recover(best["x"])
-    else:
-        xfull = None
-    zp = [z + c0 if z != learned.INT64_MAX else None for z in plain.z]
-    zl = [z + c0 if z != learned.INT64_MAX else None for z in lrn.z]
-    res = {"metric": METRIC, "workload": "ufl_learned",
-           "config": {"workload": (f"facility location {nf} x {nc} (TU: {nc} assignments eliminated)"
-                                   if a.relax == "tu" else
-                                   f"facility location {nf} x {nc} (customer rows relaxed to >= 1)"),
-                      "n_reduced": model.n, "rows": model.m1,
-                      "nnz": int(model.A.nnz), "K": a.K, "k_int": a.k_int, "rounds": R,
-                      "train": f"{a.train_instances} instances 40 x 400, {len(samples)} pairs, {a.train_steps} Adam steps",
-           "snapshot_window": list(win)},
-           "collect_s": round(t_collect, 2), "train_s": round(t_train, 2),
-           "train_loss_before": round(loss0, 5), "train_loss_after": round(loss1, 5),
-           "plain": {"first_feasible_round": next((i for i, z in enumerate(zp) if z is not None), None),
-                     "z_final": zp[-1], "ms_total": round(plain.ms[-1], 2)},
-           "learned": {"first_feasible_round": next((i for i, z in enumerate(zl) if z is not None), None),
-                       "z_final": zl[-1], "ms_total": round(lrn.ms[-1], 2)}}
-    if zp[-1] is not None:
-        target = zp[-1] + 0.001 * abs(zp[-1])
-        tp = plain.time_to(int(np.floor(target - c0)))
-        tl = lrn.time_to(int(np.floor(target - c0)))
-        res["time_to_incumbent"] = {"target": target, "plain_ms": tp, "learned_ms": tl,
-                                    "speedup": (round(tp / tl, 3) if tp and tl else None)}
-    if xfull is not None:
-        res["recovered_point_objective"] = int(full.c @ xfull.astype(np.int64))
-    G.close()
+    per = {}
+    for sd in seeds:
+        full = instances.facility_location(nf, nc, seed=sd)
+        model, rf, c0 = reform(full)
+        G = gfors.Problem(model, params(full, a.k_int, a.K))
+        plain = learned.run_plain(G, R, a.K)
+        G.reset()
+        lrn = learned.run_learned(G, net, R, a.K)
+        G.final_round()
+        best = G.best(0)
+        zp = [z + c0 if z != learned.INT64_MAX else None for z in plain.z]
+        zl = [z + c0 if z != learned.INT64_MAX else None for z in lrn.z]
+        rec = {"plain": {"first_feasible_round": next((i for i, z in enumerate(zp) if z is not None), None),
+                         "z_final": zp[-1], "ms_total": round(plain.ms[-1], 2),
+                         "ms_per_round": round(plain.ms[-1] / R, 3)},
+               "learned": {"first_feasible_round": next((i for i, z in enumerate(zl) if z is not None), None),
+                           "z_final": zl[-1], "ms_total": round(lrn.ms[-1], 2),
+                           "ms_per_round": round(lrn.ms[-1] / R, 3)}}
+        if zp[-1] is not None:
+            target = zp[-1] + 0.001 * abs(zp[-1])
+            tp = plain.time_to(int(np.floor(target - c0)))
+            tl = lrn.time_to(int(np.floor(target - c0)))
+            rec["time_to_incumbent"] = {"target": target, "plain_ms": tp, "learned_ms": tl,
+                                        "learned_reached": tl is not None,
+                                        "speedup": (round(tp / tl, 3) if tp and tl else None)}
+        if best["found"]:
+            xfull = rf.repair(best["x"]) if a.relax == "mono" else rf.recover(best["x"])
+            rec["recovered_point_objective"] = int(full.c @ xfull.astype(np.int64))
+        per[str(sd)] = rec
+        G.close()
     net.close()
-    return res
+    sp = [r["time_to_incumbent"]["speedup"] for r in per.values()
+          if r.get("time_to_incumbent") and r["time_to_incumbent"]["speedup"] is not None]
+    over = [r["learned"]["ms_per_round"] / r["plain"]["ms_per_round"] - 1.0 for r in per.values()]
+    return {"metric": METRIC, "workload": "ufl_learned",
+            "config": {"workload": (f"facility location {nf} x {nc} (TU: {nc} assignments eliminated)"
+                                    if a.relax == "tu" else
+                                    f"facility location {nf} x {nc} (customer rows relaxed to >= 1, "
+                                    f"candidates repaired on the device)"),
+                       "K": a.K, "k_int": a.k_int, "rounds": R, "eval_seeds": seeds,
+                       "train": f"{a.train_instances} instances 40 x 400, {len(samples)} pairs, {a.train_steps} Adam steps",
+                       "snapshot_window": list(win)},
+            "collect_s": round(t_collect, 2), "train_s": round(t_train, 2),
+            "train_loss_before": round(loss0, 5), "train_loss_after": round(loss1, 5),
+            "per_seed": per,
+            "median_speedup_time_to_incumbent": (round(float(np.median(sp)), 3) if sp else None),
+            "seeds_where_learned_reached_target": len(sp),
+            "median_learned_round_overhead": round(float(np.median(over)), 3)}
 
 
 def main():

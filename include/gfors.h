@@ -196,6 +196,29 @@ int gfors_sample_eval(gfors_problem *P, int32_t K, const float *p_override,
 int gfors_sample_eval_ex(gfors_problem *P, int32_t K, const float *p_override,
                          int32_t *viol_dev, int64_t *obj_dev, int32_t flags);
 
+/* Customized sampling for the 3D assignment problem (Algorithm 4, Sec. 2.4.2)
+ * in place of the Bernoulli round; the problem's variables are x_ijk at index
+ * (i n + j) n + k (n^3 of them, n <= 1024, one instance).  From p (p_override
+ * or x_k): the min(gamma n, #{p > 0}) largest entries of p (descending, lower
+ * index first on ties; gamma n <= 4096) give a conflict-free partial
+ * assignment (an entry is taken when its i, j and k are all unused); each of
+ * the K candidates completes it by matching the unassigned i's (ascending)
+ * with random permutations of the free j's and k's (Fisher-Yates from
+ * position r-1 down to 1, position t swapped with floor(u (t + 1)), u from
+ * word 0 (j) / word 1 (k) of Philox4x32-10(key = seed, counter = (l, t, round,
+ * 0xA5513D00)), u = (U >> 8) 2^-24), then takes L local steps: step q draws
+ * triple a = floor(u n) from word 0 of counter (l, n + q, round, 0xA5513D00)
+ * and applies, if its cost change is negative, the interchange of a's j or
+ * k with another triple's that changes the cost least (ties: lower partner,
+ * then the j interchange).  Candidates are then evaluated exactly on the
+ * problem's rows and objective and merged into the incumbent as in
+ * gfors_sample_eval_ex (same flags, viol_dev / obj_dev).  Async.
+ * Errors: E_ARG (n^3 != number of variables, n > 1024, gamma n > 4096,
+ * L < 0, bad K or flags, more than one instance). */
+int gfors_sample_eval_assign3d(gfors_problem *P, int32_t n, int32_t K, int32_t gamma, int32_t L,
+                               const float *p_override, int32_t *viol_dev, int64_t *obj_dev,
+                               int32_t flags);
+
 /* Evaluate round(x_k) = [x_k > 1/2] (last step of Algorithm 1) and merge it
  * into the incumbent (round id -1).  Does not advance rho.  Async. */
 int gfors_final_round(gfors_problem *P);

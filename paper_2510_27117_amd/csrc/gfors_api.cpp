@@ -175,6 +175,7 @@ struct gfors_problem {
     // (exact in FP32 either way; half the bytes of the coefficient stream)
     bool use16 = false;
     bool dense_cols = false;   // some variable's rows are one contiguous range (colT0 is read)
+    int colT_deg = 0;          // every variable has this many rows (> 0): row ranges are computed
     int16_t *val16 = nullptr, *sellT_val16 = nullptr;
     float *rowinv32 = nullptr;          // 1/||a_j|| (0 for a zero row): the GNN's edge weights
     float gnn_ictmax = 1.f, gnn_irtmax = 1.f;
@@ -193,6 +194,7 @@ struct gfors_problem {
     // per row, its variables in (cost, index) order
     int n_rep = 0;
     int *rep_rp = nullptr, *rep_var = nullptr;
+    int *a3_part = nullptr;   // partial assignment of the 3D-assignment sampler (2 x kA3MaxN)
 
     // graphs: key = (K, parity)
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -393,6 +395,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->primal_order = cv.take<int>(n);
     P->cover_ids = cv.take<int>(b.et);
     P->general_ids = cv.take<int>(b.et);
+    P->a3_part = cv.take<int>(2 * kA3MaxN);
     P->rep_rp = cv.take<int>(prm->repair_row0 >= 0 ? m1 + 1 : 1);
     P->rep_var = cv.take<int>(prm->repair_row0 >= 0 ? nnzK : 1);
     P->mf_cap = prm->eval_mfma && m > 0 ? mf_digit_cap(nnzK, m) : 0;
@@ -1117,6 +1120,9 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         if ((rc = upload(s, P->primal_order, ordT.data(), n))) return rc;
         P->heavy_cols = 0;
         while (P->heavy_cols < n && rpT[ordT[P->heavy_cols] + 1] - rpT[ordT[P->heavy_cols]] >= kHeavyLen) ++P->heavy_cols;
+        P->colT_deg = n > 0 ? rpT[1] - rpT[0] : 0;
+        for (int64_t i = 1; i < n && P->colT_deg; ++i)
+            if (rpT[i + 1] - rpT[i] != P->colT_deg) P->colT_deg = 0;
         auto classes = [](const std::vector<int> &o, const std::vector<int> &ptr, int64_t cnt, int &h, int &md) {
             int64_t k = 0;
             while (k < cnt && ptr[o[k] + 1] - ptr[o[k]] >= kGnnHeavyLen) ++k;
@@ -1464,7 +1470,7 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
         launch_primal_bits(s, lpr, P->unitK, batched, static_cast<int>(P->n), static_cast<int>(P->m),
                            P->rpT, P->ciT, P->valT, P->wy, reinterpret_cast<const uint32_t *>(P->by),
                            x_in, x_out, xbar, P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst, ctr,
-                           xb_out);
+                           xb_out, P->colT_deg);
         xbar_bits = xb_out != nullptr;
     } else if (sell) {
         launch_sell(s, P->sellT, 2, P->unitK, batched, P->wy, nullptr, 0, nullptr, nullptr, nullptr,
@@ -1724,6 +1730,33 @@ int gfors_sample_eval_ex(gfors_problem *P, int32_t K, const float *p_override, i
     const size_t cnt = static_cast<size_t>(P->T) * K;
     if (viol_dev) HIP_TRY(hipMemcpyAsync(viol_dev, P->viol, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice, P->stream));
     if (obj_dev) HIP_TRY(hipMemcpyAsync(obj_dev, P->z, cnt * sizeof(int64_t), hipMemcpyDeviceToDevice, P->stream));
+    HIP_TRY(hipGetLastError());
+    return GFORS_OK;
+}
+
+int gfors_sample_eval_assign3d(gfors_problem *P, int32_t n, int32_t K, int32_t gamma, int32_t L,
+                               const float *p_override, int32_t *viol_dev, int64_t *obj_dev,
+                               int32_t flags) {
+    if (!P) return fail(GFORS_E_ARG, "NULL handle");
+    if (P->T != 1) return fail(GFORS_E_ARG, "3D-assignment sampling: single-instance problems only");
+    if (n < 1 || n > kA3MaxN || static_cast<int64_t>(n) * n * n != P->n)
+        return fail(GFORS_E_ARG, "3D-assignment sampling: n must satisfy n^3 = number of variables, 1 <= n <= 1024");
+    if (!check_K(K) || K > P->prm.K_max)
+        return fail(GFORS_E_ARG, "K must be a multiple of 64 in [64, K_max] (multiple of 1024 above 1024)");
+    if (gamma < 0 || static_cast<int64_t>(gamma) * n > kA3MaxTop || L < 0)
+        return fail(GFORS_E_ARG, "3D-assignment sampling: need gamma >= 0, gamma n <= 4096, L >= 0");
+    if (flags & ~GFORS_SAMPLE_NO_TRIGGER) return fail(GFORS_E_ARG, "unknown flag");
+    hipStream_t s = P->stream;
+    const int W = K / 64;
+    const float *p = p_override ? p_override : P->xbuf[P->cur];
+    launch_a3(s, p, n, gamma * n, K, L, static_cast<uint32_t>(P->prm.seed & 0xffffffffu),
+              static_cast<uint32_t>(P->prm.seed >> 32), P->ctr, P->cost, P->a3_part, P->X, W, P->zpart,
+              static_cast<int64_t>(P->st.count) * K, P->xkind);
+    enqueue_eval(P, K, 0, nullptr, (flags & GFORS_SAMPLE_NO_TRIGGER) ? 0 : 1);
+    P->lastK = K;
+    const size_t cnt = static_cast<size_t>(K);
+    if (viol_dev) HIP_TRY(hipMemcpyAsync(viol_dev, P->viol, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (obj_dev) HIP_TRY(hipMemcpyAsync(obj_dev, P->z, cnt * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipGetLastError());
     return GFORS_OK;
 }

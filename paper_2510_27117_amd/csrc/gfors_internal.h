@@ -147,7 +147,7 @@ void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, 
                         const int *rpT, const int *ciT, const int *valT, const float *wy,
                         const uint32_t *bits, const float *x_in, float *x_out, float *xbar,
                         const float *ct, float tau1, const float *tau1_inst, const double *rho,
-                        const int *var_inst, DevCounters *ctr, uint64_t *xbits);
+                        const int *var_inst, DevCounters *ctr, uint64_t *xbits, int deg);
 
 void launch_copy_f32(hipStream_t s, float *dst, const float *src, int64_t n);
 void launch_set_xbar(hipStream_t s, int64_t n, const float *x, const float *xp, float *xbar);
@@ -179,6 +179,14 @@ void launch_philox_peak(hipStream_t s, int blocks, int iters, uint32_t *sink);
 // set; cleared costs are taken off the candidates' objectives in zpart[0..K).
 void launch_mono_repair(hipStream_t s, int nrows, int W, int K, const int *rp, const int *var,
                         const int64_t *cost, uint64_t *X, uint8_t *xkind, int64_t *zpart);
+// Customized 3D-assignment sampler (Algorithm 4): candidates of an n x n x n
+// assignment from p into X (cleared first, with zpart[0, nzpart) and xkind),
+// objectives into zpart[0 .. K); part: int[2 n] scratch.
+constexpr int kA3MaxN = 1024;     // largest n
+constexpr int kA3MaxTop = 4096;   // largest gamma n
+void launch_a3(hipStream_t s, const float *p, int n, int m, int K, int L, uint32_t key0,
+               uint32_t key1, const DevCounters *ctr, const int64_t *cost, int *part, uint64_t *X,
+               int W, int64_t *zpart, int64_t nzpart, uint8_t *xkind);
 void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64_t *cost,
                    uint64_t *X, const Tiles &st, const int64_t *inst_var0,
                    const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,

@@ -763,9 +763,9 @@ k_sell_bits(int nrows, int P, int nchunk, int ns, int ncols, int G, const int *_
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         const int k = min(k0 + u, L[h] - 1);
-                        const int cv = __builtin_nontemporal_load(ci + e0[h] + lane + 64 * k);
+                        const int cv = ci[e0[h] + lane + 64 * k];
                         col[h][u] = k0 + u < L[h] ? cv : ncols;
-                        a[h][u] = UNIT ? 0 : __builtin_nontemporal_load(val + e0[h] + lane + 64 * k);
+                        a[h][u] = UNIT ? 0 : val[e0[h] + lane + 64 * k];
                     }
                 } else {
 #pragma unroll
@@ -879,7 +879,7 @@ k_primal_bits(int n, int m, int nvb, const int *__restrict__ rpT, const int *__r
               float *__restrict__ x_out, float *__restrict__ xbar, const float *__restrict__ ct,
               float tau1, const float *__restrict__ tau1_inst, const double *__restrict__ rho,
               const int *__restrict__ var_inst, DevCounters *__restrict__ ctr,
-              uint64_t *__restrict__ xbits) {
+              uint64_t *__restrict__ xbits, int deg) {
     extern __shared__ uint32_t sb[];
     const int nw = (m + 31) >> 5;
     load_bitmap_lds(sb, bits, nw);
@@ -895,12 +895,14 @@ k_primal_bits(int n, int m, int nvb, const int *__restrict__ rpT, const int *__r
             xi = x_in[i];
             cti = ct[i];
             if (BATCH) t = var_inst[i];
-            const int e1 = rpT[i + 1];
+            // every variable with deg entries: its range is computed, not read
+            const int eb0 = deg ? deg * i : rpT[i];
+            const int e1 = deg ? eb0 + deg : rpT[i + 1];
             // batches of kPrimalBatch entries per lane, branch-free: row
             // indices first, then their bits, then the gathers of the nonzero
             // operands (a zero operand reads the padding element wy[m], shared
             // by the wavefront); terms are added in entry order
-            for (int eb = rpT[i] + sub; eb < e1; eb += kPrimalBatch * LPR) {
+            for (int eb = eb0 + sub; eb < e1; eb += kPrimalBatch * LPR) {
                 int j[kPrimalBatch], a[kPrimalBatch];
 #pragma unroll
                 for (int u = 0; u < kPrimalBatch; ++u) {
@@ -963,13 +965,13 @@ static void primal_bits_lpr(hipStream_t s, bool unit, bool batched, int n, int m
                             const uint32_t *bits, const float *x_in, float *x_out, float *xbar,
                             const float *ct, float tau1, const float *tau1_inst,
                             const double *rho, const int *var_inst, DevCounters *ctr,
-                            uint64_t *xbits) {
+                            uint64_t *xbits, int deg) {
     const int64_t nvb64 = (static_cast<int64_t>(n) * LPR + 1023) / 1024;
     const int nvb = static_cast<int>(nvb64);
     const int grid = nvb < 512 ? nvb : 512;   // two 16-wave workgroups per CU
     const size_t lds = static_cast<size_t>((m + 31) / 32) * 4;
     if (grid <= 0) return;
-#define GF_PB(U, B) k_primal_bits<LPR, U, B><<<grid, 1024, lds, s>>>(n, m, nvb, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr, xbits)
+#define GF_PB(U, B) k_primal_bits<LPR, U, B><<<grid, 1024, lds, s>>>(n, m, nvb, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr, xbits, deg)
     if (unit) { if (batched) GF_PB(true, true); else GF_PB(true, false); }
     else { if (batched) GF_PB(false, true); else GF_PB(false, false); }
 #undef GF_PB
@@ -979,9 +981,9 @@ void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, 
                         const int *rpT, const int *ciT, const int *valT, const float *wy,
                         const uint32_t *bits, const float *x_in, float *x_out, float *xbar,
                         const float *ct, float tau1, const float *tau1_inst, const double *rho,
-                        const int *var_inst, DevCounters *ctr, uint64_t *xbits) {
+                        const int *var_inst, DevCounters *ctr, uint64_t *xbits, int deg) {
     switch (lpr) {
-#define GF_CASE(L) case L: primal_bits_lpr<L>(s, unit, batched, n, m, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr, xbits); break;
+#define GF_CASE(L) case L: primal_bits_lpr<L>(s, unit, batched, n, m, rpT, ciT, valT, wy, bits, x_in, x_out, xbar, ct, tau1, tau1_inst, rho, var_inst, ctr, xbits, deg); break;
         GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8) GF_CASE(16) GF_CASE(32) GF_CASE(64)
 #undef GF_CASE
         default: break;

@@ -190,6 +190,294 @@ k_sample(const float *__restrict__ p, const int64_t *__restrict__ cost,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Customized sampling for the 3D assignment problem (Algorithm 4, Sec. 2.4.2).
+// x_ijk at index (i n + j) n + k.  Uniforms: Philox4x32-10(key = seed,
+// counter = (candidate l, step, round, kA3Tag)); Fisher-Yates step t (r-1 down
+// to 1) swaps position t of the free j's with floor(u (t + 1)) (word 0) and of
+// the free k's with word 1's; local step q draws triple a = floor(u n) from
+// word 0 of step n + q; floor(u m) = ((U >> 8) m) >> 24 exactly.
+constexpr uint32_t kA3Tag = 0xA5513D00u;
+
+__device__ __forceinline__ uint32_t a3_key(float p) { return p > 0.f ? __float_as_uint(p) : 0u; }
+
+__device__ __forceinline__ uint32_t a3_below(uint32_t U, uint32_t m) {
+    return static_cast<uint32_t>((static_cast<uint64_t>(U >> 8) * m) >> 24);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One workgroup: the min(m, #{p > 0}) largest entries of p (descending, lower
+// index first on ties) by a 4-digit radix select of the FP32 bit patterns
+// (monotone for p > 0), an index-ordered compaction and a bitonic sort in
+// LDS; then the greedy conflict-free partial assignment (largest first).
+// part[i] / part[n + i] = j / k of i, or -1.
+__global__ void __launch_bounds__(1024)
+k_a3_partial(const float *__restrict__ p, int64_t N, int n, int m, int *__restrict__ part) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t sel[kA3MaxTop];
+    __shared__ int J0[kA3MaxN], K0[kA3MaxN];
+    __shared__ uint8_t uj[kA3MaxN], uk[kA3MaxN];
+    __shared__ uint32_t s_prefix, s_rank, s_npos, s_ngt, s_eqbase;
+    __shared__ uint32_t s_wcnt[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nw = blockDim.x >> 6;
+    if (tid == 0) { s_npos = 0; s_ngt = 0; s_eqbase = 0; s_prefix = 0; }
+    for (int i = tid; i < n; i += blockDim.x) { J0[i] = -1; K0[i] = -1; uj[i] = 0; uk[i] = 0; }
+    __syncthreads();
+    uint32_t cnt = 0;
+    for (int64_t v = tid; v < N; v += blockDim.x) cnt += p[v] > 0.f ? 1u : 0u;
+    atomicAdd(&s_npos, cnt);
+    __syncthreads();
+    const uint32_t meff = min(static_cast<uint32_t>(m), s_npos);
+    if (meff > 0) {
+        if (tid == 0) s_rank = meff;
+        for (int d = 3; d >= 0; --d) {
+            for (int b = tid; b < 256; b += blockDim.x) hist[b] = 0;
+            __syncthreads();
+            const uint32_t pre = s_prefix;
+            const int sh = 8 * d;
+            const uint32_t himask = d == 3 ? 0u : (0xFFFFFFFFu << (sh + 8));
+            for (int64_t v = tid; v < N; v += blockDim.x) {
+                const uint32_t key = a3_key(p[v]);
+                if (key != 0u && (key & himask) == (pre & himask)) atomicAdd(&hist[(key >> sh) & 255u], 1u);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t cum = 0;
+                const uint32_t r = s_rank;
+                int b = 255;
+                for (; b > 0; --b) {
+                    if (cum + hist[b] >= r) break;
+                    cum += hist[b];
+                }
+                s_prefix = pre | (static_cast<uint32_t>(b) << sh);
+                s_rank = r - cum;
+            }
+            __syncthreads();
+        }
+        const uint32_t T = s_prefix, need_eq = s_rank, ngt_total = meff - need_eq;
+        for (int64_t base = 0; base < N; base += blockDim.x) {
+            const int64_t v = base + tid;
+            const uint32_t key = v < N ? a3_key(p[v]) : 0u;
+            const bool gt = key > T;
+            const bool eq = key != 0u && key == T;
+            if (gt) {
+                const uint32_t slot = atomicAdd(&s_ngt, 1u);
+                if (slot < ngt_total) sel[slot] = (static_cast<uint64_t>(~key) << 32) | static_cast<uint64_t>(v);
+            }
+            const uint64_t bal = __ballot(eq);
+            if (lane == 0) s_wcnt[wv] = static_cast<uint32_t>(__popcll(bal));
+            __syncthreads();
+            uint32_t off = s_eqbase;
+            for (int w = 0; w < wv; ++w) off += s_wcnt[w];
+            const uint32_t pos = off + static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
+            if (eq && pos < need_eq) sel[ngt_total + pos] = (static_cast<uint64_t>(~key) << 32) | static_cast<uint64_t>(v);
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t tot = 0;
+                for (int w = 0; w < nw; ++w) tot += s_wcnt[w];
+                s_eqbase += tot;
+            }
+            __syncthreads();
+        }
+        int M2 = 1;
+        while (M2 < static_cast<int>(meff)) M2 <<= 1;
+        for (int i = static_cast<int>(meff) + tid; i < M2; i += blockDim.x) sel[i] = ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= M2; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < M2; i += blockDim.x) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const uint64_t a = sel[i], b = sel[ixj];
+                        const bool asc = (i & k) == 0;
+                        if ((a > b) == asc) {
+                            sel[i] = b;
+                            sel[ixj] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        if (tid == 0) {
+            const int64_t nn = static_cast<int64_t>(n) * n;
+            for (uint32_t t = 0; t < meff; ++t) {
+                const int64_t v = static_cast<int64_t>(sel[t] & 0xFFFFFFFFull);
+                const int i = static_cast<int>(v / nn), j = static_cast<int>((v / n) % n), k = static_cast<int>(v % n);
+                if (J0[i] < 0 && !uj[j] && !uk[k]) {
+                    J0[i] = j;
+                    K0[i] = k;
+                    uj[j] = 1;
+                    uk[k] = 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += blockDim.x) {
+        part[i] = J0[i];
+        part[n + i] = K0[i];
+    }
+}
+
+// Zero the candidate block, the per-tile objective partials and the variable
+// kinds (every variable's words are then read by the evaluation).
+__global__ void k_a3_clear(uint64_t *__restrict__ X, int64_t nX, int64_t *__restrict__ zpart,
+                           int64_t nz, uint8_t *__restrict__ xkind, int64_t nk) {
+    const int64_t st = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < nX; t += st) X[t] = 0ull;
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < nz; t += st) zpart[t] = 0;
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < nk; t += st) xkind[t] = 0;
+}
+
+// One wavefront per candidate l: random completion of the partial assignment
+// (Fisher-Yates on the free j's and k's, swap indices drawn in parallel, the
+// swaps done in order by lane 0), L steps of pairwise interchange (lanes over
+// the partner triple, lexicographic (change, 2 b + kind) minimum), then the
+// objective into the sampler's partial of tile 0 and the candidate's bits.
+__global__ void __launch_bounds__(256)
+k_a3_cand(int n, int K, int L, uint32_t key0, uint32_t key1, const DevCounters *__restrict__ ctr,
+          const int64_t *__restrict__ cost, const int *__restrict__ part, uint64_t *__restrict__ X,
+          int W, int64_t *__restrict__ zpart) {
+    extern __shared__ int16_t a3s[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int l = blockIdx.x * (blockDim.x >> 6) + wv;
+    if (l >= K) return;                       // no workgroup barrier below
+    int16_t *J = a3s + static_cast<size_t>(wv) * 7 * kA3MaxN;
+    int16_t *Kk = J + kA3MaxN, *Ui = Kk + kA3MaxN, *Fj = Ui + kA3MaxN, *Fk = Fj + kA3MaxN;
+    int16_t *Aj = Fk + kA3MaxN, *Ak = Aj + kA3MaxN;
+    __shared__ uint32_t bits_j[4][kA3MaxN / 32], bits_k[4][kA3MaxN / 32];
+    const uint32_t round = static_cast<uint32_t>(ctr->round);
+    for (int w = lane; w < kA3MaxN / 32; w += 64) {
+        bits_j[wv][w] = 0u;
+        bits_k[wv][w] = 0u;
+    }
+    wave_sync();
+    for (int i = lane; i < n; i += 64) {
+        const int j = part[i], k = part[n + i];
+        J[i] = static_cast<int16_t>(j);
+        Kk[i] = static_cast<int16_t>(k);
+        if (j >= 0) {
+            atomicOr(&bits_j[wv][j >> 5], 1u << (j & 31));
+            atomicOr(&bits_k[wv][k >> 5], 1u << (k & 31));
+        }
+    }
+    wave_sync();
+    int r = 0, rj = 0, rk = 0;
+    for (int base = 0; base < n; base += 64) {
+        const int t = base + lane;
+        const bool fi = t < n && J[t] < 0;
+        const bool fj = t < n && !((bits_j[wv][t >> 5] >> (t & 31)) & 1u);
+        const bool fk = t < n && !((bits_k[wv][t >> 5] >> (t & 31)) & 1u);
+        const uint64_t below = (1ull << lane) - 1ull;
+        const uint64_t bi = __ballot(fi), bj = __ballot(fj), bk = __ballot(fk);
+        if (fi) Ui[r + __popcll(bi & below)] = static_cast<int16_t>(t);
+        if (fj) Fj[rj + __popcll(bj & below)] = static_cast<int16_t>(t);
+        if (fk) Fk[rk + __popcll(bk & below)] = static_cast<int16_t>(t);
+        r += __popcll(bi);
+        rj += __popcll(bj);
+        rk += __popcll(bk);
+    }
+    for (int t = lane; t < r; t += 64) {
+        if (t == 0) continue;
+        uint32_t c0 = static_cast<uint32_t>(l), c1 = static_cast<uint32_t>(t), c2 = round, c3 = kA3Tag;
+        philox10(c0, c1, c2, c3, key0, key1);
+        Aj[t] = static_cast<int16_t>(a3_below(c0, static_cast<uint32_t>(t + 1)));
+        Ak[t] = static_cast<int16_t>(a3_below(c1, static_cast<uint32_t>(t + 1)));
+    }
+    wave_sync();
+    if (lane == 0) {
+        for (int t = r - 1; t >= 1; --t) {
+            const int a = Aj[t], b = Ak[t];
+            const int16_t x = Fj[t];
+            Fj[t] = Fj[a];
+            Fj[a] = x;
+            const int16_t y = Fk[t];
+            Fk[t] = Fk[b];
+            Fk[b] = y;
+        }
+    }
+    wave_sync();
+    for (int t = lane; t < r; t += 64) {
+        J[Ui[t]] = Fj[t];
+        Kk[Ui[t]] = Fk[t];
+    }
+    wave_sync();
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    auto cst = [&](int i, int j, int k) -> int64_t { return cost[i * nn + static_cast<int64_t>(j) * n + k]; };
+    if (n >= 2) {
+        for (int q = 0; q < L; ++q) {
+            uint32_t c0 = static_cast<uint32_t>(l), c1 = static_cast<uint32_t>(n + q), c2 = round, c3 = kA3Tag;
+            philox10(c0, c1, c2, c3, key0, key1);
+            const int a = static_cast<int>(a3_below(c0, static_cast<uint32_t>(n)));
+            const int ja = J[a], ka = Kk[a];
+            const int64_t ca = cst(a, ja, ka);
+            int64_t bd = INT64_MAX;
+            int bk = 0x7FFFFFFF;
+            for (int b = lane; b < n; b += 64) {
+                if (b == a) continue;
+                const int jb = J[b], kb = Kk[b];
+                const int64_t cur = ca + cst(b, jb, kb);
+                const int64_t dj = cst(a, jb, ka) + cst(b, ja, kb) - cur;
+                const int64_t dk = cst(a, ja, kb) + cst(b, jb, ka) - cur;
+                if (dj < bd || (dj == bd && 2 * b < bk)) { bd = dj; bk = 2 * b; }
+                if (dk < bd || (dk == bd && 2 * b + 1 < bk)) { bd = dk; bk = 2 * b + 1; }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const int64_t od = static_cast<int64_t>(
+                    (static_cast<uint64_t>(static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint64_t>(bd) >> 32), o, 64))) << 32) |
+                    static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint64_t>(bd)), o, 64)));
+                const int ok = __shfl_xor(bk, o, 64);
+                if (od < bd || (od == bd && ok < bk)) { bd = od; bk = ok; }
+            }
+            if (bd < 0 && lane == 0) {
+                const int b = bk >> 1;
+                if ((bk & 1) == 0) {
+                    const int16_t x = J[a];
+                    J[a] = J[b];
+                    J[b] = x;
+                } else {
+                    const int16_t x = Kk[a];
+                    Kk[a] = Kk[b];
+                    Kk[b] = x;
+                }
+            }
+            wave_sync();
+        }
+    }
+    int64_t z = 0;
+    for (int i = lane; i < n; i += 64) {
+        const int64_t v = i * nn + static_cast<int64_t>(J[i]) * n + Kk[i];
+        z += cost[v];
+        atomicOr(reinterpret_cast<unsigned long long *>(X) + v * W + (l >> 6), 1ull << (l & 63));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t oz = static_cast<int64_t>(
+            (static_cast<uint64_t>(static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint64_t>(z) >> 32), o, 64))) << 32) |
+            static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint64_t>(z)), o, 64)));
+        z += oz;
+    }
+    if (lane == 0) zpart[l] = z;
+}
+
+void launch_a3(hipStream_t s, const float *p, int n, int m, int K, int L, uint32_t key0,
+               uint32_t key1, const DevCounters *ctr, const int64_t *cost, int *part, uint64_t *X,
+               int W, int64_t *zpart, int64_t nzpart, uint8_t *xkind) {
+    const int64_t N = static_cast<int64_t>(n) * n * n;
+    k_a3_partial<<<1, 1024, 0, s>>>(p, N, n, m, part);
+    int64_t blocks = (N * W + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_a3_clear<<<static_cast<int>(blocks), 256, 0, s>>>(X, N * W, zpart, nzpart, xkind, N);
+    const size_t lds = static_cast<size_t>(4) * 7 * kA3MaxN * sizeof(int16_t);
+    k_a3_cand<<<(K + 3) / 4, 256, lds, s>>>(n, K, L, key0, key1, ctr, cost, part, X, W, zpart);
+}
+
 void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64_t *cost,
                    uint64_t *X, const Tiles &st, const int64_t *inst_var0,
                    const int64_t *inst_nvar, int64_t *zpart, int K, uint32_t key0,

@@ -45,7 +45,7 @@ EXPORTS = [
     "gfors_gnn_forward", "gfors_gnn_grad", "gfors_gnn_adam", "gfors_gnn_train_step",
     "gfors_gnn_get_params", "gfors_gnn_set_params", "gfors_gnn_get_grad", "gfors_gnn_set_grad",
     "gfors_tu_create", "gfors_tu_dims", "gfors_tu_export", "gfors_tu_recover", "gfors_tu_destroy",
-    "gfors_tu_export_q",
+    "gfors_tu_export_q", "gfors_sample_eval_assign3d",
     "gfors_tu_last_error", "gfors_mono_rows", "gfors_mono_repair", "gfors_mono_last_error",
     "gfors_philox_throughput", "gfors_eval_planes", "gfors_create_problem_static",
 ]
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_final_round.argtypes = [c_vp]
     L.gfors_sample_eval_ex.argtypes = [c_vp, c_i32, c_vp, c_vp, c_vp, c_i32]
     L.gfors_run_rounds.argtypes = [c_vp, c_i32, c_i32, c_i32]
+    L.gfors_sample_eval_assign3d.argtypes = [c_vp, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_i32]
     L.gfors_best.argtypes = [c_vp, c_i32, P(c_i64), c_vp, P(c_i32), c_vp]
     L.gfors_get_residuals.argtypes = [c_vp, c_vp]
     L.gfors_get_history.argtypes = [c_vp, c_i32, c_vp, c_i32, P(c_i32)]
@@ -272,6 +273,29 @@ class Problem:
                                                    None if v is None else ctypes.c_void_p(v.data_ptr()),
                                                    None if z is None else ctypes.c_void_p(z.data_ptr()),
                                                    0 if trigger else 1))
+        if outputs:
+            self.synchronize()
+            return v, z
+        return None
+
+    def sample_eval_assign3d(self, n: int, K: int, gamma: int, L: int, p_override=None,
+                             outputs: bool = False, trigger: bool = True):
+        """One round of the customized 3D-assignment sampler (Algorithm 4)
+        in place of the Bernoulli round; same outputs as sample_eval."""
+        torch = self.torch
+        pp = None
+        if p_override is not None:
+            assert p_override.dtype == torch.float32 and p_override.is_cuda and p_override.numel() == self.n
+            pp = ctypes.c_void_p(p_override.contiguous().data_ptr())
+            self._p_keep = p_override
+        v = z = None
+        if outputs:
+            v = torch.empty((1, K), dtype=torch.int32, device=self.device)
+            z = torch.empty((1, K), dtype=torch.int64, device=self.device)
+        _check(load_library().gfors_sample_eval_assign3d(
+            self._h(), int(n), int(K), int(gamma), int(L), pp,
+            None if v is None else ctypes.c_void_p(v.data_ptr()),
+            None if z is None else ctypes.c_void_p(z.data_ptr()), 0 if trigger else 1))
         if outputs:
             self.synchronize()
             return v, z

@@ -55,3 +55,14 @@ def test_quad_eval_entries_upper_triangle():
     val[0] = 7
     P.Q = I.CSR(Q.nrows, Q.ncols, Q.row_ptr, Q.col, val)
     assert bench.quad_eval_entries(P) == Q.nnz
+
+
+def test_constant_degree_drops_primal_row_pointers():
+    """5 rows per column (the large set cover's structure): no row pointers
+    in the primal's bytes; a Bernoulli set cover keeps them."""
+    cols = I.set_cover_columns(400, 60, 5, seed=1)
+    bern = I.set_cover_bernoulli(400, 60, 0.05, seed=1)
+    assert bench.constant_degree(cols) and not bench.constant_degree(bern)
+    idx = bench.indexed_entries(cols)
+    n, m, nnz = cols.n, cols.m1, cols.A.nnz
+    assert bench.kernel_bytes(cols, 64, idx)["primal"] == 16 * n + 4 * idx[1] + 4 * m

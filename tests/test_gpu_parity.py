@@ -822,3 +822,47 @@ def test_monotone_repair_rejects_bad_rows(G):
         prm.repair_row0 = 1 if k == 3 else 0
         with pytest.raises(G.GforsError, match="GFORS_E_ARG"):
             G.Problem(P, prm)
+
+
+@pytest.mark.parametrize("n,gamma,L,K", [(6, 1, 0, 64), (12, 2, 8, 256), (20, 3, 25, 512), (33, 0, 5, 128)])
+def test_assign3d_sampler_matches_oracle(G, n, gamma, L, K):
+    """Customized 3D-assignment sampling (Algorithm 4) on the device: partial
+    assignment from the largest positive p (zeros left out, ties by index),
+    random completions and pairwise-interchange steps give the oracle's
+    candidates bit for bit; every candidate is feasible and its objective and
+    the incumbent are the oracle's."""
+    import torch
+    from oracle import assign3d_oracle as A3
+    P = I.assignment_3d(n, seed=n)
+    prob = G.Problem(P, _params(G, K_max=max(K, 1024), autotune=0))
+    rng = np.random.default_rng(n)
+    try:
+        inc = O.Incumbent()
+        for rnd in range(2):
+            p = rng.random(P.n).astype(np.float32)
+            p[rng.random(P.n) < 0.5] = 0.0
+            p[rng.random(P.n) < 0.05] = 0.25
+            v, z = prob.sample_eval_assign3d(n, K, gamma, L, p_override=torch.from_numpy(p).cuda(),
+                                             outputs=True)
+            X, zo = A3.assign3d_sample(p.astype(np.float64), P.c, n, K, gamma, L, seed=0, rnd=rnd)
+            assert np.array_equal(prob.candidates(), O.pack_bits(X)), rnd
+            vo, zo2 = O.evaluate(P, X)
+            assert np.all(vo == 0) and np.array_equal(zo, zo2)
+            assert np.array_equal(v.cpu().numpy()[0], vo) and np.array_equal(z.cpu().numpy()[0], zo), rnd
+            O.incumbent_update(inc, X, vo, zo, rnd, 0)
+            b = prob.best(0)
+            assert b["found"] and b["z"] == inc.z and b["l"] == inc.l and b["round"] == inc.rnd
+            assert np.array_equal(b["x"].astype(bool), inc.x)
+    finally:
+        prob.close()
+
+
+def test_assign3d_sampler_rejects_bad_sizes(G):
+    P = I.assignment_3d(4, seed=0)
+    prob = G.Problem(P, _params(G, autotune=0))
+    try:
+        for args in [(5, 64, 1, 0), (4, 64, 2000, 0), (4, 64, 1, -1), (4, 100, 1, 0)]:
+            with pytest.raises(G.GforsError, match="GFORS_E_ARG"):
+                prob.sample_eval_assign3d(*args)
+    finally:
+        prob.close()
