@@ -36,30 +36,50 @@ __global__ void __launch_bounds__(256)
 k_gnn_embed(int64_t n, int64_t m, int m1, const float *__restrict__ x, const float *__restrict__ y,
             const float *__restrict__ ct, const float *__restrict__ rt, float ictmax, float irtmax,
             const float *__restrict__ theta, uint16_t *__restrict__ Hv, uint16_t *__restrict__ Hc) {
-    const int lane = threadIdx.x & 63;
-    const float *Uv = theta + kGnnOffUv, *uv = theta + kGnnOffuv;
-    const float *Uc = theta + kGnnOffUc, *uc = theta + kGnnOffuc;
-    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-    for (int64_t node = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
-         node < n + m; node += nw) {
-        if (node < n) {
-            const float xi = x[node];
-            const float f0 = xi, f1 = 4.f * xi * (1.f - xi), f2 = ct[node] * ictmax;
-            float z = uv[lane] + Uv[3 * kGnnH + lane];
-            z = fmaf(f0, Uv[lane], z);
-            z = fmaf(f1, Uv[kGnnH + lane], z);
-            z = fmaf(f2, Uv[2 * kGnnH + lane], z);
-            Hv[node * kGnnH + lane] = f2bf(fmaxf(z, 0.f));
-        } else {
-            const int64_t j = node - n;
-            const float yj = y[j];
-            const float f0 = yj / (1.f + fabsf(yj)), f1 = rt[j] * irtmax, f2 = j >= m1 ? 1.f : 0.f;
-            float z = uc[lane] + Uc[3 * kGnnH + lane];
-            z = fmaf(f0, Uc[lane], z);
-            z = fmaf(f1, Uc[kGnnH + lane], z);
-            z = fmaf(f2, Uc[2 * kGnnH + lane], z);
-            Hc[j * kGnnH + lane] = f2bf(fmaxf(z, 0.f));
+    // 16 lanes per node, lane f = hidden units 4f..4f+3 (one 8-byte store)
+    const int f = threadIdx.x & 15;
+    float Wv[4][4], Wc[4][4], bv[4], bc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        bv[t] = theta[kGnnOffuv + 4 * f + t] + theta[kGnnOffUv + 3 * kGnnH + 4 * f + t];
+        bc[t] = theta[kGnnOffuc + 4 * f + t] + theta[kGnnOffUc + 3 * kGnnH + 4 * f + t];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            Wv[k][t] = theta[kGnnOffUv + k * kGnnH + 4 * f + t];
+            Wc[k][t] = theta[kGnnOffUc + k * kGnnH + 4 * f + t];
         }
+    }
+    const int64_t ng = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 4;
+    for (int64_t node = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 4;
+         node < n + m; node += ng) {
+        float f0, f1, f2;
+        const bool var = node < n;
+        if (var) {
+            const float xi = x[node];
+            f0 = xi;
+            f1 = 4.f * xi * (1.f - xi);
+            f2 = ct[node] * ictmax;
+        } else {
+            const int64_t j2 = node - n;
+            const float yj = y[j2];
+            f0 = yj / (1.f + fabsf(yj));
+            f1 = rt[j2] * irtmax;
+            f2 = j2 >= m1 ? 1.f : 0.f;
+        }
+        float h[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float z = var ? bv[t] : bc[t];
+            z = fmaf(f0, var ? Wv[0][t] : Wc[0][t], z);
+            z = fmaf(f1, var ? Wv[1][t] : Wc[1][t], z);
+            z = fmaf(f2, var ? Wv[2][t] : Wc[2][t], z);
+            h[t] = fmaxf(z, 0.f);
+        }
+        uint2 w;
+        w.x = static_cast<uint32_t>(f2bf(h[0])) | (static_cast<uint32_t>(f2bf(h[1])) << 16);
+        w.y = static_cast<uint32_t>(f2bf(h[2])) | (static_cast<uint32_t>(f2bf(h[3])) << 16);
+        uint16_t *dst = var ? Hv + node * kGnnH : Hc + (node - n) * kGnnH;
+        reinterpret_cast<uint2 *>(dst)[f] = w;
     }
 }
 
@@ -293,6 +313,9 @@ k_gnn_gemm(int64_t N, const uint16_t *__restrict__ A1, const uint16_t *__restric
            const uint16_t *__restrict__ BT, const float *__restrict__ bias, void *__restrict__ out1,
            void *__restrict__ out2) {
     __shared__ uint16_t sB[NO * KD];
+    // BF16 output tile of each wavefront (16 rows x 64 columns), so that rows
+    // are written with 16-byte stores instead of 2-byte ones
+    __shared__ uint16_t sO[4][16 * 64];
     for (int i = threadIdx.x; i < NO * KD / 4; i += blockDim.x)
         reinterpret_cast<uint2 *>(sB)[i] = reinterpret_cast<const uint2 *>(BT)[i];
     __syncthreads();
@@ -319,21 +342,50 @@ k_gnn_gemm(int64_t N, const uint16_t *__restrict__ A1, const uint16_t *__restric
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
             }
         }
+        if (OUTM == 0 && NO == 64) {
+            // lane (li, lk) holds rows lk..lk+3 of columns t*16 + li: through
+            // LDS, then lane L writes row L/4, columns 16 (L%4) .. +15
+            uint16_t *T = sO[wave];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int col = t * 16 + li;
+            for (int t = 0; t < NT; ++t) {
+                const int col = t * 16 + li;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t r = row0 + lk + j;
-                if (r >= N) continue;
-                float v = acc[t][j];
-                if (bias) v += bias[col];
-                if (RELU) v = fmaxf(v, 0.f);
-                void *o = col < 64 ? out1 : out2;
-                const int64_t idx = r * kGnnH + (col & 63);
-                if (OUTM == 0) static_cast<uint16_t *>(o)[idx] = f2bf(v);
-                else if (OUTM == 1) static_cast<float *>(o)[idx] = v;
-                else static_cast<float *>(o)[idx] += v;
+                for (int j = 0; j < 4; ++j) {
+                    float v = acc[t][j];
+                    if (bias) v += bias[col];
+                    if (RELU) v = fmaxf(v, 0.f);
+                    T[(lk + j) * 64 + col] = f2bf(v);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int rr = lane >> 2, cq = (lane & 3) * 16;
+            const int64_t r = row0 + rr;
+            if (r < N) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(T + rr * 64 + cq);
+                uint4 *dst = reinterpret_cast<uint4 *>(static_cast<uint16_t *>(out1) + r * kGnnH + cq);
+                dst[0] = src[0];
+                dst[1] = src[1];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        } else {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int col = t * 16 + li;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t r = row0 + lk + j;
+                    if (r >= N) continue;
+                    float v = acc[t][j];
+                    if (bias) v += bias[col];
+                    if (RELU) v = fmaxf(v, 0.f);
+                    void *o = col < 64 ? out1 : out2;
+                    const int64_t idx = r * kGnnH + (col & 63);
+                    if (OUTM == 0) static_cast<uint16_t *>(o)[idx] = f2bf(v);
+                    else if (OUTM == 1) static_cast<float *>(o)[idx] = v;
+                    else static_cast<float *>(o)[idx] += v;
+                }
             }
         }
     }
@@ -488,32 +540,60 @@ __global__ void __launch_bounds__(256)
 k_gnn_out(int64_t n, const uint16_t *__restrict__ Hv, const float *__restrict__ theta,
           float *__restrict__ logit, float *__restrict__ p, const float *__restrict__ target,
           float *__restrict__ dHv, float *__restrict__ part) {
+    // 16 lanes per node, lane f = hidden units 4f..4f+3; the 4 node groups of a
+    // wavefront add their contributions separately, in a fixed order at the end
     __shared__ float sh[4][66];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const float wo = theta[kGnnOffwo + lane];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, f = lane & 15;
+    float wo[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) wo[t] = theta[kGnnOffwo + 4 * f + t];
     const float bo = theta[kGnnOffbo];
-    float gw = 0.f, gb = 0.f, ls = 0.f;
+    float gw[4] = {0.f, 0.f, 0.f, 0.f}, gb = 0.f, ls = 0.f;
     const float inv_n = 1.f / static_cast<float>(n);
-    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-    for (int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6; i < n; i += nw) {
-        const float h = bf2f(Hv[i * kGnnH + lane]);
-        const float z = wave_sum(h * wo) + bo;
+    const int64_t ng = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 4;
+    for (int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 4; i < n; i += ng) {
+        const uint2 w = reinterpret_cast<const uint2 *>(Hv + i * kGnnH)[f];
+        const float h[4] = {__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                            __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u)};
+        float zz = h[0] * wo[0];
+        zz = fmaf(h[1], wo[1], zz);
+        zz = fmaf(h[2], wo[2], zz);
+        zz = fmaf(h[3], wo[3], zz);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) zz += __shfl_xor(zz, o, 16);
+        const float z = zz + bo;
         const float pz = 1.f / (1.f + __expf(-z));
-        if (lane == 0) {
+        if (f == 0) {
             if (logit) logit[i] = z;
             if (p) p[i] = pz;
         }
         if (target) {
             const float t = target[i];
             const float dz = (pz - t) * inv_n;
-            dHv[i * kGnnH + lane] = dz * wo;
-            gw += dz * h;
-            gb += dz;
-            ls += fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z))) - t * z;
+            reinterpret_cast<float4 *>(dHv + i * kGnnH)[f] = make_float4(dz * wo[0], dz * wo[1], dz * wo[2], dz * wo[3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) gw[q] += dz * h[q];
+            if (f == 0) {
+                gb += dz;
+                ls += fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z))) - t * z;
+            }
         }
     }
     if (!target) return;
-    sh[wave][lane] = gw;
+    // node groups of the wavefront (lanes f, f+16, f+32, f+48), in order
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        gw[q] += __shfl_down(gw[q], 16, 64);
+        gw[q] += __shfl_down(gw[q], 32, 64);
+    }
+    gb += __shfl_down(gb, 16, 64);
+    gb += __shfl_down(gb, 32, 64);
+    ls += __shfl_down(ls, 16, 64);
+    ls += __shfl_down(ls, 32, 64);
+    if (lane < 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh[wave][4 * f + q] = gw[q];
+    }
     if (lane == 0) { sh[wave][64] = gb; sh[wave][65] = ls; }
     __syncthreads();
     if (wave == 0) {
@@ -538,11 +618,13 @@ __global__ void k_gnn_out_reduce(int nparts, int64_t n, const float *__restrict_
 void launch_gnn_out(hipStream_t s, int64_t n, const uint16_t *Hv, const float *theta, float *logit,
                     float *p, const float *target, float *dHv, float *part, int max_parts,
                     float *grad, float *loss_out) {
-    int g = static_cast<int>((n * 64 + 255) / 256);
-    if (g > max_parts) g = max_parts;
+    // training keeps one partial per workgroup (max_parts of them); inference
+    // needs no partials and takes enough workgroups to fill the device
+    int64_t g = (n * 16 + 255) / 256;
+    if (g > (target ? max_parts : 8192)) g = target ? max_parts : 8192;
     if (g < 1) g = 1;
-    k_gnn_out<<<g, 256, 0, s>>>(n, Hv, theta, logit, p, target, dHv, part);
-    if (target) k_gnn_out_reduce<<<1, 128, 0, s>>>(g, n, part, grad, loss_out);
+    k_gnn_out<<<static_cast<int>(g), 256, 0, s>>>(n, Hv, theta, logit, p, target, dHv, part);
+    if (target) k_gnn_out_reduce<<<1, 128, 0, s>>>(static_cast<int>(g), n, part, grad, loss_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -605,7 +687,7 @@ void launch_gnn_embed_bwd(hipStream_t s, int64_t N, int is_var, int m1, const fl
 void launch_gnn_embed(hipStream_t s, int64_t n, int64_t m, int m1, const float *x, const float *y,
                       const float *ct, const float *rt, float ictmax, float irtmax,
                       const float *theta, uint16_t *Hv, uint16_t *Hc) {
-    int64_t blocks = ((n + m) * 64 + 255) / 256;
+    int64_t blocks = ((n + m) * 16 + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     if (blocks > 0)
         k_gnn_embed<<<static_cast<int>(blocks), 256, 0, s>>>(n, m, m1, x, y, ct, rt, ictmax, irtmax, theta, Hv, Hc);
