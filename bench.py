@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--snap-window", default=None,
                     help="ufl_learned: first,last fraction of each training run to take iterates from")
     ap.add_argument("--train-instances", type=int, default=200)
+    ap.add_argument("--net-every", type=int, default=1,
+                    help="ufl_learned: run the network at every n-th trigger (its p is reused in between)")
     ap.add_argument("--eval-seeds", default="",
                     help="ufl_learned: instance seeds of the evaluation instance (default: --seed)")
     ap.add_argument("--train-steps", type=int, default=3000)
@@ -507,8 +509,10 @@ def learned_experiment(a):
         bips.append(reform(P)[0])
     win = tuple(float(v) for v in a.snap_window.split(",")) if a.snap_window else (None, None)
     train_prm = params(instances.facility_location(40, 400, seed=1000), 50, 256)
-    samples = learned.collect(bips, train_prm, rounds=60, K=256, snapshots=6, window=win)
+    samples = learned.collect(bips, train_prm, rounds=60, K=256, snapshots=6, window=win,
+                              log=lambda msg: print(f"[ufl_learned] {msg}", file=sys.stderr, flush=True))
     t_collect = time.perf_counter() - t0
+    print(f"[ufl_learned] collected {len(samples)} pairs in {t_collect:.1f} s", file=sys.stderr, flush=True)
     net = gfors.GNN(seed=a.seed)
     loss0 = learned.mean_loss(net, samples[:64])
     t0 = time.perf_counter()
@@ -516,6 +520,8 @@ def learned_experiment(a):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     loss1 = learned.mean_loss(net, samples[:64])
+    print(f"[ufl_learned] trained {a.train_steps} steps in {t_train:.1f} s, loss {loss0:.4f} -> {loss1:.4f}",
+          file=sys.stderr, flush=True)
 
     nf, nc = (int(v) for v in a.ufl_eval.split(","))
     seeds = [int(v) for v in a.eval_seeds.split(",")] if a.eval_seeds else [a.seed]
@@ -527,7 +533,7 @@ def learned_experiment(a):
         G = gfors.Problem(model, params(full, a.k_int, a.K))
         plain = learned.run_plain(G, R, a.K)
         G.reset()
-        lrn = learned.run_learned(G, net, R, a.K)
+        lrn = learned.run_learned(G, net, R, a.K, net_every=a.net_every)
         G.final_round()
         best = G.best(0)
         zp = [z + c0 if z != learned.INT64_MAX else None for z in plain.z]
@@ -549,6 +555,7 @@ def learned_experiment(a):
             xfull = rf.repair(best["x"]) if a.relax == "mono" else rf.recover(best["x"])
             rec["recovered_point_objective"] = int(full.c @ xfull.astype(np.int64))
         per[str(sd)] = rec
+        print(f"[ufl_learned] seed {sd}: {json.dumps(rec)}", file=sys.stderr, flush=True)
         G.close()
     net.close()
     sp = [r["time_to_incumbent"]["speedup"] for r in per.values()
@@ -560,6 +567,7 @@ def learned_experiment(a):
                                     f"facility location {nf} x {nc} (customer rows relaxed to >= 1, "
                                     f"candidates repaired on the device)"),
                        "K": a.K, "k_int": a.k_int, "rounds": R, "eval_seeds": seeds,
+                       "network_every_n_triggers": a.net_every,
                        "train": f"{a.train_instances} instances 40 x 400, {len(samples)} pairs, {a.train_steps} Adam steps",
                        "snapshot_window": list(win)},
             "collect_s": round(t_collect, 2), "train_s": round(t_train, 2),

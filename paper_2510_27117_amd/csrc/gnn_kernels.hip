@@ -391,6 +391,96 @@ k_gnn_gemm(int64_t N, const uint16_t *__restrict__ A1, const uint16_t *__restric
     }
 }
 
+// Forward dense layer out = relu([H | S] W + bias) over N rows (H, S: BF16
+// [N][64]; W as BT[64 out][128 in] in LDS; BF16 out).  A wavefront owns 16
+// rows at a time; lane (li, kq) loads 16 bytes of row li four times: H and S
+// columns 8 kq .. 8 kq + 7 and 32 + 8 kq .. 32 + 8 kq + 7 (each load fills
+// 64-byte segments of 16 rows), and the next 16 rows' loads are issued before
+// the current rows' MFMAs.  The contraction order is permuted alike in A and
+// B: in the MFMA step that uses half h of load q, lane (li, kq) supplies
+// the k indices kb(q) + 8 kq + 4 h + j (j = 0..3) of both operands, with
+// kb = 0, 32, 64, 96 for H low, H high, S low, S high.  The result tile goes
+// through LDS and is written with 16-byte stores.
+__global__ void __launch_bounds__(256)
+k_gnn_dense_fwd(int64_t N, const uint16_t *__restrict__ H, const uint16_t *__restrict__ S,
+                const uint16_t *__restrict__ BT, const float *__restrict__ bias,
+                uint16_t *__restrict__ out) {
+    __shared__ uint16_t sB[64 * 128];
+    __shared__ uint16_t sO[4][16 * 64];
+    for (int i = threadIdx.x; i < 64 * 128 / 4; i += blockDim.x)
+        reinterpret_cast<uint2 *>(sB)[i] = reinterpret_cast<const uint2 *>(BT)[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, kq = lane >> 4;
+    float bcol[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) bcol[t] = bias ? bias[t * 16 + li] : 0.f;
+    const int64_t step = static_cast<int64_t>(gridDim.x) * 64;
+    auto load = [&](int64_t row0, uint4 *a) {
+        const int64_t ra = row0 + li;
+        if (ra < N) {
+            const uint4 *h = reinterpret_cast<const uint4 *>(H + ra * kGnnH);
+            const uint4 *sv = reinterpret_cast<const uint4 *>(S + ra * kGnnH);
+            a[0] = h[kq];
+            a[1] = h[4 + kq];
+            a[2] = sv[kq];
+            a[3] = sv[4 + kq];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    int64_t row0 = (static_cast<int64_t>(blockIdx.x) * 4 + wave) * 16;
+    uint4 cur[4];
+    if (row0 < N) load(row0, cur);
+    for (; row0 < N; row0 += step) {
+        uint4 nxt[4];
+        if (row0 + step < N) load(row0 + step, nxt);
+        f32x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kb = (q >> 1) * 64 + (q & 1) * 32 + 8 * kq;
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                const uint32_t w0 = hf ? cur[q].z : cur[q].x, w1 = hf ? cur[q].w : cur[q].y;
+                bf16x4 a;
+                a[0] = static_cast<short>(w0 & 0xFFFFu);
+                a[1] = static_cast<short>(w0 >> 16);
+                a[2] = static_cast<short>(w1 & 0xFFFFu);
+                a[3] = static_cast<short>(w1 >> 16);
+                const int kk = kb + 4 * hf;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&sB[(t * 16 + li) * 128 + kk]);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        uint16_t *T = sO[wave];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                T[(4 * kq + j) * 64 + t * 16 + li] = f2bf(fmaxf(acc[t][j] + bcol[t], 0.f));
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int rr = lane >> 2, cq = (lane & 3) * 16;
+        const int64_t r = row0 + rr;
+        if (r < N) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(T + rr * 64 + cq);
+            uint4 *dst = reinterpret_cast<uint4 *>(out + r * kGnnH + cq);
+            dst[0] = src[0];
+            dst[1] = src[1];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
+    }
+}
+
 static int gemm_grid(int64_t N) {
     int64_t b = (N + 63) / 64;
     if (b > 4096) b = 4096;
@@ -401,7 +491,7 @@ static int gemm_grid(int64_t N) {
 void launch_gnn_dense_fwd(hipStream_t s, int64_t N, const uint16_t *A1, const uint16_t *A2,
                           const uint16_t *BT, const float *bias, uint16_t *out) {
     if (N <= 0) return;
-    k_gnn_gemm<128, 64, true, 0><<<gemm_grid(N), 256, 0, s>>>(N, A1, A2, 64, BT, bias, out, nullptr);
+    k_gnn_dense_fwd<<<gemm_grid(N), 256, 0, s>>>(N, A1, A2, BT, bias, out);
 }
 
 // Backward through a dense layer: [dA1 | dA2] (+)= dZ W^T, with W^T given as

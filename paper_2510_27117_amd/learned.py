@@ -66,18 +66,23 @@ def run_plain(prob: "gfors.Problem", rounds: int, K: int) -> RunTrace:
     return tr
 
 
-def run_learned(prob: "gfors.Problem", net: "gfors.GNN", rounds: int, K: int) -> RunTrace:
+def run_learned(prob: "gfors.Problem", net: "gfors.GNN", rounds: int, K: int,
+                net_every: int = 1) -> RunTrace:
     """Learned Algorithm 1: per trigger K/2 candidates from x_k (rho advances)
-    and K/2 from the network's probabilities (extra round, rho unchanged)."""
+    and K/2 from the network's probabilities (extra round, rho unchanged).
+    The network runs at every net_every-th trigger; in between, its last p is
+    sampled again (fresh Philox rounds, so fresh candidates)."""
     torch = _torch()
     s = prob.stream
     k_int = prob.params.k_int
     Kh = K // 2
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(rounds + 1)]
     ev[0].record(s)
+    p = None
     for r in range(rounds):
         prob.pdhg_steps(k_int)
-        p = net.forward(prob)
+        if r % max(1, net_every) == 0 or p is None:
+            p = net.forward(prob)
         prob.sample_eval(Kh, None, trigger=True)
         prob.sample_eval(Kh, p, trigger=False)
         ev[r + 1].record(s)
@@ -115,6 +120,8 @@ def collect(bips, params, rounds: int, K: int, snapshots: int = 6, device: str =
                 log(f"instance {idx}: no incumbent, skipped")
             prob.close()
             continue
+        if log and (idx + 1) % 25 == 0:
+            log(f"collected {idx + 1} of {len(bips)} instances")
         t = torch.from_numpy(b["x"].astype(np.float32)).to(device)
         for x, y in xs:
             out.append(Sample(prob, torch.from_numpy(x).to(device),
