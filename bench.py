@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--seq-sample", type=int, default=8,
                     help="batched workloads: instances run one by one for the comparison")
-    ap.add_argument("--sub", default="setcover_small_e2e,knapsack_batch,ufl_mono",
+    ap.add_argument("--sub", default="setcover_small_e2e,knapsack_batch,ufl_mono,ufl_learned",
                     help="with the default workload: further workloads measured after it and reported as "
                          "compact sub-records ('' for none)")
     return ap.parse_args()
@@ -391,7 +391,8 @@ SUB_STEPS = {"knapsack_batch": (512, 50), "ufl_mono": (1024, 200)}
 def sub_records(a, subs, pre):
     """Compact records of further workloads (same measurement as the main
     line, fewer steps): the configured small set cover end to end, the
-    knapsack batch and facility location under the monotone relaxation."""
+    knapsack batch, facility location under the monotone relaxation, and the
+    learned proposal against the plain sampler on it."""
     import argparse as _ap
     out = {}
     keep = ("value", "unit", "ms_per_step", "candidates_per_s", "instance_iter_per_s", "config",
@@ -400,6 +401,20 @@ def sub_records(a, subs, pre):
     for w in subs:
         if w == "setcover_small_e2e":
             out[w] = c1_end_to_end(a)
+            continue
+        if w == "ufl_learned":
+            # the learned proposal at the configured facility-location size
+            # with a shortened training (50 instances, 1,000 Adam steps) and
+            # one evaluation seed, the network run every 4th trigger; the
+            # full record (200 instances, 3,000 steps, seeds 0-4, every 1st
+            # and 4th trigger) is profiles/ufl_learned_vs_plain.json
+            b = _ap.Namespace(**vars(a))
+            b.relax, b.train_instances, b.train_steps, b.eval_seeds = "mono", 50, 1000, str(a.seed)
+            b.tti_rounds, b.net_every, b.K, b.ufl_eval, b.snap_window = 300, 4, 1024, "1000,10000", None
+            r = learned_experiment(b)
+            out[w] = {k: r[k] for k in ("config", "train_loss_before", "train_loss_after", "per_seed",
+                                        "median_speedup_time_to_incumbent",
+                                        "median_learned_round_overhead")}
             continue
         if w not in SUB_STEPS:
             raise SystemExit(f"--sub: unknown workload {w}")
