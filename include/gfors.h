@@ -96,7 +96,14 @@ typedef struct {
  *                b = 1, each of its variables with c >= 0, in no other such row,
  *                in no equality row and with no positive coefficient in rows
  *                [0, repair_row0).  The workspace grows by 4 (nnz(A,B) + m1 + 1)
- *                bytes when >= 0. */
+ *                bytes when >= 0.
+ *   lu_wide_rows factorised TU problems only (gfors_create_problem_tu): a level
+ *                of a triangular solve with at least this many rows is solved
+ *                by a launch of its own (one thread per row); runs of narrower
+ *                levels share one one-workgroup launch.  Default 4096, >= 1.
+ *   lu_lds       factorised TU problems only: 1 (default) stages the solved
+ *                vector in LDS for a one-workgroup run when it fits in 64 KiB;
+ *                0 keeps it in global memory.  Results are identical. */
 typedef struct {
     double sigma, tau1, tau2;
     double rho_min, rho_max, rho_T, rho_p, rho_delta;
@@ -105,6 +112,7 @@ typedef struct {
     uint64_t seed;
     int32_t eval_mfma;
     int64_t repair_row0;
+    int32_t lu_wide_rows, lu_lds;
 } gfors_params;
 
 void gfors_default_params(gfors_params *p);
@@ -392,6 +400,49 @@ typedef struct gfors_tu gfors_tu;
 int gfors_tu_create(const gfors_csr *A, const int64_t *b, const gfors_csr *B, const int64_t *d,
                     const gfors_csr *Q, const int64_t *c, int64_t n, const int64_t *pivots,
                     gfors_tu **out);
+/* Factorised form (Remark of Sec. 2.4.1), flags = GFORS_TU_FACTORED: the pivot
+ * block is factorised once as M = L U (rows and columns in the elimination
+ * order k; a column of fewest active entries and its shortest active row
+ * pivot first; every entry of L and U in {-1, 0, 1}, else E_ARG: B_J is not
+ * TU) and S is never formed: on the device S xbar = -M^{-1} (B_JIbar xbar) and
+ * S^T v = -B_JIbar^T M^{-T} v are level-scheduled triangular solves inside
+ * every PDHG step (gfors_create_problem_tu).  The reformulated model is the
+ * same as without the flag (same rows in the same order, same kept bound
+ * rows, same c' and c'_0); its row 2-norms and kept bound rows are computed
+ * exactly on the host one row at a time, so host memory stays O(nnz(A, B, Q)
+ * + nnz(L, U)).  Q must be symmetric.  gfors_tu_dims gives -1 for the entry
+ * counts; gfors_tu_export copies only b', d', c' and kept_vars (E_STATE when
+ * a matrix pointer is given); gfors_tu_export_q gives E_STATE. */
+#define GFORS_TU_FACTORED 1
+int gfors_tu_create_ex(const gfors_csr *A, const int64_t *b, const gfors_csr *B, const int64_t *d,
+                       const gfors_csr *Q, const int64_t *c, int64_t n, const int64_t *pivots,
+                       int32_t flags, gfors_tu **out);
+/* info[10] of a factorised handle: {pivots r, nnz(L) strict, nnz(U) strict,
+ * levels of the L forward, U backward, U^T forward and L^T backward solves,
+ * nnz(B_JIbar), nnz(S) (counted, not stored), nnz of the reformulated rows}. */
+int gfors_tu_factor_info(gfors_tu *U, int64_t *info);
+/* A GFORS problem on the kept variables of a factorised handle (the handle
+ * must outlive nothing: the problem copies what it needs).  Everything of
+ * gfors_create_problem holds for it (one instance, the same calls and graph
+ * replay, the same Preprocess, PDHG, sampling, evaluation and incumbent on
+ * the reformulated model), with these differences:
+ *   - Preprocess: the row 2-norms come from the host (exact); ||K'|| and
+ *     ||Q'|| are FP64 power iterations whose products lift v to
+ *     (v, S v) and project with S^T (FP64 triangular solves);
+ *   - each PDHG step solves with L, U (lift of x_k) and U^T, L^T (S^T of the
+ *     pivot part of the gradient), in FP32, level by level;
+ *   - EvalBest solves every candidate's pivot variables exactly (int32) and
+ *     checks the original rows on the lifted integer point: the violation
+ *     count and objective equal those of the explicit reformulated model;
+ *   - no repair_row0, autotuning, launch-shape control, 3D-assignment
+ *     sampler or learned proposal (E_ARG).
+ * gfors_workspace_bytes_tu gives the workspace size for params.  Errors as
+ * gfors_create_problem, plus E_ARG for a handle made without
+ * GFORS_TU_FACTORED and E_INFEAS_ROW for a reformulated row with no
+ * coefficient that no point satisfies. */
+int gfors_workspace_bytes_tu(gfors_tu *U, const gfors_params *params, size_t *bytes);
+int gfors_create_problem_tu(gfors_tu *U, const gfors_params *params, void *workspace,
+                            size_t workspace_bytes, void *hip_stream, gfors_problem **out);
 /* dims[7] = {n', m1', m2', nnz(A'), nnz(B'), c'_0, nnz(Q')}. */
 int gfors_tu_dims(gfors_tu *U, int64_t *dims);
 /* Copy the reformulated model into caller arrays sized from gfors_tu_dims

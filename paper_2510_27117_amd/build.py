@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgfors.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["gfors_api.cpp", "pdhg_kernels.hip", "sample_eval_kernels.hip", "gnn_kernels.hip",
-           "gfors_tu.cpp", "gfors_mono.cpp"]
+           "gfors_tu.cpp", "gfors_mono.cpp", "gfors_lu.cpp", "lu_kernels.hip"]
 ARCH = os.environ.get("GFORS_ARCH", "gfx950")
 
 

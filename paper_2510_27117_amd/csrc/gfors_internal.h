@@ -218,4 +218,58 @@ void launch_argmin_update(hipStream_t s, int T, int K, int W, const int32_t *vio
 void launch_extract_best(hipStream_t s, int64_t n, int T, const int *var_inst, const uint64_t *X,
                          DevInst di, uint8_t *xbest);
 
+// ---------------------------------------------------------------------------
+// Factorised TU reformulation (lu_kernels.hip)
+// ---------------------------------------------------------------------------
+// A run of a level-scheduled in-place triangular solve: levels [a, b) in one
+// workgroup (wide = 0), or positions [a, b) of one wide level (wide = 1).
+struct LuSeg {
+    int wide, a, b;
+};
+// Device arrays of one solve (positions in level order) and its launch plan
+// (host array).
+struct LuSolve {
+    int r = 0, nseg = 0;
+    int use_lds = 1;   // stage the vector in LDS for one-workgroup runs when it fits
+    const int *row = nullptr, *ptr = nullptr, *ent = nullptr, *lvl = nullptr;
+    const LuSeg *seg = nullptr;
+};
+// LDS that a one-workgroup run may stage the solved vector in.
+constexpr size_t kLuLdsBytes = 64 * 1024;
+
+template <typename T>
+void launch_lu_trsv(hipStream_t s, const LuSolve &sv, T *x);
+void launch_lu_mv_f32(hipStream_t s, int lpr, int nrows, const int *rp, const int *ci, const int *val,
+                      const float *x, float *y, float sgn);
+void launch_lu_mv_f64(hipStream_t s, int lpr, int nrows, const int *rp, const int *ci, const int *val,
+                      const double *x, double *y, double sgn, bool accumulate);
+void launch_lu_tail_grad(hipStream_t s, int lpr, bool hasq, int r, int nk, const int *rpT, const int *ciT,
+                         const int *valT, const float *wy, const int *rpQ, const int *ciQ, const int *valQ,
+                         const float *x, const float *two_so, float *v);
+void launch_lu_primal(hipStream_t s, int lpr, bool hasq, int nk, const int *rpT, const int *ciT,
+                      const int *valT, const float *wy, const int *rpQ, const int *ciQ, const int *valQ,
+                      const int *rpB, const int *ciB, const int *valB, const float *u, const float *x_in,
+                      float *x_out, float *xbar, const float *ct, const float *tau1, const float *two_so,
+                      const double *rho, DevCounters *ctr);
+void launch_lu_xbar_tail(hipStream_t s, int r, int nk, const float *x_new, const float *x_old, float *xbar);
+void launch_lu_diff64(hipStream_t s, int n, const float *a, const float *b, double *d);
+void launch_lu_res_rows(hipStream_t s, const Tiles &rt, int m1, const int *rp, const int *ci, const int *val,
+                        const double *omega64, const int64_t *rhs, const double *d1, const double *d2,
+                        const float *y_prev, const float *y, const double *tau2d, double *part);
+void launch_lu_res_vars(hipStream_t s, const Tiles &vt, const double *qd, const float *x, const float *xp,
+                        const double *rho, const double *tau1d, const double *two_sod, double *part);
+void launch_lu_trsm(hipStream_t s, const LuSolve &sv, int *XI, int K);
+void launch_lu_eval_rhs(hipStream_t s, int r, int K, const int *rp, const int *ci, const int *val,
+                        const int64_t *dJ, const uint64_t *X, int *XI);
+void launch_lu_eval_rows(hipStream_t s, int nch, int K, int nk, int m1, const int *ch_row, const int *ch_e0,
+                         const int *ch_e1, const int *ch_slot, const int *ci, const int *val, const int64_t *rhs,
+                         const uint64_t *X, const int *XI, int *vcnt, int64_t *rsum);
+void launch_lu_eval_multi(hipStream_t s, int nslot, int K, int m1, const int *slot_row, const int64_t *rhs,
+                          const int64_t *rsum, int *vcnt);
+void launch_lu_eval_obj(hipStream_t s, int r, int K, const int64_t *c_tail, int64_t c0, const int *XI,
+                        int nqch, int nk, const int *qch_row, const int *qch_e0, const int *qch_e1,
+                        const int *ciQ, const int *valQ, const uint64_t *X, int64_t *zx);
+void launch_lu_fill_i64(hipStream_t s, int64_t *p, int64_t v, int64_t n);
+void launch_lu_fill_i32(hipStream_t s, int *p, int v, int64_t n);
+
 }  // namespace gfors

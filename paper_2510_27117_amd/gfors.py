@@ -31,7 +31,8 @@ class gfors_params(ctypes.Structure):
                 ("rho_min", c_dbl), ("rho_max", c_dbl), ("rho_T", c_dbl), ("rho_p", c_dbl),
                 ("rho_delta", c_dbl), ("k_int", c_i32), ("K_max", c_i32), ("power_iters", c_i32),
                 ("hist_cap", c_i32), ("autotune", c_i32), ("x0", c_dbl), ("seed", c_u64),
-                ("eval_mfma", c_i32), ("repair_row0", c_i64)]
+                ("eval_mfma", c_i32), ("repair_row0", c_i64), ("lu_wide_rows", c_i32),
+                ("lu_lds", c_i32)]
 
 
 EXPORTS = [
@@ -48,7 +49,10 @@ EXPORTS = [
     "gfors_tu_export_q", "gfors_sample_eval_assign3d",
     "gfors_tu_last_error", "gfors_mono_rows", "gfors_mono_repair", "gfors_mono_last_error",
     "gfors_philox_throughput", "gfors_eval_planes", "gfors_create_problem_static",
+    "gfors_tu_create_ex", "gfors_tu_factor_info", "gfors_workspace_bytes_tu", "gfors_create_problem_tu",
 ]
+
+GFORS_TU_FACTORED = 1
 
 KERNEL_NAMES = ["dual", "primal", "sample", "eval_cover", "eval_general", "eval_quad",
                 "reduce_cand", "argmin_update", "extract_best"]
@@ -112,6 +116,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(L, nm).argtypes = [c_vp, c_vp]
     L.gfors_tu_create.argtypes = [P(gfors_csr), c_vp, P(gfors_csr), c_vp, P(gfors_csr), c_vp, c_i64,
                                   c_vp, P(c_vp)]
+    L.gfors_tu_create_ex.argtypes = [P(gfors_csr), c_vp, P(gfors_csr), c_vp, P(gfors_csr), c_vp, c_i64,
+                                     c_vp, c_i32, P(c_vp)]
+    L.gfors_tu_factor_info.argtypes = [c_vp, c_vp]
+    L.gfors_workspace_bytes_tu.argtypes = [c_vp, P(gfors_params), P(ctypes.c_size_t)]
+    L.gfors_create_problem_tu.argtypes = [c_vp, P(gfors_params), c_vp, ctypes.c_size_t, c_vp, P(c_vp)]
     L.gfors_tu_dims.argtypes = [c_vp, c_vp]
     L.gfors_tu_export.argtypes = [c_vp] + [c_vp] * 10
     L.gfors_tu_export_q.argtypes = [c_vp, c_vp, c_vp, c_vp]
@@ -195,11 +204,14 @@ class Problem:
     (one live problem per device, at most GFORS_STATIC_WS_BYTES)."""
 
     def __init__(self, bip, params: Optional[gfors_params] = None, device: str = "cuda:0",
-                 stream=None, static_ws: bool = False):
+                 stream=None, static_ws: bool = False, tu=None):
         import torch
         L = load_library()
         self.torch = torch
         self.params = params if params is not None else default_params()
+        if tu is not None:
+            self._init_tu(tu, device, stream)
+            return
         self.n = int(bip.n)
         self.m1, self.m2 = int(bip.m1), int(bip.m2)
         self.T = int(bip.num_instances)
@@ -243,6 +255,30 @@ class Problem:
                     ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()),
                     ctypes.c_size_t(self.ws_bytes), ctypes.c_void_p(self.stream.cuda_stream),
                     ctypes.byref(h)))
+        self.handle = h
+        self.m = self.m1 + self.m2
+
+    def _init_tu(self, tu, device, stream):
+        """A problem in the factorised TU form (gfors_create_problem_tu) on the
+        kept variables of a TUReformulation made with factored=True."""
+        torch = self.torch
+        L = load_library()
+        self.tu = tu          # the handle must stay alive while the problem is created
+        self.n, self.m1, self.m2 = tu.n_reduced, tu.m1, tu.m2
+        self.T = 1
+        self.device = torch.device(device)
+        nbytes = ctypes.c_size_t(0)
+        _check(L.gfors_workspace_bytes_tu(tu.handle, ctypes.byref(self.params), ctypes.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        self.static_ws = False
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.inst_offsets = np.array([[0, 0, 0], [self.n, self.m1, self.m2]], dtype=np.int64)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.gfors_create_problem_tu(tu.handle, ctypes.byref(self.params),
+                                             ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_size_t(self.ws_bytes),
+                                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.handle = h
         self.m = self.m1 + self.m2
 
@@ -652,9 +688,13 @@ class TUReformulation:
     """Eliminates one pivot variable per chosen equality row (gfors_tu_create:
     B_J totally unimodular, B_JI invertible; Q allowed).  ``model`` is the
     reformulated BIP (instances.BIP); ``constant`` is c'_0;
-    ``recover(x_reduced)`` maps a reduced 0/1 point back."""
+    ``recover(x_reduced)`` maps a reduced 0/1 point back.  With
+    ``factored=True`` (gfors_tu_create_ex, GFORS_TU_FACTORED) no explicit
+    model is formed (``model`` is None; ``b``, ``d``, ``c`` hold b', d', c');
+    ``problem()`` makes the device problem that applies the LU of the pivot
+    block at every step, ``info`` gives the factor and level counts."""
 
-    def __init__(self, bip, pivots):
+    def __init__(self, bip, pivots, factored: bool = False):
         from . import instances as _inst
         L = load_library()
         keep: list = []
@@ -667,15 +707,32 @@ class TUReformulation:
         c = np.ascontiguousarray(bip.c, dtype=np.int64)
         h = ctypes.c_void_p()
         Q = _csr(bip.Q, keep)
-        rc = L.gfors_tu_create(ctypes.byref(A) if A else None, _ptr(b), ctypes.byref(B), _ptr(d),
-                               ctypes.byref(Q) if Q else None, _ptr(c), int(bip.n), _ptr(piv),
-                               ctypes.byref(h))
+        rc = L.gfors_tu_create_ex(ctypes.byref(A) if A else None, _ptr(b), ctypes.byref(B), _ptr(d),
+                                  ctypes.byref(Q) if Q else None, _ptr(c), int(bip.n), _ptr(piv),
+                                  GFORS_TU_FACTORED if factored else 0, ctypes.byref(h))
         if rc != GFORS_OK:
             raise GforsError(f"{_ERRS.get(rc, rc)}: {L.gfors_tu_last_error().decode()}")
         self.handle = h
+        self.factored = bool(factored)
+        self.n_full = int(bip.n)
         dims = np.zeros(7, dtype=np.int64)
         L.gfors_tu_dims(h, _ptr(dims))
         n2, m1, m2, nA, nB, c0, nQ = (int(v) for v in dims)
+        self.n_reduced, self.m1, self.m2 = n2, m1, m2
+        self.constant = c0
+        if factored:
+            # no explicit rows: b', d', c' and the kept variables only
+            bb, dd = np.zeros(max(m1, 1), np.int64), np.zeros(max(m2, 1), np.int64)
+            cc, kept = np.zeros(n2, np.int64), np.zeros(n2, np.int64)
+            L.gfors_tu_export(h, None, None, None, _ptr(bb), None, None, None, _ptr(dd), _ptr(cc), _ptr(kept))
+            self.b, self.d, self.c, self.kept = bb[:m1], dd[:m2], cc, kept
+            self.model = None
+            info = np.zeros(10, dtype=np.int64)
+            _check(L.gfors_tu_factor_info(h, _ptr(info)))
+            self.info = dict(zip(("pivots", "nnz_L", "nnz_U", "levels_L", "levels_U", "levels_Ut",
+                                  "levels_Lt", "nnz_BJ", "nnz_S", "nnz_reformulated_rows"),
+                                 (int(v) for v in info)))
+            return
         Arp, Aci, Aval, bb = (np.zeros(m1 + 1, np.int64), np.zeros(max(nA, 1), np.int32),
                               np.zeros(max(nA, 1), np.int32), np.zeros(max(m1, 1), np.int64))
         Brp, Bci, Bval, dd = (np.zeros(m2 + 1, np.int64), np.zeros(max(nB, 1), np.int32),
@@ -696,9 +753,12 @@ class TUReformulation:
             L.gfors_tu_export_q(h, _ptr(Qrp), _ptr(Qci), _ptr(Qval))
             model.Q = _inst.CSR(n2, n2, Qrp, Qci, Qval)
         self.model = model
-        self.constant = c0
         self.kept = kept
-        self.n_full = int(bip.n)
+
+    def problem(self, params=None, device: str = "cuda:0", stream=None) -> "Problem":
+        """The device problem of a factorised reformulation (gfors_create_problem_tu)."""
+        assert self.factored, "problem() needs factored=True (else hand self.model to Problem)"
+        return Problem(None, params, device=device, stream=stream, tu=self)
 
     def recover(self, x_reduced) -> np.ndarray:
         xr = np.ascontiguousarray(x_reduced, dtype=np.uint8)

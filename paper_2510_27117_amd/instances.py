@@ -277,7 +277,8 @@ def facility_location(n_f: int, n_c: int, seed: int, scale: int = 1000,
                meta={"n_f": n_f, "n_c": n_c, "tu_pivots": pivots})
 
 
-def assignment_qap_like(n: int, seed: int, q_density: float = 0.02, q_max: int = 5) -> BIP:
+def assignment_qap_like(n: int, seed: int, q_density: float = 0.02, q_max: int = 5,
+                        tree: str = "path", q_per_var: Optional[float] = None) -> BIP:
     """2D assignment with a sparse symmetric quadratic term and one knapsack row.
 
     Variables x_ij (index i*n + j); equality rows: sum_j x_ij = 1 (row i) then
@@ -285,9 +286,15 @@ def assignment_qap_like(n: int, seed: int, q_density: float = 0.02, q_max: int =
     unimodular).  c_ij ~ U{1..100}; Q symmetric with off-diagonal entries
     ~ U{-q_max..q_max} w.p. q_density, zero diagonal; one row
     -sum w_ij x_ij >= -cap with w ~ U{1..20}, cap = 12 n.
-    meta["tu_pivots"]: a spanning tree of the bipartite graph as pivot columns
-    (row i -> x_ii, column j >= 1 -> x_{j-1,j}, column 0 kept), so the pivot
-    block is not a signed identity."""
+    meta["tu_pivots"]: a spanning tree of the bipartite graph as pivot columns,
+    so the pivot block is not a signed identity.  tree="path": row i -> x_ii,
+    column j >= 1 -> x_{j-1,j} (a path of 2n - 1 edges: the deepest tree);
+    tree="random": a random recursive tree rooted at column 0 (each node, in
+    random order, hangs from a uniformly chosen earlier node of the other side:
+    depth O(log n)), each node's row pivoting on the edge to its parent.
+    Column 0's row is kept either way.  q_per_var: when given, Q has about
+    q_per_var entries per variable drawn as random pairs (for sizes where
+    scanning all pairs is too slow) instead of each pair w.p. q_density."""
     rng = np.random.default_rng(seed)
     N = n * n
     c = rng.integers(1, 101, size=N).astype(np.int64)
@@ -295,9 +302,16 @@ def assignment_qap_like(n: int, seed: int, q_density: float = 0.02, q_max: int =
     rows = np.concatenate([idx // n, n + idx % n])
     cols = np.concatenate([idx, idx])
     B = csr_from_coo(2 * n, N, rows, cols, None)
-    iu, ju = np.triu_indices(N, k=1)
-    pick = rng.random(iu.size) < q_density
-    iu, ju = iu[pick], ju[pick]
+    if q_per_var is None:
+        iu, ju = np.triu_indices(N, k=1)
+        pick = rng.random(iu.size) < q_density
+        iu, ju = iu[pick], ju[pick]
+    else:
+        cnt = int(q_per_var * N / 2)
+        a, b2 = rng.integers(0, N, size=cnt), rng.integers(0, N, size=cnt)
+        a, b2 = np.minimum(a, b2), np.maximum(a, b2)
+        key = np.unique(a[a != b2] * N + b2[a != b2])
+        iu, ju = key // N, key % N
     w = rng.integers(-q_max, q_max + 1, size=iu.size)
     nz = w != 0
     iu, ju, w = iu[nz], ju[nz], w[nz]
@@ -305,9 +319,28 @@ def assignment_qap_like(n: int, seed: int, q_density: float = 0.02, q_max: int =
     wk = rng.integers(1, 21, size=N)
     A = csr_from_coo(1, N, np.zeros(N, dtype=np.int64), idx, -wk)
     piv = np.empty(2 * n, dtype=np.int64)
-    piv[:n] = np.arange(n) * n + np.arange(n)
-    piv[n] = -1
-    piv[n + 1:] = (np.arange(1, n) - 1) * n + np.arange(1, n)
+    if tree == "path":
+        piv[:n] = np.arange(n) * n + np.arange(n)
+        piv[n] = -1
+        piv[n + 1:] = (np.arange(1, n) - 1) * n + np.arange(1, n)
+    elif tree == "random":
+        # nodes 0..n-1 = row constraints i, n..2n-1 = column constraints j; root = column 0
+        trng = np.random.default_rng(seed + 7919)
+        placed = ([], [n])                      # placed row nodes, placed column nodes
+        pending = list(trng.permutation(np.r_[np.arange(n), np.arange(n + 1, 2 * n)]))
+        piv[n] = -1
+        while pending:
+            v = int(pending.pop(0))
+            other = placed[1] if v < n else placed[0]
+            if not other:
+                pending.append(v)
+                continue
+            u = other[int(trng.integers(0, len(other)))]
+            i, j = (v, u - n) if v < n else (u, v - n)
+            piv[v] = i * n + j
+            placed[0 if v < n else 1].append(v)
+    else:
+        raise ValueError(f"unknown tree {tree!r}")
     return BIP(n=N, c=c, A=A, b=np.array([-12 * n], dtype=np.int64), B=B,
                d=np.ones(2 * n, dtype=np.int64), Q=Q, name=f"assignq_n{n}_s{seed}",
                meta={"tu_pivots": piv})
