@@ -172,6 +172,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     sell_carve(P->sellKS_want, m, kXcdSlices, nnzK, P->sellKS_cap, P->sellKS_buf);
     sell_carve(P->sellT_want, n, 1, nnzK, P->sellT_cap, P->sellT_buf);
     P->val16 = cv.take<int16_t>(nnzK);
+    P->ell = cv.take<int>((T == 1 && nnzQ == 0 && nnzK <= 8 * n) ? nnzK : 0);
     P->sellT_val16 = cv.take<int16_t>(P->sellT_want ? P->sellT_cap : 0);
     P->rowinv32 = cv.take<float>(m);
     P->bx_words = ceil_div(n + 64 * kXcdSlices, 64) + 1;
@@ -850,6 +851,21 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         P->colT_deg = n > 0 ? rpT[1] - rpT[0] : 0;
         for (int64_t i = 1; i < n && P->colT_deg; ++i)
             if (rpT[i + 1] - rpT[i] != P->colT_deg) P->colT_deg = 0;
+        // the primal step with wy staged in LDS: unit coefficients, every
+        // variable in the same number (<= 8) of rows, one instance, no Q
+        if (P->unitK && !P->hasQ && T == 1 && m > 0 && P->colT_deg >= 1 && P->colT_deg <= 8 &&
+            P->nnzK <= 8 * n) {
+            const int deg = P->colT_deg;
+            std::vector<int> ell(static_cast<size_t>(deg) * n);
+            for (int64_t i = 0; i < n; ++i)
+                for (int u = 0; u < deg; ++u) ell[static_cast<size_t>(u) * n + i] = ciT[static_cast<size_t>(i) * deg + u];
+            if ((rc = upload(s, P->ell, ell.data(), static_cast<int64_t>(ell.size())))) return rc;
+            if ((rc = sync(P))) return rc;
+            int dev = 0, lds_max = 0;
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            P->lds_slice = primal_lds_slice(static_cast<size_t>(lds_max));
+        }
         auto classes = [](const std::vector<int> &o, const std::vector<int> &ptr, int64_t cnt, int &h, int &md) {
             int64_t k = 0;
             while (k < cnt && ptr[o[k] + 1] - ptr[o[k]] >= kGnnHeavyLen) ++k;
@@ -1184,7 +1200,11 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
         P->by_fresh = true;
     };
     bool xbar_bits = false;
-    if (P->cfg.bits_primal >= 2 && sell && kmode != 0 && !P->hasQ) {
+    if (P->cfg.bits_primal == 4 && P->lds_slice > 0 && !sell && slices == 1) {
+        launch_primal_lds(s, static_cast<int>(P->n), static_cast<int>(P->m), P->colT_deg, P->lds_slice, P->ell,
+                          P->wy, x_in, x_out, xbar, P->ct, tau1, P->di.rho, ctr, xbits);
+        xbar_bits = xbits != nullptr;
+    } else if (P->cfg.bits_primal >= 2 && sell && kmode != 0 && !P->hasQ) {
         need_by();
         launch_sell_bits(s, P->sellT, 2, P->unitK, batched, static_cast<int>(P->m), P->wy,
                          reinterpret_cast<const uint32_t *>(P->by), nullptr, 0, nullptr, nullptr,
@@ -1245,6 +1265,7 @@ static int bits_ok_primal(gfors_problem *P, int slices, int sell, int bits) {
     if (bits == 0) return 1;
     if (P->m == 0 || P->hasQ || slices != 1) return 0;
     if (bits == 1) return (!sell && (P->m + 31) / 32 * 4 <= kMaxLdsBitmapBytes) ? 1 : 0;
+    if (bits == 4) return (!sell && P->lds_slice > 0) ? 1 : 0;   // wy staged in LDS slices
     if (bits != 2 && bits != 3) return 0;
     return (sell && P->sellT.ptr && P->sellT.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
 }
@@ -1330,6 +1351,11 @@ static int autotune(gfors_problem *P) {
             P->cfg.bits_primal = b;
             const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 1, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
             if (t < best) { best = t; best_bits = b; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 1; }
+        }
+        if (bits_ok_primal(P, 1, 0, 4)) {
+            P->cfg.bits_primal = 4;
+            const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 0, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
+            if (t < best) { best = t; best_bits = 4; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 0; }
         }
         P->cfg.bits_primal = best_bits;
     }
@@ -1776,8 +1802,8 @@ int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
         return fail(GFORS_E_ARG, "no SELL copy of the transposed rows");
     if (cfg[6] < 0 || cfg[6] > 3 || !bits_ok_dual(P, cfg[2], cfg[4], cfg[6]))
         return fail(GFORS_E_ARG, "bitmap dual: 1 needs the sliced SELL layout, 2 a SELL layout, and the slice bitmap must fit in LDS");
-    if (cfg[7] < 0 || cfg[7] > 3 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
-        return fail(GFORS_E_ARG, "bitmap primal: 1 needs the fused CSR layout, 2 the SELL layout; both need Q = 0 and a dual bitmap that fits in LDS");
+    if (cfg[7] < 0 || cfg[7] > 4 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
+        return fail(GFORS_E_ARG, "bitmap primal: 1 needs the fused CSR layout, 2 the SELL layout; both need Q = 0 and a dual bitmap that fits in LDS; 4 (wy staged in LDS) needs the fused layout, unit coefficients, every variable in the same number (<= 8) of rows, one instance and Q = 0");
     P->cfg.lpr_dual = cfg[0];
     P->cfg.lpr_primal = cfg[1];
     P->cfg.slices_dual = cfg[2];

@@ -179,6 +179,10 @@ struct gfors_problem {
     bool use16 = false;
     bool dense_cols = false;   // some variable's rows are one contiguous range (colT0 is read)
     int colT_deg = 0;          // every variable has this many rows (> 0): row ranges are computed
+    // entry-major copy of the transposed rows (ell[u n + i]) for the primal step
+    // with wy staged in LDS, and its slice length (0: that variant unavailable)
+    int *ell = nullptr;
+    int lds_slice = 0;
     int16_t *val16 = nullptr, *sellT_val16 = nullptr;
     float *rowinv32 = nullptr;          // 1/||a_j|| (0 for a zero row): the GNN's edge weights
     float gnn_ictmax = 1.f, gnn_irtmax = 1.f;

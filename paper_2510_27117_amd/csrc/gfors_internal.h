@@ -149,6 +149,14 @@ void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, 
                         const float *ct, float tau1, const float *tau1_inst, const double *rho,
                         const int *var_inst, DevCounters *ctr, uint64_t *xbits, int deg);
 
+// Primal step with wy staged in LDS slices of SL rows (unit coefficients,
+// every variable in deg <= 8 rows, one instance, no Q); ell[u n + i] = the
+// u-th row of variable i (ascending).  Returns false for an unsupported deg.
+int primal_lds_slice(size_t lds_limit);
+bool launch_primal_lds(hipStream_t s, int n, int m, int deg, int SL, const int *ell, const float *wy,
+                       const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                       const double *rho, DevCounters *ctr, uint64_t *xbits);
+
 void launch_copy_f32(hipStream_t s, float *dst, const float *src, int64_t n);
 void launch_set_xbar(hipStream_t s, int64_t n, const float *x, const float *xp, float *xbar);
 void launch_fill_f32(hipStream_t s, float *dst, float v, int64_t n);
@@ -230,15 +238,18 @@ struct LuSeg {
 // (host array).
 struct LuSolve {
     int r = 0, nseg = 0;
-    int use_lds = 1;   // stage the vector in LDS for one-workgroup runs when it fits
+    int use_lds = 1;   // stage the vector and the run in LDS for one-workgroup runs when they fit
     const int *row = nullptr, *ptr = nullptr, *ent = nullptr, *lvl = nullptr;
     const LuSeg *seg = nullptr;
+    // host copies: first position of each level, first entry of each level's first position
+    const int *hlvl = nullptr, *hptr_at_lvl = nullptr;
 };
 // LDS that a one-workgroup run may stage the solved vector in.
 constexpr size_t kLuLdsBytes = 64 * 1024;
 
+// In-place solve; with xbar given, xbar[k] = 2 x[k] - xold[k] afterwards.
 template <typename T>
-void launch_lu_trsv(hipStream_t s, const LuSolve &sv, T *x);
+void launch_lu_trsv(hipStream_t s, const LuSolve &sv, T *x, const T *xold = nullptr, T *xbar = nullptr);
 void launch_lu_mv_f32(hipStream_t s, int lpr, int nrows, const int *rp, const int *ci, const int *val,
                       const float *x, float *y, float sgn);
 void launch_lu_mv_f64(hipStream_t s, int lpr, int nrows, const int *rp, const int *ci, const int *val,
@@ -251,6 +262,10 @@ void launch_lu_primal(hipStream_t s, int lpr, bool hasq, int nk, const int *rpT,
                       const int *rpB, const int *ciB, const int *valB, const float *u, const float *x_in,
                       float *x_out, float *xbar, const float *ct, const float *tau1, const float *two_so,
                       const double *rho, DevCounters *ctr);
+void launch_lu_dual_heavy(hipStream_t s, int nchunk, int nheavy, int m1, const int *ch_row, const int *ch_e0,
+                          const int *ch_e1, const int *first, const int *order, const int *rowc0, const int *rp,
+                          const int *ci, const int *val, const float *xbar, float *part, const float *omega,
+                          const float *rt, float tau2, const float *y_in, float *y_out, float *wy);
 void launch_lu_xbar_tail(hipStream_t s, int r, int nk, const float *x_new, const float *x_old, float *xbar);
 void launch_lu_diff64(hipStream_t s, int n, const float *a, const float *b, double *d);
 void launch_lu_res_rows(hipStream_t s, const Tiles &rt, int m1, const int *rp, const int *ci, const int *val,

@@ -25,6 +25,7 @@ namespace gfh {
 struct LuDevSolve {
     int *row = nullptr, *ptr = nullptr, *ent = nullptr, *lvl = nullptr;
     std::vector<LuSeg> seg;
+    std::vector<int> hlvl, hptr_at_lvl;   // host: level starts, entry start of each level
     int r = 0, use_lds = 1;
     LuSolve view() const {
         LuSolve v;
@@ -36,6 +37,8 @@ struct LuDevSolve {
         v.ent = ent;
         v.lvl = lvl;
         v.seg = seg.data();
+        v.hlvl = hlvl.data();
+        v.hptr_at_lvl = hptr_at_lvl.data();
         return v;
     }
 };
@@ -61,6 +64,12 @@ struct LuForm {
     int64_t *c_tail = nullptr;
     int64_t c0 = 0;
     int lpr_dual = 1, lpr_bj = 1, lpr_bjt = 1, lpr_tail = 1, lpr_primal = 1;
+    int heavy_rows = 0;   // lifted rows of kHeavyLen+ entries (a prefix of dual_order)
+    // their chunks of kLuRowChunk entries (a workgroup each) and chunk sums
+    int nhch = 0;
+    int *hch_row = nullptr, *hch_e0 = nullptr, *hch_e1 = nullptr, *hch_first = nullptr;
+    float *hpart = nullptr;
+    std::vector<int> h_hch_row, h_hch_e0, h_hch_e1, h_hch_first;
     // host copies
     std::vector<int> h_ch_row, h_ch_e0, h_ch_e1, h_ch_slot, h_slot_row, h_qch_row, h_qch_e0, h_qch_e1;
 };
@@ -71,7 +80,8 @@ void lu_destroy(LuForm *L) { delete L; }
 
 namespace {
 
-constexpr int kLuChunk = 2048;     // entries per evaluation chunk of a row
+constexpr int kLuChunk = 256;      // entries per evaluation chunk of a row (a wavefront each)
+constexpr int kLuRowChunk = 4096;  // entries per chunk of a long row in the dual step (a workgroup each)
 
 int pick_lpr(double avg) {
     if (avg >= 48) return 64;
@@ -173,6 +183,11 @@ size_t lu_carve(gfors_problem *P, Carver &cv, const gftu::TuFactored &F, const g
     L.qch_e0 = cv.take<int>(L.nqch);
     L.qch_e1 = cv.take<int>(L.nqch);
     L.c_tail = cv.take<int64_t>(r);
+    L.hch_row = cv.take<int>(L.nhch);
+    L.hch_e0 = cv.take<int>(L.nhch);
+    L.hch_e1 = cv.take<int>(L.nhch);
+    L.hch_first = cv.take<int>(L.heavy_rows + 1);
+    L.hpart = cv.take<float>(L.nhch);
     return cv.off;
 }
 
@@ -187,14 +202,42 @@ void lu_plan(gfors_problem *P, const gftu::TuFactored &F, const gfors_params &pr
     std::vector<int> dummy;
     chunk_rows(F.QLrp, L.h_qch_row, L.h_qch_e0, L.h_qch_e1, nullptr, &dummy, true);
     L.nch = static_cast<int>(L.h_ch_row.size());
+    {
+        // long lifted rows (kHeavyLen+ entries), longest first, and their chunks
+        const int64_t m = static_cast<int64_t>(F.KLrp.size()) - 1;
+        std::vector<int> ord(m);
+        for (int64_t j = 0; j < m; ++j) ord[j] = static_cast<int>(j);
+        std::stable_sort(ord.begin(), ord.end(), [&](int a2, int b2) {
+            return F.KLrp[a2 + 1] - F.KLrp[a2] > F.KLrp[b2 + 1] - F.KLrp[b2];
+        });
+        L.heavy_rows = 0;
+        while (L.heavy_rows < m && F.KLrp[ord[L.heavy_rows] + 1] - F.KLrp[ord[L.heavy_rows]] >= kHeavyLen) ++L.heavy_rows;
+        L.h_hch_first.assign(1, 0);
+        for (int h = 0; h < L.heavy_rows; ++h) {
+            const int j = ord[h];
+            for (int e = F.KLrp[j]; e < F.KLrp[j + 1]; e += kLuRowChunk) {
+                L.h_hch_row.push_back(j);
+                L.h_hch_e0.push_back(e);
+                L.h_hch_e1.push_back(std::min(F.KLrp[j + 1], e + kLuRowChunk));
+            }
+            L.h_hch_first.push_back(static_cast<int>(L.h_hch_row.size()));
+        }
+        L.nhch = static_cast<int>(L.h_hch_row.size());
+    }
     L.nslot = static_cast<int>(L.h_slot_row.size());
     L.nqch = static_cast<int>(L.h_qch_row.size());
     const gftu::HostTrsv *hs[4] = {&F.Lf, &F.Ub, &F.Utf, &F.Ltb};
     LuDevSolve *ds[4] = {&L.Lf, &L.Ub, &L.Utf, &L.Ltb};
     for (int q = 0; q < 4; ++q) {
-        ds[q]->seg = plan_segments(hs[q]->lvl, std::max(1, prm.lu_wide_rows));
+        // a solve with no entries and a unit diagonal is the identity: nothing to launch
+        bool ident = hs[q]->ent.empty();
+        for (size_t p = 0; p < hs[q]->row.size() && ident; ++p) ident = (hs[q]->row[p] & 1) == 0;
+        ds[q]->seg = ident ? std::vector<LuSeg>() : plan_segments(hs[q]->lvl, std::max(1, prm.lu_wide_rows));
         ds[q]->r = static_cast<int>(F.r);
         ds[q]->use_lds = prm.lu_lds ? 1 : 0;
+        ds[q]->hlvl.assign(hs[q]->lvl.begin(), hs[q]->lvl.end());
+        ds[q]->hptr_at_lvl.resize(hs[q]->lvl.size());
+        for (size_t l = 0; l < hs[q]->lvl.size(); ++l) ds[q]->hptr_at_lvl[l] = hs[q]->ptr[hs[q]->lvl[l]];
     }
     HostTiles hs_, hv;
     build_tiles_items(hs_, 0, ceil_div(F.nk, 4), nullptr, kSampleTQ, kSampleTQ, 0);
@@ -288,6 +331,61 @@ int lu_device_norms(gfors_problem *P) {
     return GFORS_OK;
 }
 
+// Lanes per row of the SpMV-like kernels of a step, timed on the problem
+// (HIP events, 5 launches each after one untimed); the state is reset after.
+int lu_autotune(gfors_problem *P) {
+    LuForm &L = *P->lu;
+    hipStream_t s = P->stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto timeit = [&](const std::function<void()> &f) -> float {
+        f();
+        (void)hipEventRecord(e0, s);
+        for (int q = 0; q < 5; ++q) f();
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    const int nk = static_cast<int>(L.nk), r = static_cast<int>(L.r), m = static_cast<int>(P->m);
+    const int m1 = static_cast<int>(P->m1);
+    const float tau2 = static_cast<float>(P->tau2[0]);
+    auto best_of = [&](std::initializer_list<int> opts, int &slot, const std::function<void(int)> &run) {
+        float bt = 1e30f;
+        int bl = slot;
+        for (int l : opts) {
+            const float t = timeit([&] { run(l); });
+            if (t < bt) { bt = t; bl = l; }
+        }
+        slot = bl;
+    };
+    if (m > L.heavy_rows)
+        best_of({1, 2, 4, 8, 16, 32, 64}, L.lpr_dual, [&](int l) {
+            launch_dual(s, l, false, false, m, m1, P->rp, P->ci, P->val, nullptr, P->omega, P->rt, P->xbar,
+                        P->ybuf[0], P->ybuf[1], P->wy, tau2, P->di.tau2, P->row_inst, L.heavy_rows > 0 ? kHeavyLen : 0);
+        });
+    if (r > 0) {
+        best_of({1, 4, 16, 64}, L.lpr_tail, [&](int l) {
+            launch_lu_tail_grad(s, l, L.hasQ, r, nk, P->rpT, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ,
+                                P->xbuf[0], P->di.two_so, L.v32);
+        });
+        best_of({1, 4, 16, 64}, L.lpr_bj, [&](int l) {
+            launch_lu_mv_f32(s, l, r, L.BJrp, L.BJci, L.BJval, P->xbuf[0], P->xbuf[1] + nk, -1.f);
+        });
+    }
+    best_of({1, 4, 16, 64}, L.lpr_primal, [&](int l) {
+        launch_lu_primal(s, l, L.hasQ, nk, P->rpT, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ, L.BJTrp,
+                         L.BJTci, L.BJTval, L.v32, P->xbuf[0], P->xbuf[1], P->xbar, P->ct, P->di.tau1,
+                         P->di.two_so, P->di.rho, P->ctr_scratch);
+    });
+    HIP_TRY(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return sync(P);
+}
+
 }  // namespace
 
 namespace gfh {
@@ -314,9 +412,16 @@ void lu_enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *tm) {
         if (res) launch_copy_f32(s, P->xsave, P->xbar, nfull);
         const int a = P->cur, bn = 1 - P->cur;
         TB(0);
-        if (m > 0)
-            launch_dual(s, L.lpr_dual, false, false, m, m1, P->rp, P->ci, P->val, nullptr, P->omega, P->rt,
-                        P->xbar, P->ybuf[a], P->ybuf[bn], P->wy, tau2, P->di.tau2, P->row_inst, 0);
+        if (m > 0) {
+            if (L.heavy_rows > 0)
+                launch_lu_dual_heavy(s, L.nhch, L.heavy_rows, m1, L.hch_row, L.hch_e0, L.hch_e1, L.hch_first,
+                                     P->dual_order, P->rowc0, P->rp, P->ci, P->val, P->xbar, L.hpart, P->omega,
+                                     P->rt, tau2, P->ybuf[a], P->ybuf[bn], P->wy);
+            if (L.heavy_rows < m)
+                launch_dual(s, L.lpr_dual, false, false, m, m1, P->rp, P->ci, P->val, nullptr, P->omega, P->rt,
+                            P->xbar, P->ybuf[a], P->ybuf[bn], P->wy, tau2, P->di.tau2, P->row_inst,
+                            L.heavy_rows > 0 ? kHeavyLen : 0);
+        }
         TE(0);
         TB(1);
         launch_lu_tail_grad(s, L.lpr_tail, L.hasQ, r, nk, P->rpT, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ,
@@ -326,8 +431,10 @@ void lu_enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *tm) {
         launch_lu_primal(s, L.lpr_primal, L.hasQ, nk, P->rpT, P->ciT, P->valT, P->wy, P->rpQ, P->ciQ, P->valQ,
                          L.BJTrp, L.BJTci, L.BJTval, L.v32, P->xbuf[a], P->xbuf[bn], P->xbar, P->ct,
                          P->di.tau1, P->di.two_so, P->di.rho, P->ctr);
-        lift32(P, P->xbuf[bn]);
-        launch_lu_xbar_tail(s, r, nk, P->xbuf[bn], P->xbuf[a], P->xbar);
+        // lift of x_k; the last run also writes xbar's lifted part 2 t(x_k) - t(x_{k-1})
+        launch_lu_mv_f32(s, L.lpr_bj, r, L.BJrp, L.BJci, L.BJval, P->xbuf[bn], P->xbuf[bn] + nk, -1.f);
+        launch_lu_trsv<float>(s, L.Lf.view(), P->xbuf[bn] + nk);
+        launch_lu_trsv<float>(s, L.Ub.view(), P->xbuf[bn] + nk, P->xbuf[a] + nk, P->xbar + nk);
         TE(1);
         if (res) {
             // s^y and the primal gap on lift(xbar_{k-1} - x_k), lift(x_k)
@@ -567,11 +674,31 @@ int gfors_create_problem_tu(gfors_tu *U, const gfors_params *prm, void *ws, size
         if ((rc = upload(s, P->rowinv2_d, r2.data(), m))) return rc;
         if ((rc = sync(P))) return rc;
     }
-    // launch shapes
+    // launch shapes; rows of kHeavyLen+ entries a workgroup each, longest first
     auto avg = [](int64_t tot, int64_t cnt) { return cnt > 0 ? static_cast<double>(tot) / cnt : 1.0; };
     {
+        std::vector<int> ord(m), c0v(m, -1);
+        for (int64_t j = 0; j < m; ++j) ord[j] = static_cast<int>(j);
+        std::stable_sort(ord.begin(), ord.end(), [&](int a2, int b2) {
+            return F.KLrp[a2 + 1] - F.KLrp[a2] > F.KLrp[b2 + 1] - F.KLrp[b2];
+        });
+        int64_t light_nnz = 0;
+        for (int64_t q = 0; q < m; ++q) {
+            const int j = ord[q], len = F.KLrp[j + 1] - F.KLrp[j];
+            if (q >= L.heavy_rows) light_nnz += len;
+            bool dense = len > 0;
+            for (int e = F.KLrp[j] + 1; e < F.KLrp[j + 1] && dense; ++e) dense = F.KLci[e] == F.KLci[F.KLrp[j]] + (e - F.KLrp[j]);
+            if (dense) c0v[j] = F.KLci[F.KLrp[j]];
+        }
+        if ((rc = upload(s, P->dual_order, ord.data(), m))) return rc;
+        if ((rc = upload(s, P->rowc0, c0v.data(), m))) return rc;
+        if ((rc = upload(s, L.hch_row, L.h_hch_row.data(), L.nhch))) return rc;
+        if ((rc = upload(s, L.hch_e0, L.h_hch_e0.data(), L.nhch))) return rc;
+        if ((rc = upload(s, L.hch_e1, L.h_hch_e1.data(), L.nhch))) return rc;
+        if ((rc = upload(s, L.hch_first, L.h_hch_first.data(), L.heavy_rows + 1))) return rc;
+        if ((rc = sync(P))) return rc;
         int lp = 1;
-        const double a = avg(nnzK, m);
+        const double a = avg(light_nnz, m - L.heavy_rows);
         while (lp < 64 && lp * 2 <= a) lp *= 2;
         L.lpr_dual = lp;
     }
@@ -648,6 +775,10 @@ int gfors_create_problem_tu(gfors_tu *U, const gfors_params *prm, void *ws, size
         if ((rc = sync(P))) return rc;
     }
     if ((rc = gfors_reset(P))) return rc;   // iterate, incumbent, counters; lifts the iterate
+    if (prm->autotune) {
+        if ((rc = lu_autotune(P))) return rc;
+        if ((rc = gfors_reset(P))) return rc;
+    }
     *out = guard.release();
     return GFORS_OK;
 }

@@ -60,24 +60,46 @@ __device__ __forceinline__ void trsv_row(int p, const int *__restrict__ row, con
 }  // namespace
 
 // Levels [l0, l1) of a solve in one workgroup.  LDSX: the whole vector (r
-// entries) is staged in LDS for the run and written back at its end.
+// entries) and the run's rows and entries are staged in LDS first (their
+// loads are independent of each other), so that each level costs LDS reads
+// and a barrier only; the vector is written back at the end, and with xbar
+// given also xbar[k] = 2 x[k] - xold[k] (the lifted part of xbar, fused into
+// the last run of a lift).
 template <typename T, bool LDSX>
 __global__ void __launch_bounds__(256)
 k_lu_trsv_seg(const int *__restrict__ row, const int *__restrict__ ptr, const int *__restrict__ ent,
-              const int *__restrict__ lvl, int l0, int l1, T *__restrict__ x, int r) {
-    extern __shared__ unsigned char lu_lds[];
-    T *xs = LDSX ? reinterpret_cast<T *>(lu_lds) : x;
-    if (LDSX) {
-        for (int i = threadIdx.x; i < r; i += 256) xs[i] = x[i];
-        __syncthreads();
+              const int *__restrict__ lvl, int l0, int l1, T *__restrict__ x, int r,
+              const T *__restrict__ xold, T *__restrict__ xbar) {
+    extern __shared__ __align__(16) unsigned char lu_lds[];
+    if (!LDSX) {
+        for (int l = l0; l < l1; ++l) {
+            const int p1 = lvl[l + 1];
+            for (int p = lvl[l] + static_cast<int>(threadIdx.x); p < p1; p += 256) trsv_row(p, row, ptr, ent, x);
+            __syncthreads();
+        }
+        return;
     }
+    const int pb = lvl[l0], pe = lvl[l1];
+    const int np = pe - pb, eb = ptr[pb], ne = ptr[pe] - eb;
+    T *xs = reinterpret_cast<T *>(lu_lds);
+    int *srow = reinterpret_cast<int *>(xs + r);
+    int *sptr = srow + np;          // np + 1 entries, relative to eb
+    int *sent = sptr + np + 1;
+    for (int i = threadIdx.x; i < r; i += 256) xs[i] = x[i];
+    for (int i = threadIdx.x; i < np; i += 256) srow[i] = row[pb + i];
+    for (int i = threadIdx.x; i <= np; i += 256) sptr[i] = ptr[pb + i] - eb;
+    for (int i = threadIdx.x; i < ne; i += 256) sent[i] = ent[eb + i];
+    __syncthreads();
     for (int l = l0; l < l1; ++l) {
-        const int p1 = lvl[l + 1];
-        for (int p = lvl[l] + static_cast<int>(threadIdx.x); p < p1; p += 256) trsv_row(p, row, ptr, ent, xs);
+        const int p1 = lvl[l + 1] - pb;
+        for (int p = lvl[l] - pb + static_cast<int>(threadIdx.x); p < p1; p += 256) trsv_row(p, srow, sptr, sent, xs);
         __syncthreads();
     }
-    if (LDSX)
-        for (int i = threadIdx.x; i < r; i += 256) x[i] = xs[i];
+    for (int i = threadIdx.x; i < r; i += 256) {
+        const T v = xs[i];
+        x[i] = v;
+        if (xbar) xbar[i] = static_cast<T>(2) * v - xold[i];
+    }
 }
 
 // One wide level: rows [p0, p1) of the level order, one thread each.
@@ -89,24 +111,47 @@ k_lu_trsv_level(const int *__restrict__ row, const int *__restrict__ ptr, const 
     if (p < p1) trsv_row(p, row, ptr, ent, x);
 }
 
+// xbar[k] = 2 x[k] - xold[k], k < r (when it could not ride on the last run).
 template <typename T>
-void launch_lu_trsv(hipStream_t s, const LuSolve &sv, T *x) {
+__global__ void k_lu_xbar(int r, const T *__restrict__ x, const T *__restrict__ xold, T *__restrict__ xbar) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < r) xbar[k] = static_cast<T>(2) * x[k] - xold[k];
+}
+
+// LDS bytes of a staged run (vector, rows, pointers, entries).
+size_t lu_seg_lds_bytes(const LuSolve &sv, const LuSeg &sg, size_t tsize) {
+    const int np = sv.hlvl[sg.b] - sv.hlvl[sg.a];
+    const int ne = sv.hptr_at_lvl[sg.b] - sv.hptr_at_lvl[sg.a];
+    return static_cast<size_t>(sv.r) * tsize + 4u * static_cast<size_t>(2 * np + 1 + ne);
+}
+
+template <typename T>
+void launch_lu_trsv(hipStream_t s, const LuSolve &sv, T *x, const T *xold, T *xbar) {
     const int r = sv.r;
-    const bool lds = sv.use_lds && static_cast<size_t>(r) * sizeof(T) <= kLuLdsBytes;
+    bool fused = false;
     for (int g = 0; g < sv.nseg; ++g) {
         const LuSeg &sg = sv.seg[g];
+        const bool last = g == sv.nseg - 1;
         if (sg.wide) {
             const int p0 = sg.a, p1 = sg.b;
             k_lu_trsv_level<T><<<(p1 - p0 + 255) / 256, 256, 0, s>>>(sv.row, sv.ptr, sv.ent, p0, p1, x);
-        } else if (lds) {
-            k_lu_trsv_seg<T, true><<<1, 256, static_cast<size_t>(r) * sizeof(T), s>>>(sv.row, sv.ptr, sv.ent, sv.lvl, sg.a, sg.b, x, r);
+            continue;
+        }
+        const size_t lds = lu_seg_lds_bytes(sv, sg, sizeof(T));
+        if (sv.use_lds && lds <= kLuLdsBytes) {
+            const bool f = last && xbar != nullptr;
+            k_lu_trsv_seg<T, true><<<1, 256, lds, s>>>(sv.row, sv.ptr, sv.ent, sv.lvl, sg.a, sg.b, x, r,
+                                                        f ? xold : nullptr, f ? xbar : nullptr);
+            fused = fused || f;
         } else {
-            k_lu_trsv_seg<T, false><<<1, 256, 0, s>>>(sv.row, sv.ptr, sv.ent, sv.lvl, sg.a, sg.b, x, r);
+            k_lu_trsv_seg<T, false><<<1, 256, 0, s>>>(sv.row, sv.ptr, sv.ent, sv.lvl, sg.a, sg.b, x, r, nullptr,
+                                                       nullptr);
         }
     }
+    if (xbar && !fused && r > 0) k_lu_xbar<T><<<(r + 255) / 256, 256, 0, s>>>(r, x, xold, xbar);
 }
-template void launch_lu_trsv<float>(hipStream_t, const LuSolve &, float *);
-template void launch_lu_trsv<double>(hipStream_t, const LuSolve &, double *);
+template void launch_lu_trsv<float>(hipStream_t, const LuSolve &, float *, const float *, float *);
+template void launch_lu_trsv<double>(hipStream_t, const LuSolve &, double *, const double *, double *);
 
 // y[i] (+)= sgn * sum_e val_e x[col_e] over rows [0, nrows), LPR lanes per row.
 template <int LPR, typename TI, typename TO, bool ACC>
@@ -205,6 +250,55 @@ k_lu_primal(int nk, const int *__restrict__ rpT, const int *__restrict__ ciT, co
         xbar[i] = 2.f * xn - xi;
     }
     if (tid == 0) ctr->k += 1;
+}
+
+// Dual step of the long lifted rows (kHeavyLen+ entries), cut into chunks
+// spread over the device: k_lu_rowpart sums a_e xbar_{c_e} of one chunk per
+// workgroup; k_lu_heavy_combine adds a row's chunk sums in order and applies
+//   y_j = Pi(y_j + tau2 (rt_j - omega_j s_j)),  wy_j = omega_j y_j.
+__global__ void __launch_bounds__(256)
+k_lu_rowpart(const int *__restrict__ ch_row, const int *__restrict__ ch_e0, const int *__restrict__ ch_e1,
+             const int *__restrict__ rowc0, const int *__restrict__ rp, const int *__restrict__ ci,
+             const int *__restrict__ val, const float *__restrict__ xbar, float *__restrict__ part) {
+    __shared__ float ws[4];
+    const int c = blockIdx.x;
+    const int j = ch_row[c], e0 = ch_e0[c], e1 = ch_e1[c];
+    const int c0 = rowc0[j], b0 = rp[j];
+    float s = 0.f;
+#pragma unroll 4
+    for (int e = e0 + static_cast<int>(threadIdx.x); e < e1; e += 256) {
+        const int col = c0 >= 0 ? c0 + (e - b0) : ci[e];
+        s = fmaf(static_cast<float>(val[e]), xbar[col], s);
+    }
+    s = lu_group_sum<64>(s);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[c] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+__global__ void k_lu_heavy_combine(int nheavy, int m1, const int *__restrict__ order,
+                                   const int *__restrict__ first, const float *__restrict__ part,
+                                   const float *__restrict__ omega, const float *__restrict__ rt, float tau2,
+                                   const float *__restrict__ y_in, float *__restrict__ y_out,
+                                   float *__restrict__ wy) {
+    const int h = blockIdx.x * 64 + threadIdx.x;
+    if (h >= nheavy) return;
+    const int j = order[h];
+    float sum = 0.f;
+    for (int c = first[h]; c < first[h + 1]; ++c) sum += part[c];
+    const float om = omega[j];
+    float y = y_in[j] + tau2 * (rt[j] - om * sum);
+    if (j < m1) y = fmaxf(y, 0.f);
+    y_out[j] = y;
+    wy[j] = om * y;
+}
+void launch_lu_dual_heavy(hipStream_t s, int nchunk, int nheavy, int m1, const int *ch_row, const int *ch_e0,
+                          const int *ch_e1, const int *first, const int *order, const int *rowc0, const int *rp,
+                          const int *ci, const int *val, const float *xbar, float *part, const float *omega,
+                          const float *rt, float tau2, const float *y_in, float *y_out, float *wy) {
+    if (nchunk <= 0) return;
+    k_lu_rowpart<<<nchunk, 256, 0, s>>>(ch_row, ch_e0, ch_e1, rowc0, rp, ci, val, xbar, part);
+    k_lu_heavy_combine<<<(nheavy + 63) / 64, 64, 0, s>>>(nheavy, m1, order, first, part, omega, rt, tau2, y_in,
+                                                         y_out, wy);
 }
 
 // xbar's lifted part: t(xbar_k) = 2 t(x_k) - t(x_{k-1}) (the lift is linear).
@@ -351,6 +445,7 @@ k_lu_eval_rhs(int r, int W, int K, const int *__restrict__ rp, const int *__rest
     if (g >= r * W) return;
     const int k = g / W, w = g - k * W;
     int acc = static_cast<int>(dJ[k]);
+#pragma unroll 8
     for (int e = rp[k]; e < rp[k + 1]; ++e) {
         const uint64_t word = X[static_cast<int64_t>(ci[e]) * W + w];
         if ((word >> lane) & 1ull) acc -= val[e];
@@ -438,6 +533,7 @@ k_lu_eval_rows(int nch, int W, int K, int nk, int m1, const int *__restrict__ ch
     const int c = g / W, w = g - c * W;
     const int j = ch_row[c];
     int64_t acc = 0;
+#pragma unroll 8
     for (int e = ch_e0[c]; e < ch_e1[c]; ++e)
         acc += static_cast<int64_t>(val[e]) * lifted_val(ci[e], nk, X, W, w, lane, XI, K);
     const int slot = ch_slot[c];
@@ -466,14 +562,23 @@ k_lu_eval_multi(int nslot, int K, int m1, const int *__restrict__ slot_row, cons
 //        + <z_l, Q z_l>                               (k_lu_eval_quad, Q rows in chunks)
 // on the lifted integer point z_l, so that the total is the reformulated
 // objective <x', Q' x'> + <c', x'> = f(x) - c'_0.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_lu_eval_lin(int r, int K, const int64_t *__restrict__ c_tail, int64_t c0, const int *__restrict__ XI,
               int64_t *__restrict__ zx) {
-    const int l = blockIdx.x * 256 + threadIdx.x;
-    if (l >= K) return;
-    int64_t acc = -c0;
-    for (int k = 0; k < r; ++k) acc += c_tail[k] * static_cast<int64_t>(XI[static_cast<int64_t>(k) * K + l]);
-    zx[l] = acc;
+    // workgroup = 64 candidates; its 8 wavefronts split the positions k
+    __shared__ int64_t part[8][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int l = 64 * blockIdx.x + lane;
+    int64_t acc = 0;
+#pragma unroll 4
+    for (int k = wv; k < r; k += 8) acc += c_tail[k] * static_cast<int64_t>(XI[static_cast<int64_t>(k) * K + l]);
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0) {
+        int64_t t = -c0;
+        for (int j = 0; j < 8; ++j) t += part[j][lane];
+        zx[l] = t;
+    }
 }
 __global__ void __launch_bounds__(256)
 k_lu_eval_quad(int nch, int W, int K, int nk, const int *__restrict__ ch_row, const int *__restrict__ ch_e0,
@@ -512,7 +617,7 @@ void launch_lu_eval_multi(hipStream_t s, int nslot, int K, int m1, const int *sl
 void launch_lu_eval_obj(hipStream_t s, int r, int K, const int64_t *c_tail, int64_t c0, const int *XI,
                         int nqch, int nk, const int *qch_row, const int *qch_e0, const int *qch_e1,
                         const int *ciQ, const int *valQ, const uint64_t *X, int64_t *zx) {
-    k_lu_eval_lin<<<(K + 255) / 256, 256, 0, s>>>(r, K, c_tail, c0, XI, zx);
+    k_lu_eval_lin<<<K / 64, 512, 0, s>>>(r, K, c_tail, c0, XI, zx);
     const int W = K / 64;
     const int64_t waves = static_cast<int64_t>(nqch) * W;
     if (waves > 0)

@@ -990,6 +990,129 @@ void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Primal step with the dual vector staged in LDS (unit coefficients, every
+// variable in exactly DEG rows, one instance, no Q).  The random gathers of
+// wy are the cost of the plain kernels: each is an L1 -> L2 request.  Here a
+// workgroup owns VPT x 1024 consecutive variables (thread t: variables
+// i0 + 1024 v + t), keeps their DEG row indices in registers (read once from
+// an entry-major copy, ell[u n + i]), and walks the rows in slices of SL: the
+// slice of wy is loaded into LDS with coalesced 16-byte loads (the next slice
+// is in flight while the current one is used: two LDS buffers), and every
+// variable consumes its entries that fall in the slice from LDS.  A
+// variable's rows are ascending, so its terms are added in entry order, as in
+// the plain kernels.  The epilogue is the one of k_primal (box projection,
+// extrapolation) plus the nonzero bitmap of xbar for the next dual step.
+// ---------------------------------------------------------------------------
+template <int VPT, int DEG>
+__global__ void __launch_bounds__(1024)
+k_primal_lds(int n, int m, int SL, const int *__restrict__ ell, const float *__restrict__ wy,
+             const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ xbar,
+             const float *__restrict__ ct, float tau1, const double *__restrict__ rho,
+             DevCounters *__restrict__ ctr, uint64_t *__restrict__ xbits) {
+    extern __shared__ float4 stage4[];
+    float *stage = reinterpret_cast<float *>(stage4);
+    const int t = static_cast<int>(threadIdx.x);
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * (VPT * 1024);
+    if (blockIdx.x == 0 && t == 0) ctr->k += 1;
+    int row[VPT][DEG];
+    float sum[VPT];
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) {
+        const int64_t i = i0 + v * 1024 + t;
+        sum[v] = 0.f;
+#pragma unroll
+        for (int u = 0; u < DEG; ++u) row[v][u] = i < n ? ell[static_cast<int64_t>(u) * n + i] : 0x7fffffff;
+    }
+    const int nslice = (m + SL - 1) / SL;
+    const int q4 = SL / 4096;   // float4 loads per thread per slice (SL a multiple of 4096)
+    float4 pre[4];
+    auto fetch = [&](int sl) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= q4) break;
+            const int e = sl * SL + (q * 1024 + t) * 4;   // first row of this float4
+            if (e + 3 < m) pre[q] = *reinterpret_cast<const float4 *>(wy + e);
+            else {
+                pre[q].x = e < m ? wy[e] : 0.f;
+                pre[q].y = e + 1 < m ? wy[e + 1] : 0.f;
+                pre[q].z = e + 2 < m ? wy[e + 2] : 0.f;
+                pre[q].w = 0.f;
+            }
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= q4) break;
+            stage4[buf * (SL / 4) + q * 1024 + t] = pre[q];
+        }
+    };
+    fetch(0);
+    put(0);
+    __syncthreads();
+    for (int sl = 0; sl < nslice; ++sl) {
+        if (sl + 1 < nslice) fetch(sl + 1);
+        const float *cur = stage + (sl & 1) * SL;
+        const int lo = sl * SL, hi = lo + SL;
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+#pragma unroll
+            for (int u = 0; u < DEG; ++u) {
+                if (row[v][0] >= hi) break;
+                sum[v] += cur[row[v][0] - lo];
+#pragma unroll
+                for (int w = 0; w < DEG - 1; ++w) row[v][w] = row[v][w + 1];
+                row[v][DEG - 1] = 0x7fffffff;
+            }
+        }
+        if (sl + 1 < nslice) put((sl + 1) & 1);
+        __syncthreads();
+    }
+    const float rh = static_cast<float>(rho[0]);
+    const int lane = t & 63;
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) {
+        const int64_t i = i0 + v * 1024 + t;
+        float xb = 0.f;
+        if (i < n) {
+            const float xi = x_in[i];
+            const float g = ct[i] + rh - sum[v] - 2.f * rh * xi;
+            const float xn = fminf(fmaxf(xi - tau1 * g, 0.f), 1.f);
+            x_out[i] = xn;
+            xb = 2.f * xn - xi;
+            xbar[i] = xb;
+        }
+        if (xbits) {
+            const uint64_t bal = __ballot(i < n && xb != 0.f);
+            const int64_t w0 = i0 + v * 1024 + (t & ~63);
+            if (lane == 0 && w0 < n) xbits[w0 >> 6] = bal;
+        }
+    }
+}
+
+// Rows per LDS slice of k_primal_lds for a workgroup LDS limit (two buffers).
+int primal_lds_slice(size_t lds_limit) {
+    if (lds_limit >= 2 * 16384 * sizeof(float)) return 16384;
+    if (lds_limit >= 2 * 8192 * sizeof(float)) return 8192;
+    return 4096;
+}
+
+bool launch_primal_lds(hipStream_t s, int n, int m, int deg, int SL, const int *ell, const float *wy,
+                       const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                       const double *rho, DevCounters *ctr, uint64_t *xbits) {
+    constexpr int VPT = 8;
+    const int grid = static_cast<int>((static_cast<int64_t>(n) + VPT * 1024 - 1) / (VPT * 1024));
+    const size_t lds = 2 * static_cast<size_t>(SL) * sizeof(float);
+    if (grid == 0) return true;
+    switch (deg) {
+#define GF_PL(D) case D: k_primal_lds<VPT, D><<<grid, 1024, lds, s>>>(n, m, SL, ell, wy, x_in, x_out, xbar, ct, tau1, rho, ctr, xbits); return true;
+        GF_PL(1) GF_PL(2) GF_PL(3) GF_PL(4) GF_PL(5) GF_PL(6) GF_PL(7) GF_PL(8)
+#undef GF_PL
+        default: return false;
+    }
+}
+
 // ------------------------------------------------------------ small helpers
 __global__ void k_copy_f32(float *__restrict__ d, const float *__restrict__ s, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;

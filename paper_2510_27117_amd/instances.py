@@ -427,6 +427,9 @@ def workload(name: str, seed: int = 0) -> BIP:
     maxcut         : n=200,000 Erdos-Renyi, average degree 10, weights +-1
     knapsack_batch : 512 multidimensional knapsacks, n in [1e3, 5e4], m in [5, 50]
     ufl            : 1,000 facilities x 10,000 customers
+    qap_tu         : 2D assignment n = 300 (90,000 variables) with a quadratic
+                     term of ~10 entries per variable and a knapsack row; its
+                     meta["tu_pivots"] a random recursive spanning tree (599 pivots)
     """
     if name == "setcover_small":
         return set_cover_bernoulli(200, 100, 0.05, seed)
@@ -438,4 +441,6 @@ def workload(name: str, seed: int = 0) -> BIP:
         return concat_instances(knapsack_batch(512, seed))
     if name == "ufl":
         return facility_location(1000, 10000, seed)
+    if name == "qap_tu":
+        return assignment_qap_like(300, seed, tree="random", q_per_var=10.0)
     raise KeyError(name)

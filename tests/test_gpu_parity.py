@@ -559,6 +559,53 @@ def test_batched_issue_bitmap_kernels_equal_plain_sell(G):
     prob.close()
 
 
+@pytest.mark.parametrize("shape", [(600_000, 60_000, 5, 3), (20_011, 1_003, 3, 4), (70_001, 250_007, 7, 5)])
+def test_lds_staged_primal_equals_plain(G, shape):
+    """The primal step with wy staged in LDS slices adds the same terms in the
+    same order as the fused CSR kernel with one lane per variable, so a step
+    through it equals that step exactly; over 20 steps (one enqueued sequence,
+    the zero-skipping dual reading the xbar bitmap the LDS primal writes) the
+    two configurations stay equal; and both are within tolerance of the
+    oracle.  Shapes: several slices with a ragged last one, a single slice
+    with m not a multiple of 4, more rows than variables (many slices)."""
+    n, m, deg, seed = shape
+    P = I.set_cover_columns(n, m, deg, seed=seed)
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=61, keep_every=60)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+
+    def run(cfg, steps):
+        prob.set_launch_cfg(*cfg)
+        prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+        prob.pdhg_steps(steps)
+        return prob.get_state()
+
+    a, b = run((16, 1, 1, 1, 0, 0, 0, 0), 1), run((16, 1, 1, 1, 0, 0, 0, 4), 1)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+    assert rel_inf(b["x"], ref.x) <= TOL_PDHG and rel_inf(b["y"], ref.y) <= TOL_PDHG
+    assert b["k"] == st.k + 1
+    skip = (1, 1, 8, 1, 1, 0, 2, 1)
+    try:
+        c = run(skip, 20)
+    except G.GforsError:
+        skip = (16, 1, 1, 1, 0, 0, 0, 1)
+        c = run(skip, 20)
+    d = run(skip[:7] + (4,), 20)
+    assert np.array_equal(c["x"], d["x"]) and np.array_equal(c["y"], d["y"])
+    prob.close()
+
+
+def test_lds_staged_primal_rejected_where_it_does_not_apply(G):
+    for P in (I.knapsack_multi(777, 7, seed=3), I.set_cover_bernoulli(1037, 301, 0.02, seed=1),
+              mixed_problem(150, seed=6)):
+        prob = G.Problem(P, _params(G, autotune=0))
+        with pytest.raises(G.GforsError):
+            prob.set_launch_cfg(16, 1, 1, 1, 0, 0, 0, 4)
+        prob.close()
+
+
 def test_fused_bitmaps_over_many_steps(G):
     """The primal kernel writes the nonzero bitmap of xbar and the dual combine
     the bitmap of wy, which the next step's zero-skipping kernels read.  Over

@@ -40,6 +40,12 @@ def case(name):
         P = I.from_dense([1, 2, 3, 4], A=[[1, 0, 0, 1]], b=[1], B=[[1, 1, 0, 0], [0, 1, 1, 0], [1, 1, 1, 1]],
                          d=[1, 1, 2])
         return P, np.array([1, 2, -1])
+    if name == "interval_fill":
+        # interval rows [0,1], [1,3], [0,4] (consecutive ones: TU); the pivot
+        # block [[1,1,0],[0,1,1],[1,1,1]] leaves a multiplier in L
+        P = I.from_dense([4, -1, 3, 2, -2, 1], A=[[1, 0, 1, 0, 1, 1], [-1, -1, 0, 0, 0, -1]], b=[1, -2],
+                         B=[[1, 1, 0, 0, 0, 0], [0, 1, 1, 1, 0, 0], [1, 1, 1, 1, 1, 0]], d=[1, 1, 2])
+        return P, np.array([0, 1, 2])
     if name.startswith("qap"):
         n, seed, tree = {"qap_path4": (4, 0, "path"), "qap_path6": (6, 1, "path"),
                          "qap_rand5": (5, 2, "random"), "qap_rand8": (8, 3, "random")}[name]
@@ -48,8 +54,8 @@ def case(name):
     raise KeyError(name)
 
 
-CASES = ["fl0", "fl1", "tri0", "tri1", "tri2", "interval", "kept_row", "qap_path4", "qap_path6",
-         "qap_rand5", "qap_rand8"]
+CASES = ["fl0", "fl1", "tri0", "tri1", "tri2", "interval", "interval_fill", "kept_row", "qap_path4",
+         "qap_path6", "qap_rand5", "qap_rand8"]
 
 
 def _S_from_recover(rec, P, piv, nred):
@@ -84,6 +90,8 @@ def test_factored_model_equals_oracle(name):
     assert T.info["nnz_S"] == int(np.count_nonzero(S))
     r = int(np.sum(np.asarray(piv) >= 0))
     assert T.info["pivots"] == r
+    if name == "interval_fill":
+        assert T.info["nnz_L"] > 0       # the L solves are not the identity here
     # the same handle without the flag agrees
     E = gfors.TUReformulation(P, piv)
     assert np.array_equal(E.model.c, T.c) and E.constant == T.constant
