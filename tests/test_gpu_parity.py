@@ -559,7 +559,7 @@ def test_batched_issue_bitmap_kernels_equal_plain_sell(G):
     prob.close()
 
 
-@pytest.mark.parametrize("shape", [(600_000, 60_000, 5, 3), (20_011, 1_003, 3, 4), (70_001, 250_007, 7, 5)])
+@pytest.mark.parametrize("shape", [(600_000, 60_000, 5, 3), (20_011, 1_003, 3, 4), (600_000, 250_007, 7, 5)])
 def test_lds_staged_primal_equals_plain(G, shape):
     """The primal step with wy staged in LDS slices adds the same terms in the
     same order as the fused CSR kernel with one lane per variable, so a step
