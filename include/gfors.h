@@ -301,7 +301,7 @@ int gfors_philox_throughput(void *hip_stream, int64_t calls, void *dev_sink, dou
 /* Launch shapes in use: out[8] = {lanes per row of the dual SpMV, lanes per row
  * of the primal SpMV, column slices of the dual SpMV, slices of the primal,
  * SELL-64 layout for the dual (0/1), SELL-64 layout for the primal (0/1),
- * zero-operand skipping in the dual (0..3), in the primal (0..4)}
+ * zero-operand skipping / layout variant of the dual (0..4), of the primal (0..5)}
  * (1 slice = fused kernel; with SELL the lanes-per-row entry is unused; dual
  * lanes per row 256 = a workgroup per row, longest rows first).  Skipping
  * keeps the nonzero bitmap of the gathered vector in LDS and issues only the
@@ -310,7 +310,11 @@ int gfors_philox_throughput(void *hip_stream, int64_t calls, void *dev_sink, dou
  * wavefront at once.  Primal 4 = no gathers from memory at all: wy is staged
  * in LDS slice by slice and every variable takes its terms from LDS (unit
  * coefficients, every variable in the same number <= 8 of rows, one
- * instance, Q = 0; the terms are added in the same order). */
+ * instance, Q = 0; the terms are added in the same order).  Dual 4 / primal
+ * 5 = dense-block tiles for problems whose every row spans all variables of
+ * its instance (at most 64 rows per instance, Q = 0: the knapsack batch): a
+ * workgroup per 2,048 columns of one instance, xbar (dual) or wy (primal) of
+ * the tile read once and reused by every row. */
 int gfors_get_launch_cfg(gfors_problem *P, int32_t *out);
 
 /* Re-run the autotuner on the current iterate (the zero-operand bitmap
@@ -325,7 +329,8 @@ int gfors_autotune(gfors_problem *P);
  * (then lanes <= 16; the primal also needs Q = 0); SELL only where the problem
  * holds the SELL copy; skipping 1 only for the sliced SELL dual / the fused CSR
  * primal, 2 and 3 only with a SELL layout, all without Q and with bitmaps of at most
- * 64 KB; primal 4 only with 1 slice, no SELL, and where the problem qualifies.
+ * 64 KB; primal 4 and 5 and dual 4 only with 1 slice, no SELL, and where the
+ * problem qualifies.
  * E_ARG otherwise (nothing is changed).  Drops captured graphs. */
 int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg);
 

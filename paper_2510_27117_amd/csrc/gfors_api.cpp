@@ -173,6 +173,17 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     sell_carve(P->sellT_want, n, 1, nnzK, P->sellT_cap, P->sellT_buf);
     P->val16 = cv.take<int16_t>(nnzK);
     P->ell = cv.take<int>((T == 1 && nnzQ == 0 && nnzK <= 8 * n) ? nnzK : 0);
+    {
+        // dense-block SpMV tables (filled only when the problem qualifies)
+        const int64_t tb = n / kBlockCols + T + 1;
+        BlockView &bv = P->blk;
+        int *tile_inst = cv.take<int>(tb), *tile_c0 = cv.take<int>(tb);
+        int *row0 = cv.take<int>(T), *nrow = cv.take<int>(T), *rows = cv.take<int>(m), *rank = cv.take<int>(m);
+        int *t0 = cv.take<int>(T), *nt = cv.take<int>(T);
+        bv.tile_inst = tile_inst; bv.tile_c0 = tile_c0; bv.row0 = row0; bv.nrow = nrow; bv.rows = rows;
+        bv.row_rank = rank; bv.inst_tile0 = t0; bv.inst_ntile = nt;
+        bv.pp = cv.take<float>(tb * 64);
+    }
     P->sellT_val16 = cv.take<int16_t>(P->sellT_want ? P->sellT_cap : 0);
     P->rowinv32 = cv.take<float>(m);
     P->bx_words = ceil_div(n + 64 * kXcdSlices, 64) + 1;
@@ -829,6 +840,47 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             if (dense) c0v[j] = ci[b0];
         }
         if ((rc = upload(s, P->rowc0, c0v.data(), m))) return rc;
+        // dense blocks: every row of every instance spans all its instance's
+        // variables, at most 64 rows per instance, no Q
+        {
+            bool ok = !P->hasQ && m > 0;
+            std::vector<std::vector<int>> irows(T);
+            for (int64_t j = 0; j < m && ok; ++j) {
+                const int t = row_inst[j];
+                ok = c0v[j] == P->inst_var0[t] && rp[j + 1] - rp[j] == P->inst_nvar[t];
+                irows[t].push_back(static_cast<int>(j));
+            }
+            for (int t = 0; t < T && ok; ++t) ok = !irows[t].empty() && irows[t].size() <= 64;
+            if (ok) {
+                std::vector<int> tinst, tc0, row0(T), nrow(T), rows, rank(m), t0(T), nt(T);
+                for (int t = 0; t < T; ++t) {
+                    row0[t] = static_cast<int>(rows.size());
+                    nrow[t] = static_cast<int>(irows[t].size());
+                    for (size_t r = 0; r < irows[t].size(); ++r) {
+                        rows.push_back(irows[t][r]);
+                        rank[irows[t][r]] = static_cast<int>(r);
+                    }
+                    t0[t] = static_cast<int>(tinst.size());
+                    for (int64_t c = P->inst_var0[t]; c < P->inst_var0[t] + P->inst_nvar[t]; c += kBlockCols) {
+                        tinst.push_back(t);
+                        tc0.push_back(static_cast<int>(c));
+                    }
+                    nt[t] = static_cast<int>(tinst.size()) - t0[t];
+                }
+                BlockView &bv = P->blk;
+                bv.ntile = static_cast<int>(tinst.size());
+                if ((rc = upload(s, const_cast<int *>(bv.tile_inst), tinst.data(), bv.ntile))) return rc;
+                if ((rc = upload(s, const_cast<int *>(bv.tile_c0), tc0.data(), bv.ntile))) return rc;
+                if ((rc = upload(s, const_cast<int *>(bv.row0), row0.data(), T))) return rc;
+                if ((rc = upload(s, const_cast<int *>(bv.nrow), nrow.data(), T))) return rc;
+                if ((rc = upload(s, const_cast<int *>(bv.rows), rows.data(), m))) return rc;
+                if ((rc = upload(s, const_cast<int *>(bv.row_rank), rank.data(), m))) return rc;
+                if ((rc = upload(s, const_cast<int *>(bv.inst_tile0), t0.data(), T))) return rc;
+                if ((rc = upload(s, const_cast<int *>(bv.inst_ntile), nt.data(), T))) return rc;
+                if ((rc = sync(P))) return rc;
+                P->dense_block = true;
+            }
+        }
         std::vector<int> r0v(n, -1);
         for (int64_t i = 0; i < n; ++i) {
             const int b0 = rpT[i], b1 = rpT[i + 1];
@@ -1130,7 +1182,10 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
                             P->wy, tau2, P->di.tau2, P->row_inst, P->by);
     };
     bool wy_bits = false;
-    if (sell && P->cfg.bits_dual >= 2) {
+    if (P->cfg.bits_dual == 4 && P->dense_block && !sell && slices == 1) {
+        launch_dual_block(s, P->blk, m, m1, P->rp, P->val, P->use16 ? P->val16 : nullptr, P->d_inst_var0,
+                          P->d_inst_nvar, P->xbar, P->omega, P->rt, P->di.tau2, P->row_inst, y_in, y_out, P->wy);
+    } else if (sell && P->cfg.bits_dual >= 2) {
         const int nc = P->cfg.bits_dual == 3 ? 4 : 2;
         need_bx();
         if (slices > 1) {
@@ -1200,7 +1255,10 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
         P->by_fresh = true;
     };
     bool xbar_bits = false;
-    if (P->cfg.bits_primal == 4 && P->lds_slice > 0 && !sell && slices == 1) {
+    if (P->cfg.bits_primal == 5 && P->dense_block && !sell && slices == 1) {
+        launch_primal_block(s, P->blk, P->rp, P->val, P->use16 ? P->val16 : nullptr, P->d_inst_var0, P->d_inst_nvar,
+                            P->wy, x_in, x_out, xbar, P->ct, P->di.tau1, P->di.rho, ctr);
+    } else if (P->cfg.bits_primal == 4 && P->lds_slice > 0 && !sell && slices == 1) {
         launch_primal_lds(s, static_cast<int>(P->n), static_cast<int>(P->m), P->colT_deg, P->lds_slice, P->ell,
                           P->wy, x_in, x_out, xbar, P->ct, tau1, P->di.rho, ctr, xbits);
         xbar_bits = xbits != nullptr;
@@ -1255,6 +1313,7 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
 // Each needs its bitmap to fit in LDS.
 static int bits_ok_dual(gfors_problem *P, int slices, int sell, int bits) {
     if (bits == 0) return 1;
+    if (bits == 4) return (P->dense_block && slices == 1 && !sell) ? 1 : 0;   // dense-block tiles
     if (!sell) return 0;
     if (bits == 1) return (slices > 1 && P->sellKS.ptr && P->sellKS.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
     if (bits != 2 && bits != 3) return 0;
@@ -1266,6 +1325,7 @@ static int bits_ok_primal(gfors_problem *P, int slices, int sell, int bits) {
     if (P->m == 0 || P->hasQ || slices != 1) return 0;
     if (bits == 1) return (!sell && (P->m + 31) / 32 * 4 <= kMaxLdsBitmapBytes) ? 1 : 0;
     if (bits == 4) return (!sell && P->lds_slice > 0) ? 1 : 0;   // wy staged in LDS slices
+    if (bits == 5) return (!sell && P->dense_block) ? 1 : 0;     // dense-block tiles
     if (bits != 2 && bits != 3) return 0;
     return (sell && P->sellT.ptr && P->sellT.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
 }
@@ -1319,6 +1379,11 @@ static int autotune(gfors_problem *P) {
                 if (t < best) { best = t; best_bits = b; P->cfg.lpr_dual = 1; P->cfg.slices_dual = sl; P->cfg.sell_dual = 1; }
             }
         }
+        if (bits_ok_dual(P, 1, 0, 4)) {
+            P->cfg.bits_dual = 4;
+            const float t = timeit([&] { launch_dual_cfg(P, 1, 1, 0, P->ybuf[P->cur], P->ybuf[1 - P->cur]); });
+            if (t < best) { best = t; best_bits = 4; P->cfg.lpr_dual = 1; P->cfg.slices_dual = 1; P->cfg.sell_dual = 0; }
+        }
         P->cfg.bits_dual = best_bits;
     }
     {
@@ -1352,10 +1417,11 @@ static int autotune(gfors_problem *P) {
             const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 1, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
             if (t < best) { best = t; best_bits = b; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 1; }
         }
-        if (bits_ok_primal(P, 1, 0, 4)) {
-            P->cfg.bits_primal = 4;
+        for (int b : {4, 5}) {
+            if (!bits_ok_primal(P, 1, 0, b)) continue;
+            P->cfg.bits_primal = b;
             const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 0, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
-            if (t < best) { best = t; best_bits = 4; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 0; }
+            if (t < best) { best = t; best_bits = b; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 0; }
         }
         P->cfg.bits_primal = best_bits;
     }
@@ -1800,9 +1866,9 @@ int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
         return fail(GFORS_E_ARG, "no SELL copy of the constraint rows for this slicing");
     if (cfg[5] && !(cfg[3] == 1 && P->sellT.ptr))
         return fail(GFORS_E_ARG, "no SELL copy of the transposed rows");
-    if (cfg[6] < 0 || cfg[6] > 3 || !bits_ok_dual(P, cfg[2], cfg[4], cfg[6]))
-        return fail(GFORS_E_ARG, "bitmap dual: 1 needs the sliced SELL layout, 2 a SELL layout, and the slice bitmap must fit in LDS");
-    if (cfg[7] < 0 || cfg[7] > 4 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
+    if (cfg[6] < 0 || cfg[6] > 4 || !bits_ok_dual(P, cfg[2], cfg[4], cfg[6]))
+        return fail(GFORS_E_ARG, "bitmap dual: 1 needs the sliced SELL layout, 2 a SELL layout, and the slice bitmap must fit in LDS; 4 (dense-block tiles) needs rows dense over their instance's variables, <= 64 rows per instance, Q = 0, 1 slice, no SELL");
+    if (cfg[7] < 0 || cfg[7] > 5 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
         return fail(GFORS_E_ARG, "bitmap primal: 1 needs the fused CSR layout, 2 the SELL layout; both need Q = 0 and a dual bitmap that fits in LDS; 4 (wy staged in LDS) needs the fused layout, unit coefficients, every variable in the same number (<= 8) of rows, one instance and Q = 0");
     P->cfg.lpr_dual = cfg[0];
     P->cfg.lpr_primal = cfg[1];

@@ -183,6 +183,9 @@ struct gfors_problem {
     // with wy staged in LDS, and its slice length (0: that variant unavailable)
     int *ell = nullptr;
     int lds_slice = 0;
+    // dense-block SpMVs (every row dense over its instance's variables)
+    bool dense_block = false;
+    BlockView blk;
     int16_t *val16 = nullptr, *sellT_val16 = nullptr;
     float *rowinv32 = nullptr;          // 1/||a_j|| (0 for a zero row): the GNN's edge weights
     float gnn_ictmax = 1.f, gnn_irtmax = 1.f;

@@ -149,6 +149,27 @@ void launch_primal_bits(hipStream_t s, int lpr, bool unit, bool batched, int n, 
                         const float *ct, float tau1, const float *tau1_inst, const double *rho,
                         const int *var_inst, DevCounters *ctr, uint64_t *xbits, int deg);
 
+// Dense-block SpMVs of batched instances whose rows are dense over their
+// instance's variables (at most 64 rows per instance, no Q).
+struct BlockView {
+    int ntile = 0;
+    const int *tile_inst = nullptr, *tile_c0 = nullptr;   // per tile: instance, first column
+    const int *row0 = nullptr, *nrow = nullptr;            // per instance: its rows in `rows`
+    const int *rows = nullptr;                             // rows of each instance, in order
+    const int *row_rank = nullptr;                         // per row: index within its instance
+    const int *inst_tile0 = nullptr, *inst_ntile = nullptr;   // per instance: its tiles
+    float *pp = nullptr;                                   // per tile: 64 row sums
+};
+constexpr int kBlockCols = 2048;   // columns per tile of the dense-block SpMVs
+void launch_dual_block(hipStream_t s, const BlockView &b, int m, int m1, const int *rp, const int *val,
+                       const int16_t *val16, const int64_t *inst_var0, const int64_t *inst_nvar,
+                       const float *xbar, const float *omega, const float *rt, const float *tau2_inst,
+                       const int *row_inst, const float *y_in, float *y_out, float *wy);
+void launch_primal_block(hipStream_t s, const BlockView &b, const int *rp, const int *val, const int16_t *val16,
+                         const int64_t *inst_var0, const int64_t *inst_nvar, const float *wy,
+                         const float *x_in, float *x_out, float *xbar, const float *ct, const float *tau1_inst,
+                         const double *rho, DevCounters *ctr);
+
 // Primal step with wy staged in LDS slices of SL rows (unit coefficients,
 // every variable in deg <= 8 rows, one instance, no Q); ell[u n + i] = the
 // u-th row of variable i (ascending).  Returns false for an unsupported deg.

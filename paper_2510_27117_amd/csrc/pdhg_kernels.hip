@@ -1113,6 +1113,164 @@ bool launch_primal_lds(hipStream_t s, int n, int m, int deg, int SL, const int *
     }
 }
 
+// ---------------------------------------------------------------------------
+// Dense-block SpMVs for batched instances whose rows are dense over their
+// instance's variables (every row of instance t has the columns
+// v0_t .. v0_t + n_t - 1 in order, at most 64 rows per instance, no Q): the
+// knapsack batch.  A tile is kBlkCols consecutive columns of one instance;
+// thread t of its workgroup owns the columns c0 + 256 k + t (k < 8).
+//   dual:   per tile, xbar of the tile is loaded once into registers and every
+//           row of the instance streams its coefficients over it; the row's
+//           tile sum (lanes, then the 4 wavefronts in order) goes to pp; a
+//           combine kernel adds a row's tile sums in tile order and applies
+//           the dual update.  The row kernels re-read xbar per row instead.
+//   primal: per tile, wy of the instance's rows sits in LDS and each column
+//           adds a_rc wy_r over the rows in order (the order of the CSR
+//           kernels), then the primal update of its 8 columns.
+// ---------------------------------------------------------------------------
+constexpr int kBlkCols = kBlockCols;
+
+template <typename VT>
+__global__ void __launch_bounds__(256)
+k_dual_block(const int *__restrict__ tile_inst, const int *__restrict__ tile_c0,
+             const int *__restrict__ blk_row0, const int *__restrict__ blk_nrow,
+             const int *__restrict__ blk_rows, const int *__restrict__ rp,
+             const int64_t *__restrict__ inst_var0, const int64_t *__restrict__ inst_nvar,
+             const VT *__restrict__ val, const float *__restrict__ xbar, float *__restrict__ pp) {
+    __shared__ float red[4][64];
+    __shared__ int rbase[64];
+    const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int t = tile_inst[g];
+    const int v0 = static_cast<int>(inst_var0[t]);
+    const int c0 = tile_c0[g], c1 = min(c0 + kBlkCols, v0 + static_cast<int>(inst_nvar[t]));
+    const int nr = blk_nrow[t], r0 = blk_row0[t];
+    // the rows' first entries, once: the row loop then issues only coefficient loads
+    if (tid < nr) rbase[tid] = rp[blk_rows[r0 + tid]];
+    float xv[8];
+    int off[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int c = c0 + 256 * k + tid;
+        xv[k] = c < c1 ? xbar[c] : 0.f;
+        off[k] = c < c1 ? c - v0 : 0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int r = 0; r < nr; ++r) {
+        const VT *a = val + rbase[r];
+        float sacc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sacc = fmaf(static_cast<float>(a[off[k]]), xv[k], sacc);
+        sacc = group_sum<64>(sacc);
+        if (lane == 0) red[wv][r] = sacc;
+    }
+    __syncthreads();
+    if (tid < nr) pp[static_cast<int64_t>(g) * 64 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
+__global__ void __launch_bounds__(256)
+k_dual_block_combine(int m, int m1, const int *__restrict__ row_inst, const int *__restrict__ row_rank,
+                     const int *__restrict__ inst_tile0, const int *__restrict__ inst_ntile,
+                     const float *__restrict__ pp, const float *__restrict__ omega,
+                     const float *__restrict__ rt, const float *__restrict__ tau2_inst,
+                     const float *__restrict__ y_in, float *__restrict__ y_out, float *__restrict__ wy) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const int t = row_inst[j], rk = row_rank[j];
+    const int g0 = inst_tile0[t], ng = inst_ntile[t];
+    float sacc = 0.f;
+    for (int q = 0; q < ng; ++q) sacc += pp[static_cast<int64_t>(g0 + q) * 64 + rk];
+    const float om = omega[j];
+    float y = y_in[j] + tau2_inst[t] * (rt[j] - om * sacc);
+    if (j < m1) y = fmaxf(y, 0.f);
+    y_out[j] = y;
+    wy[j] = om * y;
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(256)
+k_primal_block(const int *__restrict__ tile_inst, const int *__restrict__ tile_c0,
+               const int *__restrict__ blk_row0, const int *__restrict__ blk_nrow,
+               const int *__restrict__ blk_rows, const int *__restrict__ rp,
+               const int64_t *__restrict__ inst_var0, const int64_t *__restrict__ inst_nvar,
+               const VT *__restrict__ val, const float *__restrict__ wy, const float *__restrict__ x_in,
+               float *__restrict__ x_out, float *__restrict__ xbar, const float *__restrict__ ct,
+               const float *__restrict__ tau1_inst, const double *__restrict__ rho,
+               DevCounters *__restrict__ ctr) {
+    __shared__ float wys[64];
+    __shared__ int rbase[64];
+    const int g = blockIdx.x, tid = threadIdx.x;
+    const int t = tile_inst[g];
+    const int v0 = static_cast<int>(inst_var0[t]);
+    const int c0 = tile_c0[g], c1 = min(c0 + kBlkCols, v0 + static_cast<int>(inst_nvar[t]));
+    const int nr = blk_nrow[t], r0 = blk_row0[t];
+    if (tid < nr) {
+        const int j = blk_rows[r0 + tid];
+        wys[tid] = wy[j];
+        rbase[tid] = rp[j];
+    }
+    if (g == 0 && tid == 0) ctr->k += 1;
+    __syncthreads();
+    float acc[8];
+    int off[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int c = c0 + 256 * k + tid;
+        acc[k] = 0.f;
+        off[k] = c < c1 ? c - v0 : 0;
+    }
+#pragma unroll 2
+    for (int r = 0; r < nr; ++r) {
+        const VT *a = val + rbase[r];
+        const float w = wys[r];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = fmaf(static_cast<float>(a[off[k]]), w, acc[k]);
+    }
+    const float rh = static_cast<float>(rho[t]);
+    const float ta = tau1_inst[t];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int c = c0 + 256 * k + tid;
+        if (c >= c1) continue;
+        const float xi = x_in[c];
+        float gr = ct[c] + rh;
+        gr -= acc[k];
+        gr -= 2.f * rh * xi;
+        const float xn = fminf(fmaxf(xi - ta * gr, 0.f), 1.f);
+        x_out[c] = xn;
+        xbar[c] = 2.f * xn - xi;
+    }
+}
+
+void launch_dual_block(hipStream_t s, const BlockView &b, int m, int m1, const int *rp, const int *val,
+                       const int16_t *val16, const int64_t *inst_var0, const int64_t *inst_nvar,
+                       const float *xbar, const float *omega, const float *rt, const float *tau2_inst,
+                       const int *row_inst, const float *y_in, float *y_out, float *wy) {
+    if (b.ntile <= 0) return;
+    if (val16)
+        k_dual_block<int16_t><<<b.ntile, 256, 0, s>>>(b.tile_inst, b.tile_c0, b.row0, b.nrow, b.rows, rp, inst_var0,
+                                                       inst_nvar, val16, xbar, b.pp);
+    else
+        k_dual_block<int><<<b.ntile, 256, 0, s>>>(b.tile_inst, b.tile_c0, b.row0, b.nrow, b.rows, rp, inst_var0,
+                                                   inst_nvar, val, xbar, b.pp);
+    k_dual_block_combine<<<(m + 255) / 256, 256, 0, s>>>(m, m1, row_inst, b.row_rank, b.inst_tile0, b.inst_ntile,
+                                                         b.pp, omega, rt, tau2_inst, y_in, y_out, wy);
+}
+
+void launch_primal_block(hipStream_t s, const BlockView &b, const int *rp, const int *val, const int16_t *val16,
+                         const int64_t *inst_var0, const int64_t *inst_nvar, const float *wy,
+                         const float *x_in, float *x_out, float *xbar, const float *ct, const float *tau1_inst,
+                         const double *rho, DevCounters *ctr) {
+    if (b.ntile <= 0) return;
+    if (val16)
+        k_primal_block<int16_t><<<b.ntile, 256, 0, s>>>(b.tile_inst, b.tile_c0, b.row0, b.nrow, b.rows, rp, inst_var0,
+                                                         inst_nvar, val16, wy, x_in, x_out, xbar, ct, tau1_inst, rho,
+                                                         ctr);
+    else
+        k_primal_block<int><<<b.ntile, 256, 0, s>>>(b.tile_inst, b.tile_c0, b.row0, b.nrow, b.rows, rp, inst_var0,
+                                                     inst_nvar, val, wy, x_in, x_out, xbar, ct, tau1_inst, rho, ctr);
+}
+
 // ------------------------------------------------------------ small helpers
 __global__ void k_copy_f32(float *__restrict__ d, const float *__restrict__ s, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;

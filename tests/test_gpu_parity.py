@@ -347,6 +347,60 @@ def test_batched_graph_replay_matches_eager(G, kind):
         b.close()
 
 
+@pytest.mark.parametrize("which", ["single", "batch"])
+def test_dense_block_spmvs_match_oracle(G, which):
+    """The dense-block dual (tile of xbar reused by every row of its
+    instance, tile sums combined in order) and primal (the instance's wy in
+    LDS, rows in order) give the teacher-forced step of the oracle, per
+    instance, on a dense knapsack and on a batch of uneven knapsacks (ragged
+    last tiles, 1-9 rows, int16 and int32 coefficients); over 10 steps they
+    stay with the row kernels; they are refused where rows are not dense."""
+    if which == "single":
+        parts = [I.knapsack_multi(5001, 5, seed=9)]
+    else:
+        parts = I.knapsack_batch(6, seed=13, n_lo=700, n_hi=9000, m_lo=1, m_hi=9)
+        parts[3] = I.knapsack_multi(2500, 4, seed=4, wmax=100_000)    # coefficients beyond int16
+    Bt = parts[0] if which == "single" else I.concat_instances(parts)
+    T = len(parts)
+    off = Bt.inst_offsets if which == "batch" else np.array([[0, 0, 0], [Bt.n, Bt.m1, Bt.m2]])
+    prob = G.Problem(Bt, _params(G, autotune=0))
+    states, Ss = [], []
+    for Pt in parts:
+        S, traj = oracle_trajectory(Pt, O.Params(k_int=20), steps=40, keep_every=39)
+        st, rho = traj[-1]
+        states.append((f32_state(st), rho))
+        Ss.append(S)
+    x = np.concatenate([f32(s.x) for s, _ in states])
+    xp = np.concatenate([f32(s.x_prev) for s, _ in states])
+    y = np.concatenate([f32(s.y) for s, _ in states])
+    rho = np.array([r for _, r in states])
+
+    def run(cfg, steps):
+        prob.set_launch_cfg(*cfg)
+        prob.set_state(x, xp, y, rho if T > 1 else rho[0], k=39)
+        prob.pdhg_steps(steps)
+        return prob.get_state()
+
+    got = run((16, 4, 1, 1, 0, 0, 4, 5), 1)
+    for t in range(T):
+        ref = O.pdhg_step(Ss[t], states[t][0], states[t][1])
+        gx = got["x"][off[t, 0]:off[t + 1, 0]]
+        gy = got["y"][off[t, 1]:off[t + 1, 1]]
+        assert rel_inf(gx, ref.x) <= TOL_PDHG and rel_inf(gy, ref.y) <= TOL_PDHG, t
+    assert got["k"] == 40
+    a, b = run((16, 4, 1, 1, 0, 0, 0, 0), 10), run((16, 4, 1, 1, 0, 0, 4, 5), 10)
+    assert rel_inf(b["x"], a["x"]) <= 1e-4 and rel_inf(b["y"], a["y"]) <= 1e-4
+    prob.close()
+    # not dense: a set cover, and a batch whose one instance has a sparse row
+    for P in (I.set_cover_bernoulli(1037, 301, 0.02, seed=1), mixed_problem(150, seed=6)):
+        q = G.Problem(P, _params(G, autotune=0))
+        with pytest.raises(G.GforsError):
+            q.set_launch_cfg(16, 4, 1, 1, 0, 0, 4, 0)
+        with pytest.raises(G.GforsError):
+            q.set_launch_cfg(16, 4, 1, 1, 0, 0, 0, 5)
+        q.close()
+
+
 def test_batched_matches_per_instance(G):
     """A block-diagonal batch behaves as independent instances: per-instance
     scales, one teacher-forced step and a sampling round equal the oracle run
