@@ -496,8 +496,11 @@ int gfors_get_dims(gfors_problem *P, int64_t *n, int64_t *m1, int64_t *m2, int32
 
 /* How EvalBest (Sec. 3) evaluates the general rows of this problem: *planes
  * = 1..3 when they run as dense int8 digit blocks on the matrix cores (the
- * number of signed base-256 digit planes), 0 when row by row.  Fixed at
- * creation (see gfors_params.eval_mfma). */
+ * number of signed base-256 digit planes), 0 when row by row.  The blocks
+ * exist when gfors_params.eval_mfma allows them and the rows qualify; with
+ * autotune the matrix-core kernel and the row-by-row kernels (rows split over
+ * wavefronts / a wavefront per row) are timed on candidates drawn from
+ * p = 1/2 and the fastest is kept (all give identical results). */
 int gfors_eval_planes(gfors_problem *P, int32_t *planes);
 
 #ifdef __cplusplus

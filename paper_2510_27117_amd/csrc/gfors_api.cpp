@@ -255,7 +255,8 @@ void gfors_destroy_problem(gfors_problem *P) {
 }
 
 static int device_norms(gfors_problem *P);
-static int autotune(gfors_problem *P);
+static int autotune(gfors_problem *P, bool with_eval);
+static void launch_eval_general_rows(gfors_problem *P, int K);
 static int setup_repair(gfors_problem *P, const gfors_csr *A, const int64_t *b, const gfors_csr *B,
                         const gfors_csr *Q, const int64_t *c);
 
@@ -1066,7 +1067,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     }
     if (prm->repair_row0 >= 0 && (rc = setup_repair(P, A, b, B, Q, c))) return rc;
     if ((rc = sync(P))) return rc;
-    if (prm->autotune && (rc = autotune(P))) return rc;
+    if (prm->autotune && (rc = autotune(P, true))) return rc;
     *out = guard.release();
     return GFORS_OK;
 }
@@ -1333,7 +1334,7 @@ static int bits_ok_primal(gfors_problem *P, int slices, int sell, int bits) {
 // Autotuner: time every candidate launch shape of the dual and primal SpMV on
 // this problem's own data (HIP events, 1 warm-up + 5 timed launches each) and
 // keep the fastest.  Outputs go to buffers that carry no state at this point.
-static int autotune(gfors_problem *P) {
+static int autotune(gfors_problem *P, bool with_eval) {
     hipStream_t s = P->stream;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -1425,6 +1426,28 @@ static int autotune(gfors_problem *P) {
         }
         P->cfg.bits_primal = best_bits;
     }
+    // EvalBest's general rows: time each kernel that applies on candidates
+    // drawn from p = 1/2 (K = min(K_max, 1024)); the candidates, counts and
+    // partial sums are scratch at this point
+    if (with_eval && P->n_general > 0) {
+        const int K = std::min(P->prm.K_max, 1024);
+        const int W = K / 64;
+        float *p = P->xsave;
+        launch_fill_f32(s, p, 0.5f, P->n);
+        launch_sample(s, W, P->obj64, p, P->cost, P->X, P->st, P->d_inst_var0, P->d_inst_nvar, P->zpart, K,
+                      static_cast<uint32_t>(P->prm.seed & 0xffffffffu), static_cast<uint32_t>(P->prm.seed >> 32),
+                      P->ctr, 0, P->xkind);
+        float best = 1e30f;
+        int bestv = 0;
+        for (int v : {1, 2, 3}) {
+            if (v == 1 && !P->mfma) continue;
+            if ((v == 2 || v == 3) && !(W <= 16 && (W & (W - 1)) == 0)) continue;
+            P->eval_variant = v;
+            const float t = timeit([&] { launch_eval_general_rows(P, K); });
+            if (t < best) { best = t; bestv = v; }
+        }
+        P->eval_variant = bestv;
+    }
     HIP_TRY(hipGetLastError());
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1476,6 +1499,25 @@ static void enqueue_steps(gfors_problem *P, int nsteps, bool want_res, KTimer *t
 
 static void enqueue_eval(gfors_problem *P, int K, int threshold, KTimer *tm, int trigger);
 
+// The general rows of EvalBest in the chosen kernel: on the matrix cores
+// (digit blocks, when the problem holds them), rows split over wavefronts, or
+// a wavefront per row; all give the same exact counts.
+static void launch_eval_general_rows(gfors_problem *P, int K) {
+    hipStream_t s = P->stream;
+    const int W = K / 64;
+    const int v = P->eval_variant;
+    if (P->mfma && (v == 0 || v == 1)) {
+        launch_eval_mfma(s, P->n_general, P->general_ids, P->et, P->mf_npl, P->acc64, P->rows, P->mf_off,
+                         P->mf_c0, P->mf_span, P->mf_dig, P->rhs, static_cast<int>(P->m1), P->X, W,
+                         P->vpart, K);
+        return;
+    }
+    const bool split = v == 2 ? true : (v == 3 ? false : P->general_long);
+    launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
+                        P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X,
+                        P->xkind, W, P->vpart, K, split, P->coef24);
+}
+
 static void enqueue_sample_eval(gfors_problem *P, int K, const float *p_override, int threshold,
                                 KTimer *tm = nullptr, int trigger = 1) {
     hipStream_t s = P->stream;
@@ -1506,14 +1548,7 @@ static void enqueue_eval(gfors_problem *P, int K, int threshold, KTimer *tm, int
                       P->xkind, W, P->vpart, K);
     TE(3);
     TB(4);
-    if (P->mfma)
-        launch_eval_mfma(s, P->n_general, P->general_ids, P->et, P->mf_npl, P->acc64, P->rows, P->mf_off,
-                         P->mf_c0, P->mf_span, P->mf_dig, P->rhs, static_cast<int>(P->m1), P->X, W,
-                         P->vpart, K);
-    else
-        launch_eval_general(s, P->n_general, P->general_ids, P->et, P->acc64, P->rows, P->rp, P->ci,
-                            P->unitK ? nullptr : P->val, P->rhs, static_cast<int>(P->m1), P->X,
-                            P->xkind, W, P->vpart, K, P->general_long, P->coef24);
+    launch_eval_general_rows(P, K);
     TE(4);
     TB(5);
     if (P->hasQ)
@@ -1824,12 +1859,12 @@ int gfors_autotune(gfors_problem *P) {
     if (!P) return fail(GFORS_E_ARG, "NULL handle");
     if (P->lu) return GFORS_OK;   // one launch shape (the lifted rows are short)
     P->graphs_clear();
-    return autotune(P);
+    return autotune(P, false);
 }
 
 int gfors_eval_planes(gfors_problem *P, int32_t *planes) {
     if (!P || !planes) return fail(GFORS_E_ARG, "bad argument");
-    *planes = P->mfma ? P->mf_npl : 0;
+    *planes = (P->mfma && (P->eval_variant == 0 || P->eval_variant == 1)) ? P->mf_npl : 0;
     return GFORS_OK;
 }
 

@@ -183,6 +183,10 @@ struct gfors_problem {
     // with wy staged in LDS, and its slice length (0: that variant unavailable)
     int *ell = nullptr;
     int lds_slice = 0;
+    // evaluation kernel of the general rows: 0 the creation's choice (matrix
+    // cores when the blocks qualify, else row by row), 1 matrix cores, 2 rows
+    // split over wavefronts, 3 a wavefront per row and word set (timed by the autotuner)
+    int eval_variant = 0;
     // dense-block SpMVs (every row dense over its instance's variables)
     bool dense_block = false;
     BlockView blk;

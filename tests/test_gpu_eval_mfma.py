@@ -78,7 +78,9 @@ def _check_round(G, P, parts, K, planes, seed):
     import torch
     res = []
     for mf in (1, 0):
-        prob = G.Problem(P, G.default_params(k_int=20, K_max=max(K, 1024), eval_mfma=mf))
+        # autotune off: the matrix-core kernel is the one under test (the timed
+        # choice between it and the row kernels is tested below)
+        prob = G.Problem(P, G.default_params(k_int=20, K_max=max(K, 1024), eval_mfma=mf, autotune=0))
         assert prob.eval_planes() == (planes if mf else 0)
         p = np.random.default_rng(seed).random(P.n).astype(np.float32)
         prob.set_state(p, p, np.zeros(P.m1 + P.m2), 0.0, k=0, round=2)
@@ -214,4 +216,25 @@ def test_quadratic_triangle(G, symmetric):
     vo, zo = O.evaluate(P, X)
     assert np.array_equal(v.cpu().numpy()[0], vo)
     assert np.array_equal(z.cpu().numpy()[0], zo)
+    prob.close()
+
+
+def test_timed_choice_of_the_evaluation_kernel(G):
+    """With autotune the creation times the matrix-core kernel against the
+    row-by-row kernels and keeps one; the counts and objectives are the
+    oracle's whichever it keeps, and eval_planes reports the choice."""
+    import torch
+    parts = I.knapsack_batch(4, seed=21, n_lo=800, n_hi=4000, m_lo=3, m_hi=12)
+    P = I.concat_instances(parts)
+    prob = G.Problem(P, G.default_params(k_int=20, K_max=1024))
+    assert prob.eval_planes() in (0, 2)
+    p = np.random.default_rng(3).random(P.n).astype(np.float32)
+    prob.set_state(p, p, np.zeros(P.m1 + P.m2), 0.0, k=0, round=4)
+    v, z = prob.sample_eval(512, p_override=torch.from_numpy(p).to("cuda:0"), outputs=True)
+    v, z = v.cpu().numpy(), z.cpu().numpy()
+    off = P.inst_offsets
+    for t, Pt in enumerate(parts):
+        X = O.sample_bits(p[off[t, 0]:off[t + 1, 0]].astype(np.float64), 512, seed=0, rnd=4, instance=t)
+        vo, zo = O.evaluate(Pt, X)
+        assert np.array_equal(v[t], vo) and np.array_equal(z[t], zo), t
     prob.close()
