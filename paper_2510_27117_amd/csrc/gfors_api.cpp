@@ -183,6 +183,10 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
         bv.tile_inst = tile_inst; bv.tile_c0 = tile_c0; bv.row0 = row0; bv.nrow = nrow; bv.rows = rows;
         bv.row_rank = rank; bv.inst_tile0 = t0; bv.inst_ntile = nt;
         bv.pp = cv.take<float>(tb * 64);
+        // padded int16 coefficients for the dense-block kernels (Q = 0 only)
+        P->blk_pval_cap = nnzQ == 0 ? nnzK + 8 * m : 0;
+        P->blk_pval = cv.take<int16_t>(P->blk_pval_cap);
+        P->blk_pbase = cv.take<int64_t>(nnzQ == 0 ? m : 0);
     }
     P->sellT_val16 = cv.take<int16_t>(P->sellT_want ? P->sellT_cap : 0);
     P->rowinv32 = cv.take<float>(m);
@@ -880,6 +884,28 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
                 if ((rc = upload(s, const_cast<int *>(bv.inst_ntile), nt.data(), T))) return rc;
                 if ((rc = sync(P))) return rc;
                 P->dense_block = true;
+                // int16 coefficients: a copy with every row at a multiple of 8
+                // entries (aligned 16-byte loads of 8 consecutive columns)
+                if (P->use16 && P->blk_pval_cap > 0) {
+                    std::vector<int16_t> pv;
+                    std::vector<int64_t> pb(m);
+                    for (int t = 0; t < T; ++t) {
+                        const int64_t nv = P->inst_nvar[t], stride = (nv + 7) / 8 * 8;
+                        for (int r = 0; r < nrow[t]; ++r) {
+                            const int j = rows[row0[t] + r];
+                            pb[row0[t] + r] = static_cast<int64_t>(pv.size());
+                            for (int e = rp[j]; e < rp[j + 1]; ++e) pv.push_back(static_cast<int16_t>(val[e]));
+                            pv.resize(pb[row0[t] + r] + stride, 0);
+                        }
+                    }
+                    if (static_cast<int64_t>(pv.size()) <= P->blk_pval_cap) {
+                        if ((rc = upload(s, P->blk_pval, pv.data(), static_cast<int64_t>(pv.size())))) return rc;
+                        if ((rc = upload(s, P->blk_pbase, pb.data(), m))) return rc;
+                        if ((rc = sync(P))) return rc;
+                        bv.pval = P->blk_pval;
+                        bv.pbase = P->blk_pbase;
+                    }
+                }
             }
         }
         std::vector<int> r0v(n, -1);

@@ -190,6 +190,9 @@ struct gfors_problem {
     // dense-block SpMVs (every row dense over its instance's variables)
     bool dense_block = false;
     BlockView blk;
+    int16_t *blk_pval = nullptr;   // its padded int16 coefficients (capacity blk_pval_cap)
+    int64_t *blk_pbase = nullptr;
+    int64_t blk_pval_cap = 0;
     int16_t *val16 = nullptr, *sellT_val16 = nullptr;
     float *rowinv32 = nullptr;          // 1/||a_j|| (0 for a zero row): the GNN's edge weights
     float gnn_ictmax = 1.f, gnn_irtmax = 1.f;

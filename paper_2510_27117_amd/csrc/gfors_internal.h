@@ -159,8 +159,13 @@ struct BlockView {
     const int *row_rank = nullptr;                         // per row: index within its instance
     const int *inst_tile0 = nullptr, *inst_ntile = nullptr;   // per instance: its tiles
     float *pp = nullptr;                                   // per tile: 64 row sums
+    // padded int16 copy (each row of an instance at a multiple of 8 entries,
+    // zero past its end; null when absent) and the first entry of every row
+    // of `rows` in it
+    const int16_t *pval = nullptr;
+    const int64_t *pbase = nullptr;
 };
-constexpr int kBlockCols = 2048;   // columns per tile of the dense-block SpMVs
+constexpr int kBlockCols = 2048;   // columns per tile of the dense-block SpMVs (256 threads x 8)
 void launch_dual_block(hipStream_t s, const BlockView &b, int m, int m1, const int *rp, const int *val,
                        const int16_t *val16, const int64_t *inst_var0, const int64_t *inst_nvar,
                        const float *xbar, const float *omega, const float *rt, const float *tau2_inst,

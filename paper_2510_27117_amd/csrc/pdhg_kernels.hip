@@ -1117,8 +1117,10 @@ bool launch_primal_lds(hipStream_t s, int n, int m, int deg, int SL, const int *
 // Dense-block SpMVs for batched instances whose rows are dense over their
 // instance's variables (every row of instance t has the columns
 // v0_t .. v0_t + n_t - 1 in order, at most 64 rows per instance, no Q): the
-// knapsack batch.  A tile is kBlkCols consecutive columns of one instance;
-// thread t of its workgroup owns the columns c0 + 256 k + t (k < 8).
+// knapsack batch.  A tile is kBlkCols consecutive columns of one instance
+// (2,048: tiles of 4,096 and a persistent grid over the tiles were measured
+// slower); thread t of its workgroup owns the columns c0 + 256 k + t
+// (k < kBlkCols / 256).
 //   dual:   per tile, xbar of the tile is loaded once into registers and every
 //           row of the instance streams its coefficients over it; the row's
 //           tile sum (lanes, then the 4 wavefronts in order) goes to pp; a
@@ -1129,6 +1131,144 @@ bool launch_primal_lds(hipStream_t s, int n, int m, int deg, int SL, const int *
 //           kernels), then the primal update of its 8 columns.
 // ---------------------------------------------------------------------------
 constexpr int kBlkCols = kBlockCols;
+constexpr int kBlkGrid = 1 << 30;   // one tile per workgroup (measured faster than a persistent grid)
+
+// The same two kernels over a padded int16 copy of the coefficients (each
+// row of an instance at a multiple of 8 entries, zeros past its end): thread
+// t owns the kBlkCols / 256 consecutive columns from c0 + (kBlkCols / 256) t
+// and reads their coefficients of a row with aligned 16-byte loads; xbar of
+// the tile and the primal's column sums pass through LDS so that the
+// global loads and stores stay coalesced.
+__device__ __forceinline__ void unpack8(const int4 q, float *a) {
+    const uint32_t w[4] = {static_cast<uint32_t>(q.x), static_cast<uint32_t>(q.y), static_cast<uint32_t>(q.z),
+                           static_cast<uint32_t>(q.w)};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        a[2 * h] = static_cast<float>(static_cast<int16_t>(w[h] & 0xffffu));
+        a[2 * h + 1] = static_cast<float>(static_cast<int16_t>(w[h] >> 16));
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_dual_block16(int ntile, const int *__restrict__ tile_inst, const int *__restrict__ tile_c0,
+               const int *__restrict__ blk_row0, const int *__restrict__ blk_nrow,
+               const int64_t *__restrict__ pbase, const int64_t *__restrict__ inst_var0,
+               const int64_t *__restrict__ inst_nvar, const int16_t *__restrict__ pval,
+               const float *__restrict__ xbar, float *__restrict__ pp) {
+    __shared__ float red[4][64];
+    __shared__ float4 xs4[kBlkCols / 4];
+    constexpr int CPT = kBlkCols / 256;   // consecutive columns per thread (a multiple of 8)
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    float *xs = reinterpret_cast<float *>(xs4);
+    // a persistent grid (a few workgroups per CU) walks the tiles: many
+    // short-lived workgroups would cost more in dispatch than they stream
+    for (int g = blockIdx.x; g < ntile; g += gridDim.x) {
+        const int t = tile_inst[g];
+        const int v0 = static_cast<int>(inst_var0[t]);
+        const int c0 = tile_c0[g], c1 = min(c0 + kBlkCols, v0 + static_cast<int>(inst_nvar[t]));
+        const int nr = blk_nrow[t], r0 = blk_row0[t];
+        // the tile's xbar: coalesced loads into LDS, then 8 consecutive values per thread
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int c = c0 + 256 * k + tid;
+            xs[256 * k + tid] = c < c1 ? xbar[c] : 0.f;
+        }
+        __syncthreads();
+        const int cb = c0 + CPT * tid;
+        float xv[CPT];
+#pragma unroll
+        for (int h = 0; h < CPT / 4; ++h) {
+            const float4 a = xs4[(CPT / 4) * tid + h];
+            xv[4 * h] = a.x; xv[4 * h + 1] = a.y; xv[4 * h + 2] = a.z; xv[4 * h + 3] = a.w;
+        }
+        const int coff = cb - v0;
+#pragma unroll 2
+        for (int r = 0; r < nr; ++r) {
+            float sacc = 0.f;
+            if (cb < c1) {
+                const int4 *q4 = reinterpret_cast<const int4 *>(pval + pbase[r0 + r] + coff);
+#pragma unroll
+                for (int h = 0; h < CPT / 8; ++h) {
+                    if (cb + 8 * h >= c1) break;
+                    float a[8];
+                    unpack8(q4[h], a);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) sacc = fmaf(a[k], xv[8 * h + k], sacc);
+                }
+            }
+            sacc = group_sum<64>(sacc);
+            if (lane == 0) red[wv][r] = sacc;
+        }
+        __syncthreads();
+        if (tid < nr) pp[static_cast<int64_t>(g) * 64 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+        __syncthreads();   // red and xs are reused by the next tile
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_primal_block16(int ntile, const int *__restrict__ tile_inst, const int *__restrict__ tile_c0,
+                 const int *__restrict__ blk_row0, const int *__restrict__ blk_nrow,
+                 const int *__restrict__ blk_rows, const int64_t *__restrict__ pbase,
+                 const int64_t *__restrict__ inst_var0, const int64_t *__restrict__ inst_nvar,
+                 const int16_t *__restrict__ pval, const float *__restrict__ wy, const float *__restrict__ x_in,
+                 float *__restrict__ x_out, float *__restrict__ xbar, const float *__restrict__ ct,
+                 const float *__restrict__ tau1_inst, const double *__restrict__ rho,
+                 DevCounters *__restrict__ ctr) {
+    __shared__ float wys[64];
+    __shared__ float4 gs4[kBlkCols / 4];
+    constexpr int CPT = kBlkCols / 256;
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid == 0) ctr->k += 1;
+    const float *gsum = reinterpret_cast<const float *>(gs4);
+    for (int g = blockIdx.x; g < ntile; g += gridDim.x) {
+        const int t = tile_inst[g];
+        const int v0 = static_cast<int>(inst_var0[t]);
+        const int c0 = tile_c0[g], c1 = min(c0 + kBlkCols, v0 + static_cast<int>(inst_nvar[t]));
+        const int nr = blk_nrow[t], r0 = blk_row0[t];
+        if (tid < nr) wys[tid] = wy[blk_rows[r0 + tid]];
+        __syncthreads();
+        const int cb = c0 + CPT * tid;
+        const int coff = cb - v0;
+        float acc[CPT];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) acc[k] = 0.f;
+        if (cb < c1) {
+#pragma unroll 2
+            for (int r = 0; r < nr; ++r) {
+                const int4 *q4 = reinterpret_cast<const int4 *>(pval + pbase[r0 + r] + coff);
+                const float w = wys[r];
+#pragma unroll
+                for (int h = 0; h < CPT / 8; ++h) {
+                    if (cb + 8 * h >= c1) break;
+                    float a[8];
+                    unpack8(q4[h], a);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) acc[8 * h + k] = fmaf(a[k], w, acc[8 * h + k]);
+                }
+            }
+        }
+        // through LDS, so that the epilogue's loads and stores are coalesced
+#pragma unroll
+        for (int h = 0; h < CPT / 4; ++h)
+            gs4[(CPT / 4) * tid + h] = make_float4(acc[4 * h], acc[4 * h + 1], acc[4 * h + 2], acc[4 * h + 3]);
+        __syncthreads();
+        const float rh = static_cast<float>(rho[t]);
+        const float ta = tau1_inst[t];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int c = c0 + 256 * k + tid;
+            if (c >= c1) break;
+            const float xi = x_in[c];
+            float gr = ct[c] + rh;
+            gr -= gsum[256 * k + tid];
+            gr -= 2.f * rh * xi;
+            const float xn = fminf(fmaxf(xi - ta * gr, 0.f), 1.f);
+            x_out[c] = xn;
+            xbar[c] = 2.f * xn - xi;
+        }
+        __syncthreads();   // wys and gs4 are reused by the next tile
+    }
+}
 
 template <typename VT>
 __global__ void __launch_bounds__(256)
@@ -1146,10 +1286,11 @@ k_dual_block(const int *__restrict__ tile_inst, const int *__restrict__ tile_c0,
     const int nr = blk_nrow[t], r0 = blk_row0[t];
     // the rows' first entries, once: the row loop then issues only coefficient loads
     if (tid < nr) rbase[tid] = rp[blk_rows[r0 + tid]];
-    float xv[8];
-    int off[8];
+    constexpr int CPT = kBlkCols / 256;
+    float xv[CPT];
+    int off[CPT];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < CPT; ++k) {
         const int c = c0 + 256 * k + tid;
         xv[k] = c < c1 ? xbar[c] : 0.f;
         off[k] = c < c1 ? c - v0 : 0;
@@ -1160,7 +1301,7 @@ k_dual_block(const int *__restrict__ tile_inst, const int *__restrict__ tile_c0,
         const VT *a = val + rbase[r];
         float sacc = 0.f;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) sacc = fmaf(static_cast<float>(a[off[k]]), xv[k], sacc);
+        for (int k = 0; k < CPT; ++k) sacc = fmaf(static_cast<float>(a[off[k]]), xv[k], sacc);
         sacc = group_sum<64>(sacc);
         if (lane == 0) red[wv][r] = sacc;
     }
@@ -1211,10 +1352,11 @@ k_primal_block(const int *__restrict__ tile_inst, const int *__restrict__ tile_c
     }
     if (g == 0 && tid == 0) ctr->k += 1;
     __syncthreads();
-    float acc[8];
-    int off[8];
+    constexpr int CPT = kBlkCols / 256;
+    float acc[CPT];
+    int off[CPT];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < CPT; ++k) {
         const int c = c0 + 256 * k + tid;
         acc[k] = 0.f;
         off[k] = c < c1 ? c - v0 : 0;
@@ -1224,12 +1366,12 @@ k_primal_block(const int *__restrict__ tile_inst, const int *__restrict__ tile_c
         const VT *a = val + rbase[r];
         const float w = wys[r];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] = fmaf(static_cast<float>(a[off[k]]), w, acc[k]);
+        for (int k = 0; k < CPT; ++k) acc[k] = fmaf(static_cast<float>(a[off[k]]), w, acc[k]);
     }
     const float rh = static_cast<float>(rho[t]);
     const float ta = tau1_inst[t];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < CPT; ++k) {
         const int c = c0 + 256 * k + tid;
         if (c >= c1) continue;
         const float xi = x_in[c];
@@ -1247,7 +1389,10 @@ void launch_dual_block(hipStream_t s, const BlockView &b, int m, int m1, const i
                        const float *xbar, const float *omega, const float *rt, const float *tau2_inst,
                        const int *row_inst, const float *y_in, float *y_out, float *wy) {
     if (b.ntile <= 0) return;
-    if (val16)
+    if (b.pval)
+        k_dual_block16<<<std::min(b.ntile, kBlkGrid), 256, 0, s>>>(b.ntile, b.tile_inst, b.tile_c0, b.row0, b.nrow,
+                                                                   b.pbase, inst_var0, inst_nvar, b.pval, xbar, b.pp);
+    else if (val16)
         k_dual_block<int16_t><<<b.ntile, 256, 0, s>>>(b.tile_inst, b.tile_c0, b.row0, b.nrow, b.rows, rp, inst_var0,
                                                        inst_nvar, val16, xbar, b.pp);
     else
@@ -1262,7 +1407,11 @@ void launch_primal_block(hipStream_t s, const BlockView &b, const int *rp, const
                          const float *x_in, float *x_out, float *xbar, const float *ct, const float *tau1_inst,
                          const double *rho, DevCounters *ctr) {
     if (b.ntile <= 0) return;
-    if (val16)
+    if (b.pval)
+        k_primal_block16<<<std::min(b.ntile, kBlkGrid), 256, 0, s>>>(b.ntile, b.tile_inst, b.tile_c0, b.row0, b.nrow,
+                                                                     b.rows, b.pbase, inst_var0, inst_nvar, b.pval, wy,
+                                                                     x_in, x_out, xbar, ct, tau1_inst, rho, ctr);
+    else if (val16)
         k_primal_block<int16_t><<<b.ntile, 256, 0, s>>>(b.tile_inst, b.tile_c0, b.row0, b.nrow, b.rows, rp, inst_var0,
                                                          inst_nvar, val16, wy, x_in, x_out, xbar, ct, tau1_inst, rho,
                                                          ctr);

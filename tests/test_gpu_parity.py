@@ -347,7 +347,7 @@ def test_batched_graph_replay_matches_eager(G, kind):
         b.close()
 
 
-@pytest.mark.parametrize("which", ["single", "batch"])
+@pytest.mark.parametrize("which", ["single", "batch", "batch16"])
 def test_dense_block_spmvs_match_oracle(G, which):
     """The dense-block dual (tile of xbar reused by every row of its
     instance, tile sums combined in order) and primal (the instance's wy in
@@ -358,11 +358,14 @@ def test_dense_block_spmvs_match_oracle(G, which):
     if which == "single":
         parts = [I.knapsack_multi(5001, 5, seed=9)]
     else:
+        # batch16: int16 coefficients (the padded copy, aligned 16-byte loads);
+        # batch: one instance beyond int16 (int32 coefficients, strided loads)
         parts = I.knapsack_batch(6, seed=13, n_lo=700, n_hi=9000, m_lo=1, m_hi=9)
-        parts[3] = I.knapsack_multi(2500, 4, seed=4, wmax=100_000)    # coefficients beyond int16
+        if which == "batch":
+            parts[3] = I.knapsack_multi(2500, 4, seed=4, wmax=100_000)
     Bt = parts[0] if which == "single" else I.concat_instances(parts)
     T = len(parts)
-    off = Bt.inst_offsets if which == "batch" else np.array([[0, 0, 0], [Bt.n, Bt.m1, Bt.m2]])
+    off = Bt.inst_offsets if which != "single" else np.array([[0, 0, 0], [Bt.n, Bt.m1, Bt.m2]])
     prob = G.Problem(Bt, _params(G, autotune=0))
     states, Ss = [], []
     for Pt in parts:
