@@ -788,7 +788,11 @@ def run_workload(a):
                 traffic = ent.get("bytes_per_launch")
     except (OSError, ValueError):
         pass
+    # the device's bare streaming-read rate (1,024 workgroups, 512 MiB), next to the published peak
+    stream_ref = gfors.read_throughput(512 << 20, 1024) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "measured_stream_read_gbs": round(stream_ref, 1),
+                "frac_of_measured_stream_read": round(achieved / stream_ref, 4) if stream_ref > 0 else None,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_source": ("rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel on the same workload, K "
                                    "and launch shape, taken from profiles/hbm_traffic.json (not measured in this run)"

@@ -298,6 +298,16 @@ int gfors_kernel_times(gfors_problem *P, int32_t nsteps, int32_t K, double *avg_
  * Errors: GFORS_E_ARG for calls <= 0 or NULL pointers, GFORS_E_HIP. */
 int gfors_philox_throughput(void *hip_stream, int64_t calls, void *dev_sink, double *calls_per_s);
 
+/* Achievable streaming read bandwidth of the device: `workgroups` workgroups
+ * of 256 lanes read the caller's device buffer (bytes, a multiple of 16;
+ * 16-byte aligned) with one 16-byte load per lane and step, 5 timed passes
+ * after a warm-up on hip_stream; *bytes_per_s = bytes read per second.  A
+ * reference for the HBM rooflines next to the published 8 TB/s.  dev_sink:
+ * device memory of at least 4 bytes (written at most once).  E_ARG for bad
+ * sizes or pointers, E_HIP. */
+int gfors_read_throughput(void *hip_stream, const void *dev_buf, int64_t bytes, int32_t workgroups,
+                          void *dev_sink, double *bytes_per_s);
+
 /* Launch shapes in use: out[8] = {lanes per row of the dual SpMV, lanes per row
  * of the primal SpMV, column slices of the dual SpMV, slices of the primal,
  * SELL-64 layout for the dual (0/1), SELL-64 layout for the primal (0/1),

@@ -1881,6 +1881,30 @@ int gfors_philox_throughput(void *hip_stream, int64_t calls, void *dev_sink, dou
     return GFORS_OK;
 }
 
+int gfors_read_throughput(void *hip_stream, const void *dev_buf, int64_t bytes, int32_t workgroups,
+                          void *dev_sink, double *bytes_per_s) {
+    if (!dev_buf || !dev_sink || !bytes_per_s || bytes <= 0 || bytes % 16 != 0 || workgroups < 1 ||
+        (reinterpret_cast<uintptr_t>(dev_buf) & 15u) != 0)
+        return fail(GFORS_E_ARG, "bad argument (bytes > 0 and a multiple of 16, buffer 16-byte aligned, workgroups >= 1)");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    uint32_t *sink = static_cast<uint32_t *>(dev_sink);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    launch_read_peak(s, workgroups, dev_buf, bytes / 16, sink);   // warm-up
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < 5; ++r) launch_read_peak(s, workgroups, dev_buf, bytes / 16, sink);
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    HIP_TRY(hipEventDestroy(e0));
+    HIP_TRY(hipEventDestroy(e1));
+    HIP_TRY(hipGetLastError());
+    *bytes_per_s = ms > 0.f ? 5.0 * static_cast<double>(bytes) / (ms * 1e-3) : 0.0;
+    return GFORS_OK;
+}
+
 int gfors_autotune(gfors_problem *P) {
     if (!P) return fail(GFORS_E_ARG, "NULL handle");
     if (P->lu) return GFORS_OK;   // one launch shape (the lifted rows are short)

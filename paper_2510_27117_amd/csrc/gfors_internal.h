@@ -207,6 +207,7 @@ void launch_res_vars(hipStream_t s, const Tiles &vt, const int *rpQ, const int *
 
 // --------------------------------------------------------- sampling / eval
 void launch_philox_peak(hipStream_t s, int blocks, int iters, uint32_t *sink);
+void launch_read_peak(hipStream_t s, int blocks, const void *p, int64_t n16, uint32_t *sink);
 // Monotone relaxation repair (Sec. 2.4) of the sampled candidates: in each of
 // the nrows relaxed set-partitioning rows (variables var[rp[r]..rp[r+1]) in
 // (cost, index) order) only the first set variable of every candidate stays

@@ -576,6 +576,25 @@ void launch_philox_peak(hipStream_t s, int blocks, int iters, uint32_t *sink) {
     if (blocks > 0 && iters > 0) k_philox_peak<<<blocks, 256, 0, s>>>(iters, 0x243f6a88u, 0x85a308d3u, sink);
 }
 
+// Streaming read of n 16-byte words (grid-stride, one load per lane and
+// step, results folded so the loads are not dropped): the device's
+// achievable read bandwidth for a given number of workgroups, a reference
+// next to the published HBM peak.
+__global__ void __launch_bounds__(256)
+k_read_peak(const int4 *__restrict__ p, int64_t n, uint32_t *__restrict__ sink) {
+    const int64_t st = static_cast<int64_t>(gridDim.x) * 256;
+    uint32_t acc = 0u;
+    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += st) {
+        const int4 q = p[i];
+        acc ^= static_cast<uint32_t>(q.x ^ q.y ^ q.z ^ q.w);
+    }
+    if (acc == 0x9e3779b9u) sink[0] = acc;
+}
+
+void launch_read_peak(hipStream_t s, int blocks, const void *p, int64_t n16, uint32_t *sink) {
+    if (blocks > 0 && n16 > 0) k_read_peak<<<blocks, 256, 0, s>>>(static_cast<const int4 *>(p), n16, sink);
+}
+
 // ---------------------------------------------------------------------------
 // Rows whose violation is a bitwise function of the candidate words (64
 // candidates per word):

@@ -50,6 +50,7 @@ EXPORTS = [
     "gfors_tu_last_error", "gfors_mono_rows", "gfors_mono_repair", "gfors_mono_last_error",
     "gfors_philox_throughput", "gfors_eval_planes", "gfors_create_problem_static",
     "gfors_tu_create_ex", "gfors_tu_factor_info", "gfors_workspace_bytes_tu", "gfors_create_problem_tu",
+    "gfors_read_throughput",
 ]
 
 GFORS_TU_FACTORED = 1
@@ -132,6 +133,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gfors_mono_rows.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_int64, c_vp]
     L.gfors_mono_repair.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int64, c_vp]
     L.gfors_philox_throughput.argtypes = [c_vp, c_i64, c_vp, P(c_dbl)]
+    L.gfors_read_throughput.argtypes = [c_vp, c_vp, c_i64, c_i32, c_vp, P(c_dbl)]
     L.gfors_mono_last_error.argtypes = []
     L.gfors_mono_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -179,6 +181,22 @@ def philox_throughput(calls: int = 2_000_000_000, device: str = "cuda:0") -> flo
     out = c_dbl(0.0)
     _check(L.gfors_philox_throughput(ctypes.c_void_p(stream.cuda_stream), int(calls),
                                      ctypes.c_void_p(sink.data_ptr()), ctypes.byref(out)))
+    return float(out.value)
+
+
+def read_throughput(nbytes: int = 512 << 20, workgroups: int = 1024, device: str = "cuda:0") -> float:
+    """Bytes per second of a bare streaming read of nbytes on the device with
+    the given number of 256-lane workgroups (gfors_read_throughput)."""
+    import torch
+    L = load_library()
+    dev = torch.device(device)
+    buf = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = c_dbl(0.0)
+    _check(L.gfors_read_throughput(ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p(buf.data_ptr()),
+                                   int(buf.numel() * 4), int(workgroups), ctypes.c_void_p(sink.data_ptr()),
+                                   ctypes.byref(out)))
     return float(out.value)
 
 
