@@ -857,8 +857,15 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             }
             for (int t = 0; t < T && ok; ++t) ok = !irows[t].empty() && irows[t].size() <= 64;
             if (ok) {
-                std::vector<int> tinst, tc0, row0(T), nrow(T), rows, rank(m), t0(T), nt(T);
-                for (int t = 0; t < T; ++t) {
+                // instances with more rows first (their tiles take longest):
+                // the dispatcher hands out tiles in this order, so the last
+                // ones to start are short and the tail shrinks; the tiles of
+                // one instance stay consecutive and in column order
+                std::vector<int> tinst, tc0, row0(T), nrow(T), rows, rank(m), t0(T), nt(T), ord(T);
+                for (int t = 0; t < T; ++t) ord[t] = t;
+                std::stable_sort(ord.begin(), ord.end(),
+                                 [&](int u, int v) { return irows[u].size() > irows[v].size(); });
+                for (int t : ord) {
                     row0[t] = static_cast<int>(rows.size());
                     nrow[t] = static_cast<int>(irows[t].size());
                     for (size_t r = 0; r < irows[t].size(); ++r) {

@@ -1160,14 +1160,14 @@ k_dual_block16(int ntile, const int *__restrict__ tile_inst, const int *__restri
     constexpr int CPT = kBlkCols / 256;   // consecutive columns per thread (a multiple of 8)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     float *xs = reinterpret_cast<float *>(xs4);
-    // a persistent grid (a few workgroups per CU) walks the tiles: many
-    // short-lived workgroups would cost more in dispatch than they stream
+    // the launch gives every tile its own workgroup (kBlkGrid); the loop
+    // also serves a smaller grid
     for (int g = blockIdx.x; g < ntile; g += gridDim.x) {
         const int t = tile_inst[g];
         const int v0 = static_cast<int>(inst_var0[t]);
         const int c0 = tile_c0[g], c1 = min(c0 + kBlkCols, v0 + static_cast<int>(inst_nvar[t]));
         const int nr = blk_nrow[t], r0 = blk_row0[t];
-        // the tile's xbar: coalesced loads into LDS, then 8 consecutive values per thread
+        // the tile's xbar: coalesced loads into LDS, then CPT consecutive values per thread
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int c = c0 + 256 * k + tid;
@@ -1182,7 +1182,7 @@ k_dual_block16(int ntile, const int *__restrict__ tile_inst, const int *__restri
             xv[4 * h] = a.x; xv[4 * h + 1] = a.y; xv[4 * h + 2] = a.z; xv[4 * h + 3] = a.w;
         }
         const int coff = cb - v0;
-#pragma unroll 2
+#pragma unroll 4
         for (int r = 0; r < nr; ++r) {
             float sacc = 0.f;
             if (cb < c1) {
@@ -1233,7 +1233,7 @@ k_primal_block16(int ntile, const int *__restrict__ tile_inst, const int *__rest
 #pragma unroll
         for (int k = 0; k < CPT; ++k) acc[k] = 0.f;
         if (cb < c1) {
-#pragma unroll 2
+#pragma unroll 4
             for (int r = 0; r < nr; ++r) {
                 const int4 *q4 = reinterpret_cast<const int4 *>(pval + pbase[r0 + r] + coff);
                 const float w = wys[r];
