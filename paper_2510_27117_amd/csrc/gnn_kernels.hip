@@ -31,7 +31,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 // ------------------------------------------------------------------ features
 // Hv0 = relu(Fv Uv + uv), Fv_i = [x_i, 4 x_i (1 - x_i), ct_i / ctmax, 1]
 // Hc0 = relu(Fc Uc + uc), Fc_j = [y_j / (1 + |y_j|), rt_j / rtmax, [j >= m1], 1]
-// One wavefront per node, lane = hidden unit.
+// 16 lanes per node (four hidden units each), four nodes per wavefront.
 __global__ void __launch_bounds__(256)
 k_gnn_embed(int64_t n, int64_t m, int m1, const float *__restrict__ x, const float *__restrict__ y,
             const float *__restrict__ ct, const float *__restrict__ rt, float ictmax, float irtmax,
@@ -49,37 +49,52 @@ k_gnn_embed(int64_t n, int64_t m, int m1, const float *__restrict__ x, const flo
             Wc[k][t] = theta[kGnnOffUc + k * kGnnH + 4 * f + t];
         }
     }
+    // four nodes per 16-lane group and pass: their inputs are loaded together,
+    // so a wavefront keeps 8-12 loads in flight instead of 2-3
+    constexpr int NPG = 4;
+    const int64_t N = n + m;
     const int64_t ng = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 4;
-    for (int64_t node = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 4;
-         node < n + m; node += ng) {
-        float f0, f1, f2;
-        const bool var = node < n;
-        if (var) {
-            const float xi = x[node];
-            f0 = xi;
-            f1 = 4.f * xi * (1.f - xi);
-            f2 = ct[node] * ictmax;
-        } else {
-            const int64_t j2 = node - n;
-            const float yj = y[j2];
-            f0 = yj / (1.f + fabsf(yj));
-            f1 = rt[j2] * irtmax;
-            f2 = j2 >= m1 ? 1.f : 0.f;
-        }
-        float h[4];
+    for (int64_t base = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 4; base < N;
+         base += NPG * ng) {
+        float f0[NPG], f1[NPG], f2[NPG];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            float z = var ? bv[t] : bc[t];
-            z = fmaf(f0, var ? Wv[0][t] : Wc[0][t], z);
-            z = fmaf(f1, var ? Wv[1][t] : Wc[1][t], z);
-            z = fmaf(f2, var ? Wv[2][t] : Wc[2][t], z);
-            h[t] = fmaxf(z, 0.f);
+        for (int q = 0; q < NPG; ++q) {
+            const int64_t node = base + q * ng;
+            if (node < n) {
+                const float xi = x[node];
+                f0[q] = xi;
+                f1[q] = 4.f * xi * (1.f - xi);
+                f2[q] = ct[node] * ictmax;
+            } else if (node < N) {
+                const int64_t j2 = node - n;
+                const float yj = y[j2];
+                f0[q] = yj / (1.f + fabsf(yj));
+                f1[q] = rt[j2] * irtmax;
+                f2[q] = j2 >= m1 ? 1.f : 0.f;
+            } else {
+                f0[q] = f1[q] = f2[q] = 0.f;
+            }
         }
-        uint2 w;
-        w.x = static_cast<uint32_t>(f2bf(h[0])) | (static_cast<uint32_t>(f2bf(h[1])) << 16);
-        w.y = static_cast<uint32_t>(f2bf(h[2])) | (static_cast<uint32_t>(f2bf(h[3])) << 16);
-        uint16_t *dst = var ? Hv + node * kGnnH : Hc + (node - n) * kGnnH;
-        reinterpret_cast<uint2 *>(dst)[f] = w;
+#pragma unroll
+        for (int q = 0; q < NPG; ++q) {
+            const int64_t node = base + q * ng;
+            if (node >= N) break;
+            const bool var = node < n;
+            float h[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                float z = var ? bv[t] : bc[t];
+                z = fmaf(f0[q], var ? Wv[0][t] : Wc[0][t], z);
+                z = fmaf(f1[q], var ? Wv[1][t] : Wc[1][t], z);
+                z = fmaf(f2[q], var ? Wv[2][t] : Wc[2][t], z);
+                h[t] = fmaxf(z, 0.f);
+            }
+            uint2 w;
+            w.x = static_cast<uint32_t>(f2bf(h[0])) | (static_cast<uint32_t>(f2bf(h[1])) << 16);
+            w.y = static_cast<uint32_t>(f2bf(h[2])) | (static_cast<uint32_t>(f2bf(h[3])) << 16);
+            uint16_t *dst = var ? Hv + node * kGnnH : Hc + (node - n) * kGnnH;
+            reinterpret_cast<uint2 *>(dst)[f] = w;
+        }
     }
 }
 
@@ -242,36 +257,60 @@ k_gnn_spmm_short(int k0, int k1, const int *__restrict__ order, const int *__res
                  const int *__restrict__ ci, const int *__restrict__ val,
                  const float *__restrict__ rowinv, const void *__restrict__ in,
                  void *__restrict__ out) {
+    // two nodes per 16-lane group and pass, their entries walked in lockstep
+    // (slots past a node's end add 0 x a finite feature), so a wavefront has
+    // twice as many independent gathers in flight
+    constexpr int NPG = 2;
     const int f = threadIdx.x & 15;
     const int ng = (gridDim.x * blockDim.x) >> 4;
-    for (int k = k0 + static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 4); k < k1; k += ng) {
-        const int64_t r = order[k];
-        const int e0 = rp[r], e1 = rp[r + 1];
-        const float rs = ROWS ? rowinv[r] : 1.f;
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int eb = e0; eb < e1; eb += 4) {
-            int c[4];
-            float a[4];
+    for (int kb = k0 + static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 4); kb < k1; kb += NPG * ng) {
+        int64_t r[NPG];
+        int e0[NPG], e1[NPG];
+        float rs[NPG], acc[NPG][4];
+        int len = 0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = eb + u;
-                const bool ok = e < e1;
-                const int ee = ok ? e : e0;
-                c[u] = ci[ee];
-                a[u] = ok ? (val ? static_cast<float>(val[ee]) : 1.f) : 0.f;
-            }
-            Feat4 h[4];
+        for (int q = 0; q < NPG; ++q) {
+            const int k = kb + q * ng;
+            const bool live = k < k1;
+            r[q] = live ? order[k] : -1;
+            e0[q] = live ? rp[r[q]] : 0;
+            e1[q] = live ? rp[r[q] + 1] : 0;
+            rs[q] = (ROWS && live) ? rowinv[r[q]] : 1.f;
+            len = max(len, e1[q] - e0[q]);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] *= ROWS ? rs : rowinv[c[u]];
-                h[u] = load_feat4<IN_BF16>(in, c[u], f);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) acc[t] = fmaf(a[u], h[u].v[t], acc[t]);
+            for (int t = 0; t < 4; ++t) acc[q][t] = 0.f;
         }
-        store_feat4<OUT>(out, r, f, acc);
+        for (int d = 0; d < len; d += 4) {
+            int c[NPG][4];
+            float a[NPG][4];
+#pragma unroll
+            for (int q = 0; q < NPG; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0[q] + d + u;
+                    const bool ok = e < e1[q];
+                    // an entry exists (len > 0), so feature row 0 is a valid stand-in
+                    c[q][u] = ok ? ci[e] : 0;
+                    a[q][u] = ok ? (val ? static_cast<float>(val[e]) : 1.f) : 0.f;
+                }
+            Feat4 h[NPG][4];
+#pragma unroll
+            for (int q = 0; q < NPG; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[q][u] *= ROWS ? rs[q] : rowinv[c[q][u]];
+                    h[q][u] = load_feat4<IN_BF16>(in, c[q][u], f);
+                }
+#pragma unroll
+            for (int q = 0; q < NPG; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) acc[q][t] = fmaf(a[q][u], h[q][u].v[t], acc[q][t]);
+        }
+#pragma unroll
+        for (int q = 0; q < NPG; ++q)
+            if (r[q] >= 0) store_feat4<OUT>(out, r[q], f, acc[q]);
     }
 }
 

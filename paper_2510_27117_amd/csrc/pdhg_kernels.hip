@@ -1319,8 +1319,19 @@ k_dual_block_combine(int m, int m1, const int *__restrict__ row_inst, const int 
     if (j >= m) return;
     const int t = row_inst[j], rk = row_rank[j];
     const int g0 = inst_tile0[t], ng = inst_ntile[t];
+    const float *pr = pp + static_cast<int64_t>(g0) * 64 + rk;
+    // the tile sums in tile order; eight loads issued before their adds, so
+    // the chain waits on one memory latency per eight tiles, not per tile
     float sacc = 0.f;
-    for (int q = 0; q < ng; ++q) sacc += pp[static_cast<int64_t>(g0 + q) * 64 + rk];
+    int q = 0;
+    for (; q + 8 <= ng; q += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pr[static_cast<int64_t>(q + u) * 64];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sacc += v[u];
+    }
+    for (; q < ng; ++q) sacc += pr[static_cast<int64_t>(q) * 64];
     const float om = omega[j];
     float y = y_in[j] + tau2_inst[t] * (rt[j] - om * sacc);
     if (j < m1) y = fmaxf(y, 0.f);
