@@ -680,31 +680,46 @@ k_gnn_out(int64_t n, const uint16_t *__restrict__ Hv, const float *__restrict__ 
     float gw[4] = {0.f, 0.f, 0.f, 0.f}, gb = 0.f, ls = 0.f;
     const float inv_n = 1.f / static_cast<float>(n);
     const int64_t ng = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 4;
-    for (int64_t i = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 4; i < n; i += ng) {
-        const uint2 w = reinterpret_cast<const uint2 *>(Hv + i * kGnnH)[f];
-        const float h[4] = {__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
-                            __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u)};
-        float zz = h[0] * wo[0];
-        zz = fmaf(h[1], wo[1], zz);
-        zz = fmaf(h[2], wo[2], zz);
-        zz = fmaf(h[3], wo[3], zz);
+    // four nodes per group and pass, their feature loads issued together; the
+    // nodes are then taken in the order of a one-node loop (same sums)
+    constexpr int NPG = 4;
+    for (int64_t ib = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 4; ib < n; ib += NPG * ng) {
+        uint2 wq[NPG];
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) zz += __shfl_xor(zz, o, 16);
-        const float z = zz + bo;
-        const float pz = 1.f / (1.f + __expf(-z));
-        if (f == 0) {
-            if (logit) logit[i] = z;
-            if (p) p[i] = pz;
+        for (int u = 0; u < NPG; ++u) {
+            const int64_t i = ib + u * ng;
+            wq[u] = i < n ? reinterpret_cast<const uint2 *>(Hv + i * kGnnH)[f] : make_uint2(0u, 0u);
         }
-        if (target) {
-            const float t = target[i];
-            const float dz = (pz - t) * inv_n;
-            reinterpret_cast<float4 *>(dHv + i * kGnnH)[f] = make_float4(dz * wo[0], dz * wo[1], dz * wo[2], dz * wo[3]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) gw[q] += dz * h[q];
+        for (int u = 0; u < NPG; ++u) {
+            const int64_t i = ib + u * ng;
+            if (i >= n) break;   // uniform over the node's 16 lanes
+            const uint2 w = wq[u];
+            const float h[4] = {__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                                __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u)};
+            float zz = h[0] * wo[0];
+            zz = fmaf(h[1], wo[1], zz);
+            zz = fmaf(h[2], wo[2], zz);
+            zz = fmaf(h[3], wo[3], zz);
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) zz += __shfl_xor(zz, o, 16);
+            const float z = zz + bo;
+            const float pz = 1.f / (1.f + __expf(-z));
             if (f == 0) {
-                gb += dz;
-                ls += fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z))) - t * z;
+                if (logit) logit[i] = z;
+                if (p) p[i] = pz;
+            }
+            if (target) {
+                const float t = target[i];
+                const float dz = (pz - t) * inv_n;
+                reinterpret_cast<float4 *>(dHv + i * kGnnH)[f] =
+                    make_float4(dz * wo[0], dz * wo[1], dz * wo[2], dz * wo[3]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gw[q] += dz * h[q];
+                if (f == 0) {
+                    gb += dz;
+                    ls += fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z))) - t * z;
+                }
             }
         }
     }
