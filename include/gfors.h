@@ -311,7 +311,7 @@ int gfors_read_throughput(void *hip_stream, const void *dev_buf, int64_t bytes, 
 /* Launch shapes in use: out[8] = {lanes per row of the dual SpMV, lanes per row
  * of the primal SpMV, column slices of the dual SpMV, slices of the primal,
  * SELL-64 layout for the dual (0/1), SELL-64 layout for the primal (0/1),
- * zero-operand skipping / layout variant of the dual (0..4), of the primal (0..5)}
+ * zero-operand skipping / layout variant of the dual (0..5), of the primal (0..6)}
  * (1 slice = fused kernel; with SELL the lanes-per-row entry is unused; dual
  * lanes per row 256 = a workgroup per row, longest rows first).  Skipping
  * keeps the nonzero bitmap of the gathered vector in LDS and issues only the
@@ -324,7 +324,13 @@ int gfors_read_throughput(void *hip_stream, const void *dev_buf, int64_t bytes, 
  * 5 = dense-block tiles for problems whose every row spans all variables of
  * its instance (at most 64 rows per instance, Q = 0: the knapsack batch): a
  * workgroup per 2,048 columns of one instance, xbar (dual) or wy (primal) of
- * the tile read once and reused by every row. */
+ * the tile read once and reused by every row.  Dual 5 / primal 6 = light
+ * items with signed indices (one instance, Q = 0, every |a| = 1, and the rows /
+ * variables below 256 entries one contiguous range of the same number <= 8 of
+ * entries: facility location): the heavy items keep a workgroup each, the
+ * light ones read an entry-major copy of their indices with the
+ * coefficient's sign in bit 31 instead of row pointers and coefficients (the
+ * terms are added in the same order as with 1 lane per item). */
 int gfors_get_launch_cfg(gfors_problem *P, int32_t *out);
 
 /* Re-run the autotuner on the current iterate (the zero-operand bitmap
@@ -339,7 +345,7 @@ int gfors_autotune(gfors_problem *P);
  * (then lanes <= 16; the primal also needs Q = 0); SELL only where the problem
  * holds the SELL copy; skipping 1 only for the sliced SELL dual / the fused CSR
  * primal, 2 and 3 only with a SELL layout, all without Q and with bitmaps of at most
- * 64 KB; primal 4 and 5 and dual 4 only with 1 slice, no SELL, and where the
+ * 64 KB; primal 4, 5, 6 and dual 4, 5 only with 1 slice, no SELL, and where the
  * problem qualifies.
  * E_ARG otherwise (nothing is changed).  Drops captured graphs. */
 int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg);

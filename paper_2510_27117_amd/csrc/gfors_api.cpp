@@ -173,6 +173,8 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     sell_carve(P->sellT_want, n, 1, nnzK, P->sellT_cap, P->sellT_buf);
     P->val16 = cv.take<int16_t>(nnzK);
     P->ell = cv.take<int>((T == 1 && nnzQ == 0 && nnzK <= 8 * n) ? nnzK : 0);
+    P->lgt_d = cv.take<int>((T == 1 && nnzQ == 0) ? nnzK : 0);
+    P->lgt_p = cv.take<int>((T == 1 && nnzQ == 0) ? nnzK : 0);
     {
         // dense-block SpMV tables (filled only when the problem qualifies)
         const int64_t tb = n / kBlockCols + T + 1;
@@ -934,6 +936,46 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         if ((rc = upload(s, P->primal_order, ordT.data(), n))) return rc;
         P->heavy_cols = 0;
         while (P->heavy_cols < n && rpT[ordT[P->heavy_cols] + 1] - rpT[ordT[P->heavy_cols]] >= kHeavyLen) ++P->heavy_cols;
+        // light part with signed indices: one instance, no Q, every |a| = 1,
+        // the items below kHeavyLen entries one contiguous range of D <= 8
+        // entries each (the heavy ones keep a workgroup each)
+        if (T == 1 && !P->hasQ && m > 0 && P->lgt_d && P->lgt_p) {
+            bool unit_mag = true;
+            for (int64_t e = 0; e < P->nnzK && unit_mag; ++e) unit_mag = val[e] == 1 || val[e] == -1;
+            auto light_range = [&](const std::vector<int> &ptr, const std::vector<int> &ix, const std::vector<int> &vv,
+                                   int64_t cnt, int *dst, int &i0, int &L, int &D) -> int {
+                i0 = L = D = 0;
+                if (!unit_mag) return GFORS_OK;
+                int64_t lo = -1, hi = -1, nl = 0;
+                int d = -1;
+                for (int64_t i = 0; i < cnt; ++i) {
+                    const int len = ptr[i + 1] - ptr[i];
+                    if (len >= kHeavyLen) continue;
+                    if (d < 0) d = len;
+                    if (len != d) return GFORS_OK;
+                    if (lo < 0) lo = i;
+                    hi = i;
+                    ++nl;
+                }
+                if (nl == 0 || d < 1 || d > 8 || hi - lo + 1 != nl) return GFORS_OK;
+                std::vector<int> h(static_cast<size_t>(d) * nl);
+                for (int64_t k = 0; k < nl; ++k)
+                    for (int u = 0; u < d; ++u) {
+                        const int64_t e = ptr[lo + k] + u;
+                        h[static_cast<size_t>(u) * nl + k] =
+                            static_cast<int>(static_cast<uint32_t>(ix[e]) | (vv[e] < 0 ? 0x80000000u : 0u));
+                    }
+                int rc2 = upload(s, dst, h.data(), static_cast<int64_t>(h.size()));
+                if (rc2) return rc2;
+                if ((rc2 = sync(P))) return rc2;
+                i0 = static_cast<int>(lo);
+                L = static_cast<int>(nl);
+                D = d;
+                return GFORS_OK;
+            };
+            if ((rc = light_range(rp, ci, val, m, P->lgt_d, P->lgt_d0, P->lgt_dn, P->lgt_dd))) return rc;
+            if ((rc = light_range(rpT, ciT, valT, n, P->lgt_p, P->lgt_p0, P->lgt_pn, P->lgt_pd))) return rc;
+        }
         P->colT_deg = n > 0 ? rpT[1] - rpT[0] : 0;
         for (int64_t i = 1; i < n && P->colT_deg; ++i)
             if (rpT[i + 1] - rpT[i] != P->colT_deg) P->colT_deg = 0;
@@ -1219,6 +1261,13 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
     if (P->cfg.bits_dual == 4 && P->dense_block && !sell && slices == 1) {
         launch_dual_block(s, P->blk, m, m1, P->rp, P->val, P->use16 ? P->val16 : nullptr, P->d_inst_var0,
                           P->d_inst_nvar, P->xbar, P->omega, P->rt, P->di.tau2, P->row_inst, y_in, y_out, P->wy);
+    } else if (P->cfg.bits_dual == 5 && P->lgt_dd > 0 && !sell && slices == 1) {
+        // heavy rows a workgroup each, the light range a lane per row with signed indices
+        launch_dual_long(s, P->unitK, false, P->heavy_rows, m1, P->dual_order, P->rp, P->rowc0, P->ci, P->val,
+                         P->use16 ? P->val16 : nullptr, P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2,
+                         P->di.tau2, P->row_inst);
+        launch_dual_light(s, P->lgt_dd, P->lgt_d0, P->lgt_dn, m1, P->lgt_d, P->omega, P->rt, P->xbar, y_in, y_out,
+                          P->wy, tau2);
     } else if (sell && P->cfg.bits_dual >= 2) {
         const int nc = P->cfg.bits_dual == 3 ? 4 : 2;
         need_bx();
@@ -1289,7 +1338,13 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
         P->by_fresh = true;
     };
     bool xbar_bits = false;
-    if (P->cfg.bits_primal == 5 && P->dense_block && !sell && slices == 1) {
+    if (P->cfg.bits_primal == 6 && P->lgt_pd > 0 && !sell && slices == 1) {
+        // heavy variables a workgroup each, the light range a lane per variable with signed indices
+        launch_primal_long(s, P->unitK, false, P->heavy_cols, P->primal_order, P->rpT, P->ciT, P->valT, P->wy,
+                           x_in, x_out, xbar, P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst);
+        launch_primal_light(s, P->lgt_pd, P->lgt_p0, P->lgt_pn, P->lgt_p, P->wy, x_in, x_out, xbar, P->ct, tau1,
+                            P->di.rho, ctr);
+    } else if (P->cfg.bits_primal == 5 && P->dense_block && !sell && slices == 1) {
         launch_primal_block(s, P->blk, P->rp, P->val, P->use16 ? P->val16 : nullptr, P->d_inst_var0, P->d_inst_nvar,
                             P->wy, x_in, x_out, xbar, P->ct, P->di.tau1, P->di.rho, ctr);
     } else if (P->cfg.bits_primal == 4 && P->lds_slice > 0 && !sell && slices == 1) {
@@ -1348,6 +1403,7 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
 static int bits_ok_dual(gfors_problem *P, int slices, int sell, int bits) {
     if (bits == 0) return 1;
     if (bits == 4) return (P->dense_block && slices == 1 && !sell) ? 1 : 0;   // dense-block tiles
+    if (bits == 5) return (P->lgt_dd > 0 && slices == 1 && !sell) ? 1 : 0;    // light rows, signed indices
     if (!sell) return 0;
     if (bits == 1) return (slices > 1 && P->sellKS.ptr && P->sellKS.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
     if (bits != 2 && bits != 3) return 0;
@@ -1360,6 +1416,7 @@ static int bits_ok_primal(gfors_problem *P, int slices, int sell, int bits) {
     if (bits == 1) return (!sell && (P->m + 31) / 32 * 4 <= kMaxLdsBitmapBytes) ? 1 : 0;
     if (bits == 4) return (!sell && P->lds_slice > 0) ? 1 : 0;   // wy staged in LDS slices
     if (bits == 5) return (!sell && P->dense_block) ? 1 : 0;     // dense-block tiles
+    if (bits == 6) return (!sell && P->lgt_pd > 0) ? 1 : 0;      // light variables, signed indices
     if (bits != 2 && bits != 3) return 0;
     return (sell && P->sellT.ptr && P->sellT.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
 }
@@ -1413,10 +1470,11 @@ static int autotune(gfors_problem *P, bool with_eval) {
                 if (t < best) { best = t; best_bits = b; P->cfg.lpr_dual = 1; P->cfg.slices_dual = sl; P->cfg.sell_dual = 1; }
             }
         }
-        if (bits_ok_dual(P, 1, 0, 4)) {
-            P->cfg.bits_dual = 4;
+        for (int b : {4, 5}) {
+            if (!bits_ok_dual(P, 1, 0, b)) continue;
+            P->cfg.bits_dual = b;
             const float t = timeit([&] { launch_dual_cfg(P, 1, 1, 0, P->ybuf[P->cur], P->ybuf[1 - P->cur]); });
-            if (t < best) { best = t; best_bits = 4; P->cfg.lpr_dual = 1; P->cfg.slices_dual = 1; P->cfg.sell_dual = 0; }
+            if (t < best) { best = t; best_bits = b; P->cfg.lpr_dual = 1; P->cfg.slices_dual = 1; P->cfg.sell_dual = 0; }
         }
         P->cfg.bits_dual = best_bits;
     }
@@ -1451,7 +1509,7 @@ static int autotune(gfors_problem *P, bool with_eval) {
             const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 1, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
             if (t < best) { best = t; best_bits = b; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 1; }
         }
-        for (int b : {4, 5}) {
+        for (int b : {4, 5, 6}) {
             if (!bits_ok_primal(P, 1, 0, b)) continue;
             P->cfg.bits_primal = b;
             const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 0, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
@@ -1958,10 +2016,10 @@ int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
         return fail(GFORS_E_ARG, "no SELL copy of the constraint rows for this slicing");
     if (cfg[5] && !(cfg[3] == 1 && P->sellT.ptr))
         return fail(GFORS_E_ARG, "no SELL copy of the transposed rows");
-    if (cfg[6] < 0 || cfg[6] > 4 || !bits_ok_dual(P, cfg[2], cfg[4], cfg[6]))
-        return fail(GFORS_E_ARG, "bitmap dual: 1 needs the sliced SELL layout, 2 a SELL layout, and the slice bitmap must fit in LDS; 4 (dense-block tiles) needs rows dense over their instance's variables, <= 64 rows per instance, Q = 0, 1 slice, no SELL");
-    if (cfg[7] < 0 || cfg[7] > 5 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
-        return fail(GFORS_E_ARG, "bitmap primal: 1 needs the fused CSR layout, 2 the SELL layout; both need Q = 0 and a dual bitmap that fits in LDS; 4 (wy staged in LDS) needs the fused layout, unit coefficients, every variable in the same number (<= 8) of rows, one instance and Q = 0");
+    if (cfg[6] < 0 || cfg[6] > 5 || !bits_ok_dual(P, cfg[2], cfg[4], cfg[6]))
+        return fail(GFORS_E_ARG, "bitmap dual: 1 needs the sliced SELL layout, 2 a SELL layout, and the slice bitmap must fit in LDS; 4 (dense-block tiles) needs rows dense over their instance's variables, <= 64 rows per instance, Q = 0, 1 slice, no SELL; 5 (light rows with signed indices) needs one instance, Q = 0, every |a| = 1 and the rows below 256 entries one range of <= 8 entries each, 1 slice, no SELL");
+    if (cfg[7] < 0 || cfg[7] > 6 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
+        return fail(GFORS_E_ARG, "bitmap primal: 1 needs the fused CSR layout, 2 the SELL layout; both need Q = 0 and a dual bitmap that fits in LDS; 4 (wy staged in LDS) needs the fused layout, unit coefficients, every variable in the same number (<= 8) of rows, one instance and Q = 0; 6 (light variables with signed indices) as dual 5 for the variables");
     P->cfg.lpr_dual = cfg[0];
     P->cfg.lpr_primal = cfg[1];
     P->cfg.slices_dual = cfg[2];

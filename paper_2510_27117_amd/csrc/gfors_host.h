@@ -158,6 +158,10 @@ struct gfors_problem {
     int *colT0 = nullptr;        // first row of a variable whose rows are one contiguous range, else -1
     int *primal_order = nullptr; // variables, most rows first (block-per-variable primal)
     int heavy_rows = 0, heavy_cols = 0;   // rows / variables with kHeavyLen+ entries
+    // light rows / variables with signed entry-major indices (launch variants
+    // dual 5 / primal 6): items [lgt_*0, lgt_*0 + lgt_*n) of lgt_*d entries
+    int *lgt_d = nullptr, *lgt_p = nullptr;
+    int lgt_d0 = 0, lgt_dn = 0, lgt_dd = 0, lgt_p0 = 0, lgt_pn = 0, lgt_pd = 0;
     // node classes of the learned proposal's messages (prefixes of dual_order /
     // primal_order): kGnnHeavyLen+ entries, then more than kGnnShortLen
     int gnn_rh = 0, gnn_rm = 0, gnn_ch = 0, gnn_cm = 0;

@@ -179,6 +179,14 @@ void launch_primal_block(hipStream_t s, const BlockView &b, const int *rp, const
 // every variable in deg <= 8 rows, one instance, no Q); ell[u n + i] = the
 // u-th row of variable i (ascending).  Returns false for an unsupported deg.
 int primal_lds_slice(size_t lds_limit);
+// Light rows / variables [i0, i0 + L) of D <= 8 entries each, indices entry-major
+// with the coefficient's sign (|a| = 1) in bit 31; one instance, no Q.
+void launch_dual_light(hipStream_t s, int D, int i0, int L, int m1, const int *sidx, const float *omega,
+                       const float *rt, const float *xbar, const float *y_in, float *y_out, float *wy,
+                       float tau2);
+void launch_primal_light(hipStream_t s, int D, int i0, int L, const int *sidx, const float *wy,
+                         const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                         const double *rho, DevCounters *ctr);
 bool launch_primal_lds(hipStream_t s, int n, int m, int deg, int SL, const int *ell, const float *wy,
                        const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
                        const double *rho, DevCounters *ctr, uint64_t *xbits);

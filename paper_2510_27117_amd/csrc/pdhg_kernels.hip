@@ -1114,6 +1114,97 @@ bool launch_primal_lds(hipStream_t s, int n, int m, int deg, int SL, const int *
 }
 
 // ---------------------------------------------------------------------------
+// Light part with signed indices (one instance, every |a| = 1, no Q): the rows
+// (dual) or variables (primal) with fewer than kHeavyLen entries are one
+// contiguous range [i0, i0 + L) of D entries each, stored entry-major with
+// the coefficient's sign in bit 31 (sidx[u L + k] = index of entry u of item
+// i0 + k, negative when a = -1).  A lane per item loads its D indices with
+// coalesced loads and reads neither row pointers nor coefficients; the terms
+// are added in entry order (a +-1 product is exact, so the sums equal the CSR
+// kernels' with one lane per item).  The heavy items keep their
+// workgroup-per-item kernels.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256)
+k_dual_light(int i0, int L, int m1, const int *__restrict__ sidx, const float *__restrict__ omega,
+             const float *__restrict__ rt, const float *__restrict__ xbar, const float *__restrict__ y_in,
+             float *__restrict__ y_out, float *__restrict__ wy, float tau2) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= L) return;
+    int c[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) c[u] = sidx[static_cast<int64_t>(u) * L + k];
+    float g[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) g[u] = xbar[c[u] & 0x7fffffff];
+    float sum = 0.f;
+#pragma unroll
+    for (int u = 0; u < D; ++u) sum += c[u] < 0 ? -g[u] : g[u];
+    const int row = i0 + k;
+    const float om = omega[row];
+    const float t = rt[row] - om * sum;
+    float y = y_in[row] + tau2 * t;
+    if (row < m1) y = fmaxf(y, 0.f);
+    y_out[row] = y;
+    wy[row] = om * y;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256)
+k_primal_light(int i0, int L, const int *__restrict__ sidx, const float *__restrict__ wy,
+               const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ xbar,
+               const float *__restrict__ ct, float tau1, const double *__restrict__ rho,
+               DevCounters *__restrict__ ctr) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k == 0) ctr->k += 1;
+    if (k >= L) return;
+    const int i = i0 + k;
+    const float xi = x_in[i], cti = ct[i];
+    int c[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) c[u] = sidx[static_cast<int64_t>(u) * L + k];
+    float g[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) g[u] = wy[c[u] & 0x7fffffff];
+    float sum = 0.f;
+#pragma unroll
+    for (int u = 0; u < D; ++u) sum += c[u] < 0 ? -g[u] : g[u];
+    const float rh = static_cast<float>(rho[0]);
+    float gr = cti + rh;
+    gr -= sum;
+    gr -= 2.f * rh * xi;
+    const float xn = fminf(fmaxf(xi - tau1 * gr, 0.f), 1.f);
+    x_out[i] = xn;
+    xbar[i] = 2.f * xn - xi;
+}
+
+void launch_dual_light(hipStream_t s, int D, int i0, int L, int m1, const int *sidx, const float *omega,
+                       const float *rt, const float *xbar, const float *y_in, float *y_out, float *wy,
+                       float tau2) {
+    const int blocks = (L + 255) / 256;
+    if (blocks == 0) return;
+    switch (D) {
+#define GF_DL(DD) case DD: k_dual_light<DD><<<blocks, 256, 0, s>>>(i0, L, m1, sidx, omega, rt, xbar, y_in, y_out, wy, tau2); break;
+        GF_DL(1) GF_DL(2) GF_DL(3) GF_DL(4) GF_DL(5) GF_DL(6) GF_DL(7) GF_DL(8)
+#undef GF_DL
+        default: break;
+    }
+}
+
+void launch_primal_light(hipStream_t s, int D, int i0, int L, const int *sidx, const float *wy,
+                         const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                         const double *rho, DevCounters *ctr) {
+    const int blocks = (L + 255) / 256;
+    if (blocks == 0) return;
+    switch (D) {
+#define GF_PLG(DD) case DD: k_primal_light<DD><<<blocks, 256, 0, s>>>(i0, L, sidx, wy, x_in, x_out, xbar, ct, tau1, rho, ctr); break;
+        GF_PLG(1) GF_PLG(2) GF_PLG(3) GF_PLG(4) GF_PLG(5) GF_PLG(6) GF_PLG(7) GF_PLG(8)
+#undef GF_PLG
+        default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Dense-block SpMVs for batched instances whose rows are dense over their
 // instance's variables (every row of instance t has the columns
 // v0_t .. v0_t + n_t - 1 in order, at most 64 rows per instance, no Q): the

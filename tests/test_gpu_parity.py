@@ -970,3 +970,49 @@ def test_assign3d_sampler_rejects_bad_sizes(G):
                 prob.sample_eval_assign3d(*args)
     finally:
         prob.close()
+
+
+@pytest.mark.parametrize("nf,nc,seed", [(256, 260, 0), (300, 257, 4)])
+def test_light_signed_index_kernels_equal_csr(G, nf, nc, seed):
+    """Launch variants dual 5 / primal 6 (facility location with >= 256
+    facilities and customers: the assignment rows and the facility variables
+    are heavy, every link row and assignment variable has 2 entries of
+    coefficient +-1): the light items read signed entry-major indices instead
+    of row pointers and coefficients, and add the same terms in the same order
+    as the one-lane CSR kernels, so steps through them equal those of
+    (257, 257) exactly; one step is within tolerance of the oracle."""
+    P = I.facility_location(nf, nc, seed)
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=41, keep_every=40)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+
+    def run(cfg, steps):
+        prob.set_launch_cfg(*cfg)
+        prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+        prob.pdhg_steps(steps)
+        return prob.get_state()
+
+    base = (257, 257, 1, 1, 0, 0, 0, 0)
+    # the variants take no lanes-per-row entry of their own (1 stands for it)
+    for cfg in [(1, 257, 1, 1, 0, 0, 5, 0), (257, 1, 1, 1, 0, 0, 0, 6), (1, 1, 1, 1, 0, 0, 5, 6)]:
+        a, b = run(base, 1), run(cfg, 1)
+        assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"]), cfg
+        assert b["k"] == st.k + 1
+        assert rel_inf(b["x"], ref.x) <= TOL_PDHG and rel_inf(b["y"], ref.y) <= TOL_PDHG
+        a, b = run(base, 15), run(cfg, 15)
+        assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"]), cfg
+    prob.close()
+
+
+def test_light_signed_index_kernels_rejected_where_they_do_not_apply(G):
+    # coefficients beyond +-1; light items of two different lengths (small
+    # facility location: the assignment rows are light too); a quadratic term
+    for P in (I.knapsack_multi(777, 7, seed=3), I.facility_location(20, 60, 1), mixed_problem(150, seed=6)):
+        prob = G.Problem(P, _params(G, autotune=0))
+        with pytest.raises(G.GforsError, match="signed indices"):
+            prob.set_launch_cfg(1, 1, 1, 1, 0, 0, 5, 0)
+        with pytest.raises(G.GforsError, match="signed indices"):
+            prob.set_launch_cfg(1, 1, 1, 1, 0, 0, 0, 6)
+        prob.close()
