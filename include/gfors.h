@@ -311,7 +311,7 @@ int gfors_read_throughput(void *hip_stream, const void *dev_buf, int64_t bytes, 
 /* Launch shapes in use: out[8] = {lanes per row of the dual SpMV, lanes per row
  * of the primal SpMV, column slices of the dual SpMV, slices of the primal,
  * SELL-64 layout for the dual (0/1), SELL-64 layout for the primal (0/1),
- * zero-operand skipping / layout variant of the dual (0..5), of the primal (0..6)}
+ * zero-operand skipping / layout variant of the dual (0..5), of the primal (0..7)}
  * (1 slice = fused kernel; with SELL the lanes-per-row entry is unused; dual
  * lanes per row 256 = a workgroup per row, longest rows first).  Skipping
  * keeps the nonzero bitmap of the gathered vector in LDS and issues only the
@@ -330,7 +330,12 @@ int gfors_read_throughput(void *hip_stream, const void *dev_buf, int64_t bytes, 
  * entries: facility location): the heavy items keep a workgroup each, the
  * light ones read an entry-major copy of their indices with the
  * coefficient's sign in bit 31 instead of row pointers and coefficients (the
- * terms are added in the same order as with 1 lane per item). */
+ * terms are added in the same order as with 1 lane per item).  Primal 7 =
+ * primal 6 with the heavy variables in groups of up to 16 consecutive ones
+ * whose rows are those of the group's first variable shifted by their
+ * distance to it (same coefficients): the 16 variables of a group read wy of
+ * one entry as 16 consecutive floats (their sums are added in another order
+ * than with a workgroup per variable). */
 int gfors_get_launch_cfg(gfors_problem *P, int32_t *out);
 
 /* Re-run the autotuner on the current iterate (the zero-operand bitmap
@@ -345,7 +350,7 @@ int gfors_autotune(gfors_problem *P);
  * (then lanes <= 16; the primal also needs Q = 0); SELL only where the problem
  * holds the SELL copy; skipping 1 only for the sliced SELL dual / the fused CSR
  * primal, 2 and 3 only with a SELL layout, all without Q and with bitmaps of at most
- * 64 KB; primal 4, 5, 6 and dual 4, 5 only with 1 slice, no SELL, and where the
+ * 64 KB; primal 4 to 7 and dual 4, 5 only with 1 slice, no SELL, and where the
  * problem qualifies.
  * E_ARG otherwise (nothing is changed).  Drops captured graphs. */
 int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg);

@@ -175,6 +175,16 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->ell = cv.take<int>((T == 1 && nnzQ == 0 && nnzK <= 8 * n) ? nnzK : 0);
     P->lgt_d = cv.take<int>((T == 1 && nnzQ == 0) ? nnzK : 0);
     P->lgt_p = cv.take<int>((T == 1 && nnzQ == 0) ? nnzK : 0);
+    P->hg_cap_g = (T == 1 && nnzQ == 0) ? nnzK / kHeavyLen + 1 : 0;
+    P->hg_cap_c = (T == 1 && nnzQ == 0) ? nnzK / kHgChunk + P->hg_cap_g : 0;
+    P->hg_var0 = cv.take<int>(P->hg_cap_g);
+    P->hg_w = cv.take<int>(P->hg_cap_g);
+    P->hg_e0 = cv.take<int>(P->hg_cap_g);
+    P->hg_c0 = cv.take<int>(P->hg_cap_g + 1);
+    P->hg_chg = cv.take<int>(P->hg_cap_c);
+    P->hg_chb = cv.take<int>(P->hg_cap_c);
+    P->hg_che = cv.take<int>(P->hg_cap_c);
+    P->hg_part = cv.take<float>(P->hg_cap_c * 16);
     {
         // dense-block SpMV tables (filled only when the problem qualifies)
         const int64_t tb = n / kBlockCols + T + 1;
@@ -976,6 +986,56 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             if ((rc = light_range(rp, ci, val, m, P->lgt_d, P->lgt_d0, P->lgt_dn, P->lgt_dd))) return rc;
             if ((rc = light_range(rpT, ciT, valT, n, P->lgt_p, P->lgt_p0, P->lgt_pn, P->lgt_pd))) return rc;
         }
+        // heavy variables grouped: consecutive heavy variables (up to 16) of one
+        // length whose rows are those of the group's first variable shifted by
+        // their distance to it, with the same coefficients
+        P->hg_ngroup = P->hg_nchunk = 0;
+        if (P->lgt_pd > 0 && P->hg_cap_g > 0) {
+            std::vector<int> hv;
+            for (int64_t i = 0; i < n; ++i)
+                if (rpT[i + 1] - rpT[i] >= kHeavyLen) hv.push_back(static_cast<int>(i));
+            std::vector<int> gv0, gw, ge0, gc0, chg, chb, che;
+            size_t k = 0;
+            while (k < hv.size()) {
+                const int v0 = hv[k], len = rpT[v0 + 1] - rpT[v0];
+                int w = 1;
+                while (w < 16 && k + w < hv.size() && hv[k + w] == v0 + w) {
+                    const int v = v0 + w;
+                    bool same = rpT[v + 1] - rpT[v] == len;
+                    for (int e = 0; e < len && same; ++e)
+                        same = ciT[rpT[v] + e] == ciT[rpT[v0] + e] + w && valT[rpT[v] + e] == valT[rpT[v0] + e];
+                    if (!same) break;
+                    ++w;
+                }
+                gc0.push_back(static_cast<int>(chg.size()));
+                for (int b = 0; b < len; b += kHgChunk) {
+                    chg.push_back(static_cast<int>(gv0.size()));
+                    chb.push_back(b);
+                    che.push_back(std::min(len, b + kHgChunk));
+                }
+                gv0.push_back(v0);
+                gw.push_back(w);
+                ge0.push_back(rpT[v0]);
+                k += w;
+            }
+            gc0.push_back(static_cast<int>(chg.size()));
+            // worth it only when the groups are wide on average
+            const bool useful = !gv0.empty() && hv.size() >= 4 * gv0.size();
+            if (useful && static_cast<int64_t>(gv0.size()) <= P->hg_cap_g &&
+                static_cast<int64_t>(chg.size()) <= P->hg_cap_c) {
+                const int64_t G = static_cast<int64_t>(gv0.size()), C = static_cast<int64_t>(chg.size());
+                if ((rc = upload(s, P->hg_var0, gv0.data(), G))) return rc;
+                if ((rc = upload(s, P->hg_w, gw.data(), G))) return rc;
+                if ((rc = upload(s, P->hg_e0, ge0.data(), G))) return rc;
+                if ((rc = upload(s, P->hg_c0, gc0.data(), G + 1))) return rc;
+                if ((rc = upload(s, P->hg_chg, chg.data(), C))) return rc;
+                if ((rc = upload(s, P->hg_chb, chb.data(), C))) return rc;
+                if ((rc = upload(s, P->hg_che, che.data(), C))) return rc;
+                if ((rc = sync(P))) return rc;
+                P->hg_ngroup = static_cast<int>(G);
+                P->hg_nchunk = static_cast<int>(C);
+            }
+        }
         P->colT_deg = n > 0 ? rpT[1] - rpT[0] : 0;
         for (int64_t i = 1; i < n && P->colT_deg; ++i)
             if (rpT[i + 1] - rpT[i] != P->colT_deg) P->colT_deg = 0;
@@ -1338,12 +1398,20 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
         P->by_fresh = true;
     };
     bool xbar_bits = false;
-    if (P->cfg.bits_primal == 6 && P->lgt_pd > 0 && !sell && slices == 1) {
-        // heavy variables a workgroup each, the light range a lane per variable with signed indices
-        launch_primal_long(s, P->unitK, false, P->heavy_cols, P->primal_order, P->rpT, P->ciT, P->valT, P->wy,
-                           x_in, x_out, xbar, P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst);
+    if ((P->cfg.bits_primal == 6 || P->cfg.bits_primal == 7) && P->lgt_pd > 0 && !sell && slices == 1) {
+        // heavy variables a workgroup each (6) or in shift groups (7), the
+        // light range a lane per variable with signed indices
+        if (P->cfg.bits_primal == 7)
+            launch_primal_hgroup(s, P->unitK, P->hg_nchunk, P->hg_ngroup, P->hg_chg, P->hg_chb, P->hg_che,
+                                 P->hg_var0, P->hg_w, P->hg_e0, P->hg_c0, P->ciT, P->valT, P->wy, P->hg_part,
+                                 x_in, x_out, xbar, P->ct, tau1, P->di.rho);
+        else
+            launch_primal_long(s, P->unitK, false, P->heavy_cols, P->primal_order, P->rpT, P->ciT, P->valT,
+                               P->wy, x_in, x_out, xbar, P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst);
+        uint64_t *xb_out = (P->lgt_p0 == 0 && P->lgt_pn == P->n) ? xbits : nullptr;
         launch_primal_light(s, P->lgt_pd, P->lgt_p0, P->lgt_pn, P->lgt_p, P->wy, x_in, x_out, xbar, P->ct, tau1,
-                            P->di.rho, ctr);
+                            P->di.rho, ctr, xb_out);
+        xbar_bits = xb_out != nullptr;
     } else if (P->cfg.bits_primal == 5 && P->dense_block && !sell && slices == 1) {
         launch_primal_block(s, P->blk, P->rp, P->val, P->use16 ? P->val16 : nullptr, P->d_inst_var0, P->d_inst_nvar,
                             P->wy, x_in, x_out, xbar, P->ct, P->di.tau1, P->di.rho, ctr);
@@ -1417,6 +1485,7 @@ static int bits_ok_primal(gfors_problem *P, int slices, int sell, int bits) {
     if (bits == 4) return (!sell && P->lds_slice > 0) ? 1 : 0;   // wy staged in LDS slices
     if (bits == 5) return (!sell && P->dense_block) ? 1 : 0;     // dense-block tiles
     if (bits == 6) return (!sell && P->lgt_pd > 0) ? 1 : 0;      // light variables, signed indices
+    if (bits == 7) return (!sell && P->lgt_pd > 0 && P->hg_ngroup > 0) ? 1 : 0;   // + heavy shift groups
     if (bits != 2 && bits != 3) return 0;
     return (sell && P->sellT.ptr && P->sellT.ns / 8 <= kMaxLdsBitmapBytes) ? 1 : 0;
 }
@@ -1509,7 +1578,7 @@ static int autotune(gfors_problem *P, bool with_eval) {
             const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 1, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
             if (t < best) { best = t; best_bits = b; P->cfg.lpr_primal = 1; P->cfg.slices_primal = 1; P->cfg.sell_primal = 1; }
         }
-        for (int b : {4, 5, 6}) {
+        for (int b : {4, 5, 6, 7}) {
             if (!bits_ok_primal(P, 1, 0, b)) continue;
             P->cfg.bits_primal = b;
             const float t = timeit([&] { launch_primal_cfg(P, 1, 1, 0, P->xbuf[P->cur], xs, xb, P->ctr_scratch); });
@@ -2018,8 +2087,8 @@ int gfors_set_launch_cfg(gfors_problem *P, const int32_t *cfg) {
         return fail(GFORS_E_ARG, "no SELL copy of the transposed rows");
     if (cfg[6] < 0 || cfg[6] > 5 || !bits_ok_dual(P, cfg[2], cfg[4], cfg[6]))
         return fail(GFORS_E_ARG, "bitmap dual: 1 needs the sliced SELL layout, 2 a SELL layout, and the slice bitmap must fit in LDS; 4 (dense-block tiles) needs rows dense over their instance's variables, <= 64 rows per instance, Q = 0, 1 slice, no SELL; 5 (light rows with signed indices) needs one instance, Q = 0, every |a| = 1 and the rows below 256 entries one range of <= 8 entries each, 1 slice, no SELL");
-    if (cfg[7] < 0 || cfg[7] > 6 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
-        return fail(GFORS_E_ARG, "bitmap primal: 1 needs the fused CSR layout, 2 the SELL layout; both need Q = 0 and a dual bitmap that fits in LDS; 4 (wy staged in LDS) needs the fused layout, unit coefficients, every variable in the same number (<= 8) of rows, one instance and Q = 0; 6 (light variables with signed indices) as dual 5 for the variables");
+    if (cfg[7] < 0 || cfg[7] > 7 || !bits_ok_primal(P, cfg[3], cfg[5], cfg[7]))
+        return fail(GFORS_E_ARG, "bitmap primal: 1 needs the fused CSR layout, 2 the SELL layout; both need Q = 0 and a dual bitmap that fits in LDS; 4 (wy staged in LDS) needs the fused layout, unit coefficients, every variable in the same number (<= 8) of rows, one instance and Q = 0; 6 (light variables with signed indices) as dual 5 for the variables; 7 = 6 with the heavy variables in groups of up to 16 whose rows are unit shifts of each other");
     P->cfg.lpr_dual = cfg[0];
     P->cfg.lpr_primal = cfg[1];
     P->cfg.slices_dual = cfg[2];

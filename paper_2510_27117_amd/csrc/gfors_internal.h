@@ -89,6 +89,7 @@ constexpr int kEvalPair = 3;         // one or two entries: truth table over (x_
 constexpr int kLprBlock = 256;  // launch shape "a workgroup of 256 lanes per row"; 256 + L:
                                 // rows of kHeavyLen+ entries a workgroup each, others L lanes
 constexpr int kHeavyLen = 256;
+constexpr int kHgChunk = 512;   // entries per workgroup of the heavy shift-group primal
 
 // ------------------------------------------------------------------ PDHG
 // val16: the coefficients as int16 when every |a| <= 32767 (else null)
@@ -180,13 +181,21 @@ void launch_primal_block(hipStream_t s, const BlockView &b, const int *rp, const
 // u-th row of variable i (ascending).  Returns false for an unsupported deg.
 int primal_lds_slice(size_t lds_limit);
 // Light rows / variables [i0, i0 + L) of D <= 8 entries each, indices entry-major
-// with the coefficient's sign (|a| = 1) in bit 31; one instance, no Q.
+// with the coefficient's sign (|a| = 1) in bit 31; one instance, no Q.  xbits:
+// nonzero bitmap of xbar (only when the range is every variable), or null.
 void launch_dual_light(hipStream_t s, int D, int i0, int L, int m1, const int *sidx, const float *omega,
                        const float *rt, const float *xbar, const float *y_in, float *y_out, float *wy,
                        float tau2);
 void launch_primal_light(hipStream_t s, int D, int i0, int L, const int *sidx, const float *wy,
                          const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
-                         const double *rho, DevCounters *ctr);
+                         const double *rho, DevCounters *ctr, uint64_t *xbits);
+// Heavy variables in groups of <= 16 whose rows are unit shifts of the first
+// one's (one instance, no Q): chunk partials, then the per-variable update.
+void launch_primal_hgroup(hipStream_t s, bool unit, int nchunk, int ngroup, const int *ch_g, const int *ch_b,
+                          const int *ch_e, const int *hg_var0, const int *hg_w, const int *hg_e0,
+                          const int *hg_c0, const int *ciT, const int *valT, const float *wy, float *part,
+                          const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                          const double *rho);
 bool launch_primal_lds(hipStream_t s, int n, int m, int deg, int SL, const int *ell, const float *wy,
                        const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
                        const double *rho, DevCounters *ctr, uint64_t *xbits);

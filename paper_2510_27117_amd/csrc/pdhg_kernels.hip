@@ -1149,33 +1149,129 @@ k_dual_light(int i0, int L, int m1, const int *__restrict__ sidx, const float *_
     wy[row] = om * y;
 }
 
+// xbits (optional, only when the light range is every variable): the nonzero
+// bitmap of the new xbar for the zero-skipping dual, one word per wavefront.
 template <int D>
 __global__ void __launch_bounds__(256)
 k_primal_light(int i0, int L, const int *__restrict__ sidx, const float *__restrict__ wy,
                const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ xbar,
                const float *__restrict__ ct, float tau1, const double *__restrict__ rho,
-               DevCounters *__restrict__ ctr) {
+               DevCounters *__restrict__ ctr, uint64_t *__restrict__ xbits) {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k == 0) ctr->k += 1;
-    if (k >= L) return;
-    const int i = i0 + k;
-    const float xi = x_in[i], cti = ct[i];
-    int c[D];
+    float xb = 0.f;
+    if (k < L) {
+        const int i = i0 + k;
+        const float xi = x_in[i], cti = ct[i];
+        int c[D];
 #pragma unroll
-    for (int u = 0; u < D; ++u) c[u] = sidx[static_cast<int64_t>(u) * L + k];
-    float g[D];
+        for (int u = 0; u < D; ++u) c[u] = sidx[static_cast<int64_t>(u) * L + k];
+        float g[D];
 #pragma unroll
-    for (int u = 0; u < D; ++u) g[u] = wy[c[u] & 0x7fffffff];
-    float sum = 0.f;
+        for (int u = 0; u < D; ++u) g[u] = wy[c[u] & 0x7fffffff];
+        float sum = 0.f;
 #pragma unroll
-    for (int u = 0; u < D; ++u) sum += c[u] < 0 ? -g[u] : g[u];
+        for (int u = 0; u < D; ++u) sum += c[u] < 0 ? -g[u] : g[u];
+        const float rh = static_cast<float>(rho[0]);
+        float gr = cti + rh;
+        gr -= sum;
+        gr -= 2.f * rh * xi;
+        const float xn = fminf(fmaxf(xi - tau1 * gr, 0.f), 1.f);
+        x_out[i] = xn;
+        xb = 2.f * xn - xi;
+        xbar[i] = xb;
+    }
+    if (xbits) {
+        const uint64_t bal = __ballot(k < L && xb != 0.f);
+        if ((threadIdx.x & 63) == 0 && k < L) xbits[k >> 6] = bal;
+    }
+}
+
+// Heavy variables in groups of up to 16 consecutive ones whose rows are unit
+// shifts of each other (variable v0 + d has rows r + d for the rows r of v0,
+// with the same coefficients: the facilities of a facility location, whose
+// link rows are numbered customer-major).  A workgroup takes a chunk of a
+// group's entries: 16 entry slots x 16 variables, lane (q, d) adds a_e
+// wy[r_e + d] over the entries e = q, q + 16, ... of the chunk, so the 16 lanes
+// of one entry read 16 consecutive floats (one request instead of 16 gathers).
+// The chunk's 16 slot sums are added in slot order; k_primal_hgroup_fin adds
+// a variable's chunk sums in chunk order and applies the primal update.
+template <bool UNIT>
+__global__ void __launch_bounds__(256)
+k_primal_hgroup(const int *__restrict__ ch_g, const int *__restrict__ ch_b, const int *__restrict__ ch_e,
+                const int *__restrict__ hg_w, const int *__restrict__ hg_e0, const int *__restrict__ ciT,
+                const int *__restrict__ valT, const float *__restrict__ wy, float *__restrict__ part) {
+    __shared__ float red[16][17];
+    const int c = blockIdx.x;
+    const int g = ch_g[c];
+    const int d = threadIdx.x & 15, q = threadIdx.x >> 4;
+    const int w = hg_w[g], base = hg_e0[g];
+    const int b1 = ch_e[c];
+    float acc = 0.f;
+    for (int e = ch_b[c] + q; e < b1; e += 16 * kLongUnroll) {
+        int r[kLongUnroll], a[kLongUnroll];
+#pragma unroll
+        for (int u = 0; u < kLongUnroll; ++u) {
+            const int ee = e + 16 * u;
+            const bool in = ee < b1;
+            r[u] = in ? ciT[base + ee] : 0;
+            a[u] = UNIT ? (in ? 1 : 0) : (in ? valT[base + ee] : 0);
+        }
+        float v[kLongUnroll];
+#pragma unroll
+        for (int u = 0; u < kLongUnroll; ++u) v[u] = (a[u] != 0 && d < w) ? wy[r[u] + d] : 0.f;
+#pragma unroll
+        for (int u = 0; u < kLongUnroll; ++u) acc = fmaf(static_cast<float>(a[u]), v[u], acc);
+    }
+    red[q][d] = acc;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        float sum = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sum += red[k][threadIdx.x];
+        part[static_cast<int64_t>(c) * 16 + threadIdx.x] = sum;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_primal_hgroup_fin(int ngroup, const int *__restrict__ hg_var0, const int *__restrict__ hg_w,
+                    const int *__restrict__ hg_c0, const float *__restrict__ part,
+                    const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ xbar,
+                    const float *__restrict__ ct, float tau1, const double *__restrict__ rho) {
+    const int tid = blockIdx.x * 256 + threadIdx.x;
+    const int g = tid >> 4, d = tid & 15;
+    if (g >= ngroup || d >= hg_w[g]) return;
+    const int c0 = hg_c0[g], c1 = hg_c0[g + 1];
+    const float *pr = part + static_cast<int64_t>(c0) * 16 + d;
+    float tot = 0.f;
+    int c = 0;
+    for (; c + 8 <= c1 - c0; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pr[static_cast<int64_t>(c + u) * 16];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tot += v[u];
+    }
+    for (; c < c1 - c0; ++c) tot += pr[static_cast<int64_t>(c) * 16];
+    const int i = hg_var0[g] + d;
+    const float xi = x_in[i];
     const float rh = static_cast<float>(rho[0]);
-    float gr = cti + rh;
-    gr -= sum;
-    gr -= 2.f * rh * xi;
+    const float gr = ct[i] + rh - tot - 2.f * rh * xi;
     const float xn = fminf(fmaxf(xi - tau1 * gr, 0.f), 1.f);
     x_out[i] = xn;
     xbar[i] = 2.f * xn - xi;
+}
+
+void launch_primal_hgroup(hipStream_t s, bool unit, int nchunk, int ngroup, const int *ch_g, const int *ch_b,
+                          const int *ch_e, const int *hg_var0, const int *hg_w, const int *hg_e0,
+                          const int *hg_c0, const int *ciT, const int *valT, const float *wy, float *part,
+                          const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
+                          const double *rho) {
+    if (nchunk <= 0 || ngroup <= 0) return;
+    if (unit) k_primal_hgroup<true><<<nchunk, 256, 0, s>>>(ch_g, ch_b, ch_e, hg_w, hg_e0, ciT, valT, wy, part);
+    else k_primal_hgroup<false><<<nchunk, 256, 0, s>>>(ch_g, ch_b, ch_e, hg_w, hg_e0, ciT, valT, wy, part);
+    k_primal_hgroup_fin<<<(ngroup * 16 + 255) / 256, 256, 0, s>>>(ngroup, hg_var0, hg_w, hg_c0, part, x_in, x_out,
+                                                                   xbar, ct, tau1, rho);
 }
 
 void launch_dual_light(hipStream_t s, int D, int i0, int L, int m1, const int *sidx, const float *omega,
@@ -1193,11 +1289,11 @@ void launch_dual_light(hipStream_t s, int D, int i0, int L, int m1, const int *s
 
 void launch_primal_light(hipStream_t s, int D, int i0, int L, const int *sidx, const float *wy,
                          const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
-                         const double *rho, DevCounters *ctr) {
+                         const double *rho, DevCounters *ctr, uint64_t *xbits) {
     const int blocks = (L + 255) / 256;
     if (blocks == 0) return;
     switch (D) {
-#define GF_PLG(DD) case DD: k_primal_light<DD><<<blocks, 256, 0, s>>>(i0, L, sidx, wy, x_in, x_out, xbar, ct, tau1, rho, ctr); break;
+#define GF_PLG(DD) case DD: k_primal_light<DD><<<blocks, 256, 0, s>>>(i0, L, sidx, wy, x_in, x_out, xbar, ct, tau1, rho, ctr, xbits); break;
         GF_PLG(1) GF_PLG(2) GF_PLG(3) GF_PLG(4) GF_PLG(5) GF_PLG(6) GF_PLG(7) GF_PLG(8)
 #undef GF_PLG
         default: break;

@@ -1016,3 +1016,75 @@ def test_light_signed_index_kernels_rejected_where_they_do_not_apply(G):
         with pytest.raises(G.GforsError, match="signed indices"):
             prob.set_launch_cfg(1, 1, 1, 1, 0, 0, 0, 6)
         prob.close()
+
+
+@pytest.mark.parametrize("shape", [(200_003, 20_011, 5, 3), (70_001, 9_001, 3, 8)])
+def test_light_signed_index_primal_writes_the_xbar_bitmap(G, shape):
+    """Set cover (unit coefficients, every variable in the same number of
+    rows: the light range is every variable): primal 6 equals the one-lane CSR
+    primal exactly, and writes the nonzero bitmap of xbar that the
+    zero-skipping dual then reads, so 20 steps through (dual 2 on the sliced
+    SELL copy, primal 6) equal 20 steps through (dual 2, primal 1)."""
+    n, m, deg, seed = shape
+    P = I.set_cover_columns(n, m, deg, seed=seed)
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=61, keep_every=60)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+
+    def run(cfg, steps):
+        prob.set_launch_cfg(*cfg)
+        prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+        prob.pdhg_steps(steps)
+        return prob.get_state()
+
+    a, b = run((16, 1, 1, 1, 0, 0, 0, 0), 1), run((16, 1, 1, 1, 0, 0, 0, 6), 1)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+    assert rel_inf(b["x"], ref.x) <= TOL_PDHG and rel_inf(b["y"], ref.y) <= TOL_PDHG
+    skip = (1, 1, 8, 1, 1, 0, 2, 1)
+    try:
+        c = run(skip, 20)
+    except G.GforsError:
+        skip = (16, 1, 1, 1, 0, 0, 0, 1)
+        c = run(skip, 20)
+    d = run(skip[:7] + (6,), 20)
+    assert np.array_equal(c["x"], d["x"]) and np.array_equal(c["y"], d["y"])
+    prob.close()
+
+
+@pytest.mark.parametrize("nf,nc,seed", [(256, 260, 0), (300, 257, 4)])
+def test_heavy_shift_group_primal(G, nf, nc, seed):
+    """Launch variant primal 7 (facility location: the facility variables are
+    heavy, and facility i + d has the link rows of facility i shifted by d):
+    groups of up to 16 facilities read wy of one entry as 16 consecutive
+    floats.  The heavy sums are added in another order than with a workgroup
+    per variable, so one step is checked against the oracle; two runs give the
+    same bits; and 15 steps stay within 1e-5 of primal 6."""
+    P = I.facility_location(nf, nc, seed)
+    S, traj = oracle_trajectory(P, O.Params(k_int=20), steps=41, keep_every=40)
+    st, rho = traj[-1]
+    s32 = f32_state(st)
+    ref = O.pdhg_step(S, s32, rho)
+    prob = G.Problem(P, _params(G, autotune=0))
+
+    def run(cfg, steps):
+        prob.set_launch_cfg(*cfg)
+        prob.set_state(s32.x, s32.x_prev, s32.y, rho, k=st.k)
+        prob.pdhg_steps(steps)
+        return prob.get_state()
+
+    a = run((1, 1, 1, 1, 0, 0, 5, 7), 1)
+    assert rel_inf(a["x"], ref.x) <= TOL_PDHG and rel_inf(a["y"], ref.y) <= TOL_PDHG
+    assert a["k"] == st.k + 1
+    b = run((1, 1, 1, 1, 0, 0, 5, 7), 1)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+    c, d = run((1, 1, 1, 1, 0, 0, 5, 6), 15), run((1, 1, 1, 1, 0, 0, 5, 7), 15)
+    assert rel_inf(d["x"], c["x"]) <= TOL_PDHG and rel_inf(d["y"], c["y"]) <= TOL_PDHG
+    prob.close()
+    # no shift groups where the heavy variables do not line up (set cover
+    # columns have no heavy variable at all)
+    prob = G.Problem(I.set_cover_columns(5003, 997, 5, seed=2), _params(G, autotune=0))
+    with pytest.raises(G.GforsError, match="unit shifts"):
+        prob.set_launch_cfg(1, 1, 1, 1, 0, 0, 0, 7)
+    prob.close()
