@@ -967,14 +967,21 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
                     hi = i;
                     ++nl;
                 }
-                if (nl == 0 || d < 1 || d > 8 || hi - lo + 1 != nl) return GFORS_OK;
-                std::vector<int> h(static_cast<size_t>(d) * nl);
-                for (int64_t k = 0; k < nl; ++k)
+                // heavy items inside the range (at most one in eight) are
+                // holes marked kLightHole; the light kernels skip them
+                const int64_t span = hi - lo + 1;
+                if (nl == 0 || d < 1 || d > 8 || span > nl + nl / 8 || static_cast<int64_t>(d) * span > P->nnzK)
+                    return GFORS_OK;
+                std::vector<int> h(static_cast<size_t>(d) * span, kLightHole);
+                for (int64_t k = 0; k < span; ++k) {
+                    if (ptr[lo + k + 1] - ptr[lo + k] >= kHeavyLen) continue;
                     for (int u = 0; u < d; ++u) {
                         const int64_t e = ptr[lo + k] + u;
-                        h[static_cast<size_t>(u) * nl + k] =
+                        h[static_cast<size_t>(u) * span + k] =
                             static_cast<int>(static_cast<uint32_t>(ix[e]) | (vv[e] < 0 ? 0x80000000u : 0u));
                     }
+                }
+                nl = span;
                 int rc2 = upload(s, dst, h.data(), static_cast<int64_t>(h.size()));
                 if (rc2) return rc2;
                 if ((rc2 = sync(P))) return rc2;
@@ -1408,7 +1415,7 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
         else
             launch_primal_long(s, P->unitK, false, P->heavy_cols, P->primal_order, P->rpT, P->ciT, P->valT,
                                P->wy, x_in, x_out, xbar, P->ct, tau1, P->di.tau1, P->di.rho, P->var_inst);
-        uint64_t *xb_out = (P->lgt_p0 == 0 && P->lgt_pn == P->n) ? xbits : nullptr;
+        uint64_t *xb_out = (P->lgt_p0 == 0 && P->lgt_pn == P->n && P->heavy_cols == 0) ? xbits : nullptr;
         launch_primal_light(s, P->lgt_pd, P->lgt_p0, P->lgt_pn, P->lgt_p, P->wy, x_in, x_out, xbar, P->ct, tau1,
                             P->di.rho, ctr, xb_out);
         xbar_bits = xb_out != nullptr;

@@ -89,6 +89,7 @@ constexpr int kEvalPair = 3;         // one or two entries: truth table over (x_
 constexpr int kLprBlock = 256;  // launch shape "a workgroup of 256 lanes per row"; 256 + L:
                                 // rows of kHeavyLen+ entries a workgroup each, others L lanes
 constexpr int kHeavyLen = 256;
+constexpr int kLightHole = 0x7fffffff;   // signed-index slot of a heavy item inside the light range
 constexpr int kHgChunk = 512;   // entries per workgroup of the heavy shift-group primal
 
 // ------------------------------------------------------------------ PDHG

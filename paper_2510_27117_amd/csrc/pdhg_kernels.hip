@@ -1115,10 +1115,11 @@ bool launch_primal_lds(hipStream_t s, int n, int m, int deg, int SL, const int *
 
 // ---------------------------------------------------------------------------
 // Light part with signed indices (one instance, every |a| = 1, no Q): the rows
-// (dual) or variables (primal) with fewer than kHeavyLen entries are one
-// contiguous range [i0, i0 + L) of D entries each, stored entry-major with
-// the coefficient's sign in bit 31 (sidx[u L + k] = index of entry u of item
-// i0 + k, negative when a = -1).  A lane per item loads its D indices with
+// (dual) or variables (primal) with fewer than kHeavyLen entries lie in a
+// range [i0, i0 + L) and have D entries each, stored entry-major with the
+// coefficient's sign in bit 31 (sidx[u L + k] = index of entry u of item
+// i0 + k, negative when a = -1); a heavy item inside the range is a hole
+// (sidx[k] = kLightHole) left to its workgroup kernel.  A lane per item loads its D indices with
 // coalesced loads and reads neither row pointers nor coefficients; the terms
 // are added in entry order (a +-1 product is exact, so the sums equal the CSR
 // kernels' with one lane per item).  The heavy items keep their
@@ -1134,6 +1135,7 @@ k_dual_light(int i0, int L, int m1, const int *__restrict__ sidx, const float *_
     int c[D];
 #pragma unroll
     for (int u = 0; u < D; ++u) c[u] = sidx[static_cast<int64_t>(u) * L + k];
+    if (c[0] == kLightHole) return;   // a heavy row: its workgroup kernel updates it
     float g[D];
 #pragma unroll
     for (int u = 0; u < D; ++u) g[u] = xbar[c[u] & 0x7fffffff];
@@ -1160,7 +1162,8 @@ k_primal_light(int i0, int L, const int *__restrict__ sidx, const float *__restr
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k == 0) ctr->k += 1;
     float xb = 0.f;
-    if (k < L) {
+    const bool live = k < L && sidx[k] != kLightHole;   // holes: heavy variables, updated elsewhere
+    if (live) {
         const int i = i0 + k;
         const float xi = x_in[i], cti = ct[i];
         int c[D];
@@ -1182,7 +1185,7 @@ k_primal_light(int i0, int L, const int *__restrict__ sidx, const float *__restr
         xbar[i] = xb;
     }
     if (xbits) {
-        const uint64_t bal = __ballot(k < L && xb != 0.f);
+        const uint64_t bal = __ballot(live && xb != 0.f);
         if ((threadIdx.x & 63) == 0 && k < L) xbits[k >> 6] = bal;
     }
 }
