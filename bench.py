@@ -157,6 +157,60 @@ def kernel_bytes(bip, K, idx=None):
     return out
 
 
+def signed_index_bytes(bip, bits_dual, bits_primal, kb):
+    """The SpMVs' bytes in the signed-index launch variants (dual 5, primal 6
+    and 7): a light item (< 256 entries) reads its D 4-byte signed indices and
+    neither a row pointer nor a coefficient; a heavy item its two row pointers,
+    its indices (unless its entries are one contiguous range) and
+    coefficients; in primal 7 a group of up to 16 heavy variables with
+    unit-shifted rows reads the indices and coefficients of its first variable
+    only.  Vectors as in kernel_bytes.  Returns kb updated."""
+    import scipy.sparse as sp
+    if bits_dual != 5 and bits_primal not in (6, 7):
+        return kb
+    mats = [M for M in (bip.A, bip.B) if M is not None and M.nrows]
+    K = sp.vstack([sp.csr_matrix((M.values().astype(np.int64), np.asarray(M.col), np.asarray(M.row_ptr)),
+                                 shape=(M.nrows, bip.n)) for M in mats]).tocsr()
+    m, n = K.shape
+    vb = 2 if np.abs(K.data).max(initial=0) <= 32767 else 4
+    heavy = 256
+    out = dict(kb)
+
+    def side(M, nvec_other, extra, group):
+        ln = np.diff(M.indptr)
+        hv = ln >= heavy
+        b = int(4 * ln[~hv].sum())                         # light: signed indices
+        first = M.indices[np.minimum(M.indptr[:-1], max(M.nnz - 1, 0))]
+        last = M.indices[np.maximum(M.indptr[1:] - 1, 0)]
+        cont = hv & (last - first + 1 == ln)
+        if group:
+            idxs = np.flatnonzero(hv)
+            k = 0
+            while k < len(idxs):
+                v0 = idxs[k]
+                r0 = M.indices[M.indptr[v0]:M.indptr[v0 + 1]]
+                a0 = M.data[M.indptr[v0]:M.indptr[v0 + 1]]
+                w = 1
+                while w < 16 and k + w < len(idxs) and idxs[k + w] == v0 + w:
+                    v = v0 + w
+                    r = M.indices[M.indptr[v]:M.indptr[v + 1]]
+                    a = M.data[M.indptr[v]:M.indptr[v + 1]]
+                    if len(r) != len(r0) or np.any(r != r0 + w) or np.any(a != a0):
+                        break
+                    w += 1
+                b += int(ln[v0]) * (4 + vb) + 16   # first variable's entries; group table
+                k += w
+        else:
+            b += int(8 * hv.sum() + 4 * ln[hv & ~cont].sum() + vb * ln[hv].sum())
+        return b + 4 * nvec_other + extra
+
+    if bits_dual == 5 and "dual" in out:
+        out["dual"] = side(K, n, 20 * m, False)
+    if bits_primal in (6, 7) and "primal" in out:
+        out["primal"] = side(K.T.tocsr(), m, 16 * n, bits_primal == 7)
+    return out
+
+
 VALU_LANE_OPS = 256 * 64 * 2.4e9   # lanes x clock of the 256 CUs: one integer op per lane per clock
 MFMA_INT8_TOPS = 5000.0             # dense int8 matrix-core peak of the MI355X (TOP/s)
 
@@ -773,6 +827,8 @@ def run_workload(a):
     kt = G.kernel_times(a.k_int, a.K)
     per_step = {k: ms * (a.k_int if k in ("dual", "primal") else 1) for k, (ms, cnt) in kt.items() if cnt}
     kb = kernel_bytes(bip, a.K, indexed_entries(bip))
+    lc = G.launch_cfg()
+    kb = signed_index_bytes(bip, lc.get("bits_dual", 0), lc.get("bits_primal", 0), kb)
     dom = max((k for k in per_step if k in kb), key=lambda k: per_step[k])
     avg_ms = kt[dom][0]
     achieved = kb[dom] / (avg_ms * 1e-3) / 1e9

@@ -66,3 +66,25 @@ def test_constant_degree_drops_primal_row_pointers():
     idx = bench.indexed_entries(cols)
     n, m, nnz = cols.n, cols.m1, cols.A.nnz
     assert bench.kernel_bytes(cols, 64, idx)["primal"] == 16 * n + 4 * idx[1] + 4 * m
+
+
+def test_signed_index_variant_bytes_facility_location():
+    """Dual 5 / primal 6 / primal 7 on a facility location with heavy
+    facilities and assignment rows, against the count written out: light items
+    4 bytes per entry; heavy rows two row pointers, no indices (contiguous
+    columns) and 2-byte coefficients; heavy variables two row pointers, 4-byte
+    indices and 2-byte coefficients (6), or per group of 16 one variable's
+    entries and a 16-byte table entry (7); vectors as in kernel_bytes."""
+    nf, nc = 300, 257
+    P = I.facility_location(nf, nc, 4)
+    n, m = nf + nf * nc, nf * nc + nc
+    kb = bench.kernel_bytes(P, 1024, bench.indexed_entries(P))
+    d5 = bench.signed_index_bytes(P, 5, 0, kb)
+    assert d5["dual"] == 4 * 2 * nf * nc + 8 * nc + 2 * nf * nc + 4 * n + 20 * m
+    assert d5["primal"] == kb["primal"]
+    p6 = bench.signed_index_bytes(P, 0, 6, kb)
+    assert p6["primal"] == 4 * 2 * nf * nc + 8 * nf + (4 + 2) * nf * nc + 4 * m + 16 * n
+    p7 = bench.signed_index_bytes(P, 0, 7, kb)
+    groups = (nf + 15) // 16
+    assert p7["primal"] == 4 * 2 * nf * nc + groups * (nc * (4 + 2) + 16) + 4 * m + 16 * n
+    assert bench.signed_index_bytes(P, 0, 0, kb) == kb
