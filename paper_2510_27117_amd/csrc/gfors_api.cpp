@@ -184,7 +184,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->hg_chg = cv.take<int>(P->hg_cap_c);
     P->hg_chb = cv.take<int>(P->hg_cap_c);
     P->hg_che = cv.take<int>(P->hg_cap_c);
-    P->hg_part = cv.take<float>(P->hg_cap_c * 16);
+    P->hg_part = cv.take<float>(P->hg_cap_c * kHgWidth);
     {
         // dense-block SpMV tables (filled only when the problem qualifies)
         const int64_t tb = n / kBlockCols + T + 1;
@@ -993,7 +993,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             if ((rc = light_range(rp, ci, val, m, P->lgt_d, P->lgt_d0, P->lgt_dn, P->lgt_dd))) return rc;
             if ((rc = light_range(rpT, ciT, valT, n, P->lgt_p, P->lgt_p0, P->lgt_pn, P->lgt_pd))) return rc;
         }
-        // heavy variables grouped: consecutive heavy variables (up to 16) of one
+        // heavy variables grouped: consecutive heavy variables (up to kHgWidth) of one
         // length whose rows are those of the group's first variable shifted by
         // their distance to it, with the same coefficients
         P->hg_ngroup = P->hg_nchunk = 0;
@@ -1006,7 +1006,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             while (k < hv.size()) {
                 const int v0 = hv[k], len = rpT[v0 + 1] - rpT[v0];
                 int w = 1;
-                while (w < 16 && k + w < hv.size() && hv[k + w] == v0 + w) {
+                while (w < kHgWidth && k + w < hv.size() && hv[k + w] == v0 + w) {
                     const int v = v0 + w;
                     bool same = rpT[v + 1] - rpT[v] == len;
                     for (int e = 0; e < len && same; ++e)

@@ -162,7 +162,7 @@ struct gfors_problem {
     // dual 5 / primal 6): items [lgt_*0, lgt_*0 + lgt_*n) of lgt_*d entries
     int *lgt_d = nullptr, *lgt_p = nullptr;
     int lgt_d0 = 0, lgt_dn = 0, lgt_dd = 0, lgt_p0 = 0, lgt_pn = 0, lgt_pd = 0;
-    // heavy variables in groups of <= 16 with unit-shifted rows (launch
+    // heavy variables in groups of <= kHgWidth with unit-shifted rows (launch
     // variant primal 7 = these groups + the light range of primal 6)
     int *hg_var0 = nullptr, *hg_w = nullptr, *hg_e0 = nullptr, *hg_c0 = nullptr;
     int *hg_chg = nullptr, *hg_chb = nullptr, *hg_che = nullptr;

@@ -91,6 +91,7 @@ constexpr int kLprBlock = 256;  // launch shape "a workgroup of 256 lanes per ro
 constexpr int kHeavyLen = 256;
 constexpr int kLightHole = 0x7fffffff;   // signed-index slot of a heavy item inside the light range
 constexpr int kHgChunk = 512;   // entries per workgroup of the heavy shift-group primal
+constexpr int kHgWidth = 16;    // variables per shift group (32 measured slower: fewer entries in flight)
 
 // ------------------------------------------------------------------ PDHG
 // val16: the coefficients as int16 when every |a| <= 32767 (else null)
@@ -190,7 +191,7 @@ void launch_dual_light(hipStream_t s, int D, int i0, int L, int m1, const int *s
 void launch_primal_light(hipStream_t s, int D, int i0, int L, const int *sidx, const float *wy,
                          const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
                          const double *rho, DevCounters *ctr, uint64_t *xbits);
-// Heavy variables in groups of <= 16 whose rows are unit shifts of the first
+// Heavy variables in groups of <= kHgWidth whose rows are unit shifts of the first
 // one's (one instance, no Q): chunk partials, then the per-variable update.
 void launch_primal_hgroup(hipStream_t s, bool unit, int nchunk, int ngroup, const int *ch_g, const int *ch_b,
                           const int *ch_e, const int *hg_var0, const int *hg_w, const int *hg_e0,

@@ -1190,32 +1190,34 @@ k_primal_light(int i0, int L, const int *__restrict__ sidx, const float *__restr
     }
 }
 
-// Heavy variables in groups of up to 16 consecutive ones whose rows are unit
-// shifts of each other (variable v0 + d has rows r + d for the rows r of v0,
-// with the same coefficients: the facilities of a facility location, whose
-// link rows are numbered customer-major).  A workgroup takes a chunk of a
-// group's entries: 16 entry slots x 16 variables, lane (q, d) adds a_e
-// wy[r_e + d] over the entries e = q, q + 16, ... of the chunk, so the 16 lanes
-// of one entry read 16 consecutive floats (one request instead of 16 gathers).
-// The chunk's 16 slot sums are added in slot order; k_primal_hgroup_fin adds
-// a variable's chunk sums in chunk order and applies the primal update.
+// Heavy variables in groups of up to kHgWidth (16) consecutive ones whose
+// rows are unit shifts of each other (variable v0 + d has rows r + d for the
+// rows r of v0, with the same coefficients: the facilities of a facility
+// location, whose link rows are numbered customer-major).  A workgroup takes a
+// chunk of a group's entries: 256 / kHgWidth entry slots x kHgWidth
+// variables, lane (q, d) adds a_e wy[r_e + d] over its slot's entries of the
+// chunk, so the lanes of one entry read consecutive floats (one request
+// instead of kHgWidth gathers).  The chunk's slot sums are added in slot order;
+// k_primal_hgroup_fin adds a variable's chunk sums in chunk order and applies
+// the primal update.
 template <bool UNIT>
 __global__ void __launch_bounds__(256)
 k_primal_hgroup(const int *__restrict__ ch_g, const int *__restrict__ ch_b, const int *__restrict__ ch_e,
                 const int *__restrict__ hg_w, const int *__restrict__ hg_e0, const int *__restrict__ ciT,
                 const int *__restrict__ valT, const float *__restrict__ wy, float *__restrict__ part) {
-    __shared__ float red[16][17];
+    constexpr int NS = 256 / kHgWidth;   // entry slots
+    __shared__ float red[NS][kHgWidth + 1];
     const int c = blockIdx.x;
     const int g = ch_g[c];
-    const int d = threadIdx.x & 15, q = threadIdx.x >> 4;
+    const int d = threadIdx.x % kHgWidth, q = threadIdx.x / kHgWidth;
     const int w = hg_w[g], base = hg_e0[g];
     const int b1 = ch_e[c];
     float acc = 0.f;
-    for (int e = ch_b[c] + q; e < b1; e += 16 * kLongUnroll) {
+    for (int e = ch_b[c] + q; e < b1; e += NS * kLongUnroll) {
         int r[kLongUnroll], a[kLongUnroll];
 #pragma unroll
         for (int u = 0; u < kLongUnroll; ++u) {
-            const int ee = e + 16 * u;
+            const int ee = e + NS * u;
             const bool in = ee < b1;
             r[u] = in ? ciT[base + ee] : 0;
             a[u] = UNIT ? (in ? 1 : 0) : (in ? valT[base + ee] : 0);
@@ -1228,11 +1230,11 @@ k_primal_hgroup(const int *__restrict__ ch_g, const int *__restrict__ ch_b, cons
     }
     red[q][d] = acc;
     __syncthreads();
-    if (threadIdx.x < 16) {
+    if (threadIdx.x < kHgWidth) {
         float sum = 0.f;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) sum += red[k][threadIdx.x];
-        part[static_cast<int64_t>(c) * 16 + threadIdx.x] = sum;
+        for (int k = 0; k < NS; ++k) sum += red[k][threadIdx.x];
+        part[static_cast<int64_t>(c) * kHgWidth + threadIdx.x] = sum;
     }
 }
 
@@ -1242,20 +1244,20 @@ k_primal_hgroup_fin(int ngroup, const int *__restrict__ hg_var0, const int *__re
                     const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ xbar,
                     const float *__restrict__ ct, float tau1, const double *__restrict__ rho) {
     const int tid = blockIdx.x * 256 + threadIdx.x;
-    const int g = tid >> 4, d = tid & 15;
+    const int g = tid / kHgWidth, d = tid % kHgWidth;
     if (g >= ngroup || d >= hg_w[g]) return;
     const int c0 = hg_c0[g], c1 = hg_c0[g + 1];
-    const float *pr = part + static_cast<int64_t>(c0) * 16 + d;
+    const float *pr = part + static_cast<int64_t>(c0) * kHgWidth + d;
     float tot = 0.f;
     int c = 0;
     for (; c + 8 <= c1 - c0; c += 8) {
         float v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = pr[static_cast<int64_t>(c + u) * 16];
+        for (int u = 0; u < 8; ++u) v[u] = pr[static_cast<int64_t>(c + u) * kHgWidth];
 #pragma unroll
         for (int u = 0; u < 8; ++u) tot += v[u];
     }
-    for (; c < c1 - c0; ++c) tot += pr[static_cast<int64_t>(c) * 16];
+    for (; c < c1 - c0; ++c) tot += pr[static_cast<int64_t>(c) * kHgWidth];
     const int i = hg_var0[g] + d;
     const float xi = x_in[i];
     const float rh = static_cast<float>(rho[0]);
@@ -1273,7 +1275,7 @@ void launch_primal_hgroup(hipStream_t s, bool unit, int nchunk, int ngroup, cons
     if (nchunk <= 0 || ngroup <= 0) return;
     if (unit) k_primal_hgroup<true><<<nchunk, 256, 0, s>>>(ch_g, ch_b, ch_e, hg_w, hg_e0, ciT, valT, wy, part);
     else k_primal_hgroup<false><<<nchunk, 256, 0, s>>>(ch_g, ch_b, ch_e, hg_w, hg_e0, ciT, valT, wy, part);
-    k_primal_hgroup_fin<<<(ngroup * 16 + 255) / 256, 256, 0, s>>>(ngroup, hg_var0, hg_w, hg_c0, part, x_in, x_out,
+    k_primal_hgroup_fin<<<(ngroup * kHgWidth + 255) / 256, 256, 0, s>>>(ngroup, hg_var0, hg_w, hg_c0, part, x_in, x_out,
                                                                    xbar, ct, tau1, rho);
 }
 
