@@ -375,6 +375,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     P->rowinv.assign(m, 1.0);
     std::vector<uint8_t> cls(m);
     P->rkind_host.assign(m, 0);
+    int64_t npair = 0, nbit = 0;   // pair rows, rows evaluated bitwise
     for (int64_t j = 0; j < m; ++j) {
         double sq = 0.0;
         int64_t absum = 0, amax = 0;
@@ -413,10 +414,13 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             kind = kEvalPair;
         }
         cls[j] = kind >= 0 ? kCover : kGeneral;
+        if (kind == kEvalPair) ++npair;
+        if (kind >= 0) ++nbit;
         P->rkind_host[j] = static_cast<uint8_t>(kind >= 0 ? (kind << 4) | tt : 0);
         if (cls[j] == kGeneral && absum > 2147483647LL) P->acc64 = true;
         if (cls[j] == kGeneral && amax >= (1LL << 23)) P->coef24 = false;
     }
+    P->pair_rows_mostly = nbit > 0 && 2 * npair > nbit;
     // transpose (counting sort by column; rows ascending within a column)
     std::vector<int> rpT(n + 1, 0), ciT(P->nnzK), valT(P->nnzK);
     for (int64_t e = 0; e < P->nnzK; ++e) rpT[ci[e] + 1]++;
@@ -1712,7 +1716,7 @@ static void enqueue_eval(gfors_problem *P, int K, int threshold, KTimer *tm, int
     const int W = K / 64;
     TB(3);
     launch_eval_cover(s, P->n_cover, P->cover_ids, P->et, P->rows, P->rkind, P->rp, P->ci, P->X,
-                      P->xkind, W, P->vpart, K);
+                      P->xkind, W, P->vpart, K, P->pair_rows_mostly);
     TE(3);
     TB(4);
     launch_eval_general_rows(P, K);

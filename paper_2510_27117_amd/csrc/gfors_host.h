@@ -169,6 +169,7 @@ struct gfors_problem {
     float *hg_part = nullptr;
     int64_t hg_cap_g = 0, hg_cap_c = 0;
     int hg_ngroup = 0, hg_nchunk = 0;
+    bool pair_rows_mostly = false;   // most bitwise-evaluated rows have one or two entries
     // node classes of the learned proposal's messages (prefixes of dual_order /
     // primal_order): kGnnHeavyLen+ entries, then more than kGnnShortLen
     int gnn_rh = 0, gnn_rm = 0, gnn_ch = 0, gnn_cm = 0;

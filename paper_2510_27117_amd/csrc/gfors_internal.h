@@ -248,7 +248,8 @@ void launch_sample(hipStream_t s, int W, bool obj64, const float *p, const int64
 
 void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                        const int *rows, const uint8_t *rkind, const int *rp, const int *ci,
-                       const uint64_t *X, const uint8_t *xkind, int W, int *vpart, int K);
+                       const uint64_t *X, const uint8_t *xkind, int W, int *vpart, int K,
+                       bool pair_rows);   // most rows of two entries: four rows in flight per group
 void launch_eval_general(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                          bool acc64, const int *rows, const int *rp, const int *ci,
                          const int *val, const int64_t *rhs, int m1, const uint64_t *X,

@@ -635,6 +635,7 @@ __device__ __forceinline__ uint64_t cand_word(const uint64_t *__restrict__ X,
     return X[static_cast<int64_t>(c) * W + sub];
 }
 
+template <int RU>
 __global__ void __launch_bounds__(256)
 k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
              const int *__restrict__ tb1, const int *__restrict__ rows,
@@ -653,56 +654,91 @@ k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
 #pragma unroll
     for (int pl = 0; pl < 8; ++pl) c[pl] = 0;
     int since = 0;
-    for (int rr = r0 + grp; rr < r1; rr += ngrp) {
+    // RU rows per group and pass: their row data, and the two words of pair
+    // rows, are loaded together (a row's count does not depend on the order
+    // in which rows are added).  Four pay on pair rows (two entries, a chain
+    // of dependent loads each); on long covering rows they cost occupancy.
+    for (int rb = r0 + grp; rb < r1; rb += RU * ngrp) {
         if (sub < W) {
-            const int j = rows[rr];
-            const int kd = rkind[j];
-            const int kind = kd >> 4;
-            const int e0 = rp[j], e1 = rp[j + 1];
-            uint64_t viol;
-            if (kind == kEvalPair) {
-                const uint64_t P = cand_word(X, xkind, ci[e0], W, sub);
-                const uint64_t Q = cand_word(X, xkind, ci[e1 - 1], W, sub);
-                viol = ((kd & 1) ? (~P & ~Q) : 0ull) | ((kd & 2) ? (~P & Q) : 0ull) |
-                       ((kd & 4) ? (P & ~Q) : 0ull) | ((kd & 8) ? (P & Q) : 0ull);
-            } else {
-                // "at least one / at least two set" do not depend on the
-                // order of the entries: kCoverBatch at a time, their column
-                // indices, kind bytes and words each loaded together
-                uint64_t one = 0, two = 0;
-                int e = e0;
-                for (; e + kCoverBatch <= e1; e += kCoverBatch) {
-                    int cc[kCoverBatch];
-                    uint8_t kk[kCoverBatch];
-                    uint64_t xx[kCoverBatch];
+            int j[RU], kd[RU], e0[RU], e1[RU];
 #pragma unroll
-                    for (int u = 0; u < kCoverBatch; ++u) cc[u] = ci[e + u];
+            for (int u = 0; u < RU; ++u) j[u] = rb + u * ngrp < r1 ? rows[rb + u * ngrp] : -1;
 #pragma unroll
-                    for (int u = 0; u < kCoverBatch; ++u) kk[u] = xkind[cc[u]];
+            for (int u = 0; u < RU; ++u) {
+                kd[u] = j[u] >= 0 ? rkind[j[u]] : 0;
+                e0[u] = j[u] >= 0 ? rp[j[u]] : 0;
+                e1[u] = j[u] >= 0 ? rp[j[u] + 1] : 0;
+            }
+            uint64_t P[RU], Q[RU];
+            {
+                int c0[RU], c1[RU];
+                uint8_t k0[RU], k1[RU];
 #pragma unroll
-                    for (int u = 0; u < kCoverBatch; ++u)
-                        xx[u] = kk[u] == 0 ? X[static_cast<int64_t>(cc[u]) * W + sub] : (kk[u] == 2 ? ~0ull : 0ull);
+                for (int u = 0; u < RU; ++u) {
+                    const bool pr = j[u] >= 0 && (kd[u] >> 4) == kEvalPair;
+                    c0[u] = pr ? ci[e0[u]] : -1;
+                    c1[u] = pr ? ci[e1[u] - 1] : -1;
+                }
 #pragma unroll
-                    for (int u = 0; u < kCoverBatch; ++u) {
-                        two |= one & xx[u];
-                        one |= xx[u];
+                for (int u = 0; u < RU; ++u) {
+                    k0[u] = c0[u] >= 0 ? xkind[c0[u]] : 1;
+                    k1[u] = c1[u] >= 0 ? xkind[c1[u]] : 1;
+                }
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    P[u] = k0[u] == 0 ? X[static_cast<int64_t>(c0[u]) * W + sub] : (k0[u] == 2 ? ~0ull : 0ull);
+                    Q[u] = k1[u] == 0 ? X[static_cast<int64_t>(c1[u]) * W + sub] : (k1[u] == 2 ? ~0ull : 0ull);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (j[u] < 0) break;
+                const int kind = kd[u] >> 4;
+                uint64_t viol;
+                if (kind == kEvalPair) {
+                    const int k = kd[u];
+                    viol = ((k & 1) ? (~P[u] & ~Q[u]) : 0ull) | ((k & 2) ? (~P[u] & Q[u]) : 0ull) |
+                           ((k & 4) ? (P[u] & ~Q[u]) : 0ull) | ((k & 8) ? (P[u] & Q[u]) : 0ull);
+                } else {
+                    // "at least one / at least two set" do not depend on the
+                    // order of the entries: kCoverBatch at a time, their column
+                    // indices, kind bytes and words each loaded together
+                    uint64_t one = 0, two = 0;
+                    int e = e0[u];
+                    const int ee1 = e1[u];
+                    for (; e + kCoverBatch <= ee1; e += kCoverBatch) {
+                        int cc[kCoverBatch];
+                        uint8_t kk[kCoverBatch];
+                        uint64_t xx[kCoverBatch];
+#pragma unroll
+                        for (int v = 0; v < kCoverBatch; ++v) cc[v] = ci[e + v];
+#pragma unroll
+                        for (int v = 0; v < kCoverBatch; ++v) kk[v] = xkind[cc[v]];
+#pragma unroll
+                        for (int v = 0; v < kCoverBatch; ++v)
+                            xx[v] = kk[v] == 0 ? X[static_cast<int64_t>(cc[v]) * W + sub] : (kk[v] == 2 ? ~0ull : 0ull);
+#pragma unroll
+                        for (int v = 0; v < kCoverBatch; ++v) {
+                            two |= one & xx[v];
+                            one |= xx[v];
+                        }
                     }
+                    for (; e < ee1; ++e) {
+                        const uint64_t x = cand_word(X, xkind, ci[e], W, sub);
+                        two |= one & x;
+                        one |= x;
+                    }
+                    viol = kind == kEvalCover ? ~one : (kind == kEvalAtMostOne ? two : (~one | two));
                 }
-                for (; e < e1; ++e) {
-                    const uint64_t x = cand_word(X, xkind, ci[e], W, sub);
-                    two |= one & x;
-                    one |= x;
-                }
-                viol = kind == kEvalCover ? ~one : (kind == kEvalAtMostOne ? two : (~one | two));
-            }
-            uint64_t carry = viol;
+                uint64_t carry = viol;
 #pragma unroll
-            for (int pl = 0; pl < 8; ++pl) {
-                const uint64_t t = c[pl] & carry;
-                c[pl] ^= carry;
-                carry = t;
+                for (int pl = 0; pl < 8; ++pl) {
+                    const uint64_t t = c[pl] & carry;
+                    c[pl] ^= carry;
+                    carry = t;
+                }
+                if (++since == 255) { flush_planes(c, cnt, sub); since = 0; }
             }
-            if (++since == 255) { flush_planes(c, cnt, sub); since = 0; }
         }
     }
     if (sub < W && since) flush_planes(c, cnt, sub);
@@ -713,11 +749,14 @@ k_eval_cover(const int *__restrict__ tile_ids, const int *__restrict__ tb0,
 
 void launch_eval_cover(hipStream_t s, int ntiles, const int *tile_ids, const Tiles &et,
                        const int *rows, const uint8_t *rkind, const int *rp, const int *ci,
-                       const uint64_t *X, const uint8_t *xkind, int W, int *vpart, int K) {
+                       const uint64_t *X, const uint8_t *xkind, int W, int *vpart, int K, bool pair_rows) {
     if (!ntiles) return;
     int lg = 0;
     while ((1 << lg) < W) ++lg;
-    k_eval_cover<<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rkind, rp, ci, X, xkind, W, lg, vpart, K);
+    if (pair_rows)
+        k_eval_cover<4><<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rkind, rp, ci, X, xkind, W, lg, vpart, K);
+    else
+        k_eval_cover<1><<<ntiles, 256, 0, s>>>(tile_ids, et.b0, et.b1, rows, rkind, rp, ci, X, xkind, W, lg, vpart, K);
 }
 
 // ---------------------------------------------------------------------------
