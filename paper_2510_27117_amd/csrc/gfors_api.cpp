@@ -184,6 +184,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->hg_chg = cv.take<int>(P->hg_cap_c);
     P->hg_chb = cv.take<int>(P->hg_cap_c);
     P->hg_che = cv.take<int>(P->hg_cap_c);
+    P->hg_ord = cv.take<int>(P->hg_cap_c > 0 ? 2 * P->hg_cap_c + 16 : 0);
     P->hg_part = cv.take<float>(P->hg_cap_c * kHgWidth);
     {
         // dense-block SpMV tables (filled only when the problem qualifies)
@@ -1032,9 +1033,27 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
             gc0.push_back(static_cast<int>(chg.size()));
             // worth it only when the groups are wide on average
             const bool useful = !gv0.empty() && hv.size() >= 4 * gv0.size();
+            // launch order: the chunks of groups 2k and 2k + 1 (same chunk
+            // count) in units of 16 slots, eight of each group, so that
+            // chunk i of both lands on one XCD; other groups in units of 8;
+            // empty slots -1
+            std::vector<int> ord;
+            for (size_t g = 0; g < gv0.size();) {
+                const int c0 = gc0[g], nc = gc0[g + 1] - gc0[g];
+                const bool pair = g + 1 < gv0.size() && gc0[g + 2] - gc0[g + 1] == nc;
+                for (int cb = 0; cb < nc; cb += 8) {
+                    for (int i = 0; i < 8; ++i) ord.push_back(cb + i < nc ? c0 + cb + i : -1);
+                    if (pair)
+                        for (int i = 0; i < 8; ++i) ord.push_back(cb + i < nc ? gc0[g + 1] + cb + i : -1);
+                }
+                g += pair ? 2 : 1;
+            }
             if (useful && static_cast<int64_t>(gv0.size()) <= P->hg_cap_g &&
-                static_cast<int64_t>(chg.size()) <= P->hg_cap_c) {
+                static_cast<int64_t>(chg.size()) <= P->hg_cap_c &&
+                static_cast<int64_t>(ord.size()) <= 2 * P->hg_cap_c + 16) {
                 const int64_t G = static_cast<int64_t>(gv0.size()), C = static_cast<int64_t>(chg.size());
+                if ((rc = upload(s, P->hg_ord, ord.data(), static_cast<int64_t>(ord.size())))) return rc;
+                P->hg_nslot = static_cast<int>(ord.size());
                 if ((rc = upload(s, P->hg_var0, gv0.data(), G))) return rc;
                 if ((rc = upload(s, P->hg_w, gw.data(), G))) return rc;
                 if ((rc = upload(s, P->hg_e0, ge0.data(), G))) return rc;
@@ -1413,7 +1432,7 @@ static void launch_primal_cfg(gfors_problem *P, int lpr, int slices, int sell, c
         // heavy variables a workgroup each (6) or in shift groups (7), the
         // light range a lane per variable with signed indices
         if (P->cfg.bits_primal == 7)
-            launch_primal_hgroup(s, P->unitK, P->hg_nchunk, P->hg_ngroup, P->hg_chg, P->hg_chb, P->hg_che,
+            launch_primal_hgroup(s, P->unitK, P->hg_nslot, P->hg_ngroup, P->hg_ord, P->hg_chg, P->hg_chb, P->hg_che,
                                  P->hg_var0, P->hg_w, P->hg_e0, P->hg_c0, P->ciT, P->valT, P->wy, P->hg_part,
                                  x_in, x_out, xbar, P->ct, tau1, P->di.rho);
         else

@@ -165,10 +165,10 @@ struct gfors_problem {
     // heavy variables in groups of <= kHgWidth with unit-shifted rows (launch
     // variant primal 7 = these groups + the light range of primal 6)
     int *hg_var0 = nullptr, *hg_w = nullptr, *hg_e0 = nullptr, *hg_c0 = nullptr;
-    int *hg_chg = nullptr, *hg_chb = nullptr, *hg_che = nullptr;
+    int *hg_chg = nullptr, *hg_chb = nullptr, *hg_che = nullptr, *hg_ord = nullptr;
     float *hg_part = nullptr;
     int64_t hg_cap_g = 0, hg_cap_c = 0;
-    int hg_ngroup = 0, hg_nchunk = 0;
+    int hg_ngroup = 0, hg_nchunk = 0, hg_nslot = 0;
     bool pair_rows_mostly = false;   // most bitwise-evaluated rows have one or two entries
     // node classes of the learned proposal's messages (prefixes of dual_order /
     // primal_order): kGnnHeavyLen+ entries, then more than kGnnShortLen

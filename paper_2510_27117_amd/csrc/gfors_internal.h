@@ -193,8 +193,8 @@ void launch_primal_light(hipStream_t s, int D, int i0, int L, const int *sidx, c
                          const double *rho, DevCounters *ctr, uint64_t *xbits);
 // Heavy variables in groups of <= kHgWidth whose rows are unit shifts of the first
 // one's (one instance, no Q): chunk partials, then the per-variable update.
-void launch_primal_hgroup(hipStream_t s, bool unit, int nchunk, int ngroup, const int *ch_g, const int *ch_b,
-                          const int *ch_e, const int *hg_var0, const int *hg_w, const int *hg_e0,
+void launch_primal_hgroup(hipStream_t s, bool unit, int nslot, int ngroup, const int *ord, const int *ch_g,
+                          const int *ch_b, const int *ch_e, const int *hg_var0, const int *hg_w, const int *hg_e0,
                           const int *hg_c0, const int *ciT, const int *valT, const float *wy, float *part,
                           const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
                           const double *rho);

@@ -1200,14 +1200,20 @@ k_primal_light(int i0, int L, const int *__restrict__ sidx, const float *__restr
 // instead of kHgWidth gathers).  The chunk's slot sums are added in slot order;
 // k_primal_hgroup_fin adds a variable's chunk sums in chunk order and applies
 // the primal update.
+// Workgroup b takes chunk ord[b] (-1: none): the host places the chunks of
+// two neighbouring groups, which share the 128-byte lines of wy, eight slots
+// apart, so that both run on one XCD (workgroup b runs on XCD b % 8) at about
+// the same time and fetch each line into one L2 once.
 template <bool UNIT>
 __global__ void __launch_bounds__(256)
-k_primal_hgroup(const int *__restrict__ ch_g, const int *__restrict__ ch_b, const int *__restrict__ ch_e,
-                const int *__restrict__ hg_w, const int *__restrict__ hg_e0, const int *__restrict__ ciT,
-                const int *__restrict__ valT, const float *__restrict__ wy, float *__restrict__ part) {
+k_primal_hgroup(const int *__restrict__ ord, const int *__restrict__ ch_g, const int *__restrict__ ch_b,
+                const int *__restrict__ ch_e, const int *__restrict__ hg_w, const int *__restrict__ hg_e0,
+                const int *__restrict__ ciT, const int *__restrict__ valT, const float *__restrict__ wy,
+                float *__restrict__ part) {
     constexpr int NS = 256 / kHgWidth;   // entry slots
     __shared__ float red[NS][kHgWidth + 1];
-    const int c = blockIdx.x;
+    const int c = ord[blockIdx.x];
+    if (c < 0) return;                   // padding slot (whole workgroup, before any barrier)
     const int g = ch_g[c];
     const int d = threadIdx.x % kHgWidth, q = threadIdx.x / kHgWidth;
     const int w = hg_w[g], base = hg_e0[g];
@@ -1267,14 +1273,14 @@ k_primal_hgroup_fin(int ngroup, const int *__restrict__ hg_var0, const int *__re
     xbar[i] = 2.f * xn - xi;
 }
 
-void launch_primal_hgroup(hipStream_t s, bool unit, int nchunk, int ngroup, const int *ch_g, const int *ch_b,
-                          const int *ch_e, const int *hg_var0, const int *hg_w, const int *hg_e0,
+void launch_primal_hgroup(hipStream_t s, bool unit, int nslot, int ngroup, const int *ord, const int *ch_g,
+                          const int *ch_b, const int *ch_e, const int *hg_var0, const int *hg_w, const int *hg_e0,
                           const int *hg_c0, const int *ciT, const int *valT, const float *wy, float *part,
                           const float *x_in, float *x_out, float *xbar, const float *ct, float tau1,
                           const double *rho) {
-    if (nchunk <= 0 || ngroup <= 0) return;
-    if (unit) k_primal_hgroup<true><<<nchunk, 256, 0, s>>>(ch_g, ch_b, ch_e, hg_w, hg_e0, ciT, valT, wy, part);
-    else k_primal_hgroup<false><<<nchunk, 256, 0, s>>>(ch_g, ch_b, ch_e, hg_w, hg_e0, ciT, valT, wy, part);
+    if (nslot <= 0 || ngroup <= 0) return;
+    if (unit) k_primal_hgroup<true><<<nslot, 256, 0, s>>>(ord, ch_g, ch_b, ch_e, hg_w, hg_e0, ciT, valT, wy, part);
+    else k_primal_hgroup<false><<<nslot, 256, 0, s>>>(ord, ch_g, ch_b, ch_e, hg_w, hg_e0, ciT, valT, wy, part);
     k_primal_hgroup_fin<<<(ngroup * kHgWidth + 255) / 256, 256, 0, s>>>(ngroup, hg_var0, hg_w, hg_c0, part, x_in, x_out,
                                                                    xbar, ct, tau1, rho);
 }
