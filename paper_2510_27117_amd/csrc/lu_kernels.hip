@@ -445,10 +445,24 @@ k_lu_eval_rhs(int r, int W, int K, const int *__restrict__ rp, const int *__rest
     if (g >= r * W) return;
     const int k = g / W, w = g - k * W;
     int acc = static_cast<int>(dJ[k]);
-#pragma unroll 8
-    for (int e = rp[k]; e < rp[k + 1]; ++e) {
-        const uint64_t word = X[static_cast<int64_t>(ci[e]) * W + w];
-        if ((word >> lane) & 1ull) acc -= val[e];
+    // 64 entries at a time: lane j loads entry j's column, coefficient and
+    // candidate word (one gather for all 64), then every lane walks them in
+    // entry order through lane reads (integer sums: the order is free anyway)
+    const int e0 = rp[k], e1 = rp[k + 1];
+    for (int eb = e0; eb < e1; eb += 64) {
+        const int e = eb + lane;
+        const bool in = e < e1;
+        const int vl = in ? val[e] : 0;
+        const uint64_t wl = in ? X[static_cast<int64_t>(ci[e]) * W + w] : 0ull;
+        const uint32_t wlo = static_cast<uint32_t>(wl), whi = static_cast<uint32_t>(wl >> 32);
+        const int cnt = min(64, e1 - eb);
+        for (int j = 0; j < cnt; ++j) {
+            const int vj = __builtin_amdgcn_readlane(vl, j);
+            const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wlo), j));
+            const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(whi), j));
+            const uint32_t half = lane < 32 ? lo : hi;
+            if ((half >> (lane & 31)) & 1u) acc -= vj;
+        }
     }
     XI[static_cast<int64_t>(k) * K + 64 * w + lane] = acc;
 }
@@ -533,9 +547,33 @@ k_lu_eval_rows(int nch, int W, int K, int nk, int m1, const int *__restrict__ ch
     const int c = g / W, w = g - c * W;
     const int j = ch_row[c];
     int64_t acc = 0;
-#pragma unroll 8
-    for (int e = ch_e0[c]; e < ch_e1[c]; ++e)
-        acc += static_cast<int64_t>(val[e]) * lifted_val(ci[e], nk, X, W, w, lane, XI, K);
+    // 64 entries at a time: lane q loads entry q's column and coefficient and,
+    // for a kept variable, its candidate word (one gather for all 64); every
+    // lane then walks them in entry order through lane reads, loading only the
+    // lifted integers (one coalesced load per lifted entry)
+    const int e0 = ch_e0[c], e1 = ch_e1[c];
+    for (int eb = e0; eb < e1; eb += 64) {
+        const int e = eb + lane;
+        const bool in = e < e1;
+        const int cl = in ? ci[e] : 0;
+        const int vl = in ? val[e] : 0;
+        const uint64_t wl = (in && cl < nk) ? X[static_cast<int64_t>(cl) * W + w] : 0ull;
+        const uint32_t wlo = static_cast<uint32_t>(wl), whi = static_cast<uint32_t>(wl >> 32);
+        const int cnt = min(64, e1 - eb);
+        for (int q = 0; q < cnt; ++q) {
+            const int cq = __builtin_amdgcn_readlane(cl, q);
+            const int vq = __builtin_amdgcn_readlane(vl, q);
+            int64_t xv;
+            if (cq < nk) {   // uniform over the wavefront
+                const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wlo), q));
+                const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(whi), q));
+                xv = static_cast<int64_t>(((lane < 32 ? lo : hi) >> (lane & 31)) & 1u);
+            } else {
+                xv = static_cast<int64_t>(XI[static_cast<int64_t>(cq - nk) * K + 64 * w + lane]);
+            }
+            acc += static_cast<int64_t>(vq) * xv;
+        }
+    }
     const int slot = ch_slot[c];
     const int l = 64 * w + lane;
     if (slot < 0) {
