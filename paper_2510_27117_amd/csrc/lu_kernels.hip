@@ -628,11 +628,34 @@ k_lu_eval_quad(int nch, int W, int K, int nk, const int *__restrict__ ch_row, co
     const int c = g / W, w = g - c * W;
     const int a = ch_row[c];
     const int64_t va = lifted_val(a, nk, X, W, w, lane, XI, K);
-    if (va == 0) return;
+    if (__ballot(va != 0) == 0) return;   // no candidate of the word has x_a != 0 (uniform)
     int64_t acc = 0;
-    for (int e = ch_e0[c]; e < ch_e1[c]; ++e)
-        acc += static_cast<int64_t>(valQ[e]) * lifted_val(ciQ[e], nk, X, W, w, lane, XI, K);
-    if (acc) atomicAdd(&zx[64 * w + lane], static_cast<unsigned long long>(acc * va));
+    // 64 entries at a time, as in k_lu_eval_rows (every lane of the wavefront
+    // takes part in the lane reads; lanes with x_a = 0 add nothing at the end)
+    const int e0 = ch_e0[c], e1 = ch_e1[c];
+    for (int eb = e0; eb < e1; eb += 64) {
+        const int e = eb + lane;
+        const bool in = e < e1;
+        const int cl = in ? ciQ[e] : 0;
+        const int vl = in ? valQ[e] : 0;
+        const uint64_t wl = (in && cl < nk) ? X[static_cast<int64_t>(cl) * W + w] : 0ull;
+        const uint32_t wlo = static_cast<uint32_t>(wl), whi = static_cast<uint32_t>(wl >> 32);
+        const int cnt = min(64, e1 - eb);
+        for (int q = 0; q < cnt; ++q) {
+            const int cq = __builtin_amdgcn_readlane(cl, q);
+            const int vq = __builtin_amdgcn_readlane(vl, q);
+            int64_t xv;
+            if (cq < nk) {   // uniform over the wavefront
+                const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wlo), q));
+                const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(whi), q));
+                xv = static_cast<int64_t>(((lane < 32 ? lo : hi) >> (lane & 31)) & 1u);
+            } else {
+                xv = static_cast<int64_t>(XI[static_cast<int64_t>(cq - nk) * K + 64 * w + lane]);
+            }
+            acc += static_cast<int64_t>(vq) * xv;
+        }
+    }
+    if (va != 0 && acc) atomicAdd(&zx[64 * w + lane], static_cast<unsigned long long>(acc * va));
 }
 
 void launch_lu_eval_rows(hipStream_t s, int nch, int K, int nk, int m1, const int *ch_row, const int *ch_e0,
