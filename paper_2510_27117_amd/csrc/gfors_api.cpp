@@ -117,6 +117,7 @@ static size_t carve(gfors_problem *P, Carver &cv, int64_t n, int64_t m1, int64_t
     P->xkind = cv.take<uint8_t>(n);
     P->dual_order = cv.take<int>(m);
     P->rowc0 = cv.take<int>(std::max<int64_t>(m, 1));
+    P->rowunit = cv.take<uint8_t>(std::max<int64_t>(m, 1));
     P->colT0 = cv.take<int>(std::max<int64_t>(n, 1));
     P->primal_order = cv.take<int>(n);
     P->cover_ids = cv.take<int>(b.et);
@@ -422,6 +423,12 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
         if (cls[j] == kGeneral && amax >= (1LL << 23)) P->coef24 = false;
     }
     P->pair_rows_mostly = nbit > 0 && 2 * npair > nbit;
+    std::vector<uint8_t> rowunit_h(m, 0);
+    for (int64_t j = 0; j < m; ++j) {
+        bool one = rp[j + 1] > rp[j];
+        for (int e = rp[j]; e < rp[j + 1] && one; ++e) one = val[e] == 1;
+        rowunit_h[j] = one ? 1 : 0;
+    }
     // transpose (counting sort by column; rows ascending within a column)
     std::vector<int> rpT(n + 1, 0), ciT(P->nnzK), valT(P->nnzK);
     for (int64_t e = 0; e < P->nnzK; ++e) rpT[ci[e] + 1]++;
@@ -807,6 +814,7 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     if ((rc = upload(s, P->d_inst_nvar, P->inst_nvar.data(), T))) return rc;
     if ((rc = upload(s, P->rows, rows_list.data(), m))) return rc;
     if ((rc = upload(s, P->rkind, P->rkind_host.data(), m))) return rc;
+    if ((rc = upload(s, P->rowunit, rowunit_h.data(), m))) return rc;
     if ((rc = upload(s, P->cover_ids, cover_ids.data(), P->n_cover))) return rc;
     if ((rc = upload(s, P->general_ids, general_ids.data(), P->n_general))) return rc;
     if (P->mfma) {
@@ -1354,7 +1362,7 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
     } else if (P->cfg.bits_dual == 5 && P->lgt_dd > 0 && !sell && slices == 1) {
         // heavy rows a workgroup each, the light range a lane per row with signed indices
         launch_dual_long(s, P->unitK, false, P->heavy_rows, m1, P->dual_order, P->rp, P->rowc0, P->ci, P->val,
-                         P->use16 ? P->val16 : nullptr, P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2,
+                         P->use16 ? P->val16 : nullptr, P->rowunit, P->omega, P->rt, P->xbar, y_in, y_out, P->wy, tau2,
                          P->di.tau2, P->row_inst);
         launch_dual_light(s, P->lgt_dd, P->lgt_d0, P->lgt_dn, m1, P->lgt_d, P->omega, P->rt, P->xbar, y_in, y_out,
                           P->wy, tau2);
@@ -1399,7 +1407,8 @@ static void launch_dual_cfg(gfors_problem *P, int lpr, int slices, int sell, con
         // the others with lpr - 256 lanes each
         const bool all = lpr == kLprBlock;
         launch_dual_long(s, P->unitK, batched, all ? m : P->heavy_rows, m1, P->dual_order, P->rp,
-                         P->rowc0, P->ci, P->val, P->use16 ? P->val16 : nullptr, P->omega, P->rt, P->xbar,
+                         P->rowc0, P->ci, P->val, P->use16 ? P->val16 : nullptr, P->rowunit, P->omega, P->rt,
+                         P->xbar,
                          y_in, y_out, P->wy, tau2,
                          P->di.tau2, P->row_inst);
         if (!all)

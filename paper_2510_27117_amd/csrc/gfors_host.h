@@ -155,6 +155,7 @@ struct gfors_problem {
     uint8_t *xkind = nullptr;    // per variable, last round: 0 sampled, 1 all zero, 2 all one
     int *dual_order = nullptr;   // constraint rows, longest first (block-per-row dual)
     int *rowc0 = nullptr;        // first column of a row whose columns are one contiguous range, else -1
+    uint8_t *rowunit = nullptr;  // 1 where every coefficient of the row is 1 (no coefficient stream)
     int *colT0 = nullptr;        // first row of a variable whose rows are one contiguous range, else -1
     int *primal_order = nullptr; // variables, most rows first (block-per-variable primal)
     int heavy_rows = 0, heavy_cols = 0;   // rows / variables with kHeavyLen+ entries

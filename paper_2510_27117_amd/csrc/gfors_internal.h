@@ -133,7 +133,7 @@ void launch_sell(hipStream_t s, const SellView &sv, int mode, bool unit, bool ba
 void launch_nzbits(hipStream_t s, const float *v, int64_t n, int64_t nwords64, uint64_t *bits);
 void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, const int *order,
                       const int *rp, const int *rowc0, const int *ci, const int *val,
-                      const int16_t *val16, const float *omega,
+                      const int16_t *val16, const uint8_t *rowunit, const float *omega,
                       const float *rt, const float *xbar, const float *y_in, float *y_out,
                       float *wy, float tau2, const float *tau2_inst, const int *row_inst);
 void launch_sell_bits(hipStream_t s, const SellView &sv, int mode, bool unit, bool batched,

@@ -107,7 +107,8 @@ template <bool UNIT, bool BATCH>
 __global__ void __launch_bounds__(256)
 k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restrict__ rp,
             const int *__restrict__ rowc0, const int *__restrict__ ci, const int *__restrict__ val,
-            const int16_t *__restrict__ val16, const float *__restrict__ omega, const float *__restrict__ rt,
+            const int16_t *__restrict__ val16, const uint8_t *__restrict__ rowunit,
+            const float *__restrict__ omega, const float *__restrict__ rt,
             const float *__restrict__ xbar, const float *__restrict__ y_in,
             float *__restrict__ y_out, float *__restrict__ wy, float tau2,
             const float *__restrict__ tau2_inst, const int *__restrict__ row_inst) {
@@ -119,7 +120,10 @@ k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restr
     const int c0 = rowc0[row];                          // first column of a dense row, else -1
     // val16: the same coefficients as int16 (all fit), half the stream
     float s;
-    if (!UNIT && val16)
+    if (!UNIT && rowunit && rowunit[row])   // every coefficient of the row is 1: no coefficient stream
+        s = c0 >= 0 ? long_row_sum<true, true>(e0, e1, c0, ci, val, xbar)
+                    : long_row_sum<true, false>(e0, e1, c0, ci, val, xbar);
+    else if (!UNIT && val16)
         s = c0 >= 0 ? long_row_sum<UNIT, true>(e0, e1, c0, ci, val16, xbar)
                     : long_row_sum<UNIT, false>(e0, e1, c0, ci, val16, xbar);
     else
@@ -141,12 +145,13 @@ k_dual_long(int count, int m1, const int *__restrict__ order, const int *__restr
 }
 
 void launch_dual_long(hipStream_t s, bool unit, bool batched, int m, int m1, const int *order,
-                      const int *rp, const int *rowc0, const int *ci, const int *val, const int16_t *val16, const float *omega,
+                      const int *rp, const int *rowc0, const int *ci, const int *val, const int16_t *val16,
+                      const uint8_t *rowunit, const float *omega,
                       const float *rt, const float *xbar, const float *y_in, float *y_out,
                       float *wy, float tau2, const float *tau2_inst, const int *row_inst) {
     if (m <= 0) return;
     const int grid = ((m + 127) / 128) * 128;
-#define GF_DL(U, B) k_dual_long<U, B><<<grid, 256, 0, s>>>(m, m1, order, rp, rowc0, ci, val, val16, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
+#define GF_DL(U, B) k_dual_long<U, B><<<grid, 256, 0, s>>>(m, m1, order, rp, rowc0, ci, val, val16, rowunit, omega, rt, xbar, y_in, y_out, wy, tau2, tau2_inst, row_inst)
     if (unit) { if (batched) GF_DL(true, true); else GF_DL(true, false); }
     else { if (batched) GF_DL(false, true); else GF_DL(false, false); }
 #undef GF_DL
