@@ -816,7 +816,16 @@ int gfors_create_problem(const gfors_csr *A, const int64_t *b, const gfors_csr *
     if ((rc = upload(s, P->rkind, P->rkind_host.data(), m))) return rc;
     if ((rc = upload(s, P->rowunit, rowunit_h.data(), m))) return rc;
     if ((rc = upload(s, P->cover_ids, cover_ids.data(), P->n_cover))) return rc;
-    if ((rc = upload(s, P->general_ids, general_ids.data(), P->n_general))) return rc;
+    {
+        // launch order of the general tiles: most entries first (a tile's time
+        // grows with them; the counts of a tile do not depend on the order)
+        std::vector<int> gl(general_ids);
+        std::vector<int64_t> work(he.inst.size(), 0);
+        for (int id : gl)
+            for (int q = he.b0[id]; q < he.b1[id]; ++q) work[id] += rp[rows_list[q] + 1] - rp[rows_list[q]];
+        std::stable_sort(gl.begin(), gl.end(), [&](int a, int b2) { return work[a] > work[b2]; });
+        if ((rc = upload(s, P->general_ids, gl.data(), P->n_general))) return rc;
+    }
     if (P->mfma) {
         // densified digit blocks of the general tiles (signed base-256 digits)
         const int npl = P->mf_npl;
